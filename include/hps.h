@@ -1,0 +1,175 @@
+/*
+ * hps.h -- C ABI of the MI355X (gfx950) HPS direct solver for the variable-coefficient
+ * Helmholtz impedance problem
+ *
+ *     -Lap u - kappa^2 c(x) u = s   in Omega = [x0,x1] x [y0,y1]
+ *     du/dnu + i eta u        = t   on dOmega,        Re(eta) != 0
+ *
+ * (eq. (basic) of Beams, Gillman, Hewett, arXiv 1812.07167).  The library implements
+ * the precomputation stage (Algorithm 1: batched leaf operators of Sec. 2.1, then the
+ * level-by-level merge of Sec. 2.2) and the solve stage (Algorithm 2: upward and
+ * downward sweeps) with hand-written HIP kernels.
+ *
+ * Conventions for every entry point:
+ *   - Every function returns an int status (HPS_OK = 0 on success).  On failure,
+ *     hps_last_error() returns a thread-local message.  No C++ exception crosses the ABI.
+ *   - Complex arrays are interleaved (re, im) pairs of double (the layout of C99
+ *     double _Complex, std::complex<double> and torch.complex128).  A "complex
+ *     pointer" below is a double* to the first real part.
+ *   - "device" pointers are HIP device memory of the current device; "host" pointers
+ *     are ordinary host memory.  The caller owns every buffer it passes; the library
+ *     owns the factor's memory (freed by hps_free).
+ *   - Work is ordered on the stream given in hps_opts (NULL = the null stream).
+ *     hps_build returns after the factorization has finished (it checks pivots);
+ *     hps_solve returns after enqueueing, so u is valid after the stream syncs.
+ *
+ * Node ordering contract (the paper fixes only I_b = [I_s, I_e, I_n, I_w] in Sec. 2.1
+ * and I_b^tau = [I_1, I_2] in Sec. 2.2; the rest is fixed here):
+ *   - 1D points on [a,b]: x_k = a + (b-a)(1 - cos(k pi/(p-1)))/2, k = 0..p-1 (ascending
+ *     Chebyshev-Lobatto points).
+ *   - Leaves: uniform nx x ny grid, leaf index l = iy*nx + ix.
+ *   - Within a leaf (n = p^2 - 4 nodes, corners dropped): [S (x ascending), E (y
+ *     ascending), N (x ascending), W (y ascending), interior (for j in 1..p-2, for i in
+ *     1..p-2)], i.e. I = [I_b, I_i] with m = p-2 nodes per side, n_b = 4m, n_i = m^2.
+ *   - Root boundary (nt = 2 (nx + ny) m nodes): [S side: leaves ix = 0..nx-1, each x
+ *     ascending; E side: iy = 0..ny-1, y ascending; N side: ix ascending; W side: iy
+ *     ascending].
+ *   - A node on an edge shared by two leaves appears once per leaf in u; both copies
+ *     agree to round-off.
+ */
+#ifndef HPS_H
+#define HPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+  HPS_OK = 0,
+  HPS_E_INVALID = 1,       /* bad argument (sizes, NULL, NaN, Re(eta) == 0, ...)        */
+  HPS_E_NOMEM = 2,         /* device allocation failed                                   */
+  HPS_E_SINGULAR = 3,      /* a zero pivot in a leaf or interface inversion              */
+  HPS_E_DEVICE = 4,        /* a HIP runtime call failed                                  */
+  HPS_E_NOT_CONVERGED = 5, /* mixed-precision refinement did not reach its tolerance     */
+  HPS_E_BUSY = 6           /* no capacity (reserved for admission control)               */
+};
+
+/* Problem geometry: Omega = [x0,x1] x [y0,y1] split into nx x ny equal leaves; nx and
+ * ny are powers of two, 1 <= nx*ny <= 65536 (Sec. 2: uniform partition + binary tree). */
+typedef struct {
+  double x0, x1, y0, y1;
+  int32_t nx, ny;
+} hps_domain;
+
+/* Build options.  hps_default_opts() fills the defaults noted below. */
+typedef struct {
+  int32_t precision;      /* 0 = complex128 throughout (default)                          */
+  int32_t keep_all_R;     /* 1 = keep every box's ItI operator R for inspection (tests);
+                             0 = free children's R after each merge, as Sec. 2.4 does     */
+  int32_t store_root_R;   /* 1 = form the root's R (Algorithm 1 does; the solve does not
+                             use it) (default 1)                                          */
+  int32_t reserved;
+  void* stream;           /* hipStream_t the work is ordered on (default NULL)            */
+} hps_opts;
+
+typedef struct hps_factor hps_factor;
+
+typedef struct {
+  int32_t p, nx, ny, levels; /* levels = log2(nx*ny); level 0 is the root               */
+  int64_t nleaf;             /* nx*ny                                                    */
+  int64_t n_leaf_nodes;      /* nleaf * (p*p - 4): length of one u vector                */
+  int64_t n_interior;        /* nleaf * (p-2)^2: length of one s vector                  */
+  int64_t n_root;            /* 2 (nx + ny)(p - 2): length of one t vector               */
+  int64_t device_bytes;      /* device memory held by the factor                         */
+} hps_factor_info;
+
+/* Which stored operator hps_factor_get copies out. */
+enum {
+  HPS_OP_PSI = 0,   /* leaf:  Psi (n x n_b), B Psi = [I; 0]      Sec. 2.1.1 eq. (hmgsolnopdef) */
+  HPS_OP_Y = 1,     /* leaf:  Y (n x n_i),   B Y = [0; I]        Sec. 2.1.2 eq. (prtsolnopdef) */
+  HPS_OP_R = 2,     /* any box with R kept: ItI operator, rows/cols in the box's [S,E,N,W]
+                       boundary order (each side in ascending coordinate)                       */
+  HPS_OP_WINV = 3,  /* merge: W^{-1}, W = I - R33^b R33^a        Sec. 2.2                       */
+  HPS_OP_PHI_A = 4, /* merge: Phi^a (n3 x nb_parent), eq. (talpha); columns in the parent's
+                       [S,E,N,W] order                                                          */
+  HPS_OP_PHI_B = 5, /* merge: Phi^b (n3 x nb_parent), eq. (tbeta); same column order          */
+  HPS_OP_R33A = 6,  /* merge: R33^a (n3 x n3)                                                   */
+  HPS_OP_R33B = 7,  /* merge: R33^b (n3 x n3)                                                   */
+  HPS_OP_R13A = 8,  /* merge: R13^a (n1 x n3); rows in alpha's boundary order restricted to I1 */
+  HPS_OP_R23B = 9   /* merge: R23^b (n2 x n3); rows in beta's boundary order restricted to I2  */
+};
+
+/* Thread-local message describing the last failure on this thread ("" if none). */
+const char* hps_last_error(void);
+
+/* Library ABI version (major*10000 + minor*100 + patch). */
+int32_t hps_version(void);
+
+/* Fill *opts with the defaults. */
+void hps_default_opts(hps_opts* opts);
+
+/* Node coordinates in the ordering contract above (host pointers, caller-allocated,
+ * each may be NULL):
+ *   xy_leaf      [nx*ny*(p*p-4)][2]   all leaf nodes, leaf-major
+ *   xy_interior  [nx*ny*(p-2)^2][2]   interior nodes only (where c and s are sampled)
+ *   xy_root      [2(nx+ny)(p-2)][2]   root boundary nodes (where t is sampled)
+ *   nrm_root     [2(nx+ny)(p-2)][2]   outward unit normals at xy_root
+ * Sec. 2.1 (classic Chebyshev product grid with the corners removed). */
+int hps_nodes(const hps_domain* dom, int32_t p, double* xy_leaf, double* xy_interior,
+              double* xy_root, double* nrm_root);
+
+/* Precomputation stage (Algorithm 1).
+ *   dom         geometry (host)
+ *   p           Chebyshev points per direction per leaf, 4 <= p <= 16
+ *   kappa       wave number, finite and >= 0
+ *   eta_re/im   impedance parameter eta (Re(eta) != 0, Definition 2.1)
+ *   c_interior  device, [nx*ny*(p-2)^2] real samples of c at the interior nodes in the
+ *               ordering contract (C only enters interior collocation rows, Sec. 2.1);
+ *               read during the call only
+ *   opts        NULL for defaults
+ *   out         receives the factor handle; *out = NULL on failure (nothing leaks)
+ * Errors: HPS_E_INVALID (arguments), HPS_E_NOMEM, HPS_E_SINGULAR (zero pivot in a leaf
+ * or interface inversion), HPS_E_DEVICE. */
+int hps_build(const hps_domain* dom, int32_t p, double kappa, double eta_re,
+              double eta_im, const double* c_interior, const hps_opts* opts,
+              hps_factor** out);
+
+/* Solve stage (Algorithm 2) for nrhs right-hand sides at once.
+ *   s   device complex, [nrhs][n_interior] body load at the interior nodes, or NULL for
+ *       s = 0 (then only the downward sweep runs, as Sec. 2 notes)
+ *   t   device complex, [nrhs][n_root] impedance data on the root boundary
+ *   u   device complex, [nrhs][n_leaf_nodes] output, the solution at every leaf node
+ * s, t and u must not overlap.  The factor is only read: several solves may use one
+ * factor concurrently.  The call allocates its own workspace.
+ * Errors: HPS_E_INVALID (NULL factor/t/u, nrhs < 1), HPS_E_NOMEM, HPS_E_DEVICE. */
+int hps_solve(hps_factor* f, int32_t nrhs, const double* s, const double* t, double* u);
+
+/* Sizes of a factor. */
+int hps_factor_query(const hps_factor* f, hps_factor_info* info);
+
+/* Copy one stored operator to a host buffer (column-major complex, ld = rows).
+ *   what    one of HPS_OP_*
+ *   level   tree level (0 = root, levels = leaves); merges live on levels 0..levels-1
+ *   box     box index within the level, 0..2^level-1, in the level's tree order (the
+ *           children of box q of level l are boxes 2q (alpha: left / bottom) and 2q+1
+ *           (beta: right / top) of level l+1)
+ *   dst     host, capacity dst_len complex entries; rows/cols receive the shape
+ * Errors: HPS_E_INVALID if the operator is not stored (e.g. R freed) or too large. */
+int hps_factor_get(const hps_factor* f, int32_t what, int32_t level, int32_t box,
+                   double* dst, int64_t dst_len, int32_t* rows, int32_t* cols);
+
+/* Leaf range [ix0,ix1) x [iy0,iy1) covered by box `box` of level `level`. */
+int hps_factor_box(const hps_factor* f, int32_t level, int32_t box, int32_t* ix0,
+                   int32_t* ix1, int32_t* iy0, int32_t* iy1);
+
+/* Release a factor (NULL is a no-op). */
+void hps_free(hps_factor* f);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPS_H */

@@ -1,0 +1,811 @@
+// C ABI of the HPS library: plan (tree, index maps, spectral matrices), the build
+// driver (Algorithm 1 as one batched leaf stage plus one batched merge pass per tree
+// level) and the solve driver (Algorithm 2 as one batched pass per level, upward then
+// downward).  Host code; all arithmetic on the hot path runs in the HIP kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/hps.h"
+#include "kernels.hpp"
+
+namespace hps {
+namespace {
+
+thread_local std::string g_err;
+
+// ------------------------------------------------------------------ device buffers
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t b) {
+    release();
+    if (b == 0) return;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Error(e == hipErrorOutOfMemory ? HPS_E_NOMEM : HPS_E_DEVICE,
+                  "device allocation of " + std::to_string(b) + " bytes failed: " +
+                      hipGetErrorString(e));
+    }
+    bytes = b;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  double* d() const { return static_cast<double*>(p); }
+  int* i() const { return static_cast<int*>(p); }
+  long* l() const { return static_cast<long*>(p); }
+};
+
+template <class T>
+void upload(DevBuf& b, const std::vector<T>& v) {
+  b.alloc(v.size() * sizeof(T));
+  if (!v.empty()) HPS_HIP(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+// ------------------------------------------------------------------ spectral matrices
+// Chebyshev-Lobatto points (ascending) and the classic differentiation matrix
+// (Sec. 2.1; Trefethen's construction): off-diagonal (c_i/c_j)(-1)^{i+j}/(x_i-x_j),
+// diagonal = -(sum of the off-diagonal row).
+void cheb(int p, std::vector<double>& x, std::vector<double>& D) {
+  x.resize(p);
+  for (int k = 0; k < p; ++k) x[k] = -std::cos(M_PI * k / (p - 1));
+  D.assign((size_t)p * p, 0.0);
+  for (int i = 0; i < p; ++i) {
+    double ci = (i == 0 || i == p - 1) ? 2.0 : 1.0, rs = 0.0;
+    for (int j = 0; j < p; ++j) {
+      if (i == j) continue;
+      double cj = (j == 0 || j == p - 1) ? 2.0 : 1.0;
+      double v = (ci / cj) * (((i + j) & 1) ? -1.0 : 1.0) / (x[i] - x[j]);
+      D[i + (size_t)p * j] = v;
+      rs += v;
+    }
+    D[i + (size_t)p * i] = -rs;
+  }
+}
+
+// ------------------------------------------------------------------ plan
+struct LevelPlan {
+  int nbox = 0;
+  int wx = 0, wy = 0;     // parent box size in leaves
+  bool split_x = true;
+  int nbc = 0, nbp = 0, n1 = 0, n2 = 0, n3 = 0;
+  std::vector<int> codeA, codeB, perm, i1a, i3a, i2b, i3b;
+  DevBuf dmaps;  // codeA | codeB | perm | i1a | i3a | i2b | i3b
+  const int* dcodeA = nullptr; const int* dcodeB = nullptr; const int* dperm = nullptr;
+  const int* di1a = nullptr; const int* di3a = nullptr; const int* di2b = nullptr;
+  const int* di3b = nullptr;
+  // stored operators of the level (Sec. 2.4)
+  DevBuf Winv, R33a, R33b, R13a, R23b, PhiA, PhiB;
+};
+
+struct Geo { int ix0, iy0, wx, wy; };
+
+bool split_x_rule(int wx, int wy) {
+  if (wy == 1) return true;
+  if (wx == 1) return false;
+  return wx >= wy;  // longer side; ties split x
+}
+
+}  // namespace
+}  // namespace hps
+
+struct hps_factor {
+  int p = 0, m = 0, n = 0, nb = 0, ni = 0;
+  int nx = 0, ny = 0, L = 0, nleaf = 0;
+  double x0 = 0, x1 = 0, y0 = 0, y1 = 0;
+  double kappa = 0, eta_re = 0, eta_im = 0;
+  hipStream_t stream = nullptr;
+  hps_opts opts{};
+  std::vector<std::vector<hps::Geo>> geo;  // per level, tree order
+  std::vector<hps::LevelPlan> lv;          // merges producing level l (l = 0..L-1)
+  std::vector<int> leaf_grid;              // tree-ordered leaf -> grid index
+  hps::DevBuf dleaf_grid, dxoff, duoff, dD;
+  hps::DevBuf BI;                          // [nleaf][n*n] complex: [Psi | Y]
+  std::vector<std::unique_ptr<hps::DevBuf>> R;  // per level ItI operators (L+1 entries)
+  std::vector<int> nbl;                    // boundary size per level
+  size_t bytes() const {
+    size_t t = BI.bytes + dleaf_grid.bytes + dxoff.bytes + duoff.bytes + dD.bytes;
+    for (auto& r : R)
+      if (r) t += r->bytes;
+    for (auto& l : lv)
+      t += l.dmaps.bytes + l.Winv.bytes + l.R33a.bytes + l.R33b.bytes + l.R13a.bytes +
+           l.R23b.bytes + l.PhiA.bytes + l.PhiB.bytes;
+    return t;
+  }
+};
+
+namespace hps {
+namespace {
+
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+void make_plan(hps_factor& f) {
+  const int m = f.m;
+  f.L = ilog2(f.nleaf);
+  f.geo.assign(f.L + 1, {});
+  f.geo[0].push_back({0, 0, f.nx, f.ny});
+  f.lv.clear();
+  f.lv.resize(f.L);
+  f.nbl.assign(f.L + 1, 0);
+  for (int l = 0; l <= f.L; ++l) {
+    const Geo& g0 = f.geo[l][0];
+    f.nbl[l] = 2 * (g0.wx + g0.wy) * m;
+    if (l == f.L) break;
+    const bool sx = split_x_rule(g0.wx, g0.wy);
+    for (const Geo& g : f.geo[l]) {
+      if (sx) {
+        int w = g.wx / 2;
+        f.geo[l + 1].push_back({g.ix0, g.iy0, w, g.wy});
+        f.geo[l + 1].push_back({g.ix0 + w, g.iy0, w, g.wy});
+      } else {
+        int h = g.wy / 2;
+        f.geo[l + 1].push_back({g.ix0, g.iy0, g.wx, h});
+        f.geo[l + 1].push_back({g.ix0, g.iy0 + h, g.wx, h});
+      }
+    }
+    LevelPlan& P = f.lv[l];
+    P.nbox = 1 << l;
+    P.wx = g0.wx;
+    P.wy = g0.wy;
+    P.split_x = sx;
+    const int wx = g0.wx, wy = g0.wy;
+    if (sx) {
+      const int wc = wx / 2;
+      P.nbc = 2 * (wc + wy) * m;
+      P.n3 = wy * m;
+      P.n1 = P.n2 = 2 * wc * m + wy * m;
+      P.codeA.resize(P.nbc);
+      P.codeB.resize(P.nbc);
+      const int S = wc * m, E = wy * m;  // child side lengths (S = N, E = W)
+      for (int t = 0; t < S; ++t) {
+        P.codeA[t] = t;                                   // S_a -> I1
+        P.codeA[S + E + t] = S + t;                       // N_a -> I1
+        P.codeB[t] = t;                                   // S_b -> I2
+        P.codeB[S + E + t] = S + E + t;                   // N_b -> I2
+      }
+      for (int t = 0; t < E; ++t) {
+        P.codeA[S + t] = (1 << 16) | t;                   // E_a -> I3
+        P.codeA[2 * S + E + t] = 2 * S + t;               // W_a -> I1
+        P.codeB[S + t] = S + t;                           // E_b -> I2
+        P.codeB[2 * S + E + t] = (1 << 16) | t;           // W_b -> I3
+      }
+      P.nbp = 2 * (wx + wy) * m;
+      P.perm.resize(P.nbp);
+      const int pS = 0, pE = wx * m, pN = wx * m + wy * m, pW = 2 * wx * m + wy * m;
+      for (int t = 0; t < S; ++t) {
+        P.perm[t] = pS + t;                               // S_a
+        P.perm[S + t] = pN + t;                           // N_a
+        P.perm[P.n1 + t] = pS + S + t;                    // S_b
+        P.perm[P.n1 + S + E + t] = pN + S + t;            // N_b
+      }
+      for (int t = 0; t < E; ++t) {
+        P.perm[2 * S + t] = pW + t;                       // W_a
+        P.perm[P.n1 + S + t] = pE + t;                    // E_b
+      }
+    } else {
+      const int hc = wy / 2;
+      P.nbc = 2 * (wx + hc) * m;
+      P.n3 = wx * m;
+      P.n1 = P.n2 = wx * m + 2 * hc * m;
+      P.codeA.resize(P.nbc);
+      P.codeB.resize(P.nbc);
+      const int S = wx * m, E = hc * m;
+      for (int t = 0; t < S; ++t) {
+        P.codeA[t] = t;                                   // S_a -> I1
+        P.codeA[S + E + t] = (1 << 16) | t;               // N_a -> I3
+        P.codeB[t] = (1 << 16) | t;                       // S_b -> I3
+        P.codeB[S + E + t] = E + t;                       // N_b -> I2
+      }
+      for (int t = 0; t < E; ++t) {
+        P.codeA[S + t] = S + t;                           // E_a -> I1
+        P.codeA[2 * S + E + t] = S + E + t;               // W_a -> I1
+        P.codeB[S + t] = t;                               // E_b -> I2
+        P.codeB[2 * S + E + t] = E + S + t;               // W_b -> I2
+      }
+      P.nbp = 2 * (wx + wy) * m;
+      P.perm.resize(P.nbp);
+      const int pS = 0, pE = wx * m, pN = wx * m + wy * m, pW = 2 * wx * m + wy * m;
+      for (int t = 0; t < S; ++t) {
+        P.perm[t] = pS + t;                               // S_a
+        P.perm[P.n1 + E + t] = pN + t;                    // N_b
+      }
+      for (int t = 0; t < E; ++t) {
+        P.perm[S + t] = pE + t;                           // E_a
+        P.perm[S + E + t] = pW + t;                       // W_a
+        P.perm[P.n1 + t] = pE + E + t;                    // E_b
+        P.perm[P.n1 + E + S + t] = pW + E + t;            // W_b
+      }
+    }
+    P.i1a.assign(P.n1, -1);
+    P.i3a.assign(P.n3, -1);
+    P.i2b.assign(P.n2, -1);
+    P.i3b.assign(P.n3, -1);
+    for (int pos = 0; pos < P.nbc; ++pos) {
+      int ca = P.codeA[pos], cb = P.codeB[pos];
+      if (ca >> 16) P.i3a[ca & 0xffff] = pos; else P.i1a[ca] = pos;
+      if (cb >> 16) P.i3b[cb & 0xffff] = pos; else P.i2b[cb] = pos;
+    }
+    for (int v : P.i1a) if (v < 0) throw Error(HPS_E_INVALID, "plan: I1 map incomplete");
+    for (int v : P.i3a) if (v < 0) throw Error(HPS_E_INVALID, "plan: I3 map incomplete");
+    for (int v : P.i2b) if (v < 0) throw Error(HPS_E_INVALID, "plan: I2 map incomplete");
+    for (int v : P.i3b) if (v < 0) throw Error(HPS_E_INVALID, "plan: I3 map incomplete");
+    std::vector<int> seen(P.nbp, 0);
+    for (int v : P.perm) {
+      if (v < 0 || v >= P.nbp || seen[v]) throw Error(HPS_E_INVALID, "plan: perm not bijective");
+      seen[v] = 1;
+    }
+  }
+  f.leaf_grid.resize(f.nleaf);
+  for (int h = 0; h < f.nleaf; ++h) {
+    const Geo& g = f.geo[f.L][h];
+    f.leaf_grid[h] = g.iy0 * f.nx + g.ix0;
+  }
+}
+
+void upload_plan(hps_factor& f) {
+  for (auto& P : f.lv) {
+    std::vector<int> all;
+    auto app = [&](const std::vector<int>& v) { all.insert(all.end(), v.begin(), v.end()); };
+    app(P.codeA); app(P.codeB); app(P.perm); app(P.i1a); app(P.i3a); app(P.i2b); app(P.i3b);
+    upload(P.dmaps, all);
+    const int* base = P.dmaps.i();
+    P.dcodeA = base; base += P.codeA.size();
+    P.dcodeB = base; base += P.codeB.size();
+    P.dperm = base; base += P.perm.size();
+    P.di1a = base; base += P.i1a.size();
+    P.di3a = base; base += P.i3a.size();
+    P.di2b = base; base += P.i2b.size();
+    P.di3b = base;
+  }
+  upload(f.dleaf_grid, f.leaf_grid);
+  std::vector<long> xoff(f.nleaf), uoff(f.nleaf);
+  for (int h = 0; h < f.nleaf; ++h) {
+    xoff[h] = (long)f.leaf_grid[h] * f.ni;
+    uoff[h] = (long)f.leaf_grid[h] * f.n;
+  }
+  upload(f.dxoff, xoff);
+  upload(f.duoff, uoff);
+  std::vector<double> x, D;
+  cheb(f.p, x, D);
+  const int p = f.p;
+  const double hx = (f.x1 - f.x0) / f.nx, hy = (f.y1 - f.y0) / f.ny;
+  std::vector<double> all(4 * (size_t)p * p, 0.0);
+  for (int e = 0; e < p * p; ++e) {
+    all[e] = D[e] * 2.0 / hx;
+    all[p * p + e] = D[e] * 2.0 / hy;
+  }
+  for (int i = 0; i < p; ++i)
+    for (int j = 0; j < p; ++j) {
+      double sx = 0, sy = 0;
+      for (int k = 0; k < p; ++k) {
+        sx += all[i + p * k] * all[k + p * j];
+        sy += all[p * p + i + p * k] * all[p * p + k + p * j];
+      }
+      all[2 * p * p + i + p * j] = sx;
+      all[3 * p * p + i + p * j] = sy;
+    }
+  upload(f.dD, all);
+}
+
+MergeLevelDesc level_desc(const hps_factor& f, const LevelPlan& P) {
+  MergeLevelDesc d;
+  d.nbox = P.nbox; d.nbc = P.nbc; d.n1 = P.n1; d.n2 = P.n2; d.n3 = P.n3; d.nbp = P.nbp;
+  d.codeA = P.dcodeA; d.codeB = P.dcodeB; d.perm = P.dperm;
+  d.i1a = P.di1a; d.i3a = P.di3a; d.i2b = P.di2b; d.i3b = P.di3b;
+  return d;
+}
+
+void check_info(const DevBuf& info, long cnt, const char* what) {
+  std::vector<int> h(cnt);
+  HPS_HIP(hipMemcpy(h.data(), info.p, cnt * sizeof(int), hipMemcpyDeviceToHost));
+  for (long i = 0; i < cnt; ++i)
+    if (h[i]) throw Error(HPS_E_SINGULAR, std::string(what) + ": zero pivot at step " +
+                                              std::to_string(h[i] - 1) + " of matrix " +
+                                              std::to_string(i));
+}
+
+// ------------------------------------------------------------------ build
+void build_leaves(hps_factor& f, const double* c) {
+  hipStream_t st = f.stream;
+  const long nl = f.nleaf;
+  f.BI.alloc((size_t)nl * f.n * f.n * 16);
+  f.R[f.L].reset(new DevBuf);
+  f.R[f.L]->alloc((size_t)nl * f.nb * f.nb * 16);
+  DevBuf X, Z, S, info, work;
+  X.alloc((size_t)nl * f.ni * f.nb * 8);
+  Z.alloc((size_t)nl * f.ni * f.nb * 8);
+  S.alloc((size_t)nl * f.nb * f.nb * 16);
+  info.alloc((size_t)nl * 2 * sizeof(int));
+  HPS_HIP(hipMemsetAsync(info.p, 0, info.bytes, st));
+  LeafDesc d;
+  d.p = f.p; d.nleaf = f.nleaf; d.kappa = f.kappa; d.eta_re = f.eta_re; d.eta_im = f.eta_im;
+  d.D = f.dD.d(); d.c = c; d.leaf_grid = f.dleaf_grid.i(); d.BI = f.BI.d(); d.R = f.R[f.L]->d();
+  d.X = X.d(); d.Z = Z.d(); d.S = S.d(); d.info = info.i();
+  const long n = f.n, nb = f.nb, ni = f.ni;
+  // process leaves in chunks that fit the grid limit
+  for (long h0 = 0; h0 < nl; h0 += 65535) {
+    const int cnt = (int)std::min<long>(65535, nl - h0);
+    LeafDesc dc = d;
+    dc.nleaf = cnt;
+    dc.leaf_grid = d.leaf_grid + h0;
+    dc.BI = d.BI + 2 * h0 * n * n;
+    dc.R = d.R + 2 * h0 * nb * nb;
+    dc.X = d.X + h0 * ni * nb;
+    dc.Z = d.Z + h0 * ni * nb;
+    dc.S = d.S + 2 * h0 * nb * nb;
+    dc.info = d.info + h0;
+    leaf_inverse_interior(dc, st);
+    leaf_xzs(dc, st);
+    // Psi_b = S^{-1}, written into the top-left block of [Psi | Y]
+    zinv(f.nb, cnt, dc.S, nb, nb * nb, dc.BI, n, n * n, d.info + nl + h0, nullptr, st);
+    leaf_r_from_psib(dc, st);
+    GemmDesc g;
+    // Psi_i = -X Psi_b
+    g = GemmDesc();
+    g.M = ni; g.N = nb; g.K = nb; g.batch = cnt;
+    g.A = dc.X; g.lda = ni; g.sA = ni * nb; g.a_real = true;
+    g.B = dc.BI; g.ldb = n; g.sB = n * n;
+    g.C = dc.BI + 2 * nb; g.ldc = n; g.sC = n * n;
+    g.alpha = -1.0; g.beta = 0.0;
+    zgemm(g, st);
+    // Y_b = -Psi_b Z
+    g = GemmDesc();
+    g.M = nb; g.N = ni; g.K = nb; g.batch = cnt;
+    g.A = dc.BI; g.lda = n; g.sA = n * n;
+    g.B = dc.Z; g.ldb = nb; g.sB = nb * ni; g.b_real = true;
+    g.C = dc.BI + 2 * n * nb; g.ldc = n; g.sC = n * n;
+    g.alpha = -1.0; g.beta = 0.0;
+    zgemm(g, st);
+    // Y_i = A_ii^{-1} - X Y_b
+    g = GemmDesc();
+    g.M = ni; g.N = ni; g.K = nb; g.batch = cnt;
+    g.A = dc.X; g.lda = ni; g.sA = ni * nb; g.a_real = true;
+    g.B = dc.BI + 2 * n * nb; g.ldb = n; g.sB = n * n;
+    g.C = dc.BI + 2 * (nb + n * nb); g.ldc = n; g.sC = n * n;
+    g.alpha = -1.0; g.beta = 1.0;
+    zgemm(g, st);
+  }
+  HPS_HIP(hipStreamSynchronize(st));
+  check_info(info, nl, "leaf interior inversion");
+  std::vector<int> hinfo(nl);
+  HPS_HIP(hipMemcpy(hinfo.data(), info.i() + nl, nl * sizeof(int), hipMemcpyDeviceToHost));
+  for (long i = 0; i < nl; ++i)
+    if (hinfo[i]) throw Error(HPS_E_SINGULAR, "leaf boundary Schur complement singular");
+}
+
+void build_level(hps_factor& f, int l) {
+  hipStream_t st = f.stream;
+  LevelPlan& P = f.lv[l];
+  const long nbox = P.nbox, n1 = P.n1, n2 = P.n2, n3 = P.n3, nbp = P.nbp;
+  const bool form_R = (l > 0) || f.opts.store_root_R;
+  P.Winv.alloc(nbox * n3 * n3 * 16);
+  P.R33a.alloc(nbox * n3 * n3 * 16);
+  P.R33b.alloc(nbox * n3 * n3 * 16);
+  P.R13a.alloc(nbox * n1 * n3 * 16);
+  P.R23b.alloc(nbox * n2 * n3 * 16);
+  P.PhiA.alloc(nbox * n3 * nbp * 16);
+  P.PhiB.alloc(nbox * n3 * nbp * 16);
+  DevBuf R31a, T, info, work;
+  R31a.alloc(nbox * n3 * n1 * 16);
+  T.alloc(nbox * n3 * nbp * 16);
+  info.alloc(nbox * sizeof(int));
+  HPS_HIP(hipMemsetAsync(info.p, 0, info.bytes, st));
+  size_t wb = zinv_workspace_bytes((int)n3, (int)nbox);
+  if (wb) work.alloc(wb);
+  f.R[l].reset(new DevBuf);
+  if (form_R) f.R[l]->alloc(nbox * nbp * nbp * 16);
+
+  MergeLevelDesc d = level_desc(f, P);
+  d.Rc = f.R[l + 1]->d();
+  d.Rp = form_R ? f.R[l]->d() : nullptr;
+  d.R33a = P.R33a.d(); d.R33b = P.R33b.d(); d.R13a = P.R13a.d(); d.R23b = P.R23b.d();
+  d.R31a = R31a.d(); d.T = T.d(); d.PhiB = P.PhiB.d();
+  if (form_R) fill_zero(d.Rp, 2 * nbox * nbp * nbp, st);
+  fill_zero(d.PhiB, 2 * nbox * n3 * nbp, st);
+  merge_extract(d, st);
+  // W = I - R33b R33a   (into the Winv buffer, inverted in place below)
+  fill_identity(P.Winv.d(), (int)n3, n3 * n3, (int)nbox, st);
+  GemmDesc g;
+  g.M = n3; g.N = n3; g.K = n3; g.batch = nbox;
+  g.A = P.R33b.d(); g.lda = n3; g.sA = n3 * n3;
+  g.B = P.R33a.d(); g.ldb = n3; g.sB = n3 * n3;
+  g.C = P.Winv.d(); g.ldc = n3; g.sC = n3 * n3;
+  g.alpha = -1.0; g.beta = 1.0;
+  zgemm(g, st);
+  // T[:, perm(I1)] = R33b R31a  (T[:, perm(I2)] = -R32b was written by the extract)
+  g = GemmDesc();
+  g.M = n3; g.N = n1; g.K = n3; g.batch = nbox;
+  g.A = P.R33b.d(); g.lda = n3; g.sA = n3 * n3;
+  g.B = R31a.d(); g.ldb = n3; g.sB = n3 * n1;
+  g.C = T.d(); g.ldc = n3; g.sC = n3 * nbp; g.ccol = P.dperm;
+  g.alpha = 1.0; g.beta = 0.0;
+  zgemm(g, st);
+  // W^{-1}
+  zinv((int)n3, (int)nbox, P.Winv.d(), n3, n3 * n3, P.Winv.d(), n3, n3 * n3, info.i(),
+       work.p, st);
+  // Phi^a = W^{-1} T   (eq. (talpha))
+  g = GemmDesc();
+  g.M = n3; g.N = nbp; g.K = n3; g.batch = nbox;
+  g.A = P.Winv.d(); g.lda = n3; g.sA = n3 * n3;
+  g.B = T.d(); g.ldb = n3; g.sB = n3 * nbp;
+  g.C = P.PhiA.d(); g.ldc = n3; g.sC = n3 * nbp;
+  g.alpha = 1.0; g.beta = 0.0;
+  zgemm(g, st);
+  // Phi^b = [-R31a, 0] - R33a Phi^a   (eq. (tbeta), short form)
+  g = GemmDesc();
+  g.M = n3; g.N = nbp; g.K = n3; g.batch = nbox;
+  g.A = P.R33a.d(); g.lda = n3; g.sA = n3 * n3;
+  g.B = P.PhiA.d(); g.ldb = n3; g.sB = n3 * nbp;
+  g.C = P.PhiB.d(); g.ldc = n3; g.sC = n3 * nbp;
+  g.alpha = -1.0; g.beta = 1.0;
+  zgemm(g, st);
+  if (form_R) {
+    // R^tau = blockdiag(R11a, R22b) + blockdiag(R13a, R23b) [Phi^a; Phi^b]   (eq. (out))
+    g = GemmDesc();
+    g.M = n1; g.N = nbp; g.K = n3; g.batch = nbox;
+    g.A = P.R13a.d(); g.lda = n1; g.sA = n1 * n3;
+    g.B = P.PhiA.d(); g.ldb = n3; g.sB = n3 * nbp;
+    g.C = f.R[l]->d(); g.ldc = nbp; g.sC = nbp * nbp; g.crow = P.dperm;
+    g.alpha = 1.0; g.beta = 1.0;
+    zgemm(g, st);
+    g.M = n2;
+    g.A = P.R23b.d(); g.lda = n2; g.sA = n2 * n3;
+    g.B = P.PhiB.d();
+    g.crow = P.dperm + n1;
+    zgemm(g, st);
+  }
+  HPS_HIP(hipStreamSynchronize(st));
+  check_info(info, nbox, "interface matrix W");
+  if (!f.opts.keep_all_R) f.R[l + 1].reset();
+}
+
+// ------------------------------------------------------------------ solve
+struct Scratch {
+  std::vector<void*> ptrs;
+  hipStream_t st;
+  explicit Scratch(hipStream_t s) : st(s) {}
+  double* get(size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMallocAsync(&p, bytes, st);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(HPS_E_NOMEM, "solve workspace allocation failed");
+    }
+    ptrs.push_back(p);
+    return static_cast<double*>(p);
+  }
+  ~Scratch() {
+    for (void* p : ptrs) (void)hipFreeAsync(p, st);
+  }
+};
+
+void solve_impl(hps_factor& f, int nrhs, const double* s, const double* t, double* u) {
+  hipStream_t st = f.stream;
+  Scratch ws(st);
+  const long nl = f.nleaf, n = f.n, nb = f.nb, ni = f.ni;
+  const bool up = (s != nullptr);
+  std::vector<double*> h(f.L + 1, nullptr), tt(f.L + 1, nullptr), tta(f.L, nullptr),
+      ttb(f.L, nullptr);
+  double* ut = nullptr;
+  if (up) {
+    ut = ws.get((size_t)nl * n * nrhs * 16);
+    // leaf: u~ = Y s   (Algorithm 2 step (3))
+    SkinnyDesc k;
+    k.M = n; k.K = ni; k.nrhs = nrhs; k.batch = (int)nl;
+    k.A = f.BI.d() + 2 * n * nb; k.lda = n; k.sA = n * n;
+    k.X = s; k.ldx = nl * ni; k.xoff = f.dxoff.l();
+    k.C = ut; k.ldc = n; k.sC = n * nrhs;
+    zgemm_skinny(k, st);
+    h[f.L] = ws.get((size_t)nl * nb * nrhs * 16);
+    leaf_h_from_u(f.nleaf, f.n, f.nb, nrhs, f.eta_re, f.eta_im, ut, h[f.L], st);
+    // merges, bottom-up   (steps (5)-(7))
+    for (int l = f.L - 1; l >= 0; --l) {
+      LevelPlan& P = f.lv[l];
+      MergeLevelDesc d = level_desc(f, P);
+      const long nbox = P.nbox, n1 = P.n1, n2 = P.n2, n3 = P.n3, nbp = P.nbp;
+      double* h3a = ws.get((size_t)nbox * n3 * nrhs * 16);
+      double* v = ws.get((size_t)nbox * n3 * nrhs * 16);
+      tta[l] = ws.get((size_t)nbox * n3 * nrhs * 16);
+      ttb[l] = ws.get((size_t)nbox * n3 * nrhs * 16);
+      h[l] = ws.get((size_t)nbox * nbp * nrhs * 16);
+      up_gather(d, nrhs, h[l + 1], h3a, v, ttb[l], h[l], st);
+      // v = R33b h3a - h3b
+      SkinnyDesc k;
+      k.M = n3; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox;
+      k.A = P.R33b.d(); k.lda = n3; k.sA = n3 * n3;
+      k.X = h3a; k.ldx = n3; k.sX = n3 * nrhs;
+      k.C = v; k.ldc = n3; k.sC = n3 * nrhs; k.accumulate = true;
+      zgemm_skinny(k, st);
+      // t~3a = W^{-1} v
+      k = SkinnyDesc();
+      k.M = n3; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox;
+      k.A = P.Winv.d(); k.lda = n3; k.sA = n3 * n3;
+      k.X = v; k.ldx = n3; k.sX = n3 * nrhs;
+      k.C = tta[l]; k.ldc = n3; k.sC = n3 * nrhs;
+      zgemm_skinny(k, st);
+      // t~3b = -h3a - R33a t~3a
+      k = SkinnyDesc();
+      k.M = n3; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox;
+      k.A = P.R33a.d(); k.lda = n3; k.sA = n3 * n3;
+      k.X = tta[l]; k.ldx = n3; k.sX = n3 * nrhs;
+      k.C = ttb[l]; k.ldc = n3; k.sC = n3 * nrhs; k.accumulate = true; k.alpha = -1.0;
+      zgemm_skinny(k, st);
+      if (l > 0) {
+        // h^tau = [h1a + R13a t~3a ; h2b + R23b t~3b]   (eq. (flux_part))
+        k = SkinnyDesc();
+        k.M = n1; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox;
+        k.A = P.R13a.d(); k.lda = n1; k.sA = n1 * n3;
+        k.X = tta[l]; k.ldx = n3; k.sX = n3 * nrhs;
+        k.C = h[l]; k.ldc = nbp; k.sC = nbp * nrhs; k.crow = P.dperm; k.accumulate = true;
+        zgemm_skinny(k, st);
+        k.M = n2;
+        k.A = P.R23b.d(); k.lda = n2; k.sA = n2 * n3;
+        k.X = ttb[l];
+        k.crow = P.dperm + n1;
+        zgemm_skinny(k, st);
+      }
+    }
+  }
+  // downward pass   (steps (10)-(18))
+  for (int l = 0; l < f.L; ++l) {
+    LevelPlan& P = f.lv[l];
+    MergeLevelDesc d = level_desc(f, P);
+    const long nbox = P.nbox, n3 = P.n3, nbp = P.nbp, nbc = P.nbc;
+    const double* tp = (l == 0) ? t : tt[l];
+    const long sp = nbp * nrhs;
+    tt[l + 1] = ws.get((size_t)2 * nbox * nbc * nrhs * 16);
+    down_scatter(d, nrhs, tp, nbp, tt[l + 1], st);
+    for (int side = 0; side < 2; ++side) {
+      SkinnyDesc k;
+      k.M = n3; k.K = nbp; k.nrhs = nrhs; k.batch = (int)nbox;
+      k.A = side ? P.PhiB.d() : P.PhiA.d(); k.lda = n3; k.sA = n3 * nbp;
+      k.X = tp; k.ldx = nbp; k.sX = sp;
+      k.C = tt[l + 1] + 2 * (side ? nbc * nrhs : 0); k.ldc = nbc; k.sC = 2 * nbc * nrhs;
+      k.crow = side ? P.di3b : P.di3a;
+      if (up) {
+        k.C0 = side ? ttb[l] : tta[l]; k.ld0 = n3; k.s0 = n3 * nrhs;
+      }
+      zgemm_skinny(k, st);
+    }
+  }
+  // leaves: u = Psi t + u~   (step (13))
+  {
+    SkinnyDesc k;
+    k.M = n; k.K = nb; k.nrhs = nrhs; k.batch = (int)nl;
+    k.A = f.BI.d(); k.lda = n; k.sA = n * n;
+    k.X = (f.L == 0) ? t : tt[f.L]; k.ldx = nb; k.sX = nb * nrhs;
+    k.C = u; k.ldc = nl * n; k.coff = f.duoff.l();
+    if (up) {
+      k.C0 = ut; k.ld0 = n; k.s0 = n * nrhs;
+    }
+    zgemm_skinny(k, st);
+  }
+}
+
+template <class F>
+int guard(F&& fn) {
+  try {
+    g_err.clear();
+    fn();
+    return HPS_OK;
+  } catch (const Error& e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return HPS_E_NOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return HPS_E_DEVICE;
+  }
+}
+
+void validate_domain(const hps_domain* dom, int p) {
+  if (!dom) throw Error(HPS_E_INVALID, "domain is NULL");
+  if (p < 4 || p > 16) throw Error(HPS_E_INVALID, "p must be in [4, 16]");
+  if (!is_pow2(dom->nx) || !is_pow2(dom->ny))
+    throw Error(HPS_E_INVALID, "nx and ny must be powers of two");
+  if ((long)dom->nx * dom->ny > 65536) throw Error(HPS_E_INVALID, "nx*ny must be <= 65536");
+  if (!(std::isfinite(dom->x0) && std::isfinite(dom->x1) && std::isfinite(dom->y0) &&
+        std::isfinite(dom->y1)) ||
+      !(dom->x1 > dom->x0) || !(dom->y1 > dom->y0))
+    throw Error(HPS_E_INVALID, "domain bounds must be finite with x1 > x0, y1 > y0");
+}
+
+}  // namespace
+}  // namespace hps
+
+using namespace hps;
+
+extern "C" {
+
+const char* hps_last_error(void) { return g_err.c_str(); }
+
+int32_t hps_version(void) { return 10000; }
+
+void hps_default_opts(hps_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = 0;
+  o->keep_all_R = 0;
+  o->store_root_R = 1;
+  o->stream = nullptr;
+}
+
+int hps_nodes(const hps_domain* dom, int32_t p, double* xy_leaf, double* xy_interior,
+              double* xy_root, double* nrm_root) {
+  return guard([&] {
+    validate_domain(dom, p);
+    std::vector<double> x, D;
+    cheb(p, x, D);
+    const int m = p - 2, n = p * p - 4, nb = 4 * m, nx = dom->nx, ny = dom->ny;
+    const double hx = (dom->x1 - dom->x0) / nx, hy = (dom->y1 - dom->y0) / ny;
+    auto X = [&](int ix, int i) { return dom->x0 + ix * hx + hx * (1.0 + x[i]) / 2.0; };
+    auto Y = [&](int iy, int j) { return dom->y0 + iy * hy + hy * (1.0 + x[j]) / 2.0; };
+    for (int iy = 0; iy < ny; ++iy)
+      for (int ix = 0; ix < nx; ++ix) {
+        const long l = (long)iy * nx + ix;
+        std::vector<double> pts;
+        pts.reserve(2 * n);
+        for (int i = 1; i <= m; ++i) { pts.push_back(X(ix, i)); pts.push_back(Y(iy, 0)); }
+        for (int j = 1; j <= m; ++j) { pts.push_back(X(ix, p - 1)); pts.push_back(Y(iy, j)); }
+        for (int i = 1; i <= m; ++i) { pts.push_back(X(ix, i)); pts.push_back(Y(iy, p - 1)); }
+        for (int j = 1; j <= m; ++j) { pts.push_back(X(ix, 0)); pts.push_back(Y(iy, j)); }
+        for (int j = 1; j <= m; ++j)
+          for (int i = 1; i <= m; ++i) { pts.push_back(X(ix, i)); pts.push_back(Y(iy, j)); }
+        if (xy_leaf) std::memcpy(xy_leaf + 2 * l * n, pts.data(), 2 * n * sizeof(double));
+        if (xy_interior)
+          std::memcpy(xy_interior + 2 * l * m * m, pts.data() + 2 * nb, 2 * m * m * sizeof(double));
+      }
+    long k = 0;
+    auto put = [&](double px, double py, double nxv, double nyv) {
+      if (xy_root) { xy_root[2 * k] = px; xy_root[2 * k + 1] = py; }
+      if (nrm_root) { nrm_root[2 * k] = nxv; nrm_root[2 * k + 1] = nyv; }
+      ++k;
+    };
+    for (int ix = 0; ix < nx; ++ix)
+      for (int i = 1; i <= m; ++i) put(X(ix, i), Y(0, 0), 0.0, -1.0);
+    for (int iy = 0; iy < ny; ++iy)
+      for (int j = 1; j <= m; ++j) put(X(nx - 1, p - 1), Y(iy, j), 1.0, 0.0);
+    for (int ix = 0; ix < nx; ++ix)
+      for (int i = 1; i <= m; ++i) put(X(ix, i), Y(ny - 1, p - 1), 0.0, 1.0);
+    for (int iy = 0; iy < ny; ++iy)
+      for (int j = 1; j <= m; ++j) put(X(0, 0), Y(iy, j), -1.0, 0.0);
+  });
+}
+
+int hps_build(const hps_domain* dom, int32_t p, double kappa, double eta_re, double eta_im,
+              const double* c_interior, const hps_opts* opts, hps_factor** out) {
+  if (out) *out = nullptr;
+  return guard([&] {
+    if (!out) throw Error(HPS_E_INVALID, "out is NULL");
+    validate_domain(dom, p);
+    if (!c_interior) throw Error(HPS_E_INVALID, "c_interior is NULL");
+    if (!std::isfinite(kappa) || kappa < 0) throw Error(HPS_E_INVALID, "kappa must be finite, >= 0");
+    if (!std::isfinite(eta_re) || !std::isfinite(eta_im) || eta_re == 0.0)
+      throw Error(HPS_E_INVALID, "eta must be finite with Re(eta) != 0");
+    std::unique_ptr<hps_factor> f(new hps_factor);
+    if (opts) f->opts = *opts; else hps_default_opts(&f->opts);
+    if (f->opts.precision != 0) throw Error(HPS_E_INVALID, "unsupported precision mode");
+    f->p = p; f->m = p - 2; f->n = p * p - 4; f->nb = 4 * (p - 2); f->ni = (p - 2) * (p - 2);
+    f->nx = dom->nx; f->ny = dom->ny; f->nleaf = dom->nx * dom->ny;
+    f->x0 = dom->x0; f->x1 = dom->x1; f->y0 = dom->y0; f->y1 = dom->y1;
+    f->kappa = kappa; f->eta_re = eta_re; f->eta_im = eta_im;
+    f->stream = static_cast<hipStream_t>(f->opts.stream);
+    make_plan(*f);
+    upload_plan(*f);
+    f->R.clear();
+    f->R.resize(f->L + 1);
+    build_leaves(*f, c_interior);
+    for (int l = f->L - 1; l >= 0; --l) build_level(*f, l);
+    *out = f.release();
+  });
+}
+
+int hps_solve(hps_factor* f, int32_t nrhs, const double* s, const double* t, double* u) {
+  return guard([&] {
+    if (!f) throw Error(HPS_E_INVALID, "factor is NULL");
+    if (!t || !u) throw Error(HPS_E_INVALID, "t and u must be non-NULL");
+    if (nrhs < 1) throw Error(HPS_E_INVALID, "nrhs must be >= 1");
+    solve_impl(*f, nrhs, s, t, u);
+  });
+}
+
+int hps_factor_query(const hps_factor* f, hps_factor_info* info) {
+  return guard([&] {
+    if (!f || !info) throw Error(HPS_E_INVALID, "NULL argument");
+    info->p = f->p; info->nx = f->nx; info->ny = f->ny; info->levels = f->L;
+    info->nleaf = f->nleaf;
+    info->n_leaf_nodes = (int64_t)f->nleaf * f->n;
+    info->n_interior = (int64_t)f->nleaf * f->ni;
+    info->n_root = 2L * (f->nx + f->ny) * f->m;
+    info->device_bytes = (int64_t)f->bytes();
+  });
+}
+
+int hps_factor_box(const hps_factor* f, int32_t level, int32_t box, int32_t* ix0, int32_t* ix1,
+                   int32_t* iy0, int32_t* iy1) {
+  return guard([&] {
+    if (!f) throw Error(HPS_E_INVALID, "factor is NULL");
+    if (level < 0 || level > f->L || box < 0 || box >= (1 << level))
+      throw Error(HPS_E_INVALID, "level/box out of range");
+    const Geo& g = f->geo[level][box];
+    if (ix0) *ix0 = g.ix0;
+    if (ix1) *ix1 = g.ix0 + g.wx;
+    if (iy0) *iy0 = g.iy0;
+    if (iy1) *iy1 = g.iy0 + g.wy;
+  });
+}
+
+int hps_factor_get(const hps_factor* f, int32_t what, int32_t level, int32_t box, double* dst,
+                   int64_t dst_len, int32_t* rows, int32_t* cols) {
+  return guard([&] {
+    if (!f || !dst) throw Error(HPS_E_INVALID, "NULL argument");
+    if (level < 0 || level > f->L || box < 0 || box >= (1 << level))
+      throw Error(HPS_E_INVALID, "level/box out of range");
+    const double* src = nullptr;
+    long r = 0, c = 0, ld = 0;
+    long off = 0;
+    if (what == HPS_OP_PSI || what == HPS_OP_Y) {
+      if (level != f->L) throw Error(HPS_E_INVALID, "Psi/Y exist on the leaf level only");
+      src = f->BI.d();
+      r = f->n; ld = f->n;
+      c = (what == HPS_OP_PSI) ? f->nb : f->ni;
+      off = (long)box * f->n * f->n + (what == HPS_OP_PSI ? 0 : (long)f->n * f->nb);
+    } else if (what == HPS_OP_R) {
+      if (!f->R[level] || !f->R[level]->p) throw Error(HPS_E_INVALID, "R of this level is not kept");
+      src = f->R[level]->d();
+      r = c = ld = f->nbl[level];
+      off = (long)box * r * r;
+    } else {
+      if (level >= f->L) throw Error(HPS_E_INVALID, "merge operators live on levels < leaves");
+      const LevelPlan& P = f->lv[level];
+      const DevBuf* b = nullptr;
+      switch (what) {
+        case HPS_OP_WINV: b = &P.Winv; r = c = P.n3; break;
+        case HPS_OP_PHI_A: b = &P.PhiA; r = P.n3; c = P.nbp; break;
+        case HPS_OP_PHI_B: b = &P.PhiB; r = P.n3; c = P.nbp; break;
+        case HPS_OP_R33A: b = &P.R33a; r = c = P.n3; break;
+        case HPS_OP_R33B: b = &P.R33b; r = c = P.n3; break;
+        case HPS_OP_R13A: b = &P.R13a; r = P.n1; c = P.n3; break;
+        case HPS_OP_R23B: b = &P.R23b; r = P.n2; c = P.n3; break;
+        default: throw Error(HPS_E_INVALID, "unknown operator id");
+      }
+      src = b->d();
+      ld = r;
+      off = (long)box * r * c;
+    }
+    if (rows) *rows = (int32_t)r;
+    if (cols) *cols = (int32_t)c;
+    if (dst_len < r * c) throw Error(HPS_E_INVALID, "destination too small");
+    HPS_HIP(hipStreamSynchronize(f->stream));
+    HPS_HIP(hipMemcpy2D(dst, r * 16, src + 2 * off, ld * 16, r * 16, c, hipMemcpyDeviceToHost));
+  });
+}
+
+void hps_free(hps_factor* f) { delete f; }
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Host-side launchers of the HPS HIP kernels (gfx950).  Every launcher enqueues on the
+// given stream and checks the launch; none synchronizes.
+#pragma once
+
+#include "common.hpp"
+
+namespace hps {
+
+// ------------------------------------------------------------------ batched GEMM
+// C_b = beta * C_b + alpha * A_b * B_b   (b = 0..batch-1), column-major.
+// A is M x K, B is K x N, C is M x N.  A and B may be real (double) or complex
+// (interleaved double2); C is complex.  Leading dimensions and batch strides are in
+// elements of the operand's own type.  Optional int32 maps scatter C: element (i, j)
+// lives at C_b[crow[i] + ldc * ccol[j]] (identity where the map is null).
+struct GemmDesc {
+  int M = 0, N = 0, K = 0, batch = 1;
+  const double* A = nullptr; long lda = 0, sA = 0; bool a_real = false;
+  const double* B = nullptr; long ldb = 0, sB = 0; bool b_real = false;
+  double* C = nullptr; long ldc = 0, sC = 0;
+  double alpha = 1.0, beta = 0.0;
+  const int* crow = nullptr;
+  const int* ccol = nullptr;
+};
+void zgemm(const GemmDesc& d, hipStream_t st);
+
+// ------------------------------------------------------------------ skinny GEMM (solve)
+// out_b(i, r) = alpha * sum_k A_b(i, k) X_b(k, r)  +  addend(i, r),   r < nrhs,
+// where addend is C0_b(i, r) if C0 is given, the current C_b value if accumulate is
+// set, else 0.  A complex M x K (lda, sA).  X complex (ldx, sX); if xoff is given it
+// replaces b*sX.  C complex with ldc, sC (or coff), optional row map crow.  C0
+// complex with ld0, s0 (or c0off).  All offsets in complex elements.
+struct SkinnyDesc {
+  int M = 0, K = 0, nrhs = 1, batch = 1;
+  const double* A = nullptr; long lda = 0, sA = 0;
+  const double* X = nullptr; long ldx = 0, sX = 0; const long* xoff = nullptr;
+  double* C = nullptr; long ldc = 0, sC = 0; const long* coff = nullptr;
+  const int* crow = nullptr;
+  const double* C0 = nullptr; long ld0 = 0, s0 = 0; const long* c0off = nullptr;
+  bool accumulate = false;
+  double alpha = 1.0;
+};
+void zgemm_skinny(const SkinnyDesc& d, hipStream_t st);
+
+// ------------------------------------------------------------------ complex inversion
+// Batched Gauss-Jordan inversion with partial pivoting of n x n complex matrices.
+// In: A_b (lda, sA).  Out: Inv_b (ldo, sO); may alias A only for the small path.
+// info[b] is set to (k+1) if the k-th pivot is exactly zero (info must be zeroed by
+// the caller).  Workspace is allocated by the caller through zinv_workspace_bytes.
+size_t zinv_workspace_bytes(int n, int batch);
+void zinv(int n, int batch, const double* A, long lda, long sA, double* Out, long ldo,
+          long sO, int* info, void* work, hipStream_t st);
+
+// ------------------------------------------------------------------ leaf stage
+struct LeafDesc {
+  int p = 0, nleaf = 0;
+  double kappa = 0, eta_re = 0, eta_im = 0;
+  const double* D = nullptr;     // device [4][p*p]: Dx1, Dy1, Dxx, Dyy (column-major)
+  const double* c = nullptr;     // device [nleaf * ni] in user (grid) leaf order
+  const int* leaf_grid = nullptr;  // device [nleaf]: grid index of tree-ordered leaf h
+  double* BI = nullptr;          // device [nleaf][n*n] complex: [Psi | Y]
+  double* R = nullptr;           // device [nleaf][nb*nb] complex
+  double* X = nullptr;           // scratch [nleaf][ni*nb] real
+  double* Z = nullptr;           // scratch [nleaf][nb*ni] real
+  double* S = nullptr;           // scratch [nleaf][nb*nb] complex
+  int* info = nullptr;           // device [nleaf]
+};
+void leaf_inverse_interior(const LeafDesc& d, hipStream_t st);  // Ainv -> Y_i block
+void leaf_xzs(const LeafDesc& d, hipStream_t st);               // X, Z, S
+void leaf_r_from_psib(const LeafDesc& d, hipStream_t st);       // R = I - 2 i eta Psi_b
+
+// ------------------------------------------------------------------ merge helpers
+struct MergeLevelDesc {
+  int nbox = 0;          // number of merges on the level
+  int nbc = 0;           // children's boundary size
+  int n1 = 0, n2 = 0, n3 = 0, nbp = 0;
+  const int* codeA = nullptr;  // device [nbc]: (cls << 16) | k, cls 0 = I1, 1 = I3
+  const int* codeB = nullptr;  // device [nbc]: cls 0 = I2, 1 = I3
+  const int* perm = nullptr;   // device [nbp]: [I1; I2] position -> parent canonical
+  const int* i1a = nullptr;    // device [n1]: I1 positions in alpha's boundary
+  const int* i3a = nullptr;    // device [n3]: I3 positions in alpha's boundary
+  const int* i2b = nullptr;    // device [n2]: I2 positions in beta's boundary
+  const int* i3b = nullptr;    // device [n3]: I3 positions in beta's boundary
+  const double* Rc = nullptr;  // children's R, [2*nbox][nbc*nbc]
+  double* Rp = nullptr;        // parent R [nbox][nbp*nbp] (may be null: not formed)
+  double* R33a = nullptr; double* R33b = nullptr;
+  double* R13a = nullptr; double* R23b = nullptr;
+  double* R31a = nullptr;      // scratch [nbox][n3*n1]
+  double* T = nullptr;         // scratch [nbox][n3*nbp]
+  double* PhiB = nullptr;      // [nbox][n3*nbp]
+};
+void fill_zero(double* p, long ndouble, hipStream_t st);
+void fill_identity(double* p, int n, long stride, int batch, hipStream_t st);
+void merge_extract(const MergeLevelDesc& d, hipStream_t st);
+
+// ------------------------------------------------------------------ solve helpers
+// h_b = -2 i eta * u_b[0:nb]  for every leaf (u_b is n x nrhs, h_b is nb x nrhs)
+void leaf_h_from_u(int nleaf, int n, int nb, int nrhs, double eta_re, double eta_im,
+                   const double* u, double* h, hipStream_t st);
+// Upward gather of one level: h3a, -h3a (into ttb), -h3b (into v), and the h1/h2 parts
+// of the parent's h.  hc: children's h [2*nbox][nbc x nrhs]; hp: [nbox][nbp x nrhs].
+void up_gather(const MergeLevelDesc& d, int nrhs, const double* hc, double* h3a,
+               double* v, double* ttb, double* hp, hipStream_t st);
+// Downward scatter of one level: children's t on I1 / I2 from the parent's t.
+void down_scatter(const MergeLevelDesc& d, int nrhs, const double* tp, long ldp,
+                  double* tc, hipStream_t st);
+
+}  // namespace hps

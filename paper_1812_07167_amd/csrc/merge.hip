@@ -1,0 +1,176 @@
+// Merge-stage data movement (Sec. 2.2, Algorithm 1 step (6)) and the solve-stage
+// gathers/scatters of Algorithm 2.
+//
+// Every box keeps its boundary in the canonical order [S, E, N, W] (each side in
+// ascending coordinate).  For a merge, codeA/codeB classify each child boundary
+// position as I1/I2 (exterior) or I3 (shared) with its index inside that set, and
+// perm maps the parent's boundary [I1; I2] (the order Sec. 2.2 gives it) to the
+// parent's canonical order.  The extract kernel reads each child R once and writes
+// the blocks R33, R31, R13 (alpha), R33, R32, R23 (beta) and the diagonal blocks
+// R11, R22 straight into the parent R (pre-zeroed), so no block is copied twice.
+#include "kernels.hpp"
+
+namespace hps {
+namespace {
+
+__global__ void fill_zero_kernel(double* p, long n) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = 0.0;
+}
+
+__global__ void fill_identity_kernel(double2* p, int n, long stride, int batch) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long tot = (long)n * n * batch;
+  if (e >= tot) return;
+  long b = e / ((long)n * n);
+  int loc = e % ((long)n * n);
+  int i = loc % n, j = loc / n;
+  p[b * stride + loc] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+}
+
+__global__ void extract_kernel(MergeLevelDesc d) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nn = (long)d.nbc * d.nbc;
+  if (e >= nn) return;
+  const long q = blockIdx.y;
+  const int side = blockIdx.z;
+  const int i = e % d.nbc, j = e / d.nbc;
+  const double2* R = reinterpret_cast<const double2*>(d.Rc) + (2 * q + side) * nn;
+  const double2 v = R[e];
+  const int n1 = d.n1, n2 = d.n2, n3 = d.n3, nbp = d.nbp;
+  if (side == 0) {
+    const int ci = d.codeA[i], cj = d.codeA[j];
+    const int ti = ci >> 16, ki = ci & 0xffff, tj = cj >> 16, kj = cj & 0xffff;
+    if (ti == 1 && tj == 1) {
+      reinterpret_cast<double2*>(d.R33a)[q * n3 * n3 + ki + (long)n3 * kj] = v;
+    } else if (ti == 1 && tj == 0) {
+      reinterpret_cast<double2*>(d.R31a)[q * n3 * n1 + ki + (long)n3 * kj] = v;
+      reinterpret_cast<double2*>(d.PhiB)[q * n3 * nbp + ki + (long)n3 * d.perm[kj]] =
+          make_double2(-v.x, -v.y);
+    } else if (ti == 0 && tj == 1) {
+      reinterpret_cast<double2*>(d.R13a)[q * n1 * n3 + ki + (long)n1 * kj] = v;
+    } else if (d.Rp) {
+      reinterpret_cast<double2*>(d.Rp)[q * nbp * nbp + d.perm[ki] + (long)nbp * d.perm[kj]] = v;
+    }
+  } else {
+    const int ci = d.codeB[i], cj = d.codeB[j];
+    const int ti = ci >> 16, ki = ci & 0xffff, tj = cj >> 16, kj = cj & 0xffff;
+    if (ti == 1 && tj == 1) {
+      reinterpret_cast<double2*>(d.R33b)[q * n3 * n3 + ki + (long)n3 * kj] = v;
+    } else if (ti == 1 && tj == 0) {
+      reinterpret_cast<double2*>(d.T)[q * n3 * nbp + ki + (long)n3 * d.perm[n1 + kj]] =
+          make_double2(-v.x, -v.y);
+    } else if (ti == 0 && tj == 1) {
+      reinterpret_cast<double2*>(d.R23b)[q * n2 * n3 + ki + (long)n2 * kj] = v;
+    } else if (d.Rp) {
+      reinterpret_cast<double2*>(d.Rp)[q * nbp * nbp + d.perm[n1 + ki] +
+                                       (long)nbp * d.perm[n1 + kj]] = v;
+    }
+  }
+}
+
+__global__ void leaf_h_kernel(int nleaf, int n, int nb, int nrhs, double er, double ei,
+                              const double2* u, double2* h) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long per = (long)nb * nrhs;
+  if (e >= per * nleaf) return;
+  const long b = e / per;
+  const int loc = e % per;
+  const int k = loc % nb, r = loc / nb;
+  const double2 x = u[b * (long)n * nrhs + k + (long)n * r];
+  h[e] = cmul(cmk(2.0 * ei, -2.0 * er), x);
+}
+
+__global__ void up_gather_kernel(MergeLevelDesc d, int nrhs, const double2* hc, double2* h3a,
+                                 double2* v, double2* ttb, double2* hp) {
+  const long q = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n1 = d.n1, n2 = d.n2, n3 = d.n3, nbc = d.nbc, nbp = d.nbp;
+  const int rows = n3 + n1 + n2;
+  if (e >= rows * nrhs) return;
+  const int k = e % rows, r = e / rows;
+  const double2* ha = hc + (2 * q) * (long)nbc * nrhs;
+  const double2* hb = hc + (2 * q + 1) * (long)nbc * nrhs;
+  if (k < n3) {
+    const double2 a = ha[d.i3a[k] + (long)nbc * r];
+    const double2 bb = hb[d.i3b[k] + (long)nbc * r];
+    const long o = q * (long)n3 * nrhs + k + (long)n3 * r;
+    h3a[o] = a;
+    ttb[o] = make_double2(-a.x, -a.y);
+    v[o] = make_double2(-bb.x, -bb.y);
+  } else if (k < n3 + n1) {
+    const int kk = k - n3;
+    hp[q * (long)nbp * nrhs + d.perm[kk] + (long)nbp * r] = ha[d.i1a[kk] + (long)nbc * r];
+  } else {
+    const int kk = k - n3 - n1;
+    hp[q * (long)nbp * nrhs + d.perm[n1 + kk] + (long)nbp * r] = hb[d.i2b[kk] + (long)nbc * r];
+  }
+}
+
+__global__ void down_scatter_kernel(MergeLevelDesc d, int nrhs, const double2* tp, long ldp,
+                                    double2* tc) {
+  const long q = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n1 = d.n1, n2 = d.n2, nbc = d.nbc, nbp = d.nbp;
+  const int rows = n1 + n2;
+  if (e >= rows * nrhs) return;
+  const int k = e % rows, r = e / rows;
+  const double2* t = tp + q * (long)nbp * nrhs;
+  if (k < n1) {
+    tc[(2 * q) * (long)nbc * nrhs + d.i1a[k] + (long)nbc * r] = t[d.perm[k] + ldp * r];
+  } else {
+    const int kk = k - n1;
+    tc[(2 * q + 1) * (long)nbc * nrhs + d.i2b[kk] + (long)nbc * r] = t[d.perm[n1 + kk] + ldp * r];
+  }
+}
+
+}  // namespace
+
+void fill_zero(double* p, long n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, p, n);
+  HPS_LAUNCH_CHECK();
+}
+
+void fill_identity(double* p, int n, long stride, int batch, hipStream_t st) {
+  long tot = (long)n * n * batch;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(fill_identity_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, st,
+                     reinterpret_cast<double2*>(p), n, stride, batch);
+  HPS_LAUNCH_CHECK();
+}
+
+void merge_extract(const MergeLevelDesc& d, hipStream_t st) {
+  long nn = (long)d.nbc * d.nbc;
+  hipLaunchKernelGGL(extract_kernel, dim3(cdiv(nn, 256), d.nbox, 2), dim3(256), 0, st, d);
+  HPS_LAUNCH_CHECK();
+}
+
+void leaf_h_from_u(int nleaf, int n, int nb, int nrhs, double er, double ei, const double* u,
+                   double* h, hipStream_t st) {
+  long tot = (long)nleaf * nb * nrhs;
+  hipLaunchKernelGGL(leaf_h_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, st, nleaf, n, nb, nrhs,
+                     er, ei, reinterpret_cast<const double2*>(u), reinterpret_cast<double2*>(h));
+  HPS_LAUNCH_CHECK();
+}
+
+void up_gather(const MergeLevelDesc& d, int nrhs, const double* hc, double* h3a, double* v,
+               double* ttb, double* hp, hipStream_t st) {
+  long rows = (long)(d.n3 + d.n1 + d.n2) * nrhs;
+  hipLaunchKernelGGL(up_gather_kernel, dim3(cdiv(rows, 256), d.nbox), dim3(256), 0, st, d, nrhs,
+                     reinterpret_cast<const double2*>(hc), reinterpret_cast<double2*>(h3a),
+                     reinterpret_cast<double2*>(v), reinterpret_cast<double2*>(ttb),
+                     reinterpret_cast<double2*>(hp));
+  HPS_LAUNCH_CHECK();
+}
+
+void down_scatter(const MergeLevelDesc& d, int nrhs, const double* tp, long ldp, double* tc,
+                  hipStream_t st) {
+  long rows = (long)(d.n1 + d.n2) * nrhs;
+  hipLaunchKernelGGL(down_scatter_kernel, dim3(cdiv(rows, 256), d.nbox), dim3(256), 0, st, d,
+                     nrhs, reinterpret_cast<const double2*>(tp), ldp,
+                     reinterpret_cast<double2*>(tc));
+  HPS_LAUNCH_CHECK();
+}
+
+}  // namespace hps

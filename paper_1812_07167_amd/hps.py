@@ -1,0 +1,192 @@
+"""Thin ctypes binding of libhps.so (include/hps.h).
+
+Argument marshalling only: every step of the build and the solve runs in the library's
+HIP kernels.  Torch is used for device memory and streams: the device-pointer entry
+points take torch tensors on the GPU and pass their data pointers through.  There is no
+CPU fallback; calling a compute entry point without the built library raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhps.so")
+
+HPS_OK, HPS_E_INVALID, HPS_E_NOMEM, HPS_E_SINGULAR, HPS_E_DEVICE, HPS_E_NOT_CONVERGED, HPS_E_BUSY = range(7)
+OP_PSI, OP_Y, OP_R, OP_WINV, OP_PHI_A, OP_PHI_B, OP_R33A, OP_R33B, OP_R13A, OP_R23B = range(10)
+
+EXPORTS = [
+    "hps_last_error", "hps_version", "hps_default_opts", "hps_nodes", "hps_build",
+    "hps_solve", "hps_factor_query", "hps_factor_get", "hps_factor_box", "hps_free",
+]
+
+
+class HPSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"HPS error {code}: {msg}")
+        self.code = code
+
+
+class Domain(C.Structure):
+    _fields_ = [("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+                ("nx", C.c_int32), ("ny", C.c_int32)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("keep_all_R", C.c_int32), ("store_root_R", C.c_int32),
+                ("reserved", C.c_int32), ("stream", C.c_void_p)]
+
+
+class FactorInfo(C.Structure):
+    _fields_ = [("p", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("levels", C.c_int32),
+                ("nleaf", C.c_int64), ("n_leaf_nodes", C.c_int64), ("n_interior", C.c_int64),
+                ("n_root", C.c_int64), ("device_bytes", C.c_int64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libhps.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with python -m paper_1812_07167_amd.build")
+    # One HIP runtime per process: when torch is present its bundled runtime is loaded
+    # first, and libhps.so's libamdhip64.so.7 dependency then resolves to it by soname.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = C.CDLL(path)
+    P, D, I32, I64 = C.c_void_p, C.c_double, C.c_int32, C.c_int64
+    lib.hps_last_error.restype = C.c_char_p
+    lib.hps_version.restype = I32
+    lib.hps_default_opts.argtypes = [C.POINTER(Opts)]
+    lib.hps_default_opts.restype = None
+    lib.hps_nodes.argtypes = [C.POINTER(Domain), I32, P, P, P, P]
+    lib.hps_build.argtypes = [C.POINTER(Domain), I32, D, D, D, P, C.POINTER(Opts), C.POINTER(P)]
+    lib.hps_solve.argtypes = [P, I32, P, P, P]
+    lib.hps_factor_query.argtypes = [P, C.POINTER(FactorInfo)]
+    lib.hps_factor_get.argtypes = [P, I32, I32, I32, P, I64, C.POINTER(I32), C.POINTER(I32)]
+    lib.hps_factor_box.argtypes = [P, I32, I32] + [C.POINTER(I32)] * 4
+    lib.hps_free.argtypes = [P]
+    lib.hps_free.restype = None
+    for name in ["hps_nodes", "hps_build", "hps_solve", "hps_factor_query", "hps_factor_get",
+                 "hps_factor_box"]:
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != HPS_OK:
+        raise HPSError(code, load().hps_last_error().decode())
+
+
+def domain(nx, ny, box=(0.0, 1.0, 0.0, 1.0)):
+    return Domain(box[0], box[1], box[2], box[3], nx, ny)
+
+
+def hps_nodes(dom: Domain, p: int):
+    """Host arrays (xy_leaf, xy_interior, xy_root, nrm_root) in the ordering contract."""
+    lib = load()
+    nl, m = dom.nx * dom.ny, p - 2
+    xy = np.zeros((nl * (p * p - 4), 2))
+    xyi = np.zeros((nl * m * m, 2))
+    nt = 2 * (dom.nx + dom.ny) * m
+    xyb = np.zeros((nt, 2))
+    nrm = np.zeros((nt, 2))
+    _check(lib.hps_nodes(C.byref(dom), p, xy.ctypes.data, xyi.ctypes.data, xyb.ctypes.data,
+                         nrm.ctypes.data))
+    return xy, xyi, xyb, nrm
+
+
+def _dev_ptr(t, dtype_name):
+    import torch
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if str(t.dtype) != dtype_name:
+        raise ValueError(f"expected dtype {dtype_name}, got {t.dtype}")
+    return t.data_ptr()
+
+
+class Factor:
+    """Owning handle of a built factorization (hps_build / hps_free)."""
+
+    def __init__(self, handle, stream_ptr):
+        self.h = handle
+        self.stream_ptr = stream_ptr
+        info = FactorInfo()
+        _check(load().hps_factor_query(self.h, C.byref(info)))
+        self.info = info
+
+    def free(self):
+        if self.h:
+            load().hps_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def get(self, what, level, box):
+        """Copy one stored operator to a complex128 numpy array."""
+        lib = load()
+        rows, cols = C.c_int32(), C.c_int32()
+        cap = 1
+        while True:
+            buf = np.zeros(cap, dtype=np.complex128)
+            code = lib.hps_factor_get(self.h, what, level, box, buf.ctypes.data, cap,
+                                      C.byref(rows), C.byref(cols))
+            if code == HPS_OK:
+                return buf[: rows.value * cols.value].reshape(cols.value, rows.value).T
+            if rows.value * cols.value > cap:
+                cap = rows.value * cols.value
+                continue
+            _check(code)
+
+    def box(self, level, box):
+        v = [C.c_int32() for _ in range(4)]
+        _check(load().hps_factor_box(self.h, level, box, *[C.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
+
+def hps_build(dom: Domain, p: int, kappa: float, eta: complex, c_interior, keep_all_R=False,
+              store_root_R=True, stream=None) -> Factor:
+    """c_interior: float64 device tensor [nx*ny*(p-2)^2].  Returns a Factor."""
+    import torch
+    lib = load()
+    opts = Opts()
+    lib.hps_default_opts(C.byref(opts))
+    opts.keep_all_R = int(keep_all_R)
+    opts.store_root_R = int(store_root_R)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    opts.stream = C.c_void_p(st.cuda_stream)
+    out = C.c_void_p()
+    ptr = _dev_ptr(c_interior, "torch.float64")
+    _check(lib.hps_build(C.byref(dom), p, float(kappa), float(np.real(eta)), float(np.imag(eta)),
+                         ptr, C.byref(opts), C.byref(out)))
+    return Factor(out, st.cuda_stream)
+
+
+def hps_solve(f: Factor, t, s=None, u=None):
+    """t: complex128 device tensor [nrhs, n_root]; s: [nrhs, n_interior] or None.
+    Returns u: complex128 device tensor [nrhs, n_leaf_nodes] (stream-ordered)."""
+    import torch
+    nrhs = t.shape[0]
+    if u is None:
+        u = torch.empty((nrhs, f.info.n_leaf_nodes), dtype=torch.complex128, device=t.device)
+    sp = _dev_ptr(s, "torch.complex128") if s is not None else None
+    _check(load().hps_solve(f.h, nrhs, sp, _dev_ptr(t, "torch.complex128"),
+                            _dev_ptr(u, "torch.complex128")))
+    return u

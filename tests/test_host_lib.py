@@ -1,0 +1,108 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point declared in
+include/hps.h, its host-side node generator matches the oracle's coordinates exactly,
+and argument validation fails cleanly before any device work."""
+
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import hps_oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hps.h")
+
+
+def _lib():
+    from paper_1812_07167_amd import hps as H
+    if not os.path.exists(H.LIB_PATH):
+        pytest.skip("libhps.so not built")
+    return H, H.load()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hps_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_exports():
+    from paper_1812_07167_amd import hps as H
+    assert declared_functions() == sorted(H.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    H, lib = _lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", H.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r" T (hps_\w+)", out))
+    for name in declared_functions():
+        assert name in exported, name
+        assert hasattr(lib, name)
+
+
+def test_version_and_default_opts():
+    H, lib = _lib()
+    assert lib.hps_version() >= 10000
+    o = H.Opts()
+    lib.hps_default_opts(C.byref(o))
+    assert o.precision == 0 and o.store_root_R == 1 and o.keep_all_R == 0
+
+
+@pytest.mark.parametrize("nx,ny,p,box", [(4, 2, 8, (0.0, 1.0, 0.0, 0.5)), (1, 1, 4, (0, 1, 0, 1)),
+                                         (2, 8, 16, (-1.0, 2.0, 3.0, 5.0))])
+def test_nodes_match_oracle_exactly(nx, ny, p, box):
+    H, lib = _lib()
+    xy, xyi, xyb, nrm = H.hps_nodes(H.domain(nx, ny, box), p)
+    prob = O.Problem(*box, nx, ny, p, 1.0, 1.0)
+    np.testing.assert_array_equal(xy, prob.leaf_nodes())
+    np.testing.assert_array_equal(xyi, prob.interior_nodes())
+    b, n = prob.root_boundary()
+    np.testing.assert_array_equal(xyb, b)
+    np.testing.assert_array_equal(nrm, n)
+
+
+@pytest.mark.parametrize("nx,ny,p,kappa,eta,err", [
+    (3, 2, 8, 1.0, 1.0, "powers of two"),
+    (2, 2, 3, 1.0, 1.0, "p must be"),
+    (2, 2, 17, 1.0, 1.0, "p must be"),
+    (2, 2, 8, -1.0, 1.0, "kappa"),
+    (2, 2, 8, float("nan"), 1.0, "kappa"),
+    (2, 2, 8, 1.0, 1.0j, "Re(eta)"),
+    (512, 256, 8, 1.0, 1.0, "65536"),
+])
+def test_build_rejects_invalid_arguments(nx, ny, p, kappa, eta, err):
+    H, lib = _lib()
+    dom = H.domain(nx, ny)
+    out = C.c_void_p(123)
+    code = lib.hps_build(C.byref(dom), p, kappa, float(np.real(eta)), float(np.imag(eta)),
+                         C.c_void_p(16), None, C.byref(out))
+    assert code == H.HPS_E_INVALID
+    assert out.value is None
+    assert err in lib.hps_last_error().decode()
+
+
+def test_invalid_domain_bounds_and_nulls():
+    H, lib = _lib()
+    dom = H.Domain(1.0, 0.0, 0.0, 1.0, 2, 2)
+    assert lib.hps_nodes(C.byref(dom), 8, None, None, None, None) == H.HPS_E_INVALID
+    dom = H.domain(2, 2)
+    out = C.c_void_p()
+    assert lib.hps_build(C.byref(dom), 8, 1.0, 1.0, 0.0, None, None, C.byref(out)) == H.HPS_E_INVALID
+    assert lib.hps_solve(None, 1, None, None, None) == H.HPS_E_INVALID
+    assert lib.hps_nodes(None, 8, None, None, None, None) == H.HPS_E_INVALID
+    lib.hps_free(None)  # no-op
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    from paper_1812_07167_amd import hps as H
+    saved = H._lib
+    try:
+        H._lib = None
+        with pytest.raises(RuntimeError, match="missing"):
+            H.load(str(tmp_path / "nope.so"))
+    finally:
+        H._lib = saved
