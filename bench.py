@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Benchmark of the HPS direct solver's hot path on one MI355X.
+
+Workload (the problem the headline metric is quoted on): Omega = [0,1]^2 split into
+64 x 64 leaves, p = 16 Chebyshev points per direction per leaf (DOF = 4096 * 252 =
+1,032,192), kappa = eta = 100, c(x,y) = 1 - 0.5 exp(-160((x-.5)^2 + (y-.5)^2)),
+complex128.  The 16 right-hand sides of one solve call are manufactured from
+u = exp(i kappa d.x)(1 + 0.1 sin 2 pi x sin 2 pi y) with seeded unit directions d.
+
+A step is one pass of the whole hot path: hps_build (batched leaf stage + every merge
+level) followed by one 16-RHS hps_solve (upward + downward sweeps), inputs resident in
+HBM.  Prints one JSON line (see the keys below).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HPS build DOF/s + RHS solves/s at stated rel. L2 error; p99 solve latency"
+PEAK = {"hbm": (8000.0, "GB/s"), "mfma": (78.6, "TFLOP/s"), "alu": (78.6, "TFLOP/s")}
+# which roofline bounds each kernel group of the library
+BOUND = {
+    "leaf_inv": "alu", "leaf_xzs": "hbm", "leaf_sinv": "alu", "leaf_r": "hbm",
+    "leaf_gemm": "mfma", "merge_extract": "hbm", "merge_gemm": "mfma", "merge_inv": "mfma",
+    "solve_leaf_up": "hbm", "solve_leaf_down": "hbm", "solve_merge_up": "hbm",
+    "solve_merge_down": "hbm", "solve_gather": "hbm",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(nx=64, ny=64, p=16, kappa=100.0, nrhs=16, seed=0, nodes=None):
+    from paper_1812_07167_amd import inputs as G
+    xy, xyi, xyb, nrm = nodes(nx, ny, p)
+    c = G.c_gaussian_bump(xyi)
+    thetas = G.seeded_thetas(seed, nrhs)
+    mfs = [G.Manufactured(kappa, float(a)) for a in thetas]
+    s = np.stack([mf.s(xyi, c) for mf in mfs])
+    t = np.stack([mf.t(xyb, nrm, kappa) for mf in mfs])
+    exact = np.stack([mf.u(xy) for mf in mfs])
+    return c, s, t, exact
+
+
+def cpu_baseline(n_side, p, kappa, nrhs, seed):
+    """The CPU oracle, as it stands, on a bounded sample of the workload: the same p,
+    kappa, c and right-hand sides on an n_side x n_side leaf grid."""
+    from oracle import hps_oracle as O
+
+    def onodes(nx, ny, pp):
+        prob = O.Problem(0.0, 1.0, 0.0, 1.0, nx, ny, pp, kappa, kappa)
+        b, nr = prob.root_boundary()
+        return prob.leaf_nodes(), prob.interior_nodes(), b, nr
+
+    c, s, t, exact = workload(n_side, n_side, p, kappa, nrhs, seed, onodes)
+    prob = O.Problem(0.0, 1.0, 0.0, 1.0, n_side, n_side, p, kappa, kappa)
+    t0 = time.perf_counter()
+    boxes = O.build(prob, c)
+    u = O.solve(prob, boxes, s, t)
+    dt = time.perf_counter() - t0
+    cores = os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info
+        nth = [i.get("num_threads") for i in threadpool_info() if i.get("user_api") == "blas"]
+        if nth:
+            cores = int(max(nth))
+    except Exception:
+        pass
+    dof = n_side * n_side * (p * p - 4)
+    err = float(np.linalg.norm(u - exact) / np.linalg.norm(exact))
+    return {"value": dof / dt, "unit": "DOF/s (build + one %d-RHS solve)" % nrhs, "cores": cores,
+            "kind": "oracle", "seconds": dt, "rel_l2_vs_exact": err,
+            "sample": "oracle build + one %d-RHS solve on %dx%d leaves (p=%d, kappa=%g, same c "
+                      "and right-hand sides; %.3g of the workload's DOF); numpy/OpenBLAS, "
+                      "threads as counted" % (nrhs, n_side, n_side, p, kappa,
+                                              n_side * n_side / 4096.0)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nrhs", type=int, default=16)
+    ap.add_argument("--latency-solves", type=int, default=40)
+    ap.add_argument("--cpu-side", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1812_07167_amd import hps as H
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    H.load()
+    nx = ny = 64
+    p, kappa, nrhs = 16, 100.0, args.nrhs
+    dom = H.domain(nx, ny)
+
+    def lnodes(a, b, pp):
+        return H.hps_nodes(H.domain(a, b), pp)
+
+    c, s, t, exact = workload(nx, ny, p, kappa, nrhs, 0, lnodes)
+    c_d = torch.tensor(c, dtype=torch.float64, device=dev)
+    s_d = torch.tensor(s, dtype=torch.complex128, device=dev)
+    t_d = torch.tensor(t, dtype=torch.complex128, device=dev)
+    u_d = torch.empty((nrhs, nx * ny * (p * p - 4)), dtype=torch.complex128, device=dev)
+    stream = torch.cuda.current_stream()
+    dof = nx * ny * (p * p - 4)
+
+    def step(profile):
+        f = H.hps_build(dom, p, kappa, kappa, c_d, stream=stream, profile=profile)
+        tb = time.perf_counter()
+        H.hps_solve(f, t_d, s_d, u_d)
+        return f, tb
+
+    log("warmup", args.warmup)
+    for _ in range(args.warmup):
+        f, _ = step(False)
+        torch.cuda.synchronize()
+        f.free()
+
+    build_ms, solve_ms, step_ms = [], [], []
+    stages_b = stages_s = None
+    torch.cuda.synchronize()
+    t_all0 = time.perf_counter()
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f, tb = step(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        build_ms.append((tb - t0) * 1e3)
+        solve_ms.append((t1 - tb) * 1e3)
+        step_ms.append((t1 - t0) * 1e3)
+        stages_b, stages_s = f.stage_times(0), f.stage_times(1)
+        f.free()
+        log("step", k, "build %.2f ms solve %.2f ms" % (build_ms[-1], solve_ms[-1]))
+    torch.cuda.synchronize()
+    t_all1 = time.perf_counter()
+    ms_per_step = (t_all1 - t_all0) * 1e3 / args.steps
+
+    # accuracy of the last step's solution against the closed form
+    u = u_d.cpu().numpy()
+    err = float(np.linalg.norm(u - exact) / np.linalg.norm(exact))
+
+    # steady-state solve latency on one resident factor
+    f = H.hps_build(dom, p, kappa, kappa, c_d, stream=stream)
+    lat = []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        H.hps_solve(f, t_d, s_d, u_d)
+    torch.cuda.synchronize()
+    for _ in range(args.latency_solves):
+        t0 = time.perf_counter()
+        H.hps_solve(f, t_d, s_d, u_d)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    f.free()
+    lat = np.array(lat)
+
+    # roofline of the dominant kernel group (largest summed time in a step)
+    groups = {}
+    for name, launches, ms, fl, by in list(stages_b) + list(stages_s):
+        g = groups.setdefault(name, [0, 0.0, 0.0, 0.0])
+        g[0] += launches
+        g[1] += ms
+        g[2] += fl
+        g[3] += by
+    dom_name = max(groups, key=lambda k: groups[k][1])
+    launches, ms, fl, by = groups[dom_name]
+    bound = BOUND.get(dom_name, "hbm")
+    peak, unit = PEAK[bound]
+    if bound == "hbm":
+        achieved = by / (ms * 1e-3) / 1e9
+        per_launch = by / launches
+    else:
+        achieved = fl / (ms * 1e-3) / 1e12
+        per_launch = fl / launches
+    roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 4), "traffic": None, "kernel": dom_name,
+                "launches_per_step": launches, "avg_launch_ms": round(ms / launches, 4),
+                "algorithmic_per_launch": per_launch}
+
+    out = {
+        "metric": METRIC,
+        "value": round(dof / (ms_per_step * 1e-3), 1),
+        "unit": "DOF/s (build + one 16-RHS solve per step)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128", "data": "synthetic",
+        "config": {"workload": "HPS 64x64 leaves, p=16, kappa=eta=100, Gaussian-bump c, "
+                               "complex128, 16 manufactured RHS per solve",
+                   "leaves": nx * ny, "p": p, "dof": dof, "nrhs": nrhs},
+        "build_ms": round(float(np.median(build_ms)), 3),
+        "build_dof_per_s": round(dof / (np.median(build_ms) * 1e-3), 1),
+        "solve_ms": round(float(np.median(solve_ms)), 3),
+        "rhs_solves_per_s": round(nrhs / (np.median(lat) * 1e-3), 1),
+        "solve_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                             "p99": round(float(np.percentile(lat, 99)), 3),
+                             "calls": int(len(lat)), "nrhs_per_call": nrhs},
+        "rel_l2_vs_exact": err,
+        "roofline": roofline,
+        "stages_ms": {k: round(v[1], 3) for k, v in groups.items()},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) on %dx%d leaves" % (args.cpu_side, args.cpu_side))
+        out["cpu_baseline"] = cpu_baseline(args.cpu_side, p, kappa, nrhs, 0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -72,9 +72,22 @@ typedef struct {
                              0 = free children's R after each merge, as Sec. 2.4 does     */
   int32_t store_root_R;   /* 1 = form the root's R (Algorithm 1 does; the solve does not
                              use it) (default 1)                                          */
-  int32_t reserved;
+  int32_t profile;        /* 1 = record HIP events around every kernel group of the build
+                             and of each solve; read them with hps_stage_times (default 0) */
   void* stream;           /* hipStream_t the work is ordered on (default NULL)            */
 } hps_opts;
+
+/* Timing of one kernel group (profile = 1).  flops and bytes are the algorithmic work
+ * of the group (dense-equivalent counts of the formulas it evaluates, not hardware
+ * counters); ms is the summed HIP-event time of its launches on the factor's stream. */
+typedef struct {
+  char name[32];
+  int32_t launches;
+  int32_t reserved;
+  double ms;
+  double flops;
+  double bytes;
+} hps_stage_time;
 
 typedef struct hps_factor hps_factor;
 
@@ -165,6 +178,13 @@ int hps_factor_get(const hps_factor* f, int32_t what, int32_t level, int32_t box
 /* Leaf range [ix0,ix1) x [iy0,iy1) covered by box `box` of level `level`. */
 int hps_factor_box(const hps_factor* f, int32_t level, int32_t box, int32_t* ix0,
                    int32_t* ix1, int32_t* iy0, int32_t* iy1);
+
+/* Per-kernel-group timings of the factor's build (which = 0) or of its most recent
+ * solve (which = 1), recorded when opts.profile = 1.  Writes up to cap records to out
+ * (host) and the number of records to *n.  Waits for the recorded events.  Not
+ * meaningful while several solves run concurrently on the factor. */
+int hps_stage_times(const hps_factor* f, int32_t which, hps_stage_time* out, int32_t cap,
+                    int32_t* n);
 
 /* Release a factor (NULL is a no-op). */
 void hps_free(hps_factor* f);

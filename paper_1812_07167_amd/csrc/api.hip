@@ -53,6 +53,28 @@ struct DevBuf {
   long* l() const { return static_cast<long*>(p); }
 };
 
+// Non-owning slice of an arena.
+struct View {
+  void* p = nullptr;
+  size_t bytes = 0;
+  double* d() const { return static_cast<double*>(p); }
+  int* i() const { return static_cast<int*>(p); }
+};
+
+// Carves 256-byte aligned slices out of one allocation; a first pass with base ==
+// nullptr only measures.
+struct Carver {
+  char* base = nullptr;
+  size_t used = 0;
+  View take(size_t bytes) {
+    View v;
+    v.bytes = bytes;
+    v.p = base ? base + used : nullptr;
+    used += (bytes + 255) & ~size_t(255);
+    return v;
+  }
+};
+
 template <class T>
 void upload(DevBuf& b, const std::vector<T>& v) {
   b.alloc(v.size() * sizeof(T));
@@ -91,11 +113,83 @@ struct LevelPlan {
   const int* dcodeA = nullptr; const int* dcodeB = nullptr; const int* dperm = nullptr;
   const int* di1a = nullptr; const int* di3a = nullptr; const int* di2b = nullptr;
   const int* di3b = nullptr;
-  // stored operators of the level (Sec. 2.4)
-  DevBuf Winv, R33a, R33b, R13a, R23b, PhiA, PhiB;
+  // stored operators of the level (Sec. 2.4), slices of the factor's arena
+  View Winv, R33a, R33b, R13a, R23b, PhiA, PhiB;
 };
 
 struct Geo { int ix0, iy0, wx, wy; };
+
+// ------------------------------------------------------------------ stage timers
+// HIP events around kernel groups on the factor's stream (opts.profile = 1).  The
+// flops/bytes attached to a record are the algorithmic work of the launches it covers.
+struct StageRec {
+  std::string name;
+  hipEvent_t a = nullptr, b = nullptr;
+  double flops = 0, bytes = 0;
+};
+
+struct Profiler {
+  bool on = false;
+  hipStream_t st = nullptr;
+  std::vector<StageRec> recs;
+  Profiler() = default;
+  Profiler(const Profiler&) = delete;
+  Profiler& operator=(const Profiler&) = delete;
+  ~Profiler() { clear(); }
+  void clear() {
+    for (auto& r : recs) {
+      if (r.a) (void)hipEventDestroy(r.a);
+      if (r.b) (void)hipEventDestroy(r.b);
+    }
+    recs.clear();
+  }
+  void reset(bool enable, hipStream_t s) {
+    clear();
+    on = enable;
+    st = s;
+  }
+  int begin(const char* name, double flops, double bytes) {
+    StageRec r;
+    r.name = name;
+    r.flops = flops;
+    r.bytes = bytes;
+    HPS_HIP(hipEventCreate(&r.a));
+    HPS_HIP(hipEventCreate(&r.b));
+    HPS_HIP(hipEventRecord(r.a, st));
+    recs.push_back(r);
+    return (int)recs.size() - 1;
+  }
+  void end(int i) { (void)hipEventRecord(recs[i].b, st); }
+};
+
+struct Stage {
+  Profiler& p;
+  int idx = -1;
+  Stage(Profiler& pr, const char* name, double flops, double bytes) : p(pr) {
+    if (p.on) idx = p.begin(name, flops, bytes);
+  }
+  ~Stage() {
+    if (idx >= 0) p.end(idx);
+  }
+};
+
+void timed_gemm(Profiler& pr, const char* name, const GemmDesc& g, hipStream_t st) {
+  const double mnk = (double)g.M * g.N * g.K * g.batch;
+  const double fl = (g.a_real || g.b_real) ? 4.0 * mnk : 8.0 * mnk;
+  const double by = (double)g.batch * ((double)g.M * g.K * (g.a_real ? 8 : 16) +
+                                       (double)g.K * g.N * (g.b_real ? 8 : 16) +
+                                       (double)g.M * g.N * 16 * (g.beta != 0.0 ? 2 : 1));
+  Stage s(pr, name, fl, by);
+  zgemm(g, st);
+}
+
+void timed_skinny(Profiler& pr, const char* name, const SkinnyDesc& k, hipStream_t st) {
+  const double fl = 8.0 * k.M * k.K * (double)k.nrhs * k.batch;
+  const double by = (double)k.batch * ((double)k.M * k.K * 16 +
+                                       (double)(k.K + k.M) * k.nrhs * 16);
+  Stage s(pr, name, fl, by);
+  zgemm_skinny(k, st);
+}
 
 bool split_x_rule(int wx, int wy) {
   if (wy == 1) return true;
@@ -117,16 +211,19 @@ struct hps_factor {
   std::vector<hps::LevelPlan> lv;          // merges producing level l (l = 0..L-1)
   std::vector<int> leaf_grid;              // tree-ordered leaf -> grid index
   hps::DevBuf dleaf_grid, dxoff, duoff, dD;
-  hps::DevBuf BI;                          // [nleaf][n*n] complex: [Psi | Y]
-  std::vector<std::unique_ptr<hps::DevBuf>> R;  // per level ItI operators (L+1 entries)
+  hps::DevBuf ops;                         // arena: [Psi | Y] of every leaf + merge operators
+  hps::View BI;                            // [nleaf][n*n] complex: [Psi | Y]
+  hps::DevBuf rbuf[2];                     // ping-pong ItI operators (level l uses l % 2)
+  std::vector<hps::DevBuf> rkeep;          // every level's R when opts.keep_all_R
+  std::vector<hps::View> R;                // per level ItI operators (L+1 entries)
+  std::vector<char> R_valid;               // R of the level still holds its operator
   std::vector<int> nbl;                    // boundary size per level
+  hps::Profiler build_prof, solve_prof;
   size_t bytes() const {
-    size_t t = BI.bytes + dleaf_grid.bytes + dxoff.bytes + duoff.bytes + dD.bytes;
-    for (auto& r : R)
-      if (r) t += r->bytes;
-    for (auto& l : lv)
-      t += l.dmaps.bytes + l.Winv.bytes + l.R33a.bytes + l.R33b.bytes + l.R13a.bytes +
-           l.R23b.bytes + l.PhiA.bytes + l.PhiB.bytes;
+    size_t t = ops.bytes + dleaf_grid.bytes + dxoff.bytes + duoff.bytes + dD.bytes +
+               rbuf[0].bytes + rbuf[1].bytes;
+    for (auto& r : rkeep) t += r.bytes;
+    for (auto& l : lv) t += l.dmaps.bytes;
     return t;
   }
 };
@@ -317,32 +414,129 @@ MergeLevelDesc level_desc(const hps_factor& f, const LevelPlan& P) {
   return d;
 }
 
-void check_info(const DevBuf& info, long cnt, const char* what) {
-  std::vector<int> h(cnt);
-  HPS_HIP(hipMemcpy(h.data(), info.p, cnt * sizeof(int), hipMemcpyDeviceToHost));
+void check_info(const std::vector<int>& h, long off, long cnt, const char* what) {
   for (long i = 0; i < cnt; ++i)
-    if (h[i]) throw Error(HPS_E_SINGULAR, std::string(what) + ": zero pivot at step " +
-                                              std::to_string(h[i] - 1) + " of matrix " +
-                                              std::to_string(i));
+    if (h[off + i])
+      throw Error(HPS_E_SINGULAR, std::string(what) + ": zero pivot at step " +
+                                      std::to_string(h[off + i] - 1) + " of matrix " +
+                                      std::to_string(i));
+}
+
+// ------------------------------------------------------------------ build memory
+// One arena holds every stored operator ([Psi | Y] of the leaves, then per level
+// W^{-1}, R33a, R33b, R13a, R23b, Phi^a, Phi^b); the ItI operators R ping-pong between
+// two buffers (level l in buffer l % 2), or get one buffer per level when every R is
+// kept; one scratch arena serves the leaf stage and then each merge level in turn.
+struct BuildScratch {
+  DevBuf buf;
+  View X, Z, S;            // leaf stage
+  View R31a, T, work;      // merge level (sized for the largest level)
+  View info;               // [2 * nleaf] leaf infos, then one int per merge
+  std::vector<long> info_off;  // per level offset into info
+};
+
+bool level_forms_R(const hps_factor& f, int l) {
+  return l == f.L || l > 0 || f.opts.store_root_R;
+}
+
+size_t level_R_bytes(const hps_factor& f, int l) {
+  if (l == f.L) return (size_t)f.nleaf * f.nb * f.nb * 16;
+  const LevelPlan& P = f.lv[l];
+  return (size_t)P.nbox * P.nbp * P.nbp * 16;
+}
+
+void plan_memory(hps_factor& f, BuildScratch& sc) {
+  const long nl = f.nleaf, n = f.n, nb = f.nb, ni = f.ni;
+  for (int pass = 0; pass < 2; ++pass) {
+    Carver c;
+    c.base = pass ? static_cast<char*>(f.ops.p) : nullptr;
+    f.BI = c.take((size_t)nl * n * n * 16);
+    for (auto& P : f.lv) {
+      const size_t nbox = P.nbox, n1 = P.n1, n2 = P.n2, n3 = P.n3, nbp = P.nbp;
+      P.Winv = c.take(nbox * n3 * n3 * 16);
+      P.R33a = c.take(nbox * n3 * n3 * 16);
+      P.R33b = c.take(nbox * n3 * n3 * 16);
+      P.R13a = c.take(nbox * n1 * n3 * 16);
+      P.R23b = c.take(nbox * n2 * n3 * 16);
+      P.PhiA = c.take(nbox * n3 * nbp * 16);
+      P.PhiB = c.take(nbox * n3 * nbp * 16);
+    }
+    if (pass == 0) f.ops.alloc(c.used);
+  }
+  f.R.assign(f.L + 1, View());
+  f.R_valid.assign(f.L + 1, 0);
+  if (f.opts.keep_all_R) {
+    f.rkeep.clear();
+    f.rkeep.resize(f.L + 1);
+    for (int l = 0; l <= f.L; ++l)
+      if (level_forms_R(f, l)) {
+        f.rkeep[l].alloc(level_R_bytes(f, l));
+        f.R[l].p = f.rkeep[l].p;
+        f.R[l].bytes = f.rkeep[l].bytes;
+      }
+  } else {
+    size_t need[2] = {0, 0};
+    for (int l = 0; l <= f.L; ++l)
+      if (level_forms_R(f, l)) need[l % 2] = std::max(need[l % 2], level_R_bytes(f, l));
+    for (int b = 0; b < 2; ++b) f.rbuf[b].alloc(need[b]);
+    for (int l = 0; l <= f.L; ++l)
+      if (level_forms_R(f, l)) {
+        f.R[l].p = f.rbuf[l % 2].p;
+        f.R[l].bytes = level_R_bytes(f, l);
+      }
+  }
+  // scratch: leaf part and level part share the same bytes; infos follow
+  size_t leaf_bytes = 0, level_bytes = 0;
+  {
+    Carver c;
+    c.take((size_t)nl * ni * nb * 8);
+    c.take((size_t)nl * ni * nb * 8);
+    c.take((size_t)nl * nb * nb * 16);
+    leaf_bytes = c.used;
+  }
+  for (auto& P : f.lv) {
+    Carver c;
+    c.take((size_t)P.nbox * P.n3 * P.n1 * 16);
+    c.take((size_t)P.nbox * P.n3 * P.nbp * 16);
+    c.take(zinv_workspace_bytes(P.n3, P.nbox));
+    level_bytes = std::max(level_bytes, c.used);
+  }
+  long ninfo = 2 * nl;
+  sc.info_off.assign(f.L, 0);
+  for (int l = 0; l < f.L; ++l) {
+    sc.info_off[l] = ninfo;
+    ninfo += f.lv[l].nbox;
+  }
+  const size_t shared = std::max(leaf_bytes, level_bytes);
+  sc.buf.alloc(shared + (size_t)ninfo * sizeof(int) + 256);
+  char* base = static_cast<char*>(sc.buf.p);
+  {
+    Carver c;
+    c.base = base;
+    sc.X = c.take((size_t)nl * ni * nb * 8);
+    sc.Z = c.take((size_t)nl * ni * nb * 8);
+    sc.S = c.take((size_t)nl * nb * nb * 16);
+  }
+  sc.info.p = base + ((shared + 255) & ~size_t(255));
+  sc.info.bytes = (size_t)ninfo * sizeof(int);
+}
+
+void level_scratch(const LevelPlan& P, BuildScratch& sc) {
+  Carver c;
+  c.base = static_cast<char*>(sc.buf.p);
+  sc.R31a = c.take((size_t)P.nbox * P.n3 * P.n1 * 16);
+  sc.T = c.take((size_t)P.nbox * P.n3 * P.nbp * 16);
+  sc.work = c.take(zinv_workspace_bytes(P.n3, P.nbox));
 }
 
 // ------------------------------------------------------------------ build
-void build_leaves(hps_factor& f, const double* c) {
+void build_leaves(hps_factor& f, const double* c, BuildScratch& sc) {
   hipStream_t st = f.stream;
   const long nl = f.nleaf;
-  f.BI.alloc((size_t)nl * f.n * f.n * 16);
-  f.R[f.L].reset(new DevBuf);
-  f.R[f.L]->alloc((size_t)nl * f.nb * f.nb * 16);
-  DevBuf X, Z, S, info, work;
-  X.alloc((size_t)nl * f.ni * f.nb * 8);
-  Z.alloc((size_t)nl * f.ni * f.nb * 8);
-  S.alloc((size_t)nl * f.nb * f.nb * 16);
-  info.alloc((size_t)nl * 2 * sizeof(int));
-  HPS_HIP(hipMemsetAsync(info.p, 0, info.bytes, st));
   LeafDesc d;
   d.p = f.p; d.nleaf = f.nleaf; d.kappa = f.kappa; d.eta_re = f.eta_re; d.eta_im = f.eta_im;
-  d.D = f.dD.d(); d.c = c; d.leaf_grid = f.dleaf_grid.i(); d.BI = f.BI.d(); d.R = f.R[f.L]->d();
-  d.X = X.d(); d.Z = Z.d(); d.S = S.d(); d.info = info.i();
+  d.D = f.dD.d(); d.c = c; d.leaf_grid = f.dleaf_grid.i(); d.BI = f.BI.d(); d.R = f.R[f.L].d();
+  d.X = sc.X.d(); d.Z = sc.Z.d(); d.S = sc.S.d(); d.info = sc.info.i();
   const long n = f.n, nb = f.nb, ni = f.ni;
   // process leaves in chunks that fit the grid limit
   for (long h0 = 0; h0 < nl; h0 += 65535) {
@@ -356,12 +550,28 @@ void build_leaves(hps_factor& f, const double* c) {
     dc.Z = d.Z + h0 * ni * nb;
     dc.S = d.S + 2 * h0 * nb * nb;
     dc.info = d.info + h0;
-    leaf_inverse_interior(dc, st);
-    leaf_xzs(dc, st);
-    // Psi_b = S^{-1}, written into the top-left block of [Psi | Y]
-    zinv(f.nb, cnt, dc.S, nb, nb * nb, dc.BI, n, n * n, d.info + nl + h0, nullptr, st);
-    leaf_r_from_psib(dc, st);
+    Profiler& pr = f.build_prof;
+    const double c_ = cnt;
+    {
+      Stage s(pr, "leaf_inv", c_ * 2.0 * ni * ni * ni, c_ * (ni * 8.0 + ni * ni * 16.0));
+      leaf_inverse_interior(dc, st);
+    }
+    {
+      Stage s(pr, "leaf_xzs", c_ * (16.0 * ni * ni + 2.0 * nb * nb * f.m),
+              c_ * (2.0 * ni * ni * 16 + 2.0 * ni * nb * 8 + nb * nb * 16.0));
+      leaf_xzs(dc, st);
+    }
+    {
+      // Psi_b = S^{-1}, written into the top-left block of [Psi | Y]
+      Stage s(pr, "leaf_sinv", c_ * 8.0 * nb * nb * nb, c_ * 2.0 * nb * nb * 16);
+      zinv(f.nb, cnt, dc.S, nb, nb * nb, dc.BI, n, n * n, d.info + nl + h0, nullptr, st);
+    }
+    {
+      Stage s(pr, "leaf_r", 0.0, c_ * 2.0 * nb * nb * 16);
+      leaf_r_from_psib(dc, st);
+    }
     GemmDesc g;
+    const char* gname = "leaf_gemm";
     // Psi_i = -X Psi_b
     g = GemmDesc();
     g.M = ni; g.N = nb; g.K = nb; g.batch = cnt;
@@ -369,7 +579,7 @@ void build_leaves(hps_factor& f, const double* c) {
     g.B = dc.BI; g.ldb = n; g.sB = n * n;
     g.C = dc.BI + 2 * nb; g.ldc = n; g.sC = n * n;
     g.alpha = -1.0; g.beta = 0.0;
-    zgemm(g, st);
+    timed_gemm(f.build_prof, gname, g, st);
     // Y_b = -Psi_b Z
     g = GemmDesc();
     g.M = nb; g.N = ni; g.K = nb; g.batch = cnt;
@@ -377,7 +587,7 @@ void build_leaves(hps_factor& f, const double* c) {
     g.B = dc.Z; g.ldb = nb; g.sB = nb * ni; g.b_real = true;
     g.C = dc.BI + 2 * n * nb; g.ldc = n; g.sC = n * n;
     g.alpha = -1.0; g.beta = 0.0;
-    zgemm(g, st);
+    timed_gemm(f.build_prof, gname, g, st);
     // Y_i = A_ii^{-1} - X Y_b
     g = GemmDesc();
     g.M = ni; g.N = ni; g.K = nb; g.batch = cnt;
@@ -385,74 +595,65 @@ void build_leaves(hps_factor& f, const double* c) {
     g.B = dc.BI + 2 * n * nb; g.ldb = n; g.sB = n * n;
     g.C = dc.BI + 2 * (nb + n * nb); g.ldc = n; g.sC = n * n;
     g.alpha = -1.0; g.beta = 1.0;
-    zgemm(g, st);
+    timed_gemm(f.build_prof, gname, g, st);
   }
-  HPS_HIP(hipStreamSynchronize(st));
-  check_info(info, nl, "leaf interior inversion");
-  std::vector<int> hinfo(nl);
-  HPS_HIP(hipMemcpy(hinfo.data(), info.i() + nl, nl * sizeof(int), hipMemcpyDeviceToHost));
-  for (long i = 0; i < nl; ++i)
-    if (hinfo[i]) throw Error(HPS_E_SINGULAR, "leaf boundary Schur complement singular");
+  f.R_valid[f.L] = 1;
 }
 
-void build_level(hps_factor& f, int l) {
+void build_level(hps_factor& f, int l, BuildScratch& sc) {
   hipStream_t st = f.stream;
   LevelPlan& P = f.lv[l];
   const long nbox = P.nbox, n1 = P.n1, n2 = P.n2, n3 = P.n3, nbp = P.nbp;
-  const bool form_R = (l > 0) || f.opts.store_root_R;
-  P.Winv.alloc(nbox * n3 * n3 * 16);
-  P.R33a.alloc(nbox * n3 * n3 * 16);
-  P.R33b.alloc(nbox * n3 * n3 * 16);
-  P.R13a.alloc(nbox * n1 * n3 * 16);
-  P.R23b.alloc(nbox * n2 * n3 * 16);
-  P.PhiA.alloc(nbox * n3 * nbp * 16);
-  P.PhiB.alloc(nbox * n3 * nbp * 16);
-  DevBuf R31a, T, info, work;
-  R31a.alloc(nbox * n3 * n1 * 16);
-  T.alloc(nbox * n3 * nbp * 16);
-  info.alloc(nbox * sizeof(int));
-  HPS_HIP(hipMemsetAsync(info.p, 0, info.bytes, st));
-  size_t wb = zinv_workspace_bytes((int)n3, (int)nbox);
-  if (wb) work.alloc(wb);
-  f.R[l].reset(new DevBuf);
-  if (form_R) f.R[l]->alloc(nbox * nbp * nbp * 16);
+  const bool form_R = level_forms_R(f, l);
+  level_scratch(P, sc);
+  int* info = sc.info.i() + sc.info_off[l];
 
   MergeLevelDesc d = level_desc(f, P);
-  d.Rc = f.R[l + 1]->d();
-  d.Rp = form_R ? f.R[l]->d() : nullptr;
+  d.Rc = f.R[l + 1].d();
+  d.Rp = form_R ? f.R[l].d() : nullptr;
   d.R33a = P.R33a.d(); d.R33b = P.R33b.d(); d.R13a = P.R13a.d(); d.R23b = P.R23b.d();
-  d.R31a = R31a.d(); d.T = T.d(); d.PhiB = P.PhiB.d();
-  if (form_R) fill_zero(d.Rp, 2 * nbox * nbp * nbp, st);
-  fill_zero(d.PhiB, 2 * nbox * n3 * nbp, st);
-  merge_extract(d, st);
-  // W = I - R33b R33a   (into the Winv buffer, inverted in place below)
-  fill_identity(P.Winv.d(), (int)n3, n3 * n3, (int)nbox, st);
+  d.R31a = sc.R31a.d(); d.T = sc.T.d(); d.PhiB = P.PhiB.d();
+  const char* gname = "merge_gemm";
+  {
+    const double nbc = P.nbc;
+    Stage s(f.build_prof, "merge_extract", 0.0,
+            nbox * (2.0 * nbc * nbc * 16 + (form_R ? nbp * nbp * 16.0 : 0.0) +
+                    2.0 * n3 * nbp * 16 + n3 * n3 * 16.0));
+    if (form_R) fill_zero(d.Rp, 2 * nbox * nbp * nbp, st);
+    fill_zero(d.PhiB, 2 * nbox * n3 * nbp, st);
+    merge_extract(d, st);
+    // W = I - R33b R33a   (into the Winv buffer, inverted in place below)
+    fill_identity(P.Winv.d(), (int)n3, n3 * n3, (int)nbox, st);
+  }
   GemmDesc g;
   g.M = n3; g.N = n3; g.K = n3; g.batch = nbox;
   g.A = P.R33b.d(); g.lda = n3; g.sA = n3 * n3;
   g.B = P.R33a.d(); g.ldb = n3; g.sB = n3 * n3;
   g.C = P.Winv.d(); g.ldc = n3; g.sC = n3 * n3;
   g.alpha = -1.0; g.beta = 1.0;
-  zgemm(g, st);
+  timed_gemm(f.build_prof, gname, g, st);
   // T[:, perm(I1)] = R33b R31a  (T[:, perm(I2)] = -R32b was written by the extract)
   g = GemmDesc();
   g.M = n3; g.N = n1; g.K = n3; g.batch = nbox;
   g.A = P.R33b.d(); g.lda = n3; g.sA = n3 * n3;
-  g.B = R31a.d(); g.ldb = n3; g.sB = n3 * n1;
-  g.C = T.d(); g.ldc = n3; g.sC = n3 * nbp; g.ccol = P.dperm;
+  g.B = sc.R31a.d(); g.ldb = n3; g.sB = n3 * n1;
+  g.C = sc.T.d(); g.ldc = n3; g.sC = n3 * nbp; g.ccol = P.dperm;
   g.alpha = 1.0; g.beta = 0.0;
-  zgemm(g, st);
+  timed_gemm(f.build_prof, gname, g, st);
   // W^{-1}
-  zinv((int)n3, (int)nbox, P.Winv.d(), n3, n3 * n3, P.Winv.d(), n3, n3 * n3, info.i(),
-       work.p, st);
+  {
+    Stage s(f.build_prof, "merge_inv", nbox * 8.0 * n3 * n3 * n3, nbox * 2.0 * n3 * n3 * 16);
+    zinv((int)n3, (int)nbox, P.Winv.d(), n3, n3 * n3, P.Winv.d(), n3, n3 * n3, info,
+         sc.work.p, st);
+  }
   // Phi^a = W^{-1} T   (eq. (talpha))
   g = GemmDesc();
   g.M = n3; g.N = nbp; g.K = n3; g.batch = nbox;
   g.A = P.Winv.d(); g.lda = n3; g.sA = n3 * n3;
-  g.B = T.d(); g.ldb = n3; g.sB = n3 * nbp;
+  g.B = sc.T.d(); g.ldb = n3; g.sB = n3 * nbp;
   g.C = P.PhiA.d(); g.ldc = n3; g.sC = n3 * nbp;
   g.alpha = 1.0; g.beta = 0.0;
-  zgemm(g, st);
+  timed_gemm(f.build_prof, gname, g, st);
   // Phi^b = [-R31a, 0] - R33a Phi^a   (eq. (tbeta), short form)
   g = GemmDesc();
   g.M = n3; g.N = nbp; g.K = n3; g.batch = nbox;
@@ -460,51 +661,101 @@ void build_level(hps_factor& f, int l) {
   g.B = P.PhiA.d(); g.ldb = n3; g.sB = n3 * nbp;
   g.C = P.PhiB.d(); g.ldc = n3; g.sC = n3 * nbp;
   g.alpha = -1.0; g.beta = 1.0;
-  zgemm(g, st);
+  timed_gemm(f.build_prof, gname, g, st);
   if (form_R) {
     // R^tau = blockdiag(R11a, R22b) + blockdiag(R13a, R23b) [Phi^a; Phi^b]   (eq. (out))
     g = GemmDesc();
     g.M = n1; g.N = nbp; g.K = n3; g.batch = nbox;
     g.A = P.R13a.d(); g.lda = n1; g.sA = n1 * n3;
     g.B = P.PhiA.d(); g.ldb = n3; g.sB = n3 * nbp;
-    g.C = f.R[l]->d(); g.ldc = nbp; g.sC = nbp * nbp; g.crow = P.dperm;
+    g.C = f.R[l].d(); g.ldc = nbp; g.sC = nbp * nbp; g.crow = P.dperm;
     g.alpha = 1.0; g.beta = 1.0;
-    zgemm(g, st);
+    timed_gemm(f.build_prof, gname, g, st);
     g.M = n2;
     g.A = P.R23b.d(); g.lda = n2; g.sA = n2 * n3;
     g.B = P.PhiB.d();
     g.crow = P.dperm + n1;
-    zgemm(g, st);
+    timed_gemm(f.build_prof, gname, g, st);
+    f.R_valid[l] = 1;
   }
-  HPS_HIP(hipStreamSynchronize(st));
-  check_info(info, nbox, "interface matrix W");
-  if (!f.opts.keep_all_R) f.R[l + 1].reset();
+  // children's R: overwritten two levels up (ping-pong) unless every R is kept
+  if (!f.opts.keep_all_R) f.R_valid[l + 1] = 0;
+}
+
+void build_all(hps_factor& f, const double* c) {
+  BuildScratch sc;
+  plan_memory(f, sc);
+  HPS_HIP(hipMemsetAsync(sc.info.p, 0, sc.info.bytes, f.stream));
+  build_leaves(f, c, sc);
+  for (int l = f.L - 1; l >= 0; --l) build_level(f, l, sc);
+  // one synchronization for the whole build, then the pivot checks
+  HPS_HIP(hipStreamSynchronize(f.stream));
+  std::vector<int> h(sc.info.bytes / sizeof(int));
+  HPS_HIP(hipMemcpy(h.data(), sc.info.p, sc.info.bytes, hipMemcpyDeviceToHost));
+  check_info(h, 0, f.nleaf, "leaf interior inversion");
+  check_info(h, f.nleaf, f.nleaf, "leaf boundary Schur complement");
+  for (int l = 0; l < f.L; ++l) check_info(h, sc.info_off[l], f.lv[l].nbox, "interface matrix W");
+  // release the ItI buffer that no longer holds a kept operator
+  if (!f.opts.keep_all_R) {
+    for (int b = 0; b < 2; ++b) {
+      bool holds = false;
+      for (int l = 0; l <= f.L; ++l)
+        if (f.R_valid[l] && l % 2 == b) holds = true;
+      if (!holds) f.rbuf[b].release();
+    }
+  }
 }
 
 // ------------------------------------------------------------------ solve
-struct Scratch {
-  std::vector<void*> ptrs;
-  hipStream_t st;
-  explicit Scratch(hipStream_t s) : st(s) {}
+// Workspace of one solve call: a single stream-ordered allocation carved into the
+// per-level vectors.  A dry pass over the same code sizes it (no launches).
+struct Arena {
+  bool dry = true;
+  hipStream_t st = nullptr;
+  char* base = nullptr;
+  size_t used = 0, split_need = 0;
+  void* split = nullptr;
+  void* block = nullptr;
   double* get(size_t bytes) {
-    void* p = nullptr;
-    if (bytes == 0) bytes = 16;
-    hipError_t e = hipMallocAsync(&p, bytes, st);
+    bytes = (bytes + 255) & ~size_t(255);
+    size_t off = used;
+    used += bytes;
+    // in the dry pass the pointer is a placeholder that is never dereferenced
+    return reinterpret_cast<double*>((dry ? reinterpret_cast<char*>(4096) : base) + off);
+  }
+  void skinny(Profiler& pr, const char* name, SkinnyDesc k) {
+    if (dry) {
+      split_need = std::max(split_need, skinny_work_bytes(k));
+      return;
+    }
+    k.work = split;
+    timed_skinny(pr, name, k, st);
+  }
+  void allocate() {
+    size_t total = used + split_need + 256;
+    hipError_t e = hipMallocAsync(&block, total, st);
     if (e != hipSuccess) {
       (void)hipGetLastError();
-      throw Error(HPS_E_NOMEM, "solve workspace allocation failed");
+      block = nullptr;
+      throw Error(HPS_E_NOMEM, "solve workspace allocation of " + std::to_string(total) +
+                                   " bytes failed");
     }
-    ptrs.push_back(p);
-    return static_cast<double*>(p);
+    base = static_cast<char*>(block);
+    split = base + ((used + 255) & ~size_t(255));
+    used = 0;
+    dry = false;
   }
-  ~Scratch() {
-    for (void* p : ptrs) (void)hipFreeAsync(p, st);
+  ~Arena() {
+    if (block) (void)hipFreeAsync(block, st);
   }
 };
 
-void solve_impl(hps_factor& f, int nrhs, const double* s, const double* t, double* u) {
+void solve_pass(hps_factor& f, int nrhs, const double* s, const double* t, double* u,
+                Arena& ws) {
   hipStream_t st = f.stream;
-  Scratch ws(st);
+  Profiler& pr = f.solve_prof;
+  pr.reset(!ws.dry && f.opts.profile != 0, st);
+  const char* nm = "solve_leaf_up";
   const long nl = f.nleaf, n = f.n, nb = f.nb, ni = f.ni;
   const bool up = (s != nullptr);
   std::vector<double*> h(f.L + 1, nullptr), tt(f.L + 1, nullptr), tta(f.L, nullptr),
@@ -518,10 +769,14 @@ void solve_impl(hps_factor& f, int nrhs, const double* s, const double* t, doubl
     k.A = f.BI.d() + 2 * n * nb; k.lda = n; k.sA = n * n;
     k.X = s; k.ldx = nl * ni; k.xoff = f.dxoff.l();
     k.C = ut; k.ldc = n; k.sC = n * nrhs;
-    zgemm_skinny(k, st);
+    ws.skinny(pr, nm, k);
     h[f.L] = ws.get((size_t)nl * nb * nrhs * 16);
-    leaf_h_from_u(f.nleaf, f.n, f.nb, nrhs, f.eta_re, f.eta_im, ut, h[f.L], st);
+    {
+      Stage sg(pr, "solve_gather", 0.0, nl * nb * nrhs * 32.0);
+      if (!ws.dry) leaf_h_from_u(f.nleaf, f.n, f.nb, nrhs, f.eta_re, f.eta_im, ut, h[f.L], st);
+    }
     // merges, bottom-up   (steps (5)-(7))
+    nm = "solve_merge_up";
     for (int l = f.L - 1; l >= 0; --l) {
       LevelPlan& P = f.lv[l];
       MergeLevelDesc d = level_desc(f, P);
@@ -531,28 +786,31 @@ void solve_impl(hps_factor& f, int nrhs, const double* s, const double* t, doubl
       tta[l] = ws.get((size_t)nbox * n3 * nrhs * 16);
       ttb[l] = ws.get((size_t)nbox * n3 * nrhs * 16);
       h[l] = ws.get((size_t)nbox * nbp * nrhs * 16);
-      up_gather(d, nrhs, h[l + 1], h3a, v, ttb[l], h[l], st);
+      {
+        Stage sg(pr, "solve_gather", 0.0, nbox * (2.0 * P.nbc + 3.0 * n3 + nbp) * nrhs * 16);
+        if (!ws.dry) up_gather(d, nrhs, h[l + 1], h3a, v, ttb[l], h[l], st);
+      }
       // v = R33b h3a - h3b
       SkinnyDesc k;
       k.M = n3; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox;
       k.A = P.R33b.d(); k.lda = n3; k.sA = n3 * n3;
       k.X = h3a; k.ldx = n3; k.sX = n3 * nrhs;
       k.C = v; k.ldc = n3; k.sC = n3 * nrhs; k.accumulate = true;
-      zgemm_skinny(k, st);
+      ws.skinny(pr, nm, k);
       // t~3a = W^{-1} v
       k = SkinnyDesc();
       k.M = n3; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox;
       k.A = P.Winv.d(); k.lda = n3; k.sA = n3 * n3;
       k.X = v; k.ldx = n3; k.sX = n3 * nrhs;
       k.C = tta[l]; k.ldc = n3; k.sC = n3 * nrhs;
-      zgemm_skinny(k, st);
+      ws.skinny(pr, nm, k);
       // t~3b = -h3a - R33a t~3a
       k = SkinnyDesc();
       k.M = n3; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox;
       k.A = P.R33a.d(); k.lda = n3; k.sA = n3 * n3;
       k.X = tta[l]; k.ldx = n3; k.sX = n3 * nrhs;
       k.C = ttb[l]; k.ldc = n3; k.sC = n3 * nrhs; k.accumulate = true; k.alpha = -1.0;
-      zgemm_skinny(k, st);
+      ws.skinny(pr, nm, k);
       if (l > 0) {
         // h^tau = [h1a + R13a t~3a ; h2b + R23b t~3b]   (eq. (flux_part))
         k = SkinnyDesc();
@@ -560,16 +818,17 @@ void solve_impl(hps_factor& f, int nrhs, const double* s, const double* t, doubl
         k.A = P.R13a.d(); k.lda = n1; k.sA = n1 * n3;
         k.X = tta[l]; k.ldx = n3; k.sX = n3 * nrhs;
         k.C = h[l]; k.ldc = nbp; k.sC = nbp * nrhs; k.crow = P.dperm; k.accumulate = true;
-        zgemm_skinny(k, st);
+        ws.skinny(pr, nm, k);
         k.M = n2;
         k.A = P.R23b.d(); k.lda = n2; k.sA = n2 * n3;
         k.X = ttb[l];
         k.crow = P.dperm + n1;
-        zgemm_skinny(k, st);
+        ws.skinny(pr, nm, k);
       }
     }
   }
   // downward pass   (steps (10)-(18))
+  nm = "solve_merge_down";
   for (int l = 0; l < f.L; ++l) {
     LevelPlan& P = f.lv[l];
     MergeLevelDesc d = level_desc(f, P);
@@ -577,7 +836,10 @@ void solve_impl(hps_factor& f, int nrhs, const double* s, const double* t, doubl
     const double* tp = (l == 0) ? t : tt[l];
     const long sp = nbp * nrhs;
     tt[l + 1] = ws.get((size_t)2 * nbox * nbc * nrhs * 16);
-    down_scatter(d, nrhs, tp, nbp, tt[l + 1], st);
+    {
+      Stage sg(pr, "solve_gather", 0.0, nbox * 2.0 * (P.n1 + P.n2) * nrhs * 16);
+      if (!ws.dry) down_scatter(d, nrhs, tp, nbp, tt[l + 1], st);
+    }
     for (int side = 0; side < 2; ++side) {
       SkinnyDesc k;
       k.M = n3; k.K = nbp; k.nrhs = nrhs; k.batch = (int)nbox;
@@ -588,11 +850,12 @@ void solve_impl(hps_factor& f, int nrhs, const double* s, const double* t, doubl
       if (up) {
         k.C0 = side ? ttb[l] : tta[l]; k.ld0 = n3; k.s0 = n3 * nrhs;
       }
-      zgemm_skinny(k, st);
+      ws.skinny(pr, nm, k);
     }
   }
   // leaves: u = Psi t + u~   (step (13))
   {
+    nm = "solve_leaf_down";
     SkinnyDesc k;
     k.M = n; k.K = nb; k.nrhs = nrhs; k.batch = (int)nl;
     k.A = f.BI.d(); k.lda = n; k.sA = n * n;
@@ -601,7 +864,7 @@ void solve_impl(hps_factor& f, int nrhs, const double* s, const double* t, doubl
     if (up) {
       k.C0 = ut; k.ld0 = n; k.s0 = n * nrhs;
     }
-    zgemm_skinny(k, st);
+    ws.skinny(pr, nm, k);
   }
 }
 
@@ -717,10 +980,8 @@ int hps_build(const hps_domain* dom, int32_t p, double kappa, double eta_re, dou
     f->stream = static_cast<hipStream_t>(f->opts.stream);
     make_plan(*f);
     upload_plan(*f);
-    f->R.clear();
-    f->R.resize(f->L + 1);
-    build_leaves(*f, c_interior);
-    for (int l = f->L - 1; l >= 0; --l) build_level(*f, l);
+    f->build_prof.reset(f->opts.profile != 0, f->stream);
+    build_all(*f, c_interior);
     *out = f.release();
   });
 }
@@ -730,7 +991,11 @@ int hps_solve(hps_factor* f, int32_t nrhs, const double* s, const double* t, dou
     if (!f) throw Error(HPS_E_INVALID, "factor is NULL");
     if (!t || !u) throw Error(HPS_E_INVALID, "t and u must be non-NULL");
     if (nrhs < 1) throw Error(HPS_E_INVALID, "nrhs must be >= 1");
-    solve_impl(*f, nrhs, s, t, u);
+    Arena ws;
+    ws.st = f->stream;
+    solve_pass(*f, nrhs, s, t, u, ws);  // sizes the workspace
+    ws.allocate();
+    solve_pass(*f, nrhs, s, t, u, ws);
   });
 }
 
@@ -776,14 +1041,14 @@ int hps_factor_get(const hps_factor* f, int32_t what, int32_t level, int32_t box
       c = (what == HPS_OP_PSI) ? f->nb : f->ni;
       off = (long)box * f->n * f->n + (what == HPS_OP_PSI ? 0 : (long)f->n * f->nb);
     } else if (what == HPS_OP_R) {
-      if (!f->R[level] || !f->R[level]->p) throw Error(HPS_E_INVALID, "R of this level is not kept");
-      src = f->R[level]->d();
+      if (!f->R_valid[level]) throw Error(HPS_E_INVALID, "R of this level is not kept");
+      src = f->R[level].d();
       r = c = ld = f->nbl[level];
       off = (long)box * r * r;
     } else {
       if (level >= f->L) throw Error(HPS_E_INVALID, "merge operators live on levels < leaves");
       const LevelPlan& P = f->lv[level];
-      const DevBuf* b = nullptr;
+      const View* b = nullptr;
       switch (what) {
         case HPS_OP_WINV: b = &P.Winv; r = c = P.n3; break;
         case HPS_OP_PHI_A: b = &P.PhiA; r = P.n3; c = P.nbp; break;
@@ -803,6 +1068,37 @@ int hps_factor_get(const hps_factor* f, int32_t what, int32_t level, int32_t box
     if (dst_len < r * c) throw Error(HPS_E_INVALID, "destination too small");
     HPS_HIP(hipStreamSynchronize(f->stream));
     HPS_HIP(hipMemcpy2D(dst, r * 16, src + 2 * off, ld * 16, r * 16, c, hipMemcpyDeviceToHost));
+  });
+}
+
+int hps_stage_times(const hps_factor* f, int32_t which, hps_stage_time* out, int32_t cap,
+                    int32_t* n) {
+  return guard([&] {
+    if (!f || !out || !n || cap < 0) throw Error(HPS_E_INVALID, "NULL argument");
+    if (which != 0 && which != 1) throw Error(HPS_E_INVALID, "which must be 0 (build) or 1 (solve)");
+    const Profiler& pr = which == 0 ? f->build_prof : f->solve_prof;
+    std::vector<hps_stage_time> agg;
+    for (const StageRec& r : pr.recs) {
+      HPS_HIP(hipEventSynchronize(r.b));
+      float ms = 0.f;
+      HPS_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      hps_stage_time* s = nullptr;
+      for (auto& a : agg)
+        if (r.name == a.name) s = &a;
+      if (!s) {
+        hps_stage_time z;
+        std::memset(&z, 0, sizeof(z));
+        std::strncpy(z.name, r.name.c_str(), sizeof(z.name) - 1);
+        agg.push_back(z);
+        s = &agg.back();
+      }
+      s->launches += 1;
+      s->ms += ms;
+      s->flops += r.flops;
+      s->bytes += r.bytes;
+    }
+    *n = (int32_t)std::min<size_t>(agg.size(), (size_t)cap);
+    for (int i = 0; i < *n; ++i) out[i] = agg[i];
   });
 }
 

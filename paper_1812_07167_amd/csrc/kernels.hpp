@@ -38,7 +38,10 @@ struct SkinnyDesc {
   const double* C0 = nullptr; long ld0 = 0, s0 = 0; const long* c0off = nullptr;
   bool accumulate = false;
   double alpha = 1.0;
+  // workspace for the split-K partial sums (at least skinny_work_bytes(d) bytes)
+  void* work = nullptr;
 };
+size_t skinny_work_bytes(const SkinnyDesc& d);
 void zgemm_skinny(const SkinnyDesc& d, hipStream_t st);
 
 // ------------------------------------------------------------------ complex inversion

@@ -10,7 +10,7 @@
 // Only S and what follows are complex.  A_ib, N_i, N_b are sparse (one grid line per
 // boundary node), so X, Z and S are formed by line sums.
 //
-// Kernels: leaf_inv (A_ii^{-1} by register-resident Gauss-Jordan with partial
+// Kernels: leaf_inv (A_ii^{-1} by register-resident blocked Gauss-Jordan with partial
 // pivoting, one workgroup per leaf), leaf_xzs (X, Z, S), then the batched complex
 // inverse of S and three batched MFMA GEMMs (launched by the host driver).
 #include "kernels.hpp"
@@ -18,60 +18,84 @@
 namespace hps {
 namespace {
 
-// Thread grid G x G per leaf, each thread owning E x E entries of A_ii (padded).
+// Thread grid GR x GC per leaf, each thread owning ER x EC entries of A_ii (padded):
+// rows tr + GR a, columns tc + GC b.  Pivots are taken in blocks of NBK columns.
 template <int P> struct LeafInvCfg {
   static constexpr int m = P - 2;
   static constexpr int NI = m * m;
-  static constexpr int E = P <= 9 ? (m > 0 ? m : 1)
-                         : P == 10 ? 4 : P <= 13 ? 5 : P == 14 ? 6 : 7;
-  static constexpr int G = (NI + E - 1) / E;
-  static constexpr int NLIVE = G * G;                       // threads that own entries
+  static constexpr int ER = P <= 9 ? (m > 0 ? m : 1)
+                          : P == 10 ? 4 : P <= 13 ? 5 : P == 14 ? 6 : 7;
+  static constexpr int EC = P == 16 ? 9 : ER;               // p=16: 616 threads, 63 entries
+  static constexpr int GR = (NI + ER - 1) / ER;
+  static constexpr int GC = (NI + EC - 1) / EC;
+  static constexpr int GE = (GC * EC > GR * ER ? GC * EC : GR * ER);  // LDS row stride
+  static constexpr int NLIVE = GR * GC;                     // threads that own entries
   static constexpr int NT = ((NLIVE + 63) / 64) * 64;       // whole waves (shuffles)
-  static constexpr int LDS_DOUBLES = 19200;          // staging capacity
+  static constexpr int NBK = 8;                             // pivots per block
+  static constexpr int PQ = (NI + 63) / 64;                 // panel rows per lane
+  static constexpr int LDS_DOUBLES = 19200;                 // GJ buffers / output staging
   static constexpr int CW = (LDS_DOUBLES / NI) < NI ? (LDS_DOUBLES / NI) : NI;
+  static_assert(NT <= 1024, "too many threads");
+  static_assert(GR * ER >= NI && 3 * NBK * GE <= LDS_DOUBLES, "bad leaf grid");
 };
 
+// A_ii^{-1} by blocked Gauss-Jordan with partial pivoting, matrix resident in
+// registers.  Per block K of NBK pivot columns:
+//   1. owners publish the panel columns M[:, K] to LDS;
+//   2. wave 0 runs the NBK elimination steps on the panel (pivot = largest unused
+//      |entry|), giving the block transformation Q and the pivot rows P_K;
+//   3. owners of the pivot rows publish X = M[P_K, :];
+//   4. every entry outside K becomes (pivot rows zeroed) + Q X, entries in K become Q.
+// This is the same in-place elimination as column-at-a-time Gauss-Jordan (the block
+// step applies the product of the NBK elementary transformations at once); the
+// in-place result M satisfies A^{-1}[k][piv[j]] = M[piv[k]][j].
 template <int P>
 __global__ __launch_bounds__(LeafInvCfg<P>::NT) void leaf_inv_kernel(LeafDesc d) {
   using Cfg = LeafInvCfg<P>;
-  constexpr int m = Cfg::m, NI = Cfg::NI, E = Cfg::E, G = Cfg::G;
+  constexpr int m = Cfg::m, NI = Cfg::NI, ER = Cfg::ER, EC = Cfg::EC, GR = Cfg::GR,
+                GC = Cfg::GC, GE = Cfg::GE;
+  constexpr int NBK = Cfg::NBK, PQ = Cfg::PQ;
   constexpr int NB = 4 * m, N = P * P - 4;
-  // GJ buffers and the output staging area share one LDS pool.
   __shared__ double pool[Cfg::LDS_DOUBLES];
   __shared__ int piv[NI], ipiv[NI];
+  __shared__ int slot[NI];          // position of a row in the current block's pivots, or -1
+  __shared__ int used_s[NI];
   __shared__ double sD[2][P * P];
-  __shared__ double s_cval[2][G];
-  __shared__ int s_cidx[2][G];
   __shared__ int s_bad;
-  double* colbuf = pool;              // [2][G*E]
-  double* rowbuf = pool + 2 * G * E;  // [2][G*E]
+  double* Pn = pool;                // [NBK][NI]  panel columns
+  double* Qs = pool + NBK * GE;     // [NBK][NI]  block transformation
+  double* Xs = pool + 2 * NBK * GE; // [NBK][GE]  pivot rows
 
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const bool live = tid < Cfg::NLIVE;  // padding threads own nothing and publish nothing
-  const int tr = tid % G, tc = tid / G;
+  const int tr = tid % GR, tc = tid / GR;
   const long h = blockIdx.x;
   const int g = d.leaf_grid[h];
   for (int e = tid; e < P * P; e += Cfg::NT) {
     sD[0][e] = d.D[2 * P * P + e];  // Dxx
     sD[1][e] = d.D[3 * P * P + e];  // Dyy
   }
+  for (int i = tid; i < NI; i += Cfg::NT) {
+    slot[i] = -1;
+    used_s[i] = 0;
+  }
+  for (int e = tid; e < 3 * NBK * GE; e += Cfg::NT) pool[e] = 0.0;
   if (tid == 0) s_bad = 0;
   __syncthreads();
   const double k2 = d.kappa * d.kappa;
   const double* cl = d.c + (long)g * NI;
 
   // assemble A_ii = -Dxx (x) I - I (x) Dyy - kappa^2 diag(c) on interior nodes
-  double M[E][E];
-  unsigned used = 0;
+  double M[ER][EC];
 #pragma unroll
-  for (int a = 0; a < E; ++a) {
-    const int r = tr + G * a;
+  for (int a = 0; a < ER; ++a) {
+    const int r = tr + GR * a;
     const int ir = r % m + 1, jr = r / m + 1;
     const double cr = (live && r < NI) ? cl[r] : 0.0;
-    if (!live || r >= NI) used |= 1u << a;
 #pragma unroll
-    for (int b = 0; b < E; ++b) {
-      const int c = tc + G * b;
+    for (int b = 0; b < EC; ++b) {
+      const int c = tc + GC * b;
       double v = 0.0;
       if (live && r < NI && c < NI) {
         const int ic = c % m + 1, jc = c / m + 1;
@@ -83,78 +107,131 @@ __global__ __launch_bounds__(LeafInvCfg<P>::NT) void leaf_inv_kernel(LeafDesc d)
     }
   }
 
-  for (int k = 0; k < NI; ++k) {
-    const int buf = k & 1;
-    const int tck = k % G, bk = k / G;
-    // Phase A: owners of column k publish it and their best pivot candidate
-    if (live && tc == tck) {
-      double best = -1.0;
-      int bi = NI;
+#pragma unroll 1
+  for (int k0 = 0; k0 < NI; k0 += NBK) {
+    const int nk = (NI - k0) < NBK ? (NI - k0) : NBK;
+    // 1. panel columns
+    if (live) {
 #pragma unroll
-      for (int a = 0; a < E; ++a) {
-        double v = 0.0;
+      for (int a = 0; a < ER; ++a) {
+        const int ra = tr + GR * a;
 #pragma unroll
-        for (int b = 0; b < E; ++b)
-          if (b == bk) v = M[a][b];
-        const int r = tr + G * a;
-        if (r < NI) colbuf[buf * G * E + r] = v;
-        const double av = ((used >> a) & 1u) ? -1.0 : fabs(v);
-        if (av > best) { best = av; bi = r; }
-      }
-      s_cval[buf][tr] = best;
-      s_cidx[buf][tr] = bi;
-    }
-    __syncthreads();
-    // Phase B: every wave reduces the G candidates; pivot-row owners publish the row
-    double best = -1.0;
-    int bi = NI;
-    {
-      const int ln = tid & 63;
-      if (ln < G) { best = s_cval[buf][ln]; bi = s_cidx[buf][ln]; }
-      for (int off = 32; off > 0; off >>= 1) {
-        double ob = __shfl_xor(best, off);
-        int oi = __shfl_xor(bi, off);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-    }
-    if (!(best > 0.0)) {
-      if (tid == 0) s_bad = k + 1;
-      break;
-    }
-    const int r = bi;
-    if (live && tr == r % G) {
-      const int ar = r / G;
-#pragma unroll
-      for (int b = 0; b < E; ++b) {
-        double v = 0.0;
-#pragma unroll
-        for (int a = 0; a < E; ++a)
-          if (a == ar) v = M[a][b];
-        const int c = tc + G * b;
-        if (c < NI) rowbuf[buf * G * E + c] = v;
-      }
-    }
-    if (tid == 0) piv[k] = r;
-    __syncthreads();
-    // Phase C: rank-1 update with the in-place inverse column
-    const double ip = 1.0 / colbuf[buf * G * E + r];
-#pragma unroll
-    for (int a = 0; a < E; ++a) {
-      const int ra = tr + G * a;
-      if (ra == r) {
-        used |= 1u << a;
-#pragma unroll
-        for (int b = 0; b < E; ++b) {
-          const int c = tc + G * b;
-          M[a][b] = (c == k) ? ip : M[a][b] * ip;
+        for (int b = 0; b < EC; ++b) {
+          const int j = tc + GC * b - k0;
+          if (ra < NI && j >= 0 && j < nk) Pn[j * GE + ra] = M[a][b];
         }
-      } else {
-        const double f = (ra < NI) ? colbuf[buf * G * E + ra] * ip : 0.0;
+      }
+    }
+    __syncthreads();
+    // 2. elimination on the panel (wave 0, panel in LDS)
+    if (wave == 0) {
+      if (lane == 0 && k0 > 0)
+        for (int s = 0; s < NBK; ++s) slot[piv[k0 - NBK + s]] = -1;
+      unsigned usedq = 0;
 #pragma unroll
-        for (int b = 0; b < E; ++b) {
-          const int c = tc + G * b;
-          const double rv = (c < NI) ? rowbuf[buf * G * E + c] : 0.0;
-          M[a][b] = (c == k) ? -f : fma(-f, rv, M[a][b]);
+      for (int q = 0; q < PQ; ++q) {
+        const int i = lane + 64 * q;
+        if (i >= NI || used_s[i]) usedq |= 1u << q;
+      }
+#pragma unroll 1
+      for (int s = 0; s < nk; ++s) {
+        double best = -1.0;
+        int bi = NI;
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+          const int i = lane + 64 * q;
+          const double v = ((usedq >> q) & 1u) ? -1.0 : fabs(Pn[s * GE + (i < NI ? i : 0)]);
+          if (v > best) { best = v; bi = i; }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          const double ob = __shfl_xor(best, off);
+          const int oi = __shfl_xor(bi, off);
+          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if (!(best > 0.0)) {
+          if (lane == 0) s_bad = k0 + s + 1;
+          break;
+        }
+        const int r = bi;
+        const double ip = 1.0 / Pn[s * GE + r];
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+          const int i = lane + 64 * q;
+          if (i < NI) {
+            const bool isr = (i == r);
+            const double f = Pn[s * GE + i] * ip;
+#pragma unroll
+            for (int j = 0; j < NBK; ++j) {
+              if (j < nk) {
+                const double pv = Pn[j * GE + i];
+                double v = fma(-f, Pn[j * GE + r], pv);
+                v = isr ? pv * ip : v;
+                v = (j == s) ? (isr ? ip : -f) : v;
+                Qs[j * GE + i] = v;
+              }
+            }
+            if (isr) usedq |= 1u << q;
+          }
+        }
+        // make this step's results the panel of the next step (same wave: LDS in order)
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+          const int i = lane + 64 * q;
+          if (i < NI)
+#pragma unroll
+            for (int j = 0; j < NBK; ++j)
+              if (j < nk) Pn[j * GE + i] = Qs[j * GE + i];
+        }
+        if (lane == 0) {
+          piv[k0 + s] = r;
+          slot[r] = s;
+          used_s[r] = 1;
+        }
+      }
+    }
+    __syncthreads();
+    if (s_bad) break;
+    // 3. pivot rows (values before this block's update); on the panel columns X is the
+    //    identity, so that the update below writes Q there
+    if (live) {
+#pragma unroll
+      for (int a = 0; a < ER; ++a) {
+        const int ra = tr + GR * a;
+        const int sl = ra < NI ? slot[ra] : -1;
+        if (sl >= 0)
+#pragma unroll
+          for (int b = 0; b < EC; ++b) {
+            const int j = tc + GC * b - k0;
+            Xs[sl * GE + tc + GC * b] = (j >= 0 && j < nk) ? (j == sl ? 1.0 : 0.0) : M[a][b];
+          }
+      }
+    }
+    __syncthreads();
+    // 4. block update: M <- (M with pivot rows and panel columns zeroed) + Q X
+    if (live) {
+#pragma unroll
+      for (int a = 0; a < ER; ++a) {
+        const int ra = tr + GR * a;
+        const bool isP = ra < NI && slot[ra] >= 0;
+#pragma unroll
+        for (int b = 0; b < EC; ++b) {
+          const int j = tc + GC * b - k0;
+          const bool inK = j >= 0 && j < nk;
+          M[a][b] = (isP || inK) ? 0.0 : M[a][b];
+        }
+      }
+      const double* qb = Qs + tr;
+      const double* xbp = Xs + tc;
+#pragma unroll 1
+      for (int j = 0; j < nk; ++j) {
+        double xb[EC];
+#pragma unroll
+        for (int b = 0; b < EC; ++b) xb[b] = xbp[j * GE + GC * b];
+#pragma unroll
+        for (int a = 0; a < ER; ++a) {
+          const double qa = qb[j * GE + GR * a];
+#pragma unroll
+          for (int b = 0; b < EC; ++b) M[a][b] = fma(qa, xb[b], M[a][b]);
         }
       }
     }
@@ -173,13 +250,13 @@ __global__ __launch_bounds__(LeafInvCfg<P>::NT) void leaf_inv_kernel(LeafDesc d)
   for (int c0 = 0; c0 < NI; c0 += Cfg::CW) {
     const int cw = (NI - c0) < Cfg::CW ? (NI - c0) : Cfg::CW;
 #pragma unroll
-    for (int a = 0; a < E; ++a) {
-      const int ra = tr + G * a;
+    for (int a = 0; a < ER; ++a) {
+      const int ra = tr + GR * a;
       if (!live || ra >= NI) continue;
       const int orow = ipiv[ra];
 #pragma unroll
-      for (int b = 0; b < E; ++b) {
-        const int c = tc + G * b;
+      for (int b = 0; b < EC; ++b) {
+        const int c = tc + GC * b;
         if (c >= NI) continue;
         const int ocol = piv[c] - c0;
         if (ocol >= 0 && ocol < cw) pool[orow + NI * ocol] = M[a][b];

@@ -95,35 +95,41 @@ __global__ void skinny_reduce_kernel(SkinnyDesc d, int r0, int nr, int nsplit,
   *p = v;
 }
 
-// workspace for split-K partial sums (grown on demand, freed at process exit)
-struct SplitWork {
-  double2* p = nullptr;
-  size_t bytes = 0;
-  ~SplitWork() {}
-};
+int block_threads(int M) { return M <= 64 ? 64 : (M <= 128 ? 128 : 256); }
 
-template <int NR, int BT>
-void run_chunk(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
-  const int tiles = cdiv(d.M, BT);
-  // split K when the row tiles x batch cannot fill the device
+// K is split across workgroups when the row tiles x batch cannot fill the device.
+// Returns the number of splits and the K range per split.
+int split_plan(const SkinnyDesc& d, int* kper_out) {
+  const int tiles = cdiv(d.M, block_threads(d.M));
   int nsplit = 1;
   const long blocks = (long)tiles * d.batch;
   if (blocks < 512 && d.K >= 2 * KC) {
     nsplit = (int)std::min<long>((512 + blocks - 1) / blocks, (d.K + KC - 1) / KC);
     nsplit = std::max(1, std::min(nsplit, 64));
   }
+  int kper = d.K;
+  if (nsplit > 1) {
+    kper = (d.K + nsplit - 1) / nsplit;
+    kper = ((kper + KC - 1) / KC) * KC;
+    nsplit = (d.K + kper - 1) / kper;
+  }
+  *kper_out = kper;
+  return nsplit;
+}
+
+template <int NR, int BT>
+void run_chunk(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
+  const int tiles = cdiv(d.M, BT);
+  int kper = 0;
+  const int nsplit = split_plan(d, &kper);
   if (nsplit == 1) {
     hipLaunchKernelGGL((skinny_kernel<NR, BT>), dim3(tiles, d.batch, 1), dim3(BT), 0, st, d, r0,
                        nr, d.K, (double2*)nullptr);
     HPS_LAUNCH_CHECK();
     return;
   }
-  int kper = (d.K + nsplit - 1) / nsplit;
-  kper = ((kper + KC - 1) / KC) * KC;
-  nsplit = (d.K + kper - 1) / kper;
-  size_t need = (size_t)nsplit * d.batch * NR * d.M * sizeof(double2);
-  double2* part = nullptr;
-  HPS_HIP(hipMallocAsync(reinterpret_cast<void**>(&part), need, st));
+  if (!d.work) throw Error(1, "zgemm_skinny: split-K needs a workspace");
+  double2* part = static_cast<double2*>(d.work);
   hipLaunchKernelGGL((skinny_kernel<NR, BT>), dim3(tiles, d.batch, nsplit), dim3(BT), 0, st, d,
                      r0, nr, kper, part);
   HPS_LAUNCH_CHECK();
@@ -131,7 +137,6 @@ void run_chunk(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
   hipLaunchKernelGGL(skinny_reduce_kernel<NR>, dim3(cdiv(tot, 256)), dim3(256), 0, st, d, r0, nr,
                      nsplit, (const double2*)part);
   HPS_LAUNCH_CHECK();
-  HPS_HIP(hipFreeAsync(part, st));
 }
 
 template <int NR>
@@ -142,6 +147,14 @@ void run_nr(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
 }
 
 }  // namespace
+
+size_t skinny_work_bytes(const SkinnyDesc& d) {
+  if (d.M <= 0 || d.batch <= 0 || d.K <= 0) return 0;
+  int kper = 0;
+  const int nsplit = split_plan(d, &kper);
+  if (nsplit == 1) return 0;
+  return (size_t)nsplit * d.batch * 16 * d.M * sizeof(double2);
+}
 
 void zgemm_skinny(const SkinnyDesc& d, hipStream_t st) {
   if (d.M <= 0 || d.batch <= 0 || d.nrhs <= 0) return;

@@ -9,9 +9,9 @@
 // * n <= SMALL_MAX: one workgroup per matrix, matrix resident in LDS.
 // * larger n: blocked right-looking form.  For each block K of 16 columns a panel
 //   kernel (one 16-wave workgroup per matrix, one panel column per wave, rows in
-//   registers) runs the 16 elimination steps on the panel and emits the block
-//   transformation Q; an extract kernel gathers the pivot rows X = M[P_K, :] (zero on
-//   K) and clears them; a batched MFMA GEMM applies M += Q X to every column.
+//   registers) runs the 16 elimination steps on the panel, emits the block
+//   transformation Q, gathers the pivot rows X = M[P_K, :] (zero on K) and clears
+//   them; a batched MFMA GEMM then applies M += Q X to every column.
 #include "kernels.hpp"
 
 namespace hps {
@@ -99,11 +99,12 @@ __global__ __launch_bounds__(256) void zinv_small_kernel(int n, const double* Ai
 // ------------------------------------------------------------------ blocked
 template <int Q>
 __global__ __launch_bounds__(1024) void zinv_panel_kernel(int n, double* Mg, int k0,
-                                                          double* Qbuf, int* piv, int* used,
-                                                          int* info) {
+                                                          double* Qbuf, double* Xbuf, int* piv,
+                                                          int* used, int* info) {
   __shared__ double2 colbuf[2][64 * Q];
   __shared__ int s_r[2];
   __shared__ double s_v[2];
+  __shared__ int s_piv[PNB];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const long b = blockIdx.x;
   double2* M = reinterpret_cast<double2*>(Mg) + b * (long)n * n;
@@ -165,7 +166,10 @@ __global__ __launch_bounds__(1024) void zinv_panel_kernel(int n, double* Mg, int
         }
       }
     }
-    if (threadIdx.x == 0) pv[k] = r;
+    if (threadIdx.x == 0) {
+      pv[k] = r;
+      s_piv[s] = r;
+    }
   }
   if (bad) {
     if (threadIdx.x == 0) info[b] = bad;
@@ -184,26 +188,22 @@ __global__ __launch_bounds__(1024) void zinv_panel_kernel(int n, double* Mg, int
   // rows that became pivots in this panel
   if (w == 0) {
     for (int s = lane; s < PNB; s += 64)
-      if (k0 + s < n) us[pv[k0 + s]] = 1;
+      if (k0 + s < n) us[s_piv[s]] = 1;
   }
-}
-
-__global__ void zinv_extract_kernel(int n, double* Mg, int k0, double* Xg, const int* piv,
-                                    const int* info) {
-  const long b = blockIdx.y;
-  if (info[b]) return;
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long)PNB * n) return;
-  const int k = e % PNB, j = e / PNB;
-  double2* M = reinterpret_cast<double2*>(Mg) + b * (long)n * n;
-  double2* X = reinterpret_cast<double2*>(Xg) + b * (long)PNB * n;
-  double2 val = cmk(0, 0);
-  if (k0 + k < n && (j < k0 || j >= k0 + PNB)) {
-    const int r = piv[b * (long)n + k0 + k];
-    val = M[r + (long)n * j];
-    M[r + (long)n * j] = cmk(0, 0);
+  // pivot rows X = M[P_K, :] (zero on the panel columns) for the update M += Q X, and
+  // clear those rows outside the panel
+  __syncthreads();
+  double2* X = reinterpret_cast<double2*>(Xbuf) + b * (long)n * PNB;
+  for (long e = threadIdx.x; e < (long)PNB * n; e += blockDim.x) {
+    const int k = e % PNB, j = e / PNB;
+    double2 val = cmk(0, 0);
+    if (k0 + k < n && (j < k0 || j >= k0 + PNB)) {
+      const int r = s_piv[k];
+      val = M[r + (long)n * j];
+      M[r + (long)n * j] = cmk(0, 0);
+    }
+    X[k + (long)PNB * j] = val;
   }
-  X[k + (long)PNB * j] = val;
 }
 
 __global__ void zinv_permute_kernel(int n, const double* Mg, const int* piv, double* Out,
@@ -241,10 +241,10 @@ __global__ void zero_int_kernel(int* p, long cnt) {
 }
 
 template <int Q>
-void launch_panel(int n, int batch, double* M, int k0, double* Qb, int* piv, int* used,
-                  int* info, hipStream_t st) {
-  hipLaunchKernelGGL(zinv_panel_kernel<Q>, dim3(batch), dim3(1024), 0, st, n, M, k0, Qb, piv,
-                     used, info);
+void launch_panel(int n, int batch, double* M, int k0, double* Qb, double* Xb, int* piv,
+                  int* used, int* info, hipStream_t st) {
+  hipLaunchKernelGGL(zinv_panel_kernel<Q>, dim3(batch), dim3(1024), 0, st, n, M, k0, Qb, Xb,
+                     piv, used, info);
 }
 
 }  // namespace
@@ -289,16 +289,12 @@ void zinv(int n, int batch, const double* A, long lda, long sA, double* Out, lon
   }
   const int Qr = (n + 63) / 64;
   for (int k0 = 0; k0 < n; k0 += PNB) {
-    if (Qr <= 2) launch_panel<2>(n, batch, M, k0, Qb, piv, used, info, st);
-    else if (Qr <= 4) launch_panel<4>(n, batch, M, k0, Qb, piv, used, info, st);
-    else if (Qr <= 8) launch_panel<8>(n, batch, M, k0, Qb, piv, used, info, st);
-    else if (Qr <= 16) launch_panel<16>(n, batch, M, k0, Qb, piv, used, info, st);
-    else if (Qr <= 28) launch_panel<28>(n, batch, M, k0, Qb, piv, used, info, st);
-    else launch_panel<32>(n, batch, M, k0, Qb, piv, used, info, st);
-    HPS_LAUNCH_CHECK();
-    long tot = (long)PNB * n;
-    hipLaunchKernelGGL(zinv_extract_kernel, dim3(cdiv(tot, 256), batch), dim3(256), 0, st, n, M,
-                       k0, Xb, piv, info);
+    if (Qr <= 2) launch_panel<2>(n, batch, M, k0, Qb, Xb, piv, used, info, st);
+    else if (Qr <= 4) launch_panel<4>(n, batch, M, k0, Qb, Xb, piv, used, info, st);
+    else if (Qr <= 8) launch_panel<8>(n, batch, M, k0, Qb, Xb, piv, used, info, st);
+    else if (Qr <= 16) launch_panel<16>(n, batch, M, k0, Qb, Xb, piv, used, info, st);
+    else if (Qr <= 28) launch_panel<28>(n, batch, M, k0, Qb, Xb, piv, used, info, st);
+    else launch_panel<32>(n, batch, M, k0, Qb, Xb, piv, used, info, st);
     HPS_LAUNCH_CHECK();
     GemmDesc g;
     g.M = n; g.N = n; g.K = PNB; g.batch = batch;

@@ -21,7 +21,8 @@ OP_PSI, OP_Y, OP_R, OP_WINV, OP_PHI_A, OP_PHI_B, OP_R33A, OP_R33B, OP_R13A, OP_R
 
 EXPORTS = [
     "hps_last_error", "hps_version", "hps_default_opts", "hps_nodes", "hps_build",
-    "hps_solve", "hps_factor_query", "hps_factor_get", "hps_factor_box", "hps_free",
+    "hps_solve", "hps_factor_query", "hps_factor_get", "hps_factor_box", "hps_stage_times",
+    "hps_free",
 ]
 
 
@@ -38,7 +39,12 @@ class Domain(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("keep_all_R", C.c_int32), ("store_root_R", C.c_int32),
-                ("reserved", C.c_int32), ("stream", C.c_void_p)]
+                ("profile", C.c_int32), ("stream", C.c_void_p)]
+
+
+class StageTime(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int32), ("reserved", C.c_int32),
+                ("ms", C.c_double), ("flops", C.c_double), ("bytes", C.c_double)]
 
 
 class FactorInfo(C.Structure):
@@ -75,10 +81,11 @@ def load(path: str = LIB_PATH):
     lib.hps_factor_query.argtypes = [P, C.POINTER(FactorInfo)]
     lib.hps_factor_get.argtypes = [P, I32, I32, I32, P, I64, C.POINTER(I32), C.POINTER(I32)]
     lib.hps_factor_box.argtypes = [P, I32, I32] + [C.POINTER(I32)] * 4
+    lib.hps_stage_times.argtypes = [P, I32, C.POINTER(StageTime), I32, C.POINTER(I32)]
     lib.hps_free.argtypes = [P]
     lib.hps_free.restype = None
     for name in ["hps_nodes", "hps_build", "hps_solve", "hps_factor_query", "hps_factor_get",
-                 "hps_factor_box"]:
+                 "hps_factor_box", "hps_stage_times"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -155,6 +162,14 @@ class Factor:
                 continue
             _check(code)
 
+    def stage_times(self, which):
+        """[(name, launches, ms, flops, bytes)] of the build (0) or the last solve (1)."""
+        buf = (StageTime * 64)()
+        n = C.c_int32()
+        _check(load().hps_stage_times(self.h, which, buf, 64, C.byref(n)))
+        return [(buf[i].name.decode(), buf[i].launches, buf[i].ms, buf[i].flops, buf[i].bytes)
+                for i in range(n.value)]
+
     def box(self, level, box):
         v = [C.c_int32() for _ in range(4)]
         _check(load().hps_factor_box(self.h, level, box, *[C.byref(x) for x in v]))
@@ -162,7 +177,7 @@ class Factor:
 
 
 def hps_build(dom: Domain, p: int, kappa: float, eta: complex, c_interior, keep_all_R=False,
-              store_root_R=True, stream=None) -> Factor:
+              store_root_R=True, stream=None, profile=False) -> Factor:
     """c_interior: float64 device tensor [nx*ny*(p-2)^2].  Returns a Factor."""
     import torch
     lib = load()
@@ -170,6 +185,7 @@ def hps_build(dom: Domain, p: int, kappa: float, eta: complex, c_interior, keep_
     lib.hps_default_opts(C.byref(opts))
     opts.keep_all_R = int(keep_all_R)
     opts.store_root_R = int(store_root_R)
+    opts.profile = int(profile)
     st = stream if stream is not None else torch.cuda.current_stream()
     opts.stream = C.c_void_p(st.cuda_stream)
     out = C.c_void_p()
