@@ -613,10 +613,15 @@ void build_level(hps_factor& f, int l, BuildScratch& sc) {
   d.Rp = form_R ? f.R[l].d() : nullptr;
   d.R33a = P.R33a.d(); d.R33b = P.R33b.d(); d.R13a = P.R13a.d(); d.R23b = P.R23b.d();
   d.R31a = sc.R31a.d(); d.T = sc.T.d(); d.PhiB = P.PhiB.d();
-  const char* gname = "merge_gemm";
+  // profile = 2 names the merge groups per level (for tuning); 1 aggregates them
+  const bool per_level = f.opts.profile == 2;
+  const std::string sfx = per_level ? "@" + std::to_string(l) : std::string();
+  const std::string gname_s = "merge_gemm" + sfx, ename = "merge_extract" + sfx,
+                    iname = "merge_inv" + sfx;
+  const char* gname = gname_s.c_str();
   {
     const double nbc = P.nbc;
-    Stage s(f.build_prof, "merge_extract", 0.0,
+    Stage s(f.build_prof, ename.c_str(), 0.0,
             nbox * (2.0 * nbc * nbc * 16 + (form_R ? nbp * nbp * 16.0 : 0.0) +
                     2.0 * n3 * nbp * 16 + n3 * n3 * 16.0));
     if (form_R) fill_zero(d.Rp, 2 * nbox * nbp * nbp, st);
@@ -642,7 +647,7 @@ void build_level(hps_factor& f, int l, BuildScratch& sc) {
   timed_gemm(f.build_prof, gname, g, st);
   // W^{-1}
   {
-    Stage s(f.build_prof, "merge_inv", nbox * 8.0 * n3 * n3 * n3, nbox * 2.0 * n3 * n3 * 16);
+    Stage s(f.build_prof, iname.c_str(), nbox * 8.0 * n3 * n3 * n3, nbox * 2.0 * n3 * n3 * 16);
     zinv((int)n3, (int)nbox, P.Winv.d(), n3, n3 * n3, P.Winv.d(), n3, n3 * n3, info,
          sc.work.p, st);
   }

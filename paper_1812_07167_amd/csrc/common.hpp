@@ -37,6 +37,43 @@ __host__ __device__ inline double2 crcp(double2 a) {
 }
 __host__ __device__ inline double cabs1(double2 a) { return fabs(a.x) + fabs(a.y); }
 
+// ---------------------------------------------------------------- wave reductions
+// Maximum of an unsigned value over the 64 lanes of a wave (all lanes active), by DPP
+// row shifts (prefix maximum inside each row of 16 lanes) and the row broadcasts of
+// lanes 15 and 31; lane 63 then holds the wave maximum.  0 is the neutral element.
+__device__ inline unsigned wave_max_u32(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Value of a double held by lane `lane` (uniform across the wave).
+__device__ inline double readlane_f64(double v, int lane) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __builtin_bit_cast(double, (long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Pivot search over a wave: every lane offers its best candidate (magnitude mag >= 0,
+// or a negative mag for "none") and its row index.  Returns the row of the largest
+// magnitude, compared in single precision (ties go to the lowest lane), or -1 if no
+// lane has a candidate with a positive magnitude.  Must be called by all 64 lanes.
+__device__ inline int wave_argmax(double mag, int row) {
+  // non-negative floats order like their bit patterns; a positive magnitude below the
+  // single-precision range still counts as a candidate
+  unsigned key = mag > 0.0 ? max(__float_as_uint((float)mag), 1u) : 0u;
+  unsigned best = wave_max_u32(key);
+  if (best == 0u) return -1;
+  unsigned long long hit = __ballot(key == best);
+  int src = __builtin_ctzll(hit);
+  return __builtin_amdgcn_readlane(row, src);
+}
+
 // ---------------------------------------------------------------- errors
 struct Error : std::runtime_error {
   int code;

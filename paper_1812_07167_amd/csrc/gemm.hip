@@ -1,11 +1,13 @@
 // Batched complex GEMM on the FP64 matrix cores of gfx950 (v_mfma_f64_16x16x4f64).
 //
 // A complex product is formed from four real products (Cr += Ar Br - Ai Bi,
-// Ci += Ar Bi + Ai Br); a real operand drops two of them.  Tiles of BM x BN outputs
-// per 256-thread workgroup (four waves in a 2 x 2 arrangement), K staged through LDS
-// in chunks of 16 with the next chunk's global loads issued before the current
-// chunk's MFMAs.  Used by the leaf stage (Sec. 2.1: Psi_i, Y_b, Y_i) and by every
-// merge product of Sec. 2.2 (W, Phi^a, Phi^b, R^tau).
+// Ci += Ar Bi + Ai Br); a real operand drops two of them.  A workgroup of WR x WC
+// waves computes a BM x BN tile of C; K is staged through LDS in chunks of 16, double
+// buffered, with the next chunk's global loads issued before the current chunk's
+// MFMAs.  LDS rows are padded so that the four 16-lane groups of an MFMA operand read
+// fall on alternating halves of the 64 banks.  Used by the leaf stage (Sec. 2.1: Psi_i,
+// Y_b, Y_i), by every merge product of Sec. 2.2 (W, Phi^a, Phi^b, R^tau) and by the
+// block updates of the interface inversion.
 //
 // MFMA f64 16x16x4 lane layout (measured on gfx950): lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; accumulator element v of lane l is D[l/16 + 4 v][l%16].
@@ -16,21 +18,30 @@ namespace {
 
 constexpr int BK = 16;
 
-template <int BM, int BN, bool AR, bool BR>
-__global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc d) {
+constexpr int lds_pad(int w) { return (w % 32 == 16) ? 0 : 16; }
+
+template <int BM, int BN, int WR, int WC, bool AR, bool BR>
+__global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
+  constexpr int NT = 64 * WR * WC;
   constexpr int NPA = AR ? 1 : 2;  // planes (re, im) of A
   constexpr int NPB = BR ? 1 : 2;
-  constexpr int WM = BM / 2, WN = BN / 2;  // per-wave tile
+  constexpr int WM = BM / WR, WN = BN / WC;  // per-wave tile
   constexpr int MB = WM / 16, NB = WN / 16;
-  static_assert(MB >= 1 && NB >= 1, "tile too small");
-  __shared__ double As[2][NPA][BK][BM];
-  __shared__ double Bs[2][NPB][BK][BN];
+  constexpr int LA = BM + lds_pad(BM), LB = BN + lds_pad(BN);
+  static_assert(MB >= 1 && NB >= 1 && WM % 16 == 0 && WN % 16 == 0, "bad tile");
+  static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "tile/threads mismatch");
+  __shared__ double As[2][NPA][BK][LA];
+  __shared__ double Bs[2][NPB][BK][LB];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wr = wave & 1, wc = wave >> 1;
+  const int wr = wave % WR, wc = wave / WR;
   const int tiles_m = (d.M + BM - 1) / BM;
-  const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+  const int tiles = tiles_m * ((d.N + BN - 1) / BN);
+  // keep neighbouring tiles on one XCD (workgroups are dealt to the 8 XCDs in turn)
+  int t = blockIdx.x;
+  if (tiles % 8 == 0 && tiles >= 64) t = (t % 8) * (tiles / 8) + t / 8;
+  const int tm = t % tiles_m, tn = t / tiles_m;
   const int i0 = tm * BM, j0 = tn * BN;
   const long b = blockIdx.y;
 
@@ -46,37 +57,37 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc d) {
       accI[x][y] = d4v{0, 0, 0, 0};
     }
 
-  constexpr int EA = BM * BK / 256;  // A elements per thread per chunk
-  constexpr int EB = BN * BK / 256;
+  constexpr int EA = BM * BK / NT;  // A elements per thread per chunk
+  constexpr int EB = BN * BK / NT;
   double ra[EA][NPA], rb[EB][NPB];
 
   auto gload = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
-      int idx = tid + 256 * e;
-      int i = idx % BM, k = idx / BM;
-      int gi = i0 + i, gk = k0 + k;
-      bool ok = gi < d.M && gk < d.K;
-      long off = (long)gi + d.lda * (long)gk;
+      const int idx = tid + NT * e;
+      const int i = idx % BM, k = idx / BM;
+      const int gi = i0 + i, gk = k0 + k;
+      const bool ok = gi < d.M && gk < d.K;
+      const long off = (long)gi + d.lda * (long)gk;
       if (AR) {
         ra[e][0] = ok ? A[off] : 0.0;
       } else {
-        double2 v = ok ? reinterpret_cast<const double2*>(A)[off] : make_double2(0.0, 0.0);
+        const double2 v = ok ? reinterpret_cast<const double2*>(A)[off] : make_double2(0.0, 0.0);
         ra[e][0] = v.x;
         ra[e][NPA - 1] = v.y;
       }
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
-      int idx = tid + 256 * e;
-      int k = idx % BK, j = idx / BK;
-      int gk = k0 + k, gj = j0 + j;
-      bool ok = gk < d.K && gj < d.N;
-      long off = (long)gk + d.ldb * (long)gj;
+      const int idx = tid + NT * e;
+      const int k = idx % BK, j = idx / BK;
+      const int gk = k0 + k, gj = j0 + j;
+      const bool ok = gk < d.K && gj < d.N;
+      const long off = (long)gk + d.ldb * (long)gj;
       if (BR) {
         rb[e][0] = ok ? B[off] : 0.0;
       } else {
-        double2 v = ok ? reinterpret_cast<const double2*>(B)[off] : make_double2(0.0, 0.0);
+        const double2 v = ok ? reinterpret_cast<const double2*>(B)[off] : make_double2(0.0, 0.0);
         rb[e][0] = v.x;
         rb[e][NPB - 1] = v.y;
       }
@@ -85,15 +96,15 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc d) {
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
-      int idx = tid + 256 * e;
-      int i = idx % BM, k = idx / BM;
+      const int idx = tid + NT * e;
+      const int i = idx % BM, k = idx / BM;
 #pragma unroll
       for (int pl = 0; pl < NPA; ++pl) As[buf][pl][k][i] = ra[e][pl];
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
-      int idx = tid + 256 * e;
-      int k = idx % BK, j = idx / BK;
+      const int idx = tid + NT * e;
+      const int k = idx % BK, j = idx / BK;
 #pragma unroll
       for (int pl = 0; pl < NPB; ++pl) Bs[buf][pl][k][j] = rb[e][pl];
     }
@@ -112,13 +123,13 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc d) {
       double ar[MB], ai[MB], br[NB], bi[NB];
 #pragma unroll
       for (int x = 0; x < MB; ++x) {
-        int r = wr * WM + 16 * x + (lane & 15);
+        const int r = wr * WM + 16 * x + (lane & 15);
         ar[x] = As[buf][0][kl][r];
         ai[x] = AR ? 0.0 : As[buf][NPA - 1][kl][r];
       }
 #pragma unroll
       for (int y = 0; y < NB; ++y) {
-        int c = wc * WN + 16 * y + (lane & 15);
+        const int c = wc * WN + 16 * y + (lane & 15);
         br[y] = Bs[buf][0][kl][c];
         bi[y] = BR ? 0.0 : Bs[buf][NPB - 1][kl][c];
       }
@@ -135,9 +146,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc d) {
             accI[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[x], br[y], accI[x][y], 0, 0, 0);
         }
     }
-    if (kc + 1 < nk) {
-      sstore(buf ^ 1);
-    }
+    if (kc + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
   }
 
@@ -149,15 +158,15 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc d) {
     for (int y = 0; y < NB; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int i = i0 + wr * WM + 16 * x + (lane >> 4) + 4 * v;
-        int j = j0 + wc * WN + 16 * y + (lane & 15);
+        const int i = i0 + wr * WM + 16 * x + (lane >> 4) + 4 * v;
+        const int j = j0 + wc * WN + 16 * y + (lane & 15);
         if (i < d.M && j < d.N) {
-          long ri = d.crow ? d.crow[i] : i;
-          long cj = d.ccol ? d.ccol[j] : j;
+          const long ri = d.crow ? d.crow[i] : i;
+          const long cj = d.ccol ? d.ccol[j] : j;
           double2* p = C + ri + d.ldc * cj;
           double2 val = cmk(d.alpha * accR[x][y][v], d.alpha * accI[x][y][v]);
           if (d.beta != 0.0) {
-            double2 old = *p;
+            const double2 old = *p;
             val.x += d.beta * old.x;
             val.y += d.beta * old.y;
           }
@@ -166,18 +175,19 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc d) {
       }
 }
 
-template <int BM, int BN>
+template <int BM, int BN, int WR, int WC>
 void launch_tile(const GemmDesc& d, hipStream_t st) {
-  int tiles = cdiv(d.M, BM) * cdiv(d.N, BN);
-  dim3 grid(tiles, d.batch);
+  const int tiles = cdiv(d.M, BM) * cdiv(d.N, BN);
+  const dim3 grid(tiles, d.batch);
+  const dim3 block(64 * WR * WC);
   if (d.a_real && d.b_real)
-    hipLaunchKernelGGL((zgemm_kernel<BM, BN, true, true>), grid, dim3(256), 0, st, d);
+    hipLaunchKernelGGL((zgemm_kernel<BM, BN, WR, WC, true, true>), grid, block, 0, st, d);
   else if (d.a_real)
-    hipLaunchKernelGGL((zgemm_kernel<BM, BN, true, false>), grid, dim3(256), 0, st, d);
+    hipLaunchKernelGGL((zgemm_kernel<BM, BN, WR, WC, true, false>), grid, block, 0, st, d);
   else if (d.b_real)
-    hipLaunchKernelGGL((zgemm_kernel<BM, BN, false, true>), grid, dim3(256), 0, st, d);
+    hipLaunchKernelGGL((zgemm_kernel<BM, BN, WR, WC, false, true>), grid, block, 0, st, d);
   else
-    hipLaunchKernelGGL((zgemm_kernel<BM, BN, false, false>), grid, dim3(256), 0, st, d);
+    hipLaunchKernelGGL((zgemm_kernel<BM, BN, WR, WC, false, false>), grid, block, 0, st, d);
 }
 
 }  // namespace
@@ -185,14 +195,20 @@ void launch_tile(const GemmDesc& d, hipStream_t st) {
 void zgemm(const GemmDesc& d, hipStream_t st) {
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
   if (d.batch > 65535) throw Error(1, "zgemm: batch exceeds grid limit");
-  if (d.K <= 0) {
-    // C = beta*C only; K == 0 does not occur on the solver's paths.
-    throw Error(1, "zgemm: K must be positive");
-  }
-  if (d.M <= 32 && d.N <= 32)
-    launch_tile<32, 32>(d, st);
+  if (d.K <= 0) throw Error(1, "zgemm: K must be positive");
+  // tile shape from the operand shape: thin tiles for thin operands, 64 x 64 otherwise
+  if (d.M <= 16)
+    launch_tile<16, 64, 1, 4>(d, st);
+  else if (d.N <= 16)
+    launch_tile<64, 16, 4, 1>(d, st);
+  else if (d.M <= 32 && d.N <= 32)
+    launch_tile<32, 32, 2, 2>(d, st);
+  else if (d.M <= 32)
+    launch_tile<32, 64, 2, 2>(d, st);
+  else if (d.N <= 32)
+    launch_tile<64, 32, 2, 2>(d, st);
   else
-    launch_tile<64, 64>(d, st);
+    launch_tile<64, 64, 2, 2>(d, st);
   HPS_LAUNCH_CHECK();
 }
 

@@ -62,9 +62,11 @@ __global__ __launch_bounds__(LeafInvCfg<P>::NT) void leaf_inv_kernel(LeafDesc d)
   __shared__ int used_s[NI];
   __shared__ double sD[2][P * P];
   __shared__ int s_bad;
-  double* Pn = pool;                // [NBK][NI]  panel columns
-  double* Qs = pool + NBK * GE;     // [NBK][NI]  block transformation
+  double* bufA = pool;              // [NBK][GE]  panel / block transformation
+  double* bufB = pool + NBK * GE;   // [NBK][GE]  (ping-pong partner)
   double* Xs = pool + 2 * NBK * GE; // [NBK][GE]  pivot rows
+  double* pan = bufA;               // receives the next block's panel columns
+  double* oth = bufB;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -110,7 +112,7 @@ __global__ __launch_bounds__(LeafInvCfg<P>::NT) void leaf_inv_kernel(LeafDesc d)
 #pragma unroll 1
   for (int k0 = 0; k0 < NI; k0 += NBK) {
     const int nk = (NI - k0) < NBK ? (NI - k0) : NBK;
-    // 1. panel columns
+    // 1. panel columns (into the buffer that does not hold the previous block's Q)
     if (live) {
 #pragma unroll
       for (int a = 0; a < ER; ++a) {
@@ -118,12 +120,13 @@ __global__ __launch_bounds__(LeafInvCfg<P>::NT) void leaf_inv_kernel(LeafDesc d)
 #pragma unroll
         for (int b = 0; b < EC; ++b) {
           const int j = tc + GC * b - k0;
-          if (ra < NI && j >= 0 && j < nk) Pn[j * GE + ra] = M[a][b];
+          if (ra < NI && j >= 0 && j < nk) pan[j * GE + ra] = M[a][b];
         }
       }
     }
     __syncthreads();
-    // 2. elimination on the panel (wave 0, panel in LDS)
+    // 2. elimination on the panel (wave 0); each step reads one LDS buffer and writes
+    //    the other, so the pivot row is never read after it has been rescaled
     if (wave == 0) {
       if (lane == 0 && k0 > 0)
         for (int s = 0; s < NBK; ++s) slot[piv[k0 - NBK + s]] = -1;
@@ -135,52 +138,40 @@ __global__ __launch_bounds__(LeafInvCfg<P>::NT) void leaf_inv_kernel(LeafDesc d)
       }
 #pragma unroll 1
       for (int s = 0; s < nk; ++s) {
+        const double* src = (s & 1) ? oth : pan;
+        double* dst = (s & 1) ? pan : oth;
         double best = -1.0;
         int bi = NI;
 #pragma unroll
         for (int q = 0; q < PQ; ++q) {
           const int i = lane + 64 * q;
-          const double v = ((usedq >> q) & 1u) ? -1.0 : fabs(Pn[s * GE + (i < NI ? i : 0)]);
+          const double v = ((usedq >> q) & 1u) ? -1.0 : fabs(src[s * GE + (i < NI ? i : 0)]);
           if (v > best) { best = v; bi = i; }
         }
-        for (int off = 32; off > 0; off >>= 1) {
-          const double ob = __shfl_xor(best, off);
-          const int oi = __shfl_xor(bi, off);
-          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
-        if (!(best > 0.0)) {
+        const int r = wave_argmax(best, bi);
+        if (r < 0) {
           if (lane == 0) s_bad = k0 + s + 1;
           break;
         }
-        const int r = bi;
-        const double ip = 1.0 / Pn[s * GE + r];
+        const double ip = 1.0 / src[s * GE + r];
 #pragma unroll
         for (int q = 0; q < PQ; ++q) {
           const int i = lane + 64 * q;
           if (i < NI) {
             const bool isr = (i == r);
-            const double f = Pn[s * GE + i] * ip;
+            const double f = src[s * GE + i] * ip;
 #pragma unroll
             for (int j = 0; j < NBK; ++j) {
               if (j < nk) {
-                const double pv = Pn[j * GE + i];
-                double v = fma(-f, Pn[j * GE + r], pv);
+                const double pv = src[j * GE + i];
+                double v = fma(-f, src[j * GE + r], pv);
                 v = isr ? pv * ip : v;
                 v = (j == s) ? (isr ? ip : -f) : v;
-                Qs[j * GE + i] = v;
+                dst[j * GE + i] = v;
               }
             }
             if (isr) usedq |= 1u << q;
           }
-        }
-        // make this step's results the panel of the next step (same wave: LDS in order)
-#pragma unroll
-        for (int q = 0; q < PQ; ++q) {
-          const int i = lane + 64 * q;
-          if (i < NI)
-#pragma unroll
-            for (int j = 0; j < NBK; ++j)
-              if (j < nk) Pn[j * GE + i] = Qs[j * GE + i];
         }
         if (lane == 0) {
           piv[k0 + s] = r;
@@ -191,6 +182,7 @@ __global__ __launch_bounds__(LeafInvCfg<P>::NT) void leaf_inv_kernel(LeafDesc d)
     }
     __syncthreads();
     if (s_bad) break;
+    const double* Qs = (nk & 1) ? oth : pan;  // buffer written by the last step
     // 3. pivot rows (values before this block's update); on the panel columns X is the
     //    identity, so that the update below writes Q there
     if (live) {
@@ -234,6 +226,11 @@ __global__ __launch_bounds__(LeafInvCfg<P>::NT) void leaf_inv_kernel(LeafDesc d)
           for (int b = 0; b < EC; ++b) M[a][b] = fma(qa, xb[b], M[a][b]);
         }
       }
+    }
+    if (!(nk & 1)) {  // Q is in pan: the next panel goes to the other buffer
+      double* t = pan;
+      pan = oth;
+      oth = t;
     }
   }
   __syncthreads();

@@ -8,17 +8,17 @@
 //
 // * n <= SMALL_MAX: one workgroup per matrix, matrix resident in LDS.
 // * larger n: blocked right-looking form.  For each block K of 16 columns a panel
-//   kernel (one 16-wave workgroup per matrix, one panel column per wave, rows in
-//   registers) runs the 16 elimination steps on the panel, emits the block
-//   transformation Q, gathers the pivot rows X = M[P_K, :] (zero on K) and clears
-//   them; a batched MFMA GEMM then applies M += Q X to every column.
+//   kernel (one workgroup per matrix, panel rows spread over its waves, each row's
+//   16 panel entries in registers) runs the 16 elimination steps on the panel and emits the block
+//   transformation Q; an extract kernel gathers the pivot rows X = M[P_K, :] (zero on
+//   K) and clears them; a batched MFMA GEMM then applies M += Q X to every column.
 #include "kernels.hpp"
 
 namespace hps {
 namespace {
 
 constexpr int SMALL_MAX = 96;
-constexpr int PNB = 16;  // panel width of the blocked path
+constexpr int PNB = 8;   // panel width of the blocked path
 
 // ------------------------------------------------------------------ small (LDS)
 __global__ __launch_bounds__(256) void zinv_small_kernel(int n, const double* Ain, long lda,
@@ -49,14 +49,10 @@ __global__ __launch_bounds__(256) void zinv_small_kernel(int n, const double* Ai
         double v = used[i] ? -1.0 : cabs1(M[i + n * k]);
         if (v > best) { best = v; bi = i; }
       }
-      for (int off = 32; off > 0; off >>= 1) {
-        double ob = __shfl_xor(best, off);
-        int oi = __shfl_xor(bi, off);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
+      const int r = wave_argmax(best, bi);
       if (tid == 0) {
-        s_r = bi;
-        if (!(best > 0.0)) s_bad = k + 1;
+        s_r = r < 0 ? 0 : r;
+        if (r < 0) s_bad = k + 1;
       }
     }
     __syncthreads();
@@ -97,113 +93,153 @@ __global__ __launch_bounds__(256) void zinv_small_kernel(int n, const double* Ai
 }
 
 // ------------------------------------------------------------------ blocked
-template <int Q>
-__global__ __launch_bounds__(1024) void zinv_panel_kernel(int n, double* Mg, int k0,
-                                                          double* Qbuf, double* Xbuf, int* piv,
-                                                          int* used, int* info) {
-  __shared__ double2 colbuf[2][64 * Q];
-  __shared__ int s_r[2];
-  __shared__ double s_v[2];
-  __shared__ int s_piv[PNB];
+// Panel of the blocked path: the n x 16 panel (columns k0..k0+15) of one matrix, rows
+// distributed over the (at most 8) waves of the workgroup (row i: wave i / (64 RPL), slot
+// (i / 64) % RPL, lane i % 64), all 16 panel columns of a row in the owning lane's
+// registers.  Per elimination step: every wave offers its best unused row of the pivot
+// column (DPP reduction), the winner is found from the per-wave candidates in LDS, the
+// owner publishes the pivot row (16 entries), and every lane updates its own rows:
+//     M[i][c] -= f_i M[r][c],  f_i = M[i][k]/p  (f_r = 1 - 1/p, so the pivot row
+//     becomes M[r][c]/p),   and column k becomes -f_i (1/p on the pivot row).
+// Two barriers per step; nothing but the pivot row goes through LDS.
+template <int RPL>
+__global__ __launch_bounds__(512) void zinv_panel_kernel(int n, double* Mg, int k0,
+                                                         double* Qbuf, int* piv, int* used,
+                                                         int* info) {
+  __shared__ unsigned s_key[8];
+  __shared__ int s_row[8];
+  __shared__ double2 prow[PNB];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
   const long b = blockIdx.x;
   double2* M = reinterpret_cast<double2*>(Mg) + b * (long)n * n;
   int* pv = piv + b * (long)n;
   int* us = used + b * (long)n;
-  const int c = k0 + w;
-  double2 v[Q];
-  unsigned long long umask = 0;  // bit q: row lane+64q already used as a pivot
+  const int nk = (n - k0) < PNB ? (n - k0) : PNB;
+  double2 v[RPL][PNB];
+  unsigned umask = 0;  // bit q: row of slot q is used (or beyond n)
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    int i = lane + 64 * q;
-    v[q] = (i < n && c < n) ? M[i + (long)n * c] : cmk(0, 0);
-    if (i >= n || us[i]) umask |= (1ull << q);
+  for (int q = 0; q < RPL; ++q) {
+    const int i = (w * RPL + q) * 64 + lane;
+    const bool ok = i < n;
+    if (!ok || us[i]) umask |= 1u << q;
+#pragma unroll
+    for (int c = 0; c < PNB; ++c)
+      v[q][c] = (ok && c < nk) ? M[i + (long)n * (k0 + c)] : cmk(0, 0);
   }
   int bad = 0;
-  for (int s = 0; s < PNB; ++s) {
-    const int k = k0 + s;
-    if (k >= n) break;
-    const int buf = s & 1;
-    if (w == s) {
-      double best = -1.0;
-      int bi = n;
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        int i = lane + 64 * q;
-        double val = (umask >> q) & 1 ? -1.0 : cabs1(v[q]);
-        if (val > best) { best = val; bi = i; }
-        if (i < n) colbuf[buf][i] = v[q];
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        double ob = __shfl_xor(best, off);
-        int oi = __shfl_xor(bi, off);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      if (lane == 0) { s_r[buf] = bi; s_v[buf] = best; }
+  for (int s = 0; s < PNB; ++s) {
+    if (s >= nk || bad) continue;  // uniform over the workgroup; keeps the loop unrolled
+    const int k = k0 + s;
+    // candidate of this wave
+    double best = -1.0;
+    int bi = 0;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const double val = ((umask >> q) & 1u) ? -1.0 : cabs1(v[q][s]);
+      if (val > best) { best = val; bi = (w * RPL + q) * 64 + lane; }
+    }
+    {
+      const unsigned key = best > 0.0 ? max(__float_as_uint((float)best), 1u) : 0u;
+      const unsigned wkey = wave_max_u32(key);
+      const unsigned long long hit = __ballot(key == wkey);
+      const int src = __builtin_ctzll(hit);
+      const int wrow = __builtin_amdgcn_readlane(bi, src);
+      if (lane == 0) { s_key[w] = wkey; s_row[w] = wrow; }
     }
     __syncthreads();
-    const int r = s_r[buf];
-    if (!(s_v[buf] > 0.0)) { bad = k + 1; break; }
-    const double2 ip = crcp(colbuf[buf][r]);
-    // value of this wave's column at the pivot row
-    double2 mine = cmk(0, 0);
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-      if (q == (r >> 6)) mine = v[q];
-    double2 prw;
-    prw.x = __shfl(mine.x, r & 63);
-    prw.y = __shfl(mine.y, r & 63);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      int i = lane + 64 * q;
-      if (i < n) {
-        if (i == r) {
-          v[q] = (w == s) ? ip : cmul(v[q], ip);
-          umask |= (1ull << q);
-        } else {
-          double2 f = cmul(colbuf[buf][i], ip);
-          v[q] = (w == s) ? cmk(-f.x, -f.y) : csub(v[q], cmul(f, prw));
-        }
+    // winner over the waves
+    int r;
+    {
+      const unsigned key = lane < nw ? s_key[lane] : 0u;
+      const int row = lane < nw ? s_row[lane] : 0;
+      const unsigned gkey = wave_max_u32(key);
+      if (gkey == 0u) {
+        r = -1;
+      } else {
+        const unsigned long long hit = __ballot(key == gkey);
+        r = __builtin_amdgcn_readlane(row, __builtin_ctzll(hit));
       }
     }
-    if (threadIdx.x == 0) {
-      pv[k] = r;
-      s_piv[s] = r;
+    if (r < 0) {
+      bad = k + 1;
+      continue;
     }
+    // the owner publishes the pivot row
+    const int rw = r / (64 * RPL), rq = (r / 64) % RPL, rl = r & 63;
+    if (w == rw && lane == rl) {
+#pragma unroll
+      for (int q = 0; q < RPL; ++q)
+        if (q == rq)
+#pragma unroll
+          for (int c = 0; c < PNB; ++c) prow[c] = v[q][c];
+    }
+    __syncthreads();
+    const double2 ip = crcp(prow[s]);
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int i = (w * RPL + q) * 64 + lane;
+      const bool isr = (i == r);
+      const double2 f0 = cmul(v[q][s], ip);
+      const double2 f = isr ? cmk(1.0 - ip.x, -ip.y) : f0;
+#pragma unroll
+      for (int c = 0; c < PNB; ++c) {
+        if (c == s) continue;
+        const double2 pc = prow[c];  // LDS broadcast read
+        v[q][c].x = fma(-f.x, pc.x, fma(f.y, pc.y, v[q][c].x));
+        v[q][c].y = fma(-f.x, pc.y, fma(-f.y, pc.x, v[q][c].y));
+        // bound the scheduler's look-ahead: hoisting every pivot-row read of the
+        // unrolled steps would need more registers than a 16-wave workgroup has
+        if ((c & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+      v[q][s] = isr ? ip : cmk(-f0.x, -f0.y);
+      if (isr) umask |= 1u << q;
+    }
+    if (threadIdx.x == 0) pv[k] = r;
   }
   if (bad) {
     if (threadIdx.x == 0) info[b] = bad;
     return;
   }
-  __syncthreads();
-  double2* Qb = reinterpret_cast<double2*>(Qbuf) + b * (long)n * PNB;
+  // write the panel back (it now holds Q) and keep a copy for the update GEMM.  The
+  // column stride is re-read through an empty asm so that these addresses are formed
+  // here instead of being kept live from the loads at the top (which costs registers).
+  long ld = n;
+  asm volatile("" : "+s"(ld));
+  double2* Mw = reinterpret_cast<double2*>(Mg) + b * ld * ld;
+  double2* Qb = reinterpret_cast<double2*>(Qbuf) + b * ld * PNB;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    int i = lane + 64 * q;
+  for (int q = 0; q < RPL; ++q) {
+    const int i = (w * RPL + q) * 64 + lane;
     if (i < n) {
-      if (c < n) M[i + (long)n * c] = v[q];
-      Qb[i + (long)n * w] = (c < n) ? v[q] : cmk(0, 0);
+#pragma unroll
+      for (int c = 0; c < PNB; ++c) {
+        if (c < nk) Mw[i + ld * (k0 + c)] = v[q][c];
+        Qb[i + ld * c] = c < nk ? v[q][c] : cmk(0, 0);
+      }
+      if ((umask & 1u << q) && !us[i]) us[i] = 1;
     }
   }
-  // rows that became pivots in this panel
-  if (w == 0) {
-    for (int s = lane; s < PNB; s += 64)
-      if (k0 + s < n) us[s_piv[s]] = 1;
+}
+
+// X = M[P_K, :] (zero on the panel columns), and those rows cleared outside the panel.
+__global__ void zinv_extract_kernel(int n, double* Mg, int k0, double* Xg, const int* piv,
+                                    const int* info) {
+  const long b = blockIdx.y;
+  if (info[b]) return;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)PNB * n) return;
+  const int k = e % PNB, j = e / PNB;
+  double2* M = reinterpret_cast<double2*>(Mg) + b * (long)n * n;
+  double2* X = reinterpret_cast<double2*>(Xg) + b * (long)PNB * n;
+  double2 val = cmk(0, 0);
+  if (k0 + k < n && (j < k0 || j >= k0 + PNB)) {
+    const int r = piv[b * (long)n + k0 + k];
+    val = M[r + (long)n * j];
+    M[r + (long)n * j] = cmk(0, 0);
   }
-  // pivot rows X = M[P_K, :] (zero on the panel columns) for the update M += Q X, and
-  // clear those rows outside the panel
-  __syncthreads();
-  double2* X = reinterpret_cast<double2*>(Xbuf) + b * (long)n * PNB;
-  for (long e = threadIdx.x; e < (long)PNB * n; e += blockDim.x) {
-    const int k = e % PNB, j = e / PNB;
-    double2 val = cmk(0, 0);
-    if (k0 + k < n && (j < k0 || j >= k0 + PNB)) {
-      const int r = s_piv[k];
-      val = M[r + (long)n * j];
-      M[r + (long)n * j] = cmk(0, 0);
-    }
-    X[k + (long)PNB * j] = val;
-  }
+  X[k + (long)PNB * j] = val;
 }
 
 __global__ void zinv_permute_kernel(int n, const double* Mg, const int* piv, double* Out,
@@ -240,10 +276,11 @@ __global__ void zero_int_kernel(int* p, long cnt) {
   if (e < cnt) p[e] = 0;
 }
 
-template <int Q>
-void launch_panel(int n, int batch, double* M, int k0, double* Qb, double* Xb, int* piv,
-                  int* used, int* info, hipStream_t st) {
-  hipLaunchKernelGGL(zinv_panel_kernel<Q>, dim3(batch), dim3(1024), 0, st, n, M, k0, Qb, Xb,
+template <int RPL>
+void launch_panel(int n, int batch, double* M, int k0, double* Qb, int* piv, int* used,
+                  int* info, hipStream_t st) {
+  const int waves = std::max(1, std::min(8, (n + 64 * RPL - 1) / (64 * RPL)));
+  hipLaunchKernelGGL(zinv_panel_kernel<RPL>, dim3(batch), dim3(64 * waves), 0, st, n, M, k0, Qb,
                      piv, used, info);
 }
 
@@ -287,15 +324,17 @@ void zinv(int n, int batch, const double* A, long lda, long sA, double* Out, lon
     hipLaunchKernelGGL(zero_int_kernel, dim3(cdiv(ni, 256)), dim3(256), 0, st, piv, ni);
     HPS_LAUNCH_CHECK();
   }
-  const int Qr = (n + 63) / 64;
   for (int k0 = 0; k0 < n; k0 += PNB) {
-    if (Qr <= 2) launch_panel<2>(n, batch, M, k0, Qb, Xb, piv, used, info, st);
-    else if (Qr <= 4) launch_panel<4>(n, batch, M, k0, Qb, Xb, piv, used, info, st);
-    else if (Qr <= 8) launch_panel<8>(n, batch, M, k0, Qb, Xb, piv, used, info, st);
-    else if (Qr <= 16) launch_panel<16>(n, batch, M, k0, Qb, Xb, piv, used, info, st);
-    else if (Qr <= 28) launch_panel<28>(n, batch, M, k0, Qb, Xb, piv, used, info, st);
-    else launch_panel<32>(n, batch, M, k0, Qb, Xb, piv, used, info, st);
+    if (n <= 512) launch_panel<1>(n, batch, M, k0, Qb, piv, used, info, st);
+    else if (n <= 1024) launch_panel<2>(n, batch, M, k0, Qb, piv, used, info, st);
+    else launch_panel<4>(n, batch, M, k0, Qb, piv, used, info, st);
     HPS_LAUNCH_CHECK();
+    {
+      const long tot = (long)PNB * n;
+      hipLaunchKernelGGL(zinv_extract_kernel, dim3(cdiv(tot, 256), batch), dim3(256), 0, st, n,
+                         M, k0, Xb, piv, info);
+      HPS_LAUNCH_CHECK();
+    }
     GemmDesc g;
     g.M = n; g.N = n; g.K = PNB; g.batch = batch;
     g.A = Qb; g.lda = n; g.sA = (long)n * PNB;
