@@ -29,13 +29,23 @@ sys.path.insert(0, ROOT)
 
 METRIC = "HPS build DOF/s + RHS solves/s at stated rel. L2 error; p99 solve latency"
 PEAK = {"hbm": (8000.0, "GB/s"), "mfma": (78.6, "TFLOP/s"), "alu": (78.6, "TFLOP/s")}
-# which roofline bounds each kernel group of the library
-BOUND = {
-    "leaf_inv": "alu", "leaf_xzs": "hbm", "leaf_sinv": "alu", "leaf_r": "hbm",
-    "leaf_gemm": "mfma", "merge_extract": "hbm", "merge_gemm": "mfma", "merge_inv": "mfma",
-    "solve_leaf_up": "hbm", "solve_leaf_down": "hbm", "solve_merge_up": "hbm",
-    "solve_merge_down": "hbm", "solve_gather": "hbm",
-}
+# GEMM variant recorded by the library ("MxN" tile + real/complex A and B) -> kernel
+GEMM_TILES = {"16x64": (16, 64, 1, 4), "64x16": (64, 16, 4, 1), "32x32": (32, 32, 2, 2),
+              "32x64": (32, 64, 2, 2), "64x32": (64, 32, 2, 2), "64x64": (64, 64, 2, 2)}
+
+
+def kernel_of(stage, p):
+    """The one kernel behind a timing record of the library, with its roofline bound,
+    or None when the record covers several kernels."""
+    base = stage.split("@")[0].split("[")[0]
+    if "[" in stage:
+        var = stage[stage.index("[") + 1:-1]
+        bm, bn, wr, wc = GEMM_TILES[var[:-2]]
+        ar, br = ("true" if var[-2] == "r" else "false"), ("true" if var[-1] == "r" else "false")
+        return "zgemm_kernel<%d, %d, %d, %d, %s, %s>" % (bm, bn, wr, wc, ar, br), "mfma"
+    return {"leaf_inv": ("leaf_inv_kernel<%d>" % p, "alu"),
+            "leaf_xzs": ("leaf_xzs_kernel<%d>" % p, "alu"),
+            "leaf_r": ("leaf_r_kernel", "hbm")}.get(base)
 
 
 def log(*a):
@@ -54,18 +64,20 @@ def workload(nx=64, ny=64, p=16, kappa=100.0, nrhs=16, seed=0, nodes=None):
     return c, s, t, exact
 
 
-def cpu_baseline(n_side, p, kappa, nrhs, seed):
-    """The CPU oracle, as it stands, on a bounded sample of the workload: the same p,
-    kappa, c and right-hand sides on an n_side x n_side leaf grid."""
+def cpu_baseline(nx, ny, p, kappa, nrhs, seed):
+    """The CPU oracle, as it stands, on a bounded sample of the workload: the corner
+    [0, nx/64] x [0, ny/64] of the unit square with the workload's own 1/64 x 1/64 leaves,
+    the same p, kappa, c and manufactured right-hand sides."""
     from oracle import hps_oracle as O
+    x1, y1 = nx / 64.0, ny / 64.0
 
-    def onodes(nx, ny, pp):
-        prob = O.Problem(0.0, 1.0, 0.0, 1.0, nx, ny, pp, kappa, kappa)
-        b, nr = prob.root_boundary()
-        return prob.leaf_nodes(), prob.interior_nodes(), b, nr
+    def onodes(a, b, pp):
+        prob = O.Problem(0.0, x1, 0.0, y1, a, b, pp, kappa, kappa)
+        bd, nr = prob.root_boundary()
+        return prob.leaf_nodes(), prob.interior_nodes(), bd, nr
 
-    c, s, t, exact = workload(n_side, n_side, p, kappa, nrhs, seed, onodes)
-    prob = O.Problem(0.0, 1.0, 0.0, 1.0, n_side, n_side, p, kappa, kappa)
+    c, s, t, exact = workload(nx, ny, p, kappa, nrhs, seed, onodes)
+    prob = O.Problem(0.0, x1, 0.0, y1, nx, ny, p, kappa, kappa)
     t0 = time.perf_counter()
     boxes = O.build(prob, c)
     u = O.solve(prob, boxes, s, t)
@@ -78,14 +90,28 @@ def cpu_baseline(n_side, p, kappa, nrhs, seed):
             cores = int(max(nth))
     except Exception:
         pass
-    dof = n_side * n_side * (p * p - 4)
+    dof = nx * ny * (p * p - 4)
     err = float(np.linalg.norm(u - exact) / np.linalg.norm(exact))
     return {"value": dof / dt, "unit": "DOF/s (build + one %d-RHS solve)" % nrhs, "cores": cores,
             "kind": "oracle", "seconds": dt, "rel_l2_vs_exact": err,
-            "sample": "oracle build + one %d-RHS solve on %dx%d leaves (p=%d, kappa=%g, same c "
-                      "and right-hand sides; %.3g of the workload's DOF); numpy/OpenBLAS, "
-                      "threads as counted" % (nrhs, n_side, n_side, p, kappa,
-                                              n_side * n_side / 4096.0)}
+            "sample": "oracle build + one %d-RHS solve on the %dx%d-leaf corner [0,%g]x[0,%g] "
+                      "of the workload (same leaves, p=%d, kappa=%g, c and right-hand "
+                      "sides; %.3g of its DOF); numpy/OpenBLAS, threads as counted"
+                      % (nrhs, nx, ny, x1, y1, p, kappa, nx * ny / 4096.0)}
+
+
+def copy_calibration(torch, dev, mib=256, reps=3):
+    """A plain device-to-device copy of `mib` MiB, `reps` times: the HBM byte counters
+    of a profiler run over this command read what one copy of known size costs."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "reps": reps}),
+          flush=True)
 
 
 def main():
@@ -95,8 +121,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nrhs", type=int, default=16)
     ap.add_argument("--latency-solves", type=int, default=40)
-    ap.add_argument("--cpu-side", type=int, default=32)
+    ap.add_argument("--cpu-leaves", default="64x32",
+                    help="leaf grid of the oracle's sample of the workload (NXxNY)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (for scaling the HBM "
+                         "byte counters of a profiler run) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -108,6 +138,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        copy_calibration(torch, dev)
+        return
     H.load()
     nx = ny = 64
     p, kappa, nrhs = 16, 100.0, args.nrhs
@@ -175,17 +208,22 @@ def main():
     f.free()
     lat = np.array(lat)
 
-    # roofline of the dominant kernel group (largest summed time in a step)
-    groups = {}
+    # roofline of the dominant kernel: the kernel with the largest summed time in a
+    # step, among the timing records that each cover launches of one kernel only
+    groups, kernels = {}, {}
     for name, launches, ms, fl, by in list(stages_b) + list(stages_s):
-        g = groups.setdefault(name, [0, 0.0, 0.0, 0.0])
+        base = name.split("@")[0].split("[")[0]
+        g = groups.setdefault(base, [0, 0.0, 0.0, 0.0])
         g[0] += launches
         g[1] += ms
-        g[2] += fl
-        g[3] += by
-    dom_name = max(groups, key=lambda k: groups[k][1])
-    launches, ms, fl, by = groups[dom_name]
-    bound = BOUND.get(dom_name, "hbm")
+        kb = kernel_of(name, p)
+        if kb is not None:
+            kk = kernels.setdefault(kb, [0, 0.0, 0.0, 0.0])
+            kk[0] += launches
+            kk[1] += ms
+            kk[2] += fl
+            kk[3] += by
+    (kname, bound), (launches, ms, fl, by) = max(kernels.items(), key=lambda kv: kv[1][1])
     peak, unit = PEAK[bound]
     if bound == "hbm":
         achieved = by / (ms * 1e-3) / 1e9
@@ -194,9 +232,10 @@ def main():
         achieved = fl / (ms * 1e-3) / 1e12
         per_launch = fl / launches
     roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": None, "kernel": dom_name,
-                "launches_per_step": launches, "avg_launch_ms": round(ms / launches, 4),
-                "algorithmic_per_launch": per_launch}
+                "frac": round(achieved / peak, 4), "traffic": None, "kernel": kname,
+                "launches_per_step": launches, "avg_launch_ms": round(ms / launches, 5),
+                "algorithmic_per_launch": per_launch,
+                "algorithmic_unit": "bytes" if bound == "hbm" else "flops"}
 
     out = {
         "metric": METRIC,
@@ -221,8 +260,9 @@ def main():
         "stages_ms": {k: round(v[1], 3) for k, v in groups.items()},
     }
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) on %dx%d leaves" % (args.cpu_side, args.cpu_side))
-        out["cpu_baseline"] = cpu_baseline(args.cpu_side, p, kappa, nrhs, 0)
+        cx, cy = (int(v) for v in args.cpu_leaves.lower().split("x"))
+        log("cpu baseline (oracle) on %dx%d leaves" % (cx, cy))
+        out["cpu_baseline"] = cpu_baseline(cx, cy, p, kappa, nrhs, 0)
     print(json.dumps(out), flush=True)
 
 

@@ -13,8 +13,7 @@ Everything is complex128 / float64 numpy.  Library primitives used as single ste
 (matrix product).  There is no blocking, fusion or reordering beyond the formulas of
 the paper.  Each function cites the passage it follows.
 
-Readings taken where the paper is silent, garbled or inconsistent (each is listed in
-DESIGN.md as well):
+Readings taken where the paper is silent, garbled or inconsistent:
 
 * Sec. 2.1: the "classic product Chebyshev grid" is read as Chebyshev-Lobatto points,
   p = n_c per direction, stored in ascending coordinate order, with the standard

@@ -179,7 +179,10 @@ void timed_gemm(Profiler& pr, const char* name, const GemmDesc& g, hipStream_t s
   const double by = (double)g.batch * ((double)g.M * g.K * (g.a_real ? 8 : 16) +
                                        (double)g.K * g.N * (g.b_real ? 8 : 16) +
                                        (double)g.M * g.N * 16 * (g.beta != 0.0 ? 2 : 1));
-  Stage s(pr, name, fl, by);
+  // one record name per kernel variant, so that a record's launches are launches of one
+  // kernel (what a profiler's per-kernel average refers to)
+  const std::string nm = std::string(name) + "[" + zgemm_variant(g) + "]";
+  Stage s(pr, nm.c_str(), fl, by);
   zgemm(g, st);
 }
 
@@ -690,7 +693,7 @@ void build_level(hps_factor& f, int l, BuildScratch& sc) {
 void build_all(hps_factor& f, const double* c) {
   BuildScratch sc;
   plan_memory(f, sc);
-  HPS_HIP(hipMemsetAsync(sc.info.p, 0, sc.info.bytes, f.stream));
+  fill_zero_int(sc.info.i(), (long)(sc.info.bytes / sizeof(int)), f.stream);
   build_leaves(f, c, sc);
   for (int l = f.L - 1; l >= 0; --l) build_level(f, l, sc);
   // one synchronization for the whole build, then the pivot checks

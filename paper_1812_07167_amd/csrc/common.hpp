@@ -35,6 +35,12 @@ __host__ __device__ inline double2 crcp(double2 a) {
     return cmk(r / d, -1.0 / d);
   }
 }
+// 1 / a with one division (|a|^2 must stay inside the double range: used for pivots of
+// matrices with entries of moderate size, where |a| is the column's largest entry)
+__host__ __device__ inline double2 crcp_fast(double2 a) {
+  const double d = 1.0 / fma(a.x, a.x, a.y * a.y);
+  return cmk(a.x * d, -a.y * d);
+}
 __host__ __device__ inline double cabs1(double2 a) { return fabs(a.x) + fabs(a.y); }
 
 // ---------------------------------------------------------------- wave reductions

@@ -192,23 +192,38 @@ void launch_tile(const GemmDesc& d, hipStream_t st) {
 
 }  // namespace
 
+// tile shape from the operand shape: thin tiles for thin operands, 64 x 64 otherwise
+enum Tile { T16x64, T64x16, T32x32, T32x64, T64x32, T64x64 };
+
+Tile pick_tile(const GemmDesc& d) {
+  if (d.M <= 16) return T16x64;
+  if (d.N <= 16) return T64x16;
+  if (d.M <= 32 && d.N <= 32) return T32x32;
+  if (d.M <= 32) return T32x64;
+  if (d.N <= 32) return T64x32;
+  return T64x64;
+}
+
+std::string zgemm_variant(const GemmDesc& d) {
+  static const char* names[] = {"16x64", "64x16", "32x32", "32x64", "64x32", "64x64"};
+  std::string v = names[pick_tile(d)];
+  v += d.a_real ? "r" : "c";
+  v += d.b_real ? "r" : "c";
+  return v;
+}
+
 void zgemm(const GemmDesc& d, hipStream_t st) {
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
   if (d.batch > 65535) throw Error(1, "zgemm: batch exceeds grid limit");
   if (d.K <= 0) throw Error(1, "zgemm: K must be positive");
-  // tile shape from the operand shape: thin tiles for thin operands, 64 x 64 otherwise
-  if (d.M <= 16)
-    launch_tile<16, 64, 1, 4>(d, st);
-  else if (d.N <= 16)
-    launch_tile<64, 16, 4, 1>(d, st);
-  else if (d.M <= 32 && d.N <= 32)
-    launch_tile<32, 32, 2, 2>(d, st);
-  else if (d.M <= 32)
-    launch_tile<32, 64, 2, 2>(d, st);
-  else if (d.N <= 32)
-    launch_tile<64, 32, 2, 2>(d, st);
-  else
-    launch_tile<64, 64, 2, 2>(d, st);
+  switch (pick_tile(d)) {
+    case T16x64: launch_tile<16, 64, 1, 4>(d, st); break;
+    case T64x16: launch_tile<64, 16, 4, 1>(d, st); break;
+    case T32x32: launch_tile<32, 32, 2, 2>(d, st); break;
+    case T32x64: launch_tile<32, 64, 2, 2>(d, st); break;
+    case T64x32: launch_tile<64, 32, 2, 2>(d, st); break;
+    default: launch_tile<64, 64, 2, 2>(d, st); break;
+  }
   HPS_LAUNCH_CHECK();
 }
 

@@ -22,6 +22,9 @@ struct GemmDesc {
   const int* ccol = nullptr;
 };
 void zgemm(const GemmDesc& d, hipStream_t st);
+// name of the kernel variant zgemm launches for d: tile "MxN" plus r/c for real or
+// complex A and B (e.g. "64x64cc")
+std::string zgemm_variant(const GemmDesc& d);
 
 // ------------------------------------------------------------------ skinny GEMM (solve)
 // out_b(i, r) = alpha * sum_k A_b(i, k) X_b(k, r)  +  addend(i, r),   r < nrhs,
@@ -92,6 +95,7 @@ struct MergeLevelDesc {
   double* PhiB = nullptr;      // [nbox][n3*nbp]
 };
 void fill_zero(double* p, long ndouble, hipStream_t st);
+void fill_zero_int(int* p, long n, hipStream_t st);
 void fill_identity(double* p, int n, long stride, int batch, hipStream_t st);
 void merge_extract(const MergeLevelDesc& d, hipStream_t st);
 

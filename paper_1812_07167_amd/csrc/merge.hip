@@ -18,6 +18,11 @@ __global__ void fill_zero_kernel(double* p, long n) {
   if (e < n) p[e] = 0.0;
 }
 
+__global__ void fill_zero_int_kernel(int* p, long n) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = 0;
+}
+
 __global__ void fill_identity_kernel(double2* p, int n, long stride, int batch) {
   long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   long tot = (long)n * n * batch;
@@ -129,6 +134,12 @@ __global__ void down_scatter_kernel(MergeLevelDesc d, int nrhs, const double2* t
 void fill_zero(double* p, long n, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(fill_zero_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, p, n);
+  HPS_LAUNCH_CHECK();
+}
+
+void fill_zero_int(int* p, long n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_zero_int_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, p, n);
   HPS_LAUNCH_CHECK();
 }
 

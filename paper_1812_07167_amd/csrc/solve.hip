@@ -1,76 +1,135 @@
 // Solve-stage operator application (Algorithm 2): out = alpha * A X + addend for a
 // batch of stored operators A (M x K, complex) and a block of nrhs right-hand sides.
 //
-// This is HBM-bound: every operator entry is read once per call and used for all
-// nrhs columns.  One workgroup covers a tile of rows of one batch entry; the X block
-// (K x NR) is staged through LDS in chunks and read by broadcast, each thread keeps NR
-// complex accumulators for its row.  Operators with few rows and a long K (the top
-// merges) are split along K across workgroups; the partial sums are reduced in a
-// fixed order by a second kernel, so results do not depend on scheduling.
+// This is HBM-bound: every operator entry is read once per call and used for all (up to
+// 16) right-hand sides of a pass.  The product runs on the FP64 matrix cores: a wave
+// owns TW tiles of 16 rows, the 16 right-hand sides are the 16 columns of the MFMA's B
+// operand, and a complex product is four real v_mfma_f64_16x16x4f64.  The right-hand
+// side block is staged through LDS in chunks of KC rows (each lane reads one complex
+// value per 4-deep k step, so there are no broadcast reads); operator entries go from
+// global memory straight into the A operand registers.  For short operators the waves
+// of a workgroup split K and add their partial tiles through LDS in a fixed order.
+// Operators with few rows and a long K (the top merges) are also split along K across
+// workgroups; those partial sums are reduced in a fixed order by a second kernel, so
+// results never depend on scheduling.
+//
+// MFMA f64 16x16x4 lane layout: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// accumulator element v of lane l is D[l/16 + 4 v][l%16].
 #include "kernels.hpp"
 
 namespace hps {
 namespace {
 
-constexpr int KC = 64;  // K chunk staged in LDS
+constexpr int KC = 64;   // K chunk staged in LDS
+constexpr int NRB = 16;  // right-hand sides per pass (the MFMA's N)
 
-template <int NR, int BT>
-__global__ __launch_bounds__(BT) void skinny_kernel(SkinnyDesc d, int r0, int nr, int kper,
-                                                    double2* partial) {
-  __shared__ double2 Xs[KC][NR];
+template <int TW, int WK>
+__global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int nr, int kper,
+                                                     double2* partial) {
+  constexpr int WR = 4 / WK;              // row groups of waves
+  constexpr int ROWS = 16 * TW * WR;      // rows per workgroup
+  __shared__ double2 Xs[KC][NRB];
+  __shared__ d4v red[WK > 1 ? (WK - 1) * WR * TW * 2 * 64 : 1];
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave % WR, kw = wave / WR;
+  const int li = lane & 15, lk = lane >> 4;
   const long b = blockIdx.y;
   const int ks = blockIdx.z;
-  const int i = blockIdx.x * BT + tid;
   const int kbeg = ks * kper, kend = min(d.K, kbeg + kper);
+  const int row0 = blockIdx.x * ROWS + wr * 16 * TW;
   const double2* A = reinterpret_cast<const double2*>(d.A) + b * d.sA;
   const double2* X = reinterpret_cast<const double2*>(d.X) + (d.xoff ? d.xoff[b] : b * d.sX);
-  double2 acc[NR];
+
+  // rows this lane loads (clamped into the operator; rows past M are never written)
+  long arow[TW];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r] = cmk(0, 0);
+  for (int t = 0; t < TW; ++t) arow[t] = min(row0 + 16 * t + li, d.M - 1);
+
+  d4v accR[TW], accI[TW];
+#pragma unroll
+  for (int t = 0; t < TW; ++t) {
+    accR[t] = d4v{0, 0, 0, 0};
+    accI[t] = d4v{0, 0, 0, 0};
+  }
   for (int k0 = kbeg; k0 < kend; k0 += KC) {
     const int kc = min(KC, kend - k0);
     __syncthreads();
-    for (int e = tid; e < KC * NR; e += BT) {
+    for (int e = tid; e < KC * NRB; e += 256) {
       const int k = e % KC, r = e / KC;
       Xs[k][r] = (k < kc && r < nr) ? X[(k0 + k) + d.ldx * (long)(r0 + r)] : cmk(0, 0);
     }
     __syncthreads();
-    if (i < d.M) {
-      const double2* Ai = A + i + d.lda * (long)k0;
-      for (int k = 0; k < kc; ++k) {
-        const double2 a = Ai[d.lda * (long)k];
+    const int nsteps = (kc + 3) >> 2;
+#pragma unroll 4
+    for (int s = kw; s < nsteps; s += WK) {
+      const int kl = 4 * s + lk;
+      // k past the chunk meets a zero right-hand side; clamp its address into A
+      const long kg = min(k0 + kl, d.K - 1);
+      const double2 bx = Xs[kl][li];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) acc[r] = cfma(a, Xs[k][r], acc[r]);
+      for (int t = 0; t < TW; ++t) {
+        const double2 a = A[arow[t] + d.lda * kg];
+        accR[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, bx.x, accR[t], 0, 0, 0);
+        accR[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, bx.y, accR[t], 0, 0, 0);
+        accI[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, bx.y, accI[t], 0, 0, 0);
+        accI[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, bx.x, accI[t], 0, 0, 0);
       }
     }
   }
-  if (i >= d.M) return;
-  if (partial) {
-    // [ks][b][r][i]
-    double2* P = partial + (((long)ks * d.batch + b) * NR) * d.M;
+  if (WK > 1) {
+    // waves kw > 0 hand their tiles to the kw = 0 wave of their row group
+    if (kw > 0) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r)
-      if (r < nr) P[(long)r * d.M + i] = acc[r];
+      for (int t = 0; t < TW; ++t) {
+        const int base = (((kw - 1) * WR + wr) * TW + t) * 2;
+        red[(base + 0) * 64 + lane] = accR[t];
+        red[(base + 1) * 64 + lane] = accI[t];
+      }
+    }
+    __syncthreads();
+    if (kw > 0) return;
+    for (int q = 1; q < WK; ++q)
+#pragma unroll
+      for (int t = 0; t < TW; ++t) {
+        const int base = (((q - 1) * WR + wr) * TW + t) * 2;
+        accR[t] += red[(base + 0) * 64 + lane];
+        accI[t] += red[(base + 1) * 64 + lane];
+      }
+  }
+  const int rhs = li;
+  if (rhs >= nr) return;
+  if (partial) {
+    // [ks][b][rhs][i]
+    double2* P = partial + (((long)ks * d.batch + b) * NRB + rhs) * d.M;
+#pragma unroll
+    for (int t = 0; t < TW; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = row0 + 16 * t + lk + 4 * v;
+        if (i < d.M) P[i] = cmk(accR[t][v], accI[t][v]);
+      }
     return;
   }
   double2* C = reinterpret_cast<double2*>(d.C) + (d.coff ? d.coff[b] : b * d.sC);
-  const long ci = d.crow ? d.crow[i] : i;
   const double2* C0 = d.C0 ? reinterpret_cast<const double2*>(d.C0) +
                                  (d.c0off ? d.c0off[b] : b * d.s0)
                            : nullptr;
 #pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    if (r >= nr) break;
-    double2 v = cscale(acc[r], d.alpha);
-    double2* p = C + ci + d.ldc * (long)(r0 + r);
-    if (C0) v = cadd(v, C0[i + d.ld0 * (long)(r0 + r)]);
-    else if (d.accumulate) v = cadd(v, *p);
-    *p = v;
-  }
+  for (int t = 0; t < TW; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = row0 + 16 * t + lk + 4 * v;
+      if (i >= d.M) continue;
+      const long ci = d.crow ? d.crow[i] : i;
+      double2 val = cmk(d.alpha * accR[t][v], d.alpha * accI[t][v]);
+      double2* p = C + ci + d.ldc * (long)(r0 + rhs);
+      if (C0) val = cadd(val, C0[i + d.ld0 * (long)(r0 + rhs)]);
+      else if (d.accumulate) val = cadd(val, *p);
+      *p = val;
+    }
 }
 
-template <int NR>
 __global__ void skinny_reduce_kernel(SkinnyDesc d, int r0, int nr, int nsplit,
                                      const double2* partial) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -81,7 +140,7 @@ __global__ void skinny_reduce_kernel(SkinnyDesc d, int r0, int nr, int nsplit,
   const long b = e / ((long)d.M * nr);
   double2 acc = cmk(0, 0);
   for (int s = 0; s < nsplit; ++s)
-    acc = cadd(acc, partial[(((long)s * d.batch + b) * NR + r) * d.M + i]);
+    acc = cadd(acc, partial[(((long)s * d.batch + b) * NRB + r) * d.M + i]);
   double2* C = reinterpret_cast<double2*>(d.C) + (d.coff ? d.coff[b] : b * d.sC);
   const long ci = d.crow ? d.crow[i] : i;
   double2 v = cscale(acc, d.alpha);
@@ -95,16 +154,23 @@ __global__ void skinny_reduce_kernel(SkinnyDesc d, int r0, int nr, int nsplit,
   *p = v;
 }
 
-int block_threads(int M) { return M <= 64 ? 64 : (M <= 128 ? 128 : 256); }
+// rows covered by one workgroup for an operator of M rows
+int block_rows(int M) {
+  if (M <= 16) return 16;
+  if (M <= 32) return 32;
+  if (M <= 64) return 64;
+  if (M <= 128) return 128;
+  return 256;
+}
 
-// K is split across workgroups when the row tiles x batch cannot fill the device.
+// K is split across workgroups when the row blocks x batch cannot fill the device.
 // Returns the number of splits and the K range per split.
 int split_plan(const SkinnyDesc& d, int* kper_out) {
-  const int tiles = cdiv(d.M, block_threads(d.M));
+  const int tiles = cdiv(d.M, block_rows(d.M));
   int nsplit = 1;
   const long blocks = (long)tiles * d.batch;
-  if (blocks < 512 && d.K >= 2 * KC) {
-    nsplit = (int)std::min<long>((512 + blocks - 1) / blocks, (d.K + KC - 1) / KC);
+  if (blocks < 1024 && d.K >= 2 * KC) {
+    nsplit = (int)std::min<long>((1024 + blocks - 1) / blocks, (d.K + KC - 1) / KC);
     nsplit = std::max(1, std::min(nsplit, 64));
   }
   int kper = d.K;
@@ -117,33 +183,36 @@ int split_plan(const SkinnyDesc& d, int* kper_out) {
   return nsplit;
 }
 
-template <int NR, int BT>
+template <int TW, int WK>
 void run_chunk(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
-  const int tiles = cdiv(d.M, BT);
+  const int tiles = cdiv(d.M, 16 * TW * (4 / WK));
   int kper = 0;
   const int nsplit = split_plan(d, &kper);
   if (nsplit == 1) {
-    hipLaunchKernelGGL((skinny_kernel<NR, BT>), dim3(tiles, d.batch, 1), dim3(BT), 0, st, d, r0,
+    hipLaunchKernelGGL((skinny_kernel<TW, WK>), dim3(tiles, d.batch, 1), dim3(256), 0, st, d, r0,
                        nr, d.K, (double2*)nullptr);
     HPS_LAUNCH_CHECK();
     return;
   }
   if (!d.work) throw Error(1, "zgemm_skinny: split-K needs a workspace");
   double2* part = static_cast<double2*>(d.work);
-  hipLaunchKernelGGL((skinny_kernel<NR, BT>), dim3(tiles, d.batch, nsplit), dim3(BT), 0, st, d,
+  hipLaunchKernelGGL((skinny_kernel<TW, WK>), dim3(tiles, d.batch, nsplit), dim3(256), 0, st, d,
                      r0, nr, kper, part);
   HPS_LAUNCH_CHECK();
   long tot = (long)d.batch * d.M * nr;
-  hipLaunchKernelGGL(skinny_reduce_kernel<NR>, dim3(cdiv(tot, 256)), dim3(256), 0, st, d, r0, nr,
+  hipLaunchKernelGGL(skinny_reduce_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, st, d, r0, nr,
                      nsplit, (const double2*)part);
   HPS_LAUNCH_CHECK();
 }
 
-template <int NR>
-void run_nr(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
-  if (d.M <= 64) run_chunk<NR, 64>(d, r0, nr, st);
-  else if (d.M <= 128) run_chunk<NR, 128>(d, r0, nr, st);
-  else run_chunk<NR, 256>(d, r0, nr, st);
+void run_pass(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
+  switch (block_rows(d.M)) {
+    case 16: run_chunk<1, 4>(d, r0, nr, st); break;
+    case 32: run_chunk<1, 2>(d, r0, nr, st); break;
+    case 64: run_chunk<1, 1>(d, r0, nr, st); break;
+    case 128: run_chunk<2, 1>(d, r0, nr, st); break;
+    default: run_chunk<4, 1>(d, r0, nr, st); break;
+  }
 }
 
 }  // namespace
@@ -153,21 +222,14 @@ size_t skinny_work_bytes(const SkinnyDesc& d) {
   int kper = 0;
   const int nsplit = split_plan(d, &kper);
   if (nsplit == 1) return 0;
-  return (size_t)nsplit * d.batch * 16 * d.M * sizeof(double2);
+  return (size_t)nsplit * d.batch * NRB * d.M * sizeof(double2);
 }
 
 void zgemm_skinny(const SkinnyDesc& d, hipStream_t st) {
   if (d.M <= 0 || d.batch <= 0 || d.nrhs <= 0) return;
   if (d.batch > 65535) throw Error(1, "zgemm_skinny: batch exceeds grid limit");
   if (d.K <= 0) throw Error(1, "zgemm_skinny: K must be positive");
-  for (int r0 = 0; r0 < d.nrhs; r0 += 16) {
-    const int nr = std::min(16, d.nrhs - r0);
-    if (nr <= 1) run_nr<1>(d, r0, nr, st);
-    else if (nr <= 2) run_nr<2>(d, r0, nr, st);
-    else if (nr <= 4) run_nr<4>(d, r0, nr, st);
-    else if (nr <= 8) run_nr<8>(d, r0, nr, st);
-    else run_nr<16>(d, r0, nr, st);
-  }
+  for (int r0 = 0; r0 < d.nrhs; r0 += NRB) run_pass(d, r0, std::min(NRB, d.nrhs - r0), st);
 }
 
 }  // namespace hps

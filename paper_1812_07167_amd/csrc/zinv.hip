@@ -7,17 +7,17 @@
 // inv(A)[k][r_j] = M[r_k][j], which the final write-out applies.
 //
 // * n <= SMALL_MAX: one workgroup per matrix, matrix resident in LDS.
-// * larger n: blocked right-looking form.  For each block K of 16 columns a panel
-//   kernel (one workgroup per matrix, panel rows spread over its waves, each row's
-//   16 panel entries in registers) runs the 16 elimination steps on the panel and emits the block
-//   transformation Q; an extract kernel gathers the pivot rows X = M[P_K, :] (zero on
-//   K) and clears them; a batched MFMA GEMM then applies M += Q X to every column.
+// * larger n: blocked right-looking form.  For each block K of PNB columns a panel
+//   kernel (one workgroup per matrix, panel rows spread over its waves, each row's PNB
+//   panel entries in registers) runs the PNB elimination steps on the panel and emits
+//   the block transformation Q; an update kernel then forms
+//   M = (pivot rows of K cleared) + Q M[P_K, :] on every column outside K.
 #include "kernels.hpp"
 
 namespace hps {
 namespace {
 
-constexpr int SMALL_MAX = 96;
+constexpr int SMALL_MAX = 96;  // at most 128 (two rows per lane in the small kernel)
 constexpr int PNB = 8;   // panel width of the blocked path
 
 // ------------------------------------------------------------------ small (LDS)
@@ -32,6 +32,7 @@ __global__ __launch_bounds__(256) void zinv_small_kernel(int n, const double* Ai
   __shared__ int s_r;
   __shared__ int s_bad;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
   const long b = blockIdx.x;
   const double2* A = reinterpret_cast<const double2*>(Ain) + b * sA;
   for (int e = tid; e < n * n; e += 256) {
@@ -59,11 +60,15 @@ __global__ __launch_bounds__(256) void zinv_small_kernel(int n, const double* Ai
     if (s_bad) break;
     const int r = s_r;
     const double2 ip = crcp(M[r + n * k]);
-    for (int e = tid; e < n * n; e += 256) {
-      int i = e % n, c = e / n;
-      if (i != r && c != k) {
-        double2 f = cmul(M[i + n * k], ip);
-        M[e] = csub(M[e], cmul(f, M[r + n * c]));
+    // rows lane, lane + 64 of column group wave, wave + 4, ...  (no index division)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int i = lane + 64 * q;
+      if (i >= n || i == r) continue;
+      const double2 f = cmul(M[i + n * k], ip);
+      for (int c = wv; c < n; c += 4) {
+        if (c == k) continue;
+        M[i + n * c] = csub(M[i + n * c], cmul(f, M[r + n * c]));
       }
     }
     __syncthreads();
@@ -93,26 +98,37 @@ __global__ __launch_bounds__(256) void zinv_small_kernel(int n, const double* Ai
 }
 
 // ------------------------------------------------------------------ blocked
-// Panel of the blocked path: the n x 16 panel (columns k0..k0+15) of one matrix, rows
-// distributed over the (at most 8) waves of the workgroup (row i: wave i / (64 RPL), slot
-// (i / 64) % RPL, lane i % 64), all 16 panel columns of a row in the owning lane's
-// registers.  Per elimination step: every wave offers its best unused row of the pivot
-// column (DPP reduction), the winner is found from the per-wave candidates in LDS, the
-// owner publishes the pivot row (16 entries), and every lane updates its own rows:
+// The blocked path keeps two copies of every matrix and alternates between them: block
+// K reads the current copy and writes the next one (the panel kernel writes the block
+// transformation Q into the next copy's panel columns, the update kernel every other
+// column).  The update can then read the pivot rows of the current copy directly, with
+// no gather pass and no race between workgroups.
+//
+// Panel kernel: the n x PNB panel (columns k0..k0+PNB-1) of one matrix, rows
+// distributed over the (at most 8) waves of the workgroup (row i: wave i / (64 RPL),
+// slot (i / 64) % RPL, lane i % 64), all PNB panel columns of a row in the owning lane's
+// registers.  For elimination step s every wave publishes its best unused row of column
+// s (DPP reduction): key, row index and the row's PNB values, in an LDS slot; after one
+// barrier every lane picks the winner among the slots and reads the pivot row from it.
+// Each lane then updates its own rows,
 //     M[i][c] -= f_i M[r][c],  f_i = M[i][k]/p  (f_r = 1 - 1/p, so the pivot row
-//     becomes M[r][c]/p),   and column k becomes -f_i (1/p on the pivot row).
-// Two barriers per step; nothing but the pivot row goes through LDS.
+//     becomes M[r][c]/p),   and column k becomes -f_i (1/p on the pivot row),
+// updating column s+1 first so that the next step's pivot search overlaps the update of
+// the remaining columns (the candidate row's values are published once final).  The slots alternate between two buffers, so one
+// barrier per step suffices: a wave can only overwrite a buffer after every wave has
+// passed the following step's barrier.
 template <int RPL>
-__global__ __launch_bounds__(512) void zinv_panel_kernel(int n, double* Mg, int k0,
-                                                         double* Qbuf, int* piv, int* used,
-                                                         int* info) {
-  __shared__ unsigned s_key[8];
-  __shared__ int s_row[8];
-  __shared__ double2 prow[PNB];
+__global__ __launch_bounds__(512) void zinv_panel_kernel(int n, const double* Mcur,
+                                                         double* Mnext, int k0, int* piv,
+                                                         int* used, int* info) {
+  __shared__ unsigned s_key[2][8];
+  __shared__ int s_row[2][8];
+  __shared__ double2 s_val[2][8][PNB];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   const long b = blockIdx.x;
-  double2* M = reinterpret_cast<double2*>(Mg) + b * (long)n * n;
+  if (info[b]) return;
+  const double2* M = reinterpret_cast<const double2*>(Mcur) + b * (long)n * n;
   int* pv = piv + b * (long)n;
   int* us = used + b * (long)n;
   const int nk = (n - k0) < PNB ? (n - k0) : PNB;
@@ -127,119 +143,162 @@ __global__ __launch_bounds__(512) void zinv_panel_kernel(int n, double* Mg, int 
     for (int c = 0; c < PNB; ++c)
       v[q][c] = (ok && c < nk) ? M[i + (long)n * (k0 + c)] : cmk(0, 0);
   }
+  // this wave's candidate for column s: key and row into slot buffer sb (the row's
+  // values follow with publish_row once they are final)
+  int psrc = 0, pbrow = 0;
+  auto publish_key = [&](int s, int sb) {
+    double best = -1.0;
+    int brow = 0;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const double val = ((umask >> q) & 1u) ? -1.0 : cabs1(v[q][s]);
+      if (val > best) { best = val; brow = (w * RPL + q) * 64 + lane; }
+    }
+    const unsigned key = best > 0.0 ? max(__float_as_uint((float)best), 1u) : 0u;
+    const unsigned wkey = wave_max_u32(key);
+    psrc = __builtin_ctzll(__ballot(key == wkey));
+    pbrow = brow;
+    if (lane == psrc) {
+      s_key[sb][w] = wkey;
+      s_row[sb][w] = brow;
+    }
+  };
+  auto publish_row = [&](int sb) {
+    if (lane == psrc) {
+      // select the slot by its row index (a compare the compiler cannot turn into a
+      // dynamically indexed register array)
+#pragma unroll
+      for (int q = 0; q < RPL; ++q)
+        if ((w * RPL + q) * 64 + lane == pbrow)
+#pragma unroll
+          for (int c = 0; c < PNB; ++c) s_val[sb][w][c] = v[q][c];
+    }
+  };
+  publish_key(0, 0);
+  publish_row(0);
   int bad = 0;
 #pragma unroll
   for (int s = 0; s < PNB; ++s) {
     if (s >= nk || bad) continue;  // uniform over the workgroup; keeps the loop unrolled
     const int k = k0 + s;
-    // candidate of this wave
-    double best = -1.0;
-    int bi = 0;
-#pragma unroll
-    for (int q = 0; q < RPL; ++q) {
-      const double val = ((umask >> q) & 1u) ? -1.0 : cabs1(v[q][s]);
-      if (val > best) { best = val; bi = (w * RPL + q) * 64 + lane; }
-    }
-    {
-      const unsigned key = best > 0.0 ? max(__float_as_uint((float)best), 1u) : 0u;
-      const unsigned wkey = wave_max_u32(key);
-      const unsigned long long hit = __ballot(key == wkey);
-      const int src = __builtin_ctzll(hit);
-      const int wrow = __builtin_amdgcn_readlane(bi, src);
-      if (lane == 0) { s_key[w] = wkey; s_row[w] = wrow; }
-    }
+    const int sb = s & 1;
     __syncthreads();
-    // winner over the waves
-    int r;
-    {
-      const unsigned key = lane < nw ? s_key[lane] : 0u;
-      const int row = lane < nw ? s_row[lane] : 0;
-      const unsigned gkey = wave_max_u32(key);
-      if (gkey == 0u) {
-        r = -1;
-      } else {
-        const unsigned long long hit = __ballot(key == gkey);
-        r = __builtin_amdgcn_readlane(row, __builtin_ctzll(hit));
-      }
-    }
-    if (r < 0) {
+    // winner over the waves (ties to the lowest wave): lane x reads wave x's key
+    const unsigned kx = lane < nw ? s_key[sb][lane] : 0u;
+    const unsigned gkey = wave_max_u32(kx);
+    const int ww = __builtin_ctzll(__ballot(kx == gkey));
+    if (gkey == 0u) {
       bad = k + 1;
       continue;
     }
-    // the owner publishes the pivot row
-    const int rw = r / (64 * RPL), rq = (r / 64) % RPL, rl = r & 63;
-    if (w == rw && lane == rl) {
-#pragma unroll
-      for (int q = 0; q < RPL; ++q)
-        if (q == rq)
-#pragma unroll
-          for (int c = 0; c < PNB; ++c) prow[c] = v[q][c];
-    }
-    __syncthreads();
-    const double2 ip = crcp(prow[s]);
+    const int r = s_row[sb][ww];
+    const double2 ip = crcp_fast(s_val[sb][ww][s]);
+    double2 f[RPL], f0[RPL];
+    bool isr[RPL];
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       const int i = (w * RPL + q) * 64 + lane;
-      const bool isr = (i == r);
-      const double2 f0 = cmul(v[q][s], ip);
-      const double2 f = isr ? cmk(1.0 - ip.x, -ip.y) : f0;
-#pragma unroll
-      for (int c = 0; c < PNB; ++c) {
-        if (c == s) continue;
-        const double2 pc = prow[c];  // LDS broadcast read
-        v[q][c].x = fma(-f.x, pc.x, fma(f.y, pc.y, v[q][c].x));
-        v[q][c].y = fma(-f.x, pc.y, fma(-f.y, pc.x, v[q][c].y));
-        // bound the scheduler's look-ahead: hoisting every pivot-row read of the
-        // unrolled steps would need more registers than a 16-wave workgroup has
-        if ((c & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-      }
-      v[q][s] = isr ? ip : cmk(-f0.x, -f0.y);
-      if (isr) umask |= 1u << q;
+      isr[q] = (i == r);
+      f0[q] = cmul(v[q][s], ip);
+      f[q] = isr[q] ? cmk(1.0 - ip.x, -ip.y) : f0[q];
+      if (isr[q]) umask |= 1u << q;
     }
+    auto upd = [&](int c) {
+      const double2 pc = s_val[sb][ww][c];  // LDS broadcast read
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        v[q][c].x = fma(-f[q].x, pc.x, fma(f[q].y, pc.y, v[q][c].x));
+        v[q][c].y = fma(-f[q].x, pc.y, fma(-f[q].y, pc.x, v[q][c].y));
+      }
+    };
+    if (s + 1 < nk) {
+      upd(s + 1);
+      publish_key(s + 1, sb ^ 1);
+    }
+#pragma unroll
+    for (int c = 0; c < PNB; ++c) {
+      if (c == s || c == s + 1) continue;
+      upd(c);
+      // bound the scheduler's look-ahead: hoisting every pivot-row read of the
+      // unrolled steps would need more registers than the workgroup has
+      if ((c & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) v[q][s] = isr[q] ? ip : cmk(-f0[q].x, -f0[q].y);
+    if (s + 1 < nk) publish_row(sb ^ 1);
     if (threadIdx.x == 0) pv[k] = r;
   }
   if (bad) {
     if (threadIdx.x == 0) info[b] = bad;
     return;
   }
-  // write the panel back (it now holds Q) and keep a copy for the update GEMM.  The
-  // column stride is re-read through an empty asm so that these addresses are formed
-  // here instead of being kept live from the loads at the top (which costs registers).
+  // the panel (now Q) goes into the next copy.  The column stride is re-read through an
+  // empty asm so that these addresses are formed here instead of being kept live from
+  // the loads at the top (which costs registers).
   long ld = n;
   asm volatile("" : "+s"(ld));
-  double2* Mw = reinterpret_cast<double2*>(Mg) + b * ld * ld;
-  double2* Qb = reinterpret_cast<double2*>(Qbuf) + b * ld * PNB;
+  double2* Mw = reinterpret_cast<double2*>(Mnext) + b * ld * ld;
 #pragma unroll
   for (int q = 0; q < RPL; ++q) {
     const int i = (w * RPL + q) * 64 + lane;
     if (i < n) {
 #pragma unroll
-      for (int c = 0; c < PNB; ++c) {
+      for (int c = 0; c < PNB; ++c)
         if (c < nk) Mw[i + ld * (k0 + c)] = v[q][c];
-        Qb[i + ld * c] = c < nk ? v[q][c] : cmk(0, 0);
-      }
       if ((umask & 1u << q) && !us[i]) us[i] = 1;
     }
   }
 }
 
-// X = M[P_K, :] (zero on the panel columns), and those rows cleared outside the panel.
-__global__ void zinv_extract_kernel(int n, double* Mg, int k0, double* Xg, const int* piv,
-                                    const int* info) {
-  const long b = blockIdx.y;
+// Block update, for every column j outside the panel K:
+//     next[i][j] = (i a pivot row of K ? 0 : cur[i][j]) + sum_s Q[i][s] cur[r_s][j],
+// with Q = next[:, K] (written by the panel kernel) and r_s the pivot rows of K.
+// Memory-bound (PNB complex multiply-adds per element read and written).  A workgroup
+// covers 64 rows (one per lane) and UJ consecutive columns (UJ / 4 per wave) of one
+// matrix; a wave's column loads are issued together.
+constexpr int UJ = 16;
+__global__ __launch_bounds__(256) void zinv_update_kernel(int n, const double* Mcur,
+                                                          double* Mnext, int k0, const int* piv,
+                                                          const int* info) {
+  constexpr int CW = UJ / 4;  // columns per wave
+  const long b = blockIdx.z;
   if (info[b]) return;
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long)PNB * n) return;
-  const int k = e % PNB, j = e / PNB;
-  double2* M = reinterpret_cast<double2*>(Mg) + b * (long)n * n;
-  double2* X = reinterpret_cast<double2*>(Xg) + b * (long)PNB * n;
-  double2 val = cmk(0, 0);
-  if (k0 + k < n && (j < k0 || j >= k0 + PNB)) {
-    const int r = piv[b * (long)n + k0 + k];
-    val = M[r + (long)n * j];
-    M[r + (long)n * j] = cmk(0, 0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const int nk = (n - k0) < PNB ? (n - k0) : PNB;
+  // columns outside the panel, compacted: column index jj skips [k0, k0 + nk)
+  const int ncol = n - nk;
+  const int jj0 = blockIdx.y * UJ + w * CW;
+  if (i >= n || jj0 >= ncol) return;
+  const double2* Mc = reinterpret_cast<const double2*>(Mcur) + b * (long)n * n;
+  double2* Mn = reinterpret_cast<double2*>(Mnext) + b * (long)n * n;
+  const int* pv = piv + b * (long)n + k0;
+  int pr[PNB];
+  bool isp = false;
+  double2 q[PNB];
+#pragma unroll
+  for (int s = 0; s < PNB; ++s) {
+    pr[s] = s < nk ? pv[s] : 0;
+    isp |= (s < nk && pr[s] == i);
+    q[s] = s < nk ? Mn[i + (long)n * (k0 + s)] : cmk(0, 0);
   }
-  X[k + (long)PNB * j] = val;
+  double2 m[CW];
+  int col[CW];
+#pragma unroll
+  for (int c = 0; c < CW; ++c) {
+    const int jj = min(jj0 + c, ncol - 1);
+    col[c] = jj < k0 ? jj : jj + nk;
+    m[c] = isp ? cmk(0, 0) : Mc[i + (long)n * col[c]];
+  }
+#pragma unroll
+  for (int c = 0; c < CW; ++c) {
+    if (jj0 + c >= ncol) continue;
+    const double2* cj = Mc + (long)n * col[c];
+    double2 acc = m[c];
+#pragma unroll
+    for (int s = 0; s < PNB; ++s) acc = cfma(q[s], s < nk ? cj[pr[s]] : cmk(0, 0), acc);
+    Mn[i + (long)n * col[c]] = acc;
+  }
 }
 
 __global__ void zinv_permute_kernel(int n, const double* Mg, const int* piv, double* Out,
@@ -277,10 +336,10 @@ __global__ void zero_int_kernel(int* p, long cnt) {
 }
 
 template <int RPL>
-void launch_panel(int n, int batch, double* M, int k0, double* Qb, int* piv, int* used,
+void launch_panel(int n, int batch, const double* Mc, double* Mn, int k0, int* piv, int* used,
                   int* info, hipStream_t st) {
   const int waves = std::max(1, std::min(8, (n + 64 * RPL - 1) / (64 * RPL)));
-  hipLaunchKernelGGL(zinv_panel_kernel<RPL>, dim3(batch), dim3(64 * waves), 0, st, n, M, k0, Qb,
+  hipLaunchKernelGGL(zinv_panel_kernel<RPL>, dim3(batch), dim3(64 * waves), 0, st, n, Mc, Mn, k0,
                      piv, used, info);
 }
 
@@ -289,10 +348,8 @@ void launch_panel(int n, int batch, double* M, int k0, double* Qb, int* piv, int
 size_t zinv_workspace_bytes(int n, int batch) {
   if (n <= SMALL_MAX) return 0;
   size_t nn = (size_t)n * n * 16;
-  size_t q = (size_t)n * PNB * 16;
-  size_t x = (size_t)n * PNB * 16;
   size_t ints = (size_t)n * 4 * 2;
-  return (size_t)batch * (nn + q + x + ints) + 256;
+  return (size_t)batch * (2 * nn + ints) + 256;
 }
 
 void zinv(int n, int batch, const double* A, long lda, long sA, double* Out, long ldo,
@@ -308,44 +365,36 @@ void zinv(int n, int batch, const double* A, long lda, long sA, double* Out, lon
   }
   if (n > 64 * 32) throw Error(1, "zinv: n too large (max 2048)");
   char* w = static_cast<char*>(work);
-  double* M = reinterpret_cast<double*>(w);
+  double* Mcur = reinterpret_cast<double*>(w);
   w += (size_t)batch * n * n * 16;
-  double* Qb = reinterpret_cast<double*>(w);
-  w += (size_t)batch * n * PNB * 16;
-  double* Xb = reinterpret_cast<double*>(w);
-  w += (size_t)batch * n * PNB * 16;
+  double* Mnext = reinterpret_cast<double*>(w);
+  w += (size_t)batch * n * n * 16;
   int* piv = reinterpret_cast<int*>(w);
   int* used = piv + (size_t)batch * n;
   {
     long tot = (long)n * n;
     hipLaunchKernelGGL(copy_in_kernel, dim3(cdiv(tot, 256), batch), dim3(256), 0, st, n, A, lda,
-                       sA, M);
+                       sA, Mcur);
     long ni = 2L * batch * n;
     hipLaunchKernelGGL(zero_int_kernel, dim3(cdiv(ni, 256)), dim3(256), 0, st, piv, ni);
     HPS_LAUNCH_CHECK();
   }
   for (int k0 = 0; k0 < n; k0 += PNB) {
-    if (n <= 512) launch_panel<1>(n, batch, M, k0, Qb, piv, used, info, st);
-    else if (n <= 1024) launch_panel<2>(n, batch, M, k0, Qb, piv, used, info, st);
-    else launch_panel<4>(n, batch, M, k0, Qb, piv, used, info, st);
+    if (n <= 512) launch_panel<1>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
+    else if (n <= 1024) launch_panel<2>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
+    else launch_panel<4>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
     HPS_LAUNCH_CHECK();
-    {
-      const long tot = (long)PNB * n;
-      hipLaunchKernelGGL(zinv_extract_kernel, dim3(cdiv(tot, 256), batch), dim3(256), 0, st, n,
-                         M, k0, Xb, piv, info);
+    const int ncol = n - std::min(PNB, n - k0);
+    if (ncol > 0) {
+      hipLaunchKernelGGL(zinv_update_kernel, dim3(cdiv(n, 64), cdiv(ncol, UJ), batch), dim3(256),
+                         0, st, n, Mcur, Mnext, k0, piv, info);
       HPS_LAUNCH_CHECK();
     }
-    GemmDesc g;
-    g.M = n; g.N = n; g.K = PNB; g.batch = batch;
-    g.A = Qb; g.lda = n; g.sA = (long)n * PNB;
-    g.B = Xb; g.ldb = PNB; g.sB = (long)n * PNB;
-    g.C = M; g.ldc = n; g.sC = (long)n * n;
-    g.alpha = 1.0; g.beta = 1.0;
-    zgemm(g, st);
+    std::swap(Mcur, Mnext);
   }
   int blocks_x = std::min(n, 64);
   hipLaunchKernelGGL(zinv_permute_kernel, dim3(blocks_x, batch), dim3(256), n * sizeof(int), st,
-                     n, M, piv, Out, ldo, sO, info);
+                     n, Mcur, piv, Out, ldo, sO, info);
   HPS_LAUNCH_CHECK();
 }
 
