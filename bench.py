@@ -34,6 +34,25 @@ GEMM_TILES = {"16x64": (16, 64, 1, 4), "64x16": (64, 16, 4, 1), "32x32": (32, 32
               "32x64": (32, 64, 2, 2), "64x32": (64, 32, 2, 2), "64x64": (64, 64, 2, 2)}
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from a committed profiler summary under profiles/
+    (two counter passes scaled by a plain copy), or None when there is none or the
+    kernel's source has changed since it was measured."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_1812_07167_amd", "csrc", "gemm.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest() if os.path.exists(src) else ""
+    for fn in glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md")):
+        kv = {}
+        for line in open(fn):
+            if " = " in line:
+                k, v = line.strip().split(" = ", 1)
+                kv[k] = v
+        if kv.get("kernel") == kernel and kv.get("kernel_source_sha256") == sha:
+            return float(kv["traffic_bytes_per_launch"])
+    return None
+
+
 def kernel_of(stage, p):
     """The one kernel behind a timing record of the library, with its roofline bound,
     or None when the record covers several kernels."""
@@ -232,10 +251,12 @@ def main():
         achieved = fl / (ms * 1e-3) / 1e12
         per_launch = fl / launches
     roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": None, "kernel": kname,
-                "launches_per_step": launches, "avg_launch_ms": round(ms / launches, 5),
+                "frac": round(achieved / peak, 4), "traffic": measured_traffic(kname),
+                "kernel": kname, "launches_per_step": launches,
+                "avg_launch_ms": round(ms / launches, 5),
                 "algorithmic_per_launch": per_launch,
-                "algorithmic_unit": "bytes" if bound == "hbm" else "flops"}
+                "algorithmic_unit": "bytes" if bound == "hbm" else "flops",
+                "algorithmic_bytes_per_launch": by / launches}
 
     out = {
         "metric": METRIC,
