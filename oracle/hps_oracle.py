@@ -367,19 +367,42 @@ def build(prob: Problem, c_interior: np.ndarray, tie: str = "x"):
     return boxes
 
 
-def solve(prob: Problem, boxes, s, t, upward=True):
+def shared_rows(prob: Problem):
+    """Owners of every boundary node key: key -> [(leaf, position in I_b), ...] (two
+    owners for a node on an edge shared by two leaves, one on the outer boundary)."""
+    owner = {}
+    for iy in range(prob.ny):
+        for ix in range(prob.nx):
+            l = iy * prob.nx + ix
+            for r, k in enumerate(leaf_boundary_keys(ix, iy, prob.m)):
+                owner.setdefault(k, []).append((l, r))
+    return owner
+
+
+def solve(prob: Problem, boxes, s, t, upward=True, jumps=None):
     """Algorithm 2 (solve stage) for one or several right-hand sides.
 
     s: [nrhs, nleaf*n_i] body load at interior nodes (or None for s = 0, which skips
        the upward pass as Sec. 2 allows), t: [nrhs, nt] impedance data on the root
        boundary in the external order.  Returns u: [nrhs, nleaf*n] at all leaf nodes.
+
+    jumps (not in the paper; used by residual correction): [nrhs, nleaf, nb] right-hand
+    sides of the shared-edge rows of the global system, i.e. on a node shared by leaves
+    l (position r) and l' the row F_l u_l + G_l' u_l' = jumps[:, l, r]; entries at outer
+    boundary positions are ignored.  At a merge the interface conditions then read
+    t3^a = -g3^b + j1 and t3^b = -g3^a + j2 (j1 from alpha's row, j2 from beta's), which is
+    the elimination of eqs. (talpha)/(tbeta) with h3^b replaced by h3^b - j1 and h3^a by
+    h3^a - j2 wherever the particular parts are formed.
     """
     t = np.atleast_2d(np.asarray(t, dtype=complex))
     nrhs = t.shape[0]
     if s is None:
-        upward = False
+        upward = jumps is not None
         s = np.zeros((nrhs, prob.nleaf * prob.ni), dtype=complex)
     s = np.atleast_2d(np.asarray(s, dtype=complex)).reshape(nrhs, prob.nleaf, prob.ni)
+    if jumps is not None:
+        jumps = np.asarray(jumps, dtype=complex).reshape(nrhs, prob.nleaf, prob.nb)
+        owner = shared_rows(prob)
     utilde, h, ttil_a, ttil_b = {}, {}, {}, {}
     # Upward pass, steps (1)-(9).
     for b in reversed(boxes):
@@ -396,6 +419,15 @@ def solve(prob: Problem, boxes, s, t, upward=True):
             a, c = b.children
             o = b.ops
             h3 = np.vstack([h[id(a)][o["i3a"]], h[id(c)][o["i3b"]]])
+            if jumps is not None:
+                n3 = len(o["i3a"])
+                for q, ka in enumerate(o["i3a"]):
+                    key = a.keys[ka]
+                    (l1, r1), (l2, r2) = owner[key]
+                    in_a = a.ix0 <= l1 % prob.nx < a.ix1 and a.iy0 <= l1 // prob.nx < a.iy1
+                    (la, ra), (lb, rb) = ((l1, r1), (l2, r2)) if in_a else ((l2, r2), (l1, r1))
+                    h3[q] -= jumps[:, lb, rb]                      # h3^a - j2
+                    h3[n3 + q] -= jumps[:, la, ra]                 # h3^b - j1
             ttil_a[id(b)] = o["Ups_a"] @ h3                        # step (6)
             ttil_b[id(b)] = o["Ups_b"] @ h3
             h12 = np.vstack([h[id(a)][o["i1"]], h[id(c)][o["i2"]]])
@@ -472,8 +504,9 @@ def global_system(prob: Problem, c_interior):
     return A
 
 
-def global_rhs(prob: Problem, s, t):
-    """Right-hand side of the global system for body load s and root data t."""
+def global_rhs(prob: Problem, s, t, jumps=None):
+    """Right-hand side of the global system for body load s, root data t and (optional)
+    right-hand sides of the shared-edge rows, jumps[:, l, r] as in solve()."""
     nl, n, nb, m = prob.nleaf, prob.n, prob.nb, prob.m
     t = np.atleast_2d(t)
     nrhs = t.shape[0]
@@ -483,20 +516,77 @@ def global_rhs(prob: Problem, s, t):
     rpos = {k: i for i, k in enumerate(rkeys)}
     b = np.zeros((nrhs, nl, n), dtype=complex)
     b[:, :, nb:] = s
+    if jumps is not None:
+        jumps = np.asarray(jumps, dtype=complex).reshape(nrhs, nl, nb)
     for iy in range(prob.ny):
         for ix in range(prob.nx):
             l = iy * prob.nx + ix
             for r, k in enumerate(leaf_boundary_keys(ix, iy, m)):
                 if k in rpos:
                     b[:, l, r] = t[:, rpos[k]]
+                elif jumps is not None:
+                    b[:, l, r] = jumps[:, l, r]
     return b.reshape(nrhs, -1)
 
 
-def global_solve(prob: Problem, c_interior, s, t):
+def global_solve(prob: Problem, c_interior, s, t, jumps=None):
     """Dense LU solve of the global system (tiny grids only)."""
     A = global_system(prob, c_interior)
-    rhs = global_rhs(prob, s, t)
+    rhs = global_rhs(prob, s, t, jumps)
     return np.linalg.solve(A, rhs.T).T
+
+
+def global_residual(prob: Problem, c_interior, s, t, u, jumps=None):
+    """Residual b - A u of the global system, row by row and leaf by leaf (no dense
+    assembly), in the layout of the global rows: [nrhs, nleaf, n] with positions
+    [I_b, I_i] of each leaf.
+
+    Interior rows: s - Ahat(I_i, I) u_l.  Outer boundary rows: t - F u_l.  Shared-edge
+    rows (node shared by leaves l, l'): jumps - (F_l u_l + G_l' u_l') (jumps = 0 if not
+    given).  Used for FP64 residual correction of a reduced-precision solve.
+    """
+    nl, n, nb, ni, m = prob.nleaf, prob.n, prob.nb, prob.ni, prob.m
+    u = np.atleast_2d(np.asarray(u, dtype=complex))
+    nrhs = u.shape[0]
+    u = u.reshape(nrhs, nl, n)
+    b = global_rhs(prob, s, t, jumps).reshape(nrhs, nl, n)
+    cI = np.asarray(c_interior).reshape(nl, ni)
+    ops = []
+    for iy in range(prob.ny):
+        for ix in range(prob.nx):
+            ops.append(leaf_operators(*prob.leaf_box(ix, iy), prob.p, prob.kappa, prob.eta,
+                                      cI[iy * prob.nx + ix]))
+    r = np.zeros((nrhs, nl, n), dtype=complex)
+    for l in range(nl):
+        r[:, l, nb:] = b[:, l, nb:] - (ops[l]["Ahat_iI"] @ u[:, l, :].T).T
+    for key, lst in shared_rows(prob).items():
+        if len(lst) == 1:
+            l, rr = lst[0]
+            r[:, l, rr] = b[:, l, rr] - u[:, l, :] @ ops[l]["F"][rr]
+        else:
+            (l1, r1), (l2, r2) = lst
+            r[:, l1, r1] = b[:, l1, r1] - (u[:, l1, :] @ ops[l1]["F"][r1] +
+                                           u[:, l2, :] @ ops[l2]["G"][r2])
+            r[:, l2, r2] = b[:, l2, r2] - (u[:, l2, :] @ ops[l2]["F"][r2] +
+                                           u[:, l1, :] @ ops[l1]["G"][r1])
+    return r
+
+
+def correction_rhs(prob: Problem, r):
+    """Split a global residual [nrhs, nleaf, n] into the (s, t, jumps) right-hand side of
+    the correction solve: interior rows -> s, outer boundary rows -> t (external order),
+    shared-edge rows -> jumps."""
+    nl, n, nb, m = prob.nleaf, prob.n, prob.nb, prob.m
+    r = np.asarray(r).reshape(-1, nl, n)
+    s = r[:, :, nb:].reshape(r.shape[0], -1)
+    rkeys = root_boundary_keys(prob.nx, prob.ny, m)
+    t = np.zeros((r.shape[0], len(rkeys)), dtype=complex)
+    owner = shared_rows(prob)
+    for q, k in enumerate(rkeys):
+        l, rr = owner[k][0]
+        t[:, q] = r[:, l, rr]
+    jumps = r[:, :, :nb].copy()
+    return s, t, jumps
 
 
 # --------------------------------------------------------------------------------

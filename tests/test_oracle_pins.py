@@ -434,3 +434,114 @@ def test_pins_catch_wrong_sign_in_W(monkeypatch):
     monkeypatch.setattr(O, "merge_operators", orig_merge)
     ug = O.global_solve(prob, c, None, t)
     assert O.rel_l2(u, ug) > 1e-3
+
+
+# ------------------------------------------------------------------ residual correction (jumps)
+# Not in the paper: a reduced-precision solve is corrected with the FP64 residual of the
+# global system, whose shared-edge rows then carry non-zero right-hand sides ("jumps").
+
+
+def _jump_case(nx=2, ny=2, p=6, kappa=11.0, eta=7.0 - 2.0j, seed=3, nrhs=2):
+    prob, xy, xyi, xyb, nrm, c = _setup(nx, ny, p, kappa, eta, G.FourierField.seeded(seed))
+    rng = np.random.default_rng(seed)
+    cn = lambda *sh: rng.standard_normal(sh) + 1j * rng.standard_normal(sh)
+    s = cn(nrhs, prob.nleaf * prob.ni)
+    t = cn(nrhs, len(xyb))
+    j = cn(nrhs, prob.nleaf, prob.nb)
+    return prob, c, s, t, j
+
+
+@pytest.mark.parametrize("nx,ny,p", [(2, 2, 6), (4, 2, 5), (2, 4, 7)])
+def test_jump_solve_equals_global_direct_solve(nx, ny, p):
+    """With right-hand sides on the shared-edge rows, the HPS solve (jumps injected at
+    every merge) equals the dense LU solve of the global system with those rows."""
+    prob, c, s, t, j = _jump_case(nx, ny, p)
+    u = O.solve(prob, O.build(prob, c), s, t, jumps=j)
+    ug = O.global_solve(prob, c, s, t, jumps=j)
+    assert O.rel_l2(u, ug) < 1e-11
+    # and jumps alone (s = 0, t = 0) give a non-trivial field, also equal
+    z = np.zeros_like(t)
+    u0 = O.solve(prob, O.build(prob, c), None, z, jumps=j)
+    assert np.linalg.norm(u0) > 1e-3 * np.linalg.norm(u)
+    assert O.rel_l2(u0, O.global_solve(prob, c, None, z, jumps=j)) < 1e-11
+
+
+def test_residual_vanishes_on_exact_solutions():
+    """The residual is zero (to round-off) at the dense solution of the global system,
+    and at the nodal values of a polynomial of degree <= p-1 with its exact s and t
+    (the discrete system holds exactly for such u)."""
+    prob, c, s, t, j = _jump_case(4, 2, 7)
+    ug = O.global_solve(prob, c, s, t, jumps=j)
+    r = O.global_residual(prob, c, s, t, ug, jumps=j)
+    b = O.global_rhs(prob, s, t, jumps=j)
+    assert np.linalg.norm(r) < 1e-11 * np.linalg.norm(b)
+    prob, xy, xyi, xyb, nrm, c = _setup(4, 4, 8, 15.0, 15.0, G.FourierField.seeded(2))
+    poly = G.Polynomial.seeded(5, 6)
+    sp, tp = poly.s(xyi, c, 15.0)[None], poly.t(xyb, nrm, 15.0)[None]
+    r = O.global_residual(prob, c, sp, tp, poly.u(xy)[None])
+    assert np.linalg.norm(r) < 1e-10 * np.linalg.norm(O.global_rhs(prob, sp, tp))
+
+
+def test_correction_solve_removes_a_perturbation():
+    """u' = u + e: solving with the residual of u' as (s, t, jumps) returns -e, so one
+    correction step restores u to round-off."""
+    prob, c, s, t, j = _jump_case(4, 4, 6)
+    boxes = O.build(prob, c)
+    u = O.solve(prob, boxes, s, t)
+    rng = np.random.default_rng(9)
+    e = 1e-3 * (rng.standard_normal(u.shape) + 1j * rng.standard_normal(u.shape))
+    r = O.global_residual(prob, c, s, t, u + e)
+    sc, tc, jc = O.correction_rhs(prob, r)
+    d = O.solve(prob, boxes, sc, tc, jumps=jc)
+    assert O.rel_l2(d, -e) < 1e-9
+    assert O.rel_l2(u + e + d, u) < 1e-12
+
+
+def test_plane_wave_residual_decays_with_p():
+    """The global residual of the sampled exact plane wave is a discretization error:
+    it decays spectrally in p (c = 1, s = 0)."""
+    res = []
+    for p in (6, 8, 10, 12):
+        prob, xy, xyi, xyb, nrm, c = _setup(2, 2, p, 12.0, 12.0, G.c_const)
+        pw = G.PlaneWave(12.0, 0.7)
+        r = O.global_residual(prob, c, None, pw.t(xyb, nrm, 12.0)[None], pw.u(xy)[None])
+        res.append(np.linalg.norm(r) / np.linalg.norm(pw.t(xyb, nrm, 12.0)))
+    assert all(b < a for a, b in zip(res, res[1:]))
+    assert res[-1] < 1e-3 * res[0]
+
+
+def test_pins_catch_swapped_jump_sides(monkeypatch):
+    """Injecting j1 and j2 on the wrong sides of the interface fails the jump pin."""
+    orig = O.solve
+
+    def bad_solve(prob, boxes, s, t, upward=True, jumps=None):
+        if jumps is None:
+            return orig(prob, boxes, s, t, upward)
+        # swap the roles: give every shared row the other side's right-hand side
+        jj = np.asarray(jumps).reshape(-1, prob.nleaf, prob.nb).copy()
+        for key, lst in O.shared_rows(prob).items():
+            if len(lst) == 2:
+                (l1, r1), (l2, r2) = lst
+                jj[:, l1, r1], jj[:, l2, r2] = jumps[:, l2, r2].copy(), jumps[:, l1, r1].copy()
+        return orig(prob, boxes, s, t, upward, jj)
+
+    prob, c, s, t, j = _jump_case(2, 2, 6)
+    u = bad_solve(prob, O.build(prob, c), s, t, jumps=j)
+    assert O.rel_l2(u, O.global_solve(prob, c, s, t, jumps=j)) > 1e-3
+
+
+def test_pins_catch_residual_with_F_for_G(monkeypatch):
+    """A residual that uses the neighbour's F instead of G misses the exact solution."""
+    prob, c, s, t, j = _jump_case(2, 2, 6)
+    ug = O.global_solve(prob, c, s, t, jumps=j)
+    orig = O.leaf_operators
+
+    def swapped(*a, **k):
+        ops = orig(*a, **k)
+        ops = dict(ops)
+        ops["G"] = ops["F"]
+        return ops
+
+    monkeypatch.setattr(O, "leaf_operators", swapped)
+    r = O.global_residual(prob, c, s, t, ug, jumps=j)
+    assert np.linalg.norm(r) > 1e-3 * np.linalg.norm(O.global_rhs(prob, s, t, jumps=j))
