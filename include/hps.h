@@ -65,9 +65,18 @@ typedef struct {
   int32_t nx, ny;
 } hps_domain;
 
+/* Arithmetic of the factorization and of the solve sweeps. */
+enum {
+  HPS_PREC_C128 = 0,  /* complex128 throughout                                            */
+  HPS_PREC_MIXED = 1  /* leaves and the top fp64_top_levels merge levels in complex128; the
+                         other merges and every solve product in complex64 on the matrix
+                         cores with FP32 accumulation; each solve is then corrected with the
+                         FP64 residual of the global collocation system (not in the paper) */
+};
+
 /* Build options.  hps_default_opts() fills the defaults noted below. */
 typedef struct {
-  int32_t precision;      /* 0 = complex128 throughout (default)                          */
+  int32_t precision;      /* HPS_PREC_C128 (default) or HPS_PREC_MIXED                    */
   int32_t keep_all_R;     /* 1 = keep every box's ItI operator R for inspection (tests);
                              0 = free children's R after each merge, as Sec. 2.4 does     */
   int32_t store_root_R;   /* 1 = form the root's R (Algorithm 1 does; the solve does not
@@ -75,7 +84,20 @@ typedef struct {
   int32_t profile;        /* 1 = record HIP events around every kernel group of the build
                              and of each solve; read them with hps_stage_times (default 0) */
   void* stream;           /* hipStream_t the work is ordered on (default NULL)            */
+  int32_t fp64_top_levels; /* HPS_PREC_MIXED: merge levels 0..fp64_top_levels-1 (the root
+                             is level 0) stay complex128 (default 3)                     */
+  int32_t refine_max_iter; /* residual correction steps per solve; -1 = automatic: 10 for
+                             HPS_PREC_MIXED, 0 for HPS_PREC_C128 (default -1)            */
+  double refine_tol;       /* correction stops once ||delta_r|| <= refine_tol ||u_r|| for
+                             every right-hand side r (default 1e-12)                     */
 } hps_opts;
+
+/* Outcome of the most recent solve on a factor (hps_last_solve_info). */
+typedef struct {
+  int32_t iterations;  /* residual correction steps taken (0 when correction is off)     */
+  int32_t converged;   /* 1 when the last relative correction met refine_tol             */
+  double correction;   /* max over right-hand sides of ||delta|| / ||u|| in the last step */
+} hps_solve_info;
 
 /* Timing of one kernel group (profile = 1).  flops and bytes are the algorithmic work
  * of the group (dense-equivalent counts of the formulas it evaluates, not hardware
@@ -160,6 +182,41 @@ int hps_build(const hps_domain* dom, int32_t p, double kappa, double eta_re,
  * factor concurrently.  The call allocates its own workspace.
  * Errors: HPS_E_INVALID (NULL factor/t/u, nrhs < 1), HPS_E_NOMEM, HPS_E_DEVICE. */
 int hps_solve(hps_factor* f, int32_t nrhs, const double* s, const double* t, double* u);
+
+/* Solve with right-hand sides on the shared-edge rows of the global collocation system
+ * (not in the paper; the correction step of a reduced-precision solve).  As hps_solve,
+ * plus
+ *   jumps  device complex, [nrhs][nx*ny][n_b]: for a node on the edge shared by leaf l
+ *          (position k of its boundary, order [S, E, N, W]) and leaf l', the row
+ *          F_l u_l + G_l' u_l' = jumps[r][l][k] (F = N + i eta, G = N - i eta with N the
+ *          outward normal derivative of each leaf's interpolant, Sec. 2.1); entries on
+ *          the outer boundary are ignored.  NULL means zero.
+ * At every merge the interface conditions of Sec. 2.2 become t3^a = -g3^b + j1 and
+ * t3^b = -g3^a + j2, i.e. eqs. (talpha)/(tbeta) with h3^b - j1 and h3^a - j2 in place of
+ * h3^b and h3^a in the particular parts.
+ * Errors: as hps_solve. */
+int hps_solve_jumps(hps_factor* f, int32_t nrhs, const double* s, const double* t,
+                    const double* jumps, double* u);
+
+/* FP64 residual b - A u of the global collocation system that the factorization
+ * eliminates (rows: interior collocation rows Ahat(I_i, I) u_l = s of Sec. 2.1, impedance
+ * rows F u_l = t on the outer boundary, and F_l u_l + G_l' u_l' = jumps on shared edges),
+ * evaluated matrix-free from the differentiation matrices, c, kappa and eta.
+ *   s, t, jumps  device complex as for hps_solve_jumps (NULL = zero)
+ *   u            device complex, [nrhs][n_leaf_nodes]
+ *   r            device complex, [nrhs][n_leaf_nodes] output in the layout of u: for each
+ *                leaf the n_b boundary rows (order [S, E, N, W]) then the n_i interior
+ *                rows
+ * Stream-ordered on the factor's stream; no synchronization.
+ * Errors: HPS_E_INVALID, HPS_E_DEVICE. */
+int hps_residual(hps_factor* f, int32_t nrhs, const double* s, const double* t,
+                 const double* jumps, const double* u, double* r);
+
+/* Iterations and last relative correction of the factor's most recent hps_solve /
+ * hps_solve_jumps.  With residual correction on, those calls synchronize the stream
+ * once per step and return HPS_E_NOT_CONVERGED (u holding the last iterate) when the
+ * tolerance is not met within refine_max_iter steps. */
+int hps_last_solve_info(const hps_factor* f, hps_solve_info* info);
 
 /* Sizes of a factor. */
 int hps_factor_query(const hps_factor* f, hps_factor_info* info);

@@ -4,6 +4,7 @@
 // downward).  Host code; all arithmetic on the hot path runs in the HIP kernels.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -109,10 +110,13 @@ struct LevelPlan {
   bool split_x = true;
   int nbc = 0, nbp = 0, n1 = 0, n2 = 0, n3 = 0;
   std::vector<int> codeA, codeB, perm, i1a, i3a, i2b, i3b;
-  DevBuf dmaps;  // codeA | codeB | perm | i1a | i3a | i2b | i3b
+  // per merge and interface node: index of alpha's / beta's shared-edge row in an
+  // [nleaf][nb] array of boundary rows (grid leaf order)
+  std::vector<int> ja, jb;
+  DevBuf dmaps;  // codeA | codeB | perm | i1a | i3a | i2b | i3b | ja | jb
   const int* dcodeA = nullptr; const int* dcodeB = nullptr; const int* dperm = nullptr;
   const int* di1a = nullptr; const int* di3a = nullptr; const int* di2b = nullptr;
-  const int* di3b = nullptr;
+  const int* di3b = nullptr; const int* dja = nullptr; const int* djb = nullptr;
   // stored operators of the level (Sec. 2.4), slices of the factor's arena
   View Winv, R33a, R33b, R13a, R23b, PhiA, PhiB;
 };
@@ -213,7 +217,7 @@ struct hps_factor {
   std::vector<std::vector<hps::Geo>> geo;  // per level, tree order
   std::vector<hps::LevelPlan> lv;          // merges producing level l (l = 0..L-1)
   std::vector<int> leaf_grid;              // tree-ordered leaf -> grid index
-  hps::DevBuf dleaf_grid, dxoff, duoff, dD;
+  hps::DevBuf dleaf_grid, dxoff, duoff, dD, dLT;
   hps::DevBuf ops;                         // arena: [Psi | Y] of every leaf + merge operators
   hps::View BI;                            // [nleaf][n*n] complex: [Psi | Y]
   hps::DevBuf rbuf[2];                     // ping-pong ItI operators (level l uses l % 2)
@@ -222,9 +226,11 @@ struct hps_factor {
   std::vector<char> R_valid;               // R of the level still holds its operator
   std::vector<int> nbl;                    // boundary size per level
   hps::Profiler build_prof, solve_prof;
+  hps::DevBuf dc;                          // c at the interior nodes (for the FP64 residual)
+  hps_solve_info last_info{};              // of the most recent solve
   size_t bytes() const {
-    size_t t = ops.bytes + dleaf_grid.bytes + dxoff.bytes + duoff.bytes + dD.bytes +
-               rbuf[0].bytes + rbuf[1].bytes;
+    size_t t = ops.bytes + dleaf_grid.bytes + dxoff.bytes + duoff.bytes + dD.bytes + dLT.bytes +
+               rbuf[0].bytes + rbuf[1].bytes + dc.bytes;
     for (auto& r : rkeep) t += r.bytes;
     for (auto& l : lv) t += l.dmaps.bytes;
     return t;
@@ -356,6 +362,26 @@ void make_plan(hps_factor& f) {
       if (v < 0 || v >= P.nbp || seen[v]) throw Error(HPS_E_INVALID, "plan: perm not bijective");
       seen[v] = 1;
     }
+    // I3 runs along alpha's E side (x split) or N side (y split) in ascending coordinate,
+    // m nodes per leaf edge; beta sees the same nodes on its W / S side
+    P.ja.resize((size_t)P.nbox * P.n3);
+    P.jb.resize((size_t)P.nbox * P.n3);
+    for (int b = 0; b < P.nbox; ++b) {
+      const Geo& g = f.geo[l][b];
+      for (int t = 0; t < P.n3; ++t) {
+        const int blk = t / m, q = t % m;
+        int la, lb, pa, pb;
+        if (sx) {
+          const int iy = g.iy0 + blk, ixa = g.ix0 + g.wx / 2 - 1;
+          la = iy * f.nx + ixa; lb = la + 1; pa = m + q; pb = 3 * m + q;
+        } else {
+          const int ix = g.ix0 + blk, iya = g.iy0 + g.wy / 2 - 1;
+          la = iya * f.nx + ix; lb = la + f.nx; pa = 2 * m + q; pb = q;
+        }
+        P.ja[(size_t)b * P.n3 + t] = la * f.nb + pa;
+        P.jb[(size_t)b * P.n3 + t] = lb * f.nb + pb;
+      }
+    }
   }
   f.leaf_grid.resize(f.nleaf);
   for (int h = 0; h < f.nleaf; ++h) {
@@ -364,11 +390,90 @@ void make_plan(hps_factor& f) {
   }
 }
 
+// ------------------------------------------------------------------ leaf line tables
+// The leaf stage eliminates the boundary nodes through the impedance rows F = N + i eta
+// (Sec. 2.1).  F_bb couples only the two end nodes of a grid line: (S_i, N_i) through
+// the first and last rows of D_y, (W_j, E_j) through those of D_x.  With their 2 x 2
+// inverses B (S/N) and C (W/E):
+//   (F_bb^{-1} F_bi) rows:  S_i: sS[l] = -B11 Dy(0,l) + B12 Dy(p-1,l) on nodes (i, l),
+//                           N_i: sN[l] = -B21 Dy(0,l) + B22 Dy(p-1,l), and W_j / E_j
+//                           likewise with C and D_x on nodes (k, j): oW[k], oE[k];
+//   S_i = A_ii - A_ib F_bb^{-1} F_bi = -(G_x (x) I) - (I (x) G_y) - kappa^2 diag(c),
+//     G_x(i,k) = Dxx(i,k) - Dxx(i,0) oW[k] - Dxx(i,p-1) oE[k],
+//     G_y(j,l) = Dyy(j,l) - Dyy(j,0) sS[l] - Dyy(j,p-1) sN[l];
+//   W = A_ib F_bb^{-1}: row (i, j) has wS[j] = -Dyy(j,0) B11 - Dyy(j,p-1) B21 in column
+//     S_i, wN[j] = -Dyy(j,0) B12 - Dyy(j,p-1) B22 in N_i, wW[i] = -Dxx(i,0) C11 -
+//     Dxx(i,p-1) C21 in W_j and wE[i] = -Dxx(i,0) C12 - Dxx(i,p-1) C22 in E_j.
+// (A = -Dxx - Dyy - kappa^2 c, so A_ib holds -Dxx(i,0), -Dxx(i,p-1), -Dyy(j,0),
+// -Dyy(j,p-1).)  Indices i, j, k, l run over the interior points 1..p-2.
+void leaf_tables(hps_factor& f, const double* all) {
+  using cd = std::complex<double>;
+  const int p = f.p, m = f.m;
+  const double* Dx1 = all;
+  const double* Dy1 = all + p * p;
+  const double* Dxx = all + 2 * p * p;
+  const double* Dyy = all + 3 * p * p;
+  auto at = [p](const double* A, int i, int k) { return A[i + p * k]; };
+  const cd ie(-f.eta_im, f.eta_re);  // i eta
+  auto inv2 = [](cd a11, cd a12, cd a21, cd a22, cd* o) {
+    const cd det = a11 * a22 - a12 * a21;
+    if (!(std::abs(det) > 0.0))
+      throw Error(HPS_E_SINGULAR, "leaf: singular end-node impedance block");
+    o[0] = a22 / det; o[1] = -a12 / det; o[2] = -a21 / det; o[3] = a11 / det;
+  };
+  cd B[4], Cm[4];
+  inv2(-at(Dy1, 0, 0) + ie, -at(Dy1, 0, p - 1), at(Dy1, p - 1, 0), at(Dy1, p - 1, p - 1) + ie, B);
+  inv2(-at(Dx1, 0, 0) + ie, -at(Dx1, 0, p - 1), at(Dx1, p - 1, 0), at(Dx1, p - 1, p - 1) + ie, Cm);
+  std::vector<cd> tab((size_t)leaf_table_len(p));
+  cd* Gx = tab.data();
+  cd* Gy = Gx + m * m;
+  cd* sS = Gy + m * m;
+  cd* sN = sS + m;
+  cd* oW = sN + m;
+  cd* oE = oW + m;
+  cd* wS = oE + m;
+  cd* wN = wS + m;
+  cd* wW = wN + m;
+  cd* wE = wW + m;
+  cd* by = wE + m;
+  cd* bx = by + 4;
+  for (int l = 1; l <= m; ++l) {
+    sS[l - 1] = -B[0] * at(Dy1, 0, l) + B[1] * at(Dy1, p - 1, l);
+    sN[l - 1] = -B[2] * at(Dy1, 0, l) + B[3] * at(Dy1, p - 1, l);
+    oW[l - 1] = -Cm[0] * at(Dx1, 0, l) + Cm[1] * at(Dx1, p - 1, l);
+    oE[l - 1] = -Cm[2] * at(Dx1, 0, l) + Cm[3] * at(Dx1, p - 1, l);
+  }
+  for (int i = 1; i <= m; ++i)
+    for (int k = 1; k <= m; ++k) {
+      Gx[(i - 1) + m * (k - 1)] =
+          at(Dxx, i, k) - at(Dxx, i, 0) * oW[k - 1] - at(Dxx, i, p - 1) * oE[k - 1];
+      Gy[(i - 1) + m * (k - 1)] =
+          at(Dyy, i, k) - at(Dyy, i, 0) * sS[k - 1] - at(Dyy, i, p - 1) * sN[k - 1];
+    }
+  for (int j = 1; j <= m; ++j) {
+    wS[j - 1] = -at(Dyy, j, 0) * B[0] - at(Dyy, j, p - 1) * B[2];
+    wN[j - 1] = -at(Dyy, j, 0) * B[1] - at(Dyy, j, p - 1) * B[3];
+    wW[j - 1] = -at(Dxx, j, 0) * Cm[0] - at(Dxx, j, p - 1) * Cm[2];
+    wE[j - 1] = -at(Dxx, j, 0) * Cm[1] - at(Dxx, j, p - 1) * Cm[3];
+  }
+  for (int q = 0; q < 4; ++q) {
+    by[q] = B[q];
+    bx[q] = Cm[q];
+  }
+  std::vector<double> flat(2 * tab.size());
+  for (size_t e = 0; e < tab.size(); ++e) {
+    flat[2 * e] = tab[e].real();
+    flat[2 * e + 1] = tab[e].imag();
+  }
+  upload(f.dLT, flat);
+}
+
 void upload_plan(hps_factor& f) {
   for (auto& P : f.lv) {
     std::vector<int> all;
     auto app = [&](const std::vector<int>& v) { all.insert(all.end(), v.begin(), v.end()); };
     app(P.codeA); app(P.codeB); app(P.perm); app(P.i1a); app(P.i3a); app(P.i2b); app(P.i3b);
+    app(P.ja); app(P.jb);
     upload(P.dmaps, all);
     const int* base = P.dmaps.i();
     P.dcodeA = base; base += P.codeA.size();
@@ -377,7 +482,9 @@ void upload_plan(hps_factor& f) {
     P.di1a = base; base += P.i1a.size();
     P.di3a = base; base += P.i3a.size();
     P.di2b = base; base += P.i2b.size();
-    P.di3b = base;
+    P.di3b = base; base += P.i3b.size();
+    P.dja = base; base += P.ja.size();
+    P.djb = base;
   }
   upload(f.dleaf_grid, f.leaf_grid);
   std::vector<long> xoff(f.nleaf), uoff(f.nleaf);
@@ -407,6 +514,7 @@ void upload_plan(hps_factor& f) {
       all[3 * p * p + i + p * j] = sy;
     }
   upload(f.dD, all);
+  leaf_tables(f, all.data());
 }
 
 MergeLevelDesc level_desc(const hps_factor& f, const LevelPlan& P) {
@@ -432,7 +540,6 @@ void check_info(const std::vector<int>& h, long off, long cnt, const char* what)
 // kept; one scratch arena serves the leaf stage and then each merge level in turn.
 struct BuildScratch {
   DevBuf buf;
-  View X, Z, S;            // leaf stage
   View R31a, T, work;      // merge level (sized for the largest level)
   View info;               // [2 * nleaf] leaf infos, then one int per merge
   std::vector<long> info_off;  // per level offset into info
@@ -488,15 +595,8 @@ void plan_memory(hps_factor& f, BuildScratch& sc) {
         f.R[l].bytes = level_R_bytes(f, l);
       }
   }
-  // scratch: leaf part and level part share the same bytes; infos follow
-  size_t leaf_bytes = 0, level_bytes = 0;
-  {
-    Carver c;
-    c.take((size_t)nl * ni * nb * 8);
-    c.take((size_t)nl * ni * nb * 8);
-    c.take((size_t)nl * nb * nb * 16);
-    leaf_bytes = c.used;
-  }
+  // scratch: the leaf stage and the merge levels share the same bytes; infos follow
+  size_t level_bytes = leaf_scratch_bytes(f.p, nl);
   for (auto& P : f.lv) {
     Carver c;
     c.take((size_t)P.nbox * P.n3 * P.n1 * 16);
@@ -510,16 +610,9 @@ void plan_memory(hps_factor& f, BuildScratch& sc) {
     sc.info_off[l] = ninfo;
     ninfo += f.lv[l].nbox;
   }
-  const size_t shared = std::max(leaf_bytes, level_bytes);
+  const size_t shared = level_bytes;
   sc.buf.alloc(shared + (size_t)ninfo * sizeof(int) + 256);
   char* base = static_cast<char*>(sc.buf.p);
-  {
-    Carver c;
-    c.base = base;
-    sc.X = c.take((size_t)nl * ni * nb * 8);
-    sc.Z = c.take((size_t)nl * ni * nb * 8);
-    sc.S = c.take((size_t)nl * nb * nb * 16);
-  }
   sc.info.p = base + ((shared + 255) & ~size_t(255));
   sc.info.bytes = (size_t)ninfo * sizeof(int);
 }
@@ -538,9 +631,11 @@ void build_leaves(hps_factor& f, const double* c, BuildScratch& sc) {
   const long nl = f.nleaf;
   LeafDesc d;
   d.p = f.p; d.nleaf = f.nleaf; d.kappa = f.kappa; d.eta_re = f.eta_re; d.eta_im = f.eta_im;
-  d.D = f.dD.d(); d.c = c; d.leaf_grid = f.dleaf_grid.i(); d.BI = f.BI.d(); d.R = f.R[f.L].d();
-  d.X = sc.X.d(); d.Z = sc.Z.d(); d.S = sc.S.d(); d.info = sc.info.i();
+  d.c = c; d.leaf_grid = f.dleaf_grid.i(); d.tab = f.dLT.d(); d.BI = f.BI.d();
+  d.R = f.R[f.L].d(); d.info = sc.info.i();
+  d.Mg = leaf_scratch_bytes(f.p, nl) ? static_cast<double*>(sc.buf.p) : nullptr;
   const long n = f.n, nb = f.nb, ni = f.ni;
+  Profiler& pr = f.build_prof;
   // process leaves in chunks that fit the grid limit
   for (long h0 = 0; h0 < nl; h0 += 65535) {
     const int cnt = (int)std::min<long>(65535, nl - h0);
@@ -549,56 +644,23 @@ void build_leaves(hps_factor& f, const double* c, BuildScratch& sc) {
     dc.leaf_grid = d.leaf_grid + h0;
     dc.BI = d.BI + 2 * h0 * n * n;
     dc.R = d.R + 2 * h0 * nb * nb;
-    dc.X = d.X + h0 * ni * nb;
-    dc.Z = d.Z + h0 * ni * nb;
-    dc.S = d.S + 2 * h0 * nb * nb;
     dc.info = d.info + h0;
-    Profiler& pr = f.build_prof;
+    if (d.Mg) dc.Mg = d.Mg + 2 * h0 * ni * ni;
     const double c_ = cnt;
     {
-      Stage s(pr, "leaf_inv", c_ * 2.0 * ni * ni * ni, c_ * (ni * 8.0 + ni * ni * 16.0));
-      leaf_inverse_interior(dc, st);
+      // S_i^{-1}: complex Gauss-Jordan, n_i^3 complex multiply-adds
+      Stage s(pr, "leaf_sinv", c_ * 8.0 * ni * ni * ni, c_ * (ni * 8.0 + ni * ni * 16.0));
+      leaf_interior_inverse(dc, st);
     }
     {
-      Stage s(pr, "leaf_xzs", c_ * (16.0 * ni * ni + 2.0 * nb * nb * f.m),
-              c_ * (2.0 * ni * ni * 16 + 2.0 * ni * nb * 8 + nb * nb * 16.0));
-      leaf_xzs(dc, st);
+      Stage s(pr, "leaf_psi_i", c_ * 32.0 * ni * ni, c_ * (ni * ni + ni * nb) * 16.0);
+      leaf_psi_interior(dc, st);
     }
     {
-      // Psi_b = S^{-1}, written into the top-left block of [Psi | Y]
-      Stage s(pr, "leaf_sinv", c_ * 8.0 * nb * nb * nb, c_ * 2.0 * nb * nb * 16);
-      zinv(f.nb, cnt, dc.S, nb, nb * nb, dc.BI, n, n * n, d.info + nl + h0, nullptr, st);
+      Stage s(pr, "leaf_bnd", c_ * 8.0 * nb * n * f.m,
+              c_ * (ni * n + nb * n + nb * nb) * 16.0);
+      leaf_boundary_rows(dc, st);
     }
-    {
-      Stage s(pr, "leaf_r", 0.0, c_ * 2.0 * nb * nb * 16);
-      leaf_r_from_psib(dc, st);
-    }
-    GemmDesc g;
-    const char* gname = "leaf_gemm";
-    // Psi_i = -X Psi_b
-    g = GemmDesc();
-    g.M = ni; g.N = nb; g.K = nb; g.batch = cnt;
-    g.A = dc.X; g.lda = ni; g.sA = ni * nb; g.a_real = true;
-    g.B = dc.BI; g.ldb = n; g.sB = n * n;
-    g.C = dc.BI + 2 * nb; g.ldc = n; g.sC = n * n;
-    g.alpha = -1.0; g.beta = 0.0;
-    timed_gemm(f.build_prof, gname, g, st);
-    // Y_b = -Psi_b Z
-    g = GemmDesc();
-    g.M = nb; g.N = ni; g.K = nb; g.batch = cnt;
-    g.A = dc.BI; g.lda = n; g.sA = n * n;
-    g.B = dc.Z; g.ldb = nb; g.sB = nb * ni; g.b_real = true;
-    g.C = dc.BI + 2 * n * nb; g.ldc = n; g.sC = n * n;
-    g.alpha = -1.0; g.beta = 0.0;
-    timed_gemm(f.build_prof, gname, g, st);
-    // Y_i = A_ii^{-1} - X Y_b
-    g = GemmDesc();
-    g.M = ni; g.N = ni; g.K = nb; g.batch = cnt;
-    g.A = dc.X; g.lda = ni; g.sA = ni * nb; g.a_real = true;
-    g.B = dc.BI + 2 * n * nb; g.ldb = n; g.sB = n * n;
-    g.C = dc.BI + 2 * (nb + n * nb); g.ldc = n; g.sC = n * n;
-    g.alpha = -1.0; g.beta = 1.0;
-    timed_gemm(f.build_prof, gname, g, st);
   }
   f.R_valid[f.L] = 1;
 }
@@ -700,8 +762,7 @@ void build_all(hps_factor& f, const double* c) {
   HPS_HIP(hipStreamSynchronize(f.stream));
   std::vector<int> h(sc.info.bytes / sizeof(int));
   HPS_HIP(hipMemcpy(h.data(), sc.info.p, sc.info.bytes, hipMemcpyDeviceToHost));
-  check_info(h, 0, f.nleaf, "leaf interior inversion");
-  check_info(h, f.nleaf, f.nleaf, "leaf boundary Schur complement");
+  check_info(h, 0, f.nleaf, "leaf interior Schur complement");
   for (int l = 0; l < f.L; ++l) check_info(h, sc.info_off[l], f.lv[l].nbox, "interface matrix W");
   // release the ItI buffer that no longer holds a kept operator
   if (!f.opts.keep_all_R) {
@@ -721,13 +782,14 @@ struct Arena {
   bool dry = true;
   hipStream_t st = nullptr;
   char* base = nullptr;
-  size_t used = 0, split_need = 0;
+  size_t used = 0, split_need = 0, peak = 0;
   void* split = nullptr;
   void* block = nullptr;
   double* get(size_t bytes) {
     bytes = (bytes + 255) & ~size_t(255);
     size_t off = used;
     used += bytes;
+    peak = std::max(peak, used);
     // in the dry pass the pointer is a placeholder that is never dereferenced
     return reinterpret_cast<double*>((dry ? reinterpret_cast<char*>(4096) : base) + off);
   }
@@ -740,6 +802,7 @@ struct Arena {
     timed_skinny(pr, name, k, st);
   }
   void allocate() {
+    used = std::max(used, peak);
     size_t total = used + split_need + 256;
     hipError_t e = hipMallocAsync(&block, total, st);
     if (e != hipSuccess) {
@@ -758,30 +821,34 @@ struct Arena {
   }
 };
 
-void solve_pass(hps_factor& f, int nrhs, const double* s, const double* t, double* u,
-                Arena& ws) {
+void solve_pass(hps_factor& f, int nrhs, const double* s, const double* t, const double* jmp,
+                double* u, Arena& ws) {
   hipStream_t st = f.stream;
   Profiler& pr = f.solve_prof;
   pr.reset(!ws.dry && f.opts.profile != 0, st);
   const char* nm = "solve_leaf_up";
   const long nl = f.nleaf, n = f.n, nb = f.nb, ni = f.ni;
-  const bool up = (s != nullptr);
+  // the upward pass runs for a body load or for right-hand sides on shared-edge rows
+  const bool up = (s != nullptr) || (jmp != nullptr);
   std::vector<double*> h(f.L + 1, nullptr), tt(f.L + 1, nullptr), tta(f.L, nullptr),
       ttb(f.L, nullptr);
   double* ut = nullptr;
   if (up) {
     ut = ws.get((size_t)nl * n * nrhs * 16);
-    // leaf: u~ = Y s   (Algorithm 2 step (3))
-    SkinnyDesc k;
-    k.M = n; k.K = ni; k.nrhs = nrhs; k.batch = (int)nl;
-    k.A = f.BI.d() + 2 * n * nb; k.lda = n; k.sA = n * n;
-    k.X = s; k.ldx = nl * ni; k.xoff = f.dxoff.l();
-    k.C = ut; k.ldc = n; k.sC = n * nrhs;
-    ws.skinny(pr, nm, k);
     h[f.L] = ws.get((size_t)nl * nb * nrhs * 16);
-    {
+    if (s) {
+      // leaf: u~ = Y s   (Algorithm 2 step (3))
+      SkinnyDesc k;
+      k.M = n; k.K = ni; k.nrhs = nrhs; k.batch = (int)nl;
+      k.A = f.BI.d() + 2 * n * nb; k.lda = n; k.sA = n * n;
+      k.X = s; k.ldx = nl * ni; k.xoff = f.dxoff.l();
+      k.C = ut; k.ldc = n; k.sC = n * nrhs;
+      ws.skinny(pr, nm, k);
       Stage sg(pr, "solve_gather", 0.0, nl * nb * nrhs * 32.0);
       if (!ws.dry) leaf_h_from_u(f.nleaf, f.n, f.nb, nrhs, f.eta_re, f.eta_im, ut, h[f.L], st);
+    } else if (!ws.dry) {
+      fill_zero(ut, 2 * nl * n * nrhs, st);
+      fill_zero(h[f.L], 2 * nl * nb * nrhs, st);
     }
     // merges, bottom-up   (steps (5)-(7))
     nm = "solve_merge_up";
@@ -796,7 +863,9 @@ void solve_pass(hps_factor& f, int nrhs, const double* s, const double* t, doubl
       h[l] = ws.get((size_t)nbox * nbp * nrhs * 16);
       {
         Stage sg(pr, "solve_gather", 0.0, nbox * (2.0 * P.nbc + 3.0 * n3 + nbp) * nrhs * 16);
-        if (!ws.dry) up_gather(d, nrhs, h[l + 1], h3a, v, ttb[l], h[l], st);
+        if (!ws.dry)
+          up_gather(d, nrhs, h[l + 1], h3a, v, ttb[l], h[l], jmp, nl * nb,
+                    jmp ? P.dja : nullptr, jmp ? P.djb : nullptr, st);
       }
       // v = R33b h3a - h3b
       SkinnyDesc k;
@@ -920,10 +989,13 @@ int32_t hps_version(void) { return 10000; }
 void hps_default_opts(hps_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
-  o->precision = 0;
+  o->precision = HPS_PREC_C128;
   o->keep_all_R = 0;
   o->store_root_R = 1;
   o->stream = nullptr;
+  o->fp64_top_levels = 3;
+  o->refine_max_iter = -1;
+  o->refine_tol = 1e-12;
 }
 
 int hps_nodes(const hps_domain* dom, int32_t p, double* xy_leaf, double* xy_interior,
@@ -988,22 +1060,136 @@ int hps_build(const hps_domain* dom, int32_t p, double kappa, double eta_re, dou
     f->stream = static_cast<hipStream_t>(f->opts.stream);
     make_plan(*f);
     upload_plan(*f);
+    f->dc.alloc((size_t)f->nleaf * f->ni * sizeof(double));
+    HPS_HIP(hipMemcpyAsync(f->dc.p, c_interior, f->dc.bytes, hipMemcpyDeviceToDevice, f->stream));
     f->build_prof.reset(f->opts.profile != 0, f->stream);
     build_all(*f, c_interior);
     *out = f.release();
   });
 }
 
+namespace hps {
+namespace {
+
+ResidualDesc residual_desc(const hps_factor& f, const double* s, const double* t,
+                           const double* jmp, const double* u) {
+  ResidualDesc r;
+  r.p = f.p; r.nx = f.nx; r.ny = f.ny;
+  r.kappa = f.kappa; r.eta_re = f.eta_re; r.eta_im = f.eta_im;
+  r.D = f.dD.d(); r.c = f.dc.d(); r.u = u; r.s = s; r.t = t; r.jmp = jmp;
+  return r;
+}
+
+int refine_iters(const hps_factor& f) {
+  if (f.opts.refine_max_iter >= 0) return f.opts.refine_max_iter;
+  return f.opts.precision == HPS_PREC_MIXED ? 10 : 0;
+}
+
+// Solve, then (when enabled) residual correction in FP64: r = b - A u on the global
+// collocation system, delta = Solve(r) with r's shared-edge rows as interface jumps,
+// u += delta, until max_r |delta_r| <= tol |u_r| or the iteration limit.
+void solve_impl(hps_factor& f, int nrhs, const double* s, const double* t, const double* jmp,
+                double* u) {
+  const int iters = refine_iters(f);
+  const long nl = f.nleaf, n = f.n, nb = f.nb, ni = f.ni, nt = 2L * (f.nx + f.ny) * f.m;
+  const int nblk = norms_blocks();
+  Arena ws;
+  ws.st = f.stream;
+  double *rs = nullptr, *rt = nullptr, *rj = nullptr, *dl = nullptr, *part = nullptr;
+  size_t mark = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) ws.allocate();
+    if (iters > 0) {
+      rs = ws.get((size_t)nrhs * nl * ni * 16);
+      rt = ws.get((size_t)nrhs * nt * 16);
+      rj = ws.get((size_t)nrhs * nl * nb * 16);
+      dl = ws.get((size_t)nrhs * nl * n * 16);
+      part = ws.get((size_t)nrhs * nblk * 2 * sizeof(double));
+    }
+    mark = ws.used;
+    solve_pass(f, nrhs, s, t, jmp, u, ws);  // pass 0 only sizes the workspace
+  }
+  f.last_info = hps_solve_info{};
+  if (iters <= 0) return;
+  std::vector<double> hpart((size_t)nrhs * nblk * 2);
+  double corr = 0.0;
+  int it = 0;
+  bool conv = false;
+  for (it = 1; it <= iters; ++it) {
+    ResidualDesc r = residual_desc(f, s, t, jmp, u);
+    r.rs = rs; r.rs_rhs = nl * ni; r.rs_leaf = ni;
+    r.rb = rj; r.rb_rhs = nl * nb; r.rb_leaf = nb;
+    r.rt = rt; r.rt_rhs = nt;
+    residual(r, nrhs, f.stream);
+    ws.used = mark;
+    solve_pass(f, nrhs, rs, rt, rj, dl, ws);
+    norms_partial(nl * n, nrhs, dl, u, part, f.stream);
+    axpy((long)nrhs * nl * n, dl, u, f.stream);
+    HPS_HIP(hipMemcpyAsync(hpart.data(), part, hpart.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, f.stream));
+    HPS_HIP(hipStreamSynchronize(f.stream));
+    corr = 0.0;
+    for (int q = 0; q < nrhs; ++q) {
+      double dd = 0, uu = 0;
+      for (int b = 0; b < nblk; ++b) {
+        dd += hpart[2 * ((size_t)q * nblk + b)];
+        uu += hpart[2 * ((size_t)q * nblk + b) + 1];
+      }
+      corr = std::max(corr, uu > 0 ? std::sqrt(dd / uu) : std::sqrt(dd));
+    }
+    if (corr <= f.opts.refine_tol) {
+      conv = true;
+      break;
+    }
+  }
+  f.last_info.iterations = std::min(it, iters);
+  f.last_info.converged = conv ? 1 : 0;
+  f.last_info.correction = corr;
+  if (!conv)
+    throw Error(HPS_E_NOT_CONVERGED, "residual correction did not reach refine_tol (last "
+                                     "relative correction " + std::to_string(corr) + ")");
+}
+
+}  // namespace
+}  // namespace hps
+
 int hps_solve(hps_factor* f, int32_t nrhs, const double* s, const double* t, double* u) {
   return guard([&] {
     if (!f) throw Error(HPS_E_INVALID, "factor is NULL");
     if (!t || !u) throw Error(HPS_E_INVALID, "t and u must be non-NULL");
     if (nrhs < 1) throw Error(HPS_E_INVALID, "nrhs must be >= 1");
-    Arena ws;
-    ws.st = f->stream;
-    solve_pass(*f, nrhs, s, t, u, ws);  // sizes the workspace
-    ws.allocate();
-    solve_pass(*f, nrhs, s, t, u, ws);
+    solve_impl(*f, nrhs, s, t, nullptr, u);
+  });
+}
+
+int hps_solve_jumps(hps_factor* f, int32_t nrhs, const double* s, const double* t,
+                    const double* jumps, double* u) {
+  return guard([&] {
+    if (!f) throw Error(HPS_E_INVALID, "factor is NULL");
+    if (!t || !u) throw Error(HPS_E_INVALID, "t and u must be non-NULL");
+    if (nrhs < 1) throw Error(HPS_E_INVALID, "nrhs must be >= 1");
+    solve_impl(*f, nrhs, s, t, jumps, u);
+  });
+}
+
+int hps_residual(hps_factor* f, int32_t nrhs, const double* s, const double* t,
+                 const double* jumps, const double* u, double* r) {
+  return guard([&] {
+    if (!f) throw Error(HPS_E_INVALID, "factor is NULL");
+    if (!u || !r) throw Error(HPS_E_INVALID, "u and r must be non-NULL");
+    if (nrhs < 1) throw Error(HPS_E_INVALID, "nrhs must be >= 1");
+    const long nl = f->nleaf, n = f->n, nb = f->nb;
+    ResidualDesc d = residual_desc(*f, s, t, jumps, u);
+    d.rs = r + 2 * nb; d.rs_rhs = nl * n; d.rs_leaf = n;
+    d.rb = r; d.rb_rhs = nl * n; d.rb_leaf = n;
+    residual(d, nrhs, f->stream);
+  });
+}
+
+int hps_last_solve_info(const hps_factor* f, hps_solve_info* info) {
+  return guard([&] {
+    if (!f || !info) throw Error(HPS_E_INVALID, "factor and info must be non-NULL");
+    *info = f->last_info;
   });
 }
 

@@ -60,19 +60,23 @@ void zinv(int n, int batch, const double* A, long lda, long sA, double* Out, lon
 struct LeafDesc {
   int p = 0, nleaf = 0;
   double kappa = 0, eta_re = 0, eta_im = 0;
-  const double* D = nullptr;     // device [4][p*p]: Dx1, Dy1, Dxx, Dyy (column-major)
   const double* c = nullptr;     // device [nleaf * ni] in user (grid) leaf order
   const int* leaf_grid = nullptr;  // device [nleaf]: grid index of tree-ordered leaf h
+  const double* tab = nullptr;   // device complex line table (leaf_table_len(p) entries)
   double* BI = nullptr;          // device [nleaf][n*n] complex: [Psi | Y]
   double* R = nullptr;           // device [nleaf][nb*nb] complex
-  double* X = nullptr;           // scratch [nleaf][ni*nb] real
-  double* Z = nullptr;           // scratch [nleaf][nb*ni] real
-  double* S = nullptr;           // scratch [nleaf][nb*nb] complex
+  double* Mg = nullptr;          // scratch [nleaf][ni*ni] complex (leaf_scratch_bytes)
   int* info = nullptr;           // device [nleaf]
 };
-void leaf_inverse_interior(const LeafDesc& d, hipStream_t st);  // Ainv -> Y_i block
-void leaf_xzs(const LeafDesc& d, hipStream_t st);               // X, Z, S
-void leaf_r_from_psib(const LeafDesc& d, hipStream_t st);       // R = I - 2 i eta Psi_b
+// scratch the leaf inverse needs for nleaf leaves (0 when it fits in registers)
+size_t leaf_scratch_bytes(int p, long nleaf);
+// complex entries of the line table: G_x, G_y (m x m), the F_bb^{-1} F_bi line
+// coefficients sS, sN, oW, oE, the W = A_ib F_bb^{-1} coefficients wS, wN, wW, wE (m
+// each) and the two 2 x 2 inverses of F_bb (S/N pair, W/E pair)
+int leaf_table_len(int p);
+void leaf_interior_inverse(const LeafDesc& d, hipStream_t st);  // S_i^{-1} -> Y_i block
+void leaf_psi_interior(const LeafDesc& d, hipStream_t st);      // Psi_i = -Y_i W
+void leaf_boundary_rows(const LeafDesc& d, hipStream_t st);     // [Psi_b | Y_b], R
 
 // ------------------------------------------------------------------ merge helpers
 struct MergeLevelDesc {
@@ -105,10 +109,41 @@ void leaf_h_from_u(int nleaf, int n, int nb, int nrhs, double eta_re, double eta
                    const double* u, double* h, hipStream_t st);
 // Upward gather of one level: h3a, -h3a (into ttb), -h3b (into v), and the h1/h2 parts
 // of the parent's h.  hc: children's h [2*nbox][nbc x nrhs]; hp: [nbox][nbp x nrhs].
+// With right-hand sides on the shared-edge rows (jmp: [nrhs][ldj], ja/jb: per merge and
+// interface node the index of alpha's / beta's row in jmp), h3a is replaced by
+// h3a - j2 (beta's row) and h3b by h3b - j1 (alpha's row).
 void up_gather(const MergeLevelDesc& d, int nrhs, const double* hc, double* h3a,
-               double* v, double* ttb, double* hp, hipStream_t st);
+               double* v, double* ttb, double* hp, const double* jmp, long ldj,
+               const int* ja, const int* jb, hipStream_t st);
 // Downward scatter of one level: children's t on I1 / I2 from the parent's t.
 void down_scatter(const MergeLevelDesc& d, int nrhs, const double* tp, long ldp,
                   double* tc, hipStream_t st);
+
+// ------------------------------------------------------------------ FP64 residual
+// Residual of the global collocation system for nrhs vectors u (grid leaf order), written
+// as interior rows rs[r*rs_rhs + l*rs_leaf + k] (k < n_i) and boundary rows
+// rb[r*rb_rhs + l*rb_leaf + k] (k < n_b).  Rows on the outer boundary go to
+// rt[r*rt_rhs + root position] when rt is given (rb then holds 0 there), else to rb.
+struct ResidualDesc {
+  int p = 0, nx = 0, ny = 0;
+  double kappa = 0, eta_re = 0, eta_im = 0;
+  const double* D = nullptr;    // [4][p*p] Dx1, Dy1, Dxx, Dyy (column-major, scaled)
+  const double* c = nullptr;    // [nleaf * n_i] real
+  const double* u = nullptr;    // complex [nrhs][nleaf * n]
+  const double* s = nullptr;    // complex [nrhs][nleaf * n_i] or null (zero)
+  const double* t = nullptr;    // complex [nrhs][nt] or null (zero)
+  const double* jmp = nullptr;  // complex [nrhs][nleaf * n_b] or null (zero)
+  double* rs = nullptr; long rs_rhs = 0, rs_leaf = 0;
+  double* rb = nullptr; long rb_rhs = 0, rb_leaf = 0;
+  double* rt = nullptr; long rt_rhs = 0;
+};
+void residual(const ResidualDesc& d, int nrhs, hipStream_t st);
+// y += x (complex, n entries)
+void axpy(long n, const double* x, double* y, hipStream_t st);
+// per right-hand side r (vectors of len complex entries, r-major): partial sums of |x|^2
+// and |y|^2 over norms_blocks() blocks, part[2*(r*blocks + b) + {0,1}]
+int norms_blocks();
+void norms_partial(long len, int nrhs, const double* x, const double* y, double* part,
+                   hipStream_t st);
 
 }  // namespace hps

@@ -1,72 +1,103 @@
-// Leaf stage (Sec. 2.1, 2.1.1, 2.1.2): for every leaf, the operators Psi (n x n_b),
+// Leaf stage (Sec. 2.1, 2.1.1, 2.1.2): for every leaf, the operators Psi (n x n_b) and
 // Y (n x n_i) with B [Psi | Y] = I, and the ItI operator R = G Psi.
 //
-// With u = [u_b; u_i], B = [[N_b + i eta I, N_i], [A_ib, A_ii]] where A = Ahat(I_i, :)
-// is real for real c.  Block elimination (derived from eqs. (homogeneous) and
-// (particular)):
-//   X = A_ii^{-1} A_ib,  Z = N_i A_ii^{-1},  S = N_b + i eta I - N_i X
-//   Psi_b = S^{-1},  Psi_i = -X Psi_b,  Y_b = -Psi_b Z,  Y_i = A_ii^{-1} - X Y_b
-//   R = G Psi = I - 2 i eta Psi_b      (G = F - 2 i eta E_b and F Psi = I)
-// Only S and what follows are complex.  A_ib, N_i, N_b are sparse (one grid line per
-// boundary node), so X, Z and S are formed by line sums.
+// With u = [u_b; u_i], B = [[F_bb, F_bi], [A_ib, A_ii]] (F = N + i eta E_b restricted to
+// the boundary / interior columns, A = Ahat(I_i, :)).  The boundary unknowns are
+// eliminated through the impedance rows, which keeps every step as well conditioned as
+// B itself (Re eta != 0): the interior Dirichlet block A_ii alone is singular whenever
+// kappa^2 c meets an eigenvalue of the leaf's Dirichlet Laplacian, which happens for
+// leaves of a few wavelengths.  Derived from eqs. (homogeneous) and (particular):
+//   u_b = F_bb^{-1} (f - F_bi u_i),   S_i u_i = s - A_ib F_bb^{-1} f,
+//   S_i = A_ii - A_ib F_bb^{-1} F_bi,
+//   Y_i = S_i^{-1},  Psi_i = -Y_i W  (W = A_ib F_bb^{-1}),
+//   [Psi_b | Y_b] = [F_bb^{-1} | 0] - F_bb^{-1} F_bi [Psi_i | Y_i],
+//   R = G Psi = I - 2 i eta Psi_b      (G = F - 2 i eta E_b and F Psi = I).
+// F_bb couples only the two end nodes of each grid line (S_i with N_i, W_j with E_j),
+// so F_bb^{-1} is a set of 2 x 2 inverses, F_bb^{-1} F_bi mixes the interior nodes of
+// one grid line, and S_i = -(G_x (x) I) - (I (x) G_y) - kappa^2 diag(c) has the
+// sparsity of the Laplacian with complex line operators G_x, G_y.  These line tables
+// depend only on p, the leaf size and eta; the host builds them (LeafDesc::tab).
 //
-// Kernels: leaf_inv (A_ii^{-1} by register-resident blocked Gauss-Jordan with partial
-// pivoting, one workgroup per leaf), leaf_xzs (X, Z, S), then the batched complex
-// inverse of S and three batched MFMA GEMMs (launched by the host driver).
+// Kernels: leaf_sinv (S_i^{-1} by register-resident blocked Gauss-Jordan with partial
+// pivoting, one workgroup per leaf), leaf_psi_i (Psi_i from the rows of Y_i),
+// leaf_bnd (boundary rows of [Psi | Y] and R).
 #include "kernels.hpp"
 
 namespace hps {
 namespace {
 
-// Thread grid GR x GC per leaf, each thread owning ER x EC entries of A_ii (padded):
-// rows tr + GR a, columns tc + GC b.  Pivots are taken in blocks of NBK columns.
-template <int P> struct LeafInvCfg {
+// offsets (complex entries) into the line table of LeafDesc::tab, m = p - 2
+struct TabIdx {
+  int m;
+  __host__ __device__ int gx() const { return 0; }
+  __host__ __device__ int gy() const { return m * m; }
+  __host__ __device__ int sS() const { return 2 * m * m; }
+  __host__ __device__ int sN() const { return 2 * m * m + m; }
+  __host__ __device__ int oW() const { return 2 * m * m + 2 * m; }
+  __host__ __device__ int oE() const { return 2 * m * m + 3 * m; }
+  __host__ __device__ int wS() const { return 2 * m * m + 4 * m; }
+  __host__ __device__ int wN() const { return 2 * m * m + 5 * m; }
+  __host__ __device__ int wW() const { return 2 * m * m + 6 * m; }
+  __host__ __device__ int wE() const { return 2 * m * m + 7 * m; }
+  __host__ __device__ int by() const { return 2 * m * m + 8 * m; }
+  __host__ __device__ int bx() const { return 2 * m * m + 8 * m + 4; }
+};
+
+// Thread grid GR x GC per leaf, each thread owning ER x EC complex entries of S_i
+// (padded): rows tr + GR a, columns tc + GC b.  Pivots are taken in blocks of NBK.
+template <int P> struct LeafCfg {
   static constexpr int m = P - 2;
   static constexpr int NI = m * m;
-  static constexpr int ER = P <= 9 ? (m > 0 ? m : 1)
-                          : P == 10 ? 4 : P <= 13 ? 5 : P == 14 ? 6 : 7;
-  static constexpr int EC = P == 16 ? 9 : ER;               // p=16: 616 threads, 63 entries
+  static constexpr int ER = P <= 7 ? 1 : P <= 10 ? 2 : P == 11 ? 3 : P <= 14 ? 4 : 5;
+  static constexpr int EC = P <= 7 ? 1 : P <= 9 ? 2 : P == 10 ? 4 : P == 11 ? 3
+                          : P <= 13 ? 4 : P <= 15 ? 6 : 8;
   static constexpr int GR = (NI + ER - 1) / ER;
   static constexpr int GC = (NI + EC - 1) / EC;
   static constexpr int GE = (GC * EC > GR * ER ? GC * EC : GR * ER);  // LDS row stride
   static constexpr int NLIVE = GR * GC;                     // threads that own entries
   static constexpr int NT = ((NLIVE + 63) / 64) * 64;       // whole waves (shuffles)
-  static constexpr int NBK = 8;                             // pivots per block
+  // pivots per block (wider for the scratch-copy variant: fewer passes over the copy)
+  static constexpr int NBK = P >= 14 ? 12 : 8;
   static constexpr int PQ = (NI + 63) / 64;                 // panel rows per lane
-  static constexpr int LDS_DOUBLES = 19200;                 // GJ buffers / output staging
-  static constexpr int CW = (LDS_DOUBLES / NI) < NI ? (LDS_DOUBLES / NI) : NI;
+  static constexpr int POOL = 3 * NBK * GE;                 // complex entries of LDS
+  static constexpr int CW = (POOL / NI) < NI ? (POOL / NI) : NI;  // output chunk columns
   static_assert(NT <= 1024, "too many threads");
-  static_assert(GR * ER >= NI && 3 * NBK * GE <= LDS_DOUBLES, "bad leaf grid");
+  static_assert(GR * ER >= NI && GC * EC >= NI && CW >= 1, "bad leaf grid");
 };
 
-// A_ii^{-1} by blocked Gauss-Jordan with partial pivoting, matrix resident in
-// registers.  Per block K of NBK pivot columns:
+// S_i^{-1} by blocked Gauss-Jordan with partial pivoting, matrix resident in registers.
+// Per block K of NBK pivot columns:
 //   1. owners publish the panel columns M[:, K] to LDS;
 //   2. wave 0 runs the NBK elimination steps on the panel (pivot = largest unused
-//      |entry|), giving the block transformation Q and the pivot rows P_K;
+//      |re| + |im|), giving the block transformation Q and the pivot rows P_K;
 //   3. owners of the pivot rows publish X = M[P_K, :];
 //   4. every entry outside K becomes (pivot rows zeroed) + Q X, entries in K become Q.
 // This is the same in-place elimination as column-at-a-time Gauss-Jordan (the block
 // step applies the product of the NBK elementary transformations at once); the
-// in-place result M satisfies A^{-1}[k][piv[j]] = M[piv[k]][j].
-template <int P>
-__global__ __launch_bounds__(LeafInvCfg<P>::NT) void leaf_inv_kernel(LeafDesc d) {
-  using Cfg = LeafInvCfg<P>;
+// in-place result M satisfies S^{-1}[k][piv[j]] = M[piv[k]][j].  The inverse goes to
+// the Y_i block of [Psi | Y].
+// RES: each thread keeps its entries in registers.  Otherwise (p >= 14, where a complex
+// matrix of (p-2)^4 entries needs more registers than a workgroup has) they live in a
+// per-leaf scratch copy (d.Mg) between block steps; every thread only ever reads and
+// writes its own entries there, so no cross-thread ordering is involved.
+template <int P, bool RES>
+__global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
+  using Cfg = LeafCfg<P>;
   constexpr int m = Cfg::m, NI = Cfg::NI, ER = Cfg::ER, EC = Cfg::EC, GR = Cfg::GR,
                 GC = Cfg::GC, GE = Cfg::GE;
   constexpr int NBK = Cfg::NBK, PQ = Cfg::PQ;
   constexpr int NB = 4 * m, N = P * P - 4;
-  __shared__ double pool[Cfg::LDS_DOUBLES];
+  __shared__ double2 pool[Cfg::POOL];
   __shared__ int piv[NI], ipiv[NI];
   __shared__ int slot[NI];          // position of a row in the current block's pivots, or -1
   __shared__ int used_s[NI];
-  __shared__ double sD[2][P * P];
+  __shared__ double2 sG[2][m * m];  // G_x, G_y
   __shared__ int s_bad;
-  double* bufA = pool;              // [NBK][GE]  panel / block transformation
-  double* bufB = pool + NBK * GE;   // [NBK][GE]  (ping-pong partner)
-  double* Xs = pool + 2 * NBK * GE; // [NBK][GE]  pivot rows
-  double* pan = bufA;               // receives the next block's panel columns
-  double* oth = bufB;
+  double2* bufA = pool;              // [NBK][GE]  panel / block transformation
+  double2* bufB = pool + NBK * GE;   // [NBK][GE]  (ping-pong partner)
+  double2* Xs = pool + 2 * NBK * GE; // [NBK][GE]  pivot rows
+  double2* pan = bufA;               // receives the next block's panel columns
+  double2* oth = bufB;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -74,40 +105,50 @@ __global__ __launch_bounds__(LeafInvCfg<P>::NT) void leaf_inv_kernel(LeafDesc d)
   const int tr = tid % GR, tc = tid / GR;
   const long h = blockIdx.x;
   const int g = d.leaf_grid[h];
-  for (int e = tid; e < P * P; e += Cfg::NT) {
-    sD[0][e] = d.D[2 * P * P + e];  // Dxx
-    sD[1][e] = d.D[3 * P * P + e];  // Dyy
+  const double2* tab = reinterpret_cast<const double2*>(d.tab);
+  for (int e = tid; e < m * m; e += Cfg::NT) {
+    sG[0][e] = tab[TabIdx{m}.gx() + e];
+    sG[1][e] = tab[TabIdx{m}.gy() + e];
   }
   for (int i = tid; i < NI; i += Cfg::NT) {
     slot[i] = -1;
     used_s[i] = 0;
   }
-  for (int e = tid; e < 3 * NBK * GE; e += Cfg::NT) pool[e] = 0.0;
+  for (int e = tid; e < Cfg::POOL; e += Cfg::NT) pool[e] = cmk(0, 0);
   if (tid == 0) s_bad = 0;
   __syncthreads();
   const double k2 = d.kappa * d.kappa;
   const double* cl = d.c + (long)g * NI;
+  double2* Mg = reinterpret_cast<double2*>(d.Mg) + (RES ? 0 : h * (long)NI * NI);
+  // scratch address of entry (a, b) of this thread (padding entries are never touched)
+  auto gaddr = [&](int a, int b) { return Mg + (tr + GR * a) + (long)NI * (tc + GC * b); };
 
-  // assemble A_ii = -Dxx (x) I - I (x) Dyy - kappa^2 diag(c) on interior nodes
-  double M[ER][EC];
+  // assemble S_i = -(G_x (x) I) - (I (x) G_y) - kappa^2 diag(c) on the interior nodes
+  // (node r = (j-1) m + (i-1); G_x acts along x within a grid row, G_y along y)
+  double2 M[RES ? ER : 1][RES ? EC : 1];
 #pragma unroll
   for (int a = 0; a < ER; ++a) {
     const int r = tr + GR * a;
-    const int ir = r % m + 1, jr = r / m + 1;
+    const int ir = r % m, jr = r / m;
     const double cr = (live && r < NI) ? cl[r] : 0.0;
 #pragma unroll
     for (int b = 0; b < EC; ++b) {
       const int c = tc + GC * b;
-      double v = 0.0;
+      double2 v = cmk(0, 0);
       if (live && r < NI && c < NI) {
-        const int ic = c % m + 1, jc = c / m + 1;
-        if (jr == jc) v -= sD[0][ir + P * ic];
-        if (ir == ic) v -= sD[1][jr + P * jc];
-        if (r == c) v -= k2 * cr;
+        const int ic = c % m, jc = c / m;
+        if (jr == jc) v = csub(v, sG[0][ir + m * ic]);
+        if (ir == ic) v = csub(v, sG[1][jr + m * jc]);
+        if (r == c) v.x -= k2 * cr;
       }
-      M[a][b] = v;
+      if (RES) M[RES ? a : 0][RES ? b : 0] = v;
+      else if (live && r < NI && c < NI) *gaddr(a, b) = v;
     }
   }
+  auto get = [&](int a, int b) -> double2 {
+    if (RES) return M[RES ? a : 0][RES ? b : 0];
+    return *gaddr(a, b);
+  };
 
 #pragma unroll 1
   for (int k0 = 0; k0 < NI; k0 += NBK) {
@@ -120,7 +161,7 @@ __global__ __launch_bounds__(LeafInvCfg<P>::NT) void leaf_inv_kernel(LeafDesc d)
 #pragma unroll
         for (int b = 0; b < EC; ++b) {
           const int j = tc + GC * b - k0;
-          if (ra < NI && j >= 0 && j < nk) pan[j * GE + ra] = M[a][b];
+          if (ra < NI && j >= 0 && j < nk) pan[j * GE + ra] = get(a, b);
         }
       }
     }
@@ -138,14 +179,14 @@ __global__ __launch_bounds__(LeafInvCfg<P>::NT) void leaf_inv_kernel(LeafDesc d)
       }
 #pragma unroll 1
       for (int s = 0; s < nk; ++s) {
-        const double* src = (s & 1) ? oth : pan;
-        double* dst = (s & 1) ? pan : oth;
+        const double2* src = (s & 1) ? oth : pan;
+        double2* dst = (s & 1) ? pan : oth;
         double best = -1.0;
         int bi = NI;
 #pragma unroll
         for (int q = 0; q < PQ; ++q) {
           const int i = lane + 64 * q;
-          const double v = ((usedq >> q) & 1u) ? -1.0 : fabs(src[s * GE + (i < NI ? i : 0)]);
+          const double v = ((usedq >> q) & 1u) ? -1.0 : cabs1(src[s * GE + (i < NI ? i : 0)]);
           if (v > best) { best = v; bi = i; }
         }
         const int r = wave_argmax(best, bi);
@@ -153,20 +194,20 @@ __global__ __launch_bounds__(LeafInvCfg<P>::NT) void leaf_inv_kernel(LeafDesc d)
           if (lane == 0) s_bad = k0 + s + 1;
           break;
         }
-        const double ip = 1.0 / src[s * GE + r];
+        const double2 ip = crcp(src[s * GE + r]);
 #pragma unroll
         for (int q = 0; q < PQ; ++q) {
           const int i = lane + 64 * q;
           if (i < NI) {
             const bool isr = (i == r);
-            const double f = src[s * GE + i] * ip;
+            const double2 f = cmul(src[s * GE + i], ip);
 #pragma unroll
             for (int j = 0; j < NBK; ++j) {
               if (j < nk) {
-                const double pv = src[j * GE + i];
-                double v = fma(-f, src[j * GE + r], pv);
-                v = isr ? pv * ip : v;
-                v = (j == s) ? (isr ? ip : -f) : v;
+                const double2 pv = src[j * GE + i];
+                double2 v = csub(pv, cmul(f, src[j * GE + r]));
+                v = isr ? cmul(pv, ip) : v;
+                v = (j == s) ? (isr ? ip : cmk(-f.x, -f.y)) : v;
                 dst[j * GE + i] = v;
               }
             }
@@ -182,7 +223,7 @@ __global__ __launch_bounds__(LeafInvCfg<P>::NT) void leaf_inv_kernel(LeafDesc d)
     }
     __syncthreads();
     if (s_bad) break;
-    const double* Qs = (nk & 1) ? oth : pan;  // buffer written by the last step
+    const double2* Qs = (nk & 1) ? oth : pan;  // buffer written by the last step
     // 3. pivot rows (values before this block's update); on the panel columns X is the
     //    identity, so that the update below writes Q there
     if (live) {
@@ -194,13 +235,15 @@ __global__ __launch_bounds__(LeafInvCfg<P>::NT) void leaf_inv_kernel(LeafDesc d)
 #pragma unroll
           for (int b = 0; b < EC; ++b) {
             const int j = tc + GC * b - k0;
-            Xs[sl * GE + tc + GC * b] = (j >= 0 && j < nk) ? (j == sl ? 1.0 : 0.0) : M[a][b];
+            if (tc + GC * b < NI)
+              Xs[sl * GE + tc + GC * b] =
+                  (j >= 0 && j < nk) ? cmk(j == sl ? 1.0 : 0.0, 0.0) : get(a, b);
           }
       }
     }
     __syncthreads();
     // 4. block update: M <- (M with pivot rows and panel columns zeroed) + Q X
-    if (live) {
+    if (live && RES) {
 #pragma unroll
       for (int a = 0; a < ER; ++a) {
         const int ra = tr + GR * a;
@@ -209,26 +252,52 @@ __global__ __launch_bounds__(LeafInvCfg<P>::NT) void leaf_inv_kernel(LeafDesc d)
         for (int b = 0; b < EC; ++b) {
           const int j = tc + GC * b - k0;
           const bool inK = j >= 0 && j < nk;
-          M[a][b] = (isP || inK) ? 0.0 : M[a][b];
+          M[RES ? a : 0][RES ? b : 0] = (isP || inK) ? cmk(0, 0) : M[RES ? a : 0][RES ? b : 0];
         }
       }
-      const double* qb = Qs + tr;
-      const double* xbp = Xs + tc;
+      const double2* qb = Qs + tr;
+      const double2* xbp = Xs + tc;
 #pragma unroll 1
       for (int j = 0; j < nk; ++j) {
-        double xb[EC];
+        double2 xb[EC];
 #pragma unroll
         for (int b = 0; b < EC; ++b) xb[b] = xbp[j * GE + GC * b];
 #pragma unroll
         for (int a = 0; a < ER; ++a) {
-          const double qa = qb[j * GE + GR * a];
+          const double2 qa = qb[j * GE + GR * a];
 #pragma unroll
-          for (int b = 0; b < EC; ++b) M[a][b] = fma(qa, xb[b], M[a][b]);
+          for (int b = 0; b < EC; ++b)
+            M[RES ? a : 0][RES ? b : 0] = cfma(qa, xb[b], M[RES ? a : 0][RES ? b : 0]);
         }
+      }
+    } else if (live) {
+      // one row of entries at a time: load, update with all nk pivots, store
+#pragma unroll 1
+      for (int a = 0; a < ER; ++a) {
+        const int ra = tr + GR * a;
+        if (ra >= NI) continue;
+        const bool isP = slot[ra] >= 0;
+        double2 row[EC];
+#pragma unroll
+        for (int b = 0; b < EC; ++b) {
+          const int c = tc + GC * b;
+          const int j = c - k0;
+          const bool inK = j >= 0 && j < nk;
+          row[b] = (c >= NI || isP || inK) ? cmk(0, 0) : *gaddr(a, b);
+        }
+#pragma unroll 2
+        for (int j = 0; j < nk; ++j) {
+          const double2 qa = Qs[j * GE + ra];
+#pragma unroll
+          for (int b = 0; b < EC; ++b) row[b] = cfma(qa, Xs[j * GE + tc + GC * b], row[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < EC; ++b)
+          if (tc + GC * b < NI) *gaddr(a, b) = row[b];
       }
     }
     if (!(nk & 1)) {  // Q is in pan: the next panel goes to the other buffer
-      double* t = pan;
+      double2* t = pan;
       pan = oth;
       oth = t;
     }
@@ -240,9 +309,9 @@ __global__ __launch_bounds__(LeafInvCfg<P>::NT) void leaf_inv_kernel(LeafDesc d)
   }
   for (int k = tid; k < NI; k += Cfg::NT) ipiv[piv[k]] = k;
   __syncthreads();
-  // write A_ii^{-1}[k][piv[c]] = M[piv[k]][c]:  entry (row ri, col c) goes to
-  // (ipiv[ri], piv[c]); stage column chunks in LDS for coalesced complex stores into
-  // the Y_i block of [Psi | Y].
+  // write S^{-1}[k][piv[c]] = M[piv[k]][c]:  entry (row ri, col c) goes to
+  // (ipiv[ri], piv[c]); stage column chunks in LDS for coalesced stores into the Y_i
+  // block of [Psi | Y].
   double2* BI = reinterpret_cast<double2*>(d.BI) + h * (long)N * N;
   for (int c0 = 0; c0 < NI; c0 += Cfg::CW) {
     const int cw = (NI - c0) < Cfg::CW ? (NI - c0) : Cfg::CW;
@@ -256,134 +325,150 @@ __global__ __launch_bounds__(LeafInvCfg<P>::NT) void leaf_inv_kernel(LeafDesc d)
         const int c = tc + GC * b;
         if (c >= NI) continue;
         const int ocol = piv[c] - c0;
-        if (ocol >= 0 && ocol < cw) pool[orow + NI * ocol] = M[a][b];
+        if (ocol >= 0 && ocol < cw) pool[orow + NI * ocol] = get(a, b);
       }
     }
     __syncthreads();
     for (int e = tid; e < NI * cw; e += Cfg::NT) {
       const int row = e % NI, col = e / NI;
-      BI[(NB + row) + (long)N * (NB + c0 + col)] = make_double2(pool[e], 0.0);
+      BI[(NB + row) + (long)N * (NB + c0 + col)] = pool[e];
     }
     __syncthreads();
   }
 }
 
-// X (ni x nb), Z (nb x ni), S (nb x nb) of one leaf from A_ii^{-1} (real parts of
-// the Y_i block).  One 256-thread workgroup per leaf.
+// Psi_i = -Y_i W, W = A_ib F_bb^{-1}: row (i, j) of W has four entries, in the columns
+// of S_i (wS[j]), N_i (wN[j]), W_j (wW[i]) and E_j (wE[i]).  One thread per interior
+// row r of Y_i (the threads of a workgroup read each column of Y_i together).
 template <int P>
-__global__ __launch_bounds__(256) void leaf_xzs_kernel(LeafDesc d) {
+__global__ __launch_bounds__(256) void leaf_psi_i_kernel(LeafDesc d) {
   constexpr int m = P - 2, NI = m * m, NB = 4 * m, N = P * P - 4;
-  __shared__ double sX[NI * NB];
-  __shared__ double sD[4][P * P];
+  __shared__ double2 sw[4][m];
   const int tid = threadIdx.x;
   const long h = blockIdx.x;
-  for (int e = tid; e < 4 * P * P; e += 256) sD[e / (P * P)][e % (P * P)] = d.D[e];
-  __syncthreads();
-  const double* Dx1 = sD[0];
-  const double* Dy1 = sD[1];
-  const double* Dxx = sD[2];
-  const double* Dyy = sD[3];
-  const double2* BI = reinterpret_cast<const double2*>(d.BI) + h * (long)N * N;
-  auto ainv = [&](int r, int q) { return BI[(NB + r) + (long)N * (NB + q)].x; };
-
-  if (tid < NI) {
-    // X[r, b] = sum_{q on b's line} Ainv[r, q] A_ib[q, b]
-    const int r = tid;
-    double acc[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] = 0.0;
-#pragma unroll
-    for (int j = 0; j < m; ++j)
-#pragma unroll
-      for (int i = 0; i < m; ++i) {
-        const double a = ainv(r, i + m * j);
-        acc[i] = fma(a, -Dyy[(j + 1) + P * 0], acc[i]);                    // S_i
-        acc[2 * m + i] = fma(a, -Dyy[(j + 1) + P * (P - 1)], acc[2 * m + i]);  // N_i
-        acc[m + j] = fma(a, -Dxx[(i + 1) + P * (P - 1)], acc[m + j]);      // E_j
-        acc[3 * m + j] = fma(a, -Dxx[(i + 1) + P * 0], acc[3 * m + j]);    // W_j
-      }
-    double* X = d.X + h * (long)NI * NB;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      X[r + (long)NI * b] = acc[b];
-      sX[r + NI * b] = acc[b];
-    }
-  } else {
-    // idle threads of the X phase
-  }
-  if (tid < NI) {
-    // Z[b, c] = sum_{q on b's line} N_i[b, q] Ainv[q, c]
-    const int c = tid;
-    double acc[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] = 0.0;
-#pragma unroll
-    for (int j = 0; j < m; ++j)
-#pragma unroll
-      for (int i = 0; i < m; ++i) {
-        const double a = ainv(i + m * j, c);
-        acc[i] = fma(-Dy1[0 + P * (j + 1)], a, acc[i]);                        // S_i: -D_y
-        acc[2 * m + i] = fma(Dy1[(P - 1) + P * (j + 1)], a, acc[2 * m + i]);   // N_i: +D_y
-        acc[m + j] = fma(Dx1[(P - 1) + P * (i + 1)], a, acc[m + j]);           // E_j: +D_x
-        acc[3 * m + j] = fma(-Dx1[0 + P * (i + 1)], a, acc[3 * m + j]);        // W_j: -D_x
-      }
-    double* Z = d.Z + h * (long)NB * NI;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) Z[b + (long)NB * c] = acc[b];
+  const double2* tab = reinterpret_cast<const double2*>(d.tab);
+  const TabIdx T{m};
+  for (int e = tid; e < m; e += 256) {
+    sw[0][e] = tab[T.wS() + e];
+    sw[1][e] = tab[T.wN() + e];
+    sw[2][e] = tab[T.wW() + e];
+    sw[3][e] = tab[T.wE() + e];
   }
   __syncthreads();
-  // S = N_b + i eta I - N_i X
-  double2* S = reinterpret_cast<double2*>(d.S) + h * (long)NB * NB;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int b = e % NB, bp = e / NB;
-    const int side = b / m, t = b % m;  // 0 S, 1 E, 2 N, 3 W; t = position on the side
-    double s = 0.0, nb = 0.0;
-    if (side == 0) {          // S_t: -D_y row 0 along column i = t+1
-      for (int j = 0; j < m; ++j) s = fma(-Dy1[0 + P * (j + 1)], sX[(t + m * j) + NI * bp], s);
-      if (bp == b) nb = -Dy1[0];
-      if (bp == 2 * m + t) nb = -Dy1[0 + P * (P - 1)];
-    } else if (side == 1) {   // E_t: +D_x row p-1 along row j = t+1
-      for (int i = 0; i < m; ++i) s = fma(Dx1[(P - 1) + P * (i + 1)], sX[(i + m * t) + NI * bp], s);
-      if (bp == b) nb = Dx1[(P - 1) + P * (P - 1)];
-      if (bp == 3 * m + t) nb = Dx1[(P - 1) + P * 0];
-    } else if (side == 2) {   // N_t: +D_y row p-1 along column i = t+1
-      for (int j = 0; j < m; ++j) s = fma(Dy1[(P - 1) + P * (j + 1)], sX[(t + m * j) + NI * bp], s);
-      if (bp == b) nb = Dy1[(P - 1) + P * (P - 1)];
-      if (bp == t) nb = Dy1[(P - 1) + P * 0];
-    } else {                  // W_t: -D_x row 0 along row j = t+1
-      for (int i = 0; i < m; ++i) s = fma(-Dx1[0 + P * (i + 1)], sX[(i + m * t) + NI * bp], s);
-      if (bp == b) nb = -Dx1[0];
-      if (bp == m + t) nb = -Dx1[0 + P * (P - 1)];
+  const int r = tid;
+  if (r >= NI) return;
+  double2* BI = reinterpret_cast<double2*>(d.BI) + h * (long)N * N;
+  const double2* Yr = BI + NB + r;  // row r of Y_i: Yr[N * (NB + col)]
+  double2 accW[m], accE[m];
+#pragma unroll
+  for (int j = 0; j < m; ++j) {
+    accW[j] = cmk(0, 0);
+    accE[j] = cmk(0, 0);
+  }
+#pragma unroll 1
+  for (int i = 0; i < m; ++i) {
+    double2 accS = cmk(0, 0), accN = cmk(0, 0);
+    const double2 ww = sw[2][i], we = sw[3][i];
+#pragma unroll
+    for (int j = 0; j < m; ++j) {
+      const double2 y = Yr[(long)N * (NB + j * m + i)];
+      accS = cfma(y, sw[0][j], accS);
+      accN = cfma(y, sw[1][j], accN);
+      accW[j] = cfma(y, ww, accW[j]);
+      accE[j] = cfma(y, we, accE[j]);
     }
-    double re = nb - s, im = 0.0;
-    if (bp == b) {  // + i eta
-      re -= d.eta_im;
-      im += d.eta_re;
-    }
-    S[b + (long)NB * bp] = make_double2(re, im);
+    BI[(NB + r) + (long)N * i] = cmk(-accS.x, -accS.y);              // S_i
+    BI[(NB + r) + (long)N * (2 * m + i)] = cmk(-accN.x, -accN.y);    // N_i
+  }
+#pragma unroll
+  for (int j = 0; j < m; ++j) {
+    BI[(NB + r) + (long)N * (m + j)] = cmk(-accE[j].x, -accE[j].y);      // E_j
+    BI[(NB + r) + (long)N * (3 * m + j)] = cmk(-accW[j].x, -accW[j].y);  // W_j
   }
 }
 
-__global__ void leaf_r_kernel(int nleaf, int n, int nb, double er, double ei, const double* BIg,
-                              double* Rg) {
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long tot = (long)nleaf * nb * nb;
-  if (e >= tot) return;
-  const long h = e / ((long)nb * nb);
-  const int loc = e % ((long)nb * nb);
-  const int i = loc % nb, j = loc / nb;
-  const double2 psi = reinterpret_cast<const double2*>(BIg)[h * (long)n * n + i + (long)n * j];
+// Boundary rows of [Psi | Y] = [F_bb^{-1} | 0] - F_bb^{-1} F_bi [Psi_i | Y_i]: the row of
+// S_i combines the interior rows of grid column i with sS, N_i with sN, the rows of
+// E_j / W_j combine grid row j with oE / oW; plus the 2 x 2 inverses on the boundary
+// columns.  Then R = I - 2 i eta Psi_b.  Columns are staged through LDS in chunks.
+template <int P>
+__global__ __launch_bounds__(256) void leaf_bnd_kernel(LeafDesc d) {
+  constexpr int m = P - 2, NI = m * m, NB = 4 * m, N = P * P - 4;
+  constexpr int CC = 16;  // columns per chunk
+  __shared__ double2 sI[CC][NI];
+  __shared__ double2 sc[4][m];
+  __shared__ double2 sb[8];
+  const int tid = threadIdx.x;
+  const long h = blockIdx.x;
+  const double2* tab = reinterpret_cast<const double2*>(d.tab);
+  const TabIdx T{m};
+  for (int e = tid; e < m; e += 256) {
+    sc[0][e] = tab[T.sS() + e];
+    sc[1][e] = tab[T.sN() + e];
+    sc[2][e] = tab[T.oW() + e];
+    sc[3][e] = tab[T.oE() + e];
+  }
+  if (tid < 4) {
+    sb[tid] = tab[T.by() + tid];      // (S, N) pair: b11 b12 b21 b22
+    sb[4 + tid] = tab[T.bx() + tid];  // (W, E) pair: c11 c12 c21 c22
+  }
+  double2* BI = reinterpret_cast<double2*>(d.BI) + h * (long)N * N;
+  double2* R = reinterpret_cast<double2*>(d.R) + h * (long)NB * NB;
   // -2 i eta = (2 eta_im, -2 eta_re)
-  double2 v = cmul(cmk(2.0 * ei, -2.0 * er), psi);
-  if (i == j) v.x += 1.0;
-  reinterpret_cast<double2*>(Rg)[e] = v;
+  const double2 m2ie = cmk(2.0 * d.eta_im, -2.0 * d.eta_re);
+  for (int c0 = 0; c0 < N; c0 += CC) {
+    const int cw = (N - c0) < CC ? (N - c0) : CC;
+    __syncthreads();
+    for (int e = tid; e < NI * cw; e += 256) {
+      const int row = e % NI, col = e / NI;
+      sI[col][row] = BI[(NB + row) + (long)N * (c0 + col)];
+    }
+    __syncthreads();
+    for (int e = tid; e < NB * cw; e += 256) {
+      const int b = e % NB, col = e / NB;
+      const int gcol = c0 + col;
+      const int side = b / m, t = b % m;  // 0 S, 1 E, 2 N, 3 W
+      double2 acc = cmk(0, 0);
+      double2 base = cmk(0, 0);
+      if (side == 0 || side == 2) {       // grid column i = t: interior rows (t, l)
+        const double2* co = sc[side == 0 ? 0 : 1];
+#pragma unroll
+        for (int l = 0; l < m; ++l) acc = cfma(co[l], sI[col][l * m + t], acc);
+        const int rs = (side == 0) ? 0 : 2;  // b11 b12 | b21 b22
+        if (gcol == t) base = sb[rs];                // column S_t
+        else if (gcol == 2 * m + t) base = sb[rs + 1];  // column N_t
+      } else {                            // grid row j = t: interior rows (k, t)
+        const double2* co = sc[side == 3 ? 2 : 3];
+#pragma unroll
+        for (int k = 0; k < m; ++k) acc = cfma(co[k], sI[col][t * m + k], acc);
+        const int rs = (side == 3) ? 4 : 6;  // c11 c12 | c21 c22
+        if (gcol == 3 * m + t) base = sb[rs];        // column W_t
+        else if (gcol == m + t) base = sb[rs + 1];   // column E_t
+      }
+      const double2 v = csub(base, acc);
+      BI[b + (long)N * gcol] = v;
+      if (gcol < NB) {
+        double2 rv = cmul(m2ie, v);
+        if (gcol == b) rv.x += 1.0;
+        R[b + (long)NB * gcol] = rv;
+      }
+    }
+  }
 }
 
-template <int P> void launch_inv(const LeafDesc& d, hipStream_t st) {
-  hipLaunchKernelGGL(leaf_inv_kernel<P>, dim3(d.nleaf), dim3(LeafInvCfg<P>::NT), 0, st, d);
+// register-resident for p <= 13; the scratch copy for larger p
+template <int P> constexpr bool leaf_resident() { return P <= 13; }
+
+template <int P> void launch_sinv(const LeafDesc& d, hipStream_t st) {
+  constexpr bool RES = leaf_resident<P>();
+  if (!RES && !d.Mg) throw Error(1, "leaf: scratch copy of S_i missing");
+  hipLaunchKernelGGL((leaf_sinv_kernel<P, RES>), dim3(d.nleaf), dim3(LeafCfg<P>::NT), 0, st, d);
 }
-template <int P> void launch_xzs(const LeafDesc& d, hipStream_t st) {
-  hipLaunchKernelGGL(leaf_xzs_kernel<P>, dim3(d.nleaf), dim3(256), 0, st, d);
+template <int P> void launch_psi_i(const LeafDesc& d, hipStream_t st) {
+  hipLaunchKernelGGL(leaf_psi_i_kernel<P>, dim3(d.nleaf), dim3(256), 0, st, d);
+}
+template <int P> void launch_bnd(const LeafDesc& d, hipStream_t st) {
+  hipLaunchKernelGGL(leaf_bnd_kernel<P>, dim3(d.nleaf), dim3(256), 0, st, d);
 }
 
 #define HPS_P_SWITCH(FN, p, ...)                   \
@@ -406,23 +491,32 @@ template <int P> void launch_xzs(const LeafDesc& d, hipStream_t st) {
 
 }  // namespace
 
-void leaf_inverse_interior(const LeafDesc& d, hipStream_t st) {
+size_t leaf_scratch_bytes(int p, long nleaf) {
+  if (p <= 13) return 0;
+  const long ni = (long)(p - 2) * (p - 2);
+  return (size_t)nleaf * ni * ni * 16;
+}
+
+int leaf_table_len(int p) {
+  const int m = p - 2;
+  return 2 * m * m + 8 * m + 8;
+}
+
+void leaf_interior_inverse(const LeafDesc& d, hipStream_t st) {
   if (d.nleaf <= 0) return;
-  HPS_P_SWITCH(launch_inv, d.p, d, st);
+  HPS_P_SWITCH(launch_sinv, d.p, d, st);
   HPS_LAUNCH_CHECK();
 }
 
-void leaf_xzs(const LeafDesc& d, hipStream_t st) {
+void leaf_psi_interior(const LeafDesc& d, hipStream_t st) {
   if (d.nleaf <= 0) return;
-  HPS_P_SWITCH(launch_xzs, d.p, d, st);
+  HPS_P_SWITCH(launch_psi_i, d.p, d, st);
   HPS_LAUNCH_CHECK();
 }
 
-void leaf_r_from_psib(const LeafDesc& d, hipStream_t st) {
-  const int n = d.p * d.p - 4, nb = 4 * d.p - 8;
-  const long tot = (long)d.nleaf * nb * nb;
-  hipLaunchKernelGGL(leaf_r_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, st, d.nleaf, n, nb,
-                     d.eta_re, d.eta_im, d.BI, d.R);
+void leaf_boundary_rows(const LeafDesc& d, hipStream_t st) {
+  if (d.nleaf <= 0) return;
+  HPS_P_SWITCH(launch_bnd, d.p, d, st);
   HPS_LAUNCH_CHECK();
 }
 

@@ -87,7 +87,8 @@ __global__ void leaf_h_kernel(int nleaf, int n, int nb, int nrhs, double er, dou
 }
 
 __global__ void up_gather_kernel(MergeLevelDesc d, int nrhs, const double2* hc, double2* h3a,
-                                 double2* v, double2* ttb, double2* hp) {
+                                 double2* v, double2* ttb, double2* hp, const double2* jmp,
+                                 long ldj, const int* ja, const int* jb) {
   const long q = blockIdx.y;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const int n1 = d.n1, n2 = d.n2, n3 = d.n3, nbc = d.nbc, nbp = d.nbp;
@@ -97,8 +98,13 @@ __global__ void up_gather_kernel(MergeLevelDesc d, int nrhs, const double2* hc, 
   const double2* ha = hc + (2 * q) * (long)nbc * nrhs;
   const double2* hb = hc + (2 * q + 1) * (long)nbc * nrhs;
   if (k < n3) {
-    const double2 a = ha[d.i3a[k] + (long)nbc * r];
-    const double2 bb = hb[d.i3b[k] + (long)nbc * r];
+    double2 a = ha[d.i3a[k] + (long)nbc * r];
+    double2 bb = hb[d.i3b[k] + (long)nbc * r];
+    if (jmp) {
+      const long qk = q * (long)n3 + k;
+      a = csub(a, jmp[(long)r * ldj + jb[qk]]);    // h3a - j2
+      bb = csub(bb, jmp[(long)r * ldj + ja[qk]]);  // h3b - j1
+    }
     const long o = q * (long)n3 * nrhs + k + (long)n3 * r;
     h3a[o] = a;
     ttb[o] = make_double2(-a.x, -a.y);
@@ -166,12 +172,14 @@ void leaf_h_from_u(int nleaf, int n, int nb, int nrhs, double er, double ei, con
 }
 
 void up_gather(const MergeLevelDesc& d, int nrhs, const double* hc, double* h3a, double* v,
-               double* ttb, double* hp, hipStream_t st) {
+               double* ttb, double* hp, const double* jmp, long ldj, const int* ja,
+               const int* jb, hipStream_t st) {
   long rows = (long)(d.n3 + d.n1 + d.n2) * nrhs;
   hipLaunchKernelGGL(up_gather_kernel, dim3(cdiv(rows, 256), d.nbox), dim3(256), 0, st, d, nrhs,
                      reinterpret_cast<const double2*>(hc), reinterpret_cast<double2*>(h3a),
                      reinterpret_cast<double2*>(v), reinterpret_cast<double2*>(ttb),
-                     reinterpret_cast<double2*>(hp));
+                     reinterpret_cast<double2*>(hp), reinterpret_cast<const double2*>(jmp), ldj,
+                     ja, jb);
   HPS_LAUNCH_CHECK();
 }
 

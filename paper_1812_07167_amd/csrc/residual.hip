@@ -1,0 +1,211 @@
+// FP64 residual of the global collocation system that the HPS factorization eliminates
+// (not in the paper: it drives the residual correction of a reduced-precision solve).
+//
+// Rows of leaf l (grid order), with u_l its n nodal values in the order [I_b, I_i]:
+//   interior node (i, j):   s - Ahat(I_i, I) u_l,  Ahat = -Dxx - Dyy - kappa^2 c   (Sec. 2.1)
+//   boundary node on dOmega: t - F u_l,             F = N + i eta on that side       (Sec. 2.1)
+//   node shared with leaf l': jump - (F_l u_l + G_l' u_l'),  G = N - i eta           (Sec. 2.2)
+// where N is the outward normal derivative of the leaf's own interpolant.  Matrix-free:
+// the Laplacian and normal derivatives are applied with the p x p differentiation
+// matrices on the leaf's full tensor grid; the four corners are never read (interior
+// rows and normal rows only touch nodes off the corners).
+//
+// One workgroup per (leaf, right-hand side): the leaf's values go into LDS on the full
+// p x p grid; interior rows and the leaf's own F on its boundary come from there, the
+// neighbour's G from the neighbour's values in global memory (p values per node).
+#include "kernels.hpp"
+
+namespace hps {
+namespace {
+
+// position of full-grid node (i, j) in a leaf vector [S, E, N, W, interior], m = p - 2;
+// -1 for the corners
+__device__ inline int node_pos(int i, int j, int p) {
+  const int m = p - 2;
+  const bool bi = (i == 0 || i == p - 1), bj = (j == 0 || j == p - 1);
+  if (bi && bj) return -1;
+  if (j == 0) return i - 1;                  // S
+  if (i == p - 1) return m + j - 1;          // E
+  if (j == p - 1) return 2 * m + i - 1;      // N
+  if (i == 0) return 3 * m + j - 1;          // W
+  return 4 * m + (j - 1) * m + (i - 1);      // interior
+}
+
+// Outward normal derivative, at edge node `idx` (1..p-2) of side `side` (0 S, 1 E, 2 N,
+// 3 W), of the leaf whose values are read by val(i, j).
+template <class V>
+__device__ inline double2 normal_deriv(int side, int idx, int p, const double* Dx1,
+                                       const double* Dy1, V val) {
+  double2 acc = cmk(0, 0);
+  for (int k = 0; k < p; ++k) {
+    double2 x;
+    double w;
+    switch (side) {
+      case 0: w = -Dy1[0 + p * k]; x = val(idx, k); break;             // -d/dy at y = y0
+      case 1: w = Dx1[(p - 1) + p * k]; x = val(k, idx); break;        // +d/dx at x = x1
+      case 2: w = Dy1[(p - 1) + p * k]; x = val(idx, k); break;        // +d/dy at y = y1
+      default: w = -Dx1[0 + p * k]; x = val(k, idx); break;            // -d/dx at x = x0
+    }
+    // corners carry zero weight in these sums only through the zero grid entries
+    acc.x += w * x.x;
+    acc.y += w * x.y;
+  }
+  return acc;
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void residual_kernel(ResidualDesc d) {
+  constexpr int M = P - 2, NB = 4 * M, NI = M * M, N = NB + NI;
+  __shared__ double2 Ug[P * P];
+  __shared__ double sD[4][P * P];
+  const int tid = threadIdx.x;
+  const int l = blockIdx.x, r = blockIdx.y;
+  const int nleaf = d.nx * d.ny;
+  const int ix = l % d.nx, iy = l / d.nx;
+  for (int e = tid; e < 4 * P * P; e += 256) sD[e / (P * P)][e % (P * P)] = d.D[e];
+  const double2* u = reinterpret_cast<const double2*>(d.u) + (long)r * nleaf * N;
+  const double2* ul = u + (long)l * N;
+  for (int e = tid; e < P * P; e += 256) {
+    const int i = e % P, j = e / P;
+    const int pos = node_pos(i, j, P);
+    Ug[e] = pos < 0 ? cmk(0, 0) : ul[pos];
+  }
+  __syncthreads();
+  const double* Dx1 = sD[0];
+  const double* Dy1 = sD[1];
+  const double* Dxx = sD[2];
+  const double* Dyy = sD[3];
+  const double k2 = d.kappa * d.kappa;
+  // interior rows
+  for (int e = tid; e < NI; e += 256) {
+    const int i = e % M + 1, j = e / M + 1;
+    double2 lap = cmk(0, 0);
+    for (int k = 0; k < P; ++k) {
+      const double2 a = Ug[k + P * j], b = Ug[i + P * k];
+      lap.x += Dxx[i + P * k] * a.x + Dyy[j + P * k] * b.x;
+      lap.y += Dxx[i + P * k] * a.y + Dyy[j + P * k] * b.y;
+    }
+    const double cc = k2 * d.c[(long)l * NI + e];
+    const double2 uc = Ug[i + P * j];
+    const double2 Au = cmk(-lap.x - cc * uc.x, -lap.y - cc * uc.y);
+    double2 b = cmk(0, 0);
+    if (d.s) b = reinterpret_cast<const double2*>(d.s)[(long)r * nleaf * NI + (long)l * NI + e];
+    reinterpret_cast<double2*>(d.rs)[r * d.rs_rhs + l * d.rs_leaf + e] = csub(b, Au);
+  }
+  // boundary rows
+  const int nt = 2 * (d.nx + d.ny) * M;
+  for (int e = tid; e < NB; e += 256) {
+    const int side = e / M, q = e % M, idx = q + 1;
+    auto own = [&](int i, int j) { return Ug[i + P * j]; };
+    const double2 nd = normal_deriv(side, idx, P, Dx1, Dy1, own);
+    const double2 ue = ul[e];
+    // F u = N u + i eta u
+    const double2 Fu = cmk(nd.x - d.eta_im * ue.x - d.eta_re * ue.y,
+                           nd.y + d.eta_re * ue.x - d.eta_im * ue.y);
+    // neighbour across this side, and the root-boundary position when there is none
+    int jx = ix, jy = iy, nside = 0, root = -1;
+    switch (side) {
+      case 0: jy = iy - 1; nside = 2; if (iy == 0) root = ix * M + q; break;
+      case 1: jx = ix + 1; nside = 3; if (ix == d.nx - 1) root = d.nx * M + iy * M + q; break;
+      case 2: jy = iy + 1; nside = 0; if (iy == d.ny - 1) root = (d.nx + d.ny) * M + ix * M + q; break;
+      default: jx = ix - 1; nside = 1; if (ix == 0) root = (2 * d.nx + d.ny) * M + iy * M + q; break;
+    }
+    double2* rb = reinterpret_cast<double2*>(d.rb) + r * d.rb_rhs + l * d.rb_leaf;
+    if (root >= 0) {
+      double2 tv = cmk(0, 0);
+      if (d.t) tv = reinterpret_cast<const double2*>(d.t)[(long)r * nt + root];
+      const double2 res = csub(tv, Fu);
+      if (d.rt) {
+        reinterpret_cast<double2*>(d.rt)[r * d.rt_rhs + root] = res;
+        rb[e] = cmk(0, 0);
+      } else {
+        rb[e] = res;
+      }
+    } else {
+      const double2* un = u + (long)(jy * d.nx + jx) * N;
+      auto nbr = [&](int i, int j) {
+        const int pos = node_pos(i, j, P);
+        return pos < 0 ? cmk(0, 0) : un[pos];
+      };
+      const double2 ndn = normal_deriv(nside, idx, P, Dx1, Dy1, nbr);
+      const double2 un_e = un[nside * M + q];
+      // G u' = N' u' - i eta u'
+      const double2 Gu = cmk(ndn.x + d.eta_im * un_e.x + d.eta_re * un_e.y,
+                             ndn.y - d.eta_re * un_e.x + d.eta_im * un_e.y);
+      double2 jv = cmk(0, 0);
+      if (d.jmp) jv = reinterpret_cast<const double2*>(d.jmp)[(long)r * nleaf * NB + (long)l * NB + e];
+      rb[e] = csub(jv, cadd(Fu, Gu));
+    }
+  }
+}
+
+__global__ void axpy_kernel(long n, const double2* x, double2* y) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) y[e] = cadd(y[e], x[e]);
+}
+
+// partial sums of |x|^2 and |y|^2 per block of one right-hand side (fixed order)
+__global__ __launch_bounds__(256) void norms_kernel(long len, const double2* x, const double2* y,
+                                                    double* part) {
+  __shared__ double sx[256], sy[256];
+  const int r = blockIdx.y;
+  const long base = (long)r * len;
+  double ax = 0, ay = 0;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < len; e += (long)gridDim.x * 256) {
+    const double2 a = x[base + e], b = y[base + e];
+    ax += a.x * a.x + a.y * a.y;
+    ay += b.x * b.x + b.y * b.y;
+  }
+  sx[threadIdx.x] = ax;
+  sy[threadIdx.x] = ay;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      sx[threadIdx.x] += sx[threadIdx.x + w];
+      sy[threadIdx.x] += sy[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * ((long)r * gridDim.x + blockIdx.x)] = sx[0];
+    part[2 * ((long)r * gridDim.x + blockIdx.x) + 1] = sy[0];
+  }
+}
+
+}  // namespace
+
+void residual(const ResidualDesc& d, int nrhs, hipStream_t st) {
+  if (nrhs <= 0) return;
+  if (nrhs > 65535) throw Error(1, "residual: too many right-hand sides");
+  const dim3 grid(d.nx * d.ny, nrhs);
+  switch (d.p) {
+#define HPS_RES_CASE(PP) \
+  case PP: hipLaunchKernelGGL(residual_kernel<PP>, grid, dim3(256), 0, st, d); break;
+    HPS_RES_CASE(4) HPS_RES_CASE(5) HPS_RES_CASE(6) HPS_RES_CASE(7) HPS_RES_CASE(8)
+    HPS_RES_CASE(9) HPS_RES_CASE(10) HPS_RES_CASE(11) HPS_RES_CASE(12) HPS_RES_CASE(13)
+    HPS_RES_CASE(14) HPS_RES_CASE(15) HPS_RES_CASE(16)
+#undef HPS_RES_CASE
+    default: throw Error(1, "residual: unsupported p");
+  }
+  HPS_LAUNCH_CHECK();
+}
+
+void axpy(long n, const double* x, double* y, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(axpy_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, n,
+                     reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y));
+  HPS_LAUNCH_CHECK();
+}
+
+int norms_blocks() { return 64; }
+
+void norms_partial(long len, int nrhs, const double* x, const double* y, double* part,
+                   hipStream_t st) {
+  if (len <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(norms_kernel, dim3(norms_blocks(), nrhs), dim3(256), 0, st, len,
+                     reinterpret_cast<const double2*>(x), reinterpret_cast<const double2*>(y),
+                     part);
+  HPS_LAUNCH_CHECK();
+}
+
+}  // namespace hps

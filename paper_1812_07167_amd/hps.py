@@ -21,9 +21,10 @@ OP_PSI, OP_Y, OP_R, OP_WINV, OP_PHI_A, OP_PHI_B, OP_R33A, OP_R33B, OP_R13A, OP_R
 
 EXPORTS = [
     "hps_last_error", "hps_version", "hps_default_opts", "hps_nodes", "hps_build",
-    "hps_solve", "hps_factor_query", "hps_factor_get", "hps_factor_box", "hps_stage_times",
-    "hps_free",
+    "hps_solve", "hps_solve_jumps", "hps_residual", "hps_last_solve_info", "hps_factor_query",
+    "hps_factor_get", "hps_factor_box", "hps_stage_times", "hps_free",
 ]
+HPS_PREC_C128, HPS_PREC_MIXED = 0, 1
 
 
 class HPSError(RuntimeError):
@@ -39,7 +40,12 @@ class Domain(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("keep_all_R", C.c_int32), ("store_root_R", C.c_int32),
-                ("profile", C.c_int32), ("stream", C.c_void_p)]
+                ("profile", C.c_int32), ("stream", C.c_void_p), ("fp64_top_levels", C.c_int32),
+                ("refine_max_iter", C.c_int32), ("refine_tol", C.c_double)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("correction", C.c_double)]
 
 
 class StageTime(C.Structure):
@@ -78,14 +84,18 @@ def load(path: str = LIB_PATH):
     lib.hps_nodes.argtypes = [C.POINTER(Domain), I32, P, P, P, P]
     lib.hps_build.argtypes = [C.POINTER(Domain), I32, D, D, D, P, C.POINTER(Opts), C.POINTER(P)]
     lib.hps_solve.argtypes = [P, I32, P, P, P]
+    lib.hps_solve_jumps.argtypes = [P, I32, P, P, P, P]
+    lib.hps_residual.argtypes = [P, I32, P, P, P, P, P]
+    lib.hps_last_solve_info.argtypes = [P, C.POINTER(SolveInfo)]
     lib.hps_factor_query.argtypes = [P, C.POINTER(FactorInfo)]
     lib.hps_factor_get.argtypes = [P, I32, I32, I32, P, I64, C.POINTER(I32), C.POINTER(I32)]
     lib.hps_factor_box.argtypes = [P, I32, I32] + [C.POINTER(I32)] * 4
     lib.hps_stage_times.argtypes = [P, I32, C.POINTER(StageTime), I32, C.POINTER(I32)]
     lib.hps_free.argtypes = [P]
     lib.hps_free.restype = None
-    for name in ["hps_nodes", "hps_build", "hps_solve", "hps_factor_query", "hps_factor_get",
-                 "hps_factor_box", "hps_stage_times"]:
+    for name in ["hps_nodes", "hps_build", "hps_solve", "hps_solve_jumps", "hps_residual",
+                 "hps_last_solve_info", "hps_factor_query", "hps_factor_get", "hps_factor_box",
+                 "hps_stage_times"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -170,6 +180,12 @@ class Factor:
         return [(buf[i].name.decode(), buf[i].launches, buf[i].ms, buf[i].flops, buf[i].bytes)
                 for i in range(n.value)]
 
+    def last_solve_info(self):
+        """(iterations, converged, last relative correction) of the most recent solve."""
+        info = SolveInfo()
+        _check(load().hps_last_solve_info(self.h, C.byref(info)))
+        return info.iterations, bool(info.converged), info.correction
+
     def box(self, level, box):
         v = [C.c_int32() for _ in range(4)]
         _check(load().hps_factor_box(self.h, level, box, *[C.byref(x) for x in v]))
@@ -177,8 +193,10 @@ class Factor:
 
 
 def hps_build(dom: Domain, p: int, kappa: float, eta: complex, c_interior, keep_all_R=False,
-              store_root_R=True, stream=None, profile=False) -> Factor:
-    """c_interior: float64 device tensor [nx*ny*(p-2)^2].  Returns a Factor."""
+              store_root_R=True, stream=None, profile=False, precision=HPS_PREC_C128,
+              fp64_top_levels=None, refine_max_iter=None, refine_tol=None) -> Factor:
+    """c_interior: float64 device tensor [nx*ny*(p-2)^2].  Returns a Factor.  Options left
+    at None keep the library's defaults."""
     import torch
     lib = load()
     opts = Opts()
@@ -186,6 +204,13 @@ def hps_build(dom: Domain, p: int, kappa: float, eta: complex, c_interior, keep_
     opts.keep_all_R = int(keep_all_R)
     opts.store_root_R = int(store_root_R)
     opts.profile = int(profile)
+    opts.precision = int(precision)
+    if fp64_top_levels is not None:
+        opts.fp64_top_levels = int(fp64_top_levels)
+    if refine_max_iter is not None:
+        opts.refine_max_iter = int(refine_max_iter)
+    if refine_tol is not None:
+        opts.refine_tol = float(refine_tol)
     st = stream if stream is not None else torch.cuda.current_stream()
     opts.stream = C.c_void_p(st.cuda_stream)
     out = C.c_void_p()
@@ -206,3 +231,32 @@ def hps_solve(f: Factor, t, s=None, u=None):
     _check(load().hps_solve(f.h, nrhs, sp, _dev_ptr(t, "torch.complex128"),
                             _dev_ptr(u, "torch.complex128")))
     return u
+
+
+def hps_solve_jumps(f: Factor, t, s=None, jumps=None, u=None):
+    """As hps_solve, with right-hand sides jumps [nrhs, nleaf, n_b] (complex128 device
+    tensor or None) on the shared-edge rows of the global system."""
+    import torch
+    nrhs = t.shape[0]
+    if u is None:
+        u = torch.empty((nrhs, f.info.n_leaf_nodes), dtype=torch.complex128, device=t.device)
+    sp = _dev_ptr(s, "torch.complex128") if s is not None else None
+    jp = _dev_ptr(jumps, "torch.complex128") if jumps is not None else None
+    _check(load().hps_solve_jumps(f.h, nrhs, sp, _dev_ptr(t, "torch.complex128"), jp,
+                                  _dev_ptr(u, "torch.complex128")))
+    return u
+
+
+def hps_residual(f: Factor, u, t=None, s=None, jumps=None, r=None):
+    """FP64 residual of the global collocation system at u [nrhs, n_leaf_nodes]; returns r
+    of the same shape (per leaf: n_b boundary rows, then n_i interior rows)."""
+    import torch
+    nrhs = u.shape[0]
+    if r is None:
+        r = torch.empty_like(u)
+    sp = _dev_ptr(s, "torch.complex128") if s is not None else None
+    tp = _dev_ptr(t, "torch.complex128") if t is not None else None
+    jp = _dev_ptr(jumps, "torch.complex128") if jumps is not None else None
+    _check(load().hps_residual(f.h, nrhs, sp, tp, jp, _dev_ptr(u, "torch.complex128"),
+                               _dev_ptr(r, "torch.complex128")))
+    return r

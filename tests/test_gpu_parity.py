@@ -122,6 +122,22 @@ def test_solve_random_rhs(nx, ny, p, kappa, eta, box, nrhs):
     f.free()
 
 
+@pytest.mark.parametrize("nx,ny,p,kappa,seed", [(4, 4, 8, 17.0, 8), (8, 8, 8, 80.0, 1),
+                                                 (8, 8, 12, 80.0, 2), (8, 8, 16, 80.0, 3),
+                                                 (4, 8, 14, 60.0, 4), (8, 4, 15, 70.0, 5)])
+def test_leaves_of_several_wavelengths(nx, ny, p, kappa, seed):
+    """Leaves of a few wavelengths (kappa h up to 10 with c in [0.5, 1.5]): kappa^2 c
+    crosses eigenvalues of the leaves' Dirichlet Laplacian, where a leaf's interior
+    block alone is (nearly) singular; the impedance rows keep the leaf system well
+    posed and the GPU path must still match the oracle.  Covers the register-resident
+    (p <= 13) and the scratch-copy (p >= 14) leaf inverses."""
+    _say("several wavelengths", nx, ny, p, kappa)
+    cs = Case(nx, ny, p, kappa, seed=seed, nrhs=2)
+    f = cs.gpu_build()
+    assert rel(cs.gpu_solve(f), cs.oracle_solve(cs.oracle_build())) < TOL
+    f.free()
+
+
 def test_config1_plane_wave():
     """4x4 leaves, p = 8, kappa = eta = 20, c = 1, s = 0, plane wave with seeded angle."""
     _say("config 1")
