@@ -119,6 +119,7 @@ struct LevelPlan {
   const int* di3b = nullptr; const int* dja = nullptr; const int* djb = nullptr;
   // stored operators of the level (Sec. 2.4), slices of the factor's arena
   View Winv, R33a, R33b, R13a, R23b, PhiA, PhiB;
+  bool c64 = false;  // the level's operators (and its R) are complex64
 };
 
 struct Geo { int ix0, iy0, wx, wy; };
@@ -219,7 +220,10 @@ struct hps_factor {
   std::vector<int> leaf_grid;              // tree-ordered leaf -> grid index
   hps::DevBuf dleaf_grid, dxoff, duoff, dD, dLT;
   hps::DevBuf ops;                         // arena: [Psi | Y] of every leaf + merge operators
-  hps::View BI;                            // [nleaf][n*n] complex: [Psi | Y]
+  hps::View BI;                            // [nleaf][n*n] complex: [Psi | Y] (complex128;
+                                           // during the build only in mixed precision)
+  hps::View BI32;                          // mixed precision: complex64 copy of [Psi | Y]
+  bool mixed = false;                      // opts.precision == HPS_PREC_MIXED
   hps::DevBuf rbuf[2];                     // ping-pong ItI operators (level l uses l % 2)
   std::vector<hps::DevBuf> rkeep;          // every level's R when opts.keep_all_R
   std::vector<hps::View> R;                // per level ItI operators (L+1 entries)
@@ -545,6 +549,9 @@ struct BuildScratch {
   std::vector<long> info_off;  // per level offset into info
 };
 
+// bytes of one complex entry of level l's operators and R (the leaves' R is complex128)
+size_t cbytes(const hps_factor& f, int l) { return (l < f.L && f.lv[l].c64) ? 8 : 16; }
+
 bool level_forms_R(const hps_factor& f, int l) {
   return l == f.L || l > 0 || f.opts.store_root_R;
 }
@@ -552,7 +559,7 @@ bool level_forms_R(const hps_factor& f, int l) {
 size_t level_R_bytes(const hps_factor& f, int l) {
   if (l == f.L) return (size_t)f.nleaf * f.nb * f.nb * 16;
   const LevelPlan& P = f.lv[l];
-  return (size_t)P.nbox * P.nbp * P.nbp * 16;
+  return (size_t)P.nbox * P.nbp * P.nbp * cbytes(f, l);
 }
 
 void plan_memory(hps_factor& f, BuildScratch& sc) {
@@ -560,16 +567,18 @@ void plan_memory(hps_factor& f, BuildScratch& sc) {
   for (int pass = 0; pass < 2; ++pass) {
     Carver c;
     c.base = pass ? static_cast<char*>(f.ops.p) : nullptr;
-    f.BI = c.take((size_t)nl * n * n * 16);
+    if (f.mixed) f.BI32 = c.take((size_t)nl * n * n * 8);
+    else f.BI = c.take((size_t)nl * n * n * 16);
     for (auto& P : f.lv) {
       const size_t nbox = P.nbox, n1 = P.n1, n2 = P.n2, n3 = P.n3, nbp = P.nbp;
-      P.Winv = c.take(nbox * n3 * n3 * 16);
-      P.R33a = c.take(nbox * n3 * n3 * 16);
-      P.R33b = c.take(nbox * n3 * n3 * 16);
-      P.R13a = c.take(nbox * n1 * n3 * 16);
-      P.R23b = c.take(nbox * n2 * n3 * 16);
-      P.PhiA = c.take(nbox * n3 * nbp * 16);
-      P.PhiB = c.take(nbox * n3 * nbp * 16);
+      const size_t e = P.c64 ? 8 : 16;
+      P.Winv = c.take(nbox * n3 * n3 * e);
+      P.R33a = c.take(nbox * n3 * n3 * e);
+      P.R33b = c.take(nbox * n3 * n3 * e);
+      P.R13a = c.take(nbox * n1 * n3 * e);
+      P.R23b = c.take(nbox * n2 * n3 * e);
+      P.PhiA = c.take(nbox * n3 * nbp * e);
+      P.PhiB = c.take(nbox * n3 * nbp * e);
     }
     if (pass == 0) f.ops.alloc(c.used);
   }
@@ -599,9 +608,10 @@ void plan_memory(hps_factor& f, BuildScratch& sc) {
   size_t level_bytes = leaf_scratch_bytes(f.p, nl);
   for (auto& P : f.lv) {
     Carver c;
-    c.take((size_t)P.nbox * P.n3 * P.n1 * 16);
-    c.take((size_t)P.nbox * P.n3 * P.nbp * 16);
-    c.take(zinv_workspace_bytes(P.n3, P.nbox));
+    const size_t e = P.c64 ? 8 : 16;
+    c.take((size_t)P.nbox * P.n3 * P.n1 * e);
+    c.take((size_t)P.nbox * P.n3 * P.nbp * e);
+    c.take(zinv_workspace_bytes(P.n3, P.nbox, P.c64));
     level_bytes = std::max(level_bytes, c.used);
   }
   long ninfo = 2 * nl;
@@ -610,19 +620,27 @@ void plan_memory(hps_factor& f, BuildScratch& sc) {
     sc.info_off[l] = ninfo;
     ninfo += f.lv[l].nbox;
   }
-  const size_t shared = level_bytes;
-  sc.buf.alloc(shared + (size_t)ninfo * sizeof(int) + 256);
+  // mixed precision: the complex128 [Psi | Y] of the leaf stage lives in the scratch
+  // until its complex64 copy is made
+  const size_t shared = (level_bytes + 255) & ~size_t(255);
+  const size_t bi64 = f.mixed ? (size_t)nl * n * n * 16 : 0;
+  sc.buf.alloc(shared + bi64 + (size_t)ninfo * sizeof(int) + 256);
   char* base = static_cast<char*>(sc.buf.p);
-  sc.info.p = base + ((shared + 255) & ~size_t(255));
+  if (f.mixed) {
+    f.BI.p = base + shared;
+    f.BI.bytes = bi64;
+  }
+  sc.info.p = base + shared + ((bi64 + 255) & ~size_t(255));
   sc.info.bytes = (size_t)ninfo * sizeof(int);
 }
 
 void level_scratch(const LevelPlan& P, BuildScratch& sc) {
   Carver c;
   c.base = static_cast<char*>(sc.buf.p);
-  sc.R31a = c.take((size_t)P.nbox * P.n3 * P.n1 * 16);
-  sc.T = c.take((size_t)P.nbox * P.n3 * P.nbp * 16);
-  sc.work = c.take(zinv_workspace_bytes(P.n3, P.nbox));
+  const size_t e = P.c64 ? 8 : 16;
+  sc.R31a = c.take((size_t)P.nbox * P.n3 * P.n1 * e);
+  sc.T = c.take((size_t)P.nbox * P.n3 * P.nbp * e);
+  sc.work = c.take(zinv_workspace_bytes(P.n3, P.nbox, P.c64));
 }
 
 // ------------------------------------------------------------------ build
@@ -674,6 +692,9 @@ void build_level(hps_factor& f, int l, BuildScratch& sc) {
   int* info = sc.info.i() + sc.info_off[l];
 
   MergeLevelDesc d = level_desc(f, P);
+  d.c64 = P.c64;
+  d.child_c64 = (l + 1 < f.L) && f.lv[l + 1].c64;
+  const double ez = P.c64 ? 0.5 : 1.0;  // doubles per complex entry / 2
   d.Rc = f.R[l + 1].d();
   d.Rp = form_R ? f.R[l].d() : nullptr;
   d.R33a = P.R33a.d(); d.R33b = P.R33b.d(); d.R13a = P.R13a.d(); d.R23b = P.R23b.d();
@@ -689,11 +710,11 @@ void build_level(hps_factor& f, int l, BuildScratch& sc) {
     Stage s(f.build_prof, ename.c_str(), 0.0,
             nbox * (2.0 * nbc * nbc * 16 + (form_R ? nbp * nbp * 16.0 : 0.0) +
                     2.0 * n3 * nbp * 16 + n3 * n3 * 16.0));
-    if (form_R) fill_zero(d.Rp, 2 * nbox * nbp * nbp, st);
-    fill_zero(d.PhiB, 2 * nbox * n3 * nbp, st);
+    if (form_R) fill_zero(d.Rp, (long)(2 * ez * nbox * nbp * nbp), st);
+    fill_zero(d.PhiB, (long)(2 * ez * nbox * n3 * nbp), st);
     merge_extract(d, st);
     // W = I - R33b R33a   (into the Winv buffer, inverted in place below)
-    fill_identity(P.Winv.d(), (int)n3, n3 * n3, (int)nbox, st);
+    fill_identity(P.Winv.d(), (int)n3, n3 * n3, (int)nbox, st, P.c64);
   }
   GemmDesc g;
   g.M = n3; g.N = n3; g.K = n3; g.batch = nbox;
@@ -701,6 +722,7 @@ void build_level(hps_factor& f, int l, BuildScratch& sc) {
   g.B = P.R33a.d(); g.ldb = n3; g.sB = n3 * n3;
   g.C = P.Winv.d(); g.ldc = n3; g.sC = n3 * n3;
   g.alpha = -1.0; g.beta = 1.0;
+  g.c64 = P.c64;
   timed_gemm(f.build_prof, gname, g, st);
   // T[:, perm(I1)] = R33b R31a  (T[:, perm(I2)] = -R32b was written by the extract)
   g = GemmDesc();
@@ -709,12 +731,13 @@ void build_level(hps_factor& f, int l, BuildScratch& sc) {
   g.B = sc.R31a.d(); g.ldb = n3; g.sB = n3 * n1;
   g.C = sc.T.d(); g.ldc = n3; g.sC = n3 * nbp; g.ccol = P.dperm;
   g.alpha = 1.0; g.beta = 0.0;
+  g.c64 = P.c64;
   timed_gemm(f.build_prof, gname, g, st);
   // W^{-1}
   {
     Stage s(f.build_prof, iname.c_str(), nbox * 8.0 * n3 * n3 * n3, nbox * 2.0 * n3 * n3 * 16);
     zinv((int)n3, (int)nbox, P.Winv.d(), n3, n3 * n3, P.Winv.d(), n3, n3 * n3, info,
-         sc.work.p, st);
+         sc.work.p, st, P.c64);
   }
   // Phi^a = W^{-1} T   (eq. (talpha))
   g = GemmDesc();
@@ -723,6 +746,7 @@ void build_level(hps_factor& f, int l, BuildScratch& sc) {
   g.B = sc.T.d(); g.ldb = n3; g.sB = n3 * nbp;
   g.C = P.PhiA.d(); g.ldc = n3; g.sC = n3 * nbp;
   g.alpha = 1.0; g.beta = 0.0;
+  g.c64 = P.c64;
   timed_gemm(f.build_prof, gname, g, st);
   // Phi^b = [-R31a, 0] - R33a Phi^a   (eq. (tbeta), short form)
   g = GemmDesc();
@@ -731,6 +755,7 @@ void build_level(hps_factor& f, int l, BuildScratch& sc) {
   g.B = P.PhiA.d(); g.ldb = n3; g.sB = n3 * nbp;
   g.C = P.PhiB.d(); g.ldc = n3; g.sC = n3 * nbp;
   g.alpha = -1.0; g.beta = 1.0;
+  g.c64 = P.c64;
   timed_gemm(f.build_prof, gname, g, st);
   if (form_R) {
     // R^tau = blockdiag(R11a, R22b) + blockdiag(R13a, R23b) [Phi^a; Phi^b]   (eq. (out))
@@ -740,12 +765,14 @@ void build_level(hps_factor& f, int l, BuildScratch& sc) {
     g.B = P.PhiA.d(); g.ldb = n3; g.sB = n3 * nbp;
     g.C = f.R[l].d(); g.ldc = nbp; g.sC = nbp * nbp; g.crow = P.dperm;
     g.alpha = 1.0; g.beta = 1.0;
-    timed_gemm(f.build_prof, gname, g, st);
+    g.c64 = P.c64;
+  timed_gemm(f.build_prof, gname, g, st);
     g.M = n2;
     g.A = P.R23b.d(); g.lda = n2; g.sA = n2 * n3;
     g.B = P.PhiB.d();
     g.crow = P.dperm + n1;
-    timed_gemm(f.build_prof, gname, g, st);
+    g.c64 = P.c64;
+  timed_gemm(f.build_prof, gname, g, st);
     f.R_valid[l] = 1;
   }
   // children's R: overwritten two levels up (ping-pong) unless every R is kept
@@ -757,6 +784,11 @@ void build_all(hps_factor& f, const double* c) {
   plan_memory(f, sc);
   fill_zero_int(sc.info.i(), (long)(sc.info.bytes / sizeof(int)), f.stream);
   build_leaves(f, c, sc);
+  if (f.mixed) {
+    // the solve reads the leaf operators in complex64
+    Stage s(f.build_prof, "leaf_to_c64", 0.0, (double)f.nleaf * f.n * f.n * 24);
+    to_c64(f.BI.d(), reinterpret_cast<float*>(f.BI32.p), 2L * f.nleaf * f.n * f.n, f.stream);
+  }
   for (int l = f.L - 1; l >= 0; --l) build_level(f, l, sc);
   // one synchronization for the whole build, then the pivot checks
   HPS_HIP(hipStreamSynchronize(f.stream));
@@ -764,6 +796,7 @@ void build_all(hps_factor& f, const double* c) {
   HPS_HIP(hipMemcpy(h.data(), sc.info.p, sc.info.bytes, hipMemcpyDeviceToHost));
   check_info(h, 0, f.nleaf, "leaf interior Schur complement");
   for (int l = 0; l < f.L; ++l) check_info(h, sc.info_off[l], f.lv[l].nbox, "interface matrix W");
+  if (f.mixed) f.BI = View();  // lived in the build scratch
   // release the ItI buffer that no longer holds a kept operator
   if (!f.opts.keep_all_R) {
     for (int b = 0; b < 2; ++b) {
@@ -782,7 +815,7 @@ struct Arena {
   bool dry = true;
   hipStream_t st = nullptr;
   char* base = nullptr;
-  size_t used = 0, split_need = 0, peak = 0;
+  size_t used = 0, split_need = 0, peak = 0, cap = 0;
   void* split = nullptr;
   void* block = nullptr;
   double* get(size_t bytes) {
@@ -790,6 +823,8 @@ struct Arena {
     size_t off = used;
     used += bytes;
     peak = std::max(peak, used);
+    // a pass that needs more than the sizing pass measured is a planning error
+    if (!dry && used > cap) throw Error(HPS_E_INVALID, "solve workspace exceeded its plan");
     // in the dry pass the pointer is a placeholder that is never dereferenced
     return reinterpret_cast<double*>((dry ? reinterpret_cast<char*>(4096) : base) + off);
   }
@@ -803,6 +838,7 @@ struct Arena {
   }
   void allocate() {
     used = std::max(used, peak);
+    cap = used;
     size_t total = used + split_need + 256;
     hipError_t e = hipMallocAsync(&block, total, st);
     if (e != hipSuccess) {
@@ -840,7 +876,9 @@ void solve_pass(hps_factor& f, int nrhs, const double* s, const double* t, const
       // leaf: u~ = Y s   (Algorithm 2 step (3))
       SkinnyDesc k;
       k.M = n; k.K = ni; k.nrhs = nrhs; k.batch = (int)nl;
-      k.A = f.BI.d() + 2 * n * nb; k.lda = n; k.sA = n * n;
+      k.A = f.mixed ? f.BI32.d() + n * nb : f.BI.d() + 2 * n * nb;
+      k.a_c64 = f.mixed;
+      k.lda = n; k.sA = n * n;
       k.X = s; k.ldx = nl * ni; k.xoff = f.dxoff.l();
       k.C = ut; k.ldc = n; k.sC = n * nrhs;
       ws.skinny(pr, nm, k);
@@ -870,6 +908,7 @@ void solve_pass(hps_factor& f, int nrhs, const double* s, const double* t, const
       // v = R33b h3a - h3b
       SkinnyDesc k;
       k.M = n3; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox;
+      k.a_c64 = P.c64;
       k.A = P.R33b.d(); k.lda = n3; k.sA = n3 * n3;
       k.X = h3a; k.ldx = n3; k.sX = n3 * nrhs;
       k.C = v; k.ldc = n3; k.sC = n3 * nrhs; k.accumulate = true;
@@ -877,6 +916,7 @@ void solve_pass(hps_factor& f, int nrhs, const double* s, const double* t, const
       // t~3a = W^{-1} v
       k = SkinnyDesc();
       k.M = n3; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox;
+      k.a_c64 = P.c64;
       k.A = P.Winv.d(); k.lda = n3; k.sA = n3 * n3;
       k.X = v; k.ldx = n3; k.sX = n3 * nrhs;
       k.C = tta[l]; k.ldc = n3; k.sC = n3 * nrhs;
@@ -884,6 +924,7 @@ void solve_pass(hps_factor& f, int nrhs, const double* s, const double* t, const
       // t~3b = -h3a - R33a t~3a
       k = SkinnyDesc();
       k.M = n3; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox;
+      k.a_c64 = P.c64;
       k.A = P.R33a.d(); k.lda = n3; k.sA = n3 * n3;
       k.X = tta[l]; k.ldx = n3; k.sX = n3 * nrhs;
       k.C = ttb[l]; k.ldc = n3; k.sC = n3 * nrhs; k.accumulate = true; k.alpha = -1.0;
@@ -892,6 +933,7 @@ void solve_pass(hps_factor& f, int nrhs, const double* s, const double* t, const
         // h^tau = [h1a + R13a t~3a ; h2b + R23b t~3b]   (eq. (flux_part))
         k = SkinnyDesc();
         k.M = n1; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox;
+        k.a_c64 = P.c64;
         k.A = P.R13a.d(); k.lda = n1; k.sA = n1 * n3;
         k.X = tta[l]; k.ldx = n3; k.sX = n3 * nrhs;
         k.C = h[l]; k.ldc = nbp; k.sC = nbp * nrhs; k.crow = P.dperm; k.accumulate = true;
@@ -921,6 +963,7 @@ void solve_pass(hps_factor& f, int nrhs, const double* s, const double* t, const
       SkinnyDesc k;
       k.M = n3; k.K = nbp; k.nrhs = nrhs; k.batch = (int)nbox;
       k.A = side ? P.PhiB.d() : P.PhiA.d(); k.lda = n3; k.sA = n3 * nbp;
+      k.a_c64 = P.c64;
       k.X = tp; k.ldx = nbp; k.sX = sp;
       k.C = tt[l + 1] + 2 * (side ? nbc * nrhs : 0); k.ldc = nbc; k.sC = 2 * nbc * nrhs;
       k.crow = side ? P.di3b : P.di3a;
@@ -935,7 +978,9 @@ void solve_pass(hps_factor& f, int nrhs, const double* s, const double* t, const
     nm = "solve_leaf_down";
     SkinnyDesc k;
     k.M = n; k.K = nb; k.nrhs = nrhs; k.batch = (int)nl;
-    k.A = f.BI.d(); k.lda = n; k.sA = n * n;
+    k.A = f.mixed ? f.BI32.d() : f.BI.d();
+    k.a_c64 = f.mixed;
+    k.lda = n; k.sA = n * n;
     k.X = (f.L == 0) ? t : tt[f.L]; k.ldx = nb; k.sX = nb * nrhs;
     k.C = u; k.ldc = nl * n; k.coff = f.duoff.l();
     if (up) {
@@ -1052,13 +1097,18 @@ int hps_build(const hps_domain* dom, int32_t p, double kappa, double eta_re, dou
       throw Error(HPS_E_INVALID, "eta must be finite with Re(eta) != 0");
     std::unique_ptr<hps_factor> f(new hps_factor);
     if (opts) f->opts = *opts; else hps_default_opts(&f->opts);
-    if (f->opts.precision != 0) throw Error(HPS_E_INVALID, "unsupported precision mode");
+    if (f->opts.precision != HPS_PREC_C128 && f->opts.precision != HPS_PREC_MIXED)
+      throw Error(HPS_E_INVALID, "unsupported precision mode");
+    if (f->opts.fp64_top_levels < 0) throw Error(HPS_E_INVALID, "fp64_top_levels must be >= 0");
+    if (!(f->opts.refine_tol > 0.0)) throw Error(HPS_E_INVALID, "refine_tol must be > 0");
+    f->mixed = f->opts.precision == HPS_PREC_MIXED;
     f->p = p; f->m = p - 2; f->n = p * p - 4; f->nb = 4 * (p - 2); f->ni = (p - 2) * (p - 2);
     f->nx = dom->nx; f->ny = dom->ny; f->nleaf = dom->nx * dom->ny;
     f->x0 = dom->x0; f->x1 = dom->x1; f->y0 = dom->y0; f->y1 = dom->y1;
     f->kappa = kappa; f->eta_re = eta_re; f->eta_im = eta_im;
     f->stream = static_cast<hipStream_t>(f->opts.stream);
     make_plan(*f);
+    for (int l = 0; l < f->L; ++l) f->lv[l].c64 = f->mixed && l >= f->opts.fp64_top_levels;
     upload_plan(*f);
     f->dc.alloc((size_t)f->nleaf * f->ni * sizeof(double));
     HPS_HIP(hipMemcpyAsync(f->dc.p, c_interior, f->dc.bytes, hipMemcpyDeviceToDevice, f->stream));
@@ -1108,6 +1158,11 @@ void solve_impl(hps_factor& f, int nrhs, const double* s, const double* t, const
     }
     mark = ws.used;
     solve_pass(f, nrhs, s, t, jmp, u, ws);  // pass 0 only sizes the workspace
+    if (pass == 0 && iters > 0) {
+      // the correction sweeps always run the upward pass: size the workspace for them too
+      ws.used = mark;
+      solve_pass(f, nrhs, rs, rt, rj, dl, ws);
+    }
   }
   f.last_info = hps_solve_info{};
   if (iters <= 0) return;
@@ -1228,14 +1283,17 @@ int hps_factor_get(const hps_factor* f, int32_t what, int32_t level, int32_t box
     const double* src = nullptr;
     long r = 0, c = 0, ld = 0;
     long off = 0;
+    bool c64 = false;  // stored as complex64
     if (what == HPS_OP_PSI || what == HPS_OP_Y) {
       if (level != f->L) throw Error(HPS_E_INVALID, "Psi/Y exist on the leaf level only");
-      src = f->BI.d();
+      c64 = f->mixed;
+      src = c64 ? f->BI32.d() : f->BI.d();
       r = f->n; ld = f->n;
       c = (what == HPS_OP_PSI) ? f->nb : f->ni;
       off = (long)box * f->n * f->n + (what == HPS_OP_PSI ? 0 : (long)f->n * f->nb);
     } else if (what == HPS_OP_R) {
       if (!f->R_valid[level]) throw Error(HPS_E_INVALID, "R of this level is not kept");
+      c64 = cbytes(*f, level) == 8;
       src = f->R[level].d();
       r = c = ld = f->nbl[level];
       off = (long)box * r * r;
@@ -1254,6 +1312,7 @@ int hps_factor_get(const hps_factor* f, int32_t what, int32_t level, int32_t box
         default: throw Error(HPS_E_INVALID, "unknown operator id");
       }
       src = b->d();
+      c64 = P.c64;
       ld = r;
       off = (long)box * r * c;
     }
@@ -1261,7 +1320,15 @@ int hps_factor_get(const hps_factor* f, int32_t what, int32_t level, int32_t box
     if (cols) *cols = (int32_t)c;
     if (dst_len < r * c) throw Error(HPS_E_INVALID, "destination too small");
     HPS_HIP(hipStreamSynchronize(f->stream));
-    HPS_HIP(hipMemcpy2D(dst, r * 16, src + 2 * off, ld * 16, r * 16, c, hipMemcpyDeviceToHost));
+    if (!c64) {
+      HPS_HIP(hipMemcpy2D(dst, r * 16, src + 2 * off, ld * 16, r * 16, c, hipMemcpyDeviceToHost));
+    } else {
+      // complex64 storage: copy, then widen to the complex128 layout of dst
+      std::vector<float> tmp((size_t)2 * r * c);
+      const float* s32 = reinterpret_cast<const float*>(src) + 2 * off;
+      HPS_HIP(hipMemcpy2D(tmp.data(), r * 8, s32, ld * 8, r * 8, c, hipMemcpyDeviceToHost));
+      for (size_t e = 0; e < tmp.size(); ++e) dst[e] = tmp[e];
+    }
   });
 }
 

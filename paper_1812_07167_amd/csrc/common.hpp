@@ -12,6 +12,7 @@
 namespace hps {
 
 typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------- complex on double2
 __host__ __device__ inline double2 cmk(double r, double i) { return make_double2(r, i); }
@@ -42,6 +43,41 @@ __host__ __device__ inline double2 crcp_fast(double2 a) {
   return cmk(a.x * d, -a.y * d);
 }
 __host__ __device__ inline double cabs1(double2 a) { return fabs(a.x) + fabs(a.y); }
+
+// the same operations on complex64 (float2), for the reduced-precision merge levels
+__host__ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline float2 cfma(float2 b, float2 c, float2 a) {
+  return make_float2(a.x + b.x * c.x - b.y * c.y, a.y + b.x * c.y + b.y * c.x);
+}
+__host__ __device__ inline float2 crcp(float2 a) {
+  if (fabsf(a.x) >= fabsf(a.y)) {
+    float r = a.y / a.x, d = a.x + a.y * r;
+    return make_float2(1.0f / d, -r / d);
+  } else {
+    float r = a.x / a.y, d = a.y + a.x * r;
+    return make_float2(r / d, -1.0f / d);
+  }
+}
+__host__ __device__ inline float2 crcp_fast(float2 a) {
+  const float d = 1.0f / fmaf(a.x, a.x, a.y * a.y);
+  return make_float2(a.x * d, -a.y * d);
+}
+__host__ __device__ inline float cabs1(float2 a) { return fabsf(a.x) + fabsf(a.y); }
+
+// complex type of a real element type
+template <class T> struct Cx;
+template <> struct Cx<double> {
+  typedef double2 t;
+  static __host__ __device__ inline t mk(double r, double i) { return make_double2(r, i); }
+};
+template <> struct Cx<float> {
+  typedef float2 t;
+  static __host__ __device__ inline t mk(float r, float i) { return make_float2(r, i); }
+};
 
 // ---------------------------------------------------------------- wave reductions
 // Maximum of an unsigned value over the 64 lanes of a wave (all lanes active), by DPP

@@ -9,8 +9,10 @@
 // Y_b, Y_i), by every merge product of Sec. 2.2 (W, Phi^a, Phi^b, R^tau) and by the
 // block updates of the interface inversion.
 //
-// MFMA f64 16x16x4 lane layout (measured on gfx950): lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; accumulator element v of lane l is D[l/16 + 4 v][l%16].
+// MFMA 16x16x4 lane layouts (measured on gfx950): lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; accumulator element v of lane l is D[l/16 + 4 v][l%16] for the f64
+// instruction and D[4 (l/16) + v][l%16] for the f32 one.  Complex64 operands (the
+// reduced-precision merge levels) run on the f32 instruction with FP32 accumulation.
 #include "kernels.hpp"
 
 namespace hps {
@@ -18,10 +20,34 @@ namespace {
 
 constexpr int BK = 16;
 
+// element type traits: MFMA, accumulator and output row of accumulator slot v
+template <class T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef d4v acc;
+  typedef double2 cplx;
+  static __device__ inline acc op(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+  static __device__ inline cplx mk(double r, double i) { return make_double2(r, i); }
+};
+template <> struct Mfma<float> {
+  typedef f4v acc;
+  typedef float2 cplx;
+  static __device__ inline acc op(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+  static __device__ inline cplx mk(float r, float i) { return make_float2(r, i); }
+};
+
 constexpr int lds_pad(int w) { return (w % 32 == 16) ? 0 : 16; }
 
-template <int BM, int BN, int WR, int WC, bool AR, bool BR>
+template <class T, int BM, int BN, int WR, int WC, bool AR, bool BR>
 __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
+  typedef Mfma<T> MF;
+  typedef typename MF::acc acc_t;
+  typedef typename MF::cplx cplx_t;
   constexpr int NT = 64 * WR * WC;
   constexpr int NPA = AR ? 1 : 2;  // planes (re, im) of A
   constexpr int NPB = BR ? 1 : 2;
@@ -30,8 +56,8 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
   constexpr int LA = BM + lds_pad(BM), LB = BN + lds_pad(BN);
   static_assert(MB >= 1 && NB >= 1 && WM % 16 == 0 && WN % 16 == 0, "bad tile");
   static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "tile/threads mismatch");
-  __shared__ double As[2][NPA][BK][LA];
-  __shared__ double Bs[2][NPB][BK][LB];
+  __shared__ T As[2][NPA][BK][LA];
+  __shared__ T Bs[2][NPB][BK][LB];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -45,21 +71,21 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
   const int i0 = tm * BM, j0 = tn * BN;
   const long b = blockIdx.y;
 
-  const double* A = d.A + b * d.sA * NPA;
-  const double* B = d.B + b * d.sB * NPB;
+  const T* A = reinterpret_cast<const T*>(d.A) + b * d.sA * NPA;
+  const T* B = reinterpret_cast<const T*>(d.B) + b * d.sB * NPB;
 
-  d4v accR[MB][NB], accI[MB][NB];
+  acc_t accR[MB][NB], accI[MB][NB];
 #pragma unroll
   for (int x = 0; x < MB; ++x)
 #pragma unroll
     for (int y = 0; y < NB; ++y) {
-      accR[x][y] = d4v{0, 0, 0, 0};
-      accI[x][y] = d4v{0, 0, 0, 0};
+      accR[x][y] = acc_t{0, 0, 0, 0};
+      accI[x][y] = acc_t{0, 0, 0, 0};
     }
 
   constexpr int EA = BM * BK / NT;  // A elements per thread per chunk
   constexpr int EB = BN * BK / NT;
-  double ra[EA][NPA], rb[EB][NPB];
+  T ra[EA][NPA], rb[EB][NPB];
 
   auto gload = [&](int k0) {
 #pragma unroll
@@ -70,9 +96,9 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
       const bool ok = gi < d.M && gk < d.K;
       const long off = (long)gi + d.lda * (long)gk;
       if (AR) {
-        ra[e][0] = ok ? A[off] : 0.0;
+        ra[e][0] = ok ? A[off] : T(0);
       } else {
-        const double2 v = ok ? reinterpret_cast<const double2*>(A)[off] : make_double2(0.0, 0.0);
+        const cplx_t v = ok ? reinterpret_cast<const cplx_t*>(A)[off] : MF::mk(0, 0);
         ra[e][0] = v.x;
         ra[e][NPA - 1] = v.y;
       }
@@ -85,9 +111,9 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
       const bool ok = gk < d.K && gj < d.N;
       const long off = (long)gk + d.ldb * (long)gj;
       if (BR) {
-        rb[e][0] = ok ? B[off] : 0.0;
+        rb[e][0] = ok ? B[off] : T(0);
       } else {
-        const double2 v = ok ? reinterpret_cast<const double2*>(B)[off] : make_double2(0.0, 0.0);
+        const cplx_t v = ok ? reinterpret_cast<const cplx_t*>(B)[off] : MF::mk(0, 0);
         rb[e][0] = v.x;
         rb[e][NPB - 1] = v.y;
       }
@@ -120,30 +146,27 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kl = kk + (lane >> 4);
-      double ar[MB], ai[MB], br[NB], bi[NB];
+      T ar[MB], ai[MB], br[NB], bi[NB];
 #pragma unroll
       for (int x = 0; x < MB; ++x) {
         const int r = wr * WM + 16 * x + (lane & 15);
         ar[x] = As[buf][0][kl][r];
-        ai[x] = AR ? 0.0 : As[buf][NPA - 1][kl][r];
+        ai[x] = AR ? T(0) : As[buf][NPA - 1][kl][r];
       }
 #pragma unroll
       for (int y = 0; y < NB; ++y) {
         const int c = wc * WN + 16 * y + (lane & 15);
         br[y] = Bs[buf][0][kl][c];
-        bi[y] = BR ? 0.0 : Bs[buf][NPB - 1][kl][c];
+        bi[y] = BR ? T(0) : Bs[buf][NPB - 1][kl][c];
       }
 #pragma unroll
       for (int x = 0; x < MB; ++x)
 #pragma unroll
         for (int y = 0; y < NB; ++y) {
-          accR[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[x], br[y], accR[x][y], 0, 0, 0);
-          if (!AR && !BR)
-            accR[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[x], bi[y], accR[x][y], 0, 0, 0);
-          if (!BR)
-            accI[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[x], bi[y], accI[x][y], 0, 0, 0);
-          if (!AR)
-            accI[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[x], br[y], accI[x][y], 0, 0, 0);
+          accR[x][y] = MF::op(ar[x], br[y], accR[x][y]);
+          if (!AR && !BR) accR[x][y] = MF::op(-ai[x], bi[y], accR[x][y]);
+          if (!BR) accI[x][y] = MF::op(ar[x], bi[y], accI[x][y]);
+          if (!AR) accI[x][y] = MF::op(ai[x], br[y], accI[x][y]);
         }
     }
     if (kc + 1 < nk) sstore(buf ^ 1);
@@ -151,24 +174,25 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
   }
 
   // epilogue
-  double2* C = reinterpret_cast<double2*>(d.C) + b * d.sC;
+  cplx_t* C = reinterpret_cast<cplx_t*>(d.C) + b * d.sC;
+  const T alpha = (T)d.alpha, beta = (T)d.beta;
 #pragma unroll
   for (int x = 0; x < MB; ++x)
 #pragma unroll
     for (int y = 0; y < NB; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = i0 + wr * WM + 16 * x + (lane >> 4) + 4 * v;
+        const int i = i0 + wr * WM + 16 * x + MF::row(lane, v);
         const int j = j0 + wc * WN + 16 * y + (lane & 15);
         if (i < d.M && j < d.N) {
           const long ri = d.crow ? d.crow[i] : i;
           const long cj = d.ccol ? d.ccol[j] : j;
-          double2* p = C + ri + d.ldc * cj;
-          double2 val = cmk(d.alpha * accR[x][y][v], d.alpha * accI[x][y][v]);
+          cplx_t* p = C + ri + d.ldc * cj;
+          cplx_t val = MF::mk(alpha * accR[x][y][v], alpha * accI[x][y][v]);
           if (d.beta != 0.0) {
-            const double2 old = *p;
-            val.x += d.beta * old.x;
-            val.y += d.beta * old.y;
+            const cplx_t old = *p;
+            val.x += beta * old.x;
+            val.y += beta * old.y;
           }
           *p = val;
         }
@@ -180,14 +204,20 @@ void launch_tile(const GemmDesc& d, hipStream_t st) {
   const int tiles = cdiv(d.M, BM) * cdiv(d.N, BN);
   const dim3 grid(tiles, d.batch);
   const dim3 block(64 * WR * WC);
-  if (d.a_real && d.b_real)
-    hipLaunchKernelGGL((zgemm_kernel<BM, BN, WR, WC, true, true>), grid, block, 0, st, d);
-  else if (d.a_real)
-    hipLaunchKernelGGL((zgemm_kernel<BM, BN, WR, WC, true, false>), grid, block, 0, st, d);
-  else if (d.b_real)
-    hipLaunchKernelGGL((zgemm_kernel<BM, BN, WR, WC, false, true>), grid, block, 0, st, d);
-  else
-    hipLaunchKernelGGL((zgemm_kernel<BM, BN, WR, WC, false, false>), grid, block, 0, st, d);
+  if (d.c64) {
+    // the reduced-precision merges are complex x complex only
+    if (d.a_real || d.b_real) throw Error(1, "zgemm: complex64 operands must be complex");
+    hipLaunchKernelGGL((zgemm_kernel<float, BM, BN, WR, WC, false, false>), grid, block, 0, st, d);
+  } else if (d.a_real && d.b_real) {
+    hipLaunchKernelGGL((zgemm_kernel<double, BM, BN, WR, WC, true, true>), grid, block, 0, st, d);
+  } else if (d.a_real) {
+    hipLaunchKernelGGL((zgemm_kernel<double, BM, BN, WR, WC, true, false>), grid, block, 0, st, d);
+  } else if (d.b_real) {
+    hipLaunchKernelGGL((zgemm_kernel<double, BM, BN, WR, WC, false, true>), grid, block, 0, st, d);
+  } else {
+    hipLaunchKernelGGL((zgemm_kernel<double, BM, BN, WR, WC, false, false>), grid, block, 0, st,
+                       d);
+  }
 }
 
 }  // namespace
@@ -209,6 +239,7 @@ std::string zgemm_variant(const GemmDesc& d) {
   std::string v = names[pick_tile(d)];
   v += d.a_real ? "r" : "c";
   v += d.b_real ? "r" : "c";
+  if (d.c64) v += "s";  // complex64
   return v;
 }
 

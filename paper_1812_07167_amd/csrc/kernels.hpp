@@ -20,6 +20,7 @@ struct GemmDesc {
   double alpha = 1.0, beta = 0.0;
   const int* crow = nullptr;
   const int* ccol = nullptr;
+  bool c64 = false;  // A, B and C are complex64 (interleaved float); FP32 accumulation
 };
 void zgemm(const GemmDesc& d, hipStream_t st);
 // name of the kernel variant zgemm launches for d: tile "MxN" plus r/c for real or
@@ -41,6 +42,7 @@ struct SkinnyDesc {
   const double* C0 = nullptr; long ld0 = 0, s0 = 0; const long* c0off = nullptr;
   bool accumulate = false;
   double alpha = 1.0;
+  bool a_c64 = false;  // A is complex64 (FP32 products and accumulation)
   // workspace for the split-K partial sums (at least skinny_work_bytes(d) bytes)
   void* work = nullptr;
 };
@@ -49,12 +51,14 @@ void zgemm_skinny(const SkinnyDesc& d, hipStream_t st);
 
 // ------------------------------------------------------------------ complex inversion
 // Batched Gauss-Jordan inversion with partial pivoting of n x n complex matrices.
-// In: A_b (lda, sA).  Out: Inv_b (ldo, sO); may alias A only for the small path.
-// info[b] is set to (k+1) if the k-th pivot is exactly zero (info must be zeroed by
-// the caller).  Workspace is allocated by the caller through zinv_workspace_bytes.
-size_t zinv_workspace_bytes(int n, int batch);
+// In: A_b (lda, sA).  Out: Inv_b (ldo, sO); Out may alias A (A is read completely before
+// Out is written).  info[b] is set to (k+1) if the k-th pivot is exactly zero (info must
+// be zeroed by the caller).  Workspace is allocated by the caller through
+// zinv_workspace_bytes.  c64: A, Out and the arithmetic are complex64 (strides still in
+// complex entries).
+size_t zinv_workspace_bytes(int n, int batch, bool c64 = false);
 void zinv(int n, int batch, const double* A, long lda, long sA, double* Out, long ldo,
-          long sO, int* info, void* work, hipStream_t st);
+          long sO, int* info, void* work, hipStream_t st, bool c64 = false);
 
 // ------------------------------------------------------------------ leaf stage
 struct LeafDesc {
@@ -97,10 +101,14 @@ struct MergeLevelDesc {
   double* R31a = nullptr;      // scratch [nbox][n3*n1]
   double* T = nullptr;         // scratch [nbox][n3*nbp]
   double* PhiB = nullptr;      // [nbox][n3*nbp]
+  bool c64 = false;            // the level's blocks (and its parent R) are complex64
+  bool child_c64 = false;      // the children's R is complex64
 };
 void fill_zero(double* p, long ndouble, hipStream_t st);
 void fill_zero_int(int* p, long n, hipStream_t st);
-void fill_identity(double* p, int n, long stride, int batch, hipStream_t st);
+void fill_identity(double* p, int n, long stride, int batch, hipStream_t st, bool c64 = false);
+// round n doubles to floats (complex128 -> complex64 storage)
+void to_c64(const double* src, float* dst, long n, hipStream_t st);
 void merge_extract(const MergeLevelDesc& d, hipStream_t st);
 
 // ------------------------------------------------------------------ solve helpers

@@ -18,58 +18,69 @@ __global__ void fill_zero_kernel(double* p, long n) {
   if (e < n) p[e] = 0.0;
 }
 
+__global__ void to_f32_kernel(const double* s, float* d, long n) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) d[e] = (float)s[e];
+}
+
 __global__ void fill_zero_int_kernel(int* p, long n) {
   long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) p[e] = 0;
 }
 
-__global__ void fill_identity_kernel(double2* p, int n, long stride, int batch) {
+template <class T>
+__global__ void fill_identity_kernel(typename Cx<T>::t* p, int n, long stride, int batch) {
   long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   long tot = (long)n * n * batch;
   if (e >= tot) return;
   long b = e / ((long)n * n);
   int loc = e % ((long)n * n);
   int i = loc % n, j = loc / n;
-  p[b * stride + loc] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  p[b * stride + loc] = Cx<T>::mk(i == j ? T(1) : T(0), T(0));
 }
 
+// Tc: element type of the children's R; Tp: element type of the level's blocks (a
+// complex128 child feeding a complex64 level is rounded here)
+template <class Tc, class Tp>
 __global__ void extract_kernel(MergeLevelDesc d) {
+  typedef typename Cx<Tc>::t Cc;
+  typedef typename Cx<Tp>::t Cp;
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long nn = (long)d.nbc * d.nbc;
   if (e >= nn) return;
   const long q = blockIdx.y;
   const int side = blockIdx.z;
   const int i = e % d.nbc, j = e / d.nbc;
-  const double2* R = reinterpret_cast<const double2*>(d.Rc) + (2 * q + side) * nn;
-  const double2 v = R[e];
+  const Cc* R = reinterpret_cast<const Cc*>(d.Rc) + (2 * q + side) * nn;
+  const Cc w = R[e];
+  const Cp v = Cx<Tp>::mk((Tp)w.x, (Tp)w.y);
+  const Cp nv = Cx<Tp>::mk(-v.x, -v.y);
   const int n1 = d.n1, n2 = d.n2, n3 = d.n3, nbp = d.nbp;
   if (side == 0) {
     const int ci = d.codeA[i], cj = d.codeA[j];
     const int ti = ci >> 16, ki = ci & 0xffff, tj = cj >> 16, kj = cj & 0xffff;
     if (ti == 1 && tj == 1) {
-      reinterpret_cast<double2*>(d.R33a)[q * n3 * n3 + ki + (long)n3 * kj] = v;
+      reinterpret_cast<Cp*>(d.R33a)[q * n3 * n3 + ki + (long)n3 * kj] = v;
     } else if (ti == 1 && tj == 0) {
-      reinterpret_cast<double2*>(d.R31a)[q * n3 * n1 + ki + (long)n3 * kj] = v;
-      reinterpret_cast<double2*>(d.PhiB)[q * n3 * nbp + ki + (long)n3 * d.perm[kj]] =
-          make_double2(-v.x, -v.y);
+      reinterpret_cast<Cp*>(d.R31a)[q * n3 * n1 + ki + (long)n3 * kj] = v;
+      reinterpret_cast<Cp*>(d.PhiB)[q * n3 * nbp + ki + (long)n3 * d.perm[kj]] = nv;
     } else if (ti == 0 && tj == 1) {
-      reinterpret_cast<double2*>(d.R13a)[q * n1 * n3 + ki + (long)n1 * kj] = v;
+      reinterpret_cast<Cp*>(d.R13a)[q * n1 * n3 + ki + (long)n1 * kj] = v;
     } else if (d.Rp) {
-      reinterpret_cast<double2*>(d.Rp)[q * nbp * nbp + d.perm[ki] + (long)nbp * d.perm[kj]] = v;
+      reinterpret_cast<Cp*>(d.Rp)[q * nbp * nbp + d.perm[ki] + (long)nbp * d.perm[kj]] = v;
     }
   } else {
     const int ci = d.codeB[i], cj = d.codeB[j];
     const int ti = ci >> 16, ki = ci & 0xffff, tj = cj >> 16, kj = cj & 0xffff;
     if (ti == 1 && tj == 1) {
-      reinterpret_cast<double2*>(d.R33b)[q * n3 * n3 + ki + (long)n3 * kj] = v;
+      reinterpret_cast<Cp*>(d.R33b)[q * n3 * n3 + ki + (long)n3 * kj] = v;
     } else if (ti == 1 && tj == 0) {
-      reinterpret_cast<double2*>(d.T)[q * n3 * nbp + ki + (long)n3 * d.perm[n1 + kj]] =
-          make_double2(-v.x, -v.y);
+      reinterpret_cast<Cp*>(d.T)[q * n3 * nbp + ki + (long)n3 * d.perm[n1 + kj]] = nv;
     } else if (ti == 0 && tj == 1) {
-      reinterpret_cast<double2*>(d.R23b)[q * n2 * n3 + ki + (long)n2 * kj] = v;
+      reinterpret_cast<Cp*>(d.R23b)[q * n2 * n3 + ki + (long)n2 * kj] = v;
     } else if (d.Rp) {
-      reinterpret_cast<double2*>(d.Rp)[q * nbp * nbp + d.perm[n1 + ki] +
-                                       (long)nbp * d.perm[n1 + kj]] = v;
+      reinterpret_cast<Cp*>(d.Rp)[q * nbp * nbp + d.perm[n1 + ki] + (long)nbp * d.perm[n1 + kj]] =
+          v;
     }
   }
 }
@@ -143,23 +154,41 @@ void fill_zero(double* p, long n, hipStream_t st) {
   HPS_LAUNCH_CHECK();
 }
 
+void to_c64(const double* src, float* dst, long n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(to_f32_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, src, dst, n);
+  HPS_LAUNCH_CHECK();
+}
+
 void fill_zero_int(int* p, long n, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(fill_zero_int_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, p, n);
   HPS_LAUNCH_CHECK();
 }
 
-void fill_identity(double* p, int n, long stride, int batch, hipStream_t st) {
+void fill_identity(double* p, int n, long stride, int batch, hipStream_t st, bool c64) {
   long tot = (long)n * n * batch;
   if (tot <= 0) return;
-  hipLaunchKernelGGL(fill_identity_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, st,
-                     reinterpret_cast<double2*>(p), n, stride, batch);
+  if (c64)
+    hipLaunchKernelGGL(fill_identity_kernel<float>, dim3(cdiv(tot, 256)), dim3(256), 0, st,
+                       reinterpret_cast<float2*>(p), n, stride, batch);
+  else
+    hipLaunchKernelGGL(fill_identity_kernel<double>, dim3(cdiv(tot, 256)), dim3(256), 0, st,
+                       reinterpret_cast<double2*>(p), n, stride, batch);
   HPS_LAUNCH_CHECK();
 }
 
 void merge_extract(const MergeLevelDesc& d, hipStream_t st) {
   long nn = (long)d.nbc * d.nbc;
-  hipLaunchKernelGGL(extract_kernel, dim3(cdiv(nn, 256), d.nbox, 2), dim3(256), 0, st, d);
+  const dim3 grid(cdiv(nn, 256), d.nbox, 2);
+  if (d.child_c64 && d.c64)
+    hipLaunchKernelGGL((extract_kernel<float, float>), grid, dim3(256), 0, st, d);
+  else if (d.c64)
+    hipLaunchKernelGGL((extract_kernel<double, float>), grid, dim3(256), 0, st, d);
+  else if (d.child_c64)
+    hipLaunchKernelGGL((extract_kernel<float, double>), grid, dim3(256), 0, st, d);
+  else
+    hipLaunchKernelGGL((extract_kernel<double, double>), grid, dim3(256), 0, st, d);
   HPS_LAUNCH_CHECK();
 }
 

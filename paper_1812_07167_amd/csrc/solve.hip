@@ -13,23 +13,44 @@
 // workgroups; those partial sums are reduced in a fixed order by a second kernel, so
 // results never depend on scheduling.
 //
-// MFMA f64 16x16x4 lane layout: lane l supplies A[l%16][l/16] and B[l/16][l%16];
-// accumulator element v of lane l is D[l/16 + 4 v][l%16].
+// MFMA 16x16x4 lane layouts: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// accumulator element v of lane l is D[l/16 + 4 v][l%16] (f64) or D[4 (l/16) + v][l%16]
+// (f32).  Complex64 operators (the reduced-precision levels) run on the f32 instruction
+// with FP32 accumulation; vectors stay complex128 in memory and are rounded when staged.
 #include "kernels.hpp"
 
 namespace hps {
 namespace {
 
+template <class T> struct SkMfma;
+template <> struct SkMfma<double> {
+  typedef d4v acc;
+  static __device__ inline acc op(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lk, int v) { return lk + 4 * v; }
+};
+template <> struct SkMfma<float> {
+  typedef f4v acc;
+  static __device__ inline acc op(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lk, int v) { return 4 * lk + v; }
+};
+
 constexpr int KC = 64;   // K chunk staged in LDS
 constexpr int NRB = 16;  // right-hand sides per pass (the MFMA's N)
 
-template <int TW, int WK>
+template <class T, int TW, int WK>
 __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int nr, int kper,
                                                      double2* partial) {
+  typedef typename Cx<T>::t C2;
+  typedef SkMfma<T> MF;
+  typedef typename MF::acc acc_t;
   constexpr int WR = 4 / WK;              // row groups of waves
   constexpr int ROWS = 16 * TW * WR;      // rows per workgroup
-  __shared__ double2 Xs[KC][NRB];
-  __shared__ d4v red[WK > 1 ? (WK - 1) * WR * TW * 2 * 64 : 1];
+  __shared__ C2 Xs[KC][NRB];
+  __shared__ acc_t red[WK > 1 ? (WK - 1) * WR * TW * 2 * 64 : 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave % WR, kw = wave / WR;
@@ -38,7 +59,7 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
   const int ks = blockIdx.z;
   const int kbeg = ks * kper, kend = min(d.K, kbeg + kper);
   const int row0 = blockIdx.x * ROWS + wr * 16 * TW;
-  const double2* A = reinterpret_cast<const double2*>(d.A) + b * d.sA;
+  const C2* A = reinterpret_cast<const C2*>(d.A) + b * d.sA;
   const double2* X = reinterpret_cast<const double2*>(d.X) + (d.xoff ? d.xoff[b] : b * d.sX);
 
   // rows this lane loads (clamped into the operator; rows past M are never written)
@@ -46,18 +67,19 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
 #pragma unroll
   for (int t = 0; t < TW; ++t) arow[t] = min(row0 + 16 * t + li, d.M - 1);
 
-  d4v accR[TW], accI[TW];
+  acc_t accR[TW], accI[TW];
 #pragma unroll
   for (int t = 0; t < TW; ++t) {
-    accR[t] = d4v{0, 0, 0, 0};
-    accI[t] = d4v{0, 0, 0, 0};
+    accR[t] = acc_t{0, 0, 0, 0};
+    accI[t] = acc_t{0, 0, 0, 0};
   }
   for (int k0 = kbeg; k0 < kend; k0 += KC) {
     const int kc = min(KC, kend - k0);
     __syncthreads();
     for (int e = tid; e < KC * NRB; e += 256) {
       const int k = e % KC, r = e / KC;
-      Xs[k][r] = (k < kc && r < nr) ? X[(k0 + k) + d.ldx * (long)(r0 + r)] : cmk(0, 0);
+      const double2 xv = (k < kc && r < nr) ? X[(k0 + k) + d.ldx * (long)(r0 + r)] : cmk(0, 0);
+      Xs[k][r] = Cx<T>::mk((T)xv.x, (T)xv.y);
     }
     __syncthreads();
     const int nsteps = (kc + 3) >> 2;
@@ -66,14 +88,14 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
       const int kl = 4 * s + lk;
       // k past the chunk meets a zero right-hand side; clamp its address into A
       const long kg = min(k0 + kl, d.K - 1);
-      const double2 bx = Xs[kl][li];
+      const C2 bx = Xs[kl][li];
 #pragma unroll
       for (int t = 0; t < TW; ++t) {
-        const double2 a = A[arow[t] + d.lda * kg];
-        accR[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, bx.x, accR[t], 0, 0, 0);
-        accR[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, bx.y, accR[t], 0, 0, 0);
-        accI[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, bx.y, accI[t], 0, 0, 0);
-        accI[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, bx.x, accI[t], 0, 0, 0);
+        const C2 a = A[arow[t] + d.lda * kg];
+        accR[t] = MF::op(a.x, bx.x, accR[t]);
+        accR[t] = MF::op(-a.y, bx.y, accR[t]);
+        accI[t] = MF::op(a.x, bx.y, accI[t]);
+        accI[t] = MF::op(a.y, bx.x, accI[t]);
       }
     }
   }
@@ -106,7 +128,7 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
     for (int t = 0; t < TW; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = row0 + 16 * t + lk + 4 * v;
+        const int i = row0 + 16 * t + MF::row(lk, v);
         if (i < d.M) P[i] = cmk(accR[t][v], accI[t][v]);
       }
     return;
@@ -119,7 +141,7 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
   for (int t = 0; t < TW; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int i = row0 + 16 * t + lk + 4 * v;
+      const int i = row0 + 16 * t + MF::row(lk, v);
       if (i >= d.M) continue;
       const long ci = d.crow ? d.crow[i] : i;
       double2 val = cmk(d.alpha * accR[t][v], d.alpha * accI[t][v]);
@@ -183,21 +205,21 @@ int split_plan(const SkinnyDesc& d, int* kper_out) {
   return nsplit;
 }
 
-template <int TW, int WK>
+template <class T, int TW, int WK>
 void run_chunk(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
   const int tiles = cdiv(d.M, 16 * TW * (4 / WK));
   int kper = 0;
   const int nsplit = split_plan(d, &kper);
   if (nsplit == 1) {
-    hipLaunchKernelGGL((skinny_kernel<TW, WK>), dim3(tiles, d.batch, 1), dim3(256), 0, st, d, r0,
-                       nr, d.K, (double2*)nullptr);
+    hipLaunchKernelGGL((skinny_kernel<T, TW, WK>), dim3(tiles, d.batch, 1), dim3(256), 0, st, d,
+                       r0, nr, d.K, (double2*)nullptr);
     HPS_LAUNCH_CHECK();
     return;
   }
   if (!d.work) throw Error(1, "zgemm_skinny: split-K needs a workspace");
   double2* part = static_cast<double2*>(d.work);
-  hipLaunchKernelGGL((skinny_kernel<TW, WK>), dim3(tiles, d.batch, nsplit), dim3(256), 0, st, d,
-                     r0, nr, kper, part);
+  hipLaunchKernelGGL((skinny_kernel<T, TW, WK>), dim3(tiles, d.batch, nsplit), dim3(256), 0, st,
+                     d, r0, nr, kper, part);
   HPS_LAUNCH_CHECK();
   long tot = (long)d.batch * d.M * nr;
   hipLaunchKernelGGL(skinny_reduce_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, st, d, r0, nr,
@@ -205,14 +227,20 @@ void run_chunk(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
   HPS_LAUNCH_CHECK();
 }
 
-void run_pass(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
+template <class T>
+void run_pass_t(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
   switch (block_rows(d.M)) {
-    case 16: run_chunk<1, 4>(d, r0, nr, st); break;
-    case 32: run_chunk<1, 2>(d, r0, nr, st); break;
-    case 64: run_chunk<1, 1>(d, r0, nr, st); break;
-    case 128: run_chunk<2, 1>(d, r0, nr, st); break;
-    default: run_chunk<4, 1>(d, r0, nr, st); break;
+    case 16: run_chunk<T, 1, 4>(d, r0, nr, st); break;
+    case 32: run_chunk<T, 1, 2>(d, r0, nr, st); break;
+    case 64: run_chunk<T, 1, 1>(d, r0, nr, st); break;
+    case 128: run_chunk<T, 2, 1>(d, r0, nr, st); break;
+    default: run_chunk<T, 4, 1>(d, r0, nr, st); break;
   }
+}
+
+void run_pass(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
+  if (d.a_c64) run_pass_t<float>(d, r0, nr, st);
+  else run_pass_t<double>(d, r0, nr, st);
 }
 
 }  // namespace

@@ -21,11 +21,13 @@ constexpr int SMALL_MAX = 96;  // at most 128 (two rows per lane in the small ke
 constexpr int PNB = 8;   // panel width of the blocked path
 
 // ------------------------------------------------------------------ small (LDS)
+template <class T>
 __global__ __launch_bounds__(256) void zinv_small_kernel(int n, const double* Ain, long lda,
                                                          long sA, double* Out, long ldo,
                                                          long sO, int* info) {
-  extern __shared__ double2 sm[];
-  double2* M = sm;                                   // n*n
+  typedef typename Cx<T>::t C2;
+  extern __shared__ double sm_raw[];
+  C2* M = reinterpret_cast<C2*>(sm_raw);             // n*n
   int* piv = reinterpret_cast<int*>(M + n * n);      // n
   int* ipiv = piv + n;                               // n
   int* used = ipiv + n;                              // n
@@ -34,7 +36,7 @@ __global__ __launch_bounds__(256) void zinv_small_kernel(int n, const double* Ai
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const long b = blockIdx.x;
-  const double2* A = reinterpret_cast<const double2*>(Ain) + b * sA;
+  const C2* A = reinterpret_cast<const C2*>(Ain) + b * sA;
   for (int e = tid; e < n * n; e += 256) {
     int i = e % n, j = e / n;
     M[e] = A[i + lda * j];
@@ -59,13 +61,13 @@ __global__ __launch_bounds__(256) void zinv_small_kernel(int n, const double* Ai
     __syncthreads();
     if (s_bad) break;
     const int r = s_r;
-    const double2 ip = crcp(M[r + n * k]);
+    const C2 ip = crcp(M[r + n * k]);
     // rows lane, lane + 64 of column group wave, wave + 4, ...  (no index division)
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int i = lane + 64 * q;
       if (i >= n || i == r) continue;
-      const double2 f = cmul(M[i + n * k], ip);
+      const C2 f = cmul(M[i + n * k], ip);
       for (int c = wv; c < n; c += 4) {
         if (c == k) continue;
         M[i + n * c] = csub(M[i + n * c], cmul(f, M[r + n * c]));
@@ -74,7 +76,7 @@ __global__ __launch_bounds__(256) void zinv_small_kernel(int n, const double* Ai
     __syncthreads();
     for (int e = tid; e < n; e += 256) {
       if (e != k) M[r + n * e] = cmul(M[r + n * e], ip);
-      if (e != r) M[e + n * k] = cmk(-(M[e + n * k].x * ip.x - M[e + n * k].y * ip.y),
+      if (e != r) M[e + n * k] = Cx<T>::mk(-(M[e + n * k].x * ip.x - M[e + n * k].y * ip.y),
                                      -(M[e + n * k].x * ip.y + M[e + n * k].y * ip.x));
     }
     if (tid == 0) {
@@ -90,7 +92,7 @@ __global__ __launch_bounds__(256) void zinv_small_kernel(int n, const double* Ai
   }
   for (int k = tid; k < n; k += 256) ipiv[piv[k]] = k;
   __syncthreads();
-  double2* O = reinterpret_cast<double2*>(Out) + b * sO;
+  C2* O = reinterpret_cast<C2*>(Out) + b * sO;
   for (int e = tid; e < n * n; e += 256) {
     int k = e % n, j = e / n;
     O[k + ldo * j] = M[piv[k] + n * ipiv[j]];
@@ -117,22 +119,23 @@ __global__ __launch_bounds__(256) void zinv_small_kernel(int n, const double* Ai
 // the remaining columns (the candidate row's values are published once final).  The slots alternate between two buffers, so one
 // barrier per step suffices: a wave can only overwrite a buffer after every wave has
 // passed the following step's barrier.
-template <int RPL>
+template <class T, int RPL>
 __global__ __launch_bounds__(512) void zinv_panel_kernel(int n, const double* Mcur,
                                                          double* Mnext, int k0, int* piv,
                                                          int* used, int* info) {
+  typedef typename Cx<T>::t C2;
   __shared__ unsigned s_key[2][8];
   __shared__ int s_row[2][8];
-  __shared__ double2 s_val[2][8][PNB];
+  __shared__ C2 s_val[2][8][PNB];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   const long b = blockIdx.x;
   if (info[b]) return;
-  const double2* M = reinterpret_cast<const double2*>(Mcur) + b * (long)n * n;
+  const C2* M = reinterpret_cast<const C2*>(Mcur) + b * (long)n * n;
   int* pv = piv + b * (long)n;
   int* us = used + b * (long)n;
   const int nk = (n - k0) < PNB ? (n - k0) : PNB;
-  double2 v[RPL][PNB];
+  C2 v[RPL][PNB];
   unsigned umask = 0;  // bit q: row of slot q is used (or beyond n)
 #pragma unroll
   for (int q = 0; q < RPL; ++q) {
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(512) void zinv_panel_kernel(int n, const double* Mc
     if (!ok || us[i]) umask |= 1u << q;
 #pragma unroll
     for (int c = 0; c < PNB; ++c)
-      v[q][c] = (ok && c < nk) ? M[i + (long)n * (k0 + c)] : cmk(0, 0);
+      v[q][c] = (ok && c < nk) ? M[i + (long)n * (k0 + c)] : Cx<T>::mk(0, 0);
   }
   // this wave's candidate for column s: key and row into slot buffer sb (the row's
   // values follow with publish_row once they are final)
@@ -192,19 +195,19 @@ __global__ __launch_bounds__(512) void zinv_panel_kernel(int n, const double* Mc
       continue;
     }
     const int r = s_row[sb][ww];
-    const double2 ip = crcp_fast(s_val[sb][ww][s]);
-    double2 f[RPL], f0[RPL];
+    const C2 ip = crcp_fast(s_val[sb][ww][s]);
+    C2 f[RPL], f0[RPL];
     bool isr[RPL];
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       const int i = (w * RPL + q) * 64 + lane;
       isr[q] = (i == r);
       f0[q] = cmul(v[q][s], ip);
-      f[q] = isr[q] ? cmk(1.0 - ip.x, -ip.y) : f0[q];
+      f[q] = isr[q] ? Cx<T>::mk(T(1) - ip.x, -ip.y) : f0[q];
       if (isr[q]) umask |= 1u << q;
     }
     auto upd = [&](int c) {
-      const double2 pc = s_val[sb][ww][c];  // LDS broadcast read
+      const C2 pc = s_val[sb][ww][c];  // LDS broadcast read
 #pragma unroll
       for (int q = 0; q < RPL; ++q) {
         v[q][c].x = fma(-f[q].x, pc.x, fma(f[q].y, pc.y, v[q][c].x));
@@ -224,7 +227,7 @@ __global__ __launch_bounds__(512) void zinv_panel_kernel(int n, const double* Mc
       if ((c & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
-    for (int q = 0; q < RPL; ++q) v[q][s] = isr[q] ? ip : cmk(-f0[q].x, -f0[q].y);
+    for (int q = 0; q < RPL; ++q) v[q][s] = isr[q] ? ip : Cx<T>::mk(-f0[q].x, -f0[q].y);
     if (s + 1 < nk) publish_row(sb ^ 1);
     if (threadIdx.x == 0) pv[k] = r;
   }
@@ -237,7 +240,7 @@ __global__ __launch_bounds__(512) void zinv_panel_kernel(int n, const double* Mc
   // the loads at the top (which costs registers).
   long ld = n;
   asm volatile("" : "+s"(ld));
-  double2* Mw = reinterpret_cast<double2*>(Mnext) + b * ld * ld;
+  C2* Mw = reinterpret_cast<C2*>(Mnext) + b * ld * ld;
 #pragma unroll
   for (int q = 0; q < RPL; ++q) {
     const int i = (w * RPL + q) * 64 + lane;
@@ -257,9 +260,11 @@ __global__ __launch_bounds__(512) void zinv_panel_kernel(int n, const double* Mc
 // covers 64 rows (one per lane) and UJ consecutive columns (UJ / 4 per wave) of one
 // matrix; a wave's column loads are issued together.
 constexpr int UJ = 16;
+template <class T>
 __global__ __launch_bounds__(256) void zinv_update_kernel(int n, const double* Mcur,
                                                           double* Mnext, int k0, const int* piv,
                                                           const int* info) {
+  typedef typename Cx<T>::t C2;
   constexpr int CW = UJ / 4;  // columns per wave
   const long b = blockIdx.z;
   if (info[b]) return;
@@ -270,47 +275,49 @@ __global__ __launch_bounds__(256) void zinv_update_kernel(int n, const double* M
   const int ncol = n - nk;
   const int jj0 = blockIdx.y * UJ + w * CW;
   if (i >= n || jj0 >= ncol) return;
-  const double2* Mc = reinterpret_cast<const double2*>(Mcur) + b * (long)n * n;
-  double2* Mn = reinterpret_cast<double2*>(Mnext) + b * (long)n * n;
+  const C2* Mc = reinterpret_cast<const C2*>(Mcur) + b * (long)n * n;
+  C2* Mn = reinterpret_cast<C2*>(Mnext) + b * (long)n * n;
   const int* pv = piv + b * (long)n + k0;
   int pr[PNB];
   bool isp = false;
-  double2 q[PNB];
+  C2 q[PNB];
 #pragma unroll
   for (int s = 0; s < PNB; ++s) {
     pr[s] = s < nk ? pv[s] : 0;
     isp |= (s < nk && pr[s] == i);
-    q[s] = s < nk ? Mn[i + (long)n * (k0 + s)] : cmk(0, 0);
+    q[s] = s < nk ? Mn[i + (long)n * (k0 + s)] : Cx<T>::mk(0, 0);
   }
-  double2 m[CW];
+  C2 m[CW];
   int col[CW];
 #pragma unroll
   for (int c = 0; c < CW; ++c) {
     const int jj = min(jj0 + c, ncol - 1);
     col[c] = jj < k0 ? jj : jj + nk;
-    m[c] = isp ? cmk(0, 0) : Mc[i + (long)n * col[c]];
+    m[c] = isp ? Cx<T>::mk(0, 0) : Mc[i + (long)n * col[c]];
   }
 #pragma unroll
   for (int c = 0; c < CW; ++c) {
     if (jj0 + c >= ncol) continue;
-    const double2* cj = Mc + (long)n * col[c];
-    double2 acc = m[c];
+    const C2* cj = Mc + (long)n * col[c];
+    C2 acc = m[c];
 #pragma unroll
-    for (int s = 0; s < PNB; ++s) acc = cfma(q[s], s < nk ? cj[pr[s]] : cmk(0, 0), acc);
+    for (int s = 0; s < PNB; ++s) acc = cfma(q[s], s < nk ? cj[pr[s]] : Cx<T>::mk(0, 0), acc);
     Mn[i + (long)n * col[c]] = acc;
   }
 }
 
+template <class T>
 __global__ void zinv_permute_kernel(int n, const double* Mg, const int* piv, double* Out,
                                     long ldo, long sO, const int* info) {
+  typedef typename Cx<T>::t C2;
   extern __shared__ int ip_s[];
   const long b = blockIdx.y;
   if (info[b]) return;
   const int* pv = piv + b * (long)n;
   for (int k = threadIdx.x; k < n; k += blockDim.x) ip_s[pv[k]] = k;
   __syncthreads();
-  const double2* M = reinterpret_cast<const double2*>(Mg) + b * (long)n * n;
-  double2* O = reinterpret_cast<double2*>(Out) + b * sO;
+  const C2* M = reinterpret_cast<const C2*>(Mg) + b * (long)n * n;
+  C2* O = reinterpret_cast<C2*>(Out) + b * sO;
   // this block handles a range of output columns
   const int cols_per_block = (n + gridDim.x - 1) / gridDim.x;
   const int j0 = blockIdx.x * cols_per_block;
@@ -321,13 +328,15 @@ __global__ void zinv_permute_kernel(int n, const double* Mg, const int* piv, dou
   }
 }
 
+template <class T>
 __global__ void copy_in_kernel(int n, const double* A, long lda, long sA, double* M) {
+  typedef typename Cx<T>::t C2;
   const long b = blockIdx.y;
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)n * n) return;
   const int i = e % n, j = e / n;
-  reinterpret_cast<double2*>(M)[b * (long)n * n + e] =
-      reinterpret_cast<const double2*>(A)[b * sA + i + lda * j];
+  reinterpret_cast<C2*>(M)[b * (long)n * n + e] =
+      reinterpret_cast<const C2*>(A)[b * sA + i + lda * j];
 }
 
 __global__ void zero_int_kernel(int* p, long cnt) {
@@ -335,30 +344,21 @@ __global__ void zero_int_kernel(int* p, long cnt) {
   if (e < cnt) p[e] = 0;
 }
 
-template <int RPL>
+template <class T, int RPL>
 void launch_panel(int n, int batch, const double* Mc, double* Mn, int k0, int* piv, int* used,
                   int* info, hipStream_t st) {
   const int waves = std::max(1, std::min(8, (n + 64 * RPL - 1) / (64 * RPL)));
-  hipLaunchKernelGGL(zinv_panel_kernel<RPL>, dim3(batch), dim3(64 * waves), 0, st, n, Mc, Mn, k0,
-                     piv, used, info);
+  hipLaunchKernelGGL((zinv_panel_kernel<T, RPL>), dim3(batch), dim3(64 * waves), 0, st, n, Mc, Mn,
+                     k0, piv, used, info);
 }
 
-}  // namespace
-
-size_t zinv_workspace_bytes(int n, int batch) {
-  if (n <= SMALL_MAX) return 0;
-  size_t nn = (size_t)n * n * 16;
-  size_t ints = (size_t)n * 4 * 2;
-  return (size_t)batch * (2 * nn + ints) + 256;
-}
-
-void zinv(int n, int batch, const double* A, long lda, long sA, double* Out, long ldo,
-          long sO, int* info, void* work, hipStream_t st) {
-  if (n <= 0 || batch <= 0) return;
-  if (batch > 65535) throw Error(1, "zinv: batch exceeds grid limit");
+template <class T>
+void zinv_t(int n, int batch, const double* A, long lda, long sA, double* Out, long ldo,
+            long sO, int* info, void* work, hipStream_t st) {
+  typedef typename Cx<T>::t C2;
   if (n <= SMALL_MAX) {
-    size_t shm = (size_t)n * n * 16 + (size_t)n * 12;
-    hipLaunchKernelGGL(zinv_small_kernel, dim3(batch), dim3(256), shm, st, n, A, lda, sA, Out,
+    size_t shm = (size_t)n * n * sizeof(C2) + (size_t)n * 12;
+    hipLaunchKernelGGL(zinv_small_kernel<T>, dim3(batch), dim3(256), shm, st, n, A, lda, sA, Out,
                        ldo, sO, info);
     HPS_LAUNCH_CHECK();
     return;
@@ -366,36 +366,53 @@ void zinv(int n, int batch, const double* A, long lda, long sA, double* Out, lon
   if (n > 64 * 32) throw Error(1, "zinv: n too large (max 2048)");
   char* w = static_cast<char*>(work);
   double* Mcur = reinterpret_cast<double*>(w);
-  w += (size_t)batch * n * n * 16;
+  w += (size_t)batch * n * n * sizeof(C2);
   double* Mnext = reinterpret_cast<double*>(w);
-  w += (size_t)batch * n * n * 16;
+  w += (size_t)batch * n * n * sizeof(C2);
   int* piv = reinterpret_cast<int*>(w);
   int* used = piv + (size_t)batch * n;
   {
     long tot = (long)n * n;
-    hipLaunchKernelGGL(copy_in_kernel, dim3(cdiv(tot, 256), batch), dim3(256), 0, st, n, A, lda,
-                       sA, Mcur);
+    hipLaunchKernelGGL(copy_in_kernel<T>, dim3(cdiv(tot, 256), batch), dim3(256), 0, st, n, A,
+                       lda, sA, Mcur);
     long ni = 2L * batch * n;
     hipLaunchKernelGGL(zero_int_kernel, dim3(cdiv(ni, 256)), dim3(256), 0, st, piv, ni);
     HPS_LAUNCH_CHECK();
   }
   for (int k0 = 0; k0 < n; k0 += PNB) {
-    if (n <= 512) launch_panel<1>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
-    else if (n <= 1024) launch_panel<2>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
-    else launch_panel<4>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
+    if (n <= 512) launch_panel<T, 1>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
+    else if (n <= 1024) launch_panel<T, 2>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
+    else launch_panel<T, 4>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
     HPS_LAUNCH_CHECK();
     const int ncol = n - std::min(PNB, n - k0);
     if (ncol > 0) {
-      hipLaunchKernelGGL(zinv_update_kernel, dim3(cdiv(n, 64), cdiv(ncol, UJ), batch), dim3(256),
-                         0, st, n, Mcur, Mnext, k0, piv, info);
+      hipLaunchKernelGGL(zinv_update_kernel<T>, dim3(cdiv(n, 64), cdiv(ncol, UJ), batch),
+                         dim3(256), 0, st, n, Mcur, Mnext, k0, piv, info);
       HPS_LAUNCH_CHECK();
     }
     std::swap(Mcur, Mnext);
   }
   int blocks_x = std::min(n, 64);
-  hipLaunchKernelGGL(zinv_permute_kernel, dim3(blocks_x, batch), dim3(256), n * sizeof(int), st,
-                     n, Mcur, piv, Out, ldo, sO, info);
+  hipLaunchKernelGGL(zinv_permute_kernel<T>, dim3(blocks_x, batch), dim3(256), n * sizeof(int),
+                     st, n, Mcur, piv, Out, ldo, sO, info);
   HPS_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+size_t zinv_workspace_bytes(int n, int batch, bool c64) {
+  if (n <= SMALL_MAX) return 0;
+  size_t nn = (size_t)n * n * (c64 ? 8 : 16);
+  size_t ints = (size_t)n * 4 * 2;
+  return (size_t)batch * (2 * nn + ints) + 256;
+}
+
+void zinv(int n, int batch, const double* A, long lda, long sA, double* Out, long ldo,
+          long sO, int* info, void* work, hipStream_t st, bool c64) {
+  if (n <= 0 || batch <= 0) return;
+  if (batch > 65535) throw Error(1, "zinv: batch exceeds grid limit");
+  if (c64) zinv_t<float>(n, batch, A, lda, sA, Out, ldo, sO, info, work, st);
+  else zinv_t<double>(n, batch, A, lda, sA, Out, ldo, sO, info, work, st);
 }
 
 }  // namespace hps
