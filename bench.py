@@ -28,7 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "HPS build DOF/s + RHS solves/s at stated rel. L2 error; p99 solve latency"
-PEAK = {"hbm": (8000.0, "GB/s"), "mfma": (78.6, "TFLOP/s"), "alu": (78.6, "TFLOP/s")}
+PEAK = {"hbm": (8000.0, "GB/s"), "mfma": (78.6, "TFLOP/s"), "mfma32": (157.3, "TFLOP/s"),
+        "alu": (78.6, "TFLOP/s")}
 # GEMM variant recorded by the library ("MxN" tile + real/complex A and B) -> kernel
 GEMM_TILES = {"16x64": (16, 64, 1, 4), "64x16": (64, 16, 4, 1), "32x32": (32, 32, 2, 2),
               "32x64": (32, 64, 2, 2), "64x32": (64, 32, 2, 2), "64x64": (64, 64, 2, 2)}
@@ -56,15 +57,19 @@ def measured_traffic(kernel):
 def kernel_of(stage, p):
     """The one kernel behind a timing record of the library, with its roofline bound,
     or None when the record covers several kernels."""
+    import re
     base = stage.split("@")[0].split("[")[0]
     if "[" in stage:
         var = stage[stage.index("[") + 1:-1]
-        bm, bn, wr, wc = GEMM_TILES[var[:-2]]
-        ar, br = ("true" if var[-2] == "r" else "false"), ("true" if var[-1] == "r" else "false")
-        return "zgemm_kernel<%d, %d, %d, %d, %s, %s>" % (bm, bn, wr, wc, ar, br), "mfma"
-    return {"leaf_inv": ("leaf_inv_kernel<%d>" % p, "alu"),
-            "leaf_xzs": ("leaf_xzs_kernel<%d>" % p, "alu"),
-            "leaf_r": ("leaf_r_kernel", "hbm")}.get(base)
+        mt = re.fullmatch(r"(\d+x\d+)([rc])([rc])(s?)", var)
+        bm, bn, wr, wc = GEMM_TILES[mt.group(1)]
+        ar, br = ("true" if mt.group(2) == "r" else "false"), ("true" if mt.group(3) == "r" else "false")
+        if mt.group(4):  # complex64 operands on the FP32 matrix cores
+            return "zgemm_kernel<float, %d, %d, %d, %d, false, false>" % (bm, bn, wr, wc), "mfma32"
+        return "zgemm_kernel<double, %d, %d, %d, %d, %s, %s>" % (bm, bn, wr, wc, ar, br), "mfma"
+    return {"leaf_sinv": ("leaf_sinv_kernel<%d, %s>" % (p, "true" if p <= 13 else "false"), "alu"),
+            "leaf_psi_i": ("leaf_psi_i_kernel<%d>" % p, "alu"),
+            "leaf_bnd": ("leaf_bnd_kernel<%d>" % p, "alu")}.get(base)
 
 
 def log(*a):
@@ -119,6 +124,39 @@ def cpu_baseline(nx, ny, p, kappa, nrhs, seed):
                       % (nrhs, nx, ny, x1, y1, p, kappa, nx * ny / 4096.0)}
 
 
+def mixed_leg(H, torch, dom, p, kappa, c_d, s_d, t_d, u_ref, exact, stream, out, reps=3):
+    """The same build + 16-RHS solve with complex64 merges and solve products (FP64
+    leaves, top 3 levels and residual correction), against the complex128 result."""
+    u_c128 = u_ref.clone()
+    u = torch.empty_like(u_ref)
+    f = H.hps_build(dom, p, kappa, kappa, c_d, stream=stream, precision=H.HPS_PREC_MIXED)
+    H.hps_solve(f, t_d, s_d, u)
+    f.free()
+    torch.cuda.synchronize()
+    bms, sms = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        f = H.hps_build(dom, p, kappa, kappa, c_d, stream=stream, precision=H.HPS_PREC_MIXED)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        H.hps_solve(f, t_d, s_d, u)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        it, conv, corr = f.last_solve_info()
+        f.free()
+        bms.append((t1 - t0) * 1e3)
+        sms.append((t2 - t1) * 1e3)
+    um, uc = u.cpu().numpy(), u_c128.cpu().numpy()
+    b, s_ = float(np.median(bms)), float(np.median(sms))
+    return {"build_ms": round(b, 3), "solve_ms": round(s_, 3),
+            "correction_steps": it, "converged": conv, "last_relative_correction": corr,
+            "rel_l2_vs_c128": float(np.linalg.norm(um - uc) / np.linalg.norm(uc)),
+            "rel_l2_vs_exact": float(np.linalg.norm(um - exact) / np.linalg.norm(exact)),
+            "build_speedup_vs_c128": round(out["build_ms"] / b, 3),
+            "solve_speedup_vs_c128": round(out["solve_ms"] / s_, 3),
+            "fp64_top_levels": 3}
+
+
 def copy_calibration(torch, dev, mib=256, reps=3):
     """A plain device-to-device copy of `mib` MiB, `reps` times: the HBM byte counters
     of a profiler run over this command read what one copy of known size costs."""
@@ -143,6 +181,8 @@ def main():
     ap.add_argument("--cpu-leaves", default="64x32",
                     help="leaf grid of the oracle's sample of the workload (NXxNY)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision (complex64 + FP64 correction) leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for scaling the HBM "
                          "byte counters of a profiler run) and exit")
@@ -250,7 +290,8 @@ def main():
     else:
         achieved = fl / (ms * 1e-3) / 1e12
         per_launch = fl / launches
-    roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+    roofline = {"bound": "mfma" if bound == "mfma32" else bound, "achieved": round(achieved, 3),
+                "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4), "traffic": measured_traffic(kname),
                 "kernel": kname, "launches_per_step": launches,
                 "avg_launch_ms": round(ms / launches, 5),
@@ -280,6 +321,9 @@ def main():
         "roofline": roofline,
         "stages_ms": {k: round(v[1], 3) for k, v in groups.items()},
     }
+    if not args.no_mixed:
+        out["mixed_precision"] = mixed_leg(H, torch, dom, p, kappa, c_d, s_d, t_d, u_d, exact,
+                                           stream, out)
     if not args.no_cpu_baseline:
         cx, cy = (int(v) for v in args.cpu_leaves.lower().split("x"))
         log("cpu baseline (oracle) on %dx%d leaves" % (cx, cy))
