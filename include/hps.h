@@ -183,6 +183,27 @@ int hps_build(const hps_domain* dom, int32_t p, double kappa, double eta_re,
  * Errors: HPS_E_INVALID (NULL factor/t/u, nrhs < 1), HPS_E_NOMEM, HPS_E_DEVICE. */
 int hps_solve(hps_factor* f, int32_t nrhs, const double* s, const double* t, double* u);
 
+/* Cross-problem batching (not in the paper; the paper's parallelism is over the boxes
+ * of one problem).  Builds nprob independent problems; problems with the same domain,
+ * leaf grid and p are factored together, every leaf and merge-level launch covering all
+ * of them.  Arguments are arrays of length nprob with the meaning of hps_build's
+ * (c_interior[i] a device pointer); opts apply to all.  out[i] receives problem i's
+ * handle; handles of one group share its device memory, which is released with the
+ * last of them (hps_free).  Each handle works with every other entry point.  On failure
+ * every out[i] is NULL and nothing leaks.  Errors: as hps_build. */
+int hps_build_batch(int32_t nprob, const hps_domain* doms, const int32_t* p,
+                    const double* kappa, const double* eta_re, const double* eta_im,
+                    const double* const* c_interior, const hps_opts* opts, hps_factor** out);
+
+/* Batched solve: for i < nprob, solve problem f[i] for nrhs[i] right-hand sides
+ * (s[i] may be NULL, and s itself may be NULL for all-zero body loads; t[i], u[i] as for
+ * hps_solve).  Requests on problems of one group run as one solve over all of them (the
+ * right-hand sides padded with zeros to the largest nrhs[i] of the group), so every
+ * per-level launch covers all those problems.  A problem may appear once per call.
+ * Synchronizes the stream when residual correction is on.  Errors: as hps_solve. */
+int hps_solve_batch(int32_t nprob, hps_factor* const* f, const int32_t* nrhs,
+                    const double* const* s, const double* const* t, double* const* u);
+
 /* Solve with right-hand sides on the shared-edge rows of the global collocation system
  * (not in the paper; the correction step of a reduced-precision solve).  As hps_solve,
  * plus

@@ -208,11 +208,18 @@ bool split_x_rule(int wx, int wy) {
 }  // namespace
 }  // namespace hps
 
-struct hps_factor {
+// Factorizations of nprob problems of one shape (domain, leaf grid, p) held together:
+// every level's launches cover all of them (cross-problem batching).  Problem b owns
+// leaves [b nl1, (b+1) nl1) and, on level l, boxes [b 2^l, (b+1) 2^l) in tree order.
+struct hps_group {
   int p = 0, m = 0, n = 0, nb = 0, ni = 0;
-  int nx = 0, ny = 0, L = 0, nleaf = 0;
+  int nx = 0, ny = 0, L = 0;
+  int nprob = 1;                           // problems in the group
+  int nl1 = 0;                             // leaves per problem (nx * ny)
+  int nleaf = 0;                           // leaves of all problems
   double x0 = 0, x1 = 0, y0 = 0, y1 = 0;
-  double kappa = 0, eta_re = 0, eta_im = 0;
+  std::vector<double> prm_h;               // [nprob][4]: kappa, Re eta, Im eta, 0
+  hps::DevBuf dprm;
   hipStream_t stream = nullptr;
   hps_opts opts{};
   std::vector<std::vector<hps::Geo>> geo;  // per level, tree order
@@ -237,8 +244,14 @@ struct hps_factor {
                rbuf[0].bytes + rbuf[1].bytes + dc.bytes;
     for (auto& r : rkeep) t += r.bytes;
     for (auto& l : lv) t += l.dmaps.bytes;
-    return t;
+    return t + dprm.bytes;
   }
+};
+
+// Public handle: problem b0 of a group (the group lives while any handle does).
+struct hps_factor {
+  std::shared_ptr<hps_group> g;
+  int b0 = 0;
 };
 
 namespace hps {
@@ -251,9 +264,9 @@ int ilog2(int v) {
 }
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-void make_plan(hps_factor& f) {
+void make_plan(hps_group& f) {
   const int m = f.m;
-  f.L = ilog2(f.nleaf);
+  f.L = ilog2(f.nl1);
   f.geo.assign(f.L + 1, {});
   f.geo[0].push_back({0, 0, f.nx, f.ny});
   f.lv.clear();
@@ -276,7 +289,7 @@ void make_plan(hps_factor& f) {
       }
     }
     LevelPlan& P = f.lv[l];
-    P.nbox = 1 << l;
+    P.nbox = (1 << l) * f.nprob;
     P.wx = g0.wx;
     P.wy = g0.wy;
     P.split_x = sx;
@@ -371,7 +384,8 @@ void make_plan(hps_factor& f) {
     P.ja.resize((size_t)P.nbox * P.n3);
     P.jb.resize((size_t)P.nbox * P.n3);
     for (int b = 0; b < P.nbox; ++b) {
-      const Geo& g = f.geo[l][b];
+      const int prob = b >> l;  // boxes of problem prob: [prob 2^l, (prob+1) 2^l)
+      const Geo& g = f.geo[l][b & ((1 << l) - 1)];
       for (int t = 0; t < P.n3; ++t) {
         const int blk = t / m, q = t % m;
         int la, lb, pa, pb;
@@ -382,19 +396,20 @@ void make_plan(hps_factor& f) {
           const int ix = g.ix0 + blk, iya = g.iy0 + g.wy / 2 - 1;
           la = iya * f.nx + ix; lb = la + f.nx; pa = 2 * m + q; pb = q;
         }
-        P.ja[(size_t)b * P.n3 + t] = la * f.nb + pa;
-        P.jb[(size_t)b * P.n3 + t] = lb * f.nb + pb;
+        P.ja[(size_t)b * P.n3 + t] = (prob * f.nl1 + la) * f.nb + pa;
+        P.jb[(size_t)b * P.n3 + t] = (prob * f.nl1 + lb) * f.nb + pb;
       }
     }
   }
   f.leaf_grid.resize(f.nleaf);
   for (int h = 0; h < f.nleaf; ++h) {
-    const Geo& g = f.geo[f.L][h];
-    f.leaf_grid[h] = g.iy0 * f.nx + g.ix0;
+    const Geo& g = f.geo[f.L][h % f.nl1];
+    f.leaf_grid[h] = (h / f.nl1) * f.nl1 + g.iy0 * f.nx + g.ix0;
   }
 }
 
 // ------------------------------------------------------------------ leaf line tables
+void leaf_table_one(const hps_group& f, const double* all, double er, double ei, double* out);
 // The leaf stage eliminates the boundary nodes through the impedance rows F = N + i eta
 // (Sec. 2.1).  F_bb couples only the two end nodes of a grid line: (S_i, N_i) through
 // the first and last rows of D_y, (W_j, E_j) through those of D_x.  With their 2 x 2
@@ -410,7 +425,16 @@ void make_plan(hps_factor& f) {
 //     Dxx(i,p-1) C21 in W_j and wE[i] = -Dxx(i,0) C12 - Dxx(i,p-1) C22 in E_j.
 // (A = -Dxx - Dyy - kappa^2 c, so A_ib holds -Dxx(i,0), -Dxx(i,p-1), -Dyy(j,0),
 // -Dyy(j,p-1).)  Indices i, j, k, l run over the interior points 1..p-2.
-void leaf_tables(hps_factor& f, const double* all) {
+void leaf_tables(hps_group& f, const double* all) {
+  const int len = leaf_table_len(f.p);
+  std::vector<double> flat((size_t)2 * len * f.nprob);
+  for (int b = 0; b < f.nprob; ++b)
+    leaf_table_one(f, all, f.prm_h[4 * b + 1], f.prm_h[4 * b + 2], flat.data() + (size_t)2 * len * b);
+  upload(f.dLT, flat);
+}
+
+// the line table of one problem (eta = er + i ei) into out (2 * leaf_table_len doubles)
+void leaf_table_one(const hps_group& f, const double* all, double er, double ei, double* out) {
   using cd = std::complex<double>;
   const int p = f.p, m = f.m;
   const double* Dx1 = all;
@@ -418,7 +442,7 @@ void leaf_tables(hps_factor& f, const double* all) {
   const double* Dxx = all + 2 * p * p;
   const double* Dyy = all + 3 * p * p;
   auto at = [p](const double* A, int i, int k) { return A[i + p * k]; };
-  const cd ie(-f.eta_im, f.eta_re);  // i eta
+  const cd ie(-ei, er);  // i eta
   auto inv2 = [](cd a11, cd a12, cd a21, cd a22, cd* o) {
     const cd det = a11 * a22 - a12 * a21;
     if (!(std::abs(det) > 0.0))
@@ -464,15 +488,13 @@ void leaf_tables(hps_factor& f, const double* all) {
     by[q] = B[q];
     bx[q] = Cm[q];
   }
-  std::vector<double> flat(2 * tab.size());
   for (size_t e = 0; e < tab.size(); ++e) {
-    flat[2 * e] = tab[e].real();
-    flat[2 * e + 1] = tab[e].imag();
+    out[2 * e] = tab[e].real();
+    out[2 * e + 1] = tab[e].imag();
   }
-  upload(f.dLT, flat);
 }
 
-void upload_plan(hps_factor& f) {
+void upload_plan(hps_group& f) {
   for (auto& P : f.lv) {
     std::vector<int> all;
     auto app = [&](const std::vector<int>& v) { all.insert(all.end(), v.begin(), v.end()); };
@@ -519,9 +541,10 @@ void upload_plan(hps_factor& f) {
     }
   upload(f.dD, all);
   leaf_tables(f, all.data());
+  upload(f.dprm, f.prm_h);
 }
 
-MergeLevelDesc level_desc(const hps_factor& f, const LevelPlan& P) {
+MergeLevelDesc level_desc(const hps_group& f, const LevelPlan& P) {
   MergeLevelDesc d;
   d.nbox = P.nbox; d.nbc = P.nbc; d.n1 = P.n1; d.n2 = P.n2; d.n3 = P.n3; d.nbp = P.nbp;
   d.codeA = P.dcodeA; d.codeB = P.dcodeB; d.perm = P.dperm;
@@ -550,19 +573,19 @@ struct BuildScratch {
 };
 
 // bytes of one complex entry of level l's operators and R (the leaves' R is complex128)
-size_t cbytes(const hps_factor& f, int l) { return (l < f.L && f.lv[l].c64) ? 8 : 16; }
+size_t cbytes(const hps_group& f, int l) { return (l < f.L && f.lv[l].c64) ? 8 : 16; }
 
-bool level_forms_R(const hps_factor& f, int l) {
+bool level_forms_R(const hps_group& f, int l) {
   return l == f.L || l > 0 || f.opts.store_root_R;
 }
 
-size_t level_R_bytes(const hps_factor& f, int l) {
+size_t level_R_bytes(const hps_group& f, int l) {
   if (l == f.L) return (size_t)f.nleaf * f.nb * f.nb * 16;
   const LevelPlan& P = f.lv[l];
   return (size_t)P.nbox * P.nbp * P.nbp * cbytes(f, l);
 }
 
-void plan_memory(hps_factor& f, BuildScratch& sc) {
+void plan_memory(hps_group& f, BuildScratch& sc) {
   const long nl = f.nleaf, n = f.n, nb = f.nb, ni = f.ni;
   for (int pass = 0; pass < 2; ++pass) {
     Carver c;
@@ -644,11 +667,11 @@ void level_scratch(const LevelPlan& P, BuildScratch& sc) {
 }
 
 // ------------------------------------------------------------------ build
-void build_leaves(hps_factor& f, const double* c, BuildScratch& sc) {
+void build_leaves(hps_group& f, const double* c, BuildScratch& sc) {
   hipStream_t st = f.stream;
   const long nl = f.nleaf;
   LeafDesc d;
-  d.p = f.p; d.nleaf = f.nleaf; d.kappa = f.kappa; d.eta_re = f.eta_re; d.eta_im = f.eta_im;
+  d.p = f.p; d.nleaf = f.nleaf; d.nl1 = f.nl1; d.prm = f.dprm.d();
   d.c = c; d.leaf_grid = f.dleaf_grid.i(); d.tab = f.dLT.d(); d.BI = f.BI.d();
   d.R = f.R[f.L].d(); d.info = sc.info.i();
   d.Mg = leaf_scratch_bytes(f.p, nl) ? static_cast<double*>(sc.buf.p) : nullptr;
@@ -660,6 +683,7 @@ void build_leaves(hps_factor& f, const double* c, BuildScratch& sc) {
     LeafDesc dc = d;
     dc.nleaf = cnt;
     dc.leaf_grid = d.leaf_grid + h0;
+    dc.h0 = h0;
     dc.BI = d.BI + 2 * h0 * n * n;
     dc.R = d.R + 2 * h0 * nb * nb;
     dc.info = d.info + h0;
@@ -683,7 +707,7 @@ void build_leaves(hps_factor& f, const double* c, BuildScratch& sc) {
   f.R_valid[f.L] = 1;
 }
 
-void build_level(hps_factor& f, int l, BuildScratch& sc) {
+void build_level(hps_group& f, int l, BuildScratch& sc) {
   hipStream_t st = f.stream;
   LevelPlan& P = f.lv[l];
   const long nbox = P.nbox, n1 = P.n1, n2 = P.n2, n3 = P.n3, nbp = P.nbp;
@@ -779,7 +803,7 @@ void build_level(hps_factor& f, int l, BuildScratch& sc) {
   if (!f.opts.keep_all_R) f.R_valid[l + 1] = 0;
 }
 
-void build_all(hps_factor& f, const double* c) {
+void build_all(hps_group& f, const double* c) {
   BuildScratch sc;
   plan_memory(f, sc);
   fill_zero_int(sc.info.i(), (long)(sc.info.bytes / sizeof(int)), f.stream);
@@ -857,13 +881,19 @@ struct Arena {
   }
 };
 
-void solve_pass(hps_factor& f, int nrhs, const double* s, const double* t, const double* jmp,
-                double* u, Arena& ws) {
+// Solve sweeps of Algorithm 2 for problems [pb, pb + np) of the group, nrhs right-hand
+// sides each.  Layouts (complex128): s [nrhs][np nl1 ni], jmp [nrhs][np nl1 nb],
+// t [np][nrhs][nt], u [nrhs][np nl1 n].
+void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const double* t,
+                const double* jmp, double* u, Arena& ws) {
   hipStream_t st = f.stream;
   Profiler& pr = f.solve_prof;
   pr.reset(!ws.dry && f.opts.profile != 0, st);
   const char* nm = "solve_leaf_up";
-  const long nl = f.nleaf, n = f.n, nb = f.nb, ni = f.ni;
+  const long nl = (long)np * f.nl1, n = f.n, nb = f.nb, ni = f.ni;
+  const long h0 = (long)pb * f.nl1;  // first leaf of the range
+  const int le = f.mixed ? 1 : 2;    // doubles per complex entry of the leaf operators
+  const double* leafops = (f.mixed ? f.BI32.d() : f.BI.d()) + le * h0 * n * n;
   // the upward pass runs for a body load or for right-hand sides on shared-edge rows
   const bool up = (s != nullptr) || (jmp != nullptr);
   std::vector<double*> h(f.L + 1, nullptr), tt(f.L + 1, nullptr), tta(f.L, nullptr),
@@ -876,14 +906,14 @@ void solve_pass(hps_factor& f, int nrhs, const double* s, const double* t, const
       // leaf: u~ = Y s   (Algorithm 2 step (3))
       SkinnyDesc k;
       k.M = n; k.K = ni; k.nrhs = nrhs; k.batch = (int)nl;
-      k.A = f.mixed ? f.BI32.d() + n * nb : f.BI.d() + 2 * n * nb;
-      k.a_c64 = f.mixed;
+      k.A = leafops + le * n * nb; k.a_c64 = f.mixed;
       k.lda = n; k.sA = n * n;
-      k.X = s; k.ldx = nl * ni; k.xoff = f.dxoff.l();
+      k.X = s; k.ldx = nl * ni; k.xoff = f.dxoff.l() + h0; k.xbase = h0 * ni;
       k.C = ut; k.ldc = n; k.sC = n * nrhs;
       ws.skinny(pr, nm, k);
       Stage sg(pr, "solve_gather", 0.0, nl * nb * nrhs * 32.0);
-      if (!ws.dry) leaf_h_from_u(f.nleaf, f.n, f.nb, nrhs, f.eta_re, f.eta_im, ut, h[f.L], st);
+      if (!ws.dry)
+        leaf_h_from_u((int)nl, f.n, f.nb, nrhs, f.dprm.d() + 4 * pb, f.nl1, ut, h[f.L], st);
     } else if (!ws.dry) {
       fill_zero(ut, 2 * nl * n * nrhs, st);
       fill_zero(h[f.L], 2 * nl * nb * nrhs, st);
@@ -893,7 +923,11 @@ void solve_pass(hps_factor& f, int nrhs, const double* s, const double* t, const
     for (int l = f.L - 1; l >= 0; --l) {
       LevelPlan& P = f.lv[l];
       MergeLevelDesc d = level_desc(f, P);
-      const long nbox = P.nbox, n1 = P.n1, n2 = P.n2, n3 = P.n3, nbp = P.nbp;
+      const long nbox = (long)np << l, box0 = (long)pb << l;
+      d.nbox = (int)nbox;
+      const long n1 = P.n1, n2 = P.n2, n3 = P.n3, nbp = P.nbp;
+      const int e = P.c64 ? 1 : 2;
+      auto op = [&](const View& v, long per) { return v.d() + box0 * per * e; };
       double* h3a = ws.get((size_t)nbox * n3 * nrhs * 16);
       double* v = ws.get((size_t)nbox * n3 * nrhs * 16);
       tta[l] = ws.get((size_t)nbox * n3 * nrhs * 16);
@@ -903,43 +937,40 @@ void solve_pass(hps_factor& f, int nrhs, const double* s, const double* t, const
         Stage sg(pr, "solve_gather", 0.0, nbox * (2.0 * P.nbc + 3.0 * n3 + nbp) * nrhs * 16);
         if (!ws.dry)
           up_gather(d, nrhs, h[l + 1], h3a, v, ttb[l], h[l], jmp, nl * nb,
-                    jmp ? P.dja : nullptr, jmp ? P.djb : nullptr, st);
+                    jmp ? P.dja + box0 * n3 : nullptr, jmp ? P.djb + box0 * n3 : nullptr,
+                    h0 * nb, st);
       }
       // v = R33b h3a - h3b
       SkinnyDesc k;
-      k.M = n3; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox;
-      k.a_c64 = P.c64;
-      k.A = P.R33b.d(); k.lda = n3; k.sA = n3 * n3;
+      k.M = n3; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox; k.a_c64 = P.c64;
+      k.A = op(P.R33b, n3 * n3); k.lda = n3; k.sA = n3 * n3;
       k.X = h3a; k.ldx = n3; k.sX = n3 * nrhs;
       k.C = v; k.ldc = n3; k.sC = n3 * nrhs; k.accumulate = true;
       ws.skinny(pr, nm, k);
       // t~3a = W^{-1} v
       k = SkinnyDesc();
-      k.M = n3; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox;
-      k.a_c64 = P.c64;
-      k.A = P.Winv.d(); k.lda = n3; k.sA = n3 * n3;
+      k.M = n3; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox; k.a_c64 = P.c64;
+      k.A = op(P.Winv, n3 * n3); k.lda = n3; k.sA = n3 * n3;
       k.X = v; k.ldx = n3; k.sX = n3 * nrhs;
       k.C = tta[l]; k.ldc = n3; k.sC = n3 * nrhs;
       ws.skinny(pr, nm, k);
       // t~3b = -h3a - R33a t~3a
       k = SkinnyDesc();
-      k.M = n3; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox;
-      k.a_c64 = P.c64;
-      k.A = P.R33a.d(); k.lda = n3; k.sA = n3 * n3;
+      k.M = n3; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox; k.a_c64 = P.c64;
+      k.A = op(P.R33a, n3 * n3); k.lda = n3; k.sA = n3 * n3;
       k.X = tta[l]; k.ldx = n3; k.sX = n3 * nrhs;
       k.C = ttb[l]; k.ldc = n3; k.sC = n3 * nrhs; k.accumulate = true; k.alpha = -1.0;
       ws.skinny(pr, nm, k);
       if (l > 0) {
         // h^tau = [h1a + R13a t~3a ; h2b + R23b t~3b]   (eq. (flux_part))
         k = SkinnyDesc();
-        k.M = n1; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox;
-        k.a_c64 = P.c64;
-        k.A = P.R13a.d(); k.lda = n1; k.sA = n1 * n3;
+        k.M = n1; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox; k.a_c64 = P.c64;
+        k.A = op(P.R13a, n1 * n3); k.lda = n1; k.sA = n1 * n3;
         k.X = tta[l]; k.ldx = n3; k.sX = n3 * nrhs;
         k.C = h[l]; k.ldc = nbp; k.sC = nbp * nrhs; k.crow = P.dperm; k.accumulate = true;
         ws.skinny(pr, nm, k);
         k.M = n2;
-        k.A = P.R23b.d(); k.lda = n2; k.sA = n2 * n3;
+        k.A = op(P.R23b, n2 * n3); k.lda = n2; k.sA = n2 * n3;
         k.X = ttb[l];
         k.crow = P.dperm + n1;
         ws.skinny(pr, nm, k);
@@ -951,7 +982,10 @@ void solve_pass(hps_factor& f, int nrhs, const double* s, const double* t, const
   for (int l = 0; l < f.L; ++l) {
     LevelPlan& P = f.lv[l];
     MergeLevelDesc d = level_desc(f, P);
-    const long nbox = P.nbox, n3 = P.n3, nbp = P.nbp, nbc = P.nbc;
+    const long nbox = (long)np << l, box0 = (long)pb << l;
+    d.nbox = (int)nbox;
+    const long n3 = P.n3, nbp = P.nbp, nbc = P.nbc;
+    const int e = P.c64 ? 1 : 2;
     const double* tp = (l == 0) ? t : tt[l];
     const long sp = nbp * nrhs;
     tt[l + 1] = ws.get((size_t)2 * nbox * nbc * nrhs * 16);
@@ -961,9 +995,9 @@ void solve_pass(hps_factor& f, int nrhs, const double* s, const double* t, const
     }
     for (int side = 0; side < 2; ++side) {
       SkinnyDesc k;
-      k.M = n3; k.K = nbp; k.nrhs = nrhs; k.batch = (int)nbox;
-      k.A = side ? P.PhiB.d() : P.PhiA.d(); k.lda = n3; k.sA = n3 * nbp;
-      k.a_c64 = P.c64;
+      k.M = n3; k.K = nbp; k.nrhs = nrhs; k.batch = (int)nbox; k.a_c64 = P.c64;
+      k.A = (side ? P.PhiB.d() : P.PhiA.d()) + box0 * n3 * nbp * e;
+      k.lda = n3; k.sA = n3 * nbp;
       k.X = tp; k.ldx = nbp; k.sX = sp;
       k.C = tt[l + 1] + 2 * (side ? nbc * nrhs : 0); k.ldc = nbc; k.sC = 2 * nbc * nrhs;
       k.crow = side ? P.di3b : P.di3a;
@@ -977,12 +1011,10 @@ void solve_pass(hps_factor& f, int nrhs, const double* s, const double* t, const
   {
     nm = "solve_leaf_down";
     SkinnyDesc k;
-    k.M = n; k.K = nb; k.nrhs = nrhs; k.batch = (int)nl;
-    k.A = f.mixed ? f.BI32.d() : f.BI.d();
-    k.a_c64 = f.mixed;
-    k.lda = n; k.sA = n * n;
+    k.M = n; k.K = nb; k.nrhs = nrhs; k.batch = (int)nl; k.a_c64 = f.mixed;
+    k.A = leafops; k.lda = n; k.sA = n * n;
     k.X = (f.L == 0) ? t : tt[f.L]; k.ldx = nb; k.sX = nb * nrhs;
-    k.C = u; k.ldc = nl * n; k.coff = f.duoff.l();
+    k.C = u; k.ldc = nl * n; k.coff = f.duoff.l() + h0; k.cbase = h0 * n;
     if (up) {
       k.C0 = ut; k.ld0 = n; k.s0 = n * nrhs;
     }
@@ -1085,63 +1117,143 @@ int hps_nodes(const hps_domain* dom, int32_t p, double* xy_leaf, double* xy_inte
   });
 }
 
+namespace hps {
+namespace {
+
+void check_problem(const hps_domain* dom, int p, double kappa, double er, double ei,
+                   const double* c) {
+  validate_domain(dom, p);
+  if (!c) throw Error(HPS_E_INVALID, "c_interior is NULL");
+  if (!std::isfinite(kappa) || kappa < 0) throw Error(HPS_E_INVALID, "kappa must be finite, >= 0");
+  if (!std::isfinite(er) || !std::isfinite(ei) || er == 0.0)
+    throw Error(HPS_E_INVALID, "eta must be finite with Re(eta) != 0");
+}
+
+// Build the factorizations of nprob problems that share domain, leaf grid and p.
+std::shared_ptr<hps_group> build_group(const hps_domain& dom, int p, int nprob,
+                                       const double* kappa, const double* er, const double* ei,
+                                       const double* const* c, const hps_opts* opts) {
+  auto f = std::make_shared<hps_group>();
+  if (opts) f->opts = *opts; else hps_default_opts(&f->opts);
+  if (f->opts.precision != HPS_PREC_C128 && f->opts.precision != HPS_PREC_MIXED)
+    throw Error(HPS_E_INVALID, "unsupported precision mode");
+  if (f->opts.fp64_top_levels < 0) throw Error(HPS_E_INVALID, "fp64_top_levels must be >= 0");
+  if (!(f->opts.refine_tol > 0.0)) throw Error(HPS_E_INVALID, "refine_tol must be > 0");
+  f->mixed = f->opts.precision == HPS_PREC_MIXED;
+  f->p = p; f->m = p - 2; f->n = p * p - 4; f->nb = 4 * (p - 2); f->ni = (p - 2) * (p - 2);
+  f->nx = dom.nx; f->ny = dom.ny;
+  f->nprob = nprob; f->nl1 = dom.nx * dom.ny; f->nleaf = f->nl1 * nprob;
+  f->x0 = dom.x0; f->x1 = dom.x1; f->y0 = dom.y0; f->y1 = dom.y1;
+  f->prm_h.assign((size_t)4 * nprob, 0.0);
+  for (int b = 0; b < nprob; ++b) {
+    f->prm_h[4 * b] = kappa[b];
+    f->prm_h[4 * b + 1] = er[b];
+    f->prm_h[4 * b + 2] = ei[b];
+  }
+  f->stream = static_cast<hipStream_t>(f->opts.stream);
+  make_plan(*f);
+  for (int l = 0; l < f->L; ++l) f->lv[l].c64 = f->mixed && l >= f->opts.fp64_top_levels;
+  upload_plan(*f);
+  // the group's own copy of c (problem-major), read by the leaf stage and the residual
+  const size_t per = (size_t)f->nl1 * f->ni * sizeof(double);
+  f->dc.alloc(per * nprob);
+  for (int b = 0; b < nprob; ++b)
+    HPS_HIP(hipMemcpyAsync(static_cast<char*>(f->dc.p) + per * b, c[b], per,
+                           hipMemcpyDeviceToDevice, f->stream));
+  f->build_prof.reset(f->opts.profile != 0, f->stream);
+  build_all(*f, f->dc.d());
+  return f;
+}
+
+}  // namespace
+}  // namespace hps
+
 int hps_build(const hps_domain* dom, int32_t p, double kappa, double eta_re, double eta_im,
               const double* c_interior, const hps_opts* opts, hps_factor** out) {
   if (out) *out = nullptr;
   return guard([&] {
     if (!out) throw Error(HPS_E_INVALID, "out is NULL");
-    validate_domain(dom, p);
-    if (!c_interior) throw Error(HPS_E_INVALID, "c_interior is NULL");
-    if (!std::isfinite(kappa) || kappa < 0) throw Error(HPS_E_INVALID, "kappa must be finite, >= 0");
-    if (!std::isfinite(eta_re) || !std::isfinite(eta_im) || eta_re == 0.0)
-      throw Error(HPS_E_INVALID, "eta must be finite with Re(eta) != 0");
-    std::unique_ptr<hps_factor> f(new hps_factor);
-    if (opts) f->opts = *opts; else hps_default_opts(&f->opts);
-    if (f->opts.precision != HPS_PREC_C128 && f->opts.precision != HPS_PREC_MIXED)
-      throw Error(HPS_E_INVALID, "unsupported precision mode");
-    if (f->opts.fp64_top_levels < 0) throw Error(HPS_E_INVALID, "fp64_top_levels must be >= 0");
-    if (!(f->opts.refine_tol > 0.0)) throw Error(HPS_E_INVALID, "refine_tol must be > 0");
-    f->mixed = f->opts.precision == HPS_PREC_MIXED;
-    f->p = p; f->m = p - 2; f->n = p * p - 4; f->nb = 4 * (p - 2); f->ni = (p - 2) * (p - 2);
-    f->nx = dom->nx; f->ny = dom->ny; f->nleaf = dom->nx * dom->ny;
-    f->x0 = dom->x0; f->x1 = dom->x1; f->y0 = dom->y0; f->y1 = dom->y1;
-    f->kappa = kappa; f->eta_re = eta_re; f->eta_im = eta_im;
-    f->stream = static_cast<hipStream_t>(f->opts.stream);
-    make_plan(*f);
-    for (int l = 0; l < f->L; ++l) f->lv[l].c64 = f->mixed && l >= f->opts.fp64_top_levels;
-    upload_plan(*f);
-    f->dc.alloc((size_t)f->nleaf * f->ni * sizeof(double));
-    HPS_HIP(hipMemcpyAsync(f->dc.p, c_interior, f->dc.bytes, hipMemcpyDeviceToDevice, f->stream));
-    f->build_prof.reset(f->opts.profile != 0, f->stream);
-    build_all(*f, c_interior);
-    *out = f.release();
+    check_problem(dom, p, kappa, eta_re, eta_im, c_interior);
+    std::unique_ptr<hps_factor> h(new hps_factor);
+    h->g = build_group(*dom, p, 1, &kappa, &eta_re, &eta_im, &c_interior, opts);
+    h->b0 = 0;
+    *out = h.release();
   });
+}
+
+int hps_build_batch(int32_t nprob, const hps_domain* doms, const int32_t* p,
+                    const double* kappa, const double* eta_re, const double* eta_im,
+                    const double* const* c_interior, const hps_opts* opts, hps_factor** out) {
+  if (out && nprob > 0)
+    for (int i = 0; i < nprob; ++i) out[i] = nullptr;
+  std::vector<std::unique_ptr<hps_factor>> made;
+  int rc = guard([&] {
+    if (nprob < 1) throw Error(HPS_E_INVALID, "nprob must be >= 1");
+    if (!out || !doms || !p || !kappa || !eta_re || !eta_im || !c_interior)
+      throw Error(HPS_E_INVALID, "NULL argument");
+    for (int i = 0; i < nprob; ++i)
+      check_problem(&doms[i], p[i], kappa[i], eta_re[i], eta_im[i], c_interior[i]);
+    made.resize(nprob);
+    // problems of one shape (domain, leaf grid, p) share a group, in first-seen order
+    std::vector<char> done(nprob, 0);
+    for (int i = 0; i < nprob; ++i) {
+      if (done[i]) continue;
+      std::vector<int> mem;
+      for (int j = i; j < nprob; ++j) {
+        const hps_domain &a = doms[i], &b = doms[j];
+        if (!done[j] && p[j] == p[i] && a.nx == b.nx && a.ny == b.ny && a.x0 == b.x0 &&
+            a.x1 == b.x1 && a.y0 == b.y0 && a.y1 == b.y1) {
+          mem.push_back(j);
+          done[j] = 1;
+        }
+      }
+      std::vector<double> k(mem.size()), er(mem.size()), ei(mem.size());
+      std::vector<const double*> cs(mem.size());
+      for (size_t q = 0; q < mem.size(); ++q) {
+        k[q] = kappa[mem[q]]; er[q] = eta_re[mem[q]]; ei[q] = eta_im[mem[q]];
+        cs[q] = c_interior[mem[q]];
+      }
+      auto g = build_group(doms[i], p[i], (int)mem.size(), k.data(), er.data(), ei.data(),
+                           cs.data(), opts);
+      for (size_t q = 0; q < mem.size(); ++q) {
+        made[mem[q]].reset(new hps_factor);
+        made[mem[q]]->g = g;
+        made[mem[q]]->b0 = (int)q;
+      }
+    }
+  });
+  if (rc == HPS_OK)
+    for (int i = 0; i < nprob; ++i) out[i] = made[i].release();
+  return rc;
 }
 
 namespace hps {
 namespace {
 
-ResidualDesc residual_desc(const hps_factor& f, const double* s, const double* t,
-                           const double* jmp, const double* u) {
+ResidualDesc residual_desc(const hps_group& f, int pb, int np, int nrhs, const double* s,
+                           const double* t, const double* jmp, const double* u) {
   ResidualDesc r;
-  r.p = f.p; r.nx = f.nx; r.ny = f.ny;
-  r.kappa = f.kappa; r.eta_re = f.eta_re; r.eta_im = f.eta_im;
-  r.D = f.dD.d(); r.c = f.dc.d(); r.u = u; r.s = s; r.t = t; r.jmp = jmp;
+  r.p = f.p; r.nx = f.nx; r.ny = f.ny; r.nprob = np; r.nrhs = nrhs;
+  r.prm = f.dprm.d() + 4 * pb;
+  r.D = f.dD.d(); r.c = f.dc.d() + (long)pb * f.nl1 * f.ni;
+  r.u = u; r.s = s; r.t = t; r.jmp = jmp;
   return r;
 }
 
-int refine_iters(const hps_factor& f) {
+int refine_iters(const hps_group& f) {
   if (f.opts.refine_max_iter >= 0) return f.opts.refine_max_iter;
   return f.opts.precision == HPS_PREC_MIXED ? 10 : 0;
 }
 
-// Solve, then (when enabled) residual correction in FP64: r = b - A u on the global
-// collocation system, delta = Solve(r) with r's shared-edge rows as interface jumps,
-// u += delta, until max_r |delta_r| <= tol |u_r| or the iteration limit.
-void solve_impl(hps_factor& f, int nrhs, const double* s, const double* t, const double* jmp,
-                double* u) {
+// Solve problems [pb, pb + np), then (when enabled) residual correction in FP64:
+// r = b - A u on the global collocation system, delta = Solve(r) with r's shared-edge
+// rows as interface jumps, u += delta, until max_r |delta_r| <= tol |u_r| (norms over
+// the problems of the range) or the iteration limit.
+void solve_impl(hps_group& f, int pb, int np, int nrhs, const double* s, const double* t,
+                const double* jmp, double* u) {
   const int iters = refine_iters(f);
-  const long nl = f.nleaf, n = f.n, nb = f.nb, ni = f.ni, nt = 2L * (f.nx + f.ny) * f.m;
+  const long nl = (long)np * f.nl1, n = f.n, nb = f.nb, ni = f.ni;
+  const long nt = 2L * (f.nx + f.ny) * f.m;
   const int nblk = norms_blocks();
   Arena ws;
   ws.st = f.stream;
@@ -1151,17 +1263,17 @@ void solve_impl(hps_factor& f, int nrhs, const double* s, const double* t, const
     if (pass == 1) ws.allocate();
     if (iters > 0) {
       rs = ws.get((size_t)nrhs * nl * ni * 16);
-      rt = ws.get((size_t)nrhs * nt * 16);
+      rt = ws.get((size_t)np * nrhs * nt * 16);
       rj = ws.get((size_t)nrhs * nl * nb * 16);
       dl = ws.get((size_t)nrhs * nl * n * 16);
       part = ws.get((size_t)nrhs * nblk * 2 * sizeof(double));
     }
     mark = ws.used;
-    solve_pass(f, nrhs, s, t, jmp, u, ws);  // pass 0 only sizes the workspace
+    solve_pass(f, pb, np, nrhs, s, t, jmp, u, ws);  // pass 0 only sizes the workspace
     if (pass == 0 && iters > 0) {
       // the correction sweeps always run the upward pass: size the workspace for them too
       ws.used = mark;
-      solve_pass(f, nrhs, rs, rt, rj, dl, ws);
+      solve_pass(f, pb, np, nrhs, rs, rt, rj, dl, ws);
     }
   }
   f.last_info = hps_solve_info{};
@@ -1171,13 +1283,13 @@ void solve_impl(hps_factor& f, int nrhs, const double* s, const double* t, const
   int it = 0;
   bool conv = false;
   for (it = 1; it <= iters; ++it) {
-    ResidualDesc r = residual_desc(f, s, t, jmp, u);
+    ResidualDesc r = residual_desc(f, pb, np, nrhs, s, t, jmp, u);
     r.rs = rs; r.rs_rhs = nl * ni; r.rs_leaf = ni;
     r.rb = rj; r.rb_rhs = nl * nb; r.rb_leaf = nb;
-    r.rt = rt; r.rt_rhs = nt;
+    r.rt = rt;
     residual(r, nrhs, f.stream);
     ws.used = mark;
-    solve_pass(f, nrhs, rs, rt, rj, dl, ws);
+    solve_pass(f, pb, np, nrhs, rs, rt, rj, dl, ws);
     norms_partial(nl * n, nrhs, dl, u, part, f.stream);
     axpy((long)nrhs * nl * n, dl, u, f.stream);
     HPS_HIP(hipMemcpyAsync(hpart.data(), part, hpart.size() * sizeof(double),
@@ -1213,7 +1325,7 @@ int hps_solve(hps_factor* f, int32_t nrhs, const double* s, const double* t, dou
     if (!f) throw Error(HPS_E_INVALID, "factor is NULL");
     if (!t || !u) throw Error(HPS_E_INVALID, "t and u must be non-NULL");
     if (nrhs < 1) throw Error(HPS_E_INVALID, "nrhs must be >= 1");
-    solve_impl(*f, nrhs, s, t, nullptr, u);
+    solve_impl(*f->g, f->b0, 1, nrhs, s, t, nullptr, u);
   });
 }
 
@@ -1223,7 +1335,82 @@ int hps_solve_jumps(hps_factor* f, int32_t nrhs, const double* s, const double* 
     if (!f) throw Error(HPS_E_INVALID, "factor is NULL");
     if (!t || !u) throw Error(HPS_E_INVALID, "t and u must be non-NULL");
     if (nrhs < 1) throw Error(HPS_E_INVALID, "nrhs must be >= 1");
-    solve_impl(*f, nrhs, s, t, jumps, u);
+    solve_impl(*f->g, f->b0, 1, nrhs, s, t, jumps, u);
+  });
+}
+
+int hps_solve_batch(int32_t nprob, hps_factor* const* f, const int32_t* nrhs,
+                    const double* const* s, const double* const* t, double* const* u) {
+  return guard([&] {
+    if (nprob < 1) throw Error(HPS_E_INVALID, "nprob must be >= 1");
+    if (!f || !nrhs || !t || !u) throw Error(HPS_E_INVALID, "NULL argument");
+    for (int i = 0; i < nprob; ++i) {
+      if (!f[i] || !t[i] || !u[i]) throw Error(HPS_E_INVALID, "NULL factor, t or u");
+      if (nrhs[i] < 1) throw Error(HPS_E_INVALID, "nrhs must be >= 1");
+    }
+    // requests of one group go through one batched solve over the problem range they
+    // span (problems of the range without a request get zero data)
+    std::vector<char> done(nprob, 0);
+    for (int i = 0; i < nprob; ++i) {
+      if (done[i]) continue;
+      hps_group& G = *f[i]->g;
+      std::vector<int> mem;
+      for (int j = i; j < nprob; ++j)
+        if (!done[j] && f[j]->g.get() == &G) {
+          mem.push_back(j);
+          done[j] = 1;
+        }
+      int pb = G.nprob, pe = 0, R = 1;
+      bool any_s = false;
+      std::vector<char> seen(G.nprob, 0);
+      for (int j : mem) {
+        const int b = f[j]->b0;
+        if (seen[b]) throw Error(HPS_E_INVALID, "a problem appears twice in one batch");
+        seen[b] = 1;
+        pb = std::min(pb, b);
+        pe = std::max(pe, b + 1);
+        R = std::max(R, (int)nrhs[j]);
+        any_s = any_s || (s && s[j]);
+      }
+      const int np = pe - pb;
+      const long nl = (long)np * G.nl1, n = G.n, ni = G.ni;
+      const long nt = 2L * (G.nx + G.ny) * G.m;
+      hipStream_t st = G.stream;
+      const size_t bs = any_s ? (size_t)R * nl * ni * 16 : 0, bt = (size_t)np * R * nt * 16,
+                   bu = (size_t)R * nl * n * 16;
+      void* stage = nullptr;
+      if (hipMallocAsync(&stage, bs + bt + bu + 512, st) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(HPS_E_NOMEM, "batch staging allocation failed");
+      }
+      struct Free {
+        void* p; hipStream_t st;
+        ~Free() { (void)hipFreeAsync(p, st); }
+      } fr{stage, st};
+      char* base = static_cast<char*>(stage);
+      double* S = any_s ? reinterpret_cast<double*>(base) : nullptr;
+      double* T = reinterpret_cast<double*>(base + ((bs + 255) & ~size_t(255)));
+      double* U = reinterpret_cast<double*>(base + ((bs + 255) & ~size_t(255)) +
+                                            ((bt + 255) & ~size_t(255)));
+      if (S) fill_zero(S, (long)(bs / 8), st);
+      fill_zero(T, (long)(bt / 8), st);
+      for (int j : mem) {
+        const long o = f[j]->b0 - pb;
+        if (S && s[j])
+          HPS_HIP(hipMemcpy2DAsync(S + 2 * o * G.nl1 * ni, (size_t)nl * ni * 16, s[j],
+                                   (size_t)G.nl1 * ni * 16, (size_t)G.nl1 * ni * 16, nrhs[j],
+                                   hipMemcpyDeviceToDevice, st));
+        HPS_HIP(hipMemcpyAsync(T + 2 * o * R * nt, t[j], (size_t)nrhs[j] * nt * 16,
+                               hipMemcpyDeviceToDevice, st));
+      }
+      solve_impl(G, pb, np, R, S, T, nullptr, U);
+      for (int j : mem) {
+        const long o = f[j]->b0 - pb;
+        HPS_HIP(hipMemcpy2DAsync(u[j], (size_t)G.nl1 * n * 16, U + 2 * o * G.nl1 * n,
+                                 (size_t)nl * n * 16, (size_t)G.nl1 * n * 16, nrhs[j],
+                                 hipMemcpyDeviceToDevice, st));
+      }
+    }
   });
 }
 
@@ -1233,37 +1420,40 @@ int hps_residual(hps_factor* f, int32_t nrhs, const double* s, const double* t,
     if (!f) throw Error(HPS_E_INVALID, "factor is NULL");
     if (!u || !r) throw Error(HPS_E_INVALID, "u and r must be non-NULL");
     if (nrhs < 1) throw Error(HPS_E_INVALID, "nrhs must be >= 1");
-    const long nl = f->nleaf, n = f->n, nb = f->nb;
-    ResidualDesc d = residual_desc(*f, s, t, jumps, u);
+    hps_group& G = *f->g;
+    const long nl = G.nl1, n = G.n, nb = G.nb;
+    ResidualDesc d = residual_desc(G, f->b0, 1, nrhs, s, t, jumps, u);
     d.rs = r + 2 * nb; d.rs_rhs = nl * n; d.rs_leaf = n;
     d.rb = r; d.rb_rhs = nl * n; d.rb_leaf = n;
-    residual(d, nrhs, f->stream);
+    residual(d, nrhs, G.stream);
   });
 }
 
 int hps_last_solve_info(const hps_factor* f, hps_solve_info* info) {
   return guard([&] {
     if (!f || !info) throw Error(HPS_E_INVALID, "factor and info must be non-NULL");
-    *info = f->last_info;
+    *info = f->g->last_info;
   });
 }
 
-int hps_factor_query(const hps_factor* f, hps_factor_info* info) {
+int hps_factor_query(const hps_factor* h, hps_factor_info* info) {
   return guard([&] {
-    if (!f || !info) throw Error(HPS_E_INVALID, "NULL argument");
+    if (!h || !info) throw Error(HPS_E_INVALID, "NULL argument");
+    const hps_group* f = h->g.get();
     info->p = f->p; info->nx = f->nx; info->ny = f->ny; info->levels = f->L;
-    info->nleaf = f->nleaf;
-    info->n_leaf_nodes = (int64_t)f->nleaf * f->n;
-    info->n_interior = (int64_t)f->nleaf * f->ni;
+    info->nleaf = f->nl1;
+    info->n_leaf_nodes = (int64_t)f->nl1 * f->n;
+    info->n_interior = (int64_t)f->nl1 * f->ni;
     info->n_root = 2L * (f->nx + f->ny) * f->m;
     info->device_bytes = (int64_t)f->bytes();
   });
 }
 
-int hps_factor_box(const hps_factor* f, int32_t level, int32_t box, int32_t* ix0, int32_t* ix1,
+int hps_factor_box(const hps_factor* h, int32_t level, int32_t box, int32_t* ix0, int32_t* ix1,
                    int32_t* iy0, int32_t* iy1) {
   return guard([&] {
-    if (!f) throw Error(HPS_E_INVALID, "factor is NULL");
+    if (!h) throw Error(HPS_E_INVALID, "factor is NULL");
+    const hps_group* f = h->g.get();
     if (level < 0 || level > f->L || box < 0 || box >= (1 << level))
       throw Error(HPS_E_INVALID, "level/box out of range");
     const Geo& g = f->geo[level][box];
@@ -1274,10 +1464,11 @@ int hps_factor_box(const hps_factor* f, int32_t level, int32_t box, int32_t* ix0
   });
 }
 
-int hps_factor_get(const hps_factor* f, int32_t what, int32_t level, int32_t box, double* dst,
+int hps_factor_get(const hps_factor* h, int32_t what, int32_t level, int32_t box, double* dst,
                    int64_t dst_len, int32_t* rows, int32_t* cols) {
   return guard([&] {
-    if (!f || !dst) throw Error(HPS_E_INVALID, "NULL argument");
+    if (!h || !dst) throw Error(HPS_E_INVALID, "NULL argument");
+    const hps_group* f = h->g.get();
     if (level < 0 || level > f->L || box < 0 || box >= (1 << level))
       throw Error(HPS_E_INVALID, "level/box out of range");
     const double* src = nullptr;
@@ -1290,13 +1481,14 @@ int hps_factor_get(const hps_factor* f, int32_t what, int32_t level, int32_t box
       src = c64 ? f->BI32.d() : f->BI.d();
       r = f->n; ld = f->n;
       c = (what == HPS_OP_PSI) ? f->nb : f->ni;
-      off = (long)box * f->n * f->n + (what == HPS_OP_PSI ? 0 : (long)f->n * f->nb);
+      off = ((long)h->b0 * f->nl1 + box) * f->n * f->n +
+            (what == HPS_OP_PSI ? 0 : (long)f->n * f->nb);
     } else if (what == HPS_OP_R) {
       if (!f->R_valid[level]) throw Error(HPS_E_INVALID, "R of this level is not kept");
       c64 = cbytes(*f, level) == 8;
       src = f->R[level].d();
       r = c = ld = f->nbl[level];
-      off = (long)box * r * r;
+      off = (((long)h->b0 << level) + box) * r * r;
     } else {
       if (level >= f->L) throw Error(HPS_E_INVALID, "merge operators live on levels < leaves");
       const LevelPlan& P = f->lv[level];
@@ -1314,7 +1506,7 @@ int hps_factor_get(const hps_factor* f, int32_t what, int32_t level, int32_t box
       src = b->d();
       c64 = P.c64;
       ld = r;
-      off = (long)box * r * c;
+      off = (((long)h->b0 << level) + box) * r * c;
     }
     if (rows) *rows = (int32_t)r;
     if (cols) *cols = (int32_t)c;
@@ -1332,10 +1524,11 @@ int hps_factor_get(const hps_factor* f, int32_t what, int32_t level, int32_t box
   });
 }
 
-int hps_stage_times(const hps_factor* f, int32_t which, hps_stage_time* out, int32_t cap,
+int hps_stage_times(const hps_factor* h, int32_t which, hps_stage_time* out, int32_t cap,
                     int32_t* n) {
   return guard([&] {
-    if (!f || !out || !n || cap < 0) throw Error(HPS_E_INVALID, "NULL argument");
+    if (!h || !out || !n || cap < 0) throw Error(HPS_E_INVALID, "NULL argument");
+    const hps_group* f = h->g.get();
     if (which != 0 && which != 1) throw Error(HPS_E_INVALID, "which must be 0 (build) or 1 (solve)");
     const Profiler& pr = which == 0 ? f->build_prof : f->solve_prof;
     std::vector<hps_stage_time> agg;

@@ -43,6 +43,7 @@ struct SkinnyDesc {
   bool accumulate = false;
   double alpha = 1.0;
   bool a_c64 = false;  // A is complex64 (FP32 products and accumulation)
+  long xbase = 0, cbase = 0;  // subtracted from xoff[b] / coff[b]
   // workspace for the split-K partial sums (at least skinny_work_bytes(d) bytes)
   void* work = nullptr;
 };
@@ -63,10 +64,12 @@ void zinv(int n, int batch, const double* A, long lda, long sA, double* Out, lon
 // ------------------------------------------------------------------ leaf stage
 struct LeafDesc {
   int p = 0, nleaf = 0;
-  double kappa = 0, eta_re = 0, eta_im = 0;
+  int nl1 = 1;                   // leaves per problem
+  long h0 = 0;                   // index of the launch's first leaf in the factor
+  const double* prm = nullptr;   // device [problem][4]: kappa, Re eta, Im eta, 0
   const double* c = nullptr;     // device [nleaf * ni] in user (grid) leaf order
   const int* leaf_grid = nullptr;  // device [nleaf]: grid index of tree-ordered leaf h
-  const double* tab = nullptr;   // device complex line table (leaf_table_len(p) entries)
+  const double* tab = nullptr;   // device complex line tables, leaf_table_len(p) per problem
   double* BI = nullptr;          // device [nleaf][n*n] complex: [Psi | Y]
   double* R = nullptr;           // device [nleaf][nb*nb] complex
   double* Mg = nullptr;          // scratch [nleaf][ni*ni] complex (leaf_scratch_bytes)
@@ -112,17 +115,18 @@ void to_c64(const double* src, float* dst, long n, hipStream_t st);
 void merge_extract(const MergeLevelDesc& d, hipStream_t st);
 
 // ------------------------------------------------------------------ solve helpers
-// h_b = -2 i eta * u_b[0:nb]  for every leaf (u_b is n x nrhs, h_b is nb x nrhs)
-void leaf_h_from_u(int nleaf, int n, int nb, int nrhs, double eta_re, double eta_im,
+// h_b = -2 i eta * u_b[0:nb]  for every leaf (u_b is n x nrhs, h_b is nb x nrhs); eta of
+// leaf b is that of problem b / nl1 in prm ([problem][4]: kappa, Re eta, Im eta, 0)
+void leaf_h_from_u(int nleaf, int n, int nb, int nrhs, const double* prm, int nl1,
                    const double* u, double* h, hipStream_t st);
 // Upward gather of one level: h3a, -h3a (into ttb), -h3b (into v), and the h1/h2 parts
 // of the parent's h.  hc: children's h [2*nbox][nbc x nrhs]; hp: [nbox][nbp x nrhs].
 // With right-hand sides on the shared-edge rows (jmp: [nrhs][ldj], ja/jb: per merge and
-// interface node the index of alpha's / beta's row in jmp), h3a is replaced by
+// interface node the index of alpha's / beta's row in jmp, minus jbase), h3a is replaced by
 // h3a - j2 (beta's row) and h3b by h3b - j1 (alpha's row).
 void up_gather(const MergeLevelDesc& d, int nrhs, const double* hc, double* h3a,
                double* v, double* ttb, double* hp, const double* jmp, long ldj,
-               const int* ja, const int* jb, hipStream_t st);
+               const int* ja, const int* jb, long jbase, hipStream_t st);
 // Downward scatter of one level: children's t on I1 / I2 from the parent's t.
 void down_scatter(const MergeLevelDesc& d, int nrhs, const double* tp, long ldp,
                   double* tc, hipStream_t st);
@@ -132,9 +136,11 @@ void down_scatter(const MergeLevelDesc& d, int nrhs, const double* tp, long ldp,
 // as interior rows rs[r*rs_rhs + l*rs_leaf + k] (k < n_i) and boundary rows
 // rb[r*rb_rhs + l*rb_leaf + k] (k < n_b).  Rows on the outer boundary go to
 // rt[r*rt_rhs + root position] when rt is given (rb then holds 0 there), else to rb.
+// nprob problems of one shape: leaf l' of the launch belongs to problem l' / (nx*ny); u, s,
+// jumps hold [nrhs][nprob * nx*ny * len], t and rt [nprob][nrhs][nt].
 struct ResidualDesc {
-  int p = 0, nx = 0, ny = 0;
-  double kappa = 0, eta_re = 0, eta_im = 0;
+  int p = 0, nx = 0, ny = 0, nprob = 1;
+  const double* prm = nullptr;  // device [nprob][4]: kappa, Re eta, Im eta, 0
   const double* D = nullptr;    // [4][p*p] Dx1, Dy1, Dxx, Dyy (column-major, scaled)
   const double* c = nullptr;    // [nleaf * n_i] real
   const double* u = nullptr;    // complex [nrhs][nleaf * n]
@@ -143,7 +149,8 @@ struct ResidualDesc {
   const double* jmp = nullptr;  // complex [nrhs][nleaf * n_b] or null (zero)
   double* rs = nullptr; long rs_rhs = 0, rs_leaf = 0;
   double* rb = nullptr; long rb_rhs = 0, rb_leaf = 0;
-  double* rt = nullptr; long rt_rhs = 0;
+  double* rt = nullptr;
+  int nrhs = 1;
 };
 void residual(const ResidualDesc& d, int nrhs, hipStream_t st);
 // y += x (complex, n entries)

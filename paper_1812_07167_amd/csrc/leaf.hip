@@ -26,6 +26,10 @@
 namespace hps {
 namespace {
 
+__host__ __device__ constexpr int leaf_table_len_dev(int p) {
+  return 2 * (p - 2) * (p - 2) + 8 * (p - 2) + 8;
+}
+
 // offsets (complex entries) into the line table of LeafDesc::tab, m = p - 2
 struct TabIdx {
   int m;
@@ -105,7 +109,8 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
   const int tr = tid % GR, tc = tid / GR;
   const long h = blockIdx.x;
   const int g = d.leaf_grid[h];
-  const double2* tab = reinterpret_cast<const double2*>(d.tab);
+  const long prob = (d.h0 + h) / d.nl1;
+  const double2* tab = reinterpret_cast<const double2*>(d.tab) + prob * leaf_table_len_dev(P);
   for (int e = tid; e < m * m; e += Cfg::NT) {
     sG[0][e] = tab[TabIdx{m}.gx() + e];
     sG[1][e] = tab[TabIdx{m}.gy() + e];
@@ -117,7 +122,8 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
   for (int e = tid; e < Cfg::POOL; e += Cfg::NT) pool[e] = cmk(0, 0);
   if (tid == 0) s_bad = 0;
   __syncthreads();
-  const double k2 = d.kappa * d.kappa;
+  const double kap = d.prm[4 * prob];
+  const double k2 = kap * kap;
   const double* cl = d.c + (long)g * NI;
   double2* Mg = reinterpret_cast<double2*>(d.Mg) + (RES ? 0 : h * (long)NI * NI);
   // scratch address of entry (a, b) of this thread (padding entries are never touched)
@@ -346,7 +352,8 @@ __global__ __launch_bounds__(256) void leaf_psi_i_kernel(LeafDesc d) {
   __shared__ double2 sw[4][m];
   const int tid = threadIdx.x;
   const long h = blockIdx.x;
-  const double2* tab = reinterpret_cast<const double2*>(d.tab);
+  const long prob = (d.h0 + h) / d.nl1;
+  const double2* tab = reinterpret_cast<const double2*>(d.tab) + prob * leaf_table_len_dev(P);
   const TabIdx T{m};
   for (int e = tid; e < m; e += 256) {
     sw[0][e] = tab[T.wS() + e];
@@ -400,7 +407,8 @@ __global__ __launch_bounds__(256) void leaf_bnd_kernel(LeafDesc d) {
   __shared__ double2 sb[8];
   const int tid = threadIdx.x;
   const long h = blockIdx.x;
-  const double2* tab = reinterpret_cast<const double2*>(d.tab);
+  const long prob = (d.h0 + h) / d.nl1;
+  const double2* tab = reinterpret_cast<const double2*>(d.tab) + prob * leaf_table_len_dev(P);
   const TabIdx T{m};
   for (int e = tid; e < m; e += 256) {
     sc[0][e] = tab[T.sS() + e];
@@ -415,7 +423,7 @@ __global__ __launch_bounds__(256) void leaf_bnd_kernel(LeafDesc d) {
   double2* BI = reinterpret_cast<double2*>(d.BI) + h * (long)N * N;
   double2* R = reinterpret_cast<double2*>(d.R) + h * (long)NB * NB;
   // -2 i eta = (2 eta_im, -2 eta_re)
-  const double2 m2ie = cmk(2.0 * d.eta_im, -2.0 * d.eta_re);
+  const double2 m2ie = cmk(2.0 * d.prm[4 * prob + 2], -2.0 * d.prm[4 * prob + 1]);
   for (int c0 = 0; c0 < N; c0 += CC) {
     const int cw = (N - c0) < CC ? (N - c0) : CC;
     __syncthreads();
@@ -497,10 +505,7 @@ size_t leaf_scratch_bytes(int p, long nleaf) {
   return (size_t)nleaf * ni * ni * 16;
 }
 
-int leaf_table_len(int p) {
-  const int m = p - 2;
-  return 2 * m * m + 8 * m + 8;
-}
+int leaf_table_len(int p) { return leaf_table_len_dev(p); }
 
 void leaf_interior_inverse(const LeafDesc& d, hipStream_t st) {
   if (d.nleaf <= 0) return;

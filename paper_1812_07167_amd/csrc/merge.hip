@@ -85,7 +85,7 @@ __global__ void extract_kernel(MergeLevelDesc d) {
   }
 }
 
-__global__ void leaf_h_kernel(int nleaf, int n, int nb, int nrhs, double er, double ei,
+__global__ void leaf_h_kernel(int nleaf, int n, int nb, int nrhs, const double* prm, int nl1,
                               const double2* u, double2* h) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long per = (long)nb * nrhs;
@@ -93,13 +93,14 @@ __global__ void leaf_h_kernel(int nleaf, int n, int nb, int nrhs, double er, dou
   const long b = e / per;
   const int loc = e % per;
   const int k = loc % nb, r = loc / nb;
+  const double* pp = prm + 4 * (b / nl1);  // the leaf's problem: kappa, Re eta, Im eta
   const double2 x = u[b * (long)n * nrhs + k + (long)n * r];
-  h[e] = cmul(cmk(2.0 * ei, -2.0 * er), x);
+  h[e] = cmul(cmk(2.0 * pp[2], -2.0 * pp[1]), x);
 }
 
 __global__ void up_gather_kernel(MergeLevelDesc d, int nrhs, const double2* hc, double2* h3a,
                                  double2* v, double2* ttb, double2* hp, const double2* jmp,
-                                 long ldj, const int* ja, const int* jb) {
+                                 long ldj, const int* ja, const int* jb, long jbase) {
   const long q = blockIdx.y;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const int n1 = d.n1, n2 = d.n2, n3 = d.n3, nbc = d.nbc, nbp = d.nbp;
@@ -113,8 +114,8 @@ __global__ void up_gather_kernel(MergeLevelDesc d, int nrhs, const double2* hc, 
     double2 bb = hb[d.i3b[k] + (long)nbc * r];
     if (jmp) {
       const long qk = q * (long)n3 + k;
-      a = csub(a, jmp[(long)r * ldj + jb[qk]]);    // h3a - j2
-      bb = csub(bb, jmp[(long)r * ldj + ja[qk]]);  // h3b - j1
+      a = csub(a, jmp[(long)r * ldj + jb[qk] - jbase]);    // h3a - j2
+      bb = csub(bb, jmp[(long)r * ldj + ja[qk] - jbase]);  // h3b - j1
     }
     const long o = q * (long)n3 * nrhs + k + (long)n3 * r;
     h3a[o] = a;
@@ -192,23 +193,23 @@ void merge_extract(const MergeLevelDesc& d, hipStream_t st) {
   HPS_LAUNCH_CHECK();
 }
 
-void leaf_h_from_u(int nleaf, int n, int nb, int nrhs, double er, double ei, const double* u,
-                   double* h, hipStream_t st) {
+void leaf_h_from_u(int nleaf, int n, int nb, int nrhs, const double* prm, int nl1,
+                   const double* u, double* h, hipStream_t st) {
   long tot = (long)nleaf * nb * nrhs;
   hipLaunchKernelGGL(leaf_h_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, st, nleaf, n, nb, nrhs,
-                     er, ei, reinterpret_cast<const double2*>(u), reinterpret_cast<double2*>(h));
+                     prm, nl1, reinterpret_cast<const double2*>(u), reinterpret_cast<double2*>(h));
   HPS_LAUNCH_CHECK();
 }
 
 void up_gather(const MergeLevelDesc& d, int nrhs, const double* hc, double* h3a, double* v,
                double* ttb, double* hp, const double* jmp, long ldj, const int* ja,
-               const int* jb, hipStream_t st) {
+               const int* jb, long jbase, hipStream_t st) {
   long rows = (long)(d.n3 + d.n1 + d.n2) * nrhs;
   hipLaunchKernelGGL(up_gather_kernel, dim3(cdiv(rows, 256), d.nbox), dim3(256), 0, st, d, nrhs,
                      reinterpret_cast<const double2*>(hc), reinterpret_cast<double2*>(h3a),
                      reinterpret_cast<double2*>(v), reinterpret_cast<double2*>(ttb),
                      reinterpret_cast<double2*>(hp), reinterpret_cast<const double2*>(jmp), ldj,
-                     ja, jb);
+                     ja, jb, jbase);
   HPS_LAUNCH_CHECK();
 }
 

@@ -59,12 +59,15 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualDesc d) {
   __shared__ double2 Ug[P * P];
   __shared__ double sD[4][P * P];
   const int tid = threadIdx.x;
-  const int l = blockIdx.x, r = blockIdx.y;
-  const int nleaf = d.nx * d.ny;
+  const int lg = blockIdx.x, r = blockIdx.y;   // leaf of the launch, right-hand side
+  const int nl1 = d.nx * d.ny;
+  const int prob = lg / nl1, l = lg % nl1;      // problem, leaf within it (grid order)
+  const int nleaf = nl1 * d.nprob;              // leaves of the launch
   const int ix = l % d.nx, iy = l / d.nx;
+  const double kappa = d.prm[4 * prob], eta_re = d.prm[4 * prob + 1], eta_im = d.prm[4 * prob + 2];
   for (int e = tid; e < 4 * P * P; e += 256) sD[e / (P * P)][e % (P * P)] = d.D[e];
   const double2* u = reinterpret_cast<const double2*>(d.u) + (long)r * nleaf * N;
-  const double2* ul = u + (long)l * N;
+  const double2* ul = u + (long)lg * N;
   for (int e = tid; e < P * P; e += 256) {
     const int i = e % P, j = e / P;
     const int pos = node_pos(i, j, P);
@@ -75,7 +78,7 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualDesc d) {
   const double* Dy1 = sD[1];
   const double* Dxx = sD[2];
   const double* Dyy = sD[3];
-  const double k2 = d.kappa * d.kappa;
+  const double k2 = kappa * kappa;
   // interior rows
   for (int e = tid; e < NI; e += 256) {
     const int i = e % M + 1, j = e / M + 1;
@@ -85,12 +88,12 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualDesc d) {
       lap.x += Dxx[i + P * k] * a.x + Dyy[j + P * k] * b.x;
       lap.y += Dxx[i + P * k] * a.y + Dyy[j + P * k] * b.y;
     }
-    const double cc = k2 * d.c[(long)l * NI + e];
+    const double cc = k2 * d.c[(long)lg * NI + e];
     const double2 uc = Ug[i + P * j];
     const double2 Au = cmk(-lap.x - cc * uc.x, -lap.y - cc * uc.y);
     double2 b = cmk(0, 0);
-    if (d.s) b = reinterpret_cast<const double2*>(d.s)[(long)r * nleaf * NI + (long)l * NI + e];
-    reinterpret_cast<double2*>(d.rs)[r * d.rs_rhs + l * d.rs_leaf + e] = csub(b, Au);
+    if (d.s) b = reinterpret_cast<const double2*>(d.s)[(long)r * nleaf * NI + (long)lg * NI + e];
+    reinterpret_cast<double2*>(d.rs)[r * d.rs_rhs + lg * d.rs_leaf + e] = csub(b, Au);
   }
   // boundary rows
   const int nt = 2 * (d.nx + d.ny) * M;
@@ -100,8 +103,8 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualDesc d) {
     const double2 nd = normal_deriv(side, idx, P, Dx1, Dy1, own);
     const double2 ue = ul[e];
     // F u = N u + i eta u
-    const double2 Fu = cmk(nd.x - d.eta_im * ue.x - d.eta_re * ue.y,
-                           nd.y + d.eta_re * ue.x - d.eta_im * ue.y);
+    const double2 Fu = cmk(nd.x - eta_im * ue.x - eta_re * ue.y,
+                           nd.y + eta_re * ue.x - eta_im * ue.y);
     // neighbour across this side, and the root-boundary position when there is none
     int jx = ix, jy = iy, nside = 0, root = -1;
     switch (side) {
@@ -110,19 +113,20 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualDesc d) {
       case 2: jy = iy + 1; nside = 0; if (iy == d.ny - 1) root = (d.nx + d.ny) * M + ix * M + q; break;
       default: jx = ix - 1; nside = 1; if (ix == 0) root = (2 * d.nx + d.ny) * M + iy * M + q; break;
     }
-    double2* rb = reinterpret_cast<double2*>(d.rb) + r * d.rb_rhs + l * d.rb_leaf;
+    double2* rb = reinterpret_cast<double2*>(d.rb) + r * d.rb_rhs + lg * d.rb_leaf;
+    const long trow = ((long)prob * d.nrhs + r) * nt;  // t, rt: [problem][rhs][nt]
     if (root >= 0) {
       double2 tv = cmk(0, 0);
-      if (d.t) tv = reinterpret_cast<const double2*>(d.t)[(long)r * nt + root];
+      if (d.t) tv = reinterpret_cast<const double2*>(d.t)[trow + root];
       const double2 res = csub(tv, Fu);
       if (d.rt) {
-        reinterpret_cast<double2*>(d.rt)[r * d.rt_rhs + root] = res;
+        reinterpret_cast<double2*>(d.rt)[trow + root] = res;
         rb[e] = cmk(0, 0);
       } else {
         rb[e] = res;
       }
     } else {
-      const double2* un = u + (long)(jy * d.nx + jx) * N;
+      const double2* un = u + ((long)prob * nl1 + jy * d.nx + jx) * N;
       auto nbr = [&](int i, int j) {
         const int pos = node_pos(i, j, P);
         return pos < 0 ? cmk(0, 0) : un[pos];
@@ -130,10 +134,10 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualDesc d) {
       const double2 ndn = normal_deriv(nside, idx, P, Dx1, Dy1, nbr);
       const double2 un_e = un[nside * M + q];
       // G u' = N' u' - i eta u'
-      const double2 Gu = cmk(ndn.x + d.eta_im * un_e.x + d.eta_re * un_e.y,
-                             ndn.y - d.eta_re * un_e.x + d.eta_im * un_e.y);
+      const double2 Gu = cmk(ndn.x + eta_im * un_e.x + eta_re * un_e.y,
+                             ndn.y - eta_re * un_e.x + eta_im * un_e.y);
       double2 jv = cmk(0, 0);
-      if (d.jmp) jv = reinterpret_cast<const double2*>(d.jmp)[(long)r * nleaf * NB + (long)l * NB + e];
+      if (d.jmp) jv = reinterpret_cast<const double2*>(d.jmp)[(long)r * nleaf * NB + (long)lg * NB + e];
       rb[e] = csub(jv, cadd(Fu, Gu));
     }
   }
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(256) void norms_kernel(long len, const double2* x, 
 void residual(const ResidualDesc& d, int nrhs, hipStream_t st) {
   if (nrhs <= 0) return;
   if (nrhs > 65535) throw Error(1, "residual: too many right-hand sides");
-  const dim3 grid(d.nx * d.ny, nrhs);
+  const dim3 grid(d.nx * d.ny * d.nprob, nrhs);
   switch (d.p) {
 #define HPS_RES_CASE(PP) \
   case PP: hipLaunchKernelGGL(residual_kernel<PP>, grid, dim3(256), 0, st, d); break;

@@ -60,7 +60,8 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
   const int kbeg = ks * kper, kend = min(d.K, kbeg + kper);
   const int row0 = blockIdx.x * ROWS + wr * 16 * TW;
   const C2* A = reinterpret_cast<const C2*>(d.A) + b * d.sA;
-  const double2* X = reinterpret_cast<const double2*>(d.X) + (d.xoff ? d.xoff[b] : b * d.sX);
+  const double2* X =
+      reinterpret_cast<const double2*>(d.X) + (d.xoff ? d.xoff[b] - d.xbase : b * d.sX);
 
   // rows this lane loads (clamped into the operator; rows past M are never written)
   long arow[TW];
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
       }
     return;
   }
-  double2* C = reinterpret_cast<double2*>(d.C) + (d.coff ? d.coff[b] : b * d.sC);
+  double2* C = reinterpret_cast<double2*>(d.C) + (d.coff ? d.coff[b] - d.cbase : b * d.sC);
   const double2* C0 = d.C0 ? reinterpret_cast<const double2*>(d.C0) +
                                  (d.c0off ? d.c0off[b] : b * d.s0)
                            : nullptr;
@@ -163,7 +164,7 @@ __global__ void skinny_reduce_kernel(SkinnyDesc d, int r0, int nr, int nsplit,
   double2 acc = cmk(0, 0);
   for (int s = 0; s < nsplit; ++s)
     acc = cadd(acc, partial[(((long)s * d.batch + b) * NRB + r) * d.M + i]);
-  double2* C = reinterpret_cast<double2*>(d.C) + (d.coff ? d.coff[b] : b * d.sC);
+  double2* C = reinterpret_cast<double2*>(d.C) + (d.coff ? d.coff[b] - d.cbase : b * d.sC);
   const long ci = d.crow ? d.crow[i] : i;
   double2 v = cscale(acc, d.alpha);
   double2* p = C + ci + d.ldc * (long)(r0 + r);

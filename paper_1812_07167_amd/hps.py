@@ -21,7 +21,8 @@ OP_PSI, OP_Y, OP_R, OP_WINV, OP_PHI_A, OP_PHI_B, OP_R33A, OP_R33B, OP_R13A, OP_R
 
 EXPORTS = [
     "hps_last_error", "hps_version", "hps_default_opts", "hps_nodes", "hps_build",
-    "hps_solve", "hps_solve_jumps", "hps_residual", "hps_last_solve_info", "hps_factor_query",
+    "hps_build_batch", "hps_solve", "hps_solve_batch", "hps_solve_jumps", "hps_residual",
+    "hps_last_solve_info", "hps_factor_query",
     "hps_factor_get", "hps_factor_box", "hps_stage_times", "hps_free",
 ]
 HPS_PREC_C128, HPS_PREC_MIXED = 0, 1
@@ -85,6 +86,8 @@ def load(path: str = LIB_PATH):
     lib.hps_build.argtypes = [C.POINTER(Domain), I32, D, D, D, P, C.POINTER(Opts), C.POINTER(P)]
     lib.hps_solve.argtypes = [P, I32, P, P, P]
     lib.hps_solve_jumps.argtypes = [P, I32, P, P, P, P]
+    lib.hps_build_batch.argtypes = [I32, P, P, P, P, P, P, C.POINTER(Opts), P]
+    lib.hps_solve_batch.argtypes = [I32, P, P, P, P, P]
     lib.hps_residual.argtypes = [P, I32, P, P, P, P, P]
     lib.hps_last_solve_info.argtypes = [P, C.POINTER(SolveInfo)]
     lib.hps_factor_query.argtypes = [P, C.POINTER(FactorInfo)]
@@ -93,7 +96,8 @@ def load(path: str = LIB_PATH):
     lib.hps_stage_times.argtypes = [P, I32, C.POINTER(StageTime), I32, C.POINTER(I32)]
     lib.hps_free.argtypes = [P]
     lib.hps_free.restype = None
-    for name in ["hps_nodes", "hps_build", "hps_solve", "hps_solve_jumps", "hps_residual",
+    for name in ["hps_nodes", "hps_build", "hps_build_batch", "hps_solve", "hps_solve_batch",
+                 "hps_solve_jumps", "hps_residual",
                  "hps_last_solve_info", "hps_factor_query", "hps_factor_get", "hps_factor_box",
                  "hps_stage_times"]:
         getattr(lib, name).restype = C.c_int
@@ -190,6 +194,68 @@ class Factor:
         v = [C.c_int32() for _ in range(4)]
         _check(load().hps_factor_box(self.h, level, box, *[C.byref(x) for x in v]))
         return tuple(x.value for x in v)
+
+
+def _opts(keep_all_R, store_root_R, stream, profile, precision, fp64_top_levels,
+          refine_max_iter, refine_tol):
+    import torch
+    lib = load()
+    opts = Opts()
+    lib.hps_default_opts(C.byref(opts))
+    opts.keep_all_R = int(keep_all_R)
+    opts.store_root_R = int(store_root_R)
+    opts.profile = int(profile)
+    opts.precision = int(precision)
+    if fp64_top_levels is not None:
+        opts.fp64_top_levels = int(fp64_top_levels)
+    if refine_max_iter is not None:
+        opts.refine_max_iter = int(refine_max_iter)
+    if refine_tol is not None:
+        opts.refine_tol = float(refine_tol)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    opts.stream = C.c_void_p(st.cuda_stream)
+    return opts, st
+
+
+def hps_build_batch(doms, ps, kappas, etas, cs, keep_all_R=False, store_root_R=True,
+                    stream=None, profile=False, precision=HPS_PREC_C128, fp64_top_levels=None,
+                    refine_max_iter=None, refine_tol=None):
+    """Build several problems at once (problems of one shape share every launch).  doms:
+    list of Domain; cs: list of float64 device tensors.  Returns a list of Factors."""
+    lib = load()
+    n = len(doms)
+    opts, st = _opts(keep_all_R, store_root_R, stream, profile, precision, fp64_top_levels,
+                     refine_max_iter, refine_tol)
+    D = (Domain * n)(*doms)
+    P = (C.c_int32 * n)(*[int(p) for p in ps])
+    K = (C.c_double * n)(*[float(k) for k in kappas])
+    ER = (C.c_double * n)(*[float(np.real(e)) for e in etas])
+    EI = (C.c_double * n)(*[float(np.imag(e)) for e in etas])
+    CP = (C.c_void_p * n)(*[_dev_ptr(c, "torch.float64") for c in cs])
+    out = (C.c_void_p * n)()
+    _check(lib.hps_build_batch(n, D, P, K, ER, EI, CP, C.byref(opts), out))
+    return [Factor(C.c_void_p(out[i]), st.cuda_stream) for i in range(n)]
+
+
+def hps_solve_batch(fs, ts, ss=None, us=None):
+    """Solve several problems at once: ts[i] complex128 device tensor [nrhs_i, n_root];
+    ss[i] [nrhs_i, n_interior] or None.  Returns the list of u tensors."""
+    import torch
+    lib = load()
+    n = len(fs)
+    if us is None:
+        us = [torch.empty((t.shape[0], f.info.n_leaf_nodes), dtype=torch.complex128,
+                          device=t.device) for f, t in zip(fs, ts)]
+    H = (C.c_void_p * n)(*[f.h for f in fs])
+    NR = (C.c_int32 * n)(*[int(t.shape[0]) for t in ts])
+    S = None
+    if ss is not None:
+        S = (C.c_void_p * n)(*[(_dev_ptr(s, "torch.complex128") if s is not None else None)
+                              for s in ss])
+    T = (C.c_void_p * n)(*[_dev_ptr(t, "torch.complex128") for t in ts])
+    U = (C.c_void_p * n)(*[_dev_ptr(u, "torch.complex128") for u in us])
+    _check(lib.hps_solve_batch(n, H, NR, S, T, U))
+    return us
 
 
 def hps_build(dom: Domain, p: int, kappa: float, eta: complex, c_interior, keep_all_R=False,

@@ -1,0 +1,103 @@
+"""Cross-problem batching: hps_build_batch / hps_solve_batch against per-problem builds and
+solves and against the oracle.  Problems of one shape are factored and solved together;
+results must not depend on what else is in the batch (rel. 1e-12 between the batched and
+the single-problem results; 1e-10 against the oracle)."""
+
+import numpy as np
+import pytest
+
+from tests.hps_cases import Case, rel
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+SAME = 1e-12
+
+
+def _mix():
+    # three shapes, uneven: (nx, ny, p, kappa, eta, seed)
+    return [(4, 4, 8, 20.0, 20.0, 1), (4, 4, 8, 35.0, 10.0 + 2.0j, 2), (4, 4, 8, 12.0, 12.0, 3),
+            (8, 4, 10, 40.0, 40.0, 4), (8, 4, 10, 25.0, 30.0, 5),
+            (2, 2, 12, 15.0, 15.0, 6)]
+
+
+def _cases(nrhs=2):
+    return [Case(nx, ny, p, k, eta=e, seed=sd, nrhs=nrhs) for nx, ny, p, k, e, sd in _mix()]
+
+
+def _dev(a, dt="complex128"):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=getattr(torch, dt), device="cuda")
+
+
+def _batch_build(cases, **kw):
+    from paper_1812_07167_amd import hps as H
+    doms = [H.domain(c.nx, c.ny, c.box) for c in cases]
+    return H.hps_build_batch(doms, [c.p for c in cases], [c.kappa for c in cases],
+                             [c.eta for c in cases], [_dev(c.c, "float64") for c in cases], **kw)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_equals_single_problem_calls(precision):
+    import torch
+    from paper_1812_07167_amd import hps as H
+    cases = _cases()
+    fs = _batch_build(cases, precision=precision)
+    us = H.hps_solve_batch(fs, [_dev(c.t) for c in cases], [_dev(c.s) for c in cases])
+    torch.cuda.synchronize()
+    for c, u in zip(cases, us):
+        f1 = c.gpu_build(precision=precision)
+        u1 = c.gpu_solve(f1)
+        assert rel(u.cpu().numpy(), u1) < (SAME if precision == 0 else TOL)
+        f1.free()
+    for f in fs:
+        f.free()
+
+
+def test_batch_matches_oracle_and_single_handle_solves():
+    import torch
+    from paper_1812_07167_amd import hps as H
+    cases = _cases()
+    fs = _batch_build(cases)
+    us = H.hps_solve_batch(fs, [_dev(c.t) for c in cases], [_dev(c.s) for c in cases])
+    torch.cuda.synchronize()
+    for i, (c, f, u) in enumerate(zip(cases, fs, us)):
+        uo = c.oracle_solve(c.oracle_build())
+        assert rel(u.cpu().numpy(), uo) < TOL, i
+        # the same handle alone (hps_solve on one problem of a group)
+        assert rel(c.gpu_solve(f), u.cpu().numpy()) < SAME, i
+    for f in fs:
+        f.free()
+
+
+def test_batch_uneven_nrhs_subset_and_null_s():
+    """A subset of the problems, different nrhs per problem, s = NULL for some."""
+    import torch
+    from paper_1812_07167_amd import hps as H
+    cases = _cases(nrhs=3)
+    fs = _batch_build(cases)
+    pick = [1, 2, 4]
+    nr = {1: 1, 2: 3, 4: 2}
+    ts = [_dev(cases[i].t[: nr[i]]) for i in pick]
+    ss = [None if i == 2 else _dev(cases[i].s[: nr[i]]) for i in pick]
+    us = H.hps_solve_batch([fs[i] for i in pick], ts, ss)
+    torch.cuda.synchronize()
+    for i, u in zip(pick, us):
+        c = cases[i]
+        s = None if i == 2 else c.s[: nr[i]]
+        from oracle import hps_oracle as O
+        uo = O.solve(c.prob, c.oracle_build(), s, c.t[: nr[i]])
+        assert u.shape[0] == nr[i]
+        assert rel(u.cpu().numpy(), uo) < TOL, i
+    for f in fs:
+        f.free()
+
+
+def test_batch_handles_outlive_each_other():
+    """Freeing some handles of a group keeps the others usable."""
+    cases = _cases()[:3]
+    fs = _batch_build(cases)
+    fs[0].free()
+    fs[2].free()
+    u = cases[1].gpu_solve(fs[1])
+    assert rel(u, cases[1].oracle_solve(cases[1].oracle_build())) < TOL
+    fs[1].free()
