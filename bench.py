@@ -157,6 +157,73 @@ def mixed_leg(H, torch, dom, p, kappa, c_d, s_d, t_d, u_ref, exact, stream, out,
             "fp64_top_levels": 3}
 
 
+def batch_leg(H, torch, dev, stream, count=256, seed0=0, reps=2):
+    """Cross-problem batching: `count` independent seeded problems (leaf grids 8^2..32^2,
+    p in {8, 12, 16}, kappa in [10, 80], Fourier c, one manufactured right-hand side each)
+    built with hps_build_batch and solved with hps_solve_batch, in complex128 and in mixed
+    precision, against the same problems built and solved one at a time."""
+    from paper_1812_07167_amd import inputs as G
+    probs = G.batch_problems(seed0, count)
+    nodes = {}
+    doms, ps, ks, cs, ss, ts, exact = [], [], [], [], [], [], []
+    dof = 0
+    for q in probs:
+        key = (q["nx"], q["p"])
+        if key not in nodes:
+            nodes[key] = H.hps_nodes(H.domain(q["nx"], q["ny"]), q["p"])
+        xy, xyi, xyb, nrm = nodes[key]
+        c = G.FourierField.seeded(q["seed"])(xyi)
+        mf = G.Manufactured(q["kappa"], q["theta"])
+        doms.append(H.domain(q["nx"], q["ny"]))
+        ps.append(q["p"])
+        ks.append(q["kappa"])
+        cs.append(torch.tensor(c, dtype=torch.float64, device=dev))
+        ss.append(torch.tensor(mf.s(xyi, c)[None], dtype=torch.complex128, device=dev))
+        ts.append(torch.tensor(mf.t(xyb, nrm, q["kappa"])[None], dtype=torch.complex128,
+                               device=dev))
+        exact.append(mf.u(xy))
+        dof += q["nx"] * q["ny"] * (q["p"] ** 2 - 4)
+    res = {"problems": count, "dof": dof, "shape_groups": len(nodes)}
+
+    def run(precision):
+        bt, st_ = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fs = H.hps_build_batch(doms, ps, ks, ks, cs, stream=stream, precision=precision)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            us = H.hps_solve_batch(fs, ts, ss)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            bt.append((t1 - t0) * 1e3)
+            st_.append((t2 - t1) * 1e3)
+            for f in fs:
+                f.free()
+        err = max(float(np.linalg.norm(u.cpu().numpy()[0] - e) / np.linalg.norm(e))
+                  for u, e in zip(us, exact))
+        b, s_ = float(np.min(bt)), float(np.min(st_))
+        return {"build_ms": round(b, 2), "solve_ms": round(s_, 2),
+                "build_dof_per_s": round(dof / (b * 1e-3), 1),
+                "rhs_solves_per_s": round(count / (s_ * 1e-3), 1),
+                "max_rel_l2_vs_exact": err}
+
+    res["c128"] = run(H.HPS_PREC_C128)
+    res["mixed"] = run(H.HPS_PREC_MIXED)
+    # the same problems one at a time
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(count):
+        f = H.hps_build(doms[i], ps[i], ks[i], ks[i], cs[i], stream=stream)
+        H.hps_solve(f, ts[i], ss[i])
+        f.free()
+    torch.cuda.synchronize()
+    seq = (time.perf_counter() - t0) * 1e3
+    res["one_at_a_time_ms"] = round(seq, 2)
+    res["batch_speedup_c128"] = round(seq / (res["c128"]["build_ms"] + res["c128"]["solve_ms"]), 3)
+    return res
+
+
 def copy_calibration(torch, dev, mib=256, reps=3):
     """A plain device-to-device copy of `mib` MiB, `reps` times: the HBM byte counters
     of a profiler run over this command read what one copy of known size costs."""
@@ -181,6 +248,8 @@ def main():
     ap.add_argument("--cpu-leaves", default="64x32",
                     help="leaf grid of the oracle's sample of the workload (NXxNY)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the cross-problem batching leg (256 problems)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision (complex64 + FP64 correction) leg")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -321,6 +390,9 @@ def main():
         "roofline": roofline,
         "stages_ms": {k: round(v[1], 3) for k, v in groups.items()},
     }
+    if not args.no_batch:
+        log("batch leg")
+        out["batch_256_problems"] = batch_leg(H, torch, dev, stream)
     if not args.no_mixed:
         out["mixed_precision"] = mixed_leg(H, torch, dom, p, kappa, c_d, s_d, t_d, u_d, exact,
                                            stream, out)

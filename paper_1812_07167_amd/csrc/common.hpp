@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
 #include <stdexcept>
@@ -133,5 +134,9 @@ struct Error : std::runtime_error {
 #define HPS_LAUNCH_CHECK() HPS_HIP(hipGetLastError())
 
 inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
+
+// Blocks of 256 threads for an elementwise kernel over n items with a grid-stride loop:
+// a dispatch counts its work-items in 32 bits, so the grid is capped (2^28 threads).
+inline unsigned grid1d(long n) { return (unsigned)std::min<long>(cdiv(n, 256), 1L << 20); }
 
 }  // namespace hps

@@ -14,29 +14,30 @@ namespace hps {
 namespace {
 
 __global__ void fill_zero_kernel(double* p, long n) {
-  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) p[e] = 0.0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    p[e] = 0.0;
 }
 
 __global__ void to_f32_kernel(const double* s, float* d, long n) {
-  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) d[e] = (float)s[e];
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    d[e] = (float)s[e];
 }
 
 __global__ void fill_zero_int_kernel(int* p, long n) {
-  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) p[e] = 0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    p[e] = 0;
 }
 
 template <class T>
 __global__ void fill_identity_kernel(typename Cx<T>::t* p, int n, long stride, int batch) {
-  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  long tot = (long)n * n * batch;
-  if (e >= tot) return;
-  long b = e / ((long)n * n);
-  int loc = e % ((long)n * n);
-  int i = loc % n, j = loc / n;
-  p[b * stride + loc] = Cx<T>::mk(i == j ? T(1) : T(0), T(0));
+  const long tot = (long)n * n * batch;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long)gridDim.x * blockDim.x) {
+    const long b = e / ((long)n * n);
+    const int loc = e % ((long)n * n);
+    const int i = loc % n, j = loc / n;
+    p[b * stride + loc] = Cx<T>::mk(i == j ? T(1) : T(0), T(0));
+  }
 }
 
 // Tc: element type of the children's R; Tp: element type of the level's blocks (a
@@ -87,15 +88,16 @@ __global__ void extract_kernel(MergeLevelDesc d) {
 
 __global__ void leaf_h_kernel(int nleaf, int n, int nb, int nrhs, const double* prm, int nl1,
                               const double2* u, double2* h) {
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long per = (long)nb * nrhs;
-  if (e >= per * nleaf) return;
-  const long b = e / per;
-  const int loc = e % per;
-  const int k = loc % nb, r = loc / nb;
-  const double* pp = prm + 4 * (b / nl1);  // the leaf's problem: kappa, Re eta, Im eta
-  const double2 x = u[b * (long)n * nrhs + k + (long)n * r];
-  h[e] = cmul(cmk(2.0 * pp[2], -2.0 * pp[1]), x);
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < per * nleaf;
+       e += (long)gridDim.x * blockDim.x) {
+    const long b = e / per;
+    const int loc = e % per;
+    const int k = loc % nb, r = loc / nb;
+    const double* pp = prm + 4 * (b / nl1);  // the leaf's problem: kappa, Re eta, Im eta
+    const double2 x = u[b * (long)n * nrhs + k + (long)n * r];
+    h[e] = cmul(cmk(2.0 * pp[2], -2.0 * pp[1]), x);
+  }
 }
 
 __global__ void up_gather_kernel(MergeLevelDesc d, int nrhs, const double2* hc, double2* h3a,
@@ -151,19 +153,19 @@ __global__ void down_scatter_kernel(MergeLevelDesc d, int nrhs, const double2* t
 
 void fill_zero(double* p, long n, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(fill_zero_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, p, n);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(grid1d(n)), dim3(256), 0, st, p, n);
   HPS_LAUNCH_CHECK();
 }
 
 void to_c64(const double* src, float* dst, long n, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(to_f32_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, src, dst, n);
+  hipLaunchKernelGGL(to_f32_kernel, dim3(grid1d(n)), dim3(256), 0, st, src, dst, n);
   HPS_LAUNCH_CHECK();
 }
 
 void fill_zero_int(int* p, long n, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(fill_zero_int_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, p, n);
+  hipLaunchKernelGGL(fill_zero_int_kernel, dim3(grid1d(n)), dim3(256), 0, st, p, n);
   HPS_LAUNCH_CHECK();
 }
 
@@ -171,10 +173,10 @@ void fill_identity(double* p, int n, long stride, int batch, hipStream_t st, boo
   long tot = (long)n * n * batch;
   if (tot <= 0) return;
   if (c64)
-    hipLaunchKernelGGL(fill_identity_kernel<float>, dim3(cdiv(tot, 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL(fill_identity_kernel<float>, dim3(grid1d(tot)), dim3(256), 0, st,
                        reinterpret_cast<float2*>(p), n, stride, batch);
   else
-    hipLaunchKernelGGL(fill_identity_kernel<double>, dim3(cdiv(tot, 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL(fill_identity_kernel<double>, dim3(grid1d(tot)), dim3(256), 0, st,
                        reinterpret_cast<double2*>(p), n, stride, batch);
   HPS_LAUNCH_CHECK();
 }
@@ -196,7 +198,7 @@ void merge_extract(const MergeLevelDesc& d, hipStream_t st) {
 void leaf_h_from_u(int nleaf, int n, int nb, int nrhs, const double* prm, int nl1,
                    const double* u, double* h, hipStream_t st) {
   long tot = (long)nleaf * nb * nrhs;
-  hipLaunchKernelGGL(leaf_h_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, st, nleaf, n, nb, nrhs,
+  hipLaunchKernelGGL(leaf_h_kernel, dim3(grid1d(tot)), dim3(256), 0, st, nleaf, n, nb, nrhs,
                      prm, nl1, reinterpret_cast<const double2*>(u), reinterpret_cast<double2*>(h));
   HPS_LAUNCH_CHECK();
 }

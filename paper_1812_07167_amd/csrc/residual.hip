@@ -144,8 +144,8 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualDesc d) {
 }
 
 __global__ void axpy_kernel(long n, const double2* x, double2* y) {
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) y[e] = cadd(y[e], x[e]);
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    y[e] = cadd(y[e], x[e]);
 }
 
 // partial sums of |x|^2 and |y|^2 per block of one right-hand side (fixed order)
@@ -196,7 +196,7 @@ void residual(const ResidualDesc& d, int nrhs, hipStream_t st) {
 
 void axpy(long n, const double* x, double* y, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(axpy_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, n,
+  hipLaunchKernelGGL(axpy_kernel, dim3(grid1d(n)), dim3(256), 0, st, n,
                      reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y));
   HPS_LAUNCH_CHECK();
 }

@@ -155,26 +155,28 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
 
 __global__ void skinny_reduce_kernel(SkinnyDesc d, int r0, int nr, int nsplit,
                                      const double2* partial) {
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long tot = (long)d.batch * d.M * nr;
-  if (e >= tot) return;
-  const int i = e % d.M;
-  const int r = (e / d.M) % nr;
-  const long b = e / ((long)d.M * nr);
-  double2 acc = cmk(0, 0);
-  for (int s = 0; s < nsplit; ++s)
-    acc = cadd(acc, partial[(((long)s * d.batch + b) * NRB + r) * d.M + i]);
-  double2* C = reinterpret_cast<double2*>(d.C) + (d.coff ? d.coff[b] - d.cbase : b * d.sC);
-  const long ci = d.crow ? d.crow[i] : i;
-  double2 v = cscale(acc, d.alpha);
-  double2* p = C + ci + d.ldc * (long)(r0 + r);
-  if (d.C0) {
-    const double2* C0 = reinterpret_cast<const double2*>(d.C0) + (d.c0off ? d.c0off[b] : b * d.s0);
-    v = cadd(v, C0[i + d.ld0 * (long)(r0 + r)]);
-  } else if (d.accumulate) {
-    v = cadd(v, *p);
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long)gridDim.x * blockDim.x) {
+    const int i = e % d.M;
+    const int r = (e / d.M) % nr;
+    const long b = e / ((long)d.M * nr);
+    double2 acc = cmk(0, 0);
+    for (int s = 0; s < nsplit; ++s)
+      acc = cadd(acc, partial[(((long)s * d.batch + b) * NRB + r) * d.M + i]);
+    double2* C = reinterpret_cast<double2*>(d.C) + (d.coff ? d.coff[b] - d.cbase : b * d.sC);
+    const long ci = d.crow ? d.crow[i] : i;
+    double2 v = cscale(acc, d.alpha);
+    double2* p = C + ci + d.ldc * (long)(r0 + r);
+    if (d.C0) {
+      const double2* C0 =
+          reinterpret_cast<const double2*>(d.C0) + (d.c0off ? d.c0off[b] : b * d.s0);
+      v = cadd(v, C0[i + d.ld0 * (long)(r0 + r)]);
+    } else if (d.accumulate) {
+      v = cadd(v, *p);
+    }
+    *p = v;
   }
-  *p = v;
 }
 
 // rows covered by one workgroup for an operator of M rows
@@ -223,7 +225,7 @@ void run_chunk(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
                      d, r0, nr, kper, part);
   HPS_LAUNCH_CHECK();
   long tot = (long)d.batch * d.M * nr;
-  hipLaunchKernelGGL(skinny_reduce_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, st, d, r0, nr,
+  hipLaunchKernelGGL(skinny_reduce_kernel, dim3(grid1d(tot)), dim3(256), 0, st, d, r0, nr,
                      nsplit, (const double2*)part);
   HPS_LAUNCH_CHECK();
 }

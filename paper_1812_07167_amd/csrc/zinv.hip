@@ -340,8 +340,9 @@ __global__ void copy_in_kernel(int n, const double* A, long lda, long sA, double
 }
 
 __global__ void zero_int_kernel(int* p, long cnt) {
-  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < cnt) p[e] = 0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < cnt;
+       e += (long)gridDim.x * blockDim.x)
+    p[e] = 0;
 }
 
 template <class T, int RPL>
@@ -376,7 +377,7 @@ void zinv_t(int n, int batch, const double* A, long lda, long sA, double* Out, l
     hipLaunchKernelGGL(copy_in_kernel<T>, dim3(cdiv(tot, 256), batch), dim3(256), 0, st, n, A,
                        lda, sA, Mcur);
     long ni = 2L * batch * n;
-    hipLaunchKernelGGL(zero_int_kernel, dim3(cdiv(ni, 256)), dim3(256), 0, st, piv, ni);
+    hipLaunchKernelGGL(zero_int_kernel, dim3(grid1d(ni)), dim3(256), 0, st, piv, ni);
     HPS_LAUNCH_CHECK();
   }
   for (int k0 = 0; k0 < n; k0 += PNB) {

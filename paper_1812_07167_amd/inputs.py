@@ -165,3 +165,19 @@ def root_normals(nx, ny, m):
     return np.concatenate([
         np.tile([0.0, -1.0], (nx * m, 1)), np.tile([1.0, 0.0], (ny * m, 1)),
         np.tile([0.0, 1.0], (nx * m, 1)), np.tile([-1.0, 0.0], (ny * m, 1))])
+
+
+def batch_problems(seed0=0, count=256):
+    """Seeded parameters of a batch of independent problems on the unit square: leaf grid
+    side from {8, 16, 32}, p from {8, 12, 16}, kappa ~ U[10, 80], eta = kappa, c a seeded
+    Fourier field (8 modes, wave numbers <= 4, total amplitude 0.5) and one manufactured
+    right-hand side with a seeded direction.  Returns a list of dicts."""
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng(seed0 + i)
+        side = int(rng.choice([8, 16, 32]))
+        p = int(rng.choice([8, 12, 16]))
+        kappa = float(rng.uniform(10.0, 80.0))
+        out.append({"seed": seed0 + i, "nx": side, "ny": side, "p": p, "kappa": kappa,
+                    "theta": float(rng.uniform(0.0, 2 * np.pi))})
+    return out
