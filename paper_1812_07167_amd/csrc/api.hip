@@ -227,8 +227,8 @@ struct hps_group {
   std::vector<int> leaf_grid;              // tree-ordered leaf -> grid index
   hps::DevBuf dleaf_grid, dxoff, duoff, dD, dLT;
   hps::DevBuf ops;                         // arena: [Psi | Y] of every leaf + merge operators
-  hps::View BI;                            // [nleaf][n*n] complex: [Psi | Y] (complex128;
-                                           // during the build only in mixed precision)
+  hps::View BI;                            // [nleaf][n*n] complex128 [Psi | Y] (complex128
+                                           // precision only)
   hps::View BI32;                          // mixed precision: complex64 copy of [Psi | Y]
   bool mixed = false;                      // opts.precision == HPS_PREC_MIXED
   hps::DevBuf rbuf[2];                     // ping-pong ItI operators (level l uses l % 2)
@@ -575,6 +575,9 @@ struct BuildScratch {
 // bytes of one complex entry of level l's operators and R (the leaves' R is complex128)
 size_t cbytes(const hps_group& f, int l) { return (l < f.L && f.lv[l].c64) ? 8 : 16; }
 
+// leaves per launch of the leaf stage (bounds its scratch)
+constexpr long kLeafChunk = 4096;
+
 bool level_forms_R(const hps_group& f, int l) {
   return l == f.L || l > 0 || f.opts.store_root_R;
 }
@@ -627,8 +630,12 @@ void plan_memory(hps_group& f, BuildScratch& sc) {
         f.R[l].bytes = level_R_bytes(f, l);
       }
   }
-  // scratch: the leaf stage and the merge levels share the same bytes; infos follow
-  size_t level_bytes = leaf_scratch_bytes(f.p, nl);
+  // scratch: the leaf stage (per chunk of leaves: the inverse's copies and, in mixed
+  // precision, the complex128 [Psi | Y] before its complex64 copy) and the merge levels
+  // share the same bytes; infos follow
+  const long lch = std::min<long>(nl, kLeafChunk);
+  size_t level_bytes = leaf_scratch_bytes(f.p, lch) +
+                       (f.mixed ? (size_t)lch * n * n * 16 + 256 : 0);
   for (auto& P : f.lv) {
     Carver c;
     const size_t e = P.c64 ? 8 : 16;
@@ -643,17 +650,10 @@ void plan_memory(hps_group& f, BuildScratch& sc) {
     sc.info_off[l] = ninfo;
     ninfo += f.lv[l].nbox;
   }
-  // mixed precision: the complex128 [Psi | Y] of the leaf stage lives in the scratch
-  // until its complex64 copy is made
   const size_t shared = (level_bytes + 255) & ~size_t(255);
-  const size_t bi64 = f.mixed ? (size_t)nl * n * n * 16 : 0;
-  sc.buf.alloc(shared + bi64 + (size_t)ninfo * sizeof(int) + 256);
+  sc.buf.alloc(shared + (size_t)ninfo * sizeof(int) + 256);
   char* base = static_cast<char*>(sc.buf.p);
-  if (f.mixed) {
-    f.BI.p = base + shared;
-    f.BI.bytes = bi64;
-  }
-  sc.info.p = base + shared + ((bi64 + 255) & ~size_t(255));
+  sc.info.p = base + shared;
   sc.info.bytes = (size_t)ninfo * sizeof(int);
 }
 
@@ -670,24 +670,29 @@ void level_scratch(const LevelPlan& P, BuildScratch& sc) {
 void build_leaves(hps_group& f, const double* c, BuildScratch& sc) {
   hipStream_t st = f.stream;
   const long nl = f.nleaf;
+  const long n = f.n, nb = f.nb, ni = f.ni;
   LeafDesc d;
   d.p = f.p; d.nleaf = f.nleaf; d.nl1 = f.nl1; d.prm = f.dprm.d();
-  d.c = c; d.leaf_grid = f.dleaf_grid.i(); d.tab = f.dLT.d(); d.BI = f.BI.d();
+  d.c = c; d.leaf_grid = f.dleaf_grid.i(); d.tab = f.dLT.d();
   d.R = f.R[f.L].d(); d.info = sc.info.i();
-  d.Mg = leaf_scratch_bytes(f.p, nl) ? static_cast<double*>(sc.buf.p) : nullptr;
-  const long n = f.n, nb = f.nb, ni = f.ni;
+  // scratch per chunk: the inverse's per-leaf copies, then (mixed precision) the
+  // complex128 [Psi | Y] of the chunk, rounded into the complex64 arena afterwards
+  char* scr = static_cast<char*>(sc.buf.p);
+  const long lch = std::min<long>(nl, kLeafChunk);
+  const size_t mg_bytes = leaf_scratch_bytes(f.p, lch);
+  double* bi64 = f.mixed ? reinterpret_cast<double*>(scr + ((mg_bytes + 255) & ~size_t(255)))
+                         : nullptr;
   Profiler& pr = f.build_prof;
-  // process leaves in chunks that fit the grid limit
-  for (long h0 = 0; h0 < nl; h0 += 65535) {
-    const int cnt = (int)std::min<long>(65535, nl - h0);
+  for (long h0 = 0; h0 < nl; h0 += lch) {
+    const int cnt = (int)std::min<long>(lch, nl - h0);
     LeafDesc dc = d;
     dc.nleaf = cnt;
-    dc.leaf_grid = d.leaf_grid + h0;
     dc.h0 = h0;
-    dc.BI = d.BI + 2 * h0 * n * n;
+    dc.leaf_grid = d.leaf_grid + h0;
+    dc.BI = f.mixed ? bi64 : f.BI.d() + 2 * h0 * n * n;
     dc.R = d.R + 2 * h0 * nb * nb;
     dc.info = d.info + h0;
-    if (d.Mg) dc.Mg = d.Mg + 2 * h0 * ni * ni;
+    dc.Mg = mg_bytes ? reinterpret_cast<double*>(scr) : nullptr;
     const double c_ = cnt;
     {
       // S_i^{-1}: complex Gauss-Jordan, n_i^3 complex multiply-adds
@@ -702,6 +707,11 @@ void build_leaves(hps_group& f, const double* c, BuildScratch& sc) {
       Stage s(pr, "leaf_bnd", c_ * 8.0 * nb * n * f.m,
               c_ * (ni * n + nb * n + nb * nb) * 16.0);
       leaf_boundary_rows(dc, st);
+    }
+    if (f.mixed) {
+      // the solve reads the leaf operators in complex64
+      Stage s(pr, "leaf_to_c64", 0.0, c_ * n * n * 24);
+      to_c64(bi64, reinterpret_cast<float*>(f.BI32.p) + 2 * h0 * n * n, 2L * cnt * n * n, st);
     }
   }
   f.R_valid[f.L] = 1;
@@ -808,11 +818,6 @@ void build_all(hps_group& f, const double* c) {
   plan_memory(f, sc);
   fill_zero_int(sc.info.i(), (long)(sc.info.bytes / sizeof(int)), f.stream);
   build_leaves(f, c, sc);
-  if (f.mixed) {
-    // the solve reads the leaf operators in complex64
-    Stage s(f.build_prof, "leaf_to_c64", 0.0, (double)f.nleaf * f.n * f.n * 24);
-    to_c64(f.BI.d(), reinterpret_cast<float*>(f.BI32.p), 2L * f.nleaf * f.n * f.n, f.stream);
-  }
   for (int l = f.L - 1; l >= 0; --l) build_level(f, l, sc);
   // one synchronization for the whole build, then the pivot checks
   HPS_HIP(hipStreamSynchronize(f.stream));
@@ -820,7 +825,6 @@ void build_all(hps_group& f, const double* c) {
   HPS_HIP(hipMemcpy(h.data(), sc.info.p, sc.info.bytes, hipMemcpyDeviceToHost));
   check_info(h, 0, f.nleaf, "leaf interior Schur complement");
   for (int l = 0; l < f.L; ++l) check_info(h, sc.info_off[l], f.lv[l].nbox, "interface matrix W");
-  if (f.mixed) f.BI = View();  // lived in the build scratch
   // release the ItI buffer that no longer holds a kept operator
   if (!f.opts.keep_all_R) {
     for (int b = 0; b < 2; ++b) {

@@ -101,3 +101,21 @@ def test_batch_handles_outlive_each_other():
     u = cases[1].gpu_solve(fs[1])
     assert rel(u, cases[1].oracle_solve(cases[1].oracle_build())) < TOL
     fs[1].free()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_spanning_several_leaf_chunks(precision):
+    """5 problems of 32 x 32 leaves: 5120 leaves, more than one chunk of the leaf stage
+    (4096 leaves), against the same problems built alone (one chunk each)."""
+    import torch
+    from paper_1812_07167_amd import hps as H
+    cases = [Case(32, 32, 6, 30.0 + 5 * i, seed=40 + i, nrhs=1) for i in range(5)]
+    fs = _batch_build(cases, precision=precision)
+    us = H.hps_solve_batch(fs, [_dev(c.t) for c in cases], [_dev(c.s) for c in cases])
+    torch.cuda.synchronize()
+    for i in (0, 4):
+        f1 = cases[i].gpu_build(precision=precision)
+        assert rel(us[i].cpu().numpy(), cases[i].gpu_solve(f1)) < (SAME if precision == 0 else TOL)
+        f1.free()
+    for f in fs:
+        f.free()
