@@ -55,7 +55,7 @@ enum {
   HPS_E_SINGULAR = 3,      /* a zero pivot in a leaf or interface inversion              */
   HPS_E_DEVICE = 4,        /* a HIP runtime call failed                                  */
   HPS_E_NOT_CONVERGED = 5, /* mixed-precision refinement did not reach its tolerance     */
-  HPS_E_BUSY = 6           /* no capacity (reserved for admission control)               */
+  HPS_E_BUSY = 6           /* no capacity: a server refused the request (admission)      */
 };
 
 /* Problem geometry: Omega = [x0,x1] x [y0,y1] split into nx x ny equal leaves; nx and
@@ -266,6 +266,114 @@ int hps_stage_times(const hps_factor* f, int32_t which, hps_stage_time* out, int
 
 /* Release a factor (NULL is a no-op). */
 void hps_free(hps_factor* f);
+
+/* Device bytes that hps_build of one problem of this shape would use, from the same plan
+ * the build lays out (host arithmetic only; nothing is allocated):
+ *   build_peak  the most held at once during the build (operators, ItI buffers, scratch)
+ *   resident    what the factor holds afterwards (hps_factor_query's device_bytes, up to
+ *               the rounding of small tables)
+ * Either output may be NULL (not both).  Errors: HPS_E_INVALID. */
+int hps_estimate_bytes(const hps_domain* dom, int32_t p, const hps_opts* opts,
+                       int64_t* build_peak, int64_t* resident);
+
+/* ---------------------------------------------------------------- request loop
+ * Serving (not in the paper).  A server keeps factored problems resident in device
+ * memory and runs build and solve requests on a pool of work slots, each a host thread
+ * with its own stream, so that work of several requests overlaps on the device.
+ *   - Admission by memory: every work item (a build, or one solve of a problem) starts
+ *     only when the bytes it needs (hps_estimate_bytes' build_peak, or the solve's
+ *     workspace and staging) fit under the budget beside what is already committed
+ *     (resident factors, running items).  If it does not fit, factors of idle problems
+ *     (no queued or running request) are freed, least recently used first (when
+ *     evict_idle is set); an evicted problem is rebuilt from the server's copy of its
+ *     data when its next solve request comes up.
+ *   - Continuous batching: when a slot takes a problem's solve, it merges every queued
+ *     request of that problem (up to max_batch_rhs right-hand sides) into one solve.
+ *     Requests that arrive while others run are taken as soon as a slot and memory free
+ *     up.
+ * A request's result does not depend on what it was batched with beyond round-off.
+ * Inputs (c, s, t) must be complete on the device when submitted (the server's streams
+ * do not wait on the caller's); u is complete when its completion is returned by
+ * hps_server_poll.  Buffers passed to submit_solve must stay valid until then. */
+typedef struct hps_server hps_server;
+
+typedef struct {
+  int32_t slots;              /* work slots: streams and host threads (default 4)           */
+  int32_t max_batch_rhs;      /* right-hand sides merged into one solve (default 64)        */
+  int32_t max_pending_builds; /* queued builds beyond which submit_build returns
+                                 HPS_E_BUSY (default 64)                                   */
+  int32_t evict_idle;         /* 1 = free idle factors, least recently used first, to admit
+                                 work (default 1)                                          */
+} hps_server_opts;
+
+enum { HPS_REQ_BUILD = 0, HPS_REQ_SOLVE = 1 };
+
+typedef struct {
+  uint64_t req;        /* id returned by the submit call                                  */
+  uint64_t problem;    /* problem id                                                       */
+  int32_t kind;        /* HPS_REQ_BUILD or HPS_REQ_SOLVE                                   */
+  int32_t status;      /* HPS_OK or the error code of the work item                       */
+  int32_t nrhs;        /* right-hand sides of the request (0 for a build)                */
+  int32_t batch_rhs;   /* right-hand sides of the solve that served it                   */
+  int32_t iterations;  /* residual-correction steps of that solve                        */
+  int32_t rebuilt;     /* 1 if the factor was rebuilt after an eviction to serve it       */
+  double t_submit;     /* seconds since hps_server_create: submission,                    */
+  double t_start;      /*   start of the work item that served it,                        */
+  double t_end;        /*   and its end (results complete)                                */
+} hps_completion;
+
+typedef struct {
+  int64_t builds, rebuilds, evictions;  /* factorizations done, of them after eviction   */
+  int64_t solves, rhs, batches;         /* solve requests done, their RHS, solve calls    */
+  int64_t rejected, failed;             /* submissions refused (HPS_E_BUSY), failed items */
+  int32_t resident, pending;            /* problems with a factor; requests not returned  */
+  int32_t max_concurrent;               /* most work items that ran at once               */
+  int32_t slots;
+  double p50_ms, p99_ms, max_ms;        /* solve latency, submission to completion        */
+  double wall_s;                        /* first submission to last completion            */
+  double rhs_per_s, solves_per_s;       /* over wall_s                                    */
+  int64_t budget_bytes, committed_bytes, peak_committed_bytes;
+} hps_stats;
+
+/* Fill *opts with the defaults. */
+void hps_server_default_opts(hps_server_opts* opts);
+
+/* Start a server on the current device.  hbm_budget: bytes the server may commit (0 =
+ * 90% of the device memory free at the call); opts NULL for defaults.
+ * Errors: HPS_E_INVALID, HPS_E_DEVICE. */
+int hps_server_create(size_t hbm_budget, const hps_server_opts* opts, hps_server** out);
+
+/* Queue the factorization of a problem (arguments as for hps_build; opts.stream is
+ * ignored, opts.profile must be 0).  c_interior is copied before the call returns.
+ * *problem receives the id to solve with, *req the id of its completion.
+ * Errors: HPS_E_INVALID; HPS_E_BUSY when the build alone exceeds the budget or too many
+ * builds are queued (the request is rejected); HPS_E_NOMEM, HPS_E_DEVICE. */
+int hps_server_submit_build(hps_server* srv, const hps_domain* dom, int32_t p, double kappa,
+                            double eta_re, double eta_im, const double* c_interior,
+                            const hps_opts* opts, uint64_t* problem, uint64_t* req);
+
+/* Queue a solve of nrhs right-hand sides of a problem (s, t, u as for hps_solve; device
+ * pointers owned by the caller, valid until the completion is returned).  Allowed as
+ * soon as the problem's build is submitted.  Errors: HPS_E_INVALID (unknown or released
+ * problem, arguments). */
+int hps_server_submit_solve(hps_server* srv, uint64_t problem, int32_t nrhs, const double* s,
+                            const double* t, double* u, uint64_t* req);
+
+/* Drop a problem: its factor and data are freed once its queued requests are done;
+ * later submissions for it fail with HPS_E_INVALID. */
+int hps_server_release(hps_server* srv, uint64_t problem);
+
+/* Return up to max completions (host array out) in completion order; *n receives the
+ * count.  Waits up to timeout_ms for the first one (0 = do not wait). */
+int hps_server_poll(hps_server* srv, hps_completion* out, int32_t max, int32_t timeout_ms,
+                    int32_t* n);
+
+/* Counters and solve-latency percentiles so far. */
+int hps_server_stats(hps_server* srv, hps_stats* stats);
+
+/* Stop the server: running work items finish, queued requests are dropped without a
+ * completion, every factor is freed.  NULL is a no-op. */
+void hps_server_destroy(hps_server* srv);
 
 #ifdef __cplusplus
 }

@@ -588,26 +588,73 @@ size_t level_R_bytes(const hps_group& f, int l) {
   return (size_t)P.nbox * P.nbp * P.nbp * cbytes(f, l);
 }
 
-void plan_memory(hps_group& f, BuildScratch& sc) {
-  const long nl = f.nleaf, n = f.n, nb = f.nb, ni = f.ni;
-  for (int pass = 0; pass < 2; ++pass) {
-    Carver c;
-    c.base = pass ? static_cast<char*>(f.ops.p) : nullptr;
-    if (f.mixed) f.BI32 = c.take((size_t)nl * n * n * 8);
-    else f.BI = c.take((size_t)nl * n * n * 16);
-    for (auto& P : f.lv) {
-      const size_t nbox = P.nbox, n1 = P.n1, n2 = P.n2, n3 = P.n3, nbp = P.nbp;
-      const size_t e = P.c64 ? 8 : 16;
-      P.Winv = c.take(nbox * n3 * n3 * e);
-      P.R33a = c.take(nbox * n3 * n3 * e);
-      P.R33b = c.take(nbox * n3 * n3 * e);
-      P.R13a = c.take(nbox * n1 * n3 * e);
-      P.R23b = c.take(nbox * n2 * n3 * e);
-      P.PhiA = c.take(nbox * n3 * nbp * e);
-      P.PhiB = c.take(nbox * n3 * nbp * e);
-    }
-    if (pass == 0) f.ops.alloc(c.used);
+// Layout of the operator arena (base = nullptr only sizes it); returns its bytes.
+size_t arena_layout(hps_group& f, char* base) {
+  const long nl = f.nleaf, n = f.n;
+  Carver c;
+  c.base = base;
+  if (f.mixed) f.BI32 = c.take((size_t)nl * n * n * 8);
+  else f.BI = c.take((size_t)nl * n * n * 16);
+  for (auto& P : f.lv) {
+    const size_t nbox = P.nbox, n1 = P.n1, n2 = P.n2, n3 = P.n3, nbp = P.nbp;
+    const size_t e = P.c64 ? 8 : 16;
+    P.Winv = c.take(nbox * n3 * n3 * e);
+    P.R33a = c.take(nbox * n3 * n3 * e);
+    P.R33b = c.take(nbox * n3 * n3 * e);
+    P.R13a = c.take(nbox * n1 * n3 * e);
+    P.R23b = c.take(nbox * n2 * n3 * e);
+    P.PhiA = c.take(nbox * n3 * nbp * e);
+    P.PhiB = c.take(nbox * n3 * nbp * e);
   }
+  return c.used;
+}
+
+// Bytes of the build scratch (leaf chunks and merge levels; the info words follow).
+size_t scratch_bytes(const hps_group& f) {
+  const long nl = f.nleaf, n = f.n;
+  const long lch = std::min<long>(nl, kLeafChunk);
+  size_t level_bytes = leaf_scratch_bytes(f.p, lch) +
+                       (f.mixed ? (size_t)lch * n * n * 16 + 256 : 0);
+  for (auto& P : f.lv) {
+    Carver c;
+    const size_t e = P.c64 ? 8 : 16;
+    c.take((size_t)P.nbox * P.n3 * P.n1 * e);
+    c.take((size_t)P.nbox * P.n3 * P.nbp * e);
+    c.take(zinv_workspace_bytes(P.n3, P.nbox, P.c64));
+    level_bytes = std::max(level_bytes, c.used);
+  }
+  return (level_bytes + 255) & ~size_t(255);
+}
+
+// Device bytes of a planned group (make_plan done, nothing allocated): the peak during
+// the build and what stays resident afterwards, from the same sizes the build allocates.
+void estimate_bytes(hps_group& f, size_t* peak, size_t* resident) {
+  const size_t arena = arena_layout(f, nullptr);
+  size_t rb[2] = {0, 0}, kept = 0, keep_all = 0;
+  for (int l = 0; l <= f.L; ++l)
+    if (level_forms_R(f, l)) {
+      rb[l % 2] = std::max(rb[l % 2], level_R_bytes(f, l));
+      keep_all += level_R_bytes(f, l);
+    }
+  if (f.opts.keep_all_R) kept = keep_all;
+  else if (level_forms_R(f, 0)) kept = rb[0];
+  const size_t rbufs = f.opts.keep_all_R ? keep_all : rb[0] + rb[1];
+  // leaf maps (int grid index, long x/u offsets), c, the four p x p differentiation
+  // matrices, per-problem parameters and line tables, then the level maps
+  size_t small = (size_t)f.nleaf * (4 + 16) + (size_t)f.nleaf * f.ni * 8 + (size_t)32 * f.p * f.p +
+                 (size_t)32 * f.nprob + (size_t)f.nprob * leaf_table_len(f.p) * 16;
+  for (auto& P : f.lv)
+    small += 4 * (P.codeA.size() + P.codeB.size() + P.perm.size() + P.i1a.size() +
+                  P.i3a.size() + P.i2b.size() + P.i3b.size() + P.ja.size() + P.jb.size());
+  const size_t ninfo = 4 * (2 * (size_t)f.nleaf + (size_t)f.nleaf);
+  *resident = arena + kept + small;
+  *peak = arena + rbufs + small + scratch_bytes(f) + ninfo;
+}
+
+void plan_memory(hps_group& f, BuildScratch& sc) {
+  const long nl = f.nleaf;
+  f.ops.alloc(arena_layout(f, nullptr));
+  arena_layout(f, static_cast<char*>(f.ops.p));
   f.R.assign(f.L + 1, View());
   f.R_valid.assign(f.L + 1, 0);
   if (f.opts.keep_all_R) {
@@ -633,24 +680,13 @@ void plan_memory(hps_group& f, BuildScratch& sc) {
   // scratch: the leaf stage (per chunk of leaves: the inverse's copies and, in mixed
   // precision, the complex128 [Psi | Y] before its complex64 copy) and the merge levels
   // share the same bytes; infos follow
-  const long lch = std::min<long>(nl, kLeafChunk);
-  size_t level_bytes = leaf_scratch_bytes(f.p, lch) +
-                       (f.mixed ? (size_t)lch * n * n * 16 + 256 : 0);
-  for (auto& P : f.lv) {
-    Carver c;
-    const size_t e = P.c64 ? 8 : 16;
-    c.take((size_t)P.nbox * P.n3 * P.n1 * e);
-    c.take((size_t)P.nbox * P.n3 * P.nbp * e);
-    c.take(zinv_workspace_bytes(P.n3, P.nbox, P.c64));
-    level_bytes = std::max(level_bytes, c.used);
-  }
   long ninfo = 2 * nl;
   sc.info_off.assign(f.L, 0);
   for (int l = 0; l < f.L; ++l) {
     sc.info_off[l] = ninfo;
     ninfo += f.lv[l].nbox;
   }
-  const size_t shared = (level_bytes + 255) & ~size_t(255);
+  const size_t shared = scratch_bytes(f);
   sc.buf.alloc(shared + (size_t)ninfo * sizeof(int) + 256);
   char* base = static_cast<char*>(sc.buf.p);
   sc.info.p = base + shared;
@@ -890,7 +926,7 @@ struct Arena {
 // t [np][nrhs][nt], u [nrhs][np nl1 n].
 void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const double* t,
                 const double* jmp, double* u, Arena& ws) {
-  hipStream_t st = f.stream;
+  hipStream_t st = ws.st;
   Profiler& pr = f.solve_prof;
   pr.reset(!ws.dry && f.opts.profile != 0, st);
   const char* nm = "solve_leaf_up";
@@ -1121,6 +1157,8 @@ int hps_nodes(const hps_domain* dom, int32_t p, double* xy_leaf, double* xy_inte
   });
 }
 
+}  // extern "C"
+
 namespace hps {
 namespace {
 
@@ -1171,6 +1209,8 @@ std::shared_ptr<hps_group> build_group(const hps_domain& dom, int p, int nprob,
 
 }  // namespace
 }  // namespace hps
+
+extern "C" {
 
 int hps_build(const hps_domain* dom, int32_t p, double kappa, double eta_re, double eta_im,
               const double* c_interior, const hps_opts* opts, hps_factor** out) {
@@ -1231,6 +1271,8 @@ int hps_build_batch(int32_t nprob, const hps_domain* doms, const int32_t* p,
   return rc;
 }
 
+}  // extern "C"
+
 namespace hps {
 namespace {
 
@@ -1254,17 +1296,24 @@ int refine_iters(const hps_group& f) {
 // rows as interface jumps, u += delta, until max_r |delta_r| <= tol |u_r| (norms over
 // the problems of the range) or the iteration limit.
 void solve_impl(hps_group& f, int pb, int np, int nrhs, const double* s, const double* t,
-                const double* jmp, double* u) {
+                const double* jmp, double* u, hipStream_t st, hps_solve_info* info,
+                size_t* ws_bytes = nullptr) {
   const int iters = refine_iters(f);
   const long nl = (long)np * f.nl1, n = f.n, nb = f.nb, ni = f.ni;
   const long nt = 2L * (f.nx + f.ny) * f.m;
   const int nblk = norms_blocks();
   Arena ws;
-  ws.st = f.stream;
+  ws.st = st;
   double *rs = nullptr, *rt = nullptr, *rj = nullptr, *dl = nullptr, *part = nullptr;
   size_t mark = 0;
   for (int pass = 0; pass < 2; ++pass) {
-    if (pass == 1) ws.allocate();
+    if (pass == 1) {
+      if (ws_bytes) {  // sizing only
+        *ws_bytes = std::max(ws.used, ws.peak) + ws.split_need + 256;
+        return;
+      }
+      ws.allocate();
+    }
     if (iters > 0) {
       rs = ws.get((size_t)nrhs * nl * ni * 16);
       rt = ws.get((size_t)np * nrhs * nt * 16);
@@ -1280,7 +1329,7 @@ void solve_impl(hps_group& f, int pb, int np, int nrhs, const double* s, const d
       solve_pass(f, pb, np, nrhs, rs, rt, rj, dl, ws);
     }
   }
-  f.last_info = hps_solve_info{};
+  *info = hps_solve_info{};
   if (iters <= 0) return;
   std::vector<double> hpart((size_t)nrhs * nblk * 2);
   double corr = 0.0;
@@ -1291,14 +1340,14 @@ void solve_impl(hps_group& f, int pb, int np, int nrhs, const double* s, const d
     r.rs = rs; r.rs_rhs = nl * ni; r.rs_leaf = ni;
     r.rb = rj; r.rb_rhs = nl * nb; r.rb_leaf = nb;
     r.rt = rt;
-    residual(r, nrhs, f.stream);
+    residual(r, nrhs, st);
     ws.used = mark;
     solve_pass(f, pb, np, nrhs, rs, rt, rj, dl, ws);
-    norms_partial(nl * n, nrhs, dl, u, part, f.stream);
-    axpy((long)nrhs * nl * n, dl, u, f.stream);
+    norms_partial(nl * n, nrhs, dl, u, part, st);
+    axpy((long)nrhs * nl * n, dl, u, st);
     HPS_HIP(hipMemcpyAsync(hpart.data(), part, hpart.size() * sizeof(double),
-                           hipMemcpyDeviceToHost, f.stream));
-    HPS_HIP(hipStreamSynchronize(f.stream));
+                           hipMemcpyDeviceToHost, st));
+    HPS_HIP(hipStreamSynchronize(st));
     corr = 0.0;
     for (int q = 0; q < nrhs; ++q) {
       double dd = 0, uu = 0;
@@ -1313,9 +1362,9 @@ void solve_impl(hps_group& f, int pb, int np, int nrhs, const double* s, const d
       break;
     }
   }
-  f.last_info.iterations = std::min(it, iters);
-  f.last_info.converged = conv ? 1 : 0;
-  f.last_info.correction = corr;
+  info->iterations = std::min(it, iters);
+  info->converged = conv ? 1 : 0;
+  info->correction = corr;
   if (!conv)
     throw Error(HPS_E_NOT_CONVERGED, "residual correction did not reach refine_tol (last "
                                      "relative correction " + std::to_string(corr) + ")");
@@ -1324,12 +1373,15 @@ void solve_impl(hps_group& f, int pb, int np, int nrhs, const double* s, const d
 }  // namespace
 }  // namespace hps
 
+extern "C" {
+
 int hps_solve(hps_factor* f, int32_t nrhs, const double* s, const double* t, double* u) {
   return guard([&] {
     if (!f) throw Error(HPS_E_INVALID, "factor is NULL");
     if (!t || !u) throw Error(HPS_E_INVALID, "t and u must be non-NULL");
     if (nrhs < 1) throw Error(HPS_E_INVALID, "nrhs must be >= 1");
-    solve_impl(*f->g, f->b0, 1, nrhs, s, t, nullptr, u);
+    hps_group& G = *f->g;
+    solve_impl(G, f->b0, 1, nrhs, s, t, nullptr, u, G.stream, &G.last_info);
   });
 }
 
@@ -1339,7 +1391,8 @@ int hps_solve_jumps(hps_factor* f, int32_t nrhs, const double* s, const double* 
     if (!f) throw Error(HPS_E_INVALID, "factor is NULL");
     if (!t || !u) throw Error(HPS_E_INVALID, "t and u must be non-NULL");
     if (nrhs < 1) throw Error(HPS_E_INVALID, "nrhs must be >= 1");
-    solve_impl(*f->g, f->b0, 1, nrhs, s, t, jumps, u);
+    hps_group& G = *f->g;
+    solve_impl(G, f->b0, 1, nrhs, s, t, jumps, u, G.stream, &G.last_info);
   });
 }
 
@@ -1407,7 +1460,7 @@ int hps_solve_batch(int32_t nprob, hps_factor* const* f, const int32_t* nrhs,
         HPS_HIP(hipMemcpyAsync(T + 2 * o * R * nt, t[j], (size_t)nrhs[j] * nt * 16,
                                hipMemcpyDeviceToDevice, st));
       }
-      solve_impl(G, pb, np, R, S, T, nullptr, U);
+      solve_impl(G, pb, np, R, S, T, nullptr, U, st, &G.last_info);
       for (int j : mem) {
         const long o = f[j]->b0 - pb;
         HPS_HIP(hipMemcpy2DAsync(u[j], (size_t)G.nl1 * n * 16, U + 2 * o * G.nl1 * n,
@@ -1562,4 +1615,47 @@ int hps_stage_times(const hps_factor* h, int32_t which, hps_stage_time* out, int
 
 void hps_free(hps_factor* f) { delete f; }
 
+int hps_estimate_bytes(const hps_domain* dom, int32_t p, const hps_opts* opts,
+                       int64_t* build_peak, int64_t* resident) {
+  return guard([&] {
+    validate_domain(dom, p);
+    if (!build_peak && !resident) throw Error(HPS_E_INVALID, "no output requested");
+    hps_group f;
+    if (opts) f.opts = *opts; else hps_default_opts(&f.opts);
+    f.mixed = f.opts.precision == HPS_PREC_MIXED;
+    f.p = p; f.m = p - 2; f.n = p * p - 4; f.nb = 4 * (p - 2); f.ni = (p - 2) * (p - 2);
+    f.nx = dom->nx; f.ny = dom->ny;
+    f.nprob = 1; f.nl1 = dom->nx * dom->ny; f.nleaf = f.nl1;
+    make_plan(f);
+    for (int l = 0; l < f.L; ++l) f.lv[l].c64 = f.mixed && l >= f.opts.fp64_top_levels;
+    size_t pk = 0, rs = 0;
+    estimate_bytes(f, &pk, &rs);
+    if (build_peak) *build_peak = (int64_t)pk;
+    if (resident) *resident = (int64_t)rs;
+  });
+}
+
 }  // extern "C"
+
+// ------------------------------------------------------------------ serving hooks
+namespace hps {
+
+void set_last_error(const std::string& msg) { g_err = msg; }
+
+size_t solve_workspace_bytes(hps_factor* f, int nrhs, bool with_s) {
+  hps_group& G = *f->g;
+  // the sizing pass never dereferences the vectors: placeholders stand in for them
+  const double* ph = reinterpret_cast<const double*>(4096);
+  size_t bytes = 0;
+  hps_solve_info info{};
+  solve_impl(G, f->b0, 1, nrhs, with_s ? ph : nullptr, ph, nullptr, const_cast<double*>(ph),
+             nullptr, &info, &bytes);
+  return bytes;
+}
+
+void solve_on(hps_factor* f, int nrhs, const double* s, const double* t, double* u,
+              hipStream_t st, hps_solve_info* info) {
+  solve_impl(*f->g, f->b0, 1, nrhs, s, t, nullptr, u, st, info);
+}
+
+}  // namespace hps

@@ -23,8 +23,12 @@ EXPORTS = [
     "hps_last_error", "hps_version", "hps_default_opts", "hps_nodes", "hps_build",
     "hps_build_batch", "hps_solve", "hps_solve_batch", "hps_solve_jumps", "hps_residual",
     "hps_last_solve_info", "hps_factor_query",
-    "hps_factor_get", "hps_factor_box", "hps_stage_times", "hps_free",
+    "hps_factor_get", "hps_factor_box", "hps_stage_times", "hps_free", "hps_estimate_bytes",
+    "hps_server_default_opts", "hps_server_create", "hps_server_submit_build",
+    "hps_server_submit_solve", "hps_server_release", "hps_server_poll", "hps_server_stats",
+    "hps_server_destroy",
 ]
+HPS_REQ_BUILD, HPS_REQ_SOLVE = 0, 1
 HPS_PREC_C128, HPS_PREC_MIXED = 0, 1
 
 
@@ -58,6 +62,29 @@ class FactorInfo(C.Structure):
     _fields_ = [("p", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("levels", C.c_int32),
                 ("nleaf", C.c_int64), ("n_leaf_nodes", C.c_int64), ("n_interior", C.c_int64),
                 ("n_root", C.c_int64), ("device_bytes", C.c_int64)]
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("max_batch_rhs", C.c_int32),
+                ("max_pending_builds", C.c_int32), ("evict_idle", C.c_int32)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("req", C.c_uint64), ("problem", C.c_uint64), ("kind", C.c_int32),
+                ("status", C.c_int32), ("nrhs", C.c_int32), ("batch_rhs", C.c_int32),
+                ("iterations", C.c_int32), ("rebuilt", C.c_int32), ("t_submit", C.c_double),
+                ("t_start", C.c_double), ("t_end", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("builds", C.c_int64), ("rebuilds", C.c_int64), ("evictions", C.c_int64),
+                ("solves", C.c_int64), ("rhs", C.c_int64), ("batches", C.c_int64),
+                ("rejected", C.c_int64), ("failed", C.c_int64), ("resident", C.c_int32),
+                ("pending", C.c_int32), ("max_concurrent", C.c_int32), ("slots", C.c_int32),
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("max_ms", C.c_double),
+                ("wall_s", C.c_double), ("rhs_per_s", C.c_double), ("solves_per_s", C.c_double),
+                ("budget_bytes", C.c_int64), ("committed_bytes", C.c_int64),
+                ("peak_committed_bytes", C.c_int64)]
 
 
 _lib = None
@@ -96,10 +123,26 @@ def load(path: str = LIB_PATH):
     lib.hps_stage_times.argtypes = [P, I32, C.POINTER(StageTime), I32, C.POINTER(I32)]
     lib.hps_free.argtypes = [P]
     lib.hps_free.restype = None
+    lib.hps_estimate_bytes.argtypes = [C.POINTER(Domain), I32, C.POINTER(Opts), C.POINTER(I64),
+                                       C.POINTER(I64)]
+    lib.hps_server_default_opts.argtypes = [C.POINTER(ServerOpts)]
+    lib.hps_server_default_opts.restype = None
+    lib.hps_server_create.argtypes = [C.c_size_t, C.POINTER(ServerOpts), C.POINTER(P)]
+    U64 = C.c_uint64
+    lib.hps_server_submit_build.argtypes = [P, C.POINTER(Domain), I32, D, D, D, P,
+                                            C.POINTER(Opts), C.POINTER(U64), C.POINTER(U64)]
+    lib.hps_server_submit_solve.argtypes = [P, U64, I32, P, P, P, C.POINTER(U64)]
+    lib.hps_server_release.argtypes = [P, U64]
+    lib.hps_server_poll.argtypes = [P, C.POINTER(Completion), I32, I32, C.POINTER(I32)]
+    lib.hps_server_stats.argtypes = [P, C.POINTER(Stats)]
+    lib.hps_server_destroy.argtypes = [P]
+    lib.hps_server_destroy.restype = None
     for name in ["hps_nodes", "hps_build", "hps_build_batch", "hps_solve", "hps_solve_batch",
                  "hps_solve_jumps", "hps_residual",
                  "hps_last_solve_info", "hps_factor_query", "hps_factor_get", "hps_factor_box",
-                 "hps_stage_times"]:
+                 "hps_stage_times", "hps_estimate_bytes", "hps_server_create",
+                 "hps_server_submit_build", "hps_server_submit_solve", "hps_server_release",
+                 "hps_server_poll", "hps_server_stats"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -326,3 +369,129 @@ def hps_residual(f: Factor, u, t=None, s=None, jumps=None, r=None):
     _check(load().hps_residual(f.h, nrhs, sp, tp, jp, _dev_ptr(u, "torch.complex128"),
                                _dev_ptr(r, "torch.complex128")))
     return r
+
+
+def _plain_opts(precision=HPS_PREC_C128, fp64_top_levels=None, refine_max_iter=None,
+                refine_tol=None, keep_all_R=False, store_root_R=True):
+    """hps_opts without a stream (host-only calls and the request loop)."""
+    opts = Opts()
+    load().hps_default_opts(C.byref(opts))
+    opts.precision = int(precision)
+    opts.keep_all_R = int(keep_all_R)
+    opts.store_root_R = int(store_root_R)
+    if fp64_top_levels is not None:
+        opts.fp64_top_levels = int(fp64_top_levels)
+    if refine_max_iter is not None:
+        opts.refine_max_iter = int(refine_max_iter)
+    if refine_tol is not None:
+        opts.refine_tol = float(refine_tol)
+    return opts
+
+
+def hps_estimate_bytes(dom: Domain, p: int, **opts):
+    """(build_peak, resident) device bytes of one problem's factorization (host only)."""
+    peak, res = C.c_int64(), C.c_int64()
+    o = _plain_opts(**opts)
+    _check(load().hps_estimate_bytes(C.byref(dom), p, C.byref(o), C.byref(peak), C.byref(res)))
+    return peak.value, res.value
+
+
+class Server:
+    """Request loop over resident factorizations (hps_server_*).  Tensors handed to
+    solve() are kept referenced here until their completion has been polled."""
+
+    def __init__(self, budget_bytes=0, slots=None, max_batch_rhs=None, max_pending_builds=None,
+                 evict_idle=None):
+        lib = load()
+        o = ServerOpts()
+        lib.hps_server_default_opts(C.byref(o))
+        if slots is not None:
+            o.slots = int(slots)
+        if max_batch_rhs is not None:
+            o.max_batch_rhs = int(max_batch_rhs)
+        if max_pending_builds is not None:
+            o.max_pending_builds = int(max_pending_builds)
+        if evict_idle is not None:
+            o.evict_idle = int(evict_idle)
+        h = C.c_void_p()
+        _check(lib.hps_server_create(int(budget_bytes), C.byref(o), C.byref(h)))
+        self.h = h
+        self._held = {}   # req -> tensors that must outlive the request
+        self.shapes = {}  # problem -> (n_leaf_nodes, n_interior, n_root)
+
+    def build(self, dom: Domain, p: int, kappa: float, eta: complex, c_interior, **opts):
+        """Queue a build; c_interior (float64 device tensor) is copied before returning.
+        Returns (problem_id, request_id)."""
+        import torch
+        o = _plain_opts(**opts)
+        pid, req = C.c_uint64(), C.c_uint64()
+        torch.cuda.synchronize()  # the server's streams do not wait on torch's
+        _check(load().hps_server_submit_build(
+            self.h, C.byref(dom), p, float(kappa), float(np.real(eta)), float(np.imag(eta)),
+            _dev_ptr(c_interior, "torch.float64"), C.byref(o), C.byref(pid), C.byref(req)))
+        nl, m = dom.nx * dom.ny, p - 2
+        self.shapes[pid.value] = (nl * (p * p - 4), nl * m * m, 2 * (dom.nx + dom.ny) * m)
+        return pid.value, req.value
+
+    def solve(self, problem, t, s=None, u=None, sync=True):
+        """Queue a solve: t [nrhs, n_root], s [nrhs, n_interior] or None (complex128 device
+        tensors, complete on the device: sync=True synchronizes torch first).  Returns
+        (request_id, u); u is valid once the request's completion is polled."""
+        import torch
+        nrhs = t.shape[0]
+        if u is None:
+            u = torch.empty((nrhs, self.shapes[problem][0]), dtype=torch.complex128,
+                            device=t.device)
+        if sync:
+            torch.cuda.synchronize()
+        req = C.c_uint64()
+        sp = _dev_ptr(s, "torch.complex128") if s is not None else None
+        _check(load().hps_server_submit_solve(self.h, problem, nrhs, sp,
+                                              _dev_ptr(t, "torch.complex128"),
+                                              _dev_ptr(u, "torch.complex128"), C.byref(req)))
+        self._held[req.value] = (t, s, u)
+        return req.value, u
+
+    def release(self, problem):
+        _check(load().hps_server_release(self.h, problem))
+
+    def poll(self, max_n=256, timeout_ms=0):
+        """List of completions (dicts); waits up to timeout_ms for the first."""
+        buf = (Completion * max_n)()
+        n = C.c_int32()
+        _check(load().hps_server_poll(self.h, buf, max_n, int(timeout_ms), C.byref(n)))
+        out = []
+        for i in range(n.value):
+            c = buf[i]
+            out.append({k: getattr(c, k) for k, _ in Completion._fields_})
+            self._held.pop(c.req, None)
+        return out
+
+    def wait(self, reqs, timeout_s=120.0):
+        """Poll until every request id in reqs has completed; returns {req: completion}."""
+        import time
+        want, got = set(reqs), {}
+        t_end = time.monotonic() + timeout_s
+        while want - set(got):
+            if time.monotonic() > t_end:
+                raise TimeoutError(f"requests not completed: {sorted(want - set(got))[:8]}")
+            for c in self.poll(256, 100):
+                got[c["req"]] = c
+        return got
+
+    def stats(self):
+        st = Stats()
+        _check(load().hps_server_stats(self.h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in Stats._fields_}
+
+    def close(self):
+        if self.h:
+            load().hps_server_destroy(self.h)
+            self.h = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

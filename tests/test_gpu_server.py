@@ -1,0 +1,187 @@
+"""The request loop (hps_server_*): results served in a mix of concurrent, merged
+requests equal the same requests solved alone (rel. 1e-12 in complex128, 1e-10 with
+mixed precision, whose corrections stop at a relative change of 1e-12), admission by
+the memory budget evicts and rebuilds idle factors without changing results, and the
+bookkeeping (estimates, rejections, release) holds."""
+
+import numpy as np
+import pytest
+
+from tests.hps_cases import Case, rel
+
+pytestmark = pytest.mark.gpu
+SAME = 1e-12
+TOL = 1e-10
+
+
+def _dev(a, dt="complex128"):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=getattr(torch, dt), device="cuda")
+
+
+def _submit_build(srv, case, **kw):
+    from paper_1812_07167_amd import hps as H
+    return srv.build(H.domain(case.nx, case.ny, case.box), case.p, case.kappa, case.eta,
+                     _dev(case.c, "float64"), **kw)
+
+
+def _requests(cases, count, seed):
+    """count seeded requests over the cases: (case index, t, s or None)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(count):
+        j = int(rng.integers(len(cases)))
+        c = cases[j]
+        nr = int(rng.integers(1, 4))
+        nt, ni = c.t.shape[1], c.s.shape[1]
+        t = rng.standard_normal((nr, nt)) + 1j * rng.standard_normal((nr, nt))
+        s = None if q % 3 == 2 else rng.standard_normal((nr, ni)) + 1j * rng.standard_normal((nr, ni))
+        out.append((j, t, s))
+    return out
+
+
+def _alone(case, f, t, s):
+    import torch
+    from paper_1812_07167_amd import hps as H
+    u = H.hps_solve(f, _dev(t), None if s is None else _dev(s))
+    torch.cuda.synchronize()
+    return u.cpu().numpy()
+
+
+def test_results_alone_equal_results_in_the_mix():
+    """Requests for four problems (one in mixed precision) submitted in a burst while a
+    larger build holds the only slot, so that they queue and merge."""
+    from paper_1812_07167_amd import hps as H
+    cases = [Case(8, 8, 10, 30.0, seed=1), Case(4, 4, 8, 20.0, eta=15.0 + 3.0j, seed=2),
+             Case(8, 4, 12, 40.0, seed=3), Case(16, 16, 8, 25.0, seed=4)]
+    prec = [0, 0, 0, H.HPS_PREC_MIXED]
+    big = Case(32, 32, 12, 50.0, seed=9, nrhs=1)
+    import torch
+    reqs = _requests(cases, 30, seed=7)
+    dev = [(_dev(t), None if s is None else _dev(s)) for _, t, s in reqs]
+    torch.cuda.synchronize()
+    srv = H.Server(budget_bytes=0, slots=1, max_batch_rhs=8)
+    try:
+        _submit_build(srv, big)
+        pids = [_submit_build(srv, c, precision=pr)[0] for c, pr in zip(cases, prec)]
+        ids, us = [], []
+        for (j, _, _), (td, sd) in zip(reqs, dev):
+            r, u = srv.solve(pids[j], td, sd, sync=False)
+            ids.append(r)
+            us.append(u)
+        done = srv.wait(ids)
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert all(done[r]["status"] == 0 for r in ids), [done[r] for r in ids]
+    merged = [done[r] for r in ids if done[r]["batch_rhs"] > done[r]["nrhs"]]
+    assert merged, "no request was merged with another"
+    assert st["batches"] < st["solves"] == len(reqs)
+    assert st["rhs"] == sum(t.shape[0] for _, t, _ in reqs)
+    fs = [c.gpu_build(precision=pr) for c, pr in zip(cases, prec)]
+    for (j, t, s), u in zip(reqs, us):
+        ua = _alone(cases[j], fs[j], t, s)
+        assert rel(u.cpu().numpy(), ua) < (TOL if prec[j] else SAME), j
+    # and one request per problem against the oracle
+    from oracle import hps_oracle as O
+    for j, c in enumerate(cases):
+        q = next(k for k, (jj, _, s) in enumerate(reqs) if jj == j and s is not None)
+        _, t, s = reqs[q]
+        uo = O.solve(c.prob, c.oracle_build(), s, t)
+        assert rel(us[q].cpu().numpy(), uo) < TOL, j
+    for f in fs:
+        f.free()
+
+
+def test_work_overlaps_across_slots():
+    """With four slots, builds and solves of different problems run at the same time."""
+    from paper_1812_07167_amd import hps as H
+    cases = [Case(16, 16, 10, 30.0 + 5 * k, seed=20 + k, nrhs=2) for k in range(4)]
+    srv = H.Server(slots=4)
+    try:
+        pids = [_submit_build(srv, c)[0] for c in cases]
+        ids, us = [], []
+        for k in range(3):
+            for pid, c in zip(pids, cases):
+                r, u = srv.solve(pid, _dev(c.t), _dev(c.s), sync=False)
+                ids.append((r, c))
+                us.append(u)
+        done = srv.wait([r for r, _ in ids])
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["max_concurrent"] >= 2
+    ref = {id(c): c.oracle_solve(c.oracle_build()) for c in cases}
+    for (r, c), u in zip(ids, us):
+        assert done[r]["status"] == 0
+        assert rel(u.cpu().numpy(), ref[id(c)]) < TOL
+
+
+def test_admission_evicts_and_rebuilds_idle_factors():
+    """A budget that holds two factors beside a third one's build: building the third
+    evicts the least recently used, and solving an evicted problem rebuilds it, with the
+    same results."""
+    from paper_1812_07167_amd import hps as H
+    cases = [Case(16, 16, 10, 25.0 + 5 * k, seed=30 + k, nrhs=2) for k in range(3)]
+    peak, res = H.hps_estimate_bytes(H.domain(16, 16), 10)
+    cbytes = 16 * 16 * 64 * 8  # the server's copy of c: nx ny (p-2)^2 doubles
+    budget = res + peak + res // 2 + 3 * cbytes
+    srv = H.Server(budget_bytes=budget, slots=1)
+    try:
+        pids = [_submit_build(srv, c)[0] for c in cases]
+        ids, us = [], []
+        for k in (0, 1, 2, 0):
+            r, u = srv.solve(pids[k], _dev(cases[k].t), _dev(cases[k].s))
+            done = srv.wait([r])
+            ids.append((r, k, done[r]))
+            us.append(u)
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["evictions"] >= 2 and st["rebuilds"] >= 2, st
+    assert st["peak_committed_bytes"] <= budget
+    assert any(d["rebuilt"] for _, _, d in ids)
+    for (r, k, d), u in zip(ids, us):
+        assert d["status"] == 0
+        assert rel(u.cpu().numpy(), cases[k].oracle_solve(cases[k].oracle_build())) < TOL
+
+
+def test_estimate_equals_factor_bytes():
+    from paper_1812_07167_amd import hps as H
+    for nx, ny, p, kw in [(8, 8, 10, {}), (16, 4, 12, {"precision": 1}), (1, 1, 8, {}),
+                          (4, 8, 16, {"keep_all_R": True}), (8, 8, 8, {"store_root_R": False})]:
+        c = Case(nx, ny, p, 20.0, seed=p, nrhs=1)
+        f = c.gpu_build(**kw)
+        _, res = H.hps_estimate_bytes(H.domain(nx, ny), p, **kw)
+        assert res == f.info.device_bytes, (nx, ny, p, kw)
+        f.free()
+
+
+def test_rejection_release_and_unknown_problems():
+    from paper_1812_07167_amd import hps as H
+    c = Case(8, 8, 10, 20.0, seed=5, nrhs=1)
+    peak, _ = H.hps_estimate_bytes(H.domain(8, 8), 10)
+    srv = H.Server(budget_bytes=peak // 2, slots=2)
+    try:
+        with pytest.raises(H.HPSError) as e:
+            _submit_build(srv, c)
+        assert e.value.code == H.HPS_E_BUSY
+        assert srv.stats()["rejected"] == 1
+    finally:
+        srv.close()
+    srv = H.Server(slots=2)
+    try:
+        pid, breq = _submit_build(srv, c)
+        r, u = srv.solve(pid, _dev(c.t), _dev(c.s))
+        done = srv.wait([breq, r])
+        assert done[breq]["kind"] == H.HPS_REQ_BUILD and done[breq]["status"] == 0
+        assert rel(u.cpu().numpy(), c.oracle_solve(c.oracle_build())) < TOL
+        srv.release(pid)
+        with pytest.raises(H.HPSError) as e:
+            srv.solve(pid, _dev(c.t))
+        assert e.value.code == H.HPS_E_INVALID
+        with pytest.raises(H.HPSError) as e:
+            srv.solve(12345, _dev(c.t), u=u)
+        assert e.value.code == H.HPS_E_INVALID
+    finally:
+        srv.close()

@@ -106,3 +106,79 @@ def test_binding_fails_loudly_without_library(tmp_path):
             H.load(str(tmp_path / "nope.so"))
     finally:
         H._lib = saved
+
+
+def _est(H, nx, ny, p, **kw):
+    return H.hps_estimate_bytes(H.domain(nx, ny), p, **kw)
+
+
+def test_estimate_of_a_single_leaf_is_its_operators():
+    """One leaf, no merges: [Psi | Y] (n x n complex128), its ItI operator (n_b x n_b,
+    kept as the root's), and the small tables (host arithmetic, no device)."""
+    H, lib = _lib()
+    p = 8
+    n, nb, ni = p * p - 4, 4 * (p - 2), (p - 2) ** 2
+    peak, res = _est(H, 1, 1, p)
+    ops = n * n * 16 + nb * nb * 16
+    small = 20 + ni * 8 + 32 * p * p + 32
+    assert ops + small < res < ops + small + 16 * 2 * (p * p) * 4  # + the line tables
+    assert peak > res
+
+
+def test_estimate_of_one_merge():
+    """2 x 1 leaves: two leaves' [Psi | Y] plus one merge's stored operators (n3 = m
+    interface nodes, parent boundary 6m) and the root's ItI operator."""
+    H, lib = _lib()
+    p = 10
+    m = p - 2
+    n, n3, n1, nbp = p * p - 4, m, 3 * m, 6 * m
+    peak, res = _est(H, 2, 1, p)
+    merge = (3 * n3 * n3 + 2 * n1 * n3 + 2 * n3 * nbp) * 16
+    core = 2 * n * n * 16 + merge + nbp * nbp * 16
+    assert core < res < core + 64 * 1024
+    # without the root's R it shrinks by exactly that operator
+    _, res0 = _est(H, 2, 1, p, store_root_R=False)
+    assert res - res0 == nbp * nbp * 16
+
+
+def test_estimate_scales_and_orders():
+    H, lib = _lib()
+    pk1, r1 = _est(H, 32, 32, 12)
+    pk2, r2 = _est(H, 64, 32, 12)
+    assert 1.9 < r2 / r1 < 2.3 and pk2 > pk1 >= r1
+    pkm, rm = _est(H, 32, 32, 12, precision=H.HPS_PREC_MIXED)
+    assert rm < r1 and pkm > rm  # complex64 operators; the build stages complex128 leaves
+    _, rk = _est(H, 32, 32, 12, keep_all_R=True)
+    assert rk > r1
+
+
+def test_estimate_rejects_invalid_arguments():
+    H, lib = _lib()
+    dom = H.domain(3, 2)
+    pk = C.c_int64()
+    assert lib.hps_estimate_bytes(C.byref(dom), 8, None, C.byref(pk), None) == H.HPS_E_INVALID
+    dom = H.domain(2, 2)
+    assert lib.hps_estimate_bytes(C.byref(dom), 8, None, None, None) == H.HPS_E_INVALID
+    assert lib.hps_estimate_bytes(C.byref(dom), 20, None, C.byref(pk), None) == H.HPS_E_INVALID
+
+
+def test_server_argument_checks_before_device_work():
+    H, lib = _lib()
+    o = H.ServerOpts()
+    lib.hps_server_default_opts(C.byref(o))
+    assert (o.slots, o.max_batch_rhs, o.max_pending_builds, o.evict_idle) == (4, 64, 64, 1)
+    out = C.c_void_p(123)
+    for field, bad in [("slots", 0), ("slots", 17), ("max_batch_rhs", 0), ("max_pending_builds", 0)]:
+        b = H.ServerOpts()
+        lib.hps_server_default_opts(C.byref(b))
+        setattr(b, field, bad)
+        assert lib.hps_server_create(1 << 30, C.byref(b), C.byref(out)) == H.HPS_E_INVALID
+        assert out.value is None
+    assert lib.hps_server_create(1 << 30, None, None) == H.HPS_E_INVALID
+    n = C.c_int32()
+    assert lib.hps_server_poll(None, None, 0, 0, C.byref(n)) == H.HPS_E_INVALID
+    assert lib.hps_server_stats(None, None) == H.HPS_E_INVALID
+    req = C.c_uint64()
+    assert lib.hps_server_submit_solve(None, 1, 1, None, None, None, C.byref(req)) == H.HPS_E_INVALID
+    assert lib.hps_server_release(None, 1) == H.HPS_E_INVALID
+    lib.hps_server_destroy(None)  # no-op
