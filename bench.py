@@ -224,6 +224,150 @@ def batch_leg(H, torch, dev, stream, count=256, seed0=0, reps=2):
     return res
 
 
+def serve_leg(H, torch, dev, n_problems=32, n_requests=1000, load=0.7, slots=4, seed=0,
+              max_rhs=64, new_build_every=250, reserve_gb=48.0, checks=4):
+    """Serving: `n_problems` seeded problems (leaf grids 32^2..128^2, p 12-16, kappa
+    50-300, Fourier c; complex128) built through the request loop, then a Poisson stream
+    of `n_requests` solve requests of 1..max_rhs right-hand sides each (smooth random s,
+    plane-wave t), one new build every `new_build_every` requests, at `load` times the
+    capacity measured on the resident problems.  Latency is submission to completion."""
+    from paper_1812_07167_amd import inputs as G
+    n_new = n_requests // new_build_every if new_build_every else 0
+    probs = G.serve_problems(seed, n_problems + n_new)
+    t_setup = time.perf_counter()
+    data = []
+    for q in probs:
+        dom = H.domain(q["nx"], q["ny"])
+        _, xyi, xyb, nrm = H.hps_nodes(dom, q["p"])
+        c = G.FourierField.seeded(q["seed"])(xyi)
+        f = torch.tensor(np.stack([G.FourierField.seeded(sd)(xyi) - 1.0 for sd in q["s_seeds"]]),
+                         dtype=torch.complex128, device=dev)
+        rng = np.random.default_rng(q["seed"] + 7)
+        co = torch.tensor(rng.standard_normal((max_rhs, 2)) + 1j * rng.standard_normal((max_rhs, 2)),
+                          dtype=torch.complex128, device=dev)
+        S = co[:, 0:1] * f[0:1] + co[:, 1:2] * f[1:2]  # [max_rhs, n_interior], smooth
+        th = G.seeded_thetas(q["seed"] + 11, max_rhs)
+        T = np.stack([G.PlaneWave(q["kappa"], float(a)).t(xyb, nrm, q["kappa"]) for a in th])
+        data.append({"dom": dom, "p": q["p"], "kappa": q["kappa"],
+                     "c": torch.tensor(c, dtype=torch.float64, device=dev),
+                     "S": S.contiguous(), "T": torch.tensor(T, dtype=torch.complex128, device=dev),
+                     "n": q["nx"] * q["ny"] * (q["p"] ** 2 - 4),
+                     "est": H.hps_estimate_bytes(dom, q["p"])})
+        del f, co
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    free, total = torch.cuda.mem_get_info()
+    budget = int(free * 0.9 - reserve_gb * 1e9)
+    srv = H.Server(budget_bytes=budget, slots=slots)
+    res = {"problems": n_problems, "new_builds": n_new, "requests": n_requests,
+           "max_rhs_per_request": max_rhs, "slots": slots, "budget_gb": round(budget / 1e9, 2),
+           "resident_estimate_gb": round(sum(d["est"][1] for d in data[:n_problems]) / 1e9, 2),
+           "setup_s": round(t_setup, 2)}
+    try:
+        # builds of the resident set, all submitted at once
+        t0 = time.perf_counter()
+        built = [srv.build(d["dom"], d["p"], d["kappa"], d["kappa"], d["c"])
+                 for d in data[:n_problems]]
+        pids = [pid for pid, _ in built]
+        bdone = srv.wait([req for _, req in built], timeout_s=600)
+        assert all(c["status"] == 0 for c in bdone.values()), "a build failed"
+        res["build_phase_s"] = round(time.perf_counter() - t0, 3)
+        res["build_dof_per_s"] = round(sum(d["n"] for d in data[:n_problems]) / res["build_phase_s"], 1)
+        # capacity probe: one 1-RHS and one max_rhs solve per resident problem, alone
+        svc = []
+        for pid, d in zip(pids, data[:n_problems]):
+            tt = {}
+            for k in (1, max_rhs):
+                r, u = srv.solve(pid, d["T"][:k], d["S"][:k], sync=False)
+                c = srv.wait([r])[r]
+                tt[k] = c["t_end"] - c["t_start"]
+                del u
+            b = (tt[max_rhs] - tt[1]) / (max_rhs - 1)
+            svc.append(tt[1] - b + b * (1 + max_rhs) / 2.0)
+        mean_svc = float(np.mean(svc))
+        rate = load / mean_svc
+        res["mean_service_s"] = round(mean_svc, 5)
+        res["offered_rate_req_per_s"] = round(rate, 2)
+        # the stream
+        pick, nrhs, gaps = G.poisson_requests(seed + 1, n_requests, max_rhs)
+        arrive = np.cumsum(gaps) / rate
+        rng = np.random.default_rng(seed + 2)
+        keep = set(rng.choice(n_requests, size=min(checks, n_requests), replace=False).tolist())
+        live = list(zip(pids, range(n_problems)))  # (problem id, index into data)
+        nxt_new = n_problems
+        held_bytes, outstanding = 0, {}
+        kept, lat, rhs_done, backpressure = {}, [], 0, 0
+
+        def drain(timeout_ms):
+            nonlocal held_bytes, rhs_done
+            for c in srv.poll(256, timeout_ms):
+                if c["kind"] == H.HPS_REQ_SOLVE and c["req"] in outstanding:
+                    assert c["status"] == 0, c
+                    held_bytes -= outstanding.pop(c["req"])
+                    lat.append(c["t_end"] - c["t_submit"])
+                    rhs_done += c["nrhs"]
+
+        st0 = srv.stats()
+        t_start = time.perf_counter()
+        for k in range(n_requests):
+            if new_build_every and k > 0 and k % new_build_every == 0 and nxt_new < len(data):
+                d = data[nxt_new]
+                live.append((srv.build(d["dom"], d["p"], d["kappa"], d["kappa"], d["c"])[0],
+                             nxt_new))
+                nxt_new += 1
+            pid, di = live[int(pick[k] * len(live))]
+            d = data[di]
+            nr = int(nrhs[k])
+            ub = nr * d["n"] * 16
+            # outputs of outstanding requests stay within the memory left beside the budget
+            while held_bytes + ub > reserve_gb * 1e9 * 0.8 and outstanding:
+                backpressure += 1
+                drain(50)
+            wait = t_start + arrive[k] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            r, u = srv.solve(pid, d["T"][:nr], d["S"][:nr], sync=False)
+            outstanding[r] = ub
+            held_bytes += ub
+            if k in keep:
+                kept[r] = (d, nr, u)
+            del u
+            drain(0)
+        while outstanding:
+            drain(100)
+        t_stream = time.perf_counter() - t_start
+        st = srv.stats()
+    finally:
+        srv.close()
+    lat = np.array(lat) * 1e3
+    res.update({
+        "stream_s": round(t_stream, 3),
+        "solves_per_s": round(n_requests / t_stream, 2),
+        "rhs_per_s": round(rhs_done / t_stream, 1),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3),
+                       "max": round(float(lat.max()), 3)},
+        "solve_calls": st["batches"] - st0["batches"],
+        "mean_rhs_per_solve_call": round((st["rhs"] - st0["rhs"]) /
+                                         max(1, st["batches"] - st0["batches"]), 2),
+        "evictions": st["evictions"], "rebuilds": st["rebuilds"],
+        "max_concurrent": st["max_concurrent"], "backpressure_waits": backpressure,
+        "peak_committed_gb": round(st["peak_committed_bytes"] / 1e9, 2),
+    })
+    # the kept requests solved alone on freshly built factors
+    worst = 0.0
+    for r, (d, nr, u) in kept.items():
+        f = H.hps_build(d["dom"], d["p"], d["kappa"], d["kappa"], d["c"])
+        ua = H.hps_solve(f, d["T"][:nr], d["S"][:nr])
+        torch.cuda.synchronize()
+        worst = max(worst, float(torch.linalg.norm(u - ua) / torch.linalg.norm(ua)))
+        f.free()
+        del ua
+    res["alone_vs_mix_max_rel_l2"] = worst
+    res["alone_vs_mix_checked"] = len(kept)
+    return res
+
+
 def copy_calibration(torch, dev, mib=256, reps=3):
     """A plain device-to-device copy of `mib` MiB, `reps` times: the HBM byte counters
     of a profiler run over this command read what one copy of known size costs."""
@@ -252,6 +396,10 @@ def main():
                     help="skip the cross-problem batching leg (256 problems)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision (complex64 + FP64 correction) leg")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving leg (request loop under a Poisson stream)")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="solve requests in the serving leg's stream")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for scaling the HBM "
                          "byte counters of a profiler run) and exit")
@@ -393,6 +541,10 @@ def main():
     if not args.no_batch:
         log("batch leg")
         out["batch_256_problems"] = batch_leg(H, torch, dev, stream)
+    if not args.no_serve:
+        log("serving leg")
+        torch.cuda.empty_cache()
+        out["serving"] = serve_leg(H, torch, dev, n_requests=args.serve_requests)
     if not args.no_mixed:
         out["mixed_precision"] = mixed_leg(H, torch, dom, p, kappa, c_d, s_d, t_d, u_d, exact,
                                            stream, out)

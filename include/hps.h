@@ -179,7 +179,8 @@ int hps_build(const hps_domain* dom, int32_t p, double kappa, double eta_re,
  *   t   device complex, [nrhs][n_root] impedance data on the root boundary
  *   u   device complex, [nrhs][n_leaf_nodes] output, the solution at every leaf node
  * s, t and u must not overlap.  The factor is only read: several solves may use one
- * factor concurrently.  The call allocates its own workspace.
+ * factor concurrently.  The call takes its workspace from the library's cache of
+ * device buffers (see hps_release_cached).
  * Errors: HPS_E_INVALID (NULL factor/t/u, nrhs < 1), HPS_E_NOMEM, HPS_E_DEVICE. */
 int hps_solve(hps_factor* f, int32_t nrhs, const double* s, const double* t, double* u);
 
@@ -266,6 +267,12 @@ int hps_stage_times(const hps_factor* f, int32_t which, hps_stage_time* out, int
 
 /* Release a factor (NULL is a no-op). */
 void hps_free(hps_factor* f);
+
+/* Solve workspaces and staging come from a cache of device buffers that the library
+ * keeps per device; a buffer freed by a finished call stays allocated for the next call
+ * (reuse is ordered after the previous use with an event).  This frees the idle ones
+ * after synchronizing the device.  Errors: HPS_E_DEVICE. */
+int hps_release_cached(void);
 
 /* Device bytes that hps_build of one problem of this shape would use, from the same plan
  * the build lays out (host arithmetic only; nothing is allocated):

@@ -6,12 +6,15 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/hps.h"
 #include "kernels.hpp"
+#include "serve_hooks.hpp"
 
 namespace hps {
 namespace {
@@ -904,20 +907,14 @@ struct Arena {
     used = std::max(used, peak);
     cap = used;
     size_t total = used + split_need + 256;
-    hipError_t e = hipMallocAsync(&block, total, st);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      block = nullptr;
-      throw Error(HPS_E_NOMEM, "solve workspace allocation of " + std::to_string(total) +
-                                   " bytes failed");
-    }
+    block = ws_alloc(total, st);
     base = static_cast<char*>(block);
     split = base + ((used + 255) & ~size_t(255));
     used = 0;
     dry = false;
   }
   ~Arena() {
-    if (block) (void)hipFreeAsync(block, st);
+    if (block) ws_free(block, st);
   }
 };
 
@@ -1435,14 +1432,10 @@ int hps_solve_batch(int32_t nprob, hps_factor* const* f, const int32_t* nrhs,
       hipStream_t st = G.stream;
       const size_t bs = any_s ? (size_t)R * nl * ni * 16 : 0, bt = (size_t)np * R * nt * 16,
                    bu = (size_t)R * nl * n * 16;
-      void* stage = nullptr;
-      if (hipMallocAsync(&stage, bs + bt + bu + 512, st) != hipSuccess) {
-        (void)hipGetLastError();
-        throw Error(HPS_E_NOMEM, "batch staging allocation failed");
-      }
+      void* stage = ws_alloc(bs + bt + bu + 512, st);
       struct Free {
         void* p; hipStream_t st;
-        ~Free() { (void)hipFreeAsync(p, st); }
+        ~Free() { ws_free(p, st); }
       } fr{stage, st};
       char* base = static_cast<char*>(stage);
       double* S = any_s ? reinterpret_cast<double*>(base) : nullptr;
@@ -1615,6 +1608,13 @@ int hps_stage_times(const hps_factor* h, int32_t which, hps_stage_time* out, int
 
 void hps_free(hps_factor* f) { delete f; }
 
+int hps_release_cached(void) {
+  return guard([&] {
+    HPS_HIP(hipDeviceSynchronize());
+    ws_trim();
+  });
+}
+
 int hps_estimate_bytes(const hps_domain* dom, int32_t p, const hps_opts* opts,
                        int64_t* build_peak, int64_t* resident) {
   return guard([&] {
@@ -1639,6 +1639,113 @@ int hps_estimate_bytes(const hps_domain* dom, int32_t p, const hps_opts* opts,
 
 // ------------------------------------------------------------------ serving hooks
 namespace hps {
+
+// Solve workspaces and staging come from a cache of device buffers (plain hipMalloc
+// allocations, whose cost is a fraction of a millisecond; a stream-ordered pool that
+// maps fresh multi-GB blocks took tens of milliseconds per call).  A buffer in use
+// belongs to one call; when the call ends an event is recorded on its stream, and the
+// next call that takes the buffer makes its own stream wait for that event, so reuse is
+// ordered on the device across streams.  A call takes the smallest idle buffer that
+// fits; when none fits, the largest idle buffer of the device is replaced by one of the
+// requested size.
+namespace {
+struct WsBuf {
+  int dev = 0;
+  void* p = nullptr;
+  size_t cap = 0;
+  bool busy = false;
+  hipEvent_t ev = nullptr;
+  bool recorded = false;
+};
+std::mutex g_ws_mu;
+std::vector<WsBuf> g_ws;
+constexpr size_t kWsGrain = size_t(2) << 20;
+
+void ws_release(WsBuf& b) {
+  (void)hipFree(b.p);  // waits for the device, so pending uses of the buffer have ended
+  if (b.ev) (void)hipEventDestroy(b.ev);
+}
+}  // namespace
+
+void* ws_alloc(size_t bytes, hipStream_t st) {
+  int dev = 0;
+  HPS_HIP(hipGetDevice(&dev));
+  bytes = (std::max<size_t>(bytes, 1) + kWsGrain - 1) / kWsGrain * kWsGrain;
+  std::unique_lock<std::mutex> lk(g_ws_mu);
+  long best = -1, largest = -1;
+  for (size_t i = 0; i < g_ws.size(); ++i) {
+    const WsBuf& b = g_ws[i];
+    if (b.busy || b.dev != dev) continue;
+    if (b.cap >= bytes && (best < 0 || b.cap < g_ws[best].cap)) best = (long)i;
+    if (largest < 0 || b.cap > g_ws[largest].cap) largest = (long)i;
+  }
+  if (best >= 0) {
+    WsBuf& b = g_ws[best];
+    if (b.recorded) HPS_HIP(hipStreamWaitEvent(st, b.ev, 0));
+    b.busy = true;
+    return b.p;
+  }
+  std::vector<WsBuf> drop;
+  if (largest >= 0) {
+    drop.push_back(g_ws[largest]);
+    g_ws.erase(g_ws.begin() + largest);
+  }
+  lk.unlock();
+  for (auto& b : drop) ws_release(b);
+  WsBuf nb;
+  nb.dev = dev;
+  nb.cap = bytes;
+  hipError_t e = hipMalloc(&nb.p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    ws_trim();  // idle buffers of other sizes may be what stands in the way
+    e = hipMalloc(&nb.p, bytes);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(HPS_E_NOMEM, "workspace allocation of " + std::to_string(bytes) +
+                                 " bytes failed");
+  }
+  e = hipEventCreateWithFlags(&nb.ev, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    (void)hipFree(nb.p);
+    throw Error(HPS_E_DEVICE, "event creation failed");
+  }
+  nb.busy = true;
+  lk.lock();
+  g_ws.push_back(nb);
+  return nb.p;
+}
+
+void ws_free(void* p, hipStream_t st) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  for (auto& b : g_ws)
+    if (b.p == p) {
+      b.recorded = hipEventRecord(b.ev, st) == hipSuccess;
+      if (!b.recorded) (void)hipGetLastError();
+      b.busy = false;
+      return;
+    }
+}
+
+void ws_trim() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  std::vector<WsBuf> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    for (size_t i = 0; i < g_ws.size();) {
+      if (!g_ws[i].busy && g_ws[i].dev == dev) {
+        drop.push_back(g_ws[i]);
+        g_ws.erase(g_ws.begin() + (long)i);
+      } else {
+        ++i;
+      }
+    }
+  }
+  for (auto& b : drop) ws_release(b);
+}
 
 void set_last_error(const std::string& msg) { g_err = msg; }
 

@@ -1,5 +1,5 @@
-// Library-internal entry points the request loop uses beside the public C ABI: the
-// solve of one factor on an explicit stream, and the size of its workspace.
+// Library-internal entry points shared by the C ABI and the request loop: the solve of
+// one factor on an explicit stream, the size of its workspace, and the workspace pool.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,6 +19,14 @@ size_t solve_workspace_bytes(hps_factor* f, int nrhs, bool with_s);
 // hps::Error on failure.
 void solve_on(hps_factor* f, int nrhs, const double* s, const double* t, double* u,
               hipStream_t st, hps_solve_info* info);
+
+// Device memory for one call's workspace or staging, from the library's cache of
+// buffers on the current device: ws_alloc orders stream st after the buffer's previous
+// use, ws_free marks the buffer idle once st's queued work reaches that point, ws_trim
+// frees the idle buffers of the current device.  ws_alloc throws hps::Error.
+void* ws_alloc(size_t bytes, hipStream_t st);
+void ws_free(void* p, hipStream_t st);
+void ws_trim();
 
 // Message hps_last_error() returns on the calling thread.
 void set_last_error(const std::string& msg);

@@ -308,9 +308,7 @@ bool pick(hps_server& S, Work& w, std::vector<Freed>& fr) {
 struct StreamFree {
   void* p = nullptr;
   hipStream_t st = nullptr;
-  ~StreamFree() {
-    if (p) (void)hipFreeAsync(p, st);
-  }
+  ~StreamFree() { ws_free(p, st); }
 };
 
 // One merged solve: requests' s and t side by side in staging, one solve, u scattered.
@@ -328,11 +326,7 @@ int run_solve(Problem& p, const Work& w, hipStream_t st, hps_solve_info* info,
       const size_t bu = align256((size_t)R * nl * n * 16);
       StreamFree stage;
       stage.st = st;
-      if (hipMallocAsync(&stage.p, bs + bt + bu, st) != hipSuccess) {
-        (void)hipGetLastError();
-        stage.p = nullptr;
-        throw Error(HPS_E_NOMEM, "solve staging allocation failed");
-      }
+      stage.p = ws_alloc(bs + bt + bu, st);
       char* base = static_cast<char*>(stage.p);
       double* S = w.any_s ? reinterpret_cast<double*>(base) : nullptr;
       double* T = reinterpret_cast<double*>(base + bs);
@@ -394,6 +388,8 @@ void slot_main(hps_server* S, int slot) {
     hps_factor* built = nullptr;
     size_t built_bytes = 0;
     if (w.kind == Work::Build) {
+      // return idle cached workspaces first: the build's memory is admitted without them
+      ws_trim();
       Problem& p = *w.pr;  // fields read here are fixed while the problem is busy
       hps_opts o = p.opts;
       o.stream = st;

@@ -24,6 +24,7 @@ EXPORTS = [
     "hps_build_batch", "hps_solve", "hps_solve_batch", "hps_solve_jumps", "hps_residual",
     "hps_last_solve_info", "hps_factor_query",
     "hps_factor_get", "hps_factor_box", "hps_stage_times", "hps_free", "hps_estimate_bytes",
+    "hps_release_cached",
     "hps_server_default_opts", "hps_server_create", "hps_server_submit_build",
     "hps_server_submit_solve", "hps_server_release", "hps_server_poll", "hps_server_stats",
     "hps_server_destroy",
@@ -123,6 +124,7 @@ def load(path: str = LIB_PATH):
     lib.hps_stage_times.argtypes = [P, I32, C.POINTER(StageTime), I32, C.POINTER(I32)]
     lib.hps_free.argtypes = [P]
     lib.hps_free.restype = None
+    lib.hps_release_cached.argtypes = []
     lib.hps_estimate_bytes.argtypes = [C.POINTER(Domain), I32, C.POINTER(Opts), C.POINTER(I64),
                                        C.POINTER(I64)]
     lib.hps_server_default_opts.argtypes = [C.POINTER(ServerOpts)]
@@ -140,7 +142,7 @@ def load(path: str = LIB_PATH):
     for name in ["hps_nodes", "hps_build", "hps_build_batch", "hps_solve", "hps_solve_batch",
                  "hps_solve_jumps", "hps_residual",
                  "hps_last_solve_info", "hps_factor_query", "hps_factor_get", "hps_factor_box",
-                 "hps_stage_times", "hps_estimate_bytes", "hps_server_create",
+                 "hps_stage_times", "hps_estimate_bytes", "hps_release_cached", "hps_server_create",
                  "hps_server_submit_build", "hps_server_submit_solve", "hps_server_release",
                  "hps_server_poll", "hps_server_stats"]:
         getattr(lib, name).restype = C.c_int
@@ -386,6 +388,11 @@ def _plain_opts(precision=HPS_PREC_C128, fp64_top_levels=None, refine_max_iter=N
     if refine_tol is not None:
         opts.refine_tol = float(refine_tol)
     return opts
+
+
+def hps_release_cached():
+    """Return the library's cached workspace memory on the current device."""
+    _check(load().hps_release_cached())
 
 
 def hps_estimate_bytes(dom: Domain, p: int, **opts):

@@ -181,3 +181,32 @@ def batch_problems(seed0=0, count=256):
         out.append({"seed": seed0 + i, "nx": side, "ny": side, "p": p, "kappa": kappa,
                     "theta": float(rng.uniform(0.0, 2 * np.pi))})
     return out
+
+
+def serve_problems(seed0=0, count=32):
+    """Seeded parameters of resident problems for a request stream on the unit square:
+    leaf grid side from {32, 64, 128} (probabilities 0.4, 0.4, 0.2), p from {12, 14, 16},
+    kappa ~ U[50, 300], eta = kappa, c a seeded Fourier field as in batch_problems, and
+    two seeded smooth fields (Fourier fields of their own seeds) from which a problem's
+    body loads are formed.  Returns a list of dicts."""
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng(10_000 + seed0 + i)
+        side = int(rng.choice([32, 64, 128], p=[0.4, 0.4, 0.2]))
+        p = int(rng.choice([12, 14, 16]))
+        kappa = float(rng.uniform(50.0, 300.0))
+        out.append({"seed": 10_000 + seed0 + i, "nx": side, "ny": side, "p": p,
+                    "kappa": kappa, "s_seeds": (20_000 + seed0 + 2 * i, 20_001 + seed0 + 2 * i)})
+    return out
+
+
+def poisson_requests(seed, count, max_rhs=64):
+    """A seeded request stream: for each request a uniform draw in [0, 1) that picks its
+    problem among those known when it arrives, its number of right-hand sides (uniform
+    in 1..max_rhs; it solves the first nrhs of its problem's data) and unit-rate
+    exponential inter-arrival gaps (scaled by 1/rate for a Poisson stream)."""
+    rng = np.random.default_rng(seed)
+    pick = rng.uniform(0.0, 1.0, size=count)
+    nrhs = rng.integers(1, max_rhs + 1, size=count)
+    gaps = rng.exponential(1.0, size=count)
+    return pick, nrhs, gaps
