@@ -72,7 +72,7 @@ struct LeafDesc {
   const double* tab = nullptr;   // device complex line tables, leaf_table_len(p) per problem
   double* BI = nullptr;          // device [nleaf][n*n] complex: [Psi | Y]
   double* R = nullptr;           // device [nleaf][nb*nb] complex
-  double* Mg = nullptr;          // scratch [nleaf][ni*ni] complex (leaf_scratch_bytes)
+  double* Mg = nullptr;          // scratch of the interior inverse (leaf_scratch_bytes)
   int* info = nullptr;           // device [nleaf]
 };
 // scratch the leaf inverse needs for nleaf leaves (0 when it fits in registers)

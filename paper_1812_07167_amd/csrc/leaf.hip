@@ -18,8 +18,9 @@
 // sparsity of the Laplacian with complex line operators G_x, G_y.  These line tables
 // depend only on p, the leaf size and eta; the host builds them (LeafDesc::tab).
 //
-// Kernels: leaf_sinv (S_i^{-1} by register-resident blocked Gauss-Jordan with partial
-// pivoting, one workgroup per leaf), leaf_psi_i (Psi_i from the rows of Y_i),
+// Kernels: leaf_sinv (S_i^{-1} by blocked Gauss-Jordan with partial pivoting, the
+// matrix held in registers (partly in a scratch copy for p >= 15), one workgroup per
+// leaf), leaf_psi_i (Psi_i from the rows of Y_i),
 // leaf_bnd (boundary rows of [Psi | Y] and R).
 #include "kernels.hpp"
 
@@ -48,48 +49,51 @@ struct TabIdx {
 };
 
 // Thread grid GR x GC per leaf, each thread owning ER x EC complex entries of S_i
-// (padded): rows tr + GR a, columns tc + GC b.  Pivots are taken in blocks of NBK.
+// (padded): rows tr + GR a, columns tc + GC b.  Rows a < AR of a thread's entries stay
+// in registers for the whole inversion; the rows a >= AR (p >= 15, where the complex
+// matrix outgrows the register file of a compute unit) live in a per-leaf scratch copy
+// between block steps, in a thread-private interleaved layout.  Pivots are taken in
+// blocks of NBK.
 template <int P> struct LeafCfg {
   static constexpr int m = P - 2;
   static constexpr int NI = m * m;
-  static constexpr int ER = P <= 7 ? 1 : P <= 10 ? 2 : P == 11 ? 3 : P <= 14 ? 4 : 5;
+  static constexpr int ER = P <= 7 ? 1 : P <= 10 ? 2 : P == 11 ? 3 : P <= 13 ? 4
+                          : P == 14 ? 8 : P == 15 ? 9 : 10;
   static constexpr int EC = P <= 7 ? 1 : P <= 9 ? 2 : P == 10 ? 4 : P == 11 ? 3
-                          : P <= 13 ? 4 : P <= 15 ? 6 : 8;
+                          : P <= 13 ? 4 : P == 14 ? 6 : P == 15 ? 7 : 8;
+  static constexpr int AR = P <= 14 ? ER : P == 15 ? 6 : 5;  // register-resident rows
   static constexpr int GR = (NI + ER - 1) / ER;
   static constexpr int GC = (NI + EC - 1) / EC;
   static constexpr int GE = (GC * EC > GR * ER ? GC * EC : GR * ER);  // LDS row stride
   static constexpr int NLIVE = GR * GC;                     // threads that own entries
   static constexpr int NT = ((NLIVE + 63) / 64) * 64;       // whole waves (shuffles)
-  // pivots per block (wider for the scratch-copy variant: fewer passes over the copy)
-  static constexpr int NBK = P >= 14 ? 12 : 8;
-  static constexpr int PQ = (NI + 63) / 64;                 // panel rows per lane
-  static constexpr int POOL = 3 * NBK * GE;                 // complex entries of LDS
+  static constexpr int NBK = P >= 14 ? 16 : 8;              // pivots per block
+  static constexpr int POOL = 2 * NBK * GE;                 // panel / Q, pivot rows X
   static constexpr int CW = (POOL / NI) < NI ? (POOL / NI) : NI;  // output chunk columns
-  static_assert(NT <= 1024, "too many threads");
+  static constexpr long SCR = (long)(ER - AR) * EC * NT;    // scratch entries per leaf
+  static_assert(NT <= 1024 && NT >= NI, "one thread per panel row, at most 1024");
   static_assert(GR * ER >= NI && GC * EC >= NI && CW >= 1, "bad leaf grid");
 };
 
-// S_i^{-1} by blocked Gauss-Jordan with partial pivoting, matrix resident in registers.
-// Per block K of NBK pivot columns:
+// S_i^{-1} by blocked Gauss-Jordan with partial pivoting.  Per block K of NBK pivot
+// columns:
 //   1. owners publish the panel columns M[:, K] to LDS;
-//   2. wave 0 runs the NBK elimination steps on the panel (pivot = largest unused
-//      |re| + |im|), giving the block transformation Q and the pivot rows P_K;
+//   2. the workgroup runs the NBK elimination steps on the panel in place (pivot =
+//      largest unused |re| + |im|), giving the block transformation Q and the pivot
+//      rows P_K;
 //   3. owners of the pivot rows publish X = M[P_K, :];
 //   4. every entry outside K becomes (pivot rows zeroed) + Q X, entries in K become Q.
 // This is the same in-place elimination as column-at-a-time Gauss-Jordan (the block
 // step applies the product of the NBK elementary transformations at once); the
 // in-place result M satisfies S^{-1}[k][piv[j]] = M[piv[k]][j].  The inverse goes to
-// the Y_i block of [Psi | Y].
-// RES: each thread keeps its entries in registers.  Otherwise (p >= 14, where a complex
-// matrix of (p-2)^4 entries needs more registers than a workgroup has) they live in a
-// per-leaf scratch copy (d.Mg) between block steps; every thread only ever reads and
-// writes its own entries there, so no cross-thread ordering is involved.
-template <int P, bool RES>
+// the Y_i block of [Psi | Y].  Every thread only ever reads and writes its own entries
+// in the scratch copy, so no cross-thread ordering is involved there.
+template <int P>
 __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
   using Cfg = LeafCfg<P>;
   constexpr int m = Cfg::m, NI = Cfg::NI, ER = Cfg::ER, EC = Cfg::EC, GR = Cfg::GR,
-                GC = Cfg::GC, GE = Cfg::GE;
-  constexpr int NBK = Cfg::NBK, PQ = Cfg::PQ;
+                GC = Cfg::GC, GE = Cfg::GE, AR = Cfg::AR;
+  constexpr int NBK = Cfg::NBK;
   constexpr int NB = 4 * m, N = P * P - 4;
   __shared__ double2 pool[Cfg::POOL];
   __shared__ int piv[NI], ipiv[NI];
@@ -97,11 +101,9 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
   __shared__ int used_s[NI];
   __shared__ double2 sG[2][m * m];  // G_x, G_y
   __shared__ int s_bad;
-  double2* bufA = pool;              // [NBK][GE]  panel / block transformation
-  double2* bufB = pool + NBK * GE;   // [NBK][GE]  (ping-pong partner)
-  double2* Xs = pool + 2 * NBK * GE; // [NBK][GE]  pivot rows
-  double2* pan = bufA;               // receives the next block's panel columns
-  double2* oth = bufB;
+  __shared__ unsigned long long cand[LeafCfg<P>::NT / 64];  // per-wave pivot candidates
+  double2* pan = pool;               // [NBK][GE]  panel, then the block transformation Q
+  double2* Xs = pool + NBK * GE;     // [NBK][GE]  pivot rows
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -125,13 +127,14 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
   const double kap = d.prm[4 * prob];
   const double k2 = kap * kap;
   const double* cl = d.c + (long)g * NI;
-  double2* Mg = reinterpret_cast<double2*>(d.Mg) + (RES ? 0 : h * (long)NI * NI);
-  // scratch address of entry (a, b) of this thread (padding entries are never touched)
-  auto gaddr = [&](int a, int b) { return Mg + (tr + GR * a) + (long)NI * (tc + GC * b); };
+  double2* Mg = reinterpret_cast<double2*>(d.Mg) + (AR < ER ? h * Cfg::SCR : 0);
+  // scratch slot of this thread's entry (a >= AR, b): consecutive threads, consecutive
+  // slots
+  auto gaddr = [&](int a, int b) { return Mg + ((long)((a - AR) * EC + b) * Cfg::NT + tid); };
 
   // assemble S_i = -(G_x (x) I) - (I (x) G_y) - kappa^2 diag(c) on the interior nodes
   // (node r = (j-1) m + (i-1); G_x acts along x within a grid row, G_y along y)
-  double2 M[RES ? ER : 1][RES ? EC : 1];
+  double2 M[AR][EC];
 #pragma unroll
   for (int a = 0; a < ER; ++a) {
     const int r = tr + GR * a;
@@ -147,121 +150,120 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
         if (ir == ic) v = csub(v, sG[1][jr + m * jc]);
         if (r == c) v.x -= k2 * cr;
       }
-      if (RES) M[RES ? a : 0][RES ? b : 0] = v;
-      else if (live && r < NI && c < NI) *gaddr(a, b) = v;
+      if (a < AR) M[a < AR ? a : 0][b] = v;
+      else if (live) *gaddr(a, b) = v;
     }
   }
-  auto get = [&](int a, int b) -> double2 {
-    if (RES) return M[RES ? a : 0][RES ? b : 0];
-    return *gaddr(a, b);
+  // visit every owned entry (a, b) with its value: register rows unrolled, scratch rows
+  // one at a time (so that their loads are not all in flight at once)
+  auto for_entries = [&](auto&& fn) {
+#pragma unroll
+    for (int a = 0; a < AR; ++a)
+#pragma unroll
+      for (int b = 0; b < EC; ++b) fn(a, b, M[a][b]);
+#pragma unroll 1
+    for (int a = AR; a < ER; ++a)
+#pragma unroll
+      for (int b = 0; b < EC; ++b) fn(a, b, *gaddr(a, b));
   };
 
 #pragma unroll 1
   for (int k0 = 0; k0 < NI; k0 += NBK) {
     const int nk = (NI - k0) < NBK ? (NI - k0) : NBK;
-    // 1. panel columns (into the buffer that does not hold the previous block's Q)
-    if (live) {
-#pragma unroll
-      for (int a = 0; a < ER; ++a) {
+    // 1. panel columns
+    if (live)
+      for_entries([&](int a, int b, double2 v) {
         const int ra = tr + GR * a;
-#pragma unroll
-        for (int b = 0; b < EC; ++b) {
-          const int j = tc + GC * b - k0;
-          if (ra < NI && j >= 0 && j < nk) pan[j * GE + ra] = get(a, b);
-        }
-      }
-    }
+        const int j = tc + GC * b - k0;
+        if (ra < NI && j >= 0 && j < nk) pan[j * GE + ra] = v;
+      });
     __syncthreads();
-    // 2. elimination on the panel (wave 0); each step reads one LDS buffer and writes
-    //    the other, so the pivot row is never read after it has been rescaled
-    if (wave == 0) {
-      if (lane == 0 && k0 > 0)
-        for (int s = 0; s < NBK; ++s) slot[piv[k0 - NBK + s]] = -1;
-      unsigned usedq = 0;
-#pragma unroll
-      for (int q = 0; q < PQ; ++q) {
-        const int i = lane + 64 * q;
-        if (i >= NI || used_s[i]) usedq |= 1u << q;
-      }
+    // 2. elimination on the panel, in place, by the whole workgroup: thread i owns
+    //    panel row i.  A step takes two barriers: one after every wave has offered its
+    //    pivot candidate, one after the other rows are updated from the pivot row,
+    //    which its own thread rescales last.
+    if (tid == 0 && k0 > 0)
+      for (int s = 0; s < NBK; ++s) slot[piv[k0 - NBK + s]] = -1;
+    bool mine_free = tid < NI && !used_s[tid < NI ? tid : 0];
 #pragma unroll 1
-      for (int s = 0; s < nk; ++s) {
-        const double2* src = (s & 1) ? oth : pan;
-        double2* dst = (s & 1) ? pan : oth;
-        double best = -1.0;
-        int bi = NI;
+    for (int s = 0; s < nk; ++s) {
+      const double mag = mine_free ? cabs1(pan[s * GE + tid]) : -1.0;
+      // wave candidate: magnitude compared in single precision, ties to the lowest row
+      const unsigned key = mag > 0.0 ? max(__float_as_uint((float)mag), 1u) : 0u;
+      const unsigned wbest = wave_max_u32(key);
+      const unsigned long long hit = __ballot(key == wbest && wbest != 0u);
+      if (lane == 0) {
+        const int wr = hit ? wave * 64 + __builtin_ctzll(hit) : 0;
+        cand[wave] = ((unsigned long long)wbest << 32) | (0xffffffffu - (unsigned)wr);
+      }
+      __syncthreads();
+      unsigned long long bestc = 0;
 #pragma unroll
-        for (int q = 0; q < PQ; ++q) {
-          const int i = lane + 64 * q;
-          const double v = ((usedq >> q) & 1u) ? -1.0 : cabs1(src[s * GE + (i < NI ? i : 0)]);
-          if (v > best) { best = v; bi = i; }
-        }
-        const int r = wave_argmax(best, bi);
-        if (r < 0) {
-          if (lane == 0) s_bad = k0 + s + 1;
-          break;
-        }
-        const double2 ip = crcp(src[s * GE + r]);
+      for (int w = 0; w < Cfg::NT / 64; ++w) bestc = cand[w] > bestc ? cand[w] : bestc;
+      if ((bestc >> 32) == 0) {  // no nonzero candidate in this column: singular
+        if (tid == 0) s_bad = k0 + s + 1;
+        break;
+      }
+      const int r = (int)(0xffffffffu - (unsigned)(bestc & 0xffffffffu));
+      const double2 ip = crcp(pan[s * GE + r]);
+      if (tid < NI && tid != r) {
+        const double2 f = cmul(pan[s * GE + tid], ip);
+        // the next column's values are loaded before this one is stored (the pivot row
+        // is not written in this phase, and this row only by this thread)
+        double2 a_cur = pan[tid], p_cur = pan[r];
 #pragma unroll
-        for (int q = 0; q < PQ; ++q) {
-          const int i = lane + 64 * q;
-          if (i < NI) {
-            const bool isr = (i == r);
-            const double2 f = cmul(src[s * GE + i], ip);
-#pragma unroll
-            for (int j = 0; j < NBK; ++j) {
-              if (j < nk) {
-                const double2 pv = src[j * GE + i];
-                double2 v = csub(pv, cmul(f, src[j * GE + r]));
-                v = isr ? cmul(pv, ip) : v;
-                v = (j == s) ? (isr ? ip : cmk(-f.x, -f.y)) : v;
-                dst[j * GE + i] = v;
-              }
+        for (int j = 0; j < NBK; ++j) {
+          if (j < nk) {
+            double2 a_nxt = a_cur, p_nxt = p_cur;
+            if (j + 1 < nk) {
+              a_nxt = pan[(j + 1) * GE + tid];
+              p_nxt = pan[(j + 1) * GE + r];
             }
-            if (isr) usedq |= 1u << q;
+            pan[j * GE + tid] = (j == s) ? cmk(-f.x, -f.y) : csub(a_cur, cmul(f, p_cur));
+            a_cur = a_nxt;
+            p_cur = p_nxt;
           }
         }
-        if (lane == 0) {
-          piv[k0 + s] = r;
-          slot[r] = s;
-          used_s[r] = 1;
-        }
+      }
+      __syncthreads();
+      if (tid == r) {
+#pragma unroll
+        for (int j = 0; j < NBK; ++j)
+          if (j < nk) pan[j * GE + r] = (j == s) ? ip : cmul(pan[j * GE + r], ip);
+        mine_free = false;
+        piv[k0 + s] = r;
+        slot[r] = s;
+        used_s[r] = 1;
       }
     }
     __syncthreads();
     if (s_bad) break;
-    const double2* Qs = (nk & 1) ? oth : pan;  // buffer written by the last step
     // 3. pivot rows (values before this block's update); on the panel columns X is the
     //    identity, so that the update below writes Q there
-    if (live) {
-#pragma unroll
-      for (int a = 0; a < ER; ++a) {
+    if (live)
+      for_entries([&](int a, int b, double2 v) {
         const int ra = tr + GR * a;
         const int sl = ra < NI ? slot[ra] : -1;
-        if (sl >= 0)
-#pragma unroll
-          for (int b = 0; b < EC; ++b) {
-            const int j = tc + GC * b - k0;
-            if (tc + GC * b < NI)
-              Xs[sl * GE + tc + GC * b] =
-                  (j >= 0 && j < nk) ? cmk(j == sl ? 1.0 : 0.0, 0.0) : get(a, b);
-          }
-      }
-    }
+        const int j = tc + GC * b - k0;
+        if (sl >= 0 && tc + GC * b < NI)
+          Xs[sl * GE + tc + GC * b] = (j >= 0 && j < nk) ? cmk(j == sl ? 1.0 : 0.0, 0.0) : v;
+      });
     __syncthreads();
     // 4. block update: M <- (M with pivot rows and panel columns zeroed) + Q X
-    if (live && RES) {
+    if (live) {
+      // register rows: each pivot's X values are loaded once for all of them
 #pragma unroll
-      for (int a = 0; a < ER; ++a) {
+      for (int a = 0; a < AR; ++a) {
         const int ra = tr + GR * a;
         const bool isP = ra < NI && slot[ra] >= 0;
 #pragma unroll
         for (int b = 0; b < EC; ++b) {
           const int j = tc + GC * b - k0;
           const bool inK = j >= 0 && j < nk;
-          M[RES ? a : 0][RES ? b : 0] = (isP || inK) ? cmk(0, 0) : M[RES ? a : 0][RES ? b : 0];
+          M[a][b] = (isP || inK) ? cmk(0, 0) : M[a][b];
         }
       }
-      const double2* qb = Qs + tr;
+      const double2* qb = pan + tr;
       const double2* xbp = Xs + tc;
 #pragma unroll 1
       for (int j = 0; j < nk; ++j) {
@@ -269,17 +271,16 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
 #pragma unroll
         for (int b = 0; b < EC; ++b) xb[b] = xbp[j * GE + GC * b];
 #pragma unroll
-        for (int a = 0; a < ER; ++a) {
+        for (int a = 0; a < AR; ++a) {
           const double2 qa = qb[j * GE + GR * a];
 #pragma unroll
-          for (int b = 0; b < EC; ++b)
-            M[RES ? a : 0][RES ? b : 0] = cfma(qa, xb[b], M[RES ? a : 0][RES ? b : 0]);
+          for (int b = 0; b < EC; ++b) M[a][b] = cfma(qa, xb[b], M[a][b]);
         }
       }
-    } else if (live) {
-      // one row of entries at a time: load, update with all nk pivots, store
+      // scratch rows: one row of entries at a time: load, update with all nk pivots,
+      // store
 #pragma unroll 1
-      for (int a = 0; a < ER; ++a) {
+      for (int a = AR; a < ER; ++a) {
         const int ra = tr + GR * a;
         if (ra >= NI) continue;
         const bool isP = slot[ra] >= 0;
@@ -291,22 +292,17 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
           const bool inK = j >= 0 && j < nk;
           row[b] = (c >= NI || isP || inK) ? cmk(0, 0) : *gaddr(a, b);
         }
-#pragma unroll 2
+#pragma unroll 1
         for (int j = 0; j < nk; ++j) {
-          const double2 qa = Qs[j * GE + ra];
+          const double2 qa = pan[j * GE + ra];
 #pragma unroll
           for (int b = 0; b < EC; ++b) row[b] = cfma(qa, Xs[j * GE + tc + GC * b], row[b]);
         }
 #pragma unroll
-        for (int b = 0; b < EC; ++b)
-          if (tc + GC * b < NI) *gaddr(a, b) = row[b];
+        for (int b = 0; b < EC; ++b) *gaddr(a, b) = row[b];
       }
     }
-    if (!(nk & 1)) {  // Q is in pan: the next panel goes to the other buffer
-      double2* t = pan;
-      pan = oth;
-      oth = t;
-    }
+    __syncthreads();  // Q and X are read above; the next block overwrites them
   }
   __syncthreads();
   if (s_bad) {
@@ -321,19 +317,14 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
   double2* BI = reinterpret_cast<double2*>(d.BI) + h * (long)N * N;
   for (int c0 = 0; c0 < NI; c0 += Cfg::CW) {
     const int cw = (NI - c0) < Cfg::CW ? (NI - c0) : Cfg::CW;
-#pragma unroll
-    for (int a = 0; a < ER; ++a) {
-      const int ra = tr + GR * a;
-      if (!live || ra >= NI) continue;
-      const int orow = ipiv[ra];
-#pragma unroll
-      for (int b = 0; b < EC; ++b) {
+    if (live)
+      for_entries([&](int a, int b, double2 v) {
+        const int ra = tr + GR * a;
         const int c = tc + GC * b;
-        if (c >= NI) continue;
+        if (ra >= NI || c >= NI) return;
         const int ocol = piv[c] - c0;
-        if (ocol >= 0 && ocol < cw) pool[orow + NI * ocol] = get(a, b);
-      }
-    }
+        if (ocol >= 0 && ocol < cw) pool[ipiv[ra] + NI * ocol] = v;
+      });
     __syncthreads();
     for (int e = tid; e < NI * cw; e += Cfg::NT) {
       const int row = e % NI, col = e / NI;
@@ -464,13 +455,12 @@ __global__ __launch_bounds__(256) void leaf_bnd_kernel(LeafDesc d) {
   }
 }
 
-// register-resident for p <= 13; the scratch copy for larger p
-template <int P> constexpr bool leaf_resident() { return P <= 13; }
-
 template <int P> void launch_sinv(const LeafDesc& d, hipStream_t st) {
-  constexpr bool RES = leaf_resident<P>();
-  if (!RES && !d.Mg) throw Error(1, "leaf: scratch copy of S_i missing");
-  hipLaunchKernelGGL((leaf_sinv_kernel<P, RES>), dim3(d.nleaf), dim3(LeafCfg<P>::NT), 0, st, d);
+  if (LeafCfg<P>::SCR > 0 && !d.Mg) throw Error(1, "leaf: scratch copy of S_i missing");
+  hipLaunchKernelGGL(leaf_sinv_kernel<P>, dim3(d.nleaf), dim3(LeafCfg<P>::NT), 0, st, d);
+}
+template <int P> void scratch_of(long nleaf, size_t* out) {
+  *out = (size_t)nleaf * LeafCfg<P>::SCR * 16;
 }
 template <int P> void launch_psi_i(const LeafDesc& d, hipStream_t st) {
   hipLaunchKernelGGL(leaf_psi_i_kernel<P>, dim3(d.nleaf), dim3(256), 0, st, d);
@@ -500,9 +490,9 @@ template <int P> void launch_bnd(const LeafDesc& d, hipStream_t st) {
 }  // namespace
 
 size_t leaf_scratch_bytes(int p, long nleaf) {
-  if (p <= 13) return 0;
-  const long ni = (long)(p - 2) * (p - 2);
-  return (size_t)nleaf * ni * ni * 16;
+  size_t b = 0;
+  HPS_P_SWITCH(scratch_of, p, nleaf, &b);
+  return b;
 }
 
 int leaf_table_len(int p) { return leaf_table_len_dev(p); }
