@@ -101,7 +101,7 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
   __shared__ int used_s[NI];
   __shared__ double2 sG[2][m * m];  // G_x, G_y
   __shared__ int s_bad;
-  __shared__ unsigned long long cand[LeafCfg<P>::NT / 64];  // per-wave pivot candidates
+  __shared__ unsigned long long cand[2][LeafCfg<P>::NT / 64];  // per-wave pivot candidates
   double2* pan = pool;               // [NBK][GE]  panel, then the block transformation Q
   double2* Xs = pool + NBK * GE;     // [NBK][GE]  pivot rows
 
@@ -179,35 +179,57 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
       });
     __syncthreads();
     // 2. elimination on the panel, in place, by the whole workgroup: thread i owns
-    //    panel row i.  A step takes two barriers: one after every wave has offered its
-    //    pivot candidate, one after the other rows are updated from the pivot row,
-    //    which its own thread rescales last.
+    //    panel row i.  A pivot row is left unscaled during the block (its thread keeps
+    //    the pending factor 1/pivot and applies it after the block's steps), so the
+    //    other rows are updated from it while nothing writes it: one barrier per step,
+    //    after every wave has offered its pivot candidate (double-buffered, so a wave
+    //    that runs ahead does not overwrite candidates still being read).
     if (tid == 0 && k0 > 0)
       for (int s = 0; s < NBK; ++s) slot[piv[k0 - NBK + s]] = -1;
     bool mine_free = tid < NI && !used_s[tid < NI ? tid : 0];
+    double2 pend = cmk(1.0, 0.0);   // pending scale of this thread's row
+    bool pivoted = false;            // this row is a pivot row of this block
+    int fix_s = -1;                  // column whose entry of this row is still to be set to 1
+    double2 nextv = tid < NI ? pan[tid] : cmk(0, 0);  // this row's entry in column s
 #pragma unroll 1
     for (int s = 0; s < nk; ++s) {
-      const double mag = mine_free ? cabs1(pan[s * GE + tid]) : -1.0;
+      const double mag = mine_free ? cabs1(nextv) : -1.0;
       // wave candidate: magnitude compared in single precision, ties to the lowest row
       const unsigned key = mag > 0.0 ? max(__float_as_uint((float)mag), 1u) : 0u;
       const unsigned wbest = wave_max_u32(key);
       const unsigned long long hit = __ballot(key == wbest && wbest != 0u);
       if (lane == 0) {
         const int wr = hit ? wave * 64 + __builtin_ctzll(hit) : 0;
-        cand[wave] = ((unsigned long long)wbest << 32) | (0xffffffffu - (unsigned)wr);
+        cand[s & 1][wave] = ((unsigned long long)wbest << 32) | (0xffffffffu - (unsigned)wr);
       }
       __syncthreads();
       unsigned long long bestc = 0;
 #pragma unroll
-      for (int w = 0; w < Cfg::NT / 64; ++w) bestc = cand[w] > bestc ? cand[w] : bestc;
+      for (int w = 0; w < Cfg::NT / 64; ++w) bestc = cand[s & 1][w] > bestc ? cand[s & 1][w] : bestc;
       if ((bestc >> 32) == 0) {  // no nonzero candidate in this column: singular
         if (tid == 0) s_bad = k0 + s + 1;
         break;
       }
       const int r = (int)(0xffffffffu - (unsigned)(bestc & 0xffffffffu));
       const double2 ip = crcp(pan[s * GE + r]);
-      if (tid < NI && tid != r) {
-        const double2 f = cmul(pan[s * GE + tid], ip);
+      // the entry of an earlier pivot row in its pivot column becomes 1 (1/pivot once
+      // the pending factor is applied); written only now, after every thread has read
+      // the pivot value in that row's own step
+      if (fix_s >= 0) {
+        pan[fix_s * GE + tid] = cmk(1.0, 0.0);
+        fix_s = -1;
+      }
+      if (tid == r) {
+        pend = ip;
+        pivoted = true;
+        fix_s = s;
+        mine_free = false;
+        piv[k0 + s] = r;
+        slot[r] = s;
+        used_s[r] = 1;
+        if (s + 1 < nk) nextv = pan[(s + 1) * GE + tid];  // not updated in this step
+      } else if (tid < NI) {
+        const double2 f = cmul(nextv, ip);
         // the next column's values are loaded before this one is stored (the pivot row
         // is not written in this phase, and this row only by this thread)
         double2 a_cur = pan[tid], p_cur = pan[r];
@@ -219,25 +241,25 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
               a_nxt = pan[(j + 1) * GE + tid];
               p_nxt = pan[(j + 1) * GE + r];
             }
-            pan[j * GE + tid] = (j == s) ? cmk(-f.x, -f.y) : csub(a_cur, cmul(f, p_cur));
+            const double2 v = (j == s) ? cmk(-f.x, -f.y) : csub(a_cur, cmul(f, p_cur));
+            pan[j * GE + tid] = v;
+            if (j == s + 1) nextv = v;
             a_cur = a_nxt;
             p_cur = p_nxt;
           }
         }
       }
-      __syncthreads();
-      if (tid == r) {
-#pragma unroll
-        for (int j = 0; j < NBK; ++j)
-          if (j < nk) pan[j * GE + r] = (j == s) ? ip : cmul(pan[j * GE + r], ip);
-        mine_free = false;
-        piv[k0 + s] = r;
-        slot[r] = s;
-        used_s[r] = 1;
-      }
     }
     __syncthreads();
     if (s_bad) break;
+    // pending scales of this block's pivot rows (read by the update after the next
+    // barrier)
+    if (pivoted) {
+      if (fix_s >= 0) pan[fix_s * GE + tid] = cmk(1.0, 0.0);
+#pragma unroll
+      for (int j = 0; j < NBK; ++j)
+        if (j < nk) pan[j * GE + tid] = cmul(pan[j * GE + tid], pend);
+    }
     // 3. pivot rows (values before this block's update); on the panel columns X is the
     //    identity, so that the update below writes Q there
     if (live)
