@@ -43,6 +43,16 @@ __host__ __device__ inline double2 crcp_fast(double2 a) {
   const double d = 1.0 / fma(a.x, a.x, a.y * a.y);
   return cmk(a.x * d, -a.y * d);
 }
+// 1 / a with one division when |a|^2 is comfortably inside the double range, else by
+// Smith's method (callers with a wave-uniform a take one branch only)
+__host__ __device__ inline double2 crcp_pivot(double2 a) {
+  const double n2 = fma(a.x, a.x, a.y * a.y);
+  if (n2 > 1e-280 && n2 < 1e280) {
+    const double d = 1.0 / n2;
+    return cmk(a.x * d, -a.y * d);
+  }
+  return crcp(a);
+}
 __host__ __device__ inline double cabs1(double2 a) { return fabs(a.x) + fabs(a.y); }
 
 // the same operations on complex64 (float2), for the reduced-precision merge levels

@@ -211,7 +211,7 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
         break;
       }
       const int r = (int)(0xffffffffu - (unsigned)(bestc & 0xffffffffu));
-      const double2 ip = crcp(pan[s * GE + r]);
+      const double2 ip = crcp_pivot(pan[s * GE + r]);
       // the entry of an earlier pivot row in its pivot column becomes 1 (1/pivot once
       // the pending factor is applied); written only now, after every thread has read
       // the pivot value in that row's own step
@@ -231,22 +231,22 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
       } else if (tid < NI) {
         const double2 f = cmul(nextv, ip);
         // the next column's values are loaded before this one is stored (the pivot row
-        // is not written in this phase, and this row only by this thread)
+        // is not written in this phase, and this row only by this thread).  All NBK
+        // columns are swept; in a last, narrower block the columns from nk on hold
+        // leftovers that nothing reads.
         double2 a_cur = pan[tid], p_cur = pan[r];
 #pragma unroll
         for (int j = 0; j < NBK; ++j) {
-          if (j < nk) {
-            double2 a_nxt = a_cur, p_nxt = p_cur;
-            if (j + 1 < nk) {
-              a_nxt = pan[(j + 1) * GE + tid];
-              p_nxt = pan[(j + 1) * GE + r];
-            }
-            const double2 v = (j == s) ? cmk(-f.x, -f.y) : csub(a_cur, cmul(f, p_cur));
-            pan[j * GE + tid] = v;
-            if (j == s + 1) nextv = v;
-            a_cur = a_nxt;
-            p_cur = p_nxt;
+          double2 a_nxt = a_cur, p_nxt = p_cur;
+          if (j + 1 < NBK) {
+            a_nxt = pan[(j + 1) * GE + tid];
+            p_nxt = pan[(j + 1) * GE + r];
           }
+          const double2 v = (j == s) ? cmk(-f.x, -f.y) : csub(a_cur, cmul(f, p_cur));
+          pan[j * GE + tid] = v;
+          if (j == s + 1) nextv = v;
+          a_cur = a_nxt;
+          p_cur = p_nxt;
         }
       }
     }
