@@ -38,18 +38,20 @@ GEMM_TILES = {"16x64": (16, 64, 1, 4), "64x16": (64, 16, 4, 1), "32x32": (32, 32
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from a committed profiler summary under profiles/
     (two counter passes scaled by a plain copy), or None when there is none or the
-    kernel's source has changed since it was measured."""
+    kernel's source file has changed since it was measured."""
     import glob
     import hashlib
-    src = os.path.join(ROOT, "paper_1812_07167_amd", "csrc", "gemm.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest() if os.path.exists(src) else ""
     for fn in glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md")):
         kv = {}
         for line in open(fn):
             if " = " in line:
                 k, v = line.strip().split(" = ", 1)
                 kv[k] = v
-        if kv.get("kernel") == kernel and kv.get("kernel_source_sha256") == sha:
+        if kv.get("kernel") != kernel or "kernel_source" not in kv:
+            continue
+        src = os.path.join(ROOT, kv["kernel_source"])
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest() if os.path.exists(src) else ""
+        if kv.get("kernel_source_sha256") == sha:
             return float(kv["traffic_bytes_per_launch"])
     return None
 
@@ -67,7 +69,7 @@ def kernel_of(stage, p):
         if mt.group(4):  # complex64 operands on the FP32 matrix cores
             return "zgemm_kernel<float, %d, %d, %d, %d, false, false>" % (bm, bn, wr, wc), "mfma32"
         return "zgemm_kernel<double, %d, %d, %d, %d, %s, %s>" % (bm, bn, wr, wc, ar, br), "mfma"
-    return {"leaf_sinv": ("leaf_sinv_kernel<%d, %s>" % (p, "true" if p <= 13 else "false"), "alu"),
+    return {"leaf_sinv": ("leaf_sinv_kernel<%d>" % p, "alu"),
             "leaf_psi_i": ("leaf_psi_i_kernel<%d>" % p, "alu"),
             "leaf_bnd": ("leaf_bnd_kernel<%d>" % p, "alu")}.get(base)
 
