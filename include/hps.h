@@ -90,6 +90,12 @@ typedef struct {
                              HPS_PREC_MIXED, 0 for HPS_PREC_C128 (default -1)            */
   double refine_tol;       /* correction stops once ||delta_r|| <= refine_tol ||u_r|| for
                              every right-hand side r (default 1e-12)                     */
+  int32_t autotune;        /* 1 = time every tile variant of each merge GEMM shape not yet
+                             in the process's tuning table and record the fastest (the
+                             build synchronizes its stream per new shape); builds launch
+                             the recorded variant of a shape, else the default choice
+                             (default 0).  Not in the paper: the analog of its per-level
+                             calibration of thread counts (Sec. 3).                      */
 } hps_opts;
 
 /* Outcome of the most recent solve on a factor (hps_last_solve_info). */
@@ -267,6 +273,16 @@ int hps_stage_times(const hps_factor* f, int32_t which, hps_stage_time* out, int
 
 /* Release a factor (NULL is a no-op). */
 void hps_free(hps_factor* f);
+
+/* Tuning table of the merge GEMMs (filled by builds with opts.autotune = 1; shared by
+ * every build in the process).  The file format is text, one line per GEMM shape:
+ * "M N K batch flags variant" (flags: 1 real A, 2 real B, 4 complex64, 8 beta != 0,
+ * 16 scattered output; variant: tile "MxN", e.g. 128x64).  load merges into the table.
+ * Errors: HPS_E_INVALID (NULL, unreadable or malformed file). */
+int hps_autotune_entries(int32_t* n);
+int hps_autotune_clear(void);
+int hps_autotune_save(const char* path);
+int hps_autotune_load(const char* path);
 
 /* Solve workspaces and staging come from a cache of device buffers that the library
  * keeps per device; a buffer freed by a finished call stays allocated for the next call

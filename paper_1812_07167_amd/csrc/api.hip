@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -181,7 +182,11 @@ struct Stage {
   }
 };
 
-void timed_gemm(Profiler& pr, const char* name, const GemmDesc& g, hipStream_t st) {
+void timed_gemm(Profiler& pr, const char* name, const GemmDesc& g, hipStream_t st,
+                bool tune) {
+  // the autotuner measures the tile variants for a shape it has not seen yet; the launch
+  // below then uses the winner
+  if (tune) zgemm_tune(g, st);
   const double mnk = (double)g.M * g.N * g.K * g.batch;
   const double fl = (g.a_real || g.b_real) ? 4.0 * mnk : 8.0 * mnk;
   const double by = (double)g.batch * ((double)g.M * g.K * (g.a_real ? 8 : 16) +
@@ -796,7 +801,7 @@ void build_level(hps_group& f, int l, BuildScratch& sc) {
   g.C = P.Winv.d(); g.ldc = n3; g.sC = n3 * n3;
   g.alpha = -1.0; g.beta = 1.0;
   g.c64 = P.c64;
-  timed_gemm(f.build_prof, gname, g, st);
+  timed_gemm(f.build_prof, gname, g, st, f.opts.autotune != 0);
   // T[:, perm(I1)] = R33b R31a  (T[:, perm(I2)] = -R32b was written by the extract)
   g = GemmDesc();
   g.M = n3; g.N = n1; g.K = n3; g.batch = nbox;
@@ -805,7 +810,7 @@ void build_level(hps_group& f, int l, BuildScratch& sc) {
   g.C = sc.T.d(); g.ldc = n3; g.sC = n3 * nbp; g.ccol = P.dperm;
   g.alpha = 1.0; g.beta = 0.0;
   g.c64 = P.c64;
-  timed_gemm(f.build_prof, gname, g, st);
+  timed_gemm(f.build_prof, gname, g, st, f.opts.autotune != 0);
   // W^{-1}
   {
     Stage s(f.build_prof, iname.c_str(), nbox * 8.0 * n3 * n3 * n3, nbox * 2.0 * n3 * n3 * 16);
@@ -820,7 +825,7 @@ void build_level(hps_group& f, int l, BuildScratch& sc) {
   g.C = P.PhiA.d(); g.ldc = n3; g.sC = n3 * nbp;
   g.alpha = 1.0; g.beta = 0.0;
   g.c64 = P.c64;
-  timed_gemm(f.build_prof, gname, g, st);
+  timed_gemm(f.build_prof, gname, g, st, f.opts.autotune != 0);
   // Phi^b = [-R31a, 0] - R33a Phi^a   (eq. (tbeta), short form)
   g = GemmDesc();
   g.M = n3; g.N = nbp; g.K = n3; g.batch = nbox;
@@ -829,7 +834,7 @@ void build_level(hps_group& f, int l, BuildScratch& sc) {
   g.C = P.PhiB.d(); g.ldc = n3; g.sC = n3 * nbp;
   g.alpha = -1.0; g.beta = 1.0;
   g.c64 = P.c64;
-  timed_gemm(f.build_prof, gname, g, st);
+  timed_gemm(f.build_prof, gname, g, st, f.opts.autotune != 0);
   if (form_R) {
     // R^tau = blockdiag(R11a, R22b) + blockdiag(R13a, R23b) [Phi^a; Phi^b]   (eq. (out))
     g = GemmDesc();
@@ -839,13 +844,13 @@ void build_level(hps_group& f, int l, BuildScratch& sc) {
     g.C = f.R[l].d(); g.ldc = nbp; g.sC = nbp * nbp; g.crow = P.dperm;
     g.alpha = 1.0; g.beta = 1.0;
     g.c64 = P.c64;
-  timed_gemm(f.build_prof, gname, g, st);
+  timed_gemm(f.build_prof, gname, g, st, f.opts.autotune != 0);
     g.M = n2;
     g.A = P.R23b.d(); g.lda = n2; g.sA = n2 * n3;
     g.B = P.PhiB.d();
     g.crow = P.dperm + n1;
     g.c64 = P.c64;
-  timed_gemm(f.build_prof, gname, g, st);
+  timed_gemm(f.build_prof, gname, g, st, f.opts.autotune != 0);
     f.R_valid[l] = 1;
   }
   // children's R: overwritten two levels up (ping-pong) unless every R is kept
@@ -1110,6 +1115,7 @@ void hps_default_opts(hps_opts* o) {
   o->fp64_top_levels = 3;
   o->refine_max_iter = -1;
   o->refine_tol = 1e-12;
+  o->autotune = 0;
 }
 
 int hps_nodes(const hps_domain* dom, int32_t p, double* xy_leaf, double* xy_interior,
@@ -1607,6 +1613,43 @@ int hps_stage_times(const hps_factor* h, int32_t which, hps_stage_time* out, int
 }
 
 void hps_free(hps_factor* f) { delete f; }
+
+int hps_autotune_entries(int32_t* n) {
+  return guard([&] {
+    if (!n) throw Error(HPS_E_INVALID, "n is NULL");
+    *n = zgemm_tune_entries();
+  });
+}
+
+int hps_autotune_clear(void) {
+  return guard([&] { zgemm_tune_clear(); });
+}
+
+int hps_autotune_save(const char* path) {
+  return guard([&] {
+    if (!path) throw Error(HPS_E_INVALID, "path is NULL");
+    const std::string text = zgemm_tune_dump();
+    FILE* fp = std::fopen(path, "w");
+    if (!fp) throw Error(HPS_E_INVALID, std::string("cannot write ") + path);
+    const size_t w = std::fwrite(text.data(), 1, text.size(), fp);
+    const int c = std::fclose(fp);
+    if (w != text.size() || c != 0) throw Error(HPS_E_INVALID, std::string("write failed: ") + path);
+  });
+}
+
+int hps_autotune_load(const char* path) {
+  return guard([&] {
+    if (!path) throw Error(HPS_E_INVALID, "path is NULL");
+    FILE* fp = std::fopen(path, "r");
+    if (!fp) throw Error(HPS_E_INVALID, std::string("cannot read ") + path);
+    std::string text;
+    char buf[4096];
+    size_t k;
+    while ((k = std::fread(buf, 1, sizeof(buf), fp)) > 0) text.append(buf, k);
+    std::fclose(fp);
+    zgemm_tune_load(text);
+  });
+}
 
 int hps_release_cached(void) {
   return guard([&] {

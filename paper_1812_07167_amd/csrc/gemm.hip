@@ -13,6 +13,10 @@
 // B[l/16][l%16]; accumulator element v of lane l is D[l/16 + 4 v][l%16] for the f64
 // instruction and D[4 (l/16) + v][l%16] for the f32 one.  Complex64 operands (the
 // reduced-precision merge levels) run on the f32 instruction with FP32 accumulation.
+#include <cstdio>
+#include <map>
+#include <mutex>
+
 #include "kernels.hpp"
 
 namespace hps {
@@ -220,12 +224,15 @@ void launch_tile(const GemmDesc& d, hipStream_t st) {
   }
 }
 
-}  // namespace
+// ------------------------------------------------------------------ tile choice
+// Tile variants (BM x BN, waves WR x WC).  The default choice follows the operand shape
+// (thin tiles for thin operands, 64 x 64 otherwise); the autotuner replaces it per GEMM
+// shape with the variant measured fastest on the device.
+enum Tile { T16x64, T64x16, T32x32, T32x64, T64x32, T64x64, T128x64, T64x128, T128x128, NTILE };
+const char* const kTileName[NTILE] = {"16x64", "64x16", "32x32", "32x64", "64x32",
+                                      "64x64", "128x64", "64x128", "128x128"};
 
-// tile shape from the operand shape: thin tiles for thin operands, 64 x 64 otherwise
-enum Tile { T16x64, T64x16, T32x32, T32x64, T64x32, T64x64 };
-
-Tile pick_tile(const GemmDesc& d) {
+Tile heuristic_tile(const GemmDesc& d) {
   if (d.M <= 16) return T16x64;
   if (d.N <= 16) return T64x16;
   if (d.M <= 32 && d.N <= 32) return T32x32;
@@ -234,28 +241,176 @@ Tile pick_tile(const GemmDesc& d) {
   return T64x64;
 }
 
+struct TuneKey {
+  int M, N, K, batch, flags;
+  bool operator<(const TuneKey& o) const {
+    if (M != o.M) return M < o.M;
+    if (N != o.N) return N < o.N;
+    if (K != o.K) return K < o.K;
+    if (batch != o.batch) return batch < o.batch;
+    return flags < o.flags;
+  }
+};
+
+TuneKey key_of(const GemmDesc& d) {
+  const int flags = (d.a_real ? 1 : 0) | (d.b_real ? 2 : 0) | (d.c64 ? 4 : 0) |
+                    (d.beta != 0.0 ? 8 : 0) | ((d.crow || d.ccol) ? 16 : 0);
+  return TuneKey{d.M, d.N, d.K, d.batch, flags};
+}
+
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;  // GEMM shape -> measured best tile
+
+Tile pick_tile(const GemmDesc& d) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(key_of(d));
+  return it == g_tune.end() ? heuristic_tile(d) : (Tile)it->second;
+}
+
+void launch_variant(Tile t, const GemmDesc& d, hipStream_t st) {
+  switch (t) {
+    case T16x64: launch_tile<16, 64, 1, 4>(d, st); break;
+    case T64x16: launch_tile<64, 16, 4, 1>(d, st); break;
+    case T32x32: launch_tile<32, 32, 2, 2>(d, st); break;
+    case T32x64: launch_tile<32, 64, 2, 2>(d, st); break;
+    case T64x32: launch_tile<64, 32, 2, 2>(d, st); break;
+    case T128x64: launch_tile<128, 64, 4, 2>(d, st); break;
+    case T64x128: launch_tile<64, 128, 2, 4>(d, st); break;
+    case T128x128: launch_tile<128, 128, 4, 2>(d, st); break;
+    default: launch_tile<64, 64, 2, 2>(d, st); break;
+  }
+}
+
+}  // namespace
+
 std::string zgemm_variant(const GemmDesc& d) {
-  static const char* names[] = {"16x64", "64x16", "32x32", "32x64", "64x32", "64x64"};
-  std::string v = names[pick_tile(d)];
+  std::string v = kTileName[pick_tile(d)];
   v += d.a_real ? "r" : "c";
   v += d.b_real ? "r" : "c";
   if (d.c64) v += "s";  // complex64
   return v;
 }
 
-void zgemm(const GemmDesc& d, hipStream_t st) {
-  if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
+void zgemm_check(const GemmDesc& d) {
   if (d.batch > 65535) throw Error(1, "zgemm: batch exceeds grid limit");
   if (d.K <= 0) throw Error(1, "zgemm: K must be positive");
-  switch (pick_tile(d)) {
-    case T16x64: launch_tile<16, 64, 1, 4>(d, st); break;
-    case T64x16: launch_tile<64, 16, 4, 1>(d, st); break;
-    case T32x32: launch_tile<32, 32, 2, 2>(d, st); break;
-    case T32x64: launch_tile<32, 64, 2, 2>(d, st); break;
-    case T64x32: launch_tile<64, 32, 2, 2>(d, st); break;
-    default: launch_tile<64, 64, 2, 2>(d, st); break;
-  }
+}
+
+void zgemm(const GemmDesc& d, hipStream_t st) {
+  if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
+  zgemm_check(d);
+  launch_variant(pick_tile(d), d, st);
   HPS_LAUNCH_CHECK();
+}
+
+// Time every tile variant on d's operands (output to a dense scratch matrix, beta = 0,
+// no scatter maps: the variants differ in their main loop) and record the fastest for
+// d's shape.  Synchronizes the stream.  A shape already in the table is left alone.
+void zgemm_tune(const GemmDesc& d, hipStream_t st) {
+  if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
+  zgemm_check(d);
+  const TuneKey key = key_of(d);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (g_tune.count(key)) return;
+  }
+  const size_t esz = d.c64 ? 8 : 16;
+  void* scratch = nullptr;
+  HPS_HIP(hipMalloc(&scratch, (size_t)d.batch * d.M * d.N * esz));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int best = heuristic_tile(d);
+  float best_ms = 0.0f;
+  try {
+    HPS_HIP(hipEventCreate(&e0));
+    HPS_HIP(hipEventCreate(&e1));
+    GemmDesc t = d;
+    t.C = static_cast<double*>(scratch);
+    t.ldc = d.M;
+    t.sC = (long)d.M * d.N;
+    t.crow = t.ccol = nullptr;
+    t.beta = 0.0;
+    bool first = true;
+    for (int v = 0; v < NTILE; ++v) {
+      launch_variant((Tile)v, t, st);  // warm-up run
+      HPS_LAUNCH_CHECK();
+      float ms = 0.0f;
+      for (int rep = 0; rep < 2; ++rep) {
+        HPS_HIP(hipEventRecord(e0, st));
+        launch_variant((Tile)v, t, st);
+        HPS_LAUNCH_CHECK();
+        HPS_HIP(hipEventRecord(e1, st));
+        HPS_HIP(hipEventSynchronize(e1));
+        float m = 0.0f;
+        HPS_HIP(hipEventElapsedTime(&m, e0, e1));
+        ms = rep == 0 ? m : std::min(ms, m);
+      }
+      if (first || ms < best_ms) {
+        best = v;
+        best_ms = ms;
+        first = false;
+      }
+    }
+  } catch (...) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(scratch);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(scratch);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = best;
+}
+
+int zgemm_tune_entries() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return (int)g_tune.size();
+}
+
+void zgemm_tune_clear() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+}
+
+// Table as text: one line per shape, "M N K batch flags variant".
+std::string zgemm_tune_dump() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::string out;
+  for (const auto& kv : g_tune) {
+    const TuneKey& k = kv.first;
+    out += std::to_string(k.M) + " " + std::to_string(k.N) + " " + std::to_string(k.K) + " " +
+           std::to_string(k.batch) + " " + std::to_string(k.flags) + " " + kTileName[kv.second] +
+           "\n";
+  }
+  return out;
+}
+
+// Merge lines of zgemm_tune_dump's format into the table; returns the entries read or
+// throws on a malformed line.
+int zgemm_tune_load(const std::string& text) {
+  std::map<TuneKey, int> add;
+  size_t pos = 0;
+  while (pos < text.size()) {
+    size_t end = text.find('\n', pos);
+    if (end == std::string::npos) end = text.size();
+    const std::string line = text.substr(pos, end - pos);
+    pos = end + 1;
+    if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+    TuneKey k{};
+    char name[32] = {0};
+    if (std::sscanf(line.c_str(), "%d %d %d %d %d %31s", &k.M, &k.N, &k.K, &k.batch, &k.flags,
+                    name) != 6)
+      throw Error(1, "autotune table: malformed line: " + line);
+    int v = -1;
+    for (int i = 0; i < NTILE; ++i)
+      if (std::string(name) == kTileName[i]) v = i;
+    if (v < 0) throw Error(1, std::string("autotune table: unknown variant ") + name);
+    add[k] = v;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& kv : add) g_tune[kv.first] = kv.second;
+  return (int)add.size();
 }
 
 }  // namespace hps

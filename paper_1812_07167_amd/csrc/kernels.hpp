@@ -23,6 +23,13 @@ struct GemmDesc {
   bool c64 = false;  // A, B and C are complex64 (interleaved float); FP32 accumulation
 };
 void zgemm(const GemmDesc& d, hipStream_t st);
+// Autotuner: time every tile variant for d's shape and record the fastest (synchronizes
+// st; a shape already recorded is skipped).  zgemm then launches the recorded variant.
+void zgemm_tune(const GemmDesc& d, hipStream_t st);
+int zgemm_tune_entries();
+void zgemm_tune_clear();
+std::string zgemm_tune_dump();               // "M N K batch flags variant" per line
+int zgemm_tune_load(const std::string& text);  // merges; returns the lines read
 // name of the kernel variant zgemm launches for d: tile "MxN" plus r/c for real or
 // complex A and B (e.g. "64x64cc")
 std::string zgemm_variant(const GemmDesc& d);

@@ -24,7 +24,8 @@ EXPORTS = [
     "hps_build_batch", "hps_solve", "hps_solve_batch", "hps_solve_jumps", "hps_residual",
     "hps_last_solve_info", "hps_factor_query",
     "hps_factor_get", "hps_factor_box", "hps_stage_times", "hps_free", "hps_estimate_bytes",
-    "hps_release_cached",
+    "hps_release_cached", "hps_autotune_entries", "hps_autotune_clear", "hps_autotune_save",
+    "hps_autotune_load",
     "hps_server_default_opts", "hps_server_create", "hps_server_submit_build",
     "hps_server_submit_solve", "hps_server_release", "hps_server_poll", "hps_server_stats",
     "hps_server_destroy",
@@ -47,7 +48,8 @@ class Domain(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("keep_all_R", C.c_int32), ("store_root_R", C.c_int32),
                 ("profile", C.c_int32), ("stream", C.c_void_p), ("fp64_top_levels", C.c_int32),
-                ("refine_max_iter", C.c_int32), ("refine_tol", C.c_double)]
+                ("refine_max_iter", C.c_int32), ("refine_tol", C.c_double),
+                ("autotune", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -125,6 +127,10 @@ def load(path: str = LIB_PATH):
     lib.hps_free.argtypes = [P]
     lib.hps_free.restype = None
     lib.hps_release_cached.argtypes = []
+    lib.hps_autotune_entries.argtypes = [C.POINTER(I32)]
+    lib.hps_autotune_clear.argtypes = []
+    lib.hps_autotune_save.argtypes = [C.c_char_p]
+    lib.hps_autotune_load.argtypes = [C.c_char_p]
     lib.hps_estimate_bytes.argtypes = [C.POINTER(Domain), I32, C.POINTER(Opts), C.POINTER(I64),
                                        C.POINTER(I64)]
     lib.hps_server_default_opts.argtypes = [C.POINTER(ServerOpts)]
@@ -143,6 +149,8 @@ def load(path: str = LIB_PATH):
                  "hps_solve_jumps", "hps_residual",
                  "hps_last_solve_info", "hps_factor_query", "hps_factor_get", "hps_factor_box",
                  "hps_stage_times", "hps_estimate_bytes", "hps_release_cached", "hps_server_create",
+                 "hps_autotune_entries", "hps_autotune_clear", "hps_autotune_save",
+                 "hps_autotune_load",
                  "hps_server_submit_build", "hps_server_submit_solve", "hps_server_release",
                  "hps_server_poll", "hps_server_stats"]:
         getattr(lib, name).restype = C.c_int
@@ -242,7 +250,7 @@ class Factor:
 
 
 def _opts(keep_all_R, store_root_R, stream, profile, precision, fp64_top_levels,
-          refine_max_iter, refine_tol):
+          refine_max_iter, refine_tol, autotune=False):
     import torch
     lib = load()
     opts = Opts()
@@ -257,6 +265,7 @@ def _opts(keep_all_R, store_root_R, stream, profile, precision, fp64_top_levels,
         opts.refine_max_iter = int(refine_max_iter)
     if refine_tol is not None:
         opts.refine_tol = float(refine_tol)
+    opts.autotune = int(autotune)
     st = stream if stream is not None else torch.cuda.current_stream()
     opts.stream = C.c_void_p(st.cuda_stream)
     return opts, st
@@ -264,13 +273,13 @@ def _opts(keep_all_R, store_root_R, stream, profile, precision, fp64_top_levels,
 
 def hps_build_batch(doms, ps, kappas, etas, cs, keep_all_R=False, store_root_R=True,
                     stream=None, profile=False, precision=HPS_PREC_C128, fp64_top_levels=None,
-                    refine_max_iter=None, refine_tol=None):
+                    refine_max_iter=None, refine_tol=None, autotune=False):
     """Build several problems at once (problems of one shape share every launch).  doms:
     list of Domain; cs: list of float64 device tensors.  Returns a list of Factors."""
     lib = load()
     n = len(doms)
     opts, st = _opts(keep_all_R, store_root_R, stream, profile, precision, fp64_top_levels,
-                     refine_max_iter, refine_tol)
+                     refine_max_iter, refine_tol, autotune)
     D = (Domain * n)(*doms)
     P = (C.c_int32 * n)(*[int(p) for p in ps])
     K = (C.c_double * n)(*[float(k) for k in kappas])
@@ -305,7 +314,8 @@ def hps_solve_batch(fs, ts, ss=None, us=None):
 
 def hps_build(dom: Domain, p: int, kappa: float, eta: complex, c_interior, keep_all_R=False,
               store_root_R=True, stream=None, profile=False, precision=HPS_PREC_C128,
-              fp64_top_levels=None, refine_max_iter=None, refine_tol=None) -> Factor:
+              fp64_top_levels=None, refine_max_iter=None, refine_tol=None,
+              autotune=False) -> Factor:
     """c_interior: float64 device tensor [nx*ny*(p-2)^2].  Returns a Factor.  Options left
     at None keep the library's defaults."""
     import torch
@@ -322,6 +332,7 @@ def hps_build(dom: Domain, p: int, kappa: float, eta: complex, c_interior, keep_
         opts.refine_max_iter = int(refine_max_iter)
     if refine_tol is not None:
         opts.refine_tol = float(refine_tol)
+    opts.autotune = int(autotune)
     st = stream if stream is not None else torch.cuda.current_stream()
     opts.stream = C.c_void_p(st.cuda_stream)
     out = C.c_void_p()
@@ -388,6 +399,24 @@ def _plain_opts(precision=HPS_PREC_C128, fp64_top_levels=None, refine_max_iter=N
     if refine_tol is not None:
         opts.refine_tol = float(refine_tol)
     return opts
+
+
+def autotune_entries():
+    n = C.c_int32()
+    _check(load().hps_autotune_entries(C.byref(n)))
+    return n.value
+
+
+def autotune_clear():
+    _check(load().hps_autotune_clear())
+
+
+def autotune_save(path):
+    _check(load().hps_autotune_save(str(path).encode()))
+
+
+def autotune_load(path):
+    _check(load().hps_autotune_load(str(path).encode()))
 
 
 def hps_release_cached():

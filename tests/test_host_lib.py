@@ -182,3 +182,29 @@ def test_server_argument_checks_before_device_work():
     assert lib.hps_server_submit_solve(None, 1, 1, None, None, None, C.byref(req)) == H.HPS_E_INVALID
     assert lib.hps_server_release(None, 1) == H.HPS_E_INVALID
     lib.hps_server_destroy(None)  # no-op
+
+
+def test_autotune_table_roundtrip(tmp_path):
+    """The tuning table's text format: load merges lines, save writes them back (sorted by
+    shape), clear empties it; malformed files are refused (host only)."""
+    H, lib = _lib()
+    H.autotune_clear()
+    src = tmp_path / "t.txt"
+    src.write_text("64 64 64 8 0 128x64\n\n14 84 14 2048 17 16x64\n")
+    H.autotune_load(src)
+    assert H.autotune_entries() == 2
+    out = tmp_path / "o.txt"
+    H.autotune_save(out)
+    assert out.read_text().splitlines() == ["14 84 14 2048 17 16x64", "64 64 64 8 0 128x64"]
+    H.autotune_load(out)  # merging the same shapes adds nothing
+    assert H.autotune_entries() == 2
+    for bad in ["1 2 3\n", "64 64 64 8 0 99x99\n"]:
+        src.write_text(bad)
+        with pytest.raises(H.HPSError) as e:
+            H.autotune_load(src)
+        assert e.value.code == H.HPS_E_INVALID
+    assert H.autotune_entries() == 2  # a refused file changes nothing
+    with pytest.raises(H.HPSError):
+        H.autotune_load(tmp_path / "missing.txt")
+    H.autotune_clear()
+    assert H.autotune_entries() == 0
