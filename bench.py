@@ -32,7 +32,8 @@ PEAK = {"hbm": (8000.0, "GB/s"), "mfma": (78.6, "TFLOP/s"), "mfma32": (157.3, "T
         "alu": (78.6, "TFLOP/s")}
 # GEMM variant recorded by the library ("MxN" tile + real/complex A and B) -> kernel
 GEMM_TILES = {"16x64": (16, 64, 1, 4), "64x16": (64, 16, 4, 1), "32x32": (32, 32, 2, 2),
-              "32x64": (32, 64, 2, 2), "64x32": (64, 32, 2, 2), "64x64": (64, 64, 2, 2)}
+              "32x64": (32, 64, 2, 2), "64x32": (64, 32, 2, 2), "64x64": (64, 64, 2, 2),
+              "128x64": (128, 64, 4, 2), "64x128": (64, 128, 2, 4), "128x128": (128, 128, 4, 2)}
 
 
 def measured_traffic(kernel):

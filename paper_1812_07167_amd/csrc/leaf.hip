@@ -154,17 +154,19 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
       else if (live) *gaddr(a, b) = v;
     }
   }
-  // visit every owned entry (a, b) with its value: register rows unrolled, scratch rows
-  // one at a time (so that their loads are not all in flight at once)
-  auto for_entries = [&](auto&& fn) {
+  // visit the owned entries (a, b) that want(a, b) selects, with their values: register
+  // rows unrolled, scratch rows one at a time (only the selected entries are loaded)
+  auto for_entries = [&](auto&& want, auto&& fn) {
 #pragma unroll
     for (int a = 0; a < AR; ++a)
 #pragma unroll
-      for (int b = 0; b < EC; ++b) fn(a, b, M[a][b]);
+      for (int b = 0; b < EC; ++b)
+        if (want(a, b)) fn(a, b, M[a][b]);
 #pragma unroll 1
     for (int a = AR; a < ER; ++a)
 #pragma unroll
-      for (int b = 0; b < EC; ++b) fn(a, b, *gaddr(a, b));
+      for (int b = 0; b < EC; ++b)
+        if (want(a, b)) fn(a, b, *gaddr(a, b));
   };
 
 #pragma unroll 1
@@ -172,11 +174,12 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
     const int nk = (NI - k0) < NBK ? (NI - k0) : NBK;
     // 1. panel columns
     if (live)
-      for_entries([&](int a, int b, double2 v) {
-        const int ra = tr + GR * a;
-        const int j = tc + GC * b - k0;
-        if (ra < NI && j >= 0 && j < nk) pan[j * GE + ra] = v;
-      });
+      for_entries(
+          [&](int a, int b) {
+            const int j = tc + GC * b - k0;
+            return tr + GR * a < NI && j >= 0 && j < nk;
+          },
+          [&](int a, int b, double2 v) { pan[(tc + GC * b - k0) * GE + tr + GR * a] = v; });
     __syncthreads();
     // 2. elimination on the panel, in place, by the whole workgroup: thread i owns
     //    panel row i.  A pivot row is left unscaled during the block (its thread keeps
@@ -263,16 +266,32 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
     // 3. pivot rows (values before this block's update); on the panel columns X is the
     //    identity, so that the update below writes Q there
     if (live)
-      for_entries([&](int a, int b, double2 v) {
-        const int ra = tr + GR * a;
-        const int sl = ra < NI ? slot[ra] : -1;
-        const int j = tc + GC * b - k0;
-        if (sl >= 0 && tc + GC * b < NI)
-          Xs[sl * GE + tc + GC * b] = (j >= 0 && j < nk) ? cmk(j == sl ? 1.0 : 0.0, 0.0) : v;
-      });
+      for_entries(
+          [&](int a, int b) {
+            const int ra = tr + GR * a;
+            return ra < NI && tc + GC * b < NI && slot[ra] >= 0;
+          },
+          [&](int a, int b, double2 v) {
+            const int sl = slot[tr + GR * a];
+            const int j = tc + GC * b - k0;
+            Xs[sl * GE + tc + GC * b] = (j >= 0 && j < nk) ? cmk(j == sl ? 1.0 : 0.0, 0.0) : v;
+          });
     __syncthreads();
     // 4. block update: M <- (M with pivot rows and panel columns zeroed) + Q X
     if (live) {
+      // a scratch row's entries, pivot rows and panel columns zeroed
+      auto load_row = [&](int a, double2* row) {
+        const int ra = tr + GR * a;
+        const bool isP = ra < NI && slot[ra] >= 0;
+#pragma unroll
+        for (int b = 0; b < EC; ++b) {
+          const int c = tc + GC * b;
+          const int j = c - k0;
+          const bool inK = j >= 0 && j < nk;
+          row[b] = (ra >= NI || c >= NI || isP || inK) ? cmk(0, 0) : *gaddr(a, b);
+        }
+      };
+      double2 row[EC];
       // register rows: each pivot's X values are loaded once for all of them
 #pragma unroll
       for (int a = 0; a < AR; ++a) {
@@ -299,29 +318,21 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
           for (int b = 0; b < EC; ++b) M[a][b] = cfma(qa, xb[b], M[a][b]);
         }
       }
-      // scratch rows: one row of entries at a time: load, update with all nk pivots,
-      // store
+      // scratch rows, one at a time: update with all nk pivots, store
 #pragma unroll 1
       for (int a = AR; a < ER; ++a) {
         const int ra = tr + GR * a;
-        if (ra >= NI) continue;
-        const bool isP = slot[ra] >= 0;
-        double2 row[EC];
-#pragma unroll
-        for (int b = 0; b < EC; ++b) {
-          const int c = tc + GC * b;
-          const int j = c - k0;
-          const bool inK = j >= 0 && j < nk;
-          row[b] = (c >= NI || isP || inK) ? cmk(0, 0) : *gaddr(a, b);
-        }
+        load_row(a, row);
+        if (ra < NI) {
 #pragma unroll 1
-        for (int j = 0; j < nk; ++j) {
-          const double2 qa = pan[j * GE + ra];
+          for (int j = 0; j < nk; ++j) {
+            const double2 qa = pan[j * GE + ra];
 #pragma unroll
-          for (int b = 0; b < EC; ++b) row[b] = cfma(qa, Xs[j * GE + tc + GC * b], row[b]);
+            for (int b = 0; b < EC; ++b) row[b] = cfma(qa, Xs[j * GE + tc + GC * b], row[b]);
+          }
+#pragma unroll
+          for (int b = 0; b < EC; ++b) *gaddr(a, b) = row[b];
         }
-#pragma unroll
-        for (int b = 0; b < EC; ++b) *gaddr(a, b) = row[b];
       }
     }
     __syncthreads();  // Q and X are read above; the next block overwrites them
@@ -340,13 +351,14 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
   for (int c0 = 0; c0 < NI; c0 += Cfg::CW) {
     const int cw = (NI - c0) < Cfg::CW ? (NI - c0) : Cfg::CW;
     if (live)
-      for_entries([&](int a, int b, double2 v) {
-        const int ra = tr + GR * a;
-        const int c = tc + GC * b;
-        if (ra >= NI || c >= NI) return;
-        const int ocol = piv[c] - c0;
-        if (ocol >= 0 && ocol < cw) pool[ipiv[ra] + NI * ocol] = v;
-      });
+      for_entries(
+          [&](int a, int b) {
+            const int c = tc + GC * b;
+            return tr + GR * a < NI && c < NI && piv[c] - c0 >= 0 && piv[c] - c0 < cw;
+          },
+          [&](int a, int b, double2 v) {
+            pool[ipiv[tr + GR * a] + NI * (piv[tc + GC * b] - c0)] = v;
+          });
     __syncthreads();
     for (int e = tid; e < NI * cw; e += Cfg::NT) {
       const int row = e % NI, col = e / NI;
