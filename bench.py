@@ -206,16 +206,21 @@ def batch_leg(H, torch, dev, stream, count=256, seed0=0, reps=2):
             st_.append((t2 - t1) * 1e3)
             for f in fs:
                 f.free()
-        err = max(float(np.linalg.norm(u.cpu().numpy()[0] - e) / np.linalg.norm(e))
-                  for u, e in zip(us, exact))
+        sol = [u.cpu().numpy()[0] for u in us]
+        errs = [float(np.linalg.norm(u - e) / np.linalg.norm(e)) for u, e in zip(sol, exact)]
         b, s_ = float(np.min(bt)), float(np.min(st_))
-        return {"build_ms": round(b, 2), "solve_ms": round(s_, 2),
-                "build_dof_per_s": round(dof / (b * 1e-3), 1),
-                "rhs_solves_per_s": round(count / (s_ * 1e-3), 1),
-                "max_rel_l2_vs_exact": err}
+        return sol, {"build_ms": round(b, 2), "solve_ms": round(s_, 2),
+                     "build_dof_per_s": round(dof / (b * 1e-3), 1),
+                     "rhs_solves_per_s": round(count / (s_ * 1e-3), 1),
+                     # discretization error: some drawn problems (kappa up to 80 on 8 x 8
+                     # leaves of p = 8) are under-resolved on purpose
+                     "median_rel_l2_vs_exact": float(np.median(errs)),
+                     "max_rel_l2_vs_exact": float(np.max(errs))}
 
-    res["c128"] = run(H.HPS_PREC_C128)
-    res["mixed"] = run(H.HPS_PREC_MIXED)
+    sol128, res["c128"] = run(H.HPS_PREC_C128)
+    solmx, res["mixed"] = run(H.HPS_PREC_MIXED)
+    res["mixed"]["max_rel_l2_vs_c128"] = max(
+        float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(solmx, sol128))
     # the same problems one at a time
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -61,7 +61,7 @@ template <int P> struct LeafCfg {
                           : P == 14 ? 8 : P == 15 ? 9 : 10;
   static constexpr int EC = P <= 7 ? 1 : P <= 9 ? 2 : P == 10 ? 4 : P == 11 ? 3
                           : P <= 13 ? 4 : P == 14 ? 6 : P == 15 ? 7 : 8;
-  static constexpr int AR = P <= 14 ? ER : P == 15 ? 6 : 5;  // register-resident rows
+  static constexpr int AR = P <= 14 ? ER : 6;  // register-resident rows
   static constexpr int GR = (NI + ER - 1) / ER;
   static constexpr int GC = (NI + EC - 1) / EC;
   static constexpr int GE = (GC * EC > GR * ER ? GC * EC : GR * ER);  // LDS row stride
