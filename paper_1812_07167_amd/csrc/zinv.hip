@@ -7,7 +7,7 @@
 // inv(A)[k][r_j] = M[r_k][j], which the final write-out applies.
 //
 // * n <= SMALL_MAX: one workgroup per matrix, matrix resident in LDS.
-// * larger n: blocked right-looking form.  For each block K of PNB columns a panel
+// * larger n: blocked right-looking form.  For each block K of PNB (16, 8 or 4) columns a panel
 //   kernel (one workgroup per matrix, panel rows spread over its waves, each row's PNB
 //   panel entries in registers) runs the PNB elimination steps on the panel and emits
 //   the block transformation Q; an update kernel then forms
@@ -18,7 +18,6 @@ namespace hps {
 namespace {
 
 constexpr int SMALL_MAX = 96;  // at most 128 (two rows per lane in the small kernel)
-constexpr int PNB = 8;   // panel width of the blocked path
 
 // ------------------------------------------------------------------ small (LDS)
 template <class T>
@@ -119,7 +118,7 @@ __global__ __launch_bounds__(256) void zinv_small_kernel(int n, const double* Ai
 // the remaining columns (the candidate row's values are published once final).  The slots alternate between two buffers, so one
 // barrier per step suffices: a wave can only overwrite a buffer after every wave has
 // passed the following step's barrier.
-template <class T, int RPL>
+template <class T, int RPL, int PNB>
 __global__ __launch_bounds__(512) void zinv_panel_kernel(int n, const double* Mcur,
                                                          double* Mnext, int k0, int* piv,
                                                          int* used, int* info) {
@@ -260,7 +259,7 @@ __global__ __launch_bounds__(512) void zinv_panel_kernel(int n, const double* Mc
 // covers 64 rows (one per lane) and UJ consecutive columns (UJ / 4 per wave) of one
 // matrix; a wave's column loads are issued together.
 constexpr int UJ = 16;
-template <class T>
+template <class T, int PNB>
 __global__ __launch_bounds__(256) void zinv_update_kernel(int n, const double* Mcur,
                                                           double* Mnext, int k0, const int* piv,
                                                           const int* info) {
@@ -345,12 +344,27 @@ __global__ void zero_int_kernel(int* p, long cnt) {
     p[e] = 0;
 }
 
-template <class T, int RPL>
+template <class T, int RPL, int PNB>
 void launch_panel(int n, int batch, const double* Mc, double* Mn, int k0, int* piv, int* used,
                   int* info, hipStream_t st) {
   const int waves = std::max(1, std::min(8, (n + 64 * RPL - 1) / (64 * RPL)));
-  hipLaunchKernelGGL((zinv_panel_kernel<T, RPL>), dim3(batch), dim3(64 * waves), 0, st, n, Mc, Mn,
-                     k0, piv, used, info);
+  hipLaunchKernelGGL((zinv_panel_kernel<T, RPL, PNB>), dim3(batch), dim3(64 * waves), 0, st, n,
+                     Mc, Mn, k0, piv, used, info);
+}
+
+// One block step of the blocked path: panel columns [k0, k0 + PNB), then the update of
+// every other column.
+template <class T, int RPL, int PNB>
+void block_step(int n, int batch, const double* Mc, double* Mn, int k0, int* piv, int* used,
+                int* info, hipStream_t st) {
+  launch_panel<T, RPL, PNB>(n, batch, Mc, Mn, k0, piv, used, info, st);
+  HPS_LAUNCH_CHECK();
+  const int ncol = n - std::min(PNB, n - k0);
+  if (ncol > 0) {
+    hipLaunchKernelGGL((zinv_update_kernel<T, PNB>), dim3(cdiv(n, 64), cdiv(ncol, UJ), batch),
+                       dim3(256), 0, st, n, Mc, Mn, k0, piv, info);
+    HPS_LAUNCH_CHECK();
+  }
 }
 
 template <class T>
@@ -380,17 +394,14 @@ void zinv_t(int n, int batch, const double* A, long lda, long sA, double* Out, l
     hipLaunchKernelGGL(zero_int_kernel, dim3(grid1d(ni)), dim3(256), 0, st, piv, ni);
     HPS_LAUNCH_CHECK();
   }
-  for (int k0 = 0; k0 < n; k0 += PNB) {
-    if (n <= 512) launch_panel<T, 1>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
-    else if (n <= 1024) launch_panel<T, 2>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
-    else launch_panel<T, 4>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
-    HPS_LAUNCH_CHECK();
-    const int ncol = n - std::min(PNB, n - k0);
-    if (ncol > 0) {
-      hipLaunchKernelGGL(zinv_update_kernel<T>, dim3(cdiv(n, 64), cdiv(ncol, UJ), batch),
-                         dim3(256), 0, st, n, Mcur, Mnext, k0, piv, info);
-      HPS_LAUNCH_CHECK();
-    }
+  // panel width: 16 columns where a lane holds one panel row (n <= 512), 8 where it
+  // holds 2, 4 where it holds 4 (wider panels of several rows do not fit in a lane's
+  // registers)
+  const int pnb = n <= 512 ? 16 : n <= 1024 ? 8 : 4;
+  for (int k0 = 0; k0 < n; k0 += pnb) {
+    if (n <= 512) block_step<T, 1, 16>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
+    else if (n <= 1024) block_step<T, 2, 8>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
+    else block_step<T, 4, 4>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
     std::swap(Mcur, Mnext);
   }
   int blocks_x = std::min(n, 64);
