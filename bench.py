@@ -161,6 +161,58 @@ def mixed_leg(H, torch, dom, p, kappa, c_d, s_d, t_d, u_ref, exact, stream, out,
             "fp64_top_levels": 3}
 
 
+def precision_leg(H, torch, dev, stream, nx=128, p=16, kappa=300.0, nrhs=4, seed=4, reps=2):
+    """The precision comparison at scale: 128 x 128 leaves, p = 16 (4.1M collocation
+    nodes), kappa = eta = 300, Fourier c, manufactured right-hand sides with seeded
+    directions.  The complex128 build + solve against the mixed one (complex64 merges and
+    solve products on the FP32 matrix cores, FP64 leaves, top 3 levels and residual
+    correction): times, error against the closed form and against complex128."""
+    from paper_1812_07167_amd import inputs as G
+    dom = H.domain(nx, nx)
+    xy, xyi, xyb, nrm = H.hps_nodes(dom, p)
+    c = G.FourierField.seeded(seed)(xyi)
+    mfs = [G.Manufactured(kappa, float(a)) for a in G.seeded_thetas(seed, nrhs)]
+    s_d = torch.tensor(np.stack([mf.s(xyi, c) for mf in mfs]), dtype=torch.complex128, device=dev)
+    t_d = torch.tensor(np.stack([mf.t(xyb, nrm, kappa) for mf in mfs]), dtype=torch.complex128,
+                       device=dev)
+    exact = np.stack([mf.u(xy) for mf in mfs])
+    c_d = torch.tensor(c, dtype=torch.float64, device=dev)
+    dof = nx * nx * (p * p - 4)
+    out = {"leaves": nx * nx, "p": p, "kappa": kappa, "dof": dof, "nrhs": nrhs}
+    sols = {}
+    for name, prec in (("c128", H.HPS_PREC_C128), ("mixed", H.HPS_PREC_MIXED)):
+        bms, sms = [], []
+        for r in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            f = H.hps_build(dom, p, kappa, kappa, c_d, stream=stream, precision=prec,
+                            autotune=(r == 0))
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            u = H.hps_solve(f, t_d, s_d)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            info = f.last_solve_info()
+            f.free()
+            bms.append((t1 - t0) * 1e3)
+            sms.append((t2 - t1) * 1e3)
+        sols[name] = u.cpu().numpy()
+        del u
+        err = float(np.linalg.norm(sols[name] - exact) / np.linalg.norm(exact))
+        out[name] = {"build_ms": round(min(bms), 2), "solve_ms": round(min(sms), 2),
+                     "build_dof_per_s": round(dof / (min(bms) * 1e-3), 1),
+                     "rel_l2_vs_exact": err,
+                     "factor_gb": round(H.hps_estimate_bytes(dom, p, precision=prec)[1] / 1e9, 2)}
+        if prec == H.HPS_PREC_MIXED:
+            out[name]["correction_steps"] = info[0]
+            out[name]["last_relative_correction"] = info[2]
+    out["mixed"]["rel_l2_vs_c128"] = float(np.linalg.norm(sols["mixed"] - sols["c128"]) /
+                                          np.linalg.norm(sols["c128"]))
+    out["build_speedup_mixed"] = round(out["c128"]["build_ms"] / out["mixed"]["build_ms"], 3)
+    out["solve_speedup_mixed"] = round(out["c128"]["solve_ms"] / out["mixed"]["solve_ms"], 3)
+    return out
+
+
 def batch_leg(H, torch, dev, stream, count=256, seed0=0, reps=2):
     """Cross-problem batching: `count` independent seeded problems (leaf grids 8^2..32^2,
     p in {8, 12, 16}, kappa in [10, 80], Fourier c, one manufactured right-hand side each)
@@ -568,6 +620,10 @@ def main():
         log("serving leg")
         torch.cuda.empty_cache()
         out["serving"] = serve_leg(H, torch, dev, n_requests=args.serve_requests)
+    if not args.no_mixed:
+        log("precision leg (128 x 128 leaves)")
+        torch.cuda.empty_cache()
+        out["precision_128x128"] = precision_leg(H, torch, dev, stream)
     if not args.no_mixed:
         out["mixed_precision"] = mixed_leg(H, torch, dom, p, kappa, c_d, s_d, t_d, u_d, exact,
                                            stream, out)

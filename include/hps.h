@@ -88,8 +88,10 @@ typedef struct {
                              is level 0) stay complex128 (default 3)                     */
   int32_t refine_max_iter; /* residual correction steps per solve; -1 = automatic: 10 for
                              HPS_PREC_MIXED, 0 for HPS_PREC_C128 (default -1)            */
-  double refine_tol;       /* correction stops once ||delta_r|| <= refine_tol ||u_r|| for
-                             every right-hand side r (default 1e-12)                     */
+  double refine_tol;       /* correction stops once, for every right-hand side r,
+                             ||delta_r|| <= refine_tol ||u_r||, or the corrections contract
+                             (each below half the last) so that the next one, estimated as
+                             ||delta_r||^2 / ||delta_r^prev||, is below that (default 1e-12) */
   int32_t autotune;        /* 1 = time every tile variant of each merge GEMM shape not yet
                              in the process's tuning table and record the fastest (the
                              build synchronizes its stream per new shape); builds launch
@@ -102,7 +104,9 @@ typedef struct {
 typedef struct {
   int32_t iterations;  /* residual correction steps taken (0 when correction is off)     */
   int32_t converged;   /* 1 when the last relative correction met refine_tol             */
-  double correction;   /* max over right-hand sides of ||delta|| / ||u|| in the last step */
+  double correction;   /* max over right-hand sides of ||delta|| / ||u|| in the last step,
+                          or of its contraction estimate of the next step where that is
+                          what met the tolerance                                        */
 } hps_solve_info;
 
 /* Timing of one kernel group (profile = 1).  flops and bytes are the algorithmic work

@@ -1296,8 +1296,9 @@ int refine_iters(const hps_group& f) {
 
 // Solve problems [pb, pb + np), then (when enabled) residual correction in FP64:
 // r = b - A u on the global collocation system, delta = Solve(r) with r's shared-edge
-// rows as interface jumps, u += delta, until max_r |delta_r| <= tol |u_r| (norms over
-// the problems of the range) or the iteration limit.
+// rows as interface jumps, u += delta, until every right-hand side's relative
+// correction |delta_r| / |u_r| (norms over the problems of the range), or its contraction
+// estimate of the next one, is <= tol, or the iteration limit.
 void solve_impl(hps_group& f, int pb, int np, int nrhs, const double* s, const double* t,
                 const double* jmp, double* u, hipStream_t st, hps_solve_info* info,
                 size_t* ws_bytes = nullptr) {
@@ -1335,6 +1336,7 @@ void solve_impl(hps_group& f, int pb, int np, int nrhs, const double* s, const d
   *info = hps_solve_info{};
   if (iters <= 0) return;
   std::vector<double> hpart((size_t)nrhs * nblk * 2);
+  std::vector<double> prev((size_t)nrhs, 0.0);  // previous relative correction per RHS
   double corr = 0.0;
   int it = 0;
   bool conv = false;
@@ -1351,16 +1353,30 @@ void solve_impl(hps_group& f, int pb, int np, int nrhs, const double* s, const d
     HPS_HIP(hipMemcpyAsync(hpart.data(), part, hpart.size() * sizeof(double),
                            hipMemcpyDeviceToHost, st));
     HPS_HIP(hipStreamSynchronize(st));
+    // Per right-hand side: c = ||delta|| / ||u||.  Done when every c <= tol, or when
+    // the corrections contract (c below half the previous one) fast enough that the
+    // next one, estimated as c * (c / c_prev), is <= tol: then u already carries the
+    // accuracy another sweep would only confirm.  corr reports the larger of c and that
+    // estimate over the right-hand sides.
     corr = 0.0;
+    bool all_done = true;
     for (int q = 0; q < nrhs; ++q) {
       double dd = 0, uu = 0;
       for (int b = 0; b < nblk; ++b) {
         dd += hpart[2 * ((size_t)q * nblk + b)];
         uu += hpart[2 * ((size_t)q * nblk + b) + 1];
       }
-      corr = std::max(corr, uu > 0 ? std::sqrt(dd / uu) : std::sqrt(dd));
+      const double c = uu > 0 ? std::sqrt(dd / uu) : std::sqrt(dd);
+      double left = c;
+      if (c > f.opts.refine_tol) {
+        const double pq = prev[q];
+        if (pq > 0.0 && c < 0.5 * pq) left = c * (c / pq);
+        if (left > f.opts.refine_tol) all_done = false;
+      }
+      corr = std::max(corr, std::min(c, left));
+      prev[q] = c;
     }
-    if (corr <= f.opts.refine_tol) {
+    if (all_done) {
       conv = true;
       break;
     }
