@@ -60,6 +60,7 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
   constexpr int LA = BM + lds_pad(BM), LB = BN + lds_pad(BN);
   static_assert(MB >= 1 && NB >= 1 && WM % 16 == 0 && WN % 16 == 0, "bad tile");
   static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "tile/threads mismatch");
+  static_assert(NT % BN == 0, "B tile: whole columns per thread group");
   __shared__ T As[2][NPA][BK][LA];
   __shared__ T Bs[2][NPB][BK][LB];
 
@@ -107,10 +108,12 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
         ra[e][NPA - 1] = v.y;
       }
     }
+    // B: each thread reads EB consecutive k of one column (contiguous in memory), and
+    // neighbouring threads take neighbouring columns, so that the stores into the
+    // [k][j] LDS layout below are contiguous across lanes (no bank conflicts)
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
-      const int idx = tid + NT * e;
-      const int k = idx % BK, j = idx / BK;
+      const int j = tid % BN, k = (tid / BN) * EB + e;
       const int gk = k0 + k, gj = j0 + j;
       const bool ok = gk < d.K && gj < d.N;
       const long off = (long)gk + d.ldb * (long)gj;
@@ -133,8 +136,7 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
-      const int idx = tid + NT * e;
-      const int k = idx % BK, j = idx / BK;
+      const int j = tid % BN, k = (tid / BN) * EB + e;
 #pragma unroll
       for (int pl = 0; pl < NPB; ++pl) Bs[buf][pl][k][j] = rb[e][pl];
     }
