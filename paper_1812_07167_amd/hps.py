@@ -231,9 +231,10 @@ class Factor:
 
     def stage_times(self, which):
         """[(name, launches, ms, flops, bytes)] of the build (0) or the last solve (1)."""
-        buf = (StageTime * 64)()
+        cap = 4096
+        buf = (StageTime * cap)()
         n = C.c_int32()
-        _check(load().hps_stage_times(self.h, which, buf, 64, C.byref(n)))
+        _check(load().hps_stage_times(self.h, which, buf, cap, C.byref(n)))
         return [(buf[i].name.decode(), buf[i].launches, buf[i].ms, buf[i].flops, buf[i].bytes)
                 for i in range(n.value)]
 
