@@ -32,7 +32,8 @@ def _say(*a):
 # ---------------------------------------------------------------- leaf operators (Sec. 2.1)
 
 
-@pytest.mark.parametrize("nx,ny,p", [(2, 2, 4), (2, 1, 8), (2, 2, 12), (1, 2, 13), (2, 2, 16)])
+@pytest.mark.parametrize("nx,ny,p", [(2, 2, 4), (2, 1, 8), (2, 2, 9), (1, 1, 11), (2, 2, 12),
+                                     (1, 2, 13), (2, 1, 14), (1, 2, 15), (2, 2, 16)])
 def test_leaf_operators(nx, ny, p):
     from paper_1812_07167_amd import hps as H
     _say("leaf operators", nx, ny, p)
