@@ -129,7 +129,8 @@ def cpu_baseline(nx, ny, p, kappa, nrhs, seed):
 
 def mixed_leg(H, torch, dom, p, kappa, c_d, s_d, t_d, u_ref, exact, stream, out, reps=3):
     """The same build + 16-RHS solve with complex64 merges and solve products (FP64
-    leaves, top 3 levels and residual correction), against the complex128 result."""
+    leaves, top-3-level interface inverses and residual correction), against the
+    complex128 result."""
     u_c128 = u_ref.clone()
     u = torch.empty_like(u_ref)
     f = H.hps_build(dom, p, kappa, kappa, c_d, stream=stream, precision=H.HPS_PREC_MIXED,
@@ -165,8 +166,9 @@ def precision_leg(H, torch, dev, stream, nx=128, p=16, kappa=300.0, nrhs=4, seed
     """The precision comparison at scale: 128 x 128 leaves, p = 16 (4.1M collocation
     nodes), kappa = eta = 300, Fourier c, manufactured right-hand sides with seeded
     directions.  The complex128 build + solve against the mixed one (complex64 merges and
-    solve products on the FP32 matrix cores, FP64 leaves, top 3 levels and residual
-    correction): times, error against the closed form and against complex128."""
+    solve products on the FP32 matrix cores, FP64 leaves, top-3-level interface inverses
+    and residual correction): times, error against the closed form and against
+    complex128."""
     from paper_1812_07167_amd import inputs as G
     dom = H.domain(nx, nx)
     xy, xyi, xyb, nrm = H.hps_nodes(dom, p)

@@ -68,10 +68,12 @@ typedef struct {
 /* Arithmetic of the factorization and of the solve sweeps. */
 enum {
   HPS_PREC_C128 = 0,  /* complex128 throughout                                            */
-  HPS_PREC_MIXED = 1  /* leaves and the top fp64_top_levels merge levels in complex128; the
-                         other merges and every solve product in complex64 on the matrix
-                         cores with FP32 accumulation; each solve is then corrected with the
-                         FP64 residual of the global collocation system (not in the paper) */
+  HPS_PREC_MIXED = 1  /* leaves computed in complex128; every merge product, stored merge
+                         operator and solve product in complex64 on the matrix cores with
+                         FP32 accumulation; the interface inverses W^{-1} of the top
+                         fp64_top_levels levels computed in complex128; each solve is then
+                         corrected with the FP64 residual of the global collocation system
+                         (not in the paper)                                                 */
 };
 
 /* Build options.  hps_default_opts() fills the defaults noted below. */
@@ -85,7 +87,7 @@ typedef struct {
                              and of each solve; read them with hps_stage_times (default 0) */
   void* stream;           /* hipStream_t the work is ordered on (default NULL)            */
   int32_t fp64_top_levels; /* HPS_PREC_MIXED: merge levels 0..fp64_top_levels-1 (the root
-                             is level 0) stay complex128 (default 3)                     */
+                             is level 0) invert W in complex128 (default 3)              */
   int32_t refine_max_iter; /* residual correction steps per solve; -1 = automatic: 10 for
                              HPS_PREC_MIXED, 0 for HPS_PREC_C128 (default -1)            */
   double refine_tol;       /* correction stops once, for every right-hand side r,

@@ -123,7 +123,8 @@ struct LevelPlan {
   const int* di3b = nullptr; const int* dja = nullptr; const int* djb = nullptr;
   // stored operators of the level (Sec. 2.4), slices of the factor's arena
   View Winv, R33a, R33b, R13a, R23b, PhiA, PhiB;
-  bool c64 = false;  // the level's operators (and its R) are complex64
+  bool c64 = false;    // the level's operators (and its R) are complex64
+  bool inv64 = false;  // complex64 level whose W is inverted in complex128
 };
 
 struct Geo { int ix0, iy0, wx, wy; };
@@ -576,6 +577,7 @@ void check_info(const std::vector<int>& h, long off, long cnt, const char* what)
 struct BuildScratch {
   DevBuf buf;
   View R31a, T, work;      // merge level (sized for the largest level)
+  View w64;                // complex128 copy of a complex64 level's W (inverted in FP64)
   View info;               // [2 * nleaf] leaf infos, then one int per merge
   std::vector<long> info_off;  // per level offset into info
 };
@@ -628,7 +630,8 @@ size_t scratch_bytes(const hps_group& f) {
     const size_t e = P.c64 ? 8 : 16;
     c.take((size_t)P.nbox * P.n3 * P.n1 * e);
     c.take((size_t)P.nbox * P.n3 * P.nbp * e);
-    c.take(zinv_workspace_bytes(P.n3, P.nbox, P.c64));
+    if (P.inv64) c.take((size_t)P.nbox * P.n3 * P.n3 * 16);
+    c.take(zinv_workspace_bytes(P.n3, P.nbox, P.c64 && !P.inv64));
     level_bytes = std::max(level_bytes, c.used);
   }
   return (level_bytes + 255) & ~size_t(255);
@@ -707,7 +710,8 @@ void level_scratch(const LevelPlan& P, BuildScratch& sc) {
   const size_t e = P.c64 ? 8 : 16;
   sc.R31a = c.take((size_t)P.nbox * P.n3 * P.n1 * e);
   sc.T = c.take((size_t)P.nbox * P.n3 * P.nbp * e);
-  sc.work = c.take(zinv_workspace_bytes(P.n3, P.nbox, P.c64));
+  sc.w64 = P.inv64 ? c.take((size_t)P.nbox * P.n3 * P.n3 * 16) : View();
+  sc.work = c.take(zinv_workspace_bytes(P.n3, P.nbox, P.c64 && !P.inv64));
 }
 
 // ------------------------------------------------------------------ build
@@ -814,8 +818,18 @@ void build_level(hps_group& f, int l, BuildScratch& sc) {
   // W^{-1}
   {
     Stage s(f.build_prof, iname.c_str(), nbox * 8.0 * n3 * n3 * n3, nbox * 2.0 * n3 * n3 * 16);
-    zinv((int)n3, (int)nbox, P.Winv.d(), n3, n3 * n3, P.Winv.d(), n3, n3 * n3, info,
-         sc.work.p, st, P.c64);
+    if (P.inv64) {
+      // complex64 level, W inverted in complex128 (the pivoting of large interface
+      // matrices stays in double precision); the inverse is rounded back for storage
+      const long cnt = 2L * nbox * n3 * n3;
+      to_c128(reinterpret_cast<const float*>(P.Winv.p), sc.w64.d(), cnt, st);
+      zinv((int)n3, (int)nbox, sc.w64.d(), n3, n3 * n3, sc.w64.d(), n3, n3 * n3, info,
+           sc.work.p, st, false);
+      to_c64(sc.w64.d(), reinterpret_cast<float*>(P.Winv.p), cnt, st);
+    } else {
+      zinv((int)n3, (int)nbox, P.Winv.d(), n3, n3 * n3, P.Winv.d(), n3, n3 * n3, info,
+           sc.work.p, st, P.c64);
+    }
   }
   // Phi^a = W^{-1} T   (eq. (talpha))
   g = GemmDesc();
@@ -1197,7 +1211,10 @@ std::shared_ptr<hps_group> build_group(const hps_domain& dom, int p, int nprob,
   }
   f->stream = static_cast<hipStream_t>(f->opts.stream);
   make_plan(*f);
-  for (int l = 0; l < f->L; ++l) f->lv[l].c64 = f->mixed && l >= f->opts.fp64_top_levels;
+  for (int l = 0; l < f->L; ++l) {
+    f->lv[l].c64 = f->mixed;
+    f->lv[l].inv64 = f->mixed && l < f->opts.fp64_top_levels;
+  }
   upload_plan(*f);
   // the group's own copy of c (problem-major), read by the leaf stage and the residual
   const size_t per = (size_t)f->nl1 * f->ni * sizeof(double);
@@ -1686,7 +1703,10 @@ int hps_estimate_bytes(const hps_domain* dom, int32_t p, const hps_opts* opts,
     f.nx = dom->nx; f.ny = dom->ny;
     f.nprob = 1; f.nl1 = dom->nx * dom->ny; f.nleaf = f.nl1;
     make_plan(f);
-    for (int l = 0; l < f.L; ++l) f.lv[l].c64 = f.mixed && l >= f.opts.fp64_top_levels;
+    for (int l = 0; l < f.L; ++l) {
+      f.lv[l].c64 = f.mixed;
+      f.lv[l].inv64 = f.mixed && l < f.opts.fp64_top_levels;
+    }
     size_t pk = 0, rs = 0;
     estimate_bytes(f, &pk, &rs);
     if (build_peak) *build_peak = (int64_t)pk;

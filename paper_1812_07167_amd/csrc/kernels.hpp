@@ -119,6 +119,8 @@ void fill_zero_int(int* p, long n, hipStream_t st);
 void fill_identity(double* p, int n, long stride, int batch, hipStream_t st, bool c64 = false);
 // round n doubles to floats (complex128 -> complex64 storage)
 void to_c64(const double* src, float* dst, long n, hipStream_t st);
+// dst[i] = (double)src[i], i < n
+void to_c128(const float* src, double* dst, long n, hipStream_t st);
 void merge_extract(const MergeLevelDesc& d, hipStream_t st);
 
 // ------------------------------------------------------------------ solve helpers

@@ -23,6 +23,11 @@ __global__ void to_f32_kernel(const double* s, float* d, long n) {
     d[e] = (float)s[e];
 }
 
+__global__ void to_f64_kernel(const float* s, double* d, long n) {
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    d[e] = (double)s[e];
+}
+
 __global__ void fill_zero_int_kernel(int* p, long n) {
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
     p[e] = 0;
@@ -160,6 +165,12 @@ void fill_zero(double* p, long n, hipStream_t st) {
 void to_c64(const double* src, float* dst, long n, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(to_f32_kernel, dim3(grid1d(n)), dim3(256), 0, st, src, dst, n);
+  HPS_LAUNCH_CHECK();
+}
+
+void to_c128(const float* src, double* dst, long n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(to_f64_kernel, dim3(grid1d(n)), dim3(256), 0, st, src, dst, n);
   HPS_LAUNCH_CHECK();
 }
 

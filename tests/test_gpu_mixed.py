@@ -1,5 +1,6 @@
 """Mixed precision (complex64 merges and solve products on the FP32 matrix cores, FP64
-leaves and top levels, FP64 residual correction) against the complex128 oracle.
+leaves and top-level interface inverses, FP64 residual correction) against the complex128
+oracle.
 
 Bars: the corrected solution meets the complex128 bar (rel. L2 1e-10 against the oracle);
 the uncorrected complex64 pieces are checked at a complex64 bar (rel. 1e-4), which also
