@@ -585,8 +585,14 @@ struct BuildScratch {
 // bytes of one complex entry of level l's operators and R (the leaves' R is complex128)
 size_t cbytes(const hps_group& f, int l) { return (l < f.L && f.lv[l].c64) ? 8 : 16; }
 
-// leaves per launch of the leaf stage (bounds its scratch)
+// leaves per launch of the leaf stage (bounds its scratch); in mixed precision the
+// scratch also holds the chunk's complex128 [Psi | Y] (1 MB per leaf at p = 16), so the
+// chunks are smaller
 constexpr long kLeafChunk = 4096;
+constexpr long kLeafChunkMixed = 1024;
+long leaf_chunk(const hps_group& f) {
+  return std::min<long>(f.nleaf, f.mixed ? kLeafChunkMixed : kLeafChunk);
+}
 
 bool level_forms_R(const hps_group& f, int l) {
   return l == f.L || l > 0 || f.opts.store_root_R;
@@ -622,7 +628,7 @@ size_t arena_layout(hps_group& f, char* base) {
 // Bytes of the build scratch (leaf chunks and merge levels; the info words follow).
 size_t scratch_bytes(const hps_group& f) {
   const long nl = f.nleaf, n = f.n;
-  const long lch = std::min<long>(nl, kLeafChunk);
+  const long lch = leaf_chunk(f);
   size_t level_bytes = leaf_scratch_bytes(f.p, lch) +
                        (f.mixed ? (size_t)lch * n * n * 16 + 256 : 0);
   for (auto& P : f.lv) {
@@ -724,9 +730,10 @@ void build_leaves(hps_group& f, const double* c, BuildScratch& sc) {
   d.c = c; d.leaf_grid = f.dleaf_grid.i(); d.tab = f.dLT.d();
   d.R = f.R[f.L].d(); d.info = sc.info.i();
   // scratch per chunk: the inverse's per-leaf copies, then (mixed precision) the
-  // complex128 [Psi | Y] of the chunk, rounded into the complex64 arena afterwards
+  // complex128 interior rows of the chunk's [Psi | Y], which the boundary-row kernel
+  // reads and rounds into the complex64 arena
   char* scr = static_cast<char*>(sc.buf.p);
-  const long lch = std::min<long>(nl, kLeafChunk);
+  const long lch = leaf_chunk(f);
   const size_t mg_bytes = leaf_scratch_bytes(f.p, lch);
   double* bi64 = f.mixed ? reinterpret_cast<double*>(scr + ((mg_bytes + 255) & ~size_t(255)))
                          : nullptr;
@@ -738,6 +745,8 @@ void build_leaves(hps_group& f, const double* c, BuildScratch& sc) {
     dc.h0 = h0;
     dc.leaf_grid = d.leaf_grid + h0;
     dc.BI = f.mixed ? bi64 : f.BI.d() + 2 * h0 * n * n;
+    // mixed precision: the boundary-row kernel also writes the complex64 [Psi | Y]
+    dc.BI32 = f.mixed ? reinterpret_cast<float*>(f.BI32.p) + 2 * h0 * n * n : nullptr;
     dc.R = d.R + 2 * h0 * nb * nb;
     dc.info = d.info + h0;
     dc.Mg = mg_bytes ? reinterpret_cast<double*>(scr) : nullptr;
@@ -753,13 +762,8 @@ void build_leaves(hps_group& f, const double* c, BuildScratch& sc) {
     }
     {
       Stage s(pr, "leaf_bnd", c_ * 8.0 * nb * n * f.m,
-              c_ * (ni * n + nb * n + nb * nb) * 16.0);
+              c_ * (ni * n * 16.0 + (nb * n + nb * nb) * 16.0 + (f.mixed ? n * n * 8.0 : 0.0)));
       leaf_boundary_rows(dc, st);
-    }
-    if (f.mixed) {
-      // the solve reads the leaf operators in complex64
-      Stage s(pr, "leaf_to_c64", 0.0, c_ * n * n * 24);
-      to_c64(bi64, reinterpret_cast<float*>(f.BI32.p) + 2 * h0 * n * n, 2L * cnt * n * n, st);
     }
   }
   f.R_valid[f.L] = 1;

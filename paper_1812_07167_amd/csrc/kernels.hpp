@@ -78,6 +78,9 @@ struct LeafDesc {
   const int* leaf_grid = nullptr;  // device [nleaf]: grid index of tree-ordered leaf h
   const double* tab = nullptr;   // device complex line tables, leaf_table_len(p) per problem
   double* BI = nullptr;          // device [nleaf][n*n] complex: [Psi | Y]
+  float* BI32 = nullptr;         // if set: [nleaf][n*n] complex64 copy of [Psi | Y], written
+                                 // by the boundary-row kernel (whose complex128 boundary
+                                 // rows then go only there)
   double* R = nullptr;           // device [nleaf][nb*nb] complex
   double* Mg = nullptr;          // scratch of the interior inverse (leaf_scratch_bytes)
   int* info = nullptr;           // device [nleaf]

@@ -21,7 +21,8 @@
 // Kernels: leaf_sinv (S_i^{-1} by blocked Gauss-Jordan with partial pivoting, the
 // matrix held in registers (partly in a scratch copy for p >= 15), one workgroup per
 // leaf), leaf_psi_i (Psi_i from the rows of Y_i),
-// leaf_bnd (boundary rows of [Psi | Y] and R).
+// leaf_bnd (boundary rows of [Psi | Y] and R; for reduced-precision storage it also
+// writes the complex64 copy of the whole [Psi | Y]).
 #include "kernels.hpp"
 
 namespace hps {
@@ -446,6 +447,7 @@ __global__ __launch_bounds__(256) void leaf_bnd_kernel(LeafDesc d) {
     sb[4 + tid] = tab[T.bx() + tid];  // (W, E) pair: c11 c12 c21 c22
   }
   double2* BI = reinterpret_cast<double2*>(d.BI) + h * (long)N * N;
+  float2* B32 = d.BI32 ? reinterpret_cast<float2*>(d.BI32) + h * (long)N * N : nullptr;
   double2* R = reinterpret_cast<double2*>(d.R) + h * (long)NB * NB;
   // -2 i eta = (2 eta_im, -2 eta_re)
   const double2 m2ie = cmk(2.0 * d.prm[4 * prob + 2], -2.0 * d.prm[4 * prob + 1]);
@@ -454,7 +456,9 @@ __global__ __launch_bounds__(256) void leaf_bnd_kernel(LeafDesc d) {
     __syncthreads();
     for (int e = tid; e < NI * cw; e += 256) {
       const int row = e % NI, col = e / NI;
-      sI[col][row] = BI[(NB + row) + (long)N * (c0 + col)];
+      const double2 v = BI[(NB + row) + (long)N * (c0 + col)];
+      sI[col][row] = v;
+      if (B32) B32[(NB + row) + (long)N * (c0 + col)] = make_float2((float)v.x, (float)v.y);
     }
     __syncthreads();
     for (int e = tid; e < NB * cw; e += 256) {
@@ -479,7 +483,8 @@ __global__ __launch_bounds__(256) void leaf_bnd_kernel(LeafDesc d) {
         else if (gcol == m + t) base = sb[rs + 1];   // column E_t
       }
       const double2 v = csub(base, acc);
-      BI[b + (long)N * gcol] = v;
+      if (B32) B32[b + (long)N * gcol] = make_float2((float)v.x, (float)v.y);
+      else BI[b + (long)N * gcol] = v;
       if (gcol < NB) {
         double2 rv = cmul(m2ie, v);
         if (gcol == b) rv.x += 1.0;
