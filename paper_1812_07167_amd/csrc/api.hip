@@ -35,9 +35,18 @@ struct DevBuf {
     return *this;
   }
   ~DevBuf() { release(); }
+  // Large buffers (operator arenas, ItI buffers, build scratch) come from the library's
+  // buffer cache, so that repeated builds of one shape do not map fresh memory each
+  // time; their release waits for the device, as hipFree does.
+  static constexpr size_t kCached = size_t(64) << 20;
   void alloc(size_t b) {
     release();
     if (b == 0) return;
+    if (b >= kCached) {
+      p = ws_alloc_idle(b);
+      bytes = b;
+      return;
+    }
     hipError_t e = hipMalloc(&p, b);
     if (e != hipSuccess) {
       p = nullptr;
@@ -49,7 +58,10 @@ struct DevBuf {
     bytes = b;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (bytes >= kCached) ws_free_idle(p);
+      else (void)hipFree(p);
+    }
     p = nullptr;
     bytes = 0;
   }
@@ -1750,7 +1762,16 @@ void ws_release(WsBuf& b) {
 }
 }  // namespace
 
-void* ws_alloc(size_t bytes, hipStream_t st) {
+namespace {
+void* ws_take(size_t bytes, hipStream_t st, bool host_wait);
+}  // namespace
+
+void* ws_alloc(size_t bytes, hipStream_t st) { return ws_take(bytes, st, false); }
+
+namespace {
+// host_wait: the caller's work is not ordered on one stream, so a reused buffer's last
+// use is waited for on the host
+void* ws_take(size_t bytes, hipStream_t st, bool host_wait) {
   int dev = 0;
   HPS_HIP(hipGetDevice(&dev));
   bytes = (std::max<size_t>(bytes, 1) + kWsGrain - 1) / kWsGrain * kWsGrain;
@@ -1764,9 +1785,18 @@ void* ws_alloc(size_t bytes, hipStream_t st) {
   }
   if (best >= 0) {
     WsBuf& b = g_ws[best];
-    if (b.recorded) HPS_HIP(hipStreamWaitEvent(st, b.ev, 0));
     b.busy = true;
-    return b.p;
+    void* const ptr = b.p;
+    if (b.recorded) {
+      if (host_wait) {
+        const hipEvent_t ev = b.ev;  // not destroyed while the buffer is busy
+        lk.unlock();
+        HPS_HIP(hipEventSynchronize(ev));
+        return ptr;
+      }
+      HPS_HIP(hipStreamWaitEvent(st, b.ev, 0));
+    }
+    return ptr;
   }
   std::vector<WsBuf> drop;
   if (largest >= 0) {
@@ -1798,6 +1828,21 @@ void* ws_alloc(size_t bytes, hipStream_t st) {
   lk.lock();
   g_ws.push_back(nb);
   return nb.p;
+}
+}  // namespace
+
+void* ws_alloc_idle(size_t bytes) { return ws_take(bytes, nullptr, true); }
+
+void ws_free_idle(void* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();  // every use of the buffer, on any stream, has ended
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  for (auto& b : g_ws)
+    if (b.p == p) {
+      b.recorded = false;
+      b.busy = false;
+      return;
+    }
 }
 
 void ws_free(void* p, hipStream_t st) {

@@ -27,6 +27,10 @@ void solve_on(hps_factor* f, int nrhs, const double* s, const double* t, double*
 void* ws_alloc(size_t bytes, hipStream_t st);
 void ws_free(void* p, hipStream_t st);
 void ws_trim();
+// The same cache for long-lived buffers that several streams may use: ws_free_idle
+// synchronizes the device before the buffer becomes reusable, so reuse needs no event.
+void* ws_alloc_idle(size_t bytes);
+void ws_free_idle(void* p);
 
 // Message hps_last_error() returns on the calling thread.
 void set_last_error(const std::string& msg);
