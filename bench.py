@@ -71,8 +71,7 @@ def kernel_of(stage, p):
             return "zgemm_kernel<float, %d, %d, %d, %d, false, false>" % (bm, bn, wr, wc), "mfma32"
         return "zgemm_kernel<double, %d, %d, %d, %d, %s, %s>" % (bm, bn, wr, wc, ar, br), "mfma"
     return {"leaf_sinv": ("leaf_sinv_kernel<%d>" % p, "alu"),
-            "leaf_psi_i": ("leaf_psi_i_kernel<%d>" % p, "alu"),
-            "leaf_bnd": ("leaf_bnd_kernel<%d>" % p, "alu")}.get(base)
+            "leaf_psi_bnd": ("leaf_psi_bnd_kernel<%d>" % p, "hbm")}.get(base)
 
 
 def log(*a):

@@ -742,7 +742,7 @@ void build_leaves(hps_group& f, const double* c, BuildScratch& sc) {
   d.c = c; d.leaf_grid = f.dleaf_grid.i(); d.tab = f.dLT.d();
   d.R = f.R[f.L].d(); d.info = sc.info.i();
   // scratch per chunk: the inverse's per-leaf copies, then (mixed precision) the
-  // complex128 interior rows of the chunk's [Psi | Y], which the boundary-row kernel
+  // complex128 Y_i blocks of the chunk's [Psi | Y], which the Psi / boundary-row kernel
   // reads and rounds into the complex64 arena
   char* scr = static_cast<char*>(sc.buf.p);
   const long lch = leaf_chunk(f);
@@ -757,7 +757,7 @@ void build_leaves(hps_group& f, const double* c, BuildScratch& sc) {
     dc.h0 = h0;
     dc.leaf_grid = d.leaf_grid + h0;
     dc.BI = f.mixed ? bi64 : f.BI.d() + 2 * h0 * n * n;
-    // mixed precision: the boundary-row kernel also writes the complex64 [Psi | Y]
+    // mixed precision: the Psi / boundary-row kernel writes the complex64 [Psi | Y]
     dc.BI32 = f.mixed ? reinterpret_cast<float*>(f.BI32.p) + 2 * h0 * n * n : nullptr;
     dc.R = d.R + 2 * h0 * nb * nb;
     dc.info = d.info + h0;
@@ -769,13 +769,12 @@ void build_leaves(hps_group& f, const double* c, BuildScratch& sc) {
       leaf_interior_inverse(dc, st);
     }
     {
-      Stage s(pr, "leaf_psi_i", c_ * 32.0 * ni * ni, c_ * (ni * ni + ni * nb) * 16.0);
-      leaf_psi_interior(dc, st);
-    }
-    {
-      Stage s(pr, "leaf_bnd", c_ * 8.0 * nb * n * f.m,
-              c_ * (ni * n * 16.0 + (nb * n + nb * nb) * 16.0 + (f.mixed ? n * n * 8.0 : 0.0)));
-      leaf_boundary_rows(dc, st);
+      // Y_i read once; Psi_i and the boundary rows written (complex64 in mixed precision,
+      // with the interior Y rows), R written
+      const double out = f.mixed ? n * n * 8.0 : (ni * nb + nb * n) * 16.0;
+      Stage s(pr, "leaf_psi_bnd", c_ * (32.0 * ni * ni + 8.0 * nb * n * f.m),
+              c_ * (ni * ni * 16.0 + out + nb * nb * 16.0));
+      leaf_psi_and_boundary(dc, st);
     }
   }
   f.R_valid[f.L] = 1;

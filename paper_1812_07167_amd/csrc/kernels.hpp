@@ -79,8 +79,8 @@ struct LeafDesc {
   const double* tab = nullptr;   // device complex line tables, leaf_table_len(p) per problem
   double* BI = nullptr;          // device [nleaf][n*n] complex: [Psi | Y]
   float* BI32 = nullptr;         // if set: [nleaf][n*n] complex64 copy of [Psi | Y], written
-                                 // by the boundary-row kernel (whose complex128 boundary
-                                 // rows then go only there)
+                                 // by the Psi / boundary-row kernel (whose outputs then go
+                                 // only there)
   double* R = nullptr;           // device [nleaf][nb*nb] complex
   double* Mg = nullptr;          // scratch of the interior inverse (leaf_scratch_bytes)
   int* info = nullptr;           // device [nleaf]
@@ -92,8 +92,8 @@ size_t leaf_scratch_bytes(int p, long nleaf);
 // each) and the two 2 x 2 inverses of F_bb (S/N pair, W/E pair)
 int leaf_table_len(int p);
 void leaf_interior_inverse(const LeafDesc& d, hipStream_t st);  // S_i^{-1} -> Y_i block
-void leaf_psi_interior(const LeafDesc& d, hipStream_t st);      // Psi_i = -Y_i W
-void leaf_boundary_rows(const LeafDesc& d, hipStream_t st);     // [Psi_b | Y_b], R
+// Psi_i = -Y_i W, the boundary rows [Psi_b | Y_b] and R, from the Y_i block
+void leaf_psi_and_boundary(const LeafDesc& d, hipStream_t st);
 
 // ------------------------------------------------------------------ merge helpers
 struct MergeLevelDesc {

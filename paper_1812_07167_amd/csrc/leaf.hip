@@ -20,9 +20,9 @@
 //
 // Kernels: leaf_sinv (S_i^{-1} by blocked Gauss-Jordan with partial pivoting, the
 // matrix held in registers (partly in a scratch copy for p >= 15), one workgroup per
-// leaf), leaf_psi_i (Psi_i from the rows of Y_i),
-// leaf_bnd (boundary rows of [Psi | Y] and R; for reduced-precision storage it also
-// writes the complex64 copy of the whole [Psi | Y]).
+// leaf), leaf_psi_bnd (Psi_i, the boundary rows of [Psi | Y] and R, in one pass over
+// Y_i; for reduced-precision storage it writes the complex64 copy of the whole
+// [Psi | Y]).
 #include "kernels.hpp"
 
 namespace hps {
@@ -369,13 +369,53 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
   }
 }
 
-// Psi_i = -Y_i W, W = A_ib F_bb^{-1}: row (i, j) of W has four entries, in the columns
-// of S_i (wS[j]), N_i (wN[j]), W_j (wW[i]) and E_j (wE[i]).  One thread per interior
-// row r of Y_i (the threads of a workgroup read each column of Y_i together).
+// One entry of the boundary rows [Psi_b | Y_b] = [F_bb^{-1} | 0] - F_bb^{-1} F_bi
+// [Psi_i | Y_i] in column gcol, from that column's interior rows (col, LDS): the row of
+// S_t combines the interior rows of grid column t with sS, N_t with sN, the rows of
+// E_t / W_t combine grid row t with oE / oW; the 2 x 2 inverses of F_bb sit on the
+// boundary columns.
 template <int P>
-__global__ __launch_bounds__(256) void leaf_psi_i_kernel(LeafDesc d) {
+__device__ inline double2 bnd_entry(int b, int gcol, const double2* col, const double2 (*sc)[P - 2],
+                                    const double2* sb) {
+  constexpr int m = P - 2;
+  const int side = b / m, t = b % m;  // 0 S, 1 E, 2 N, 3 W
+  double2 acc = cmk(0, 0);
+  double2 base = cmk(0, 0);
+  if (side == 0 || side == 2) {       // grid column t: interior rows (t, l)
+    const double2* co = sc[side == 0 ? 0 : 1];
+#pragma unroll
+    for (int l = 0; l < m; ++l) acc = cfma(co[l], col[l * m + t], acc);
+    const int rs = (side == 0) ? 0 : 2;          // b11 b12 | b21 b22
+    if (gcol == t) base = sb[rs];                // column S_t
+    else if (gcol == 2 * m + t) base = sb[rs + 1];  // column N_t
+  } else {                            // grid row t: interior rows (k, t)
+    const double2* co = sc[side == 3 ? 2 : 3];
+#pragma unroll
+    for (int k = 0; k < m; ++k) acc = cfma(co[k], col[t * m + k], acc);
+    const int rs = (side == 3) ? 4 : 6;          // c11 c12 | c21 c22
+    if (gcol == 3 * m + t) base = sb[rs];        // column W_t
+    else if (gcol == m + t) base = sb[rs + 1];   // column E_t
+  }
+  return csub(base, acc);
+}
+
+// Psi_i = -Y_i W (W = A_ib F_bb^{-1}), the boundary rows of [Psi | Y] and R = I - 2 i eta
+// Psi_b, in one pass over Y_i.  Row (i, j) of W has four entries, in the columns of S_i
+// (wS[j]), N_i (wN[j]), W_j (wW[i]) and E_j (wE[i]).  Y_i is read by grid rows: chunk k
+// stages the m columns of the interior nodes (i, k) in LDS, which completes the columns
+// W_k and E_k of Psi_i (one thread per interior row) and adds the chunk's terms to the
+// row's m S and m N entries (registers); the chunk's columns of Y, W_k and E_k then get
+// their boundary rows.  The S and N columns get theirs after the last chunk.  For
+// reduced-precision storage every entry goes to the complex64 copy only.
+template <int P>
+__global__ __launch_bounds__(256) void leaf_psi_bnd_kernel(LeafDesc d) {
   constexpr int m = P - 2, NI = m * m, NB = 4 * m, N = P * P - 4;
-  __shared__ double2 sw[4][m];
+  constexpr int CC = m + 2;  // staged columns: a chunk of Y_i plus W_k and E_k of Psi_i
+  static_assert(NI <= 256, "one thread per interior row");
+  __shared__ double2 sI[CC][NI];
+  __shared__ double2 sw[4][m];  // wS wN wW wE
+  __shared__ double2 sc[4][m];  // sS sN oW oE
+  __shared__ double2 sb[8];
   const int tid = threadIdx.x;
   const long h = blockIdx.x;
   const long prob = (d.h0 + h) / d.nl1;
@@ -386,57 +426,6 @@ __global__ __launch_bounds__(256) void leaf_psi_i_kernel(LeafDesc d) {
     sw[1][e] = tab[T.wN() + e];
     sw[2][e] = tab[T.wW() + e];
     sw[3][e] = tab[T.wE() + e];
-  }
-  __syncthreads();
-  const int r = tid;
-  if (r >= NI) return;
-  double2* BI = reinterpret_cast<double2*>(d.BI) + h * (long)N * N;
-  const double2* Yr = BI + NB + r;  // row r of Y_i: Yr[N * (NB + col)]
-  double2 accW[m], accE[m];
-#pragma unroll
-  for (int j = 0; j < m; ++j) {
-    accW[j] = cmk(0, 0);
-    accE[j] = cmk(0, 0);
-  }
-#pragma unroll 1
-  for (int i = 0; i < m; ++i) {
-    double2 accS = cmk(0, 0), accN = cmk(0, 0);
-    const double2 ww = sw[2][i], we = sw[3][i];
-#pragma unroll
-    for (int j = 0; j < m; ++j) {
-      const double2 y = Yr[(long)N * (NB + j * m + i)];
-      accS = cfma(y, sw[0][j], accS);
-      accN = cfma(y, sw[1][j], accN);
-      accW[j] = cfma(y, ww, accW[j]);
-      accE[j] = cfma(y, we, accE[j]);
-    }
-    BI[(NB + r) + (long)N * i] = cmk(-accS.x, -accS.y);              // S_i
-    BI[(NB + r) + (long)N * (2 * m + i)] = cmk(-accN.x, -accN.y);    // N_i
-  }
-#pragma unroll
-  for (int j = 0; j < m; ++j) {
-    BI[(NB + r) + (long)N * (m + j)] = cmk(-accE[j].x, -accE[j].y);      // E_j
-    BI[(NB + r) + (long)N * (3 * m + j)] = cmk(-accW[j].x, -accW[j].y);  // W_j
-  }
-}
-
-// Boundary rows of [Psi | Y] = [F_bb^{-1} | 0] - F_bb^{-1} F_bi [Psi_i | Y_i]: the row of
-// S_i combines the interior rows of grid column i with sS, N_i with sN, the rows of
-// E_j / W_j combine grid row j with oE / oW; plus the 2 x 2 inverses on the boundary
-// columns.  Then R = I - 2 i eta Psi_b.  Columns are staged through LDS in chunks.
-template <int P>
-__global__ __launch_bounds__(256) void leaf_bnd_kernel(LeafDesc d) {
-  constexpr int m = P - 2, NI = m * m, NB = 4 * m, N = P * P - 4;
-  constexpr int CC = 16;  // columns per chunk
-  __shared__ double2 sI[CC][NI];
-  __shared__ double2 sc[4][m];
-  __shared__ double2 sb[8];
-  const int tid = threadIdx.x;
-  const long h = blockIdx.x;
-  const long prob = (d.h0 + h) / d.nl1;
-  const double2* tab = reinterpret_cast<const double2*>(d.tab) + prob * leaf_table_len_dev(P);
-  const TabIdx T{m};
-  for (int e = tid; e < m; e += 256) {
     sc[0][e] = tab[T.sS() + e];
     sc[1][e] = tab[T.sN() + e];
     sc[2][e] = tab[T.oW() + e];
@@ -451,46 +440,93 @@ __global__ __launch_bounds__(256) void leaf_bnd_kernel(LeafDesc d) {
   double2* R = reinterpret_cast<double2*>(d.R) + h * (long)NB * NB;
   // -2 i eta = (2 eta_im, -2 eta_re)
   const double2 m2ie = cmk(2.0 * d.prm[4 * prob + 2], -2.0 * d.prm[4 * prob + 1]);
-  for (int c0 = 0; c0 < N; c0 += CC) {
-    const int cw = (N - c0) < CC ? (N - c0) : CC;
-    __syncthreads();
-    for (int e = tid; e < NI * cw; e += 256) {
-      const int row = e % NI, col = e / NI;
-      const double2 v = BI[(NB + row) + (long)N * (c0 + col)];
-      sI[col][row] = v;
-      if (B32) B32[(NB + row) + (long)N * (c0 + col)] = make_float2((float)v.x, (float)v.y);
-    }
-    __syncthreads();
-    for (int e = tid; e < NB * cw; e += 256) {
+  auto put = [&](int row, int gcol, double2 v) {
+    if (B32) B32[row + (long)N * gcol] = make_float2((float)v.x, (float)v.y);
+    else BI[row + (long)N * gcol] = v;
+  };
+  // boundary rows (and R) of the ncol staged columns sI[0..ncol), global columns gc(col)
+  auto boundary = [&](int ncol, auto&& gc) {
+    for (int e = tid; e < NB * ncol; e += 256) {
       const int b = e % NB, col = e / NB;
-      const int gcol = c0 + col;
-      const int side = b / m, t = b % m;  // 0 S, 1 E, 2 N, 3 W
-      double2 acc = cmk(0, 0);
-      double2 base = cmk(0, 0);
-      if (side == 0 || side == 2) {       // grid column i = t: interior rows (t, l)
-        const double2* co = sc[side == 0 ? 0 : 1];
-#pragma unroll
-        for (int l = 0; l < m; ++l) acc = cfma(co[l], sI[col][l * m + t], acc);
-        const int rs = (side == 0) ? 0 : 2;  // b11 b12 | b21 b22
-        if (gcol == t) base = sb[rs];                // column S_t
-        else if (gcol == 2 * m + t) base = sb[rs + 1];  // column N_t
-      } else {                            // grid row j = t: interior rows (k, t)
-        const double2* co = sc[side == 3 ? 2 : 3];
-#pragma unroll
-        for (int k = 0; k < m; ++k) acc = cfma(co[k], sI[col][t * m + k], acc);
-        const int rs = (side == 3) ? 4 : 6;  // c11 c12 | c21 c22
-        if (gcol == 3 * m + t) base = sb[rs];        // column W_t
-        else if (gcol == m + t) base = sb[rs + 1];   // column E_t
-      }
-      const double2 v = csub(base, acc);
-      if (B32) B32[b + (long)N * gcol] = make_float2((float)v.x, (float)v.y);
-      else BI[b + (long)N * gcol] = v;
+      const int gcol = gc(col);
+      const double2 v = bnd_entry<P>(b, gcol, sI[col], sc, sb);
+      put(b, gcol, v);
       if (gcol < NB) {
         double2 rv = cmul(m2ie, v);
         if (gcol == b) rv.x += 1.0;
         R[b + (long)NB * gcol] = rv;
       }
     }
+  };
+  const int r = tid;
+  double2 accS[m], accN[m];
+#pragma unroll
+  for (int i = 0; i < m; ++i) {
+    accS[i] = cmk(0, 0);
+    accN[i] = cmk(0, 0);
+  }
+  // chunk k's columns of Y_i: IT entries per thread, loaded together; the next chunk's
+  // loads are issued as soon as this chunk is in LDS
+  constexpr int IT = (NI * m + 255) / 256;
+  double2 yv[IT];
+  auto load_chunk = [&](int k) {
+#pragma unroll
+    for (int q = 0; q < IT; ++q) {
+      const int e = tid + 256 * q;
+      yv[q] = e < NI * m ? BI[(NB + e % NI) + (long)N * (NB + k * m + e / NI)] : cmk(0, 0);
+    }
+  };
+  load_chunk(0);
+#pragma unroll 1
+  for (int k = 0; k < m; ++k) {
+    __syncthreads();  // the tables; the previous chunk's boundary rows are done
+#pragma unroll
+    for (int q = 0; q < IT; ++q) {
+      const int e = tid + 256 * q;
+      if (e < NI * m) {
+        const int row = e % NI, i = e / NI;
+        sI[i][row] = yv[q];
+        if (B32)
+          B32[(NB + row) + (long)N * (NB + k * m + i)] = make_float2((float)yv[q].x, (float)yv[q].y);
+      }
+    }
+    if (k + 1 < m) load_chunk(k + 1);
+    __syncthreads();
+    if (r < NI) {
+      const double2 ws = sw[0][k], wn = sw[1][k];
+      double2 aW = cmk(0, 0), aE = cmk(0, 0);
+#pragma unroll
+      for (int i = 0; i < m; ++i) {
+        const double2 y = sI[i][r];
+        accS[i] = cfma(y, ws, accS[i]);
+        accN[i] = cfma(y, wn, accN[i]);
+        aW = cfma(y, sw[2][i], aW);
+        aE = cfma(y, sw[3][i], aE);
+      }
+      const double2 pW = cmk(-aW.x, -aW.y), pE = cmk(-aE.x, -aE.y);
+      sI[m][r] = pW;
+      sI[m + 1][r] = pE;
+      put(NB + r, 3 * m + k, pW);  // W_k
+      put(NB + r, m + k, pE);      // E_k
+    }
+    __syncthreads();
+    boundary(CC, [&](int col) { return col < m ? NB + k * m + col : col == m ? 3 * m + k : m + k; });
+  }
+  // the S columns (q = 0, global column i) and N columns (q = 1, column 2m + i)
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    __syncthreads();
+    if (r < NI) {
+#pragma unroll
+      for (int i = 0; i < m; ++i) {
+        const double2 a = q == 0 ? accS[i] : accN[i];
+        const double2 v = cmk(-a.x, -a.y);
+        sI[i][r] = v;
+        put(NB + r, q * 2 * m + i, v);
+      }
+    }
+    __syncthreads();
+    boundary(m, [&](int col) { return q * 2 * m + col; });
   }
 }
 
@@ -501,11 +537,8 @@ template <int P> void launch_sinv(const LeafDesc& d, hipStream_t st) {
 template <int P> void scratch_of(long nleaf, size_t* out) {
   *out = (size_t)nleaf * LeafCfg<P>::SCR * 16;
 }
-template <int P> void launch_psi_i(const LeafDesc& d, hipStream_t st) {
-  hipLaunchKernelGGL(leaf_psi_i_kernel<P>, dim3(d.nleaf), dim3(256), 0, st, d);
-}
-template <int P> void launch_bnd(const LeafDesc& d, hipStream_t st) {
-  hipLaunchKernelGGL(leaf_bnd_kernel<P>, dim3(d.nleaf), dim3(256), 0, st, d);
+template <int P> void launch_psi_bnd(const LeafDesc& d, hipStream_t st) {
+  hipLaunchKernelGGL(leaf_psi_bnd_kernel<P>, dim3(d.nleaf), dim3(256), 0, st, d);
 }
 
 #define HPS_P_SWITCH(FN, p, ...)                   \
@@ -542,15 +575,9 @@ void leaf_interior_inverse(const LeafDesc& d, hipStream_t st) {
   HPS_LAUNCH_CHECK();
 }
 
-void leaf_psi_interior(const LeafDesc& d, hipStream_t st) {
+void leaf_psi_and_boundary(const LeafDesc& d, hipStream_t st) {
   if (d.nleaf <= 0) return;
-  HPS_P_SWITCH(launch_psi_i, d.p, d, st);
-  HPS_LAUNCH_CHECK();
-}
-
-void leaf_boundary_rows(const LeafDesc& d, hipStream_t st) {
-  if (d.nleaf <= 0) return;
-  HPS_P_SWITCH(launch_bnd, d.p, d, st);
+  HPS_P_SWITCH(launch_psi_bnd, d.p, d, st);
   HPS_LAUNCH_CHECK();
 }
 
