@@ -30,10 +30,12 @@ sys.path.insert(0, ROOT)
 METRIC = "HPS build DOF/s + RHS solves/s at stated rel. L2 error; p99 solve latency"
 PEAK = {"hbm": (8000.0, "GB/s"), "mfma": (78.6, "TFLOP/s"), "mfma32": (157.3, "TFLOP/s"),
         "alu": (78.6, "TFLOP/s")}
-# GEMM variant recorded by the library ("MxN" tile + real/complex A and B) -> kernel
-GEMM_TILES = {"16x64": (16, 64, 1, 4), "64x16": (64, 16, 4, 1), "32x32": (32, 32, 2, 2),
-              "32x64": (32, 64, 2, 2), "64x32": (64, 32, 2, 2), "64x64": (64, 64, 2, 2),
-              "128x64": (128, 64, 4, 2), "64x128": (64, 128, 2, 4), "128x128": (128, 128, 4, 2)}
+# GEMM tile named in the library's timing records ("MxN") -> (BM, BN, WR, WC, K chunk)
+# of the GEMM kernel's template
+GEMM_TILES = {"16x64": (16, 64, 1, 4, 16), "64x16": (64, 16, 4, 1, 16), "32x32": (32, 32, 2, 2, 16),
+              "32x64": (32, 64, 2, 2, 16), "64x32": (64, 32, 2, 2, 16), "64x64": (64, 64, 2, 2, 8),
+              "128x64": (128, 64, 4, 2, 8), "64x128": (64, 128, 2, 4, 8),
+              "128x128": (128, 128, 4, 2, 8)}
 
 
 def measured_traffic(kernel):
@@ -65,11 +67,11 @@ def kernel_of(stage, p):
     if "[" in stage:
         var = stage[stage.index("[") + 1:-1]
         mt = re.fullmatch(r"(\d+x\d+)([rc])([rc])(s?)", var)
-        bm, bn, wr, wc = GEMM_TILES[mt.group(1)]
+        bm, bn, wr, wc, bk = GEMM_TILES[mt.group(1)]
         ar, br = ("true" if mt.group(2) == "r" else "false"), ("true" if mt.group(3) == "r" else "false")
         if mt.group(4):  # complex64 operands on the FP32 matrix cores
-            return "zgemm_kernel<float, %d, %d, %d, %d, false, false>" % (bm, bn, wr, wc), "mfma32"
-        return "zgemm_kernel<double, %d, %d, %d, %d, %s, %s>" % (bm, bn, wr, wc, ar, br), "mfma"
+            return "zgemm_kernel<float, %d, %d, %d, %d, false, false, %d>" % (bm, bn, wr, wc, bk), "mfma32"
+        return "zgemm_kernel<double, %d, %d, %d, %d, %s, %s, %d>" % (bm, bn, wr, wc, ar, br, bk), "mfma"
     return {"leaf_sinv": ("leaf_sinv_kernel<%d>" % p, "alu"),
             "leaf_psi_bnd": ("leaf_psi_bnd_kernel<%d>" % p, "hbm")}.get(base)
 

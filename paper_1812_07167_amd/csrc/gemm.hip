@@ -1,10 +1,14 @@
 // Batched complex GEMM on the FP64 matrix cores of gfx950 (v_mfma_f64_16x16x4f64).
 //
-// A complex product is formed from four real products (Cr += Ar Br - Ai Bi,
-// Ci += Ar Bi + Ai Br); a real operand drops two of them.  A workgroup of WR x WC
+// A complex product is formed from three real products where the tile's third
+// accumulator fits in registers (the 3M method, Higham 1992: T1 = Ar Br, T2 = Ai Bi,
+// T3 = (Ar + Ai)(Br + Bi), Cr = T1 - T2, Ci = T3 - T1 - T2; the operand sums are formed
+// as the MFMA operands are read), else from four (Cr += Ar Br - Ai Bi,
+// Ci += Ar Bi + Ai Br); a real operand needs two.  A workgroup of WR x WC
 // waves computes a BM x BN tile of C; K is staged through LDS in chunks of 16, double
 // buffered, with the next chunk's global loads issued before the current chunk's
-// MFMAs.  LDS rows are padded so that the four 16-lane groups of an MFMA operand read
+// MFMAs.  Large tiles take K in chunks of 8, which halves their LDS footprint so that
+// two workgroups share a compute unit.  LDS rows are padded so that the four 16-lane groups of an MFMA operand read
 // fall on alternating halves of the 64 banks.  Used by the leaf stage (Sec. 2.1: Psi_i,
 // Y_b, Y_i), by every merge product of Sec. 2.2 (W, Phi^a, Phi^b, R^tau) and by the
 // block updates of the interface inversion.
@@ -21,8 +25,6 @@
 
 namespace hps {
 namespace {
-
-constexpr int BK = 16;
 
 // element type traits: MFMA, accumulator and output row of accumulator slot v
 template <class T> struct Mfma;
@@ -47,7 +49,7 @@ template <> struct Mfma<float> {
 
 constexpr int lds_pad(int w) { return (w % 32 == 16) ? 0 : 16; }
 
-template <class T, int BM, int BN, int WR, int WC, bool AR, bool BR>
+template <class T, int BM, int BN, int WR, int WC, bool AR, bool BR, int BK>
 __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
   typedef Mfma<T> MF;
   typedef typename MF::acc acc_t;
@@ -57,6 +59,7 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
   constexpr int NPB = BR ? 1 : 2;
   constexpr int WM = BM / WR, WN = BN / WC;  // per-wave tile
   constexpr int MB = WM / 16, NB = WN / 16;
+  constexpr bool M3 = !AR && !BR && MB * NB <= 4;  // three real products per complex one
   constexpr int LA = BM + lds_pad(BM), LB = BN + lds_pad(BN);
   static_assert(MB >= 1 && NB >= 1 && WM % 16 == 0 && WN % 16 == 0, "bad tile");
   static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "tile/threads mismatch");
@@ -79,13 +82,15 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
   const T* A = reinterpret_cast<const T*>(d.A) + b * d.sA * NPA;
   const T* B = reinterpret_cast<const T*>(d.B) + b * d.sB * NPB;
 
-  acc_t accR[MB][NB], accI[MB][NB];
+  // 3M: accR, accX, accI hold T1, T2, T3 until the epilogue
+  acc_t accR[MB][NB], accI[MB][NB], accX[M3 ? MB : 1][M3 ? NB : 1];
 #pragma unroll
   for (int x = 0; x < MB; ++x)
 #pragma unroll
     for (int y = 0; y < NB; ++y) {
       accR[x][y] = acc_t{0, 0, 0, 0};
       accI[x][y] = acc_t{0, 0, 0, 0};
+      if (M3) accX[M3 ? x : 0][M3 ? y : 0] = acc_t{0, 0, 0, 0};
     }
 
   constexpr int EA = BM * BK / NT;  // A elements per thread per chunk
@@ -165,18 +170,47 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
         br[y] = Bs[buf][0][kl][c];
         bi[y] = BR ? T(0) : Bs[buf][NPB - 1][kl][c];
       }
+      if constexpr (M3) {
+        T as[MB], bs[NB];
 #pragma unroll
-      for (int x = 0; x < MB; ++x)
+        for (int x = 0; x < MB; ++x) as[x] = ar[x] + ai[x];
 #pragma unroll
-        for (int y = 0; y < NB; ++y) {
-          accR[x][y] = MF::op(ar[x], br[y], accR[x][y]);
-          if (!AR && !BR) accR[x][y] = MF::op(-ai[x], bi[y], accR[x][y]);
-          if (!BR) accI[x][y] = MF::op(ar[x], bi[y], accI[x][y]);
-          if (!AR) accI[x][y] = MF::op(ai[x], br[y], accI[x][y]);
-        }
+        for (int y = 0; y < NB; ++y) bs[y] = br[y] + bi[y];
+#pragma unroll
+        for (int x = 0; x < MB; ++x)
+#pragma unroll
+          for (int y = 0; y < NB; ++y) {
+            accR[x][y] = MF::op(ar[x], br[y], accR[x][y]);
+            accX[M3 ? x : 0][M3 ? y : 0] = MF::op(ai[x], bi[y], accX[M3 ? x : 0][M3 ? y : 0]);
+            accI[x][y] = MF::op(as[x], bs[y], accI[x][y]);
+          }
+      } else {
+#pragma unroll
+        for (int x = 0; x < MB; ++x)
+#pragma unroll
+          for (int y = 0; y < NB; ++y) {
+            accR[x][y] = MF::op(ar[x], br[y], accR[x][y]);
+            if (!AR && !BR) accR[x][y] = MF::op(-ai[x], bi[y], accR[x][y]);
+            if (!BR) accI[x][y] = MF::op(ar[x], bi[y], accI[x][y]);
+            if (!AR) accI[x][y] = MF::op(ai[x], br[y], accI[x][y]);
+          }
+      }
     }
     if (kc + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
+  }
+
+  if constexpr (M3) {
+#pragma unroll
+    for (int x = 0; x < MB; ++x)
+#pragma unroll
+      for (int y = 0; y < NB; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const T t1 = accR[x][y][v], t2 = accX[M3 ? x : 0][M3 ? y : 0][v];
+          accR[x][y][v] = t1 - t2;
+          accI[x][y][v] = accI[x][y][v] - t1 - t2;
+        }
   }
 
   // epilogue
@@ -205,7 +239,7 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
       }
 }
 
-template <int BM, int BN, int WR, int WC>
+template <int BM, int BN, int WR, int WC, int BK>
 void launch_tile(const GemmDesc& d, hipStream_t st) {
   const int tiles = cdiv(d.M, BM) * cdiv(d.N, BN);
   const dim3 grid(tiles, d.batch);
@@ -213,15 +247,15 @@ void launch_tile(const GemmDesc& d, hipStream_t st) {
   if (d.c64) {
     // the reduced-precision merges are complex x complex only
     if (d.a_real || d.b_real) throw Error(1, "zgemm: complex64 operands must be complex");
-    hipLaunchKernelGGL((zgemm_kernel<float, BM, BN, WR, WC, false, false>), grid, block, 0, st, d);
+    hipLaunchKernelGGL((zgemm_kernel<float, BM, BN, WR, WC, false, false, BK>), grid, block, 0, st, d);
   } else if (d.a_real && d.b_real) {
-    hipLaunchKernelGGL((zgemm_kernel<double, BM, BN, WR, WC, true, true>), grid, block, 0, st, d);
+    hipLaunchKernelGGL((zgemm_kernel<double, BM, BN, WR, WC, true, true, BK>), grid, block, 0, st, d);
   } else if (d.a_real) {
-    hipLaunchKernelGGL((zgemm_kernel<double, BM, BN, WR, WC, true, false>), grid, block, 0, st, d);
+    hipLaunchKernelGGL((zgemm_kernel<double, BM, BN, WR, WC, true, false, BK>), grid, block, 0, st, d);
   } else if (d.b_real) {
-    hipLaunchKernelGGL((zgemm_kernel<double, BM, BN, WR, WC, false, true>), grid, block, 0, st, d);
+    hipLaunchKernelGGL((zgemm_kernel<double, BM, BN, WR, WC, false, true, BK>), grid, block, 0, st, d);
   } else {
-    hipLaunchKernelGGL((zgemm_kernel<double, BM, BN, WR, WC, false, false>), grid, block, 0, st,
+    hipLaunchKernelGGL((zgemm_kernel<double, BM, BN, WR, WC, false, false, BK>), grid, block, 0, st,
                        d);
   }
 }
@@ -271,15 +305,15 @@ Tile pick_tile(const GemmDesc& d) {
 
 void launch_variant(Tile t, const GemmDesc& d, hipStream_t st) {
   switch (t) {
-    case T16x64: launch_tile<16, 64, 1, 4>(d, st); break;
-    case T64x16: launch_tile<64, 16, 4, 1>(d, st); break;
-    case T32x32: launch_tile<32, 32, 2, 2>(d, st); break;
-    case T32x64: launch_tile<32, 64, 2, 2>(d, st); break;
-    case T64x32: launch_tile<64, 32, 2, 2>(d, st); break;
-    case T128x64: launch_tile<128, 64, 4, 2>(d, st); break;
-    case T64x128: launch_tile<64, 128, 2, 4>(d, st); break;
-    case T128x128: launch_tile<128, 128, 4, 2>(d, st); break;
-    default: launch_tile<64, 64, 2, 2>(d, st); break;
+    case T16x64: launch_tile<16, 64, 1, 4, 16>(d, st); break;
+    case T64x16: launch_tile<64, 16, 4, 1, 16>(d, st); break;
+    case T32x32: launch_tile<32, 32, 2, 2, 16>(d, st); break;
+    case T32x64: launch_tile<32, 64, 2, 2, 16>(d, st); break;
+    case T64x32: launch_tile<64, 32, 2, 2, 16>(d, st); break;
+    case T128x64: launch_tile<128, 64, 4, 2, 8>(d, st); break;
+    case T64x128: launch_tile<64, 128, 2, 4, 8>(d, st); break;
+    case T128x128: launch_tile<128, 128, 4, 2, 8>(d, st); break;
+    default: launch_tile<64, 64, 2, 2, 8>(d, st); break;
   }
 }
 
