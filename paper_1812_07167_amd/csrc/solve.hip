@@ -179,19 +179,19 @@ __global__ void skinny_reduce_kernel(SkinnyDesc d, int r0, int nr, int nsplit,
   }
 }
 
-// rows covered by one workgroup for an operator of M rows
-int block_rows(int M) {
-  if (M <= 16) return 16;
-  if (M <= 32) return 32;
-  if (M <= 64) return 64;
-  if (M <= 128) return 128;
-  return 256;
+// rows covered by one workgroup: by the operator's height, and for few tall operators
+// (the top merge levels) at most 64, so that the row blocks (times the K splits below)
+// spread the matrix-core work over the device instead of a few compute units
+int block_rows(const SkinnyDesc& d) {
+  int rows = d.M <= 16 ? 16 : d.M <= 32 ? 32 : d.M <= 64 ? 64 : d.M <= 128 ? 128 : 256;
+  while (rows > 64 && (long)cdiv(d.M, rows) * d.batch < 512) rows /= 2;
+  return rows;
 }
 
 // K is split across workgroups when the row blocks x batch cannot fill the device.
 // Returns the number of splits and the K range per split.
 int split_plan(const SkinnyDesc& d, int* kper_out) {
-  const int tiles = cdiv(d.M, block_rows(d.M));
+  const int tiles = cdiv(d.M, block_rows(d));
   int nsplit = 1;
   const long blocks = (long)tiles * d.batch;
   if (blocks < 1024 && d.K >= 2 * KC) {
@@ -232,7 +232,7 @@ void run_chunk(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
 
 template <class T>
 void run_pass_t(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
-  switch (block_rows(d.M)) {
+  switch (block_rows(d)) {
     case 16: run_chunk<T, 1, 4>(d, r0, nr, st); break;
     case 32: run_chunk<T, 1, 2>(d, r0, nr, st); break;
     case 64: run_chunk<T, 1, 1>(d, r0, nr, st); break;
