@@ -213,9 +213,9 @@ void timed_gemm(Profiler& pr, const char* name, const GemmDesc& g, hipStream_t s
 }
 
 void timed_skinny(Profiler& pr, const char* name, const SkinnyDesc& k, hipStream_t st) {
-  const double fl = 8.0 * k.M * k.K * (double)k.nrhs * k.batch;
-  const double by = (double)k.batch * ((double)k.M * k.K * 16 +
-                                       (double)(k.K + k.M) * k.nrhs * 16);
+  const double nb = k.A2 ? 2.0 * k.batch : k.batch;  // a second operator doubles the work
+  const double fl = 8.0 * k.M * k.K * (double)k.nrhs * nb;
+  const double by = nb * ((double)k.M * k.K * 16 + (double)(k.K + k.M) * k.nrhs * 16);
   Stage s(pr, name, fl, by);
   zgemm_skinny(k, st);
 }
@@ -1064,19 +1064,20 @@ void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const d
       Stage sg(pr, "solve_gather", 0.0, nbox * 2.0 * (P.n1 + P.n2) * nrhs * 16);
       if (!ws.dry) down_scatter(d, nrhs, tp, nbp, tt[l + 1], st);
     }
-    for (int side = 0; side < 2; ++side) {
-      SkinnyDesc k;
-      k.M = n3; k.K = nbp; k.nrhs = nrhs; k.batch = (int)nbox; k.a_c64 = P.c64;
-      k.A = (side ? P.PhiB.d() : P.PhiA.d()) + box0 * n3 * nbp * e;
-      k.lda = n3; k.sA = n3 * nbp;
-      k.X = tp; k.ldx = nbp; k.sX = sp;
-      k.C = tt[l + 1] + 2 * (side ? nbc * nrhs : 0); k.ldc = nbc; k.sC = 2 * nbc * nrhs;
-      k.crow = side ? P.di3b : P.di3a;
-      if (up) {
-        k.C0 = side ? ttb[l] : tta[l]; k.ld0 = n3; k.s0 = n3 * nrhs;
-      }
-      ws.skinny(pr, nm, k);
+    // both children's interface values in one launch: t3 = Phi^a t (+ t~3a) into child
+    // a's slot, Phi^b t (+ t~3b) into child b's
+    SkinnyDesc k;
+    k.M = n3; k.K = nbp; k.nrhs = nrhs; k.batch = (int)nbox; k.a_c64 = P.c64;
+    k.A = P.PhiA.d() + box0 * n3 * nbp * e;
+    k.A2 = P.PhiB.d() + box0 * n3 * nbp * e;
+    k.lda = n3; k.sA = n3 * nbp;
+    k.X = tp; k.ldx = nbp; k.sX = sp;
+    k.C = tt[l + 1]; k.C2 = tt[l + 1] + 2 * nbc * nrhs; k.ldc = nbc; k.sC = 2 * nbc * nrhs;
+    k.crow = P.di3a; k.crow2 = P.di3b;
+    if (up) {
+      k.C0 = tta[l]; k.C02 = ttb[l]; k.ld0 = n3; k.s0 = n3 * nrhs;
     }
+    ws.skinny(pr, nm, k);
   }
   // leaves: u = Psi t + u~   (step (13))
   {

@@ -11,7 +11,8 @@
 // of a workgroup split K and add their partial tiles through LDS in a fixed order.
 // Operators with few rows and a long K (the top merges) are also split along K across
 // workgroups; those partial sums are reduced in a fixed order by a second kernel, so
-// results never depend on scheduling.
+// results never depend on scheduling.  Two operators of one shape applied to the same
+// right-hand sides (the two children's Phi in the downward pass) share a launch.
 //
 // MFMA 16x16x4 lane layouts: lane l supplies A[l%16][l/16] and B[l/16][l%16];
 // accumulator element v of lane l is D[l/16 + 4 v][l%16] (f64) or D[4 (l/16) + v][l%16]
@@ -41,6 +42,9 @@ template <> struct SkMfma<float> {
 constexpr int KC = 64;   // K chunk staged in LDS
 constexpr int NRB = 16;  // right-hand sides per pass (the MFMA's N)
 
+// batch entries of a launch: the second operator's follow the first's
+__host__ __device__ inline int nbatch(const SkinnyDesc& d) { return d.A2 ? 2 * d.batch : d.batch; }
+
 template <class T, int TW, int WK>
 __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int nr, int kper,
                                                      double2* partial) {
@@ -55,11 +59,13 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave % WR, kw = wave / WR;
   const int li = lane & 15, lk = lane >> 4;
-  const long b = blockIdx.y;
+  const long bb = blockIdx.y;  // batch entry of the launch
+  const bool two = d.A2 && bb >= d.batch;
+  const long b = two ? bb - d.batch : bb;  // entry of its operator
   const int ks = blockIdx.z;
   const int kbeg = ks * kper, kend = min(d.K, kbeg + kper);
   const int row0 = blockIdx.x * ROWS + wr * 16 * TW;
-  const C2* A = reinterpret_cast<const C2*>(d.A) + b * d.sA;
+  const C2* A = reinterpret_cast<const C2*>(two ? d.A2 : d.A) + b * d.sA;
   const double2* X =
       reinterpret_cast<const double2*>(d.X) + (d.xoff ? d.xoff[b] - d.xbase : b * d.sX);
 
@@ -123,8 +129,8 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
   const int rhs = li;
   if (rhs >= nr) return;
   if (partial) {
-    // [ks][b][rhs][i]
-    double2* P = partial + (((long)ks * d.batch + b) * NRB + rhs) * d.M;
+    // [ks][bb][rhs][i]
+    double2* P = partial + (((long)ks * nbatch(d) + bb) * NRB + rhs) * d.M;
 #pragma unroll
     for (int t = 0; t < TW; ++t)
 #pragma unroll
@@ -134,17 +140,19 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
       }
     return;
   }
-  double2* C = reinterpret_cast<double2*>(d.C) + (d.coff ? d.coff[b] - d.cbase : b * d.sC);
-  const double2* C0 = d.C0 ? reinterpret_cast<const double2*>(d.C0) +
-                                 (d.c0off ? d.c0off[b] : b * d.s0)
-                           : nullptr;
+  double2* C = reinterpret_cast<double2*>(two ? d.C2 : d.C) +
+               (d.coff ? d.coff[b] - d.cbase : b * d.sC);
+  const double* c0p = two ? d.C02 : d.C0;
+  const double2* C0 =
+      c0p ? reinterpret_cast<const double2*>(c0p) + (d.c0off ? d.c0off[b] : b * d.s0) : nullptr;
+  const int* crow = two ? d.crow2 : d.crow;
 #pragma unroll
   for (int t = 0; t < TW; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = row0 + 16 * t + MF::row(lk, v);
       if (i >= d.M) continue;
-      const long ci = d.crow ? d.crow[i] : i;
+      const long ci = crow ? crow[i] : i;
       double2 val = cmk(d.alpha * accR[t][v], d.alpha * accI[t][v]);
       double2* p = C + ci + d.ldc * (long)(r0 + rhs);
       if (C0) val = cadd(val, C0[i + d.ld0 * (long)(r0 + rhs)]);
@@ -155,22 +163,28 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
 
 __global__ void skinny_reduce_kernel(SkinnyDesc d, int r0, int nr, int nsplit,
                                      const double2* partial) {
-  const long tot = (long)d.batch * d.M * nr;
+  const int nbt = nbatch(d);
+  const long tot = (long)nbt * d.M * nr;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
        e += (long)gridDim.x * blockDim.x) {
     const int i = e % d.M;
     const int r = (e / d.M) % nr;
-    const long b = e / ((long)d.M * nr);
+    const long bb = e / ((long)d.M * nr);
+    const bool two = d.A2 && bb >= d.batch;
+    const long b = two ? bb - d.batch : bb;
     double2 acc = cmk(0, 0);
     for (int s = 0; s < nsplit; ++s)
-      acc = cadd(acc, partial[(((long)s * d.batch + b) * NRB + r) * d.M + i]);
-    double2* C = reinterpret_cast<double2*>(d.C) + (d.coff ? d.coff[b] - d.cbase : b * d.sC);
-    const long ci = d.crow ? d.crow[i] : i;
+      acc = cadd(acc, partial[(((long)s * nbt + bb) * NRB + r) * d.M + i]);
+    double2* C = reinterpret_cast<double2*>(two ? d.C2 : d.C) +
+                 (d.coff ? d.coff[b] - d.cbase : b * d.sC);
+    const int* crow = two ? d.crow2 : d.crow;
+    const long ci = crow ? crow[i] : i;
     double2 v = cscale(acc, d.alpha);
     double2* p = C + ci + d.ldc * (long)(r0 + r);
-    if (d.C0) {
+    const double* c0p = two ? d.C02 : d.C0;
+    if (c0p) {
       const double2* C0 =
-          reinterpret_cast<const double2*>(d.C0) + (d.c0off ? d.c0off[b] : b * d.s0);
+          reinterpret_cast<const double2*>(c0p) + (d.c0off ? d.c0off[b] : b * d.s0);
       v = cadd(v, C0[i + d.ld0 * (long)(r0 + r)]);
     } else if (d.accumulate) {
       v = cadd(v, *p);
@@ -184,7 +198,7 @@ __global__ void skinny_reduce_kernel(SkinnyDesc d, int r0, int nr, int nsplit,
 // spread the matrix-core work over the device instead of a few compute units
 int block_rows(const SkinnyDesc& d) {
   int rows = d.M <= 16 ? 16 : d.M <= 32 ? 32 : d.M <= 64 ? 64 : d.M <= 128 ? 128 : 256;
-  while (rows > 64 && (long)cdiv(d.M, rows) * d.batch < 512) rows /= 2;
+  while (rows > 64 && (long)cdiv(d.M, rows) * nbatch(d) < 512) rows /= 2;
   return rows;
 }
 
@@ -193,7 +207,7 @@ int block_rows(const SkinnyDesc& d) {
 int split_plan(const SkinnyDesc& d, int* kper_out) {
   const int tiles = cdiv(d.M, block_rows(d));
   int nsplit = 1;
-  const long blocks = (long)tiles * d.batch;
+  const long blocks = (long)tiles * nbatch(d);
   if (blocks < 1024 && d.K >= 2 * KC) {
     nsplit = (int)std::min<long>((1024 + blocks - 1) / blocks, (d.K + KC - 1) / KC);
     nsplit = std::max(1, std::min(nsplit, 64));
@@ -214,17 +228,17 @@ void run_chunk(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
   int kper = 0;
   const int nsplit = split_plan(d, &kper);
   if (nsplit == 1) {
-    hipLaunchKernelGGL((skinny_kernel<T, TW, WK>), dim3(tiles, d.batch, 1), dim3(256), 0, st, d,
-                       r0, nr, d.K, (double2*)nullptr);
+    hipLaunchKernelGGL((skinny_kernel<T, TW, WK>), dim3(tiles, nbatch(d), 1), dim3(256), 0, st,
+                       d, r0, nr, d.K, (double2*)nullptr);
     HPS_LAUNCH_CHECK();
     return;
   }
   if (!d.work) throw Error(1, "zgemm_skinny: split-K needs a workspace");
   double2* part = static_cast<double2*>(d.work);
-  hipLaunchKernelGGL((skinny_kernel<T, TW, WK>), dim3(tiles, d.batch, nsplit), dim3(256), 0, st,
-                     d, r0, nr, kper, part);
+  hipLaunchKernelGGL((skinny_kernel<T, TW, WK>), dim3(tiles, nbatch(d), nsplit), dim3(256), 0,
+                     st, d, r0, nr, kper, part);
   HPS_LAUNCH_CHECK();
-  long tot = (long)d.batch * d.M * nr;
+  long tot = (long)nbatch(d) * d.M * nr;
   hipLaunchKernelGGL(skinny_reduce_kernel, dim3(grid1d(tot)), dim3(256), 0, st, d, r0, nr,
                      nsplit, (const double2*)part);
   HPS_LAUNCH_CHECK();
@@ -253,12 +267,13 @@ size_t skinny_work_bytes(const SkinnyDesc& d) {
   int kper = 0;
   const int nsplit = split_plan(d, &kper);
   if (nsplit == 1) return 0;
-  return (size_t)nsplit * d.batch * NRB * d.M * sizeof(double2);
+  return (size_t)nsplit * nbatch(d) * NRB * d.M * sizeof(double2);
 }
 
 void zgemm_skinny(const SkinnyDesc& d, hipStream_t st) {
   if (d.M <= 0 || d.batch <= 0 || d.nrhs <= 0) return;
-  if (d.batch > 65535) throw Error(1, "zgemm_skinny: batch exceeds grid limit");
+  if (nbatch(d) > 65535) throw Error(1, "zgemm_skinny: batch exceeds grid limit");
+  if (d.A2 && !d.C2) throw Error(1, "zgemm_skinny: second operator without output");
   if (d.K <= 0) throw Error(1, "zgemm_skinny: K must be positive");
   for (int r0 = 0; r0 < d.nrhs; r0 += NRB) run_pass(d, r0, std::min(NRB, d.nrhs - r0), st);
 }
