@@ -1776,11 +1776,15 @@ void* ws_take(size_t bytes, hipStream_t st, bool host_wait) {
   HPS_HIP(hipGetDevice(&dev));
   bytes = (std::max<size_t>(bytes, 1) + kWsGrain - 1) / kWsGrain * kWsGrain;
   std::unique_lock<std::mutex> lk(g_ws_mu);
+  // best fit among the idle buffers.  A host-waited request is a long-lived buffer (a
+  // factor's arena, a build's scratch): it takes none much larger than itself, so that a
+  // small factor never holds a large buffer (the largest idle one is released instead)
   long best = -1, largest = -1;
   for (size_t i = 0; i < g_ws.size(); ++i) {
     const WsBuf& b = g_ws[i];
     if (b.busy || b.dev != dev) continue;
-    if (b.cap >= bytes && (best < 0 || b.cap < g_ws[best].cap)) best = (long)i;
+    const bool fits = b.cap >= bytes && (!host_wait || b.cap <= bytes + bytes / 4 + kWsGrain);
+    if (fits && (best < 0 || b.cap < g_ws[best].cap)) best = (long)i;
     if (largest < 0 || b.cap > g_ws[largest].cap) largest = (long)i;
   }
   if (best >= 0) {
