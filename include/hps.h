@@ -296,6 +296,24 @@ int hps_autotune_load(const char* path);
  * after synchronizing the device.  Errors: HPS_E_DEVICE. */
 int hps_release_cached(void);
 
+/* Allocator hook: route the library's device memory (factors, build scratch, solve
+ * workspaces, staging) through the caller's allocator, e.g. a framework's caching
+ * allocator, instead of hipMalloc and the library's buffer cache.
+ *   alloc(bytes, stream, ctx)  returns device memory of at least bytes on the current
+ *       device, usable by work on `stream` (a hipStream_t; NULL for buffers that live
+ *       across calls), or NULL when it has none (the library call then fails with
+ *       HPS_E_NOMEM).
+ *   free(ptr, stream, ctx)  returns ptr.  Work queued on `stream` may still use it: a
+ *       stream-ordered allocator reuses it after that work; for buffers handed out with
+ *       stream NULL the library synchronizes the device first.
+ * Every buffer goes back to the hook that provided it, also after the hook changes.
+ * Both functions NULL restores the library's own allocator; one of them NULL is
+ * HPS_E_INVALID.  Installing a hook releases the idle cached buffers.  The functions
+ * may be called from the request loop's threads.  Errors: HPS_E_INVALID, HPS_E_DEVICE. */
+typedef void* (*hps_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*hps_free_fn)(void* ptr, void* stream, void* ctx);
+int hps_set_allocator(hps_alloc_fn alloc, hps_free_fn free, void* ctx);
+
 /* Device bytes that hps_build of one problem of this shape would use, from the same plan
  * the build lays out (host arithmetic only; nothing is allocated):
  *   build_peak  the most held at once during the build (operators, ItI buffers, scratch)

@@ -11,6 +11,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/hps.h"
@@ -42,6 +43,11 @@ struct DevBuf {
   void alloc(size_t b) {
     release();
     if (b == 0) return;
+    if (void* q = hook_alloc(b, nullptr)) {  // the caller's allocator, when installed
+      p = q;
+      bytes = b;
+      return;
+    }
     if (b >= kCached) {
       p = ws_alloc_idle(b);
       bytes = b;
@@ -58,7 +64,7 @@ struct DevBuf {
     bytes = b;
   }
   void release() {
-    if (p) {
+    if (p && !hook_free(p, nullptr, true)) {
       if (bytes >= kCached) ws_free_idle(p);
       else (void)hipFree(p);
     }
@@ -1707,6 +1713,18 @@ int hps_release_cached(void) {
   });
 }
 
+int hps_set_allocator(hps_alloc_fn alloc, hps_free_fn free, void* ctx) {
+  return guard([&] {
+    if ((alloc == nullptr) != (free == nullptr))
+      throw Error(HPS_E_INVALID, "allocator hook: alloc and free must both be set or both NULL");
+    set_hook(alloc, free, ctx);
+    if (alloc) {
+      HPS_HIP(hipDeviceSynchronize());
+      ws_trim();
+    }
+  });
+}
+
 int hps_estimate_bytes(const hps_domain* dom, int32_t p, const hps_opts* opts,
                        int64_t* build_peak, int64_t* resident) {
   return guard([&] {
@@ -1772,6 +1790,7 @@ namespace {
 // host_wait: the caller's work is not ordered on one stream, so a reused buffer's last
 // use is waited for on the host
 void* ws_take(size_t bytes, hipStream_t st, bool host_wait) {
+  if (void* q = hook_alloc(bytes, host_wait ? nullptr : st)) return q;
   int dev = 0;
   HPS_HIP(hipGetDevice(&dev));
   bytes = (std::max<size_t>(bytes, 1) + kWsGrain - 1) / kWsGrain * kWsGrain;
@@ -1838,7 +1857,7 @@ void* ws_take(size_t bytes, hipStream_t st, bool host_wait) {
 void* ws_alloc_idle(size_t bytes) { return ws_take(bytes, nullptr, true); }
 
 void ws_free_idle(void* p) {
-  if (!p) return;
+  if (!p || hook_free(p, nullptr, true)) return;
   (void)hipDeviceSynchronize();  // every use of the buffer, on any stream, has ended
   std::lock_guard<std::mutex> lk(g_ws_mu);
   for (auto& b : g_ws)
@@ -1850,7 +1869,7 @@ void ws_free_idle(void* p) {
 }
 
 void ws_free(void* p, hipStream_t st) {
-  if (!p) return;
+  if (!p || hook_free(p, st)) return;
   std::lock_guard<std::mutex> lk(g_ws_mu);
   for (auto& b : g_ws)
     if (b.p == p) {
@@ -1877,6 +1896,69 @@ void ws_trim() {
     }
   }
   for (auto& b : drop) ws_release(b);
+}
+
+// ------------------------------------------------------------------ allocator hook
+namespace {
+struct Hook {
+  hps_alloc_fn alloc = nullptr;
+  hps_free_fn free = nullptr;
+  void* ctx = nullptr;
+};
+std::mutex g_hook_mu;
+Hook g_hook;                               // installed hook (alloc == nullptr: none)
+std::unordered_map<void*, Hook> g_hooked;  // live memory from a hook, and which one
+}  // namespace
+
+void set_hook(hps_alloc_fn alloc, hps_free_fn free, void* ctx) {
+  std::lock_guard<std::mutex> lk(g_hook_mu);
+  g_hook = Hook{alloc, free, alloc ? ctx : nullptr};
+}
+
+void* hook_alloc(size_t bytes, hipStream_t st) {
+  Hook h;
+  {
+    std::lock_guard<std::mutex> lk(g_hook_mu);
+    h = g_hook;
+  }
+  if (!h.alloc) return nullptr;
+  void* p = h.alloc(std::max<size_t>(bytes, 1), st, h.ctx);
+  if (!p)
+    throw Error(HPS_E_NOMEM, "allocator hook returned no memory for " + std::to_string(bytes) +
+                                 " bytes");
+  std::lock_guard<std::mutex> lk(g_hook_mu);
+  g_hooked[p] = h;
+  return p;
+}
+
+bool hook_free(void* p, hipStream_t st, bool sync_device) {
+  Hook h;
+  {
+    std::lock_guard<std::mutex> lk(g_hook_mu);
+    auto it = g_hooked.find(p);
+    if (it == g_hooked.end()) return false;
+    h = it->second;
+    g_hooked.erase(it);
+  }
+  if (sync_device) (void)hipDeviceSynchronize();
+  h.free(p, st, h.ctx);
+  return true;
+}
+
+void* dev_alloc(size_t bytes) {
+  if (void* q = hook_alloc(bytes, nullptr)) return q;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 1));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(e == hipErrorOutOfMemory ? HPS_E_NOMEM : HPS_E_DEVICE,
+                "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  return p;
+}
+
+void dev_free(void* p) {
+  if (p && !hook_free(p, nullptr, true)) (void)hipFree(p);
 }
 
 void set_last_error(const std::string& msg) { g_err = msg; }

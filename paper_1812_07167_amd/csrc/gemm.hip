@@ -22,6 +22,7 @@
 #include <mutex>
 
 #include "kernels.hpp"
+#include "serve_hooks.hpp"
 
 namespace hps {
 namespace {
@@ -351,8 +352,7 @@ void zgemm_tune(const GemmDesc& d, hipStream_t st) {
     if (g_tune.count(key)) return;
   }
   const size_t esz = d.c64 ? 8 : 16;
-  void* scratch = nullptr;
-  HPS_HIP(hipMalloc(&scratch, (size_t)d.batch * d.M * d.N * esz));
+  void* scratch = dev_alloc((size_t)d.batch * d.M * d.N * esz);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int best = heuristic_tile(d);
   float best_ms = 0.0f;
@@ -389,12 +389,12 @@ void zgemm_tune(const GemmDesc& d, hipStream_t st) {
   } catch (...) {
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    (void)hipFree(scratch);
+    dev_free(scratch);
     throw;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  (void)hipFree(scratch);
+  dev_free(scratch);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune[key] = best;
 }

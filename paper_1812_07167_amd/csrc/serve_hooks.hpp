@@ -32,6 +32,19 @@ void ws_trim();
 void* ws_alloc_idle(size_t bytes);
 void ws_free_idle(void* p);
 
+// The caller's allocator hook (hps_set_allocator).  hook_alloc returns nullptr when no
+// hook is installed and throws hps::Error when the hook has no memory; hook_free hands p
+// back to the hook that provided it (after synchronizing the device when sync_device is
+// set) and returns false for memory no hook provided.
+void set_hook(hps_alloc_fn alloc, hps_free_fn free, void* ctx);
+void* hook_alloc(size_t bytes, hipStream_t st);
+bool hook_free(void* p, hipStream_t st, bool sync_device = false);
+// Device memory from the hook when one is installed, else hipMalloc; dev_free returns it
+// (hipFree waits for the device; hooked memory is handed back after a device
+// synchronization).  dev_alloc throws hps::Error.
+void* dev_alloc(size_t bytes);
+void dev_free(void* p);
+
 // Message hps_last_error() returns on the calling thread.
 void set_last_error(const std::string& msg);
 

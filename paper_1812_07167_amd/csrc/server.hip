@@ -379,7 +379,7 @@ void slot_main(hps_server* S, int slot) {
     lk.unlock();
     for (const Freed& x : fr) {
       hps_free(x.f);
-      if (x.c) (void)hipFree(x.c);
+      dev_free(x.c);
     }
     const double t_start = S->now();
     int status = HPS_OK;
@@ -557,13 +557,11 @@ int hps_server_submit_build(hps_server* S, const hps_domain* dom, int32_t p, dou
       }
     }
     HPS_HIP(hipSetDevice(S->device));
-    if (hipMalloc(&P->c, P->c_bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      P->c = nullptr;
-      throw Error(HPS_E_NOMEM, "copy of c");
-    }
+    P->c = static_cast<double*>(dev_alloc(P->c_bytes));
     if (hipMemcpy(P->c, c, P->c_bytes, hipMemcpyDeviceToDevice) != hipSuccess) {
-      (void)hipFree(P->c);
+      (void)hipGetLastError();
+      dev_free(P->c);
+      P->c = nullptr;
       throw Error(HPS_E_DEVICE, "copy of c failed");
     }
     {
@@ -690,7 +688,7 @@ void hps_server_destroy(hps_server* S) {
   (void)hipSetDevice(S->device);
   for (auto& kv : S->problems) {
     hps_free(kv.second->f);
-    if (kv.second->c) (void)hipFree(kv.second->c);
+    dev_free(kv.second->c);
   }
   for (hipStream_t st : S->streams) (void)hipStreamDestroy(st);
   delete S;

@@ -24,14 +24,19 @@ EXPORTS = [
     "hps_build_batch", "hps_solve", "hps_solve_batch", "hps_solve_jumps", "hps_residual",
     "hps_last_solve_info", "hps_factor_query",
     "hps_factor_get", "hps_factor_box", "hps_stage_times", "hps_free", "hps_estimate_bytes",
-    "hps_release_cached", "hps_autotune_entries", "hps_autotune_clear", "hps_autotune_save",
-    "hps_autotune_load",
+    "hps_release_cached", "hps_set_allocator", "hps_autotune_entries", "hps_autotune_clear",
+    "hps_autotune_save", "hps_autotune_load",
     "hps_server_default_opts", "hps_server_create", "hps_server_submit_build",
     "hps_server_submit_solve", "hps_server_release", "hps_server_poll", "hps_server_stats",
     "hps_server_destroy",
 ]
 HPS_REQ_BUILD, HPS_REQ_SOLVE = 0, 1
 HPS_PREC_C128, HPS_PREC_MIXED = 0, 1
+
+
+# hps_alloc_fn / hps_free_fn of include/hps.h
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 
 
 class HPSError(RuntimeError):
@@ -127,6 +132,7 @@ def load(path: str = LIB_PATH):
     lib.hps_free.argtypes = [P]
     lib.hps_free.restype = None
     lib.hps_release_cached.argtypes = []
+    lib.hps_set_allocator.argtypes = [ALLOC_FN, FREE_FN, P]
     lib.hps_autotune_entries.argtypes = [C.POINTER(I32)]
     lib.hps_autotune_clear.argtypes = []
     lib.hps_autotune_save.argtypes = [C.c_char_p]
@@ -148,7 +154,8 @@ def load(path: str = LIB_PATH):
     for name in ["hps_nodes", "hps_build", "hps_build_batch", "hps_solve", "hps_solve_batch",
                  "hps_solve_jumps", "hps_residual",
                  "hps_last_solve_info", "hps_factor_query", "hps_factor_get", "hps_factor_box",
-                 "hps_stage_times", "hps_estimate_bytes", "hps_release_cached", "hps_server_create",
+                 "hps_stage_times", "hps_estimate_bytes", "hps_release_cached",
+                 "hps_set_allocator", "hps_server_create",
                  "hps_autotune_entries", "hps_autotune_clear", "hps_autotune_save",
                  "hps_autotune_load",
                  "hps_server_submit_build", "hps_server_submit_solve", "hps_server_release",
@@ -423,6 +430,46 @@ def autotune_load(path):
 def hps_release_cached():
     """Return the library's cached workspace memory on the current device."""
     _check(load().hps_release_cached())
+
+
+_hooks = []  # the installed callbacks (ctypes keeps no reference of its own)
+
+
+def set_allocator(alloc=None, free=None):
+    """Route the library's device memory through alloc(bytes, stream) -> int pointer and
+    free(pointer, stream) (stream: the hipStream_t handle as an int, 0 for buffers that
+    live across calls); with no arguments the library's own allocator returns.  Memory
+    already handed out goes back to whoever provided it."""
+    if (alloc is None) != (free is None):
+        raise ValueError("set_allocator: give both alloc and free, or neither")
+    if alloc is None:
+        _check(load().hps_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        return
+
+    def a(nbytes, stream, ctx):
+        try:
+            return alloc(int(nbytes), int(stream or 0)) or None
+        except Exception:  # an exception cannot cross into C: report no memory
+            return None
+
+    def f(ptr, stream, ctx):
+        try:
+            free(int(ptr), int(stream or 0))
+        except Exception:
+            pass
+
+    cb = (ALLOC_FN(a), FREE_FN(f))
+    _hooks.append(cb)  # kept for as long as memory they handed out may come back
+    _check(load().hps_set_allocator(cb[0], cb[1], None))
+
+
+def use_torch_allocator():
+    """Serve the library's device memory from torch's caching allocator on the current
+    device (stream-ordered on the stream the library names)."""
+    import torch
+    dev = torch.cuda.current_device()
+    set_allocator(lambda n, st: torch.cuda.caching_allocator_alloc(n, dev, st),
+                  lambda ptr, st: torch.cuda.caching_allocator_delete(ptr))
 
 
 def hps_estimate_bytes(dom: Domain, p: int, **opts):

@@ -208,3 +208,15 @@ def test_autotune_table_roundtrip(tmp_path):
         H.autotune_load(tmp_path / "missing.txt")
     H.autotune_clear()
     assert H.autotune_entries() == 0
+
+
+def test_allocator_hook_argument_checks():
+    """Both functions or neither; a half-set hook is refused and changes nothing (host)."""
+    H, lib = _lib()
+    assert lib.hps_set_allocator(H.ALLOC_FN(lambda n, s, c: None), H.FREE_FN(), None) == H.HPS_E_INVALID
+    assert "both" in lib.hps_last_error().decode()
+    assert lib.hps_set_allocator(H.ALLOC_FN(), H.FREE_FN(lambda p, s, c: None), None) == H.HPS_E_INVALID
+    assert lib.hps_set_allocator(H.ALLOC_FN(), H.FREE_FN(), None) == H.HPS_OK
+    with pytest.raises(ValueError):
+        H.set_allocator(lambda n, s: 0)
+    H.set_allocator()
