@@ -6,7 +6,7 @@
 // |re|+|im|; rows are never moved.  After all n steps the in-place matrix M satisfies
 // inv(A)[k][r_j] = M[r_k][j], which the final write-out applies.
 //
-// * n <= SMALL_MAX: one workgroup per matrix, matrix resident in LDS.
+// * n <= SMALL_MAX: one workgroup per matrix, matrix resident in registers.
 // * larger n: blocked right-looking form.  For each block K of PNB (16, 8 or 4) columns a panel
 //   kernel (one workgroup per matrix, panel rows spread over its waves, each row's PNB
 //   panel entries in registers) runs the PNB elimination steps on the panel and emits
@@ -17,84 +17,102 @@
 namespace hps {
 namespace {
 
-constexpr int SMALL_MAX = 96;  // at most 128 (two rows per lane in the small kernel)
+constexpr int SMALL_MAX = 64;  // the small kernel: a row per lane, 4 x 16 columns
 
-// ------------------------------------------------------------------ small (LDS)
-template <class T>
+// ------------------------------------------------------------------ small (registers)
+// n <= SMALL_MAX: one workgroup of 4 waves per matrix, the matrix in registers.  Wave w
+// holds the columns c = w + 4 j (j < NJ) of every row; row i sits in lane i.  For step
+// k the wave that holds column k picks the pivot (the unused row of
+// largest |re| + |im|, a wave reduction) and publishes r and column k through LDS; after
+// one barrier every wave reads the pivot row's values of its own columns from lane r
+// (readlane) and updates its rows:  M[i][c] -= (M[i][k] / p) M[r][c],  the pivot row
+// becomes M[r][c] / p,  and column k becomes -M[i][k] / p (1 / p on the pivot row).
+// Column k and r are double-buffered by the parity of k, so one barrier per step
+// suffices.
+__device__ inline double2 readlane_c(double2 v, int lane) {
+  return make_double2(readlane_f64(v.x, lane), readlane_f64(v.y, lane));
+}
+__device__ inline float2 readlane_c(float2 v, int lane) {
+  return make_float2(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), lane)),
+                     __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), lane)));
+}
+
+template <class T, int NJ>
 __global__ __launch_bounds__(256) void zinv_small_kernel(int n, const double* Ain, long lda,
                                                          long sA, double* Out, long ldo,
                                                          long sO, int* info) {
   typedef typename Cx<T>::t C2;
-  extern __shared__ double sm_raw[];
-  C2* M = reinterpret_cast<C2*>(sm_raw);             // n*n
-  int* piv = reinterpret_cast<int*>(M + n * n);      // n
-  int* ipiv = piv + n;                               // n
-  int* used = ipiv + n;                              // n
-  __shared__ int s_r;
-  __shared__ int s_bad;
+  __shared__ C2 colv[2][64];
+  __shared__ int s_r[2];
+  __shared__ int piv[64], ipiv[64];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const long b = blockIdx.x;
   const C2* A = reinterpret_cast<const C2*>(Ain) + b * sA;
-  for (int e = tid; e < n * n; e += 256) {
-    int i = e % n, j = e / n;
-    M[e] = A[i + lda * j];
-  }
-  for (int i = tid; i < n; i += 256) used[i] = 0;
-  if (tid == 0) s_bad = 0;
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (tid < 64) {
-      double best = -1.0;
-      int bi = n;
-      for (int i = tid; i < n; i += 64) {
-        double v = used[i] ? -1.0 : cabs1(M[i + n * k]);
-        if (v > best) { best = v; bi = i; }
-      }
-      const int r = wave_argmax(best, bi);
-      if (tid == 0) {
-        s_r = r < 0 ? 0 : r;
-        if (r < 0) s_bad = k + 1;
-      }
-    }
-    __syncthreads();
-    if (s_bad) break;
-    const int r = s_r;
-    const C2 ip = crcp(M[r + n * k]);
-    // rows lane, lane + 64 of column group wave, wave + 4, ...  (no index division)
+  const int i = lane;  // this lane's row
+  C2 M[NJ];
+  bool used = i >= n;  // a pivot row already, or beyond n
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int i = lane + 64 * q;
-      if (i >= n || i == r) continue;
-      const C2 f = cmul(M[i + n * k], ip);
-      for (int c = wv; c < n; c += 4) {
-        if (c == k) continue;
-        M[i + n * c] = csub(M[i + n * c], cmul(f, M[r + n * c]));
-      }
-    }
-    __syncthreads();
-    for (int e = tid; e < n; e += 256) {
-      if (e != k) M[r + n * e] = cmul(M[r + n * e], ip);
-      if (e != r) M[e + n * k] = Cx<T>::mk(-(M[e + n * k].x * ip.x - M[e + n * k].y * ip.y),
-                                     -(M[e + n * k].x * ip.y + M[e + n * k].y * ip.x));
-    }
-    if (tid == 0) {
-      M[r + n * k] = ip;
-      used[r] = 1;
-      piv[k] = r;
-    }
-    __syncthreads();
+  for (int j = 0; j < NJ; ++j) {
+    const int c = wv + 4 * j;
+    M[j] = (i < n && c < n) ? A[i + lda * c] : Cx<T>::mk(0, 0);
   }
-  if (s_bad) {
-    if (tid == 0) info[b] = s_bad;
+  // step k = 4 jk + wk: column k is slot jk of wave wk (the slot loop is unrolled so
+  // that every register index is a constant)
+  int bad = 0;
+#pragma unroll
+  for (int jk = 0; jk < NJ; ++jk) {
+#pragma unroll 1
+    for (int wk = 0; wk < 4; ++wk) {
+      const int k = 4 * jk + wk;
+      if (k >= n || bad) break;  // uniform over the workgroup
+      const int sb = k & 1;
+      if (wv == wk) {
+        if (i < n) colv[sb][i] = M[jk];
+        const int r = wave_argmax(used ? -1.0 : (double)cabs1(M[jk]), i);
+        if (lane == 0) s_r[sb] = r;
+      }
+      __syncthreads();
+      const int r = s_r[sb];
+      if (r < 0) {  // no nonzero entry left in column k: singular
+        bad = k + 1;
+        break;
+      }
+      const C2 ip = crcp(colv[sb][r]);
+      // the pivot row's values in this wave's columns, read before this step's updates
+      C2 pr[NJ];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) pr[j] = readlane_c(M[j], r);
+      if (i == r) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) M[j] = cmul(M[j], ip);
+        used = true;
+        if (wv == wk) M[jk] = ip;
+      } else if (i < n) {
+        const C2 f = cmul(colv[sb][i], ip);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) M[j] = csub(M[j], cmul(f, pr[j]));
+        if (wv == wk) M[jk] = Cx<T>::mk(-f.x, -f.y);
+      }
+      if (tid == 0) piv[k] = r;
+    }
+  }
+  if (bad) {
+    if (tid == 0) info[b] = bad;
     return;
   }
+  __syncthreads();
   for (int k = tid; k < n; k += 256) ipiv[piv[k]] = k;
   __syncthreads();
+  // inv[ipiv[i]][piv[c]] = M[i][c]
   C2* O = reinterpret_cast<C2*>(Out) + b * sO;
-  for (int e = tid; e < n * n; e += 256) {
-    int k = e % n, j = e / n;
-    O[k + ldo * j] = M[piv[k] + n * ipiv[j]];
+  if (i < n) {
+    const long oi = ipiv[i];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int c = wv + 4 * j;
+      if (c < n) O[oi + ldo * (long)piv[c]] = M[j];
+    }
   }
 }
 
@@ -372,9 +390,16 @@ void zinv_t(int n, int batch, const double* A, long lda, long sA, double* Out, l
             long sO, int* info, void* work, hipStream_t st) {
   typedef typename Cx<T>::t C2;
   if (n <= SMALL_MAX) {
-    size_t shm = (size_t)n * n * sizeof(C2) + (size_t)n * 12;
-    hipLaunchKernelGGL(zinv_small_kernel<T>, dim3(batch), dim3(256), shm, st, n, A, lda, sA, Out,
-                       ldo, sO, info);
+    // columns per wave: n / 4 rounded up to the instantiated widths
+    if (n <= 16)
+      hipLaunchKernelGGL((zinv_small_kernel<T, 4>), dim3(batch), dim3(256), 0, st, n, A, lda, sA,
+                         Out, ldo, sO, info);
+    else if (n <= 32)
+      hipLaunchKernelGGL((zinv_small_kernel<T, 8>), dim3(batch), dim3(256), 0, st, n, A, lda, sA,
+                         Out, ldo, sO, info);
+    else
+      hipLaunchKernelGGL((zinv_small_kernel<T, 16>), dim3(batch), dim3(256), 0, st, n, A, lda, sA,
+                         Out, ldo, sO, info);
     HPS_LAUNCH_CHECK();
     return;
   }
