@@ -6,9 +6,9 @@
 // as the MFMA operands are read), else from four (Cr += Ar Br - Ai Bi,
 // Ci += Ar Bi + Ai Br); a real operand needs two.  A workgroup of WR x WC
 // waves computes a BM x BN tile of C; K is staged through LDS in chunks of 16, double
-// buffered, with the next chunk's global loads issued before the current chunk's
-// MFMAs.  Large tiles take K in chunks of 8, which halves their LDS footprint so that
-// two workgroups share a compute unit.  LDS rows are padded so that the four 16-lane groups of an MFMA operand read
+// buffered, with each chunk's global loads issued two chunks ahead (two register
+// stages).  Large tiles take K in chunks of 8, which halves their LDS footprint so that
+// two workgroups share a compute unit, with the loads one chunk ahead.  LDS rows are padded so that the four 16-lane groups of an MFMA operand read
 // fall on alternating halves of the 64 banks.  Used by the leaf stage (Sec. 2.1: Psi_i,
 // Y_b, Y_i), by every merge product of Sec. 2.2 (W, Phi^a, Phi^b, R^tau) and by the
 // block updates of the interface inversion.
@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "kernels.hpp"
 #include "serve_hooks.hpp"
@@ -96,9 +97,14 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
 
   constexpr int EA = BM * BK / NT;  // A elements per thread per chunk
   constexpr int EB = BN * BK / NT;
-  T ra[EA][NPA], rb[EB][NPB];
+  // register stages of the global loads: two for the small tiles (a chunk's loads are
+  // issued two chunks before its LDS store), one for the large tiles (whose registers
+  // are taken by their accumulators); the stage index is a constant at every use
+  constexpr int NS = BK == 16 ? 2 : 1;
+  T ra[NS][EA][NPA], rb[NS][EB][NPB];
 
-  auto gload = [&](int k0) {
+  auto gload = [&](auto stage, int k0) {
+    constexpr int S = decltype(stage)::value;
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       const int idx = tid + NT * e;
@@ -107,11 +113,11 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
       const bool ok = gi < d.M && gk < d.K;
       const long off = (long)gi + d.lda * (long)gk;
       if (AR) {
-        ra[e][0] = ok ? A[off] : T(0);
+        ra[S][e][0] = ok ? A[off] : T(0);
       } else {
         const cplx_t v = ok ? reinterpret_cast<const cplx_t*>(A)[off] : MF::mk(0, 0);
-        ra[e][0] = v.x;
-        ra[e][NPA - 1] = v.y;
+        ra[S][e][0] = v.x;
+        ra[S][e][NPA - 1] = v.y;
       }
     }
     // B: each thread reads EB consecutive k of one column (contiguous in memory), and
@@ -124,37 +130,33 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
       const bool ok = gk < d.K && gj < d.N;
       const long off = (long)gk + d.ldb * (long)gj;
       if (BR) {
-        rb[e][0] = ok ? B[off] : T(0);
+        rb[S][e][0] = ok ? B[off] : T(0);
       } else {
         const cplx_t v = ok ? reinterpret_cast<const cplx_t*>(B)[off] : MF::mk(0, 0);
-        rb[e][0] = v.x;
-        rb[e][NPB - 1] = v.y;
+        rb[S][e][0] = v.x;
+        rb[S][e][NPB - 1] = v.y;
       }
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](auto stage, int buf) {
+    constexpr int S = decltype(stage)::value;
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       const int idx = tid + NT * e;
       const int i = idx % BM, k = idx / BM;
 #pragma unroll
-      for (int pl = 0; pl < NPA; ++pl) As[buf][pl][k][i] = ra[e][pl];
+      for (int pl = 0; pl < NPA; ++pl) As[buf][pl][k][i] = ra[S][e][pl];
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const int j = tid % BN, k = (tid / BN) * EB + e;
 #pragma unroll
-      for (int pl = 0; pl < NPB; ++pl) Bs[buf][pl][k][j] = rb[e][pl];
+      for (int pl = 0; pl < NPB; ++pl) Bs[buf][pl][k][j] = rb[S][e][pl];
     }
   };
 
-  const int nk = (d.K + BK - 1) / BK;
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int kc = 0; kc < nk; ++kc) {
-    const int buf = kc & 1;
-    if (kc + 1 < nk) gload((kc + 1) * BK);
+  // the MFMAs of one K chunk, from LDS buffer buf
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kl = kk + (lane >> 4);
@@ -197,8 +199,43 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
           }
       }
     }
-    if (kc + 1 < nk) sstore(buf ^ 1);
+  };
+
+  constexpr std::integral_constant<int, 0> s0{};
+  constexpr std::integral_constant<int, NS - 1> s1{};
+  const int nk = (d.K + BK - 1) / BK;
+  if constexpr (NS == 2) {
+    // Chunk c lives in register stage c % 2 and LDS buffer c % 2.  Its global loads are
+    // issued while chunk c - 2 is computed; it is stored to LDS after chunk c - 1 is.
+    gload(s0, 0);
+    if (nk > 1) gload(s1, BK);
+    sstore(s0, 0);
     __syncthreads();
+    for (int kc = 0; kc < nk; kc += 2) {
+      // even chunk kc (buffer 0); stage 1 holds chunk kc + 1
+      if (kc + 2 < nk) gload(s0, (kc + 2) * BK);
+      compute(0);
+      if (kc + 1 < nk) sstore(s1, 1);
+      __syncthreads();
+      if (kc + 1 >= nk) break;
+      // odd chunk kc + 1 (buffer 1); stage 0 holds chunk kc + 2
+      if (kc + 3 < nk) gload(s1, (kc + 3) * BK);
+      compute(1);
+      if (kc + 2 < nk) sstore(s0, 0);
+      __syncthreads();
+    }
+  } else {
+    // chunk c + 1's global loads are issued before chunk c's MFMAs
+    gload(s0, 0);
+    sstore(s0, 0);
+    __syncthreads();
+    for (int kc = 0; kc < nk; ++kc) {
+      const int buf = kc & 1;
+      if (kc + 1 < nk) gload(s0, (kc + 1) * BK);
+      compute(buf);
+      if (kc + 1 < nk) sstore(s0, buf ^ 1);
+      __syncthreads();
+    }
   }
 
   if constexpr (M3) {
