@@ -293,7 +293,9 @@ int hps_autotune_load(const char* path);
 /* Solve workspaces and staging come from a cache of device buffers that the library
  * keeps per device; a buffer freed by a finished call stays allocated for the next call
  * (reuse is ordered after the previous use with an event).  This frees the idle ones
- * after synchronizing the device.  Errors: HPS_E_DEVICE. */
+ * after synchronizing the device, and drops the cached plans (tree and index maps of a
+ * factor shape, reused by later builds of that shape) that no factor uses.
+ * Errors: HPS_E_DEVICE. */
 int hps_release_cached(void);
 
 /* Allocator hook: route the library's device memory (factors, build scratch, solve
@@ -307,6 +309,9 @@ int hps_release_cached(void);
  *       stream-ordered allocator reuses it after that work; for buffers handed out with
  *       stream NULL the library synchronizes the device first.
  * Every buffer goes back to the hook that provided it, also after the hook changes.
+ * The index maps of a plan are shared by every factor of one shape (device, leaf grid,
+ * p, problem count) and come from the allocator that was active when the shape was
+ * first planned; hps_release_cached drops the cached plans no factor uses.
  * Both functions NULL restores the library's own allocator; one of them NULL is
  * HPS_E_INVALID.  Installing a hook releases the idle cached buffers.  The functions
  * may be called from the request loop's threads.  Errors: HPS_E_INVALID, HPS_E_DEVICE. */

@@ -7,10 +7,12 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -147,6 +149,31 @@ struct LevelPlan {
 
 struct Geo { int ix0, iy0, wx, wy; };
 
+// The part of a plan that depends only on the device, the leaf grid, p and the number of
+// problems of a group: the tree, each level's sizes and index maps (host and device),
+// and the device leaf maps.  Shared, read-only, by every group of that shape.
+struct PlanShape {
+  int L = 0;
+  std::vector<std::vector<Geo>> geo;
+  std::vector<int> nbl;
+  std::vector<LevelPlan> lv;  // sizes, maps and their device copies (no operator views)
+  DevBuf dleaf_grid, dxoff, duoff;
+  size_t bytes = 0;           // device bytes of the maps
+};
+// The plan cache.  It lives until the process ends and is never destroyed (its device
+// memory must not be freed during static destruction, when the runtime may be gone).
+typedef std::tuple<int, int, int, int, int> PlanKey;  // device, nx, ny, p, problems
+struct PlanCache {
+  std::mutex mu;
+  std::map<PlanKey, std::shared_ptr<const PlanShape>> shapes;
+  std::deque<PlanKey> order;  // oldest first
+};
+PlanCache& plan_cache() {
+  static PlanCache* c = new PlanCache;
+  return *c;
+}
+constexpr size_t kPlanCache = 32;
+
 // ------------------------------------------------------------------ stage timers
 // HIP events around kernel groups on the factor's stream (opts.profile = 1).  The
 // flops/bytes attached to a record are the algorithmic work of the launches it covers.
@@ -252,7 +279,13 @@ struct hps_group {
   std::vector<std::vector<hps::Geo>> geo;  // per level, tree order
   std::vector<hps::LevelPlan> lv;          // merges producing level l (l = 0..L-1)
   std::vector<int> leaf_grid;              // tree-ordered leaf -> grid index
-  hps::DevBuf dleaf_grid, dxoff, duoff, dD, dLT;
+  // the tree and index maps, shared by every group of the same shape (plan cache), and
+  // the device copies of the leaf maps it holds
+  std::shared_ptr<const hps::PlanShape> shape;
+  const int* pleaf_grid = nullptr;  // tree-ordered leaf -> grid index
+  const long* pxoff = nullptr;      // leaf -> offset of its interior nodes in s
+  const long* puoff = nullptr;      // leaf -> offset of its nodes in u
+  hps::DevBuf dD, dLT;
   hps::DevBuf ops;                         // arena: [Psi | Y] of every leaf + merge operators
   hps::View BI;                            // [nleaf][n*n] complex128 [Psi | Y] (complex128
                                            // precision only)
@@ -267,10 +300,9 @@ struct hps_group {
   hps::DevBuf dc;                          // c at the interior nodes (for the FP64 residual)
   hps_solve_info last_info{};              // of the most recent solve
   size_t bytes() const {
-    size_t t = ops.bytes + dleaf_grid.bytes + dxoff.bytes + duoff.bytes + dD.bytes + dLT.bytes +
-               rbuf[0].bytes + rbuf[1].bytes + dc.bytes;
+    size_t t = ops.bytes + (shape ? shape->bytes : 0) + dD.bytes + dLT.bytes + rbuf[0].bytes +
+               rbuf[1].bytes + dc.bytes;
     for (auto& r : rkeep) t += r.bytes;
-    for (auto& l : lv) t += l.dmaps.bytes;
     return t + dprm.bytes;
   }
 };
@@ -521,13 +553,35 @@ void leaf_table_one(const hps_group& f, const double* all, double er, double ei,
   }
 }
 
-void upload_plan(hps_group& f) {
-  for (auto& P : f.lv) {
+// The shape part of a plan (hps::PlanShape): make_plan's tree and maps, uploaded once
+// per device, leaf grid, p and problem count, and shared by every group of that shape
+// (a build of a shape seen before skips planning and these uploads).
+std::shared_ptr<const PlanShape> plan_for(const hps_group& f) {
+  int dev = 0;
+  HPS_HIP(hipGetDevice(&dev));
+  const PlanKey key = std::make_tuple(dev, f.nx, f.ny, f.p, f.nprob);
+  PlanCache& pc = plan_cache();
+  {
+    std::lock_guard<std::mutex> lk(pc.mu);
+    auto it = pc.shapes.find(key);
+    if (it != pc.shapes.end()) return it->second;
+  }
+  hps_group t;  // planned on the side; only the shape is kept
+  t.p = f.p; t.m = f.m; t.n = f.n; t.nb = f.nb; t.ni = f.ni;
+  t.nx = f.nx; t.ny = f.ny; t.nprob = f.nprob; t.nl1 = f.nl1; t.nleaf = f.nleaf;
+  make_plan(t);
+  auto sh = std::make_shared<PlanShape>();
+  sh->L = t.L;
+  sh->geo = std::move(t.geo);
+  sh->nbl = std::move(t.nbl);
+  sh->lv = std::move(t.lv);
+  for (auto& P : sh->lv) {
     std::vector<int> all;
     auto app = [&](const std::vector<int>& v) { all.insert(all.end(), v.begin(), v.end()); };
     app(P.codeA); app(P.codeB); app(P.perm); app(P.i1a); app(P.i3a); app(P.i2b); app(P.i3b);
     app(P.ja); app(P.jb);
     upload(P.dmaps, all);
+    sh->bytes += P.dmaps.bytes;
     const int* base = P.dmaps.i();
     P.dcodeA = base; base += P.codeA.size();
     P.dcodeB = base; base += P.codeB.size();
@@ -539,14 +593,62 @@ void upload_plan(hps_group& f) {
     P.dja = base; base += P.ja.size();
     P.djb = base;
   }
-  upload(f.dleaf_grid, f.leaf_grid);
+  upload(sh->dleaf_grid, t.leaf_grid);
   std::vector<long> xoff(f.nleaf), uoff(f.nleaf);
   for (int h = 0; h < f.nleaf; ++h) {
-    xoff[h] = (long)f.leaf_grid[h] * f.ni;
-    uoff[h] = (long)f.leaf_grid[h] * f.n;
+    xoff[h] = (long)t.leaf_grid[h] * f.ni;
+    uoff[h] = (long)t.leaf_grid[h] * f.n;
   }
-  upload(f.dxoff, xoff);
-  upload(f.duoff, uoff);
+  upload(sh->dxoff, xoff);
+  upload(sh->duoff, uoff);
+  sh->bytes += sh->dleaf_grid.bytes + sh->dxoff.bytes + sh->duoff.bytes;
+  std::lock_guard<std::mutex> lk(pc.mu);
+  auto ins = pc.shapes.emplace(key, sh);
+  if (!ins.second) return ins.first->second;  // another thread planned it meanwhile
+  pc.order.push_back(key);
+  while (pc.order.size() > kPlanCache) {  // groups hold their shape alive themselves
+    pc.shapes.erase(pc.order.front());
+    pc.order.pop_front();
+  }
+  return sh;
+}
+
+// Forget the cached plans (a factor keeps its own shape alive).
+void drop_plans() {
+  PlanCache& pc = plan_cache();
+  std::map<PlanKey, std::shared_ptr<const PlanShape>> gone;
+  {
+    std::lock_guard<std::mutex> lk(pc.mu);
+    gone.swap(pc.shapes);
+    pc.order.clear();
+  }
+}  // the unused shapes are freed here, outside the lock
+
+// A group takes its shape's tree and level sizes, and device pointers into its maps.
+void attach_plan(hps_group& f, std::shared_ptr<const PlanShape> sh) {
+  f.L = sh->L;
+  f.geo = sh->geo;
+  f.nbl = sh->nbl;
+  f.lv.clear();
+  f.lv.resize(sh->lv.size());
+  for (size_t l = 0; l < sh->lv.size(); ++l) {
+    const LevelPlan& S = sh->lv[l];
+    LevelPlan& P = f.lv[l];
+    P.nbox = S.nbox; P.wx = S.wx; P.wy = S.wy; P.split_x = S.split_x;
+    P.nbc = S.nbc; P.nbp = S.nbp; P.n1 = S.n1; P.n2 = S.n2; P.n3 = S.n3;
+    P.dcodeA = S.dcodeA; P.dcodeB = S.dcodeB; P.dperm = S.dperm;
+    P.di1a = S.di1a; P.di3a = S.di3a; P.di2b = S.di2b; P.di3b = S.di3b;
+    P.dja = S.dja; P.djb = S.djb;
+  }
+  f.pleaf_grid = sh->dleaf_grid.i();
+  f.pxoff = sh->dxoff.l();
+  f.puoff = sh->duoff.l();
+  f.shape = std::move(sh);
+}
+
+// The per-group tables: the scaled differentiation matrices (they depend on the leaf
+// size), the line tables of the leaf stage and the problems' kappa and eta.
+void upload_tables(hps_group& f) {
   std::vector<double> x, D;
   cheb(f.p, x, D);
   const int p = f.p;
@@ -745,7 +847,7 @@ void build_leaves(hps_group& f, const double* c, BuildScratch& sc) {
   const long n = f.n, nb = f.nb, ni = f.ni;
   LeafDesc d;
   d.p = f.p; d.nleaf = f.nleaf; d.nl1 = f.nl1; d.prm = f.dprm.d();
-  d.c = c; d.leaf_grid = f.dleaf_grid.i(); d.tab = f.dLT.d();
+  d.c = c; d.leaf_grid = f.pleaf_grid; d.tab = f.dLT.d();
   d.R = f.R[f.L].d(); d.info = sc.info.i();
   // scratch per chunk: the inverse's per-leaf copies, then (mixed precision) the
   // complex128 Y_i blocks of the chunk's [Psi | Y], which the Psi / boundary-row kernel
@@ -985,7 +1087,7 @@ void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const d
       k.M = n; k.K = ni; k.nrhs = nrhs; k.batch = (int)nl;
       k.A = leafops + le * n * nb; k.a_c64 = f.mixed;
       k.lda = n; k.sA = n * n;
-      k.X = s; k.ldx = nl * ni; k.xoff = f.dxoff.l() + h0; k.xbase = h0 * ni;
+      k.X = s; k.ldx = nl * ni; k.xoff = f.pxoff + h0; k.xbase = h0 * ni;
       k.C = ut; k.ldc = n; k.sC = n * nrhs;
       ws.skinny(pr, nm, k);
       Stage sg(pr, "solve_gather", 0.0, nl * nb * nrhs * 32.0);
@@ -1092,7 +1194,7 @@ void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const d
     k.M = n; k.K = nb; k.nrhs = nrhs; k.batch = (int)nl; k.a_c64 = f.mixed;
     k.A = leafops; k.lda = n; k.sA = n * n;
     k.X = (f.L == 0) ? t : tt[f.L]; k.ldx = nb; k.sX = nb * nrhs;
-    k.C = u; k.ldc = nl * n; k.coff = f.duoff.l() + h0; k.cbase = h0 * n;
+    k.C = u; k.ldc = nl * n; k.coff = f.puoff + h0; k.cbase = h0 * n;
     if (up) {
       k.C0 = ut; k.ld0 = n; k.s0 = n * nrhs;
     }
@@ -1232,12 +1334,12 @@ std::shared_ptr<hps_group> build_group(const hps_domain& dom, int p, int nprob,
     f->prm_h[4 * b + 2] = ei[b];
   }
   f->stream = static_cast<hipStream_t>(f->opts.stream);
-  make_plan(*f);
+  attach_plan(*f, plan_for(*f));
   for (int l = 0; l < f->L; ++l) {
     f->lv[l].c64 = f->mixed;
     f->lv[l].inv64 = f->mixed && l < f->opts.fp64_top_levels;
   }
-  upload_plan(*f);
+  upload_tables(*f);
   // the group's own copy of c (problem-major), read by the leaf stage and the residual
   const size_t per = (size_t)f->nl1 * f->ni * sizeof(double);
   f->dc.alloc(per * nprob);
@@ -1710,6 +1812,7 @@ int hps_release_cached(void) {
   return guard([&] {
     HPS_HIP(hipDeviceSynchronize());
     ws_trim();
+    drop_plans();
   });
 }
 

@@ -60,7 +60,9 @@ def test_build_and_solve_through_torch_allocator():
         held = torch.cuda.memory_allocated() - base
         u1 = _solve(case, f1)
         assert hook.allocs > 0 and 0 in hook.streams  # long-lived buffers: stream NULL
-        assert bytes0 <= held <= bytes0 + (64 << 20), (held, bytes0)
+        # the factor's own buffers; the index maps of its shape are shared with the
+        # earlier build of the same shape (plan cache) and were allocated then
+        assert bytes0 - (1 << 20) <= held <= bytes0 + (64 << 20), (held, bytes0)
         f1.free()
         torch.cuda.synchronize()
         assert not hook.live, "buffers not returned: %d" % len(hook.live)
