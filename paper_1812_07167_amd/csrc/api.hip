@@ -913,9 +913,7 @@ void build_level(hps_group& f, int l, BuildScratch& sc) {
   {
     const double nbc = P.nbc;
     Stage s(f.build_prof, ename.c_str(), 0.0,
-            nbox * (2.0 * nbc * nbc * 16 + (form_R ? nbp * nbp * 16.0 : 0.0) +
-                    2.0 * n3 * nbp * 16 + n3 * n3 * 16.0));
-    if (form_R) fill_zero(d.Rp, (long)(2 * ez * nbox * nbp * nbp), st);
+            nbox * (2.0 * nbc * nbc * 16 + 2.0 * n3 * nbp * 16 + n3 * n3 * 16.0));
     fill_zero(d.PhiB, (long)(2 * ez * nbox * n3 * nbp), st);
     merge_extract(d, st);
     // W = I - R33b R33a   (into the Winv buffer, inverted in place below)
@@ -973,21 +971,28 @@ void build_level(hps_group& f, int l, BuildScratch& sc) {
   g.c64 = P.c64;
   timed_gemm(f.build_prof, gname, g, st, f.opts.autotune != 0);
   if (form_R) {
-    // R^tau = blockdiag(R11a, R22b) + blockdiag(R13a, R23b) [Phi^a; Phi^b]   (eq. (out))
+    // R^tau = blockdiag(R11a, R22b) + blockdiag(R13a, R23b) [Phi^a; Phi^b]   (eq. (out)):
+    // the two products write every row (I1, then I2) and column of R^tau, then the
+    // children's diagonal blocks are added
     g = GemmDesc();
     g.M = n1; g.N = nbp; g.K = n3; g.batch = nbox;
     g.A = P.R13a.d(); g.lda = n1; g.sA = n1 * n3;
     g.B = P.PhiA.d(); g.ldb = n3; g.sB = n3 * nbp;
     g.C = f.R[l].d(); g.ldc = nbp; g.sC = nbp * nbp; g.crow = P.dperm;
-    g.alpha = 1.0; g.beta = 1.0;
+    g.alpha = 1.0; g.beta = 0.0;
     g.c64 = P.c64;
-  timed_gemm(f.build_prof, gname, g, st, f.opts.autotune != 0);
+    timed_gemm(f.build_prof, gname, g, st, f.opts.autotune != 0);
     g.M = n2;
     g.A = P.R23b.d(); g.lda = n2; g.sA = n2 * n3;
     g.B = P.PhiB.d();
     g.crow = P.dperm + n1;
     g.c64 = P.c64;
-  timed_gemm(f.build_prof, gname, g, st, f.opts.autotune != 0);
+    timed_gemm(f.build_prof, gname, g, st, f.opts.autotune != 0);
+    {
+      Stage s(f.build_prof, ename.c_str(), 0.0,
+              nbox * ((double)n1 * n1 + (double)n2 * n2) * (16.0 + 2.0 * 16.0 * ez));
+      merge_add_diag(d, st);
+    }
     f.R_valid[l] = 1;
   }
   // children's R: overwritten two levels up (ping-pong) unless every R is kept

@@ -131,6 +131,8 @@ void to_c64(const double* src, float* dst, long n, hipStream_t st);
 // dst[i] = (double)src[i], i < n
 void to_c128(const float* src, double* dst, long n, hipStream_t st);
 void merge_extract(const MergeLevelDesc& d, hipStream_t st);
+// parent R (written whole by the R^tau products) += blockdiag(R11^a, R22^b)
+void merge_add_diag(const MergeLevelDesc& d, hipStream_t st);
 
 // ------------------------------------------------------------------ solve helpers
 // h_b = -2 i eta * u_b[0:nb]  for every leaf (u_b is n x nrhs, h_b is nb x nrhs); eta of

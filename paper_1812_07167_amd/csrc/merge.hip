@@ -6,8 +6,10 @@
 // position as I1/I2 (exterior) or I3 (shared) with its index inside that set, and
 // perm maps the parent's boundary [I1; I2] (the order Sec. 2.2 gives it) to the
 // parent's canonical order.  The extract kernel reads each child R once and writes
-// the blocks R33, R31, R13 (alpha), R33, R32, R23 (beta) and the diagonal blocks
-// R11, R22 straight into the parent R (pre-zeroed), so no block is copied twice.
+// the blocks R33, R31, R13 (alpha), R33, R32, R23 (beta) that the merge products take.
+// The parent R is written whole by the two products blockdiag(R13, R23) [Phi^a; Phi^b]
+// (rows I1, then I2, every column), after which the diagonal blocks R11 and R22 are
+// added from the children in place (eq. (out)), so the parent R needs no zero fill.
 #include "kernels.hpp"
 
 namespace hps {
@@ -72,8 +74,6 @@ __global__ void extract_kernel(MergeLevelDesc d) {
       reinterpret_cast<Cp*>(d.PhiB)[q * n3 * nbp + ki + (long)n3 * d.perm[kj]] = nv;
     } else if (ti == 0 && tj == 1) {
       reinterpret_cast<Cp*>(d.R13a)[q * n1 * n3 + ki + (long)n1 * kj] = v;
-    } else if (d.Rp) {
-      reinterpret_cast<Cp*>(d.Rp)[q * nbp * nbp + d.perm[ki] + (long)nbp * d.perm[kj]] = v;
     }
   } else {
     const int ci = d.codeB[i], cj = d.codeB[j];
@@ -84,11 +84,32 @@ __global__ void extract_kernel(MergeLevelDesc d) {
       reinterpret_cast<Cp*>(d.T)[q * n3 * nbp + ki + (long)n3 * d.perm[n1 + kj]] = nv;
     } else if (ti == 0 && tj == 1) {
       reinterpret_cast<Cp*>(d.R23b)[q * n2 * n3 + ki + (long)n2 * kj] = v;
-    } else if (d.Rp) {
-      reinterpret_cast<Cp*>(d.Rp)[q * nbp * nbp + d.perm[n1 + ki] + (long)nbp * d.perm[n1 + kj]] =
-          v;
     }
   }
+}
+
+// Parent R += blockdiag(R11^a, R22^b) in canonical order: entry (i, j) of I1 x I1 comes
+// from alpha's R at (i1a[i], i1a[j]), of I2 x I2 from beta's at (i2b[i], i2b[j]).
+template <class Tc, class Tp>
+__global__ void add_diag_kernel(MergeLevelDesc d) {
+  typedef typename Cx<Tc>::t Cc;
+  typedef typename Cx<Tp>::t Cp;
+  const long q = blockIdx.y;
+  const int side = blockIdx.z;
+  const int nk = side ? d.n2 : d.n1;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)nk * nk) return;
+  const int i = e % nk, j = e / nk;
+  const long nn = (long)d.nbc * d.nbc;
+  const Cc* R = reinterpret_cast<const Cc*>(d.Rc) + (2 * q + side) * nn;
+  const int* pos = side ? d.i2b : d.i1a;
+  const int* pm = d.perm + (side ? d.n1 : 0);
+  const Cc w = R[pos[i] + (long)d.nbc * pos[j]];
+  Cp* P = reinterpret_cast<Cp*>(d.Rp) + q * (long)d.nbp * d.nbp + pm[i] + (long)d.nbp * pm[j];
+  Cp v = *P;
+  v.x += (Tp)w.x;
+  v.y += (Tp)w.y;
+  *P = v;
 }
 
 __global__ void leaf_h_kernel(int nleaf, int n, int nb, int nrhs, const double* prm, int nl1,
@@ -203,6 +224,20 @@ void merge_extract(const MergeLevelDesc& d, hipStream_t st) {
     hipLaunchKernelGGL((extract_kernel<float, double>), grid, dim3(256), 0, st, d);
   else
     hipLaunchKernelGGL((extract_kernel<double, double>), grid, dim3(256), 0, st, d);
+  HPS_LAUNCH_CHECK();
+}
+
+void merge_add_diag(const MergeLevelDesc& d, hipStream_t st) {
+  const long nk = std::max(d.n1, d.n2);
+  const dim3 grid(cdiv(nk * nk, 256), d.nbox, 2);
+  if (d.child_c64 && d.c64)
+    hipLaunchKernelGGL((add_diag_kernel<float, float>), grid, dim3(256), 0, st, d);
+  else if (d.c64)
+    hipLaunchKernelGGL((add_diag_kernel<double, float>), grid, dim3(256), 0, st, d);
+  else if (d.child_c64)
+    hipLaunchKernelGGL((add_diag_kernel<float, double>), grid, dim3(256), 0, st, d);
+  else
+    hipLaunchKernelGGL((add_diag_kernel<double, double>), grid, dim3(256), 0, st, d);
   HPS_LAUNCH_CHECK();
 }
 
