@@ -54,8 +54,10 @@ def test_leaf_operators(nx, ny, p):
 # ---------------------------------------------------------------- merge operators (Sec. 2.2)
 
 
+# interface sizes n3: (4,4,8) 6..24; (8,8,5) 3..24; (8,8,11) 9, 18, 36, 72 (every width of
+# the register-resident inverse, and the blocked one with a ragged last panel)
 @pytest.mark.parametrize("nx,ny,p,kappa", [(4, 4, 8, 20.0), (4, 2, 6, 9.0), (2, 4, 10, 14.0),
-                                           (8, 8, 5, 30.0)])
+                                           (8, 8, 5, 30.0), (8, 8, 11, 22.0)])
 def test_merge_operators_every_level(nx, ny, p, kappa):
     from paper_1812_07167_amd import hps as H
     _say("merge operators", nx, ny, p)
