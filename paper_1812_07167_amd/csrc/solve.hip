@@ -4,11 +4,15 @@
 // This is HBM-bound: every operator entry is read once per call and used for all (up to
 // 16) right-hand sides of a pass.  The product runs on the FP64 matrix cores: a wave
 // owns TW tiles of 16 rows, the 16 right-hand sides are the 16 columns of the MFMA's B
-// operand, and a complex product is four real v_mfma_f64_16x16x4f64.  The right-hand
-// side block is staged through LDS in chunks of KC rows (each lane reads one complex
-// value per 4-deep k step, so there are no broadcast reads); operator entries go from
-// global memory straight into the A operand registers.  For short operators the waves
-// of a workgroup split K and add their partial tiles through LDS in a fixed order.
+// operand.  The right-hand side block is staged through LDS in chunks of KC rows (each
+// lane reads one complex value per 4-deep k step, so there are no broadcast reads);
+// operator entries go from global memory straight into the A operand registers.  A
+// complex product takes three real MFMAs in the narrow variants (the 3M method: ArXr,
+// AiXi and (Ar + Ai)(Xr + Xi), folded into the real and imaginary parts after the K
+// loop), four in the widest (TW = 4, the leaf sweeps), whose occupancy the third
+// accumulator would lower.  For
+// short operators the waves of a workgroup split K and add their partial tiles through
+// LDS in a fixed order.
 // Operators with few rows and a long K (the top merges) are also split along K across
 // workgroups; those partial sums are reduced in a fixed order by a second kernel, so
 // results never depend on scheduling.  Two operators of one shape applied to the same
@@ -74,11 +78,14 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
 #pragma unroll
   for (int t = 0; t < TW; ++t) arow[t] = min(row0 + 16 * t + li, d.M - 1);
 
-  acc_t accR[TW], accI[TW];
+  // 3M: accR, accX, accI hold ArXr, AiXi, (Ar + Ai)(Xr + Xi) until after the K loop
+  constexpr bool M3 = TW <= 2;
+  acc_t accR[TW], accI[TW], accX[M3 ? TW : 1];
 #pragma unroll
   for (int t = 0; t < TW; ++t) {
     accR[t] = acc_t{0, 0, 0, 0};
     accI[t] = acc_t{0, 0, 0, 0};
+    if (M3) accX[M3 ? t : 0] = acc_t{0, 0, 0, 0};
   }
   for (int k0 = kbeg; k0 < kend; k0 += KC) {
     const int kc = min(KC, kend - k0);
@@ -96,15 +103,32 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
       // k past the chunk meets a zero right-hand side; clamp its address into A
       const long kg = min(k0 + kl, d.K - 1);
       const C2 bx = Xs[kl][li];
+      const T bs = bx.x + bx.y;
 #pragma unroll
       for (int t = 0; t < TW; ++t) {
         const C2 a = A[arow[t] + d.lda * kg];
-        accR[t] = MF::op(a.x, bx.x, accR[t]);
-        accR[t] = MF::op(-a.y, bx.y, accR[t]);
-        accI[t] = MF::op(a.x, bx.y, accI[t]);
-        accI[t] = MF::op(a.y, bx.x, accI[t]);
+        if constexpr (M3) {
+          accR[t] = MF::op(a.x, bx.x, accR[t]);
+          accX[M3 ? t : 0] = MF::op(a.y, bx.y, accX[M3 ? t : 0]);
+          accI[t] = MF::op(a.x + a.y, bs, accI[t]);
+        } else {
+          accR[t] = MF::op(a.x, bx.x, accR[t]);
+          accR[t] = MF::op(-a.y, bx.y, accR[t]);
+          accI[t] = MF::op(a.x, bx.y, accI[t]);
+          accI[t] = MF::op(a.y, bx.x, accI[t]);
+        }
       }
     }
+  }
+  if constexpr (M3) {
+#pragma unroll
+    for (int t = 0; t < TW; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const T t1 = accR[t][v], t2 = accX[M3 ? t : 0][v];
+        accR[t][v] = t1 - t2;
+        accI[t][v] = accI[t][v] - t1 - t2;
+      }
   }
   if (WK > 1) {
     // waves kw > 0 hand their tiles to the kw = 0 wave of their row group
