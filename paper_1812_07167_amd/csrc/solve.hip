@@ -7,10 +7,10 @@
 // operand.  The right-hand side block is staged through LDS in chunks of KC rows (each
 // lane reads one complex value per 4-deep k step, so there are no broadcast reads);
 // operator entries go from global memory straight into the A operand registers.  A
-// complex product takes three real MFMAs in the narrow variants (the 3M method: ArXr,
-// AiXi and (Ar + Ai)(Xr + Xi), folded into the real and imaginary parts after the K
-// loop), four in the widest (TW = 4, the leaf sweeps), whose occupancy the third
-// accumulator would lower.  For
+// complex product takes three real MFMAs (the 3M method: ArXr, AiXi and
+// (Ar + Ai)(Xr + Xi), folded into the real and imaginary parts after the K loop).  A
+// workgroup covers at most 128 rows (TW <= 2); registers then allow at least four waves
+// per SIMD.  For
 // short operators the waves of a workgroup split K and add their partial tiles through
 // LDS in a fixed order.
 // Operators with few rows and a long K (the top merges) are also split along K across
@@ -79,13 +79,12 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
   for (int t = 0; t < TW; ++t) arow[t] = min(row0 + 16 * t + li, d.M - 1);
 
   // 3M: accR, accX, accI hold ArXr, AiXi, (Ar + Ai)(Xr + Xi) until after the K loop
-  constexpr bool M3 = TW <= 2;
-  acc_t accR[TW], accI[TW], accX[M3 ? TW : 1];
+  acc_t accR[TW], accI[TW], accX[TW];
 #pragma unroll
   for (int t = 0; t < TW; ++t) {
     accR[t] = acc_t{0, 0, 0, 0};
     accI[t] = acc_t{0, 0, 0, 0};
-    if (M3) accX[M3 ? t : 0] = acc_t{0, 0, 0, 0};
+    accX[t] = acc_t{0, 0, 0, 0};
   }
   for (int k0 = kbeg; k0 < kend; k0 += KC) {
     const int kc = min(KC, kend - k0);
@@ -107,29 +106,20 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
 #pragma unroll
       for (int t = 0; t < TW; ++t) {
         const C2 a = A[arow[t] + d.lda * kg];
-        if constexpr (M3) {
-          accR[t] = MF::op(a.x, bx.x, accR[t]);
-          accX[M3 ? t : 0] = MF::op(a.y, bx.y, accX[M3 ? t : 0]);
-          accI[t] = MF::op(a.x + a.y, bs, accI[t]);
-        } else {
-          accR[t] = MF::op(a.x, bx.x, accR[t]);
-          accR[t] = MF::op(-a.y, bx.y, accR[t]);
-          accI[t] = MF::op(a.x, bx.y, accI[t]);
-          accI[t] = MF::op(a.y, bx.x, accI[t]);
-        }
+        accR[t] = MF::op(a.x, bx.x, accR[t]);
+        accX[t] = MF::op(a.y, bx.y, accX[t]);
+        accI[t] = MF::op(a.x + a.y, bs, accI[t]);
       }
     }
   }
-  if constexpr (M3) {
 #pragma unroll
-    for (int t = 0; t < TW; ++t)
+  for (int t = 0; t < TW; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const T t1 = accR[t][v], t2 = accX[M3 ? t : 0][v];
-        accR[t][v] = t1 - t2;
-        accI[t][v] = accI[t][v] - t1 - t2;
-      }
-  }
+    for (int v = 0; v < 4; ++v) {
+      const T t1 = accR[t][v], t2 = accX[t][v];
+      accR[t][v] = t1 - t2;
+      accI[t][v] = accI[t][v] - t1 - t2;
+    }
   if (WK > 1) {
     // waves kw > 0 hand their tiles to the kw = 0 wave of their row group
     if (kw > 0) {
@@ -221,7 +211,7 @@ __global__ void skinny_reduce_kernel(SkinnyDesc d, int r0, int nr, int nsplit,
 // (the top merge levels) at most 64, so that the row blocks (times the K splits below)
 // spread the matrix-core work over the device instead of a few compute units
 int block_rows(const SkinnyDesc& d) {
-  int rows = d.M <= 16 ? 16 : d.M <= 32 ? 32 : d.M <= 64 ? 64 : d.M <= 128 ? 128 : 256;
+  int rows = d.M <= 16 ? 16 : d.M <= 32 ? 32 : d.M <= 64 ? 64 : 128;
   while (rows > 64 && (long)cdiv(d.M, rows) * nbatch(d) < 512) rows /= 2;
   return rows;
 }
@@ -274,8 +264,7 @@ void run_pass_t(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
     case 16: run_chunk<T, 1, 4>(d, r0, nr, st); break;
     case 32: run_chunk<T, 1, 2>(d, r0, nr, st); break;
     case 64: run_chunk<T, 1, 1>(d, r0, nr, st); break;
-    case 128: run_chunk<T, 2, 1>(d, r0, nr, st); break;
-    default: run_chunk<T, 4, 1>(d, r0, nr, st); break;
+    default: run_chunk<T, 2, 1>(d, r0, nr, st); break;
   }
 }
 
