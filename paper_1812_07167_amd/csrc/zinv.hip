@@ -7,7 +7,7 @@
 // inv(A)[k][r_j] = M[r_k][j], which the final write-out applies.
 //
 // * n <= SMALL_MAX: one workgroup per matrix, matrix resident in registers.
-// * larger n: blocked right-looking form.  For each block K of PNB (16, 8 or 4) columns a panel
+// * larger n: blocked right-looking form.  For each block K of PNB (16 or 8) columns a panel
 //   kernel (one workgroup per matrix, panel rows spread over its waves, each row's PNB
 //   panel entries in registers) runs the PNB elimination steps on the panel and emits
 //   the block transformation Q; an update kernel then forms
@@ -136,14 +136,14 @@ __global__ __launch_bounds__(256) void zinv_small_kernel(int n, const double* Ai
 // the remaining columns (the candidate row's values are published once final).  The slots alternate between two buffers, so one
 // barrier per step suffices: a wave can only overwrite a buffer after every wave has
 // passed the following step's barrier.
-template <class T, int RPL, int PNB>
-__global__ __launch_bounds__(512) void zinv_panel_kernel(int n, const double* Mcur,
-                                                         double* Mnext, int k0, int* piv,
-                                                         int* used, int* info) {
+template <class T, int RPL, int PNB, int NW>
+__global__ __launch_bounds__(64 * NW) void zinv_panel_kernel(int n, const double* Mcur,
+                                                             double* Mnext, int k0, int* piv,
+                                                             int* used, int* info) {
   typedef typename Cx<T>::t C2;
-  __shared__ unsigned s_key[2][8];
-  __shared__ int s_row[2][8];
-  __shared__ C2 s_val[2][8][PNB];
+  __shared__ unsigned s_key[2][NW];
+  __shared__ int s_row[2][NW];
+  __shared__ C2 s_val[2][NW][PNB];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   const long b = blockIdx.x;
@@ -196,23 +196,25 @@ __global__ __launch_bounds__(512) void zinv_panel_kernel(int n, const double* Mc
   };
   publish_key(0, 0);
   publish_row(0);
+  // Every step runs (no branch around the updates, which would keep a second copy of
+  // the panel live at each join): a step past the panel's end, or one with no nonzero
+  // candidate (singular; reported at the end), takes the multiplier 0 and changes no
+  // column that is written out.
   int bad = 0;
 #pragma unroll
   for (int s = 0; s < PNB; ++s) {
-    if (s >= nk || bad) continue;  // uniform over the workgroup; keeps the loop unrolled
     const int k = k0 + s;
     const int sb = s & 1;
+    const bool live = s < nk;  // uniform over the workgroup
     __syncthreads();
     // winner over the waves (ties to the lowest wave): lane x reads wave x's key
     const unsigned kx = lane < nw ? s_key[sb][lane] : 0u;
     const unsigned gkey = wave_max_u32(kx);
     const int ww = __builtin_ctzll(__ballot(kx == gkey));
-    if (gkey == 0u) {
-      bad = k + 1;
-      continue;
-    }
-    const int r = s_row[sb][ww];
-    const C2 ip = crcp_fast(s_val[sb][ww][s]);
+    const bool go = live && gkey != 0u;
+    if (live && gkey == 0u && !bad) bad = k + 1;
+    const int r = go ? s_row[sb][ww] : -1;
+    const C2 ip = go ? crcp_fast(s_val[sb][ww][s]) : Cx<T>::mk(0, 0);
     C2 f[RPL], f0[RPL];
     bool isr[RPL];
 #pragma unroll
@@ -231,7 +233,7 @@ __global__ __launch_bounds__(512) void zinv_panel_kernel(int n, const double* Mc
         v[q][c].y = fma(-f[q].x, pc.y, fma(-f[q].y, pc.x, v[q][c].y));
       }
     };
-    if (s + 1 < nk) {
+    if (s + 1 < PNB) {
       upd(s + 1);
       publish_key(s + 1, sb ^ 1);
     }
@@ -241,12 +243,12 @@ __global__ __launch_bounds__(512) void zinv_panel_kernel(int n, const double* Mc
       upd(c);
       // bound the scheduler's look-ahead: hoisting every pivot-row read of the
       // unrolled steps would need more registers than the workgroup has
-      if ((c & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      if ((c & 1) == 1) __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int q = 0; q < RPL; ++q) v[q][s] = isr[q] ? ip : Cx<T>::mk(-f0[q].x, -f0[q].y);
-    if (s + 1 < nk) publish_row(sb ^ 1);
-    if (threadIdx.x == 0) pv[k] = r;
+    if (s + 1 < PNB) publish_row(sb ^ 1);
+    if (live && threadIdx.x == 0) pv[k] = r;
   }
   if (bad) {
     if (threadIdx.x == 0) info[b] = bad;
@@ -275,52 +277,79 @@ __global__ __launch_bounds__(512) void zinv_panel_kernel(int n, const double* Mc
 // with Q = next[:, K] (written by the panel kernel) and r_s the pivot rows of K.
 // Memory-bound (PNB complex multiply-adds per element read and written).  A workgroup
 // covers 64 rows (one per lane) and UJ consecutive columns (UJ / 4 per wave) of one
-// matrix; a wave's column loads are issued together.
+// matrix.  Its 64 rows of Q and the pivot rows' entries on its columns are staged in LDS
+// with every global load issued at once; the terms are then added in order from LDS.
 constexpr int UJ = 16;
 template <class T, int PNB>
-__global__ __launch_bounds__(256) void zinv_update_kernel(int n, const double* Mcur,
-                                                          double* Mnext, int k0, const int* piv,
-                                                          const int* info) {
+__global__ __launch_bounds__(256) void zinv_update_kernel(int n,
+                                                          const double* __restrict__ Mcur,
+                                                          double* __restrict__ Mnext, int k0,
+                                                          const int* piv, const int* info) {
   typedef typename Cx<T>::t C2;
   constexpr int CW = UJ / 4;  // columns per wave
+  __shared__ C2 s_p[PNB][UJ];
+  __shared__ C2 s_q[PNB][64];
   const long b = blockIdx.z;
   if (info[b]) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i = blockIdx.x * 64 + lane;
+  const int i0 = blockIdx.x * 64, i = i0 + lane;
   const int nk = (n - k0) < PNB ? (n - k0) : PNB;
   // columns outside the panel, compacted: column index jj skips [k0, k0 + nk)
   const int ncol = n - nk;
-  const int jj0 = blockIdx.y * UJ + w * CW;
-  if (i >= n || jj0 >= ncol) return;
+  const int jb = blockIdx.y * UJ, jj0 = jb + w * CW;
   const C2* Mc = reinterpret_cast<const C2*>(Mcur) + b * (long)n * n;
   C2* Mn = reinterpret_cast<C2*>(Mnext) + b * (long)n * n;
   const int* pv = piv + b * (long)n + k0;
-  int pr[PNB];
+  const bool mine = i < n && jj0 < ncol;
   bool isp = false;
-  C2 q[PNB];
 #pragma unroll
-  for (int s = 0; s < PNB; ++s) {
-    pr[s] = s < nk ? pv[s] : 0;
-    isp |= (s < nk && pr[s] == i);
-    q[s] = s < nk ? Mn[i + (long)n * (k0 + s)] : Cx<T>::mk(0, 0);
-  }
-  C2 m[CW];
+  for (int s = 0; s < PNB; ++s) isp |= (s < nk && pv[s] == i);
+  C2 acc[CW];
   int col[CW];
 #pragma unroll
   for (int c = 0; c < CW; ++c) {
     const int jj = min(jj0 + c, ncol - 1);
     col[c] = jj < k0 ? jj : jj + nk;
-    m[c] = isp ? Cx<T>::mk(0, 0) : Mc[i + (long)n * col[c]];
+    acc[c] = (mine && !isp) ? Mc[min(i, n - 1) + (long)n * col[c]] : Cx<T>::mk(0, 0);
+  }
+  // Q rows i0..i0+63 (coalesced), then the pivot rows on this workgroup's columns
+  constexpr int QPT = PNB * 64 / 256;
+  C2 qv[QPT];
+#pragma unroll
+  for (int e = 0; e < QPT; ++e) {
+    const int t = threadIdx.x + 256 * e, s = t >> 6, r = i0 + (t & 63);
+    qv[e] = (s < nk && r < n) ? Mn[r + (long)n * (k0 + s)] : Cx<T>::mk(0, 0);
+  }
+  constexpr int PPT = (PNB * UJ + 255) / 256;
+  C2 pvv[PPT];
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) {
+    const int t = threadIdx.x + 256 * e, s = t / UJ;
+    const int jj = min(jb + t % UJ, ncol - 1);
+    const int cc = jj < k0 ? jj : jj + nk;
+    pvv[e] = (t < PNB * UJ && s < nk) ? Mc[pv[s] + (long)n * cc] : Cx<T>::mk(0, 0);
   }
 #pragma unroll
-  for (int c = 0; c < CW; ++c) {
-    if (jj0 + c >= ncol) continue;
-    const C2* cj = Mc + (long)n * col[c];
-    C2 acc = m[c];
-#pragma unroll
-    for (int s = 0; s < PNB; ++s) acc = cfma(q[s], s < nk ? cj[pr[s]] : Cx<T>::mk(0, 0), acc);
-    Mn[i + (long)n * col[c]] = acc;
+  for (int e = 0; e < QPT; ++e) {
+    const int t = threadIdx.x + 256 * e;
+    s_q[t >> 6][t & 63] = qv[e];
   }
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) {
+    const int t = threadIdx.x + 256 * e;
+    if (t < PNB * UJ) s_p[t / UJ][t % UJ] = pvv[e];
+  }
+  __syncthreads();
+  if (!mine) return;
+#pragma unroll 4
+  for (int s = 0; s < nk; ++s) {
+    const C2 q = s_q[s][lane];
+#pragma unroll
+    for (int c = 0; c < CW; ++c) acc[c] = cfma(q, s_p[s][w * CW + c], acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < CW; ++c)
+    if (jj0 + c < ncol) Mn[i + (long)n * col[c]] = acc[c];
 }
 
 template <class T>
@@ -362,20 +391,20 @@ __global__ void zero_int_kernel(int* p, long cnt) {
     p[e] = 0;
 }
 
-template <class T, int RPL, int PNB>
+template <class T, int RPL, int PNB, int NW>
 void launch_panel(int n, int batch, const double* Mc, double* Mn, int k0, int* piv, int* used,
                   int* info, hipStream_t st) {
-  const int waves = std::max(1, std::min(8, (n + 64 * RPL - 1) / (64 * RPL)));
-  hipLaunchKernelGGL((zinv_panel_kernel<T, RPL, PNB>), dim3(batch), dim3(64 * waves), 0, st, n,
-                     Mc, Mn, k0, piv, used, info);
+  const int waves = std::max(1, std::min(NW, (n + 64 * RPL - 1) / (64 * RPL)));
+  hipLaunchKernelGGL((zinv_panel_kernel<T, RPL, PNB, NW>), dim3(batch), dim3(64 * waves), 0, st,
+                     n, Mc, Mn, k0, piv, used, info);
 }
 
 // One block step of the blocked path: panel columns [k0, k0 + PNB), then the update of
 // every other column.
-template <class T, int RPL, int PNB>
+template <class T, int RPL, int PNB, int NW>
 void block_step(int n, int batch, const double* Mc, double* Mn, int k0, int* piv, int* used,
                 int* info, hipStream_t st) {
-  launch_panel<T, RPL, PNB>(n, batch, Mc, Mn, k0, piv, used, info, st);
+  launch_panel<T, RPL, PNB, NW>(n, batch, Mc, Mn, k0, piv, used, info, st);
   HPS_LAUNCH_CHECK();
   const int ncol = n - std::min(PNB, n - k0);
   if (ncol > 0) {
@@ -419,14 +448,15 @@ void zinv_t(int n, int batch, const double* A, long lda, long sA, double* Out, l
     hipLaunchKernelGGL(zero_int_kernel, dim3(grid1d(ni)), dim3(256), 0, st, piv, ni);
     HPS_LAUNCH_CHECK();
   }
-  // panel width: 16 columns where a lane holds one panel row (n <= 512), 8 where it
-  // holds 2, 4 where it holds 4 (wider panels of several rows do not fit in a lane's
-  // registers)
-  const int pnb = n <= 512 ? 16 : n <= 1024 ? 8 : 4;
+  // panel shape: a lane holds one panel row of 16 columns (n <= 512), two rows of 8
+  // (n <= 2048), with 8 waves up to n = 1024 and 16 above.  A panel step's work grows
+  // with the panel width on the one compute unit that runs it, the update's passes over
+  // the matrix shrink with it; these widths measured fastest.
+  const int pnb = n <= 512 ? 16 : 8;
   for (int k0 = 0; k0 < n; k0 += pnb) {
-    if (n <= 512) block_step<T, 1, 16>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
-    else if (n <= 1024) block_step<T, 2, 8>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
-    else block_step<T, 4, 4>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
+    if (n <= 512) block_step<T, 1, 16, 8>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
+    else if (n <= 1024) block_step<T, 2, 8, 8>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
+    else block_step<T, 2, 8, 16>(n, batch, Mcur, Mnext, k0, piv, used, info, st);
     std::swap(Mcur, Mnext);
   }
   int blocks_x = std::min(n, 64);

@@ -245,6 +245,19 @@ def test_config2_sampled_leaves(config2):
         assert rel(f.get(H.OP_Y, L, int(h)), o["Y"]) < TOL
 
 
+def test_large_interfaces_polynomial_reproduction():
+    """128 x 128 leaves at p = 16: the top interface (n = 1792) takes the blocked
+    inverse's panels of two rows per lane over 16 waves, the next ones (n = 896) over 8;
+    the polynomial must still come back to round-off."""
+    _say("128x128 leaves, p=16, polynomial")
+    cs = Case(128, 128, 16, 100.0, c="bump", rhs="polynomial", nrhs=1, seed=2)
+    f = cs.gpu_build()
+    u = cs.gpu_solve(f)
+    f.free()
+    _say("128x128 poly rel", rel(u, cs.exact))
+    assert rel(u, cs.exact) < 1e-10
+
+
 def test_config2_manufactured_solution(config2):
     cs, f = config2
     mf = Case(64, 64, 16, 100.0, c="bump", rhs="manufactured", nrhs=3, seed=11)
