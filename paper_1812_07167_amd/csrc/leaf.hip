@@ -405,13 +405,17 @@ __device__ inline double2 bnd_entry(int b, int gcol, const double2* col, const d
 // stages the m columns of the interior nodes (i, k) in LDS, which completes the columns
 // W_k and E_k of Psi_i (one thread per interior row) and adds the chunk's terms to the
 // row's m S and m N entries (registers); the chunk's columns of Y, W_k and E_k then get
-// their boundary rows.  The S and N columns get theirs after the last chunk.  For
-// reduced-precision storage every entry goes to the complex64 copy only.
+// their boundary rows.  The S and N columns get theirs after the last chunk.  Each
+// interior row has two threads: one in the first half of the workgroup (the S columns
+// and W_k), one in the second (the N columns and E_k), which halves the accumulators a
+// thread holds so that two workgroups share a compute unit.  For reduced-precision
+// storage every entry goes to the complex64 copy only.
 template <int P>
-__global__ __launch_bounds__(256) void leaf_psi_bnd_kernel(LeafDesc d) {
+__global__ __launch_bounds__(512) void leaf_psi_bnd_kernel(LeafDesc d) {
+  constexpr int NT = 512;
   constexpr int m = P - 2, NI = m * m, NB = 4 * m, N = P * P - 4;
   constexpr int CC = m + 2;  // staged columns: a chunk of Y_i plus W_k and E_k of Psi_i
-  static_assert(NI <= 256, "one thread per interior row");
+  static_assert(NI <= NT / 2, "two threads per interior row");
   __shared__ double2 sI[CC][NI];
   __shared__ double2 sw[4][m];  // wS wN wW wE
   __shared__ double2 sc[4][m];  // sS sN oW oE
@@ -421,7 +425,7 @@ __global__ __launch_bounds__(256) void leaf_psi_bnd_kernel(LeafDesc d) {
   const long prob = (d.h0 + h) / d.nl1;
   const double2* tab = reinterpret_cast<const double2*>(d.tab) + prob * leaf_table_len_dev(P);
   const TabIdx T{m};
-  for (int e = tid; e < m; e += 256) {
+  for (int e = tid; e < m; e += NT) {
     sw[0][e] = tab[T.wS() + e];
     sw[1][e] = tab[T.wN() + e];
     sw[2][e] = tab[T.wW() + e];
@@ -446,7 +450,7 @@ __global__ __launch_bounds__(256) void leaf_psi_bnd_kernel(LeafDesc d) {
   };
   // boundary rows (and R) of the ncol staged columns sI[0..ncol), global columns gc(col)
   auto boundary = [&](int ncol, auto&& gc) {
-    for (int e = tid; e < NB * ncol; e += 256) {
+    for (int e = tid; e < NB * ncol; e += NT) {
       const int b = e % NB, col = e / NB;
       const int gcol = gc(col);
       const double2 v = bnd_entry<P>(b, gcol, sI[col], sc, sb);
@@ -458,21 +462,18 @@ __global__ __launch_bounds__(256) void leaf_psi_bnd_kernel(LeafDesc d) {
       }
     }
   };
-  const int r = tid;
-  double2 accS[m], accN[m];
+  const int r = tid % (NT / 2), hh = tid / (NT / 2);  // row; 0: S and W, 1: N and E
+  double2 acc[m];
 #pragma unroll
-  for (int i = 0; i < m; ++i) {
-    accS[i] = cmk(0, 0);
-    accN[i] = cmk(0, 0);
-  }
+  for (int i = 0; i < m; ++i) acc[i] = cmk(0, 0);
   // chunk k's columns of Y_i: IT entries per thread, loaded together; the next chunk's
   // loads are issued as soon as this chunk is in LDS
-  constexpr int IT = (NI * m + 255) / 256;
+  constexpr int IT = (NI * m + NT - 1) / NT;
   double2 yv[IT];
   auto load_chunk = [&](int k) {
 #pragma unroll
     for (int q = 0; q < IT; ++q) {
-      const int e = tid + 256 * q;
+      const int e = tid + NT * q;
       yv[q] = e < NI * m ? BI[(NB + e % NI) + (long)N * (NB + k * m + e / NI)] : cmk(0, 0);
     }
   };
@@ -482,7 +483,7 @@ __global__ __launch_bounds__(256) void leaf_psi_bnd_kernel(LeafDesc d) {
     __syncthreads();  // the tables; the previous chunk's boundary rows are done
 #pragma unroll
     for (int q = 0; q < IT; ++q) {
-      const int e = tid + 256 * q;
+      const int e = tid + NT * q;
       if (e < NI * m) {
         const int row = e % NI, i = e / NI;
         sI[i][row] = yv[q];
@@ -493,21 +494,18 @@ __global__ __launch_bounds__(256) void leaf_psi_bnd_kernel(LeafDesc d) {
     if (k + 1 < m) load_chunk(k + 1);
     __syncthreads();
     if (r < NI) {
-      const double2 ws = sw[0][k], wn = sw[1][k];
-      double2 aW = cmk(0, 0), aE = cmk(0, 0);
+      // hh 0: S entries (weight wS[k]) and W_k (weights wW); hh 1: N and E_k
+      const double2 wk = sw[hh][k];
+      double2 a = cmk(0, 0);
 #pragma unroll
       for (int i = 0; i < m; ++i) {
         const double2 y = sI[i][r];
-        accS[i] = cfma(y, ws, accS[i]);
-        accN[i] = cfma(y, wn, accN[i]);
-        aW = cfma(y, sw[2][i], aW);
-        aE = cfma(y, sw[3][i], aE);
+        acc[i] = cfma(y, wk, acc[i]);
+        a = cfma(y, sw[2 + hh][i], a);
       }
-      const double2 pW = cmk(-aW.x, -aW.y), pE = cmk(-aE.x, -aE.y);
-      sI[m][r] = pW;
-      sI[m + 1][r] = pE;
-      put(NB + r, 3 * m + k, pW);  // W_k
-      put(NB + r, m + k, pE);      // E_k
+      const double2 pv = cmk(-a.x, -a.y);
+      sI[m + hh][r] = pv;
+      put(NB + r, hh ? m + k : 3 * m + k, pv);  // E_k or W_k
     }
     __syncthreads();
     boundary(CC, [&](int col) { return col < m ? NB + k * m + col : col == m ? 3 * m + k : m + k; });
@@ -516,11 +514,10 @@ __global__ __launch_bounds__(256) void leaf_psi_bnd_kernel(LeafDesc d) {
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     __syncthreads();
-    if (r < NI) {
+    if (r < NI && hh == q) {
 #pragma unroll
       for (int i = 0; i < m; ++i) {
-        const double2 a = q == 0 ? accS[i] : accN[i];
-        const double2 v = cmk(-a.x, -a.y);
+        const double2 v = cmk(-acc[i].x, -acc[i].y);
         sI[i][r] = v;
         put(NB + r, q * 2 * m + i, v);
       }
@@ -538,7 +535,7 @@ template <int P> void scratch_of(long nleaf, size_t* out) {
   *out = (size_t)nleaf * LeafCfg<P>::SCR * 16;
 }
 template <int P> void launch_psi_bnd(const LeafDesc& d, hipStream_t st) {
-  hipLaunchKernelGGL(leaf_psi_bnd_kernel<P>, dim3(d.nleaf), dim3(256), 0, st, d);
+  hipLaunchKernelGGL(leaf_psi_bnd_kernel<P>, dim3(d.nleaf), dim3(512), 0, st, d);
 }
 
 #define HPS_P_SWITCH(FN, p, ...)                   \
