@@ -49,15 +49,16 @@ def _alone(case, f, t, s):
 
 
 def test_results_alone_equal_results_in_the_mix():
-    """Requests for four problems (one in mixed precision) submitted in a burst while a
-    larger build holds the only slot, so that they queue and merge."""
+    """60 seeded requests for four problems (one in mixed precision) submitted in a
+    burst while a larger build holds the only slot, so that they queue and merge; every
+    result is checked against the same request solved alone and against the oracle."""
     from paper_1812_07167_amd import hps as H
     cases = [Case(8, 8, 10, 30.0, seed=1), Case(4, 4, 8, 20.0, eta=15.0 + 3.0j, seed=2),
              Case(8, 4, 12, 40.0, seed=3), Case(16, 16, 8, 25.0, seed=4)]
     prec = [0, 0, 0, H.HPS_PREC_MIXED]
     big = Case(32, 32, 12, 50.0, seed=9, nrhs=1)
     import torch
-    reqs = _requests(cases, 30, seed=7)
+    reqs = _requests(cases, 60, seed=7)
     dev = [(_dev(t), None if s is None else _dev(s)) for _, t, s in reqs]
     torch.cuda.synchronize()
     srv = H.Server(budget_bytes=0, slots=1, max_batch_rhs=8)
@@ -82,13 +83,12 @@ def test_results_alone_equal_results_in_the_mix():
     for (j, t, s), u in zip(reqs, us):
         ua = _alone(cases[j], fs[j], t, s)
         assert rel(u.cpu().numpy(), ua) < (TOL if prec[j] else SAME), j
-    # and one request per problem against the oracle
+    # and every request against the oracle
     from oracle import hps_oracle as O
-    for j, c in enumerate(cases):
-        q = next(k for k, (jj, _, s) in enumerate(reqs) if jj == j and s is not None)
-        _, t, s = reqs[q]
-        uo = O.solve(c.prob, c.oracle_build(), s, t)
-        assert rel(us[q].cpu().numpy(), uo) < TOL, j
+    obs = [c.oracle_build() for c in cases]
+    for q, ((j, t, s), u) in enumerate(zip(reqs, us)):
+        uo = O.solve(cases[j].prob, obs[j], s, t)
+        assert rel(u.cpu().numpy(), uo) < TOL, (q, j)
     for f in fs:
         f.free()
 
