@@ -119,3 +119,55 @@ def test_batch_spanning_several_leaf_chunks(precision):
         f1.free()
     for f in fs:
         f.free()
+
+
+# ------------------------------------------------- config 3's own problems, stratified
+
+_ORACLE_U = {}
+
+
+def _config3_strata(side):
+    """The first of the 256 seeded batch problems for each p on leaf grids of this side."""
+    from paper_1812_07167_amd import inputs as G
+    seen = {}
+    for q in G.batch_problems(0, 256):
+        if q["nx"] == side:
+            seen.setdefault(q["p"], q)
+    return [seen[p] for p in sorted(seen)]
+
+
+def _config3_inputs(q):
+    from oracle import hps_oracle as O
+    from paper_1812_07167_amd import inputs as G
+    prob = O.Problem(0.0, 1.0, 0.0, 1.0, q["nx"], q["ny"], q["p"], q["kappa"], q["kappa"])
+    xyi = prob.interior_nodes()
+    xyb, nrm = prob.root_boundary()
+    c = G.FourierField.seeded(q["seed"])(xyi)
+    mf = G.Manufactured(q["kappa"], q["theta"])
+    s, t = mf.s(xyi, c)[None], mf.t(xyb, nrm, q["kappa"])[None]
+    if q["seed"] not in _ORACLE_U:
+        _ORACLE_U[q["seed"]] = O.solve(prob, O.build(prob, c), s, t)
+    return c, s, t, _ORACLE_U[q["seed"]]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("side", [8, 16, 32])
+def test_config3_strata_match_oracle(side, precision):
+    """The batch workload's own drawn problems, one per (leaf grid, p) stratum: the
+    three p (8, 12, 16) of one grid side built in one batch and solved together, each
+    against the oracle (1e-10; mixed precision after its FP64 corrections)."""
+    import torch
+    from paper_1812_07167_amd import hps as H
+    qs = _config3_strata(side)
+    print("config-3 strata", side, [(q["seed"], q["p"]) for q in qs], "precision", precision,
+          flush=True)
+    ins = [_config3_inputs(q) for q in qs]
+    fs = H.hps_build_batch([H.domain(q["nx"], q["ny"]) for q in qs], [q["p"] for q in qs],
+                           [q["kappa"] for q in qs], [q["kappa"] for q in qs],
+                           [_dev(c, "float64") for c, _, _, _ in ins], precision=precision)
+    us = H.hps_solve_batch(fs, [_dev(t) for _, _, t, _ in ins], [_dev(s) for _, s, _, _ in ins])
+    torch.cuda.synchronize()
+    for q, (_, _, _, uo), u in zip(qs, ins, us):
+        assert rel(u.cpu().numpy(), uo) < TOL, (q["seed"], q["p"])
+    for f in fs:
+        f.free()
