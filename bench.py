@@ -92,6 +92,18 @@ def workload(nx=64, ny=64, p=16, kappa=100.0, nrhs=16, seed=0, nodes=None):
     return c, s, t, exact
 
 
+def host_cpu():
+    """The host processor's model name (first entry of /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(nx, ny, p, kappa, nrhs, seed):
     """The CPU oracle, as it stands, on a bounded sample of the workload: the corner
     [0, nx/64] x [0, ny/64] of the unit square with the workload's own 1/64 x 1/64 leaves,
@@ -121,7 +133,8 @@ def cpu_baseline(nx, ny, p, kappa, nrhs, seed):
     dof = nx * ny * (p * p - 4)
     err = float(np.linalg.norm(u - exact) / np.linalg.norm(exact))
     return {"value": dof / dt, "unit": "DOF/s (build + one %d-RHS solve)" % nrhs, "cores": cores,
-            "kind": "oracle", "seconds": dt, "rel_l2_vs_exact": err,
+            "kind": "oracle", "seconds": dt, "rel_l2_vs_exact": err, "host_cpu": host_cpu(),
+            "host_cpus_visible": os.cpu_count(),
             "sample": "oracle build + one %d-RHS solve on the %dx%d-leaf corner [0,%g]x[0,%g] "
                       "of the workload (same leaves, p=%d, kappa=%g, c and right-hand "
                       "sides; %.3g of its DOF); numpy/OpenBLAS, threads as counted"
