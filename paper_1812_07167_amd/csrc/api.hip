@@ -1146,18 +1146,24 @@ void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const d
       k.C = ttb[l]; k.ldc = n3; k.sC = n3 * nrhs; k.accumulate = true; k.alpha = -1.0;
       ws.skinny(pr, nm, k);
       if (l > 0) {
-        // h^tau = [h1a + R13a t~3a ; h2b + R23b t~3b]   (eq. (flux_part))
+        // h^tau = [h1a + R13a t~3a ; h2b + R23b t~3b]   (eq. (flux_part)); the two halves
+        // write disjoint rows of h^tau and share a launch when the children are alike
         k = SkinnyDesc();
         k.M = n1; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox; k.a_c64 = P.c64;
         k.A = op(P.R13a, n1 * n3); k.lda = n1; k.sA = n1 * n3;
         k.X = tta[l]; k.ldx = n3; k.sX = n3 * nrhs;
         k.C = h[l]; k.ldc = nbp; k.sC = nbp * nrhs; k.crow = P.dperm; k.accumulate = true;
-        ws.skinny(pr, nm, k);
-        k.M = n2;
-        k.A = op(P.R23b, n2 * n3); k.lda = n2; k.sA = n2 * n3;
-        k.X = ttb[l];
-        k.crow = P.dperm + n1;
-        ws.skinny(pr, nm, k);
+        if (n1 == n2) {
+          k.A2 = op(P.R23b, n2 * n3); k.X2 = ttb[l]; k.C2 = h[l]; k.crow2 = P.dperm + n1;
+          ws.skinny(pr, nm, k);
+        } else {
+          ws.skinny(pr, nm, k);
+          k.M = n2;
+          k.A = op(P.R23b, n2 * n3); k.lda = n2; k.sA = n2 * n3;
+          k.X = ttb[l];
+          k.crow = P.dperm + n1;
+          ws.skinny(pr, nm, k);
+        }
       }
     }
   }

@@ -53,12 +53,14 @@ struct SkinnyDesc {
   long xbase = 0, cbase = 0;  // subtracted from xoff[b] / coff[b]
   // workspace for the split-K partial sums (at least skinny_work_bytes(d) bytes)
   void* work = nullptr;
-  // optional second operator of the same shape and strides, applied to the same X in
-  // the same launch (its batch entries follow the first's): its own A, C, crow and C0
+  // optional second operator of the same shape and strides, applied in the same launch
+  // (its batch entries follow the first's): its own A, C, crow and C0, and its own X
+  // (same strides and offsets) if X2 is set, else the first's X
   const double* A2 = nullptr;
   double* C2 = nullptr;
   const int* crow2 = nullptr;
   const double* C02 = nullptr;
+  const double* X2 = nullptr;
 };
 size_t skinny_work_bytes(const SkinnyDesc& d);
 void zgemm_skinny(const SkinnyDesc& d, hipStream_t st);

@@ -15,8 +15,9 @@
 // LDS in a fixed order.
 // Operators with few rows and a long K (the top merges) are also split along K across
 // workgroups; those partial sums are reduced in a fixed order by a second kernel, so
-// results never depend on scheduling.  Two operators of one shape applied to the same
-// right-hand sides (the two children's Phi in the downward pass) share a launch.
+// results never depend on scheduling.  Two operators of one shape share a launch: applied
+// to the same right-hand sides (the two children's Phi in the downward pass) or each to
+// its own block (the two halves of h^tau in the upward pass).
 //
 // MFMA 16x16x4 lane layouts: lane l supplies A[l%16][l/16] and B[l/16][l%16];
 // accumulator element v of lane l is D[l/16 + 4 v][l%16] (f64) or D[4 (l/16) + v][l%16]
@@ -70,8 +71,8 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
   const int kbeg = ks * kper, kend = min(d.K, kbeg + kper);
   const int row0 = blockIdx.x * ROWS + wr * 16 * TW;
   const C2* A = reinterpret_cast<const C2*>(two ? d.A2 : d.A) + b * d.sA;
-  const double2* X =
-      reinterpret_cast<const double2*>(d.X) + (d.xoff ? d.xoff[b] - d.xbase : b * d.sX);
+  const double2* X = reinterpret_cast<const double2*>(two && d.X2 ? d.X2 : d.X) +
+                     (d.xoff ? d.xoff[b] - d.xbase : b * d.sX);
 
   // rows this lane loads (clamped into the operator; rows past M are never written)
   long arow[TW];
@@ -287,6 +288,7 @@ void zgemm_skinny(const SkinnyDesc& d, hipStream_t st) {
   if (d.M <= 0 || d.batch <= 0 || d.nrhs <= 0) return;
   if (nbatch(d) > 65535) throw Error(1, "zgemm_skinny: batch exceeds grid limit");
   if (d.A2 && !d.C2) throw Error(1, "zgemm_skinny: second operator without output");
+  if (d.X2 && !d.A2) throw Error(1, "zgemm_skinny: second right-hand side block without operator");
   if (d.K <= 0) throw Error(1, "zgemm_skinny: K must be positive");
   for (int r0 = 0; r0 < d.nrhs; r0 += NRB) run_pass(d, r0, std::min(NRB, d.nrhs - r0), st);
 }
