@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void zinv_small_kernel(int n, const double* Ai
 // no gather pass and no race between workgroups.
 //
 // Panel kernel: the n x PNB panel (columns k0..k0+PNB-1) of one matrix, rows
-// distributed over the (at most 8) waves of the workgroup (row i: wave i / (64 RPL),
+// distributed over the (at most NW, 8 or 16) waves of the workgroup (row i: wave i / (64 RPL),
 // slot (i / 64) % RPL, lane i % 64), all PNB panel columns of a row in the owning lane's
 // registers.  For elimination step s every wave publishes its best unused row of column
 // s (DPP reduction): key, row index and the row's PNB values, in an LDS slot; after one
