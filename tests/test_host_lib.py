@@ -220,3 +220,13 @@ def test_allocator_hook_argument_checks():
     with pytest.raises(ValueError):
         H.set_allocator(lambda n, s: 0)
     H.set_allocator()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py has no multi-GPU path: --gpus above 1 exits with a message, before any
+    device work."""
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
