@@ -245,6 +245,20 @@ def test_config2_sampled_leaves(config2):
         assert rel(f.get(H.OP_Y, L, int(h)), o["Y"]) < TOL
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_many_right_hand_sides_in_ragged_passes(precision):
+    """37 right-hand sides: the solve products take them in passes of 16, 16 and 5 (the
+    paired launches of both sweeps included), with and without a body load, against the
+    oracle."""
+    _say("37 RHS, precision", precision)
+    cs = Case(8, 8, 10, 30.0, seed=21, nrhs=37)
+    f = cs.gpu_build(precision=precision)
+    boxes = cs.oracle_build()
+    assert rel(cs.gpu_solve(f), cs.oracle_solve(boxes)) < TOL
+    assert rel(cs.gpu_solve(f, s=None), cs.oracle_solve(boxes, s=None)) < TOL
+    f.free()
+
+
 def test_large_interfaces_polynomial_reproduction():
     """128 x 128 leaves at p = 16: the top interface (n = 1792) takes the blocked
     inverse's panels of two rows per lane over 16 waves, the next ones (n = 896) over 8;
