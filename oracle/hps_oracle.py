@@ -25,10 +25,10 @@ Readings taken where the paper is silent, garbled or inconsistent:
   reading.
 * Sec. 2.1.2, eq. (particular): the printed block row [A(i,i) A(i,b)] is read as
   [A(i,b) A(i,i)] so that it multiplies u = [u_b; u_i] (same B as eq. (homogeneous)).
-* Algorithm 1 steps (12)-(13) print a stacked column [R13; R23]; the block-diagonal
+* The R^tau step of Algorithm 1 prints a stacked column [R13; R23]; the block-diagonal
   form of eq. (out) / eq. (flux_part) is used.
-* Algorithm 2 step (16) gives only the t3 parts of the children's incoming data; the
-  remaining parts are the parent's incoming data restricted to I_1 and I_2.
+* Algorithm 2's downward pass gives only the t3 parts of the children's incoming data;
+  the remaining parts are the parent's incoming data restricted to I_1 and I_2.
 * The order of nodes within a side is not fixed by the paper; the oracle keeps every
   box boundary as a list of node keys and matches children by key, and maps the
   root boundary to the documented external order (S, E, N, W sides, each in
@@ -38,6 +38,8 @@ Readings taken where the paper is silent, garbled or inconsistent:
 """
 
 from __future__ import annotations
+
+import os
 
 import numpy as np
 
@@ -155,8 +157,14 @@ def leaf_operators(x0, x1, y0, y1, p, kappa, eta, c_interior):
     B = np.concatenate([F, Ahat_iI])  # eq. (homogeneous)
     rhs_h = np.concatenate([np.eye(g.nb), np.zeros((g.ni, g.nb))])  # eq. (hmgsolnopdef)
     rhs_p = np.concatenate([np.zeros((g.nb, g.ni)), np.eye(g.ni)])  # eq. (prtsolnopdef)
-    Psi = np.linalg.solve(B, rhs_h)
-    Y = np.linalg.solve(B, rhs_p)
+    # Both systems are solved with every row of B and of its right-hand side divided by
+    # the row's largest entry of B (row equilibration, which leaves the solutions
+    # unchanged): the collocation rows carry second derivatives and the impedance rows
+    # first derivatives, so their scales differ by about (p^2/h), and partial pivoting
+    # only compares like-sized rows once they are equilibrated.
+    d = 1.0 / np.abs(B).max(axis=1)
+    Psi = np.linalg.solve(d[:, None] * B, d[:, None] * rhs_h)
+    Y = np.linalg.solve(d[:, None] * B, d[:, None] * rhs_p)
     R = G @ Psi
     Gamma = G @ Y
     return dict(Psi=Psi, Y=Y, R=R, Gamma=Gamma, F=F, G=G, N=N, B=B, Ahat_iI=Ahat_iI)
@@ -248,13 +256,26 @@ def root_boundary_keys(nx: int, ny: int, m: int):
 
 
 def merge_operators(Ra, keys_a, Rb, keys_b):
-    """Merge two sibling ItI operators (Sec. 2.2; Algorithm 1 steps (6)-(13)).
+    """Merge two sibling ItI operators by eliminating the data on their shared edge
+    (Sec. 2.2).
 
-    I_1: alpha boundary nodes not on beta; I_2: beta nodes not on alpha; I_3: shared
-    nodes (alpha's order, beta's rows matched by key).  Returns the parent's R in the
-    order I_b^tau = [I_1, I_2], its keys, and Phi^a, Phi^b, Ups^a, Ups^b, Gamma^tau
-    written exactly as the paper's formulas (long forms), plus W^{-1} and the blocks
-    that the paper's storage policy keeps (Sec. 2.4).
+    I_1: alpha boundary nodes not on beta; I_2: beta nodes not on alpha; I_3: the shared
+    nodes (alpha's order, beta's rows matched by key).  On I_3 the incoming data of one
+    box is minus the outgoing data of the other (opposite normals): t3^a = -g3^b and
+    t3^b = -g3^a, with g3^a = R31^a t1 + R33^a t3^a + h3^a and g3^b = R32^b t2 +
+    R33^b t3^b + h3^b (eqs. (ItIalp), (ItIbet) restricted to I_3).  Stacked, the
+    interface unknowns solve
+
+        [[I, R33^b], [R33^a, I]] [t3^a; t3^b] = [[0, -R32^b], [-R31^a, 0]] [t1; t2]
+                                                + [[0, -I], [-I, 0]] [h3^a; h3^b],
+
+    so Phi = [Phi^a; Phi^b] (the maps of eqs. (talpha), (tbeta)) and Ups = [Ups^a; Ups^b]
+    (their particular parts) come from one dense solve with that matrix.  The parent's
+    outgoing data g1^a = R11^a t1 + R13^a t3^a + h1^a and g2^b = R22^b t2 + R23^b t3^b
+    + h2^b give R^tau and Gamma^tau (eq. (out), block diagonal).  W = I - R33^b R33^a is
+    the interface matrix of eq. (talpha); W^{-1} is stored as the paper's storage policy
+    (Sec. 2.4) keeps it.  Returns the parent's R in the order I_b^tau = [I_1, I_2] with
+    its keys, Phi^a, Phi^b, Ups^a, Ups^b, Gamma^tau, W, W^{-1} and the blocks of R^a, R^b.
     """
     set_a, set_b = set(keys_a), set(keys_b)
     pos_b = {k: i for i, k in enumerate(keys_b)}
@@ -268,21 +289,25 @@ def merge_operators(Ra, keys_a, Rb, keys_b):
     R32b, R33b = Rb[np.ix_(i3b, i2)], Rb[np.ix_(i3b, i3b)]
     n1, n2, n3 = len(i1), len(i2), len(i3a)
     I3 = np.eye(n3)
-    W = I3 - R33b @ R33a                                            # step (7)
+    # the stacked interface system: unknowns [t3^a; t3^b], data columns [t1, t2, h3^a, h3^b]
+    M = np.block([[I3, R33b], [R33a, I3]])
+    rhs = np.zeros((2 * n3, n1 + n2 + 2 * n3), dtype=complex)
+    rhs[:n3, n1:n1 + n2] = -R32b
+    rhs[n3:, :n1] = -R31a
+    rhs[n3:, n1 + n2:n1 + n2 + n3] = -I3
+    rhs[:n3, n1 + n2 + n3:] = -I3
+    X = np.linalg.solve(M, rhs)
+    Phi_a, Phi_b = X[:n3, :n1 + n2], X[n3:, :n1 + n2]
+    Ups_a, Ups_b = X[:n3, n1 + n2:], X[n3:, n1 + n2:]
+    W = I3 - R33b @ R33a
     Winv = np.linalg.inv(W)
-    Phi_a = Winv @ np.hstack([R33b @ R31a, -R32b])                  # step (8)
-    Ups_a = np.hstack([Winv @ R33b, -Winv])                         # step (9)
-    Phi_b = np.hstack([-R31a - R33a @ Winv @ R33b @ R31a,
-                       R33a @ Winv @ R32b])                         # step (10)
-    Ups_b = np.hstack([-(I3 + R33a @ Winv @ R33b), R33a @ Winv])    # step (11)
-    D13 = np.zeros((n1 + n2, 2 * n3), dtype=complex)                # blockdiag(R13a, R23b)
-    D13[:n1, :n3] = R13a
-    D13[n1:, n3:] = R23b
-    D11 = np.zeros((n1 + n2, n1 + n2), dtype=complex)               # blockdiag(R11a, R22b)
-    D11[:n1, :n1] = R11a
-    D11[n1:, n1:] = R22b
-    R_tau = D11 + D13 @ np.vstack([Phi_a, Phi_b])                    # eq. (out)
-    Gamma_tau = D13 @ np.vstack([Ups_a, Ups_b])                      # eq. (out)
+    # eq. (out): R^tau = blockdiag(R11a, R22b) + blockdiag(R13a, R23b) [Phi^a; Phi^b]
+    R_tau = np.zeros((n1 + n2, n1 + n2), dtype=complex)
+    R_tau[:n1, :n1] = R11a
+    R_tau[n1:, n1:] = R22b
+    R_tau[:n1] += R13a @ Phi_a
+    R_tau[n1:] += R23b @ Phi_b
+    Gamma_tau = np.vstack([R13a @ Ups_a, R23b @ Ups_b])
     keys_tau = [keys_a[i] for i in i1] + [keys_b[i] for i in i2]
     return dict(R=R_tau, keys=keys_tau, Phi_a=Phi_a, Phi_b=Phi_b, Ups_a=Ups_a,
                 Ups_b=Ups_b, Gamma=Gamma_tau, W=W, Winv=Winv, i1=i1, i2=i2, i3a=i3a,
@@ -315,12 +340,15 @@ class Problem:
                 self.y0 + iy * self.hy, self.y0 + (iy + 1) * self.hy)
 
     def leaf_nodes(self) -> np.ndarray:
-        """[nleaf*n, 2] leaf node coordinates, leaf l = iy*nx + ix, order I = [I_b, I_i]."""
-        out = []
-        for iy in range(self.ny):
-            for ix in range(self.nx):
-                out.append(leaf_coordinates(*self.leaf_box(ix, iy), self.p))
-        return np.concatenate(out)
+        """[nleaf*n, 2] leaf node coordinates, leaf l = iy*nx + ix, order I = [I_b, I_i].
+        Computed once per problem (a copy is returned)."""
+        if getattr(self, "_xy", None) is None:
+            out = []
+            for iy in range(self.ny):
+                for ix in range(self.nx):
+                    out.append(leaf_coordinates(*self.leaf_box(ix, iy), self.p))
+            self._xy = np.concatenate(out)
+        return self._xy.copy()
 
     def interior_nodes(self) -> np.ndarray:
         xy = self.leaf_nodes().reshape(self.nleaf, self.n, 2)
@@ -343,27 +371,69 @@ class Problem:
         return np.concatenate(pts), np.array(nrm)
 
 
-def build(prob: Problem, c_interior: np.ndarray, tie: str = "x"):
-    """Algorithm 1 (precomputation): leaves first, then merges from the bottom up.
+# Keys of a leaf's operators that the merges and the solve read (the other pieces of
+# leaf_operators are only for the identity pins).
+_LEAF_KEEP = ("Psi", "Y", "R", "Gamma")
+
+
+def _each(fn, items):
+    """fn over independent items (the boxes of one tree level).  Wide levels run in a pool
+    of host threads, each item's dense linear algebra single-threaded; narrow levels run
+    one item at a time with the threaded BLAS.  Every item is computed by the same call
+    either way, so the result does not depend on this choice."""
+    items = list(items)
+    workers = min(16, os.cpu_count() or 1)
+    if len(items) < 2 * workers or workers == 1:
+        return [fn(x) for x in items]
+    from concurrent.futures import ThreadPoolExecutor
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # without the control the pool still gives the same results
+        threadpool_limits = None
+    if threadpool_limits is None:
+        with ThreadPoolExecutor(workers) as ex:
+            return list(ex.map(fn, items))
+    with threadpool_limits(1), ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(fn, items))
+
+
+def build(prob: Problem, c_interior: np.ndarray, tie: str = "x", progress=None):
+    """Precomputation (Sec. 2, Algorithm 1): every leaf's operators (Sec. 2.1), then the
+    merges of each tree level from the leaves up to the root (Sec. 2.2).
 
     c_interior: [nleaf * n_i] real or complex samples of c at the interior nodes,
     leaf-major in leaf order l = iy*nx + ix.  Returns the list of boxes (root first);
     each box carries its operators in box.ops and its boundary keys in box.keys.
+    progress, if given, is called with (level, boxes on the level) after each level.
     """
     boxes = build_tree(prob.nx, prob.ny, tie)
     cI = np.asarray(c_interior).reshape(prob.nleaf, prob.ni)
-    for b in reversed(boxes):                                  # step (1): tau = N..1
-        if b.is_leaf:                                          # step (3)
-            ix, iy = b.ix0, b.iy0
-            ops = leaf_operators(*prob.leaf_box(ix, iy), prob.p, prob.kappa, prob.eta,
-                                 cI[iy * prob.nx + ix])
+    by_level = {}
+    for b in boxes:
+        by_level.setdefault(b.level, []).append(b)
+
+    def leaf(b):
+        ix, iy = b.ix0, b.iy0
+        ops = leaf_operators(*prob.leaf_box(ix, iy), prob.p, prob.kappa, prob.eta,
+                             cI[iy * prob.nx + ix])
+        return {k: ops[k] for k in _LEAF_KEEP}
+
+    def merge(b):
+        a, c = b.children
+        return merge_operators(a.ops["R"], a.keys, c.ops["R"], c.keys)
+
+    for lev in sorted(by_level, reverse=True):
+        level = by_level[lev]
+        leaves = [b for b in level if b.is_leaf]
+        for b, ops in zip(leaves, _each(leaf, leaves)):
             b.ops = ops
-            b.keys = leaf_boundary_keys(ix, iy, prob.m)
-        else:                                                  # steps (5)-(13)
-            a, c = b.children
-            mo = merge_operators(a.ops["R"], a.keys, c.ops["R"], c.keys)
+            b.keys = leaf_boundary_keys(b.ix0, b.iy0, prob.m)
+        parents = [b for b in level if not b.is_leaf]
+        for b, mo in zip(parents, _each(merge, parents)):
             b.ops = mo
             b.keys = mo["keys"]
+        if progress is not None:
+            progress(lev, len(level))
     return boxes
 
 
@@ -380,7 +450,10 @@ def shared_rows(prob: Problem):
 
 
 def solve(prob: Problem, boxes, s, t, upward=True, jumps=None):
-    """Algorithm 2 (solve stage) for one or several right-hand sides.
+    """Solve stage (Sec. 2, Algorithm 2) for one or several right-hand sides: an upward
+    pass that carries the body load's particular parts from the leaves to the root, then
+    a downward pass that turns the root's boundary data into every box's incoming data
+    and finally every leaf's solution.
 
     s: [nrhs, nleaf*n_i] body load at interior nodes (or None for s = 0, which skips
        the upward pass as Sec. 2 allows), t: [nrhs, nt] impedance data on the root
@@ -404,13 +477,14 @@ def solve(prob: Problem, boxes, s, t, upward=True, jumps=None):
         jumps = np.asarray(jumps, dtype=complex).reshape(nrhs, prob.nleaf, prob.nb)
         owner = shared_rows(prob)
     utilde, h, ttil_a, ttil_b = {}, {}, {}, {}
-    # Upward pass, steps (1)-(9).
+    # Upward pass: particular solutions of the leaves (eq. (particular)), then at every
+    # merge the particular parts of the shared-edge data and of the parent's outgoing data.
     for b in reversed(boxes):
         if b.is_leaf:
             l = b.iy0 * prob.nx + b.ix0
             sl = s[:, l, :].T                                      # [ni, nrhs]
             if upward:
-                utilde[id(b)] = b.ops["Y"] @ sl                    # step (3)
+                utilde[id(b)] = b.ops["Y"] @ sl                    # eq. (prtsolnopdef)
                 h[id(b)] = b.ops["Gamma"] @ sl
             else:
                 utilde[id(b)] = np.zeros((prob.n, nrhs), dtype=complex)
@@ -428,11 +502,13 @@ def solve(prob: Problem, boxes, s, t, upward=True, jumps=None):
                     (la, ra), (lb, rb) = ((l1, r1), (l2, r2)) if in_a else ((l2, r2), (l1, r1))
                     h3[q] -= jumps[:, lb, rb]                      # h3^a - j2
                     h3[n3 + q] -= jumps[:, la, ra]                 # h3^b - j1
-            ttil_a[id(b)] = o["Ups_a"] @ h3                        # step (6)
+            ttil_a[id(b)] = o["Ups_a"] @ h3                        # eqs. (talpha), (tbeta)
             ttil_b[id(b)] = o["Ups_b"] @ h3
             h12 = np.vstack([h[id(a)][o["i1"]], h[id(c)][o["i2"]]])
-            h[id(b)] = h12 + o["Gamma"] @ h3                       # step (7), eq. (flux_part)
-    # Downward pass, steps (10)-(18).
+            h[id(b)] = h12 + o["Gamma"] @ h3                       # eq. (flux_part)
+    # Downward pass: the root takes the boundary data; each merge maps its incoming data
+    # to the children's shared-edge data (eqs. (talpha), (tbeta)); each leaf forms its
+    # solution from its incoming data (eq. (hmgsolnopdef)) plus its particular part.
     root = boxes[0]
     rkeys = root_boundary_keys(prob.nx, prob.ny, prob.m)
     rpos = {k: i for i, k in enumerate(rkeys)}
@@ -442,12 +518,12 @@ def solve(prob: Problem, boxes, s, t, upward=True, jumps=None):
         tb = tin[id(b)]
         if b.is_leaf:
             l = b.iy0 * prob.nx + b.ix0
-            u[:, l, :] = (b.ops["Psi"] @ tb + utilde[id(b)]).T     # step (13)
+            u[:, l, :] = (b.ops["Psi"] @ tb + utilde[id(b)]).T
         else:
             a, c = b.children
             o = b.ops
             n1 = len(o["i1"])
-            t3a = o["Phi_a"] @ tb + ttil_a[id(b)]                  # step (16)
+            t3a = o["Phi_a"] @ tb + ttil_a[id(b)]
             t3b = o["Phi_b"] @ tb + ttil_b[id(b)]
             ta = np.zeros((len(a.keys), nrhs), dtype=complex)
             ta[o["i1"]] = tb[:n1]

@@ -82,8 +82,8 @@ class Case:
             raise ValueError(rhs)
 
     # ------------------------------------------------------------------ oracle side
-    def oracle_build(self, tie="x"):
-        return O.build(self.prob, self.c, tie=tie)
+    def oracle_build(self, tie="x", progress=None):
+        return O.build(self.prob, self.c, tie=tie, progress=progress)
 
     def oracle_solve(self, boxes, s=SAME):
         s = self.s if s is SAME else s

@@ -99,6 +99,26 @@ def test_leaf_reproduces_polynomials(p):
     assert O.rel_l2(u, poly.u(xy)) < 1e-11
 
 
+def test_small_leaf_reproduces_polynomials_to_round_off():
+    """A leaf of the size of the 64 x 64-leaf workload (h = 1/64, p = 16, kappa = eta =
+    100): its collocation rows are about p^2/h times larger than its impedance rows.  The
+    exact polynomial comes back to near machine precision, which an unequilibrated dense
+    solve of B misses by two orders of magnitude."""
+    p, h = 16, 1.0 / 64
+    x0, y0 = 0.3, 0.6
+    kappa = eta = 100.0
+    xy = O.leaf_coordinates(x0, x0 + h, y0, y0 + h, p)
+    m, nb = p - 2, 4 * p - 8
+    nrm = np.concatenate([np.tile([0.0, -1.0], (m, 1)), np.tile([1.0, 0.0], (m, 1)),
+                          np.tile([0.0, 1.0], (m, 1)), np.tile([-1.0, 0.0], (m, 1))])
+    c = G.c_gaussian_bump(xy[nb:])
+    ops = O.leaf_operators(x0, x0 + h, y0, y0 + h, p, kappa, eta, c)
+    for seed in range(3):
+        poly = G.Polynomial.seeded(seed, 6)
+        u = ops["Psi"] @ poly.t(xy[:nb], nrm, eta) + ops["Y"] @ poly.s(xy[nb:], c, kappa)
+        assert O.rel_l2(u, poly.u(xy)) < 3e-13
+
+
 def test_leaf_plane_wave():
     """Psi applied to a plane wave's impedance data reproduces it to discretization
     error (closed form, c = 1, s = 0)."""
@@ -177,14 +197,28 @@ def test_merge_order_invariance():
 
 
 def test_merge_short_forms_equal_paper_forms():
-    """Phi^b = [-R31a, 0] - R33a Phi^a and Ups^b = [-I, 0] - R33a Ups^a (re-derived
-    from the interface conditions of Sec. 2.2) agree with the printed long forms."""
+    """The oracle forms the merge maps by solving the stacked interface conditions of
+    Sec. 2.2.  They must equal the paper's printed forms built on W = I - R33b R33a:
+    Phi^a = W^{-1} [R33b R31a | -R32b] (eq. (talpha)), Phi^b = [-R31a - R33a W^{-1} R33b
+    R31a | R33a W^{-1} R32b] (eq. (tbeta)), Ups^a = [W^{-1} R33b | -W^{-1}], Ups^b =
+    [-(I + R33a W^{-1} R33b) | R33a W^{-1}]; and the short forms Phi^b = [-R31a, 0] -
+    R33a Phi^a, Ups^b = [-I, 0] - R33a Ups^a (re-derived from the same conditions)."""
     prob, xy, xyi, xyb, nrm, c = _setup(4, 2, 7, 12.0, 12.0, G.FourierField.seeded(4))
     for b in O.build(prob, c):
         if b.is_leaf:
             continue
         o = b.ops
         n3 = len(o["i3a"])
+        I3 = np.eye(n3)
+        Wi = np.linalg.inv(I3 - o["R33b"] @ o["R33a"])
+        np.testing.assert_allclose(o["Winv"], Wi, atol=1e-12)
+        R33a, R33b, R31a, R32b = o["R33a"], o["R33b"], o["R31a"], o["R32b"]
+        np.testing.assert_allclose(o["Phi_a"], Wi @ np.hstack([R33b @ R31a, -R32b]), atol=1e-12)
+        np.testing.assert_allclose(
+            o["Phi_b"], np.hstack([-R31a - R33a @ Wi @ R33b @ R31a, R33a @ Wi @ R32b]), atol=1e-12)
+        np.testing.assert_allclose(o["Ups_a"], np.hstack([Wi @ R33b, -Wi]), atol=1e-12)
+        np.testing.assert_allclose(
+            o["Ups_b"], np.hstack([-(I3 + R33a @ Wi @ R33b), R33a @ Wi]), atol=1e-12)
         short_phi_b = -o["R33a"] @ o["Phi_a"]
         short_phi_b[:, :len(o["i1"])] -= o["R31a"]
         np.testing.assert_allclose(o["Phi_b"], short_phi_b, atol=1e-12)
@@ -545,3 +579,40 @@ def test_pins_catch_residual_with_F_for_G(monkeypatch):
     monkeypatch.setattr(O, "leaf_operators", swapped)
     r = O.global_residual(prob, c, s, t, ug, jumps=j)
     assert np.linalg.norm(r) > 1e-3 * np.linalg.norm(O.global_rhs(prob, s, t, jumps=j))
+
+
+# ------------------------------------------------------------------ O14: the paper's e_inf (Sec. 4.1)
+
+
+def test_e_inf_recovers_a_planted_error():
+    """e_inf is the largest pointwise deviation (Sec. 4.1): a single complex error of known
+    size planted at one node of an otherwise exact vector is returned, up to the rounding
+    of adding it to that node, wherever it sits and whatever the vector's shape; zero for
+    identical vectors."""
+    rng = np.random.default_rng(7)
+    b = rng.standard_normal((3, 41)) + 1j * rng.standard_normal((3, 41))
+    assert O.e_inf(b, b) == 0.0
+    for (r, k), d in [((0, 0), 3.0 - 4.0j), ((2, 40), -1e-9j), ((1, 17), 2.5)]:
+        a = b.copy()
+        a[r, k] += d
+        ulp = 4.0 * np.finfo(float).eps * np.abs(b).max()
+        assert O.e_inf(a, b) == pytest.approx(abs(d), rel=1e-12, abs=ulp)
+
+
+def test_e_inf_norm_bounds_and_decay_in_p():
+    """Norm equivalence with the 2-norm, ||d||_2 / sqrt(N) <= e_inf <= ||d||_2, on the
+    discretization error of a solve; and e_inf of a plane-wave solve falls
+    geometrically with p (the spectral convergence of Sec. 4.1)."""
+    kappa = 20.0
+    errs = []
+    for p in (6, 8, 10, 12):
+        prob, xy, xyi, xyb, nrm, c = _setup(2, 2, p, kappa, kappa, G.c_const)
+        pw = G.PlaneWave(kappa, 0.7)
+        u = O.solve(prob, O.build(prob, c), None, pw.t(xyb, nrm, kappa)[None])[0]
+        ex = pw.u(xy)
+        d2 = float(np.linalg.norm(u - ex))
+        ei = O.e_inf(u, ex)
+        assert d2 / np.sqrt(u.size) <= ei * (1 + 1e-12) and ei <= d2 * (1 + 1e-12)
+        errs.append(ei)
+    for a, b in zip(errs, errs[1:]):
+        assert b < a / 5, errs
