@@ -196,6 +196,22 @@ int hps_build(const hps_domain* dom, int32_t p, double kappa, double eta_re,
  * Errors: HPS_E_INVALID (NULL factor/t/u, nrhs < 1), HPS_E_NOMEM, HPS_E_DEVICE. */
 int hps_solve(hps_factor* f, int32_t nrhs, const double* s, const double* t, double* u);
 
+/* Allocation-free solve, for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Arguments,
+ * results and errors as hps_solve; in addition it calls no hipMalloc, hipFree or
+ * allocating library routine.  Its workspace is carved from a fixed device array of
+ * HPS_NOALLOC_SCRATCH_BYTES (64 MiB) that the library holds on every GPU it runs on until
+ * the process ends (the array's device address is looked up once per device, on the
+ * first call there).  A call whose workspace exceeds that size (the upward sweep's
+ * vectors grow with nrhs and the leaf count; mixed precision adds the correction's
+ * residual) fails with HPS_E_INVALID and enqueues nothing.  Every call on one GPU uses
+ * the same array, which keeps the last call's contents (nothing is read before it is
+ * written): calls that overlap on one GPU -- several streams or host threads -- race, and
+ * the caller must order them.  opts.profile records are not taken. */
+#define HPS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int hps_solve_noalloc(hps_factor* f, int32_t nrhs, const double* s, const double* t,
+                      double* u);
+
 /* Cross-problem batching (not in the paper; the paper's parallelism is over the boxes
  * of one problem).  Builds nprob independent problems; problems with the same domain,
  * leaf grid and p are factored together, every leaf and merge-level launch covering all

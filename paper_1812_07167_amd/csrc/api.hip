@@ -20,6 +20,13 @@
 #include "kernels.hpp"
 #include "serve_hooks.hpp"
 
+// Device memory of the allocation-free solve (hps_solve_noalloc): a fixed array that every
+// GPU the library runs on holds until the process ends.  Host code never passes the
+// array's name to a kernel or a copy: it uses the device address that
+// hipGetSymbolAddress returns for the current device (noalloc_scratch below).
+constexpr size_t kNoAllocScratch = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratch];
+
 namespace hps {
 namespace {
 
@@ -1032,6 +1039,10 @@ struct Arena {
   size_t used = 0, split_need = 0, peak = 0, cap = 0;
   void* split = nullptr;
   void* block = nullptr;
+  // caller-provided memory of fixed_cap bytes (the allocation-free solve): allocate()
+  // carves the workspace from it and allocates nothing
+  char* fixed = nullptr;
+  size_t fixed_cap = 0;
   double* get(size_t bytes) {
     bytes = (bytes + 255) & ~size_t(255);
     size_t off = used;
@@ -1054,8 +1065,16 @@ struct Arena {
     used = std::max(used, peak);
     cap = used;
     size_t total = used + split_need + 256;
-    block = ws_alloc(total, st);
-    base = static_cast<char*>(block);
+    if (fixed) {
+      if (total > fixed_cap)
+        throw Error(HPS_E_INVALID, "solve workspace of " + std::to_string(total) +
+                                       " bytes exceeds the allocation-free scratch of " +
+                                       std::to_string(fixed_cap) + " bytes");
+      base = fixed;
+    } else {
+      block = ws_alloc(total, st);
+      base = static_cast<char*>(block);
+    }
     split = base + ((used + 255) & ~size_t(255));
     used = 0;
     dry = false;
@@ -1072,7 +1091,7 @@ void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const d
                 const double* jmp, double* u, Arena& ws) {
   hipStream_t st = ws.st;
   Profiler& pr = f.solve_prof;
-  pr.reset(!ws.dry && f.opts.profile != 0, st);
+  pr.reset(!ws.dry && !ws.fixed && f.opts.profile != 0, st);
   const char* nm = "solve_leaf_up";
   const long nl = (long)np * f.nl1, n = f.n, nb = f.nb, ni = f.ni;
   const long h0 = (long)pb * f.nl1;  // first leaf of the range
@@ -1431,6 +1450,24 @@ int hps_build_batch(int32_t nprob, const hps_domain* doms, const int32_t* p,
 namespace hps {
 namespace {
 
+// Device address of the scratch array on the current device, looked up once per device
+// (each GPU holds its own copy of the array, at its own address).
+char* noalloc_scratch() {
+  static std::mutex mu;
+  static std::vector<char*> addr;
+  int dev = 0;
+  HPS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    HPS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Error(HPS_E_DEVICE, "no device address for the allocation-free scratch");
+    addr[dev] = static_cast<char*>(p);
+  }
+  return addr[dev];
+}
+
 ResidualDesc residual_desc(const hps_group& f, int pb, int np, int nrhs, const double* s,
                            const double* t, const double* jmp, const double* u) {
   ResidualDesc r;
@@ -1453,13 +1490,15 @@ int refine_iters(const hps_group& f) {
 // estimate of the next one, is <= tol, or the iteration limit.
 void solve_impl(hps_group& f, int pb, int np, int nrhs, const double* s, const double* t,
                 const double* jmp, double* u, hipStream_t st, hps_solve_info* info,
-                size_t* ws_bytes = nullptr) {
+                size_t* ws_bytes = nullptr, char* fixed = nullptr, size_t fixed_cap = 0) {
   const int iters = refine_iters(f);
   const long nl = (long)np * f.nl1, n = f.n, nb = f.nb, ni = f.ni;
   const long nt = 2L * (f.nx + f.ny) * f.m;
   const int nblk = norms_blocks();
   Arena ws;
   ws.st = st;
+  ws.fixed = fixed;
+  ws.fixed_cap = fixed_cap;
   double *rs = nullptr, *rt = nullptr, *rj = nullptr, *dl = nullptr, *part = nullptr;
   size_t mark = 0;
   for (int pass = 0; pass < 2; ++pass) {
@@ -1553,6 +1592,19 @@ int hps_solve(hps_factor* f, int32_t nrhs, const double* s, const double* t, dou
     if (nrhs < 1) throw Error(HPS_E_INVALID, "nrhs must be >= 1");
     hps_group& G = *f->g;
     solve_impl(G, f->b0, 1, nrhs, s, t, nullptr, u, G.stream, &G.last_info);
+  });
+}
+
+int hps_solve_noalloc(hps_factor* f, int32_t nrhs, const double* s, const double* t,
+                      double* u) {
+  return guard([&] {
+    if (!f) throw Error(HPS_E_INVALID, "factor is NULL");
+    if (!t || !u) throw Error(HPS_E_INVALID, "t and u must be non-NULL");
+    if (nrhs < 1) throw Error(HPS_E_INVALID, "nrhs must be >= 1");
+    hps_group& G = *f->g;
+    char* base = noalloc_scratch();
+    solve_impl(G, f->b0, 1, nrhs, s, t, nullptr, u, G.stream, &G.last_info, nullptr, base,
+               kNoAllocScratch);
   });
 }
 

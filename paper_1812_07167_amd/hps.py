@@ -22,6 +22,7 @@ OP_PSI, OP_Y, OP_R, OP_WINV, OP_PHI_A, OP_PHI_B, OP_R33A, OP_R33B, OP_R13A, OP_R
 EXPORTS = [
     "hps_last_error", "hps_version", "hps_default_opts", "hps_nodes", "hps_build",
     "hps_build_batch", "hps_solve", "hps_solve_batch", "hps_solve_jumps", "hps_residual",
+    "hps_solve_noalloc",
     "hps_last_solve_info", "hps_factor_query",
     "hps_factor_get", "hps_factor_box", "hps_stage_times", "hps_free", "hps_estimate_bytes",
     "hps_release_cached", "hps_set_allocator", "hps_autotune_entries", "hps_autotune_clear",
@@ -120,6 +121,7 @@ def load(path: str = LIB_PATH):
     lib.hps_nodes.argtypes = [C.POINTER(Domain), I32, P, P, P, P]
     lib.hps_build.argtypes = [C.POINTER(Domain), I32, D, D, D, P, C.POINTER(Opts), C.POINTER(P)]
     lib.hps_solve.argtypes = [P, I32, P, P, P]
+    lib.hps_solve_noalloc.argtypes = [P, I32, P, P, P]
     lib.hps_solve_jumps.argtypes = [P, I32, P, P, P, P]
     lib.hps_build_batch.argtypes = [I32, P, P, P, P, P, P, C.POINTER(Opts), P]
     lib.hps_solve_batch.argtypes = [I32, P, P, P, P, P]
@@ -152,6 +154,7 @@ def load(path: str = LIB_PATH):
     lib.hps_server_destroy.argtypes = [P]
     lib.hps_server_destroy.restype = None
     for name in ["hps_nodes", "hps_build", "hps_build_batch", "hps_solve", "hps_solve_batch",
+                 "hps_solve_noalloc",
                  "hps_solve_jumps", "hps_residual",
                  "hps_last_solve_info", "hps_factor_query", "hps_factor_get", "hps_factor_box",
                  "hps_stage_times", "hps_estimate_bytes", "hps_release_cached",
@@ -361,6 +364,19 @@ def hps_solve(f: Factor, t, s=None, u=None):
     _check(load().hps_solve(f.h, nrhs, sp, _dev_ptr(t, "torch.complex128"),
                             _dev_ptr(u, "torch.complex128")))
     return u
+
+
+def hps_solve_noalloc(f: Factor, t, u, s=None):
+    """As hps_solve, through the allocation-free entry point: the caller passes u
+    (complex128 device tensor [nrhs, n_leaf_nodes]); the library allocates nothing."""
+    nrhs = t.shape[0]
+    sp = _dev_ptr(s, "torch.complex128") if s is not None else None
+    _check(load().hps_solve_noalloc(f.h, nrhs, sp, _dev_ptr(t, "torch.complex128"),
+                                    _dev_ptr(u, "torch.complex128")))
+    return u
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def hps_solve_jumps(f: Factor, t, s=None, jumps=None, u=None):
