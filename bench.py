@@ -73,7 +73,52 @@ def kernel_of(stage, p):
             return "zgemm_kernel<float, %d, %d, %d, %d, false, false, %d>" % (bm, bn, wr, wc, bk), "mfma32"
         return "zgemm_kernel<double, %d, %d, %d, %d, %s, %s, %d>" % (bm, bn, wr, wc, ar, br, bk), "mfma"
     return {"leaf_sinv": ("leaf_sinv_kernel<%d>" % p, "alu"),
-            "leaf_psi_bnd": ("leaf_psi_bnd_kernel<%d>" % p, "hbm")}.get(base)
+            "leaf_psi_bnd": ("leaf_psi_bnd_kernel<%d>" % p, "hbm"),
+            "leaf_ainv": ("leaf_ainv_kernel<%d>" % p, "alu"),
+            "leaf_xz": ("leaf_xz_kernel<%d>" % p, "hbm")}.get(base)
+
+
+def merge_levels(nx, ny, p):
+    """(nbox, n1, n2, n3) per merge level, root first: the tree splits a box of wx x wy
+    leaves across its longer side (ties split x); the shared edge holds n3 nodes and the
+    children's outer boundaries n1 and n2."""
+    m = p - 2
+    out, boxes = [], [(nx, ny)]
+    while boxes and max(max(b) for b in boxes) > 1:
+        nxt, lev = [], []
+        for wx, wy in boxes:
+            split_x = True if wy == 1 else False if wx == 1 else wx >= wy
+            if split_x:
+                c = (wx // 2, wy)
+                n3 = wy * m
+            else:
+                c = (wx, wy // 2)
+                n3 = wx * m
+            n1 = 2 * (c[0] + c[1]) * m - n3
+            lev.append((n1, n1, n3))
+            nxt += [c, c]
+        out.append((len(boxes),) + lev[0])
+        boxes = nxt
+    return out
+
+
+def survey_work(nx, ny, p, nrhs):
+    """Algorithmic work of one step by the survey's per-unit formulas (Sec. 8(d)): the leaf
+    stage F_leaf per leaf (real c, block elimination, Psi and Y formed), the merge stage
+    F_merge per merge (LU-count interface solve, no explicit-inverse flops), and the bytes
+    of one solve call with a body load (operators read once, s and u moved once)."""
+    m = p - 2
+    ni, nb, n = m * m, 4 * m, p * p - 4
+    nleaf = nx * ny
+    f_leaf = 2 * ni ** 3 + 8 * ni ** 2 * nb + 2 * nb ** 2 * ni + 8 * nb ** 3 + 8 * ni * nb ** 2
+    f_merge, ops_merge = 0.0, 0.0
+    for nbox, n1, n2, n3 in merge_levels(nx, ny, p):
+        f_merge += nbox * (8 * n3 ** 3 + 8.0 / 3.0 * n3 ** 3 + 8 * n3 ** 2 * n1 +
+                           16 * n3 ** 2 * (n1 + n2) + 8 * n3 * (n1 + n2) ** 2)
+        ops_merge += nbox * (3 * n3 ** 2 + 3 * n3 * (n1 + n2))
+    solve_bytes = 16.0 * (nleaf * n * n + ops_merge + nrhs * nleaf * (ni + n))
+    return {"F_leaf_per_leaf": f_leaf, "F_leaf": f_leaf * nleaf, "F_merge": f_merge,
+            "solve_bytes": solve_bytes}
 
 
 def log(*a):
@@ -611,6 +656,33 @@ def main():
                 "algorithmic_unit": "bytes" if bound == "hbm" else "flops",
                 "algorithmic_bytes_per_launch": by / launches}
 
+    # stage-level roofline fractions by the survey's algorithmic work (Sec. 8(d)): the leaf
+    # stage (F_leaf), the merge stage (F_merge over W, its LU-count solve, Phi and R^tau;
+    # gathers included in the time) and the 16-RHS solve (operator and vector bytes)
+    work = survey_work(nx, ny, p, nrhs)
+
+    def stage_ms(prefixes, recs):
+        return sum(v[2] for v in recs if v[0].split("@")[0].split("[")[0].startswith(prefixes))
+
+    leaf_ms = stage_ms(("leaf_",), stages_b)
+    merge_ms = stage_ms(("merge_",), stages_b)
+    solve_ms_p = stage_ms(("solve_",), stages_s)
+    stage_roofline = {
+        "leaf": {"algorithmic_flops": work["F_leaf"], "per_leaf": work["F_leaf_per_leaf"],
+                 "ms": round(leaf_ms, 3),
+                 "achieved_tflops": round(work["F_leaf"] / (leaf_ms * 1e-3) / 1e12, 3),
+                 "peak_tflops": 78.6,
+                 "frac": round(work["F_leaf"] / (leaf_ms * 1e-3) / 78.6e12, 4)},
+        "merge": {"algorithmic_flops": work["F_merge"], "ms": round(merge_ms, 3),
+                  "achieved_tflops": round(work["F_merge"] / (merge_ms * 1e-3) / 1e12, 3),
+                  "peak_tflops": 78.6,
+                  "frac": round(work["F_merge"] / (merge_ms * 1e-3) / 78.6e12, 4)},
+        "solve": {"algorithmic_bytes": work["solve_bytes"], "ms": round(solve_ms_p, 3),
+                  "achieved_gbs": round(work["solve_bytes"] / (solve_ms_p * 1e-3) / 1e9, 1),
+                  "peak_gbs": 8000.0,
+                  "frac": round(work["solve_bytes"] / (solve_ms_p * 1e-3) / 8e12, 4)},
+    }
+
     out = {
         "metric": METRIC,
         "value": round(dof / (ms_per_step * 1e-3), 1),
@@ -633,6 +705,7 @@ def main():
         "autotune": {"gemm_shapes_tuned": H.autotune_entries(),
                      "tuning_build_s": None if tune_s is None else round(tune_s, 3)},
         "roofline": roofline,
+        "stage_roofline": stage_roofline,
         "stages_ms": {k: round(v[1], 3) for k, v in groups.items()},
     }
     if not args.no_batch:

@@ -100,6 +100,17 @@ typedef struct {
                              the recorded variant of a shape, else the default choice
                              (default 0).  Not in the paper: the analog of its per-level
                              calibration of thread counts (Sec. 3).                      */
+  int32_t leaf_route;      /* how the leaf operators of Sec. 2.1 are formed (both give B^{-1}
+                             of eqs. (homogeneous), (particular) to round-off):
+                             0 = automatic (default): per problem, the interior Dirichlet
+                             block A = Ahat(I_i, I_i) is inverted in real arithmetic and the
+                             boundary unknowns eliminated after it when kappa^2 max(c) is at
+                             most half of pi^2 (1/h_x^2 + 1/h_y^2), the smallest eigenvalue of
+                             a leaf's Dirichlet Laplacian (A is then safely invertible);
+                             otherwise the boundary unknowns are eliminated first through the
+                             impedance rows and the complex interior Schur complement is
+                             inverted.
+                             1 = the impedance-row elimination for every problem.          */
 } hps_opts;
 
 /* Outcome of the most recent solve on a factor (hps_last_solve_info). */

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhps.so")
-SOURCES = ["gemm.hip", "zinv.hip", "leaf.hip", "merge.hip", "solve.hip", "residual.hip", "api.hip",
+SOURCES = ["gemm.hip", "zinv.hip", "leaf.hip", "leaf_dir.hip", "merge.hip", "solve.hip", "residual.hip", "api.hip",
            "server.hip"]
 ARCH = "gfx950"
 FLAGS = [

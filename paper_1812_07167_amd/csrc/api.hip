@@ -293,6 +293,10 @@ struct hps_group {
   const long* pxoff = nullptr;      // leaf -> offset of its interior nodes in s
   const long* puoff = nullptr;      // leaf -> offset of its nodes in u
   hps::DevBuf dD, dLT;
+  hps::DevBuf dRT;                         // [nprob] real line tables of the Dirichlet route
+  hps::DevBuf droute;                      // [nprob] int: 1 = Dirichlet-block leaf route
+  hps::DevBuf dcmax;                       // [nprob] largest c of each problem (route test)
+  std::vector<int> route_h;                // host copy of droute
   hps::DevBuf ops;                         // arena: [Psi | Y] of every leaf + merge operators
   hps::View BI;                            // [nleaf][n*n] complex128 [Psi | Y] (complex128
                                            // precision only)
@@ -307,7 +311,8 @@ struct hps_group {
   hps::DevBuf dc;                          // c at the interior nodes (for the FP64 residual)
   hps_solve_info last_info{};              // of the most recent solve
   size_t bytes() const {
-    size_t t = ops.bytes + (shape ? shape->bytes : 0) + dD.bytes + dLT.bytes + rbuf[0].bytes +
+    size_t t = ops.bytes + (shape ? shape->bytes : 0) + dD.bytes + dLT.bytes + dRT.bytes +
+               droute.bytes + dcmax.bytes + rbuf[0].bytes +
                rbuf[1].bytes + dc.bytes;
     for (auto& r : rkeep) t += r.bytes;
     return t + dprm.bytes;
@@ -476,6 +481,7 @@ void make_plan(hps_group& f) {
 
 // ------------------------------------------------------------------ leaf line tables
 void leaf_table_one(const hps_group& f, const double* all, double er, double ei, double* out);
+void leaf_rtables(hps_group& f, const double* all);
 // The leaf stage eliminates the boundary nodes through the impedance rows F = N + i eta
 // (Sec. 2.1).  F_bb couples only the two end nodes of a grid line: (S_i, N_i) through
 // the first and last rows of D_y, (W_j, E_j) through those of D_x.  With their 2 x 2
@@ -497,6 +503,49 @@ void leaf_tables(hps_group& f, const double* all) {
   for (int b = 0; b < f.nprob; ++b)
     leaf_table_one(f, all, f.prm_h[4 * b + 1], f.prm_h[4 * b + 2], flat.data() + (size_t)2 * len * b);
   upload(f.dLT, flat);
+}
+
+// Real line tables of the Dirichlet-block leaf route (leaf_dir.hip), the same for every
+// problem of a group (they depend on p and the leaf size only): the interior parts of
+// D_xx, D_yy; the A_ib coefficients -D_yy(j, 0), -D_yy(j, p-1), -D_xx(i, 0), -D_xx(i, p-1);
+// the N_i coefficients -D_y(0, j), D_y(p-1, j), -D_x(0, i), D_x(p-1, i) (interior j, i);
+// and N_bb on the two ends of a line, rows and columns (S, N), then (W, E).
+void leaf_rtables(hps_group& f, const double* all) {
+  const int p = f.p, m = f.m;
+  const double* Dx1 = all;
+  const double* Dy1 = all + p * p;
+  const double* Dxx = all + 2 * p * p;
+  const double* Dyy = all + 3 * p * p;
+  auto at = [p](const double* A, int i, int k) { return A[i + p * k]; };
+  std::vector<double> one((size_t)leaf_rtable_len(p));
+  double* Lx = one.data();
+  double* Ly = Lx + m * m;
+  double* t = Ly + m * m;
+  for (int i = 1; i <= m; ++i)
+    for (int k = 1; k <= m; ++k) {
+      Lx[(i - 1) + m * (k - 1)] = at(Dxx, i, k);
+      Ly[(i - 1) + m * (k - 1)] = at(Dyy, i, k);
+    }
+  for (int j = 1; j <= m; ++j) {
+    t[0 * m + j - 1] = -at(Dyy, j, 0);
+    t[1 * m + j - 1] = -at(Dyy, j, p - 1);
+    t[2 * m + j - 1] = -at(Dxx, j, 0);
+    t[3 * m + j - 1] = -at(Dxx, j, p - 1);
+    t[4 * m + j - 1] = -at(Dy1, 0, j);
+    t[5 * m + j - 1] = at(Dy1, p - 1, j);
+    t[6 * m + j - 1] = -at(Dx1, 0, j);
+    t[7 * m + j - 1] = at(Dx1, p - 1, j);
+  }
+  double* fy = t + 8 * m;
+  double* fx = fy + 4;
+  fy[0] = -at(Dy1, 0, 0); fy[1] = -at(Dy1, 0, p - 1);
+  fy[2] = at(Dy1, p - 1, 0); fy[3] = at(Dy1, p - 1, p - 1);
+  fx[0] = -at(Dx1, 0, 0); fx[1] = -at(Dx1, 0, p - 1);
+  fx[2] = at(Dx1, p - 1, 0); fx[3] = at(Dx1, p - 1, p - 1);
+  std::vector<double> flat;
+  flat.reserve(one.size() * f.nprob);
+  for (int b = 0; b < f.nprob; ++b) flat.insert(flat.end(), one.begin(), one.end());
+  upload(f.dRT, flat);
 }
 
 // the line table of one problem (eta = er + i ei) into out (2 * leaf_table_len doubles)
@@ -677,6 +726,7 @@ void upload_tables(hps_group& f) {
     }
   upload(f.dD, all);
   leaf_tables(f, all.data());
+  leaf_rtables(f, all.data());
   upload(f.dprm, f.prm_h);
 }
 
@@ -752,12 +802,28 @@ size_t arena_layout(hps_group& f, char* base) {
   return c.used;
 }
 
+// Leaf-stage scratch of one chunk of leaves (byte offsets): the impedance route's
+// inverse copies (mg), in mixed precision the chunk's complex128 [Psi | Y] (bi), then the
+// Dirichlet route's X (n_i x n_b) and Z (n_b x n_i) per leaf.  Both routes may run on
+// one chunk (problems of one group can take different routes), so both are laid out.
+struct LeafScratch {
+  size_t mg = 0, bi = 0, x = 0, z = 0, total = 0;
+};
+LeafScratch leaf_scratch(const hps_group& f) {
+  auto r256 = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t lch = (size_t)leaf_chunk(f), n = f.n, ni = f.ni, nb = f.nb;
+  LeafScratch L;
+  L.mg = 0;
+  L.bi = r256(leaf_scratch_bytes(f.p, (long)lch));
+  L.x = L.bi + (f.mixed ? r256(lch * n * n * 16) : 0);
+  L.z = L.x + r256(lch * ni * nb * 8);
+  L.total = L.z + r256(lch * nb * ni * 8);
+  return L;
+}
+
 // Bytes of the build scratch (leaf chunks and merge levels; the info words follow).
 size_t scratch_bytes(const hps_group& f) {
-  const long nl = f.nleaf, n = f.n;
-  const long lch = leaf_chunk(f);
-  size_t level_bytes = leaf_scratch_bytes(f.p, lch) +
-                       (f.mixed ? (size_t)lch * n * n * 16 + 256 : 0);
+  size_t level_bytes = leaf_scratch(f).total;
   for (auto& P : f.lv) {
     Carver c;
     const size_t e = P.c64 ? 8 : 16;
@@ -786,7 +852,8 @@ void estimate_bytes(hps_group& f, size_t* peak, size_t* resident) {
   // leaf maps (int grid index, long x/u offsets), c, the four p x p differentiation
   // matrices, per-problem parameters and line tables, then the level maps
   size_t small = (size_t)f.nleaf * (4 + 16) + (size_t)f.nleaf * f.ni * 8 + (size_t)32 * f.p * f.p +
-                 (size_t)32 * f.nprob + (size_t)f.nprob * leaf_table_len(f.p) * 16;
+                 (size_t)32 * f.nprob + (size_t)f.nprob * leaf_table_len(f.p) * 16 +
+                 (size_t)f.nprob * (leaf_rtable_len(f.p) * 8 + sizeof(int) + sizeof(double));
   for (auto& P : f.lv)
     small += 4 * (P.codeA.size() + P.codeB.size() + P.perm.size() + P.i1a.size() +
                   P.i3a.size() + P.i2b.size() + P.i3b.size() + P.ja.size() + P.jb.size());
@@ -848,6 +915,33 @@ void level_scratch(const LevelPlan& P, BuildScratch& sc) {
 }
 
 // ------------------------------------------------------------------ build
+// Route of each problem's leaves.  The Dirichlet-block route (leaf_dir.hip: real A^{-1},
+// a quarter of the complex inversion) needs the interior block A = -Lap_h - kappa^2 c to
+// be safely invertible: -Lap - kappa^2 c is coercive on a leaf when kappa^2 c stays below
+// the smallest eigenvalue pi^2 (1/h_x^2 + 1/h_y^2) of the leaf's Dirichlet Laplacian, and
+// the route is taken when kappa^2 max(c) is at most half of it.  Otherwise (leaves of a
+// wavelength or more, where kappa^2 c can meet a Dirichlet eigenvalue) the impedance
+// route eliminates through the impedance rows, which stay well posed for Re eta != 0.
+// opts.leaf_route = 1 takes the impedance route for every problem.
+void choose_routes(hps_group& f, const double* c) {
+  f.route_h.assign(f.nprob, 0);
+  if (!f.dcmax.p) f.dcmax.alloc((size_t)f.nprob * sizeof(double));
+  if (f.opts.leaf_route != 1) {
+    leaf_cmax(c, f.nprob, (long)f.nl1 * f.ni, f.dcmax.d(), f.stream);
+    std::vector<double> cm(f.nprob);
+    HPS_HIP(hipMemcpyAsync(cm.data(), f.dcmax.p, cm.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, f.stream));
+    HPS_HIP(hipStreamSynchronize(f.stream));
+    const double hx = (f.x1 - f.x0) / f.nx, hy = (f.y1 - f.y0) / f.ny;
+    const double lam1 = M_PI * M_PI * (1.0 / (hx * hx) + 1.0 / (hy * hy));
+    for (int b = 0; b < f.nprob; ++b) {
+      const double k = f.prm_h[4 * b];
+      f.route_h[b] = (std::isfinite(cm[b]) && k * k * cm[b] <= 0.5 * lam1) ? 1 : 0;
+    }
+  }
+  upload(f.droute, f.route_h);
+}
+
 void build_leaves(hps_group& f, const double* c, BuildScratch& sc) {
   hipStream_t st = f.stream;
   const long nl = f.nleaf;
@@ -856,14 +950,15 @@ void build_leaves(hps_group& f, const double* c, BuildScratch& sc) {
   d.p = f.p; d.nleaf = f.nleaf; d.nl1 = f.nl1; d.prm = f.dprm.d();
   d.c = c; d.leaf_grid = f.pleaf_grid; d.tab = f.dLT.d();
   d.R = f.R[f.L].d(); d.info = sc.info.i();
-  // scratch per chunk: the inverse's per-leaf copies, then (mixed precision) the
-  // complex128 Y_i blocks of the chunk's [Psi | Y], which the Psi / boundary-row kernel
-  // reads and rounds into the complex64 arena
+  d.route = f.droute.i(); d.rtab = f.dRT.d();
+  // scratch per chunk (leaf_scratch): the impedance route's per-leaf copies, (mixed
+  // precision) the complex128 [Psi | Y] of the chunk, rounded into the complex64 arena
+  // at the end, and the Dirichlet route's X and Z
   char* scr = static_cast<char*>(sc.buf.p);
+  const LeafScratch LS = leaf_scratch(f);
   const long lch = leaf_chunk(f);
   const size_t mg_bytes = leaf_scratch_bytes(f.p, lch);
-  double* bi64 = f.mixed ? reinterpret_cast<double*>(scr + ((mg_bytes + 255) & ~size_t(255)))
-                         : nullptr;
+  double* bi64 = f.mixed ? reinterpret_cast<double*>(scr + LS.bi) : nullptr;
   Profiler& pr = f.build_prof;
   for (long h0 = 0; h0 < nl; h0 += lch) {
     const int cnt = (int)std::min<long>(lch, nl - h0);
@@ -872,24 +967,79 @@ void build_leaves(hps_group& f, const double* c, BuildScratch& sc) {
     dc.h0 = h0;
     dc.leaf_grid = d.leaf_grid + h0;
     dc.BI = f.mixed ? bi64 : f.BI.d() + 2 * h0 * n * n;
-    // mixed precision: the Psi / boundary-row kernel writes the complex64 [Psi | Y]
-    dc.BI32 = f.mixed ? reinterpret_cast<float*>(f.BI32.p) + 2 * h0 * n * n : nullptr;
     dc.R = d.R + 2 * h0 * nb * nb;
     dc.info = d.info + h0;
     dc.Mg = mg_bytes ? reinterpret_cast<double*>(scr) : nullptr;
-    const double c_ = cnt;
-    {
-      // S_i^{-1}: complex Gauss-Jordan, n_i^3 complex multiply-adds
-      Stage s(pr, "leaf_sinv", c_ * 8.0 * ni * ni * ni, c_ * (ni * 8.0 + ni * ni * 16.0));
-      leaf_interior_inverse(dc, st);
+    dc.X = reinterpret_cast<double*>(scr + LS.x);
+    dc.Z = reinterpret_cast<double*>(scr + LS.z);
+    long nR = 0;  // leaves of the chunk on the Dirichlet route
+    for (long hh = h0; hh < h0 + cnt; ++hh) nR += f.route_h[hh / f.nl1];
+    const long nC = cnt - nR;
+    const double r_ = nR, c_ = nC;
+    if (nR > 0) {
+      {
+        // A^{-1}: real Gauss-Jordan, 2 n_i^3 flops
+        Stage s(pr, "leaf_ainv", r_ * 2.0 * ni * ni * ni, r_ * (ni * 8.0 + ni * ni * 16.0));
+        leaf_dirichlet_inverse(dc, st);
+      }
+      {
+        // X = A^{-1} A_ib and Z = N_i A^{-1} (2 n_i^2 n_b each as dense products),
+        // S = F_bb - N_i X (2 n_b^2 n_i)
+        Stage s(pr, "leaf_xz", r_ * (4.0 * ni * ni * nb + 2.0 * nb * nb * ni),
+                r_ * (ni * ni * 16.0 + 2.0 * ni * nb * 8.0 + nb * nb * 16.0));
+        leaf_dirichlet_xz(dc, st);
+      }
+      {
+        // S^{-1} (8 n_b^3), R = I - 2 i eta S^{-1}
+        Stage s(pr, "leaf_sbinv", r_ * 8.0 * nb * nb * nb, r_ * 3.0 * nb * nb * 16.0);
+        zinv((int)nb, cnt, dc.BI, n, n * n, dc.BI, n, n * n, d.info + nl + h0, nullptr, st,
+             false);
+        leaf_dirichlet_R(dc, st);
+      }
+      // Psi_i = -X Psi_b, Y_b = -Psi_b Z, Y_i = A^{-1} - X Y_b   (4 n_i n_b^2, 4 n_b^2 n_i,
+      // 4 n_i^2 n_b flops: real times complex)
+      GemmDesc g;
+      g.M = ni; g.N = nb; g.K = nb; g.batch = cnt;
+      g.A = dc.X; g.lda = ni; g.sA = ni * nb; g.a_real = true;
+      g.B = dc.BI; g.ldb = n; g.sB = n * n;
+      g.C = dc.BI + 2 * nb; g.ldc = n; g.sC = n * n;
+      g.alpha = -1.0; g.beta = 0.0;
+      timed_gemm(pr, "leaf_gemm", g, st, f.opts.autotune != 0);
+      g = GemmDesc();
+      g.M = nb; g.N = ni; g.K = nb; g.batch = cnt;
+      g.A = dc.BI; g.lda = n; g.sA = n * n;
+      g.B = dc.Z; g.ldb = nb; g.sB = nb * ni; g.b_real = true;
+      g.C = dc.BI + 2 * n * nb; g.ldc = n; g.sC = n * n;
+      g.alpha = -1.0; g.beta = 0.0;
+      timed_gemm(pr, "leaf_gemm", g, st, f.opts.autotune != 0);
+      g = GemmDesc();
+      g.M = ni; g.N = ni; g.K = nb; g.batch = cnt;
+      g.A = dc.X; g.lda = ni; g.sA = ni * nb; g.a_real = true;
+      g.B = dc.BI + 2 * n * nb; g.ldb = n; g.sB = n * n;
+      g.C = dc.BI + 2 * (n * nb + nb); g.ldc = n; g.sC = n * n;
+      g.alpha = -1.0; g.beta = 1.0;
+      timed_gemm(pr, "leaf_gemm", g, st, f.opts.autotune != 0);
+      if (f.mixed) {
+        Stage s(pr, "leaf_round", 0.0, cnt * (double)n * n * 24.0);
+        to_c64(dc.BI, reinterpret_cast<float*>(f.BI32.p) + 2 * h0 * n * n, 2L * cnt * n * n, st);
+      }
     }
-    {
-      // Y_i read once; Psi_i and the boundary rows written (complex64 in mixed precision,
-      // with the interior Y rows), R written
-      const double out = f.mixed ? n * n * 8.0 : (ni * nb + nb * n) * 16.0;
-      Stage s(pr, "leaf_psi_bnd", c_ * (32.0 * ni * ni + 8.0 * nb * n * f.m),
-              c_ * (ni * ni * 16.0 + out + nb * nb * 16.0));
-      leaf_psi_and_boundary(dc, st);
+    if (nC > 0) {
+      // mixed precision: the Psi / boundary-row kernel writes the complex64 [Psi | Y]
+      dc.BI32 = f.mixed ? reinterpret_cast<float*>(f.BI32.p) + 2 * h0 * n * n : nullptr;
+      {
+        // S_i^{-1}: complex Gauss-Jordan, n_i^3 complex multiply-adds
+        Stage s(pr, "leaf_sinv", c_ * 8.0 * ni * ni * ni, c_ * (ni * 8.0 + ni * ni * 16.0));
+        leaf_interior_inverse(dc, st);
+      }
+      {
+        // Y_i read once; Psi_i and the boundary rows written (complex64 in mixed precision,
+        // with the interior Y rows), R written
+        const double out = f.mixed ? n * n * 8.0 : (ni * nb + nb * n) * 16.0;
+        Stage s(pr, "leaf_psi_bnd", c_ * (32.0 * ni * ni + 8.0 * nb * n * f.m),
+                c_ * (ni * ni * 16.0 + out + nb * nb * 16.0));
+        leaf_psi_and_boundary(dc, st);
+      }
     }
   }
   f.R_valid[f.L] = 1;
@@ -1008,15 +1158,29 @@ void build_level(hps_group& f, int l, BuildScratch& sc) {
 
 void build_all(hps_group& f, const double* c) {
   BuildScratch sc;
-  plan_memory(f, sc);
-  fill_zero_int(sc.info.i(), (long)(sc.info.bytes / sizeof(int)), f.stream);
-  build_leaves(f, c, sc);
-  for (int l = f.L - 1; l >= 0; --l) build_level(f, l, sc);
-  // one synchronization for the whole build, then the pivot checks
-  HPS_HIP(hipStreamSynchronize(f.stream));
-  std::vector<int> h(sc.info.bytes / sizeof(int));
-  HPS_HIP(hipMemcpy(h.data(), sc.info.p, sc.info.bytes, hipMemcpyDeviceToHost));
-  check_info(h, 0, f.nleaf, "leaf interior Schur complement");
+  std::vector<int> h;
+  for (int attempt = 0;; ++attempt) {
+    plan_memory(f, sc);
+    fill_zero_int(sc.info.i(), (long)(sc.info.bytes / sizeof(int)), f.stream);
+    choose_routes(f, c);
+    build_leaves(f, c, sc);
+    for (int l = f.L - 1; l >= 0; --l) build_level(f, l, sc);
+    // one synchronization for the whole build, then the pivot checks
+    HPS_HIP(hipStreamSynchronize(f.stream));
+    h.assign(sc.info.bytes / sizeof(int), 0);
+    HPS_HIP(hipMemcpy(h.data(), sc.info.p, sc.info.bytes, hipMemcpyDeviceToHost));
+    // A leaf of the Dirichlet-block route whose elimination broke down (a zero pivot
+    // block or growth past the check) is not an error of the problem: the build is
+    // repeated with every leaf eliminated through its impedance rows.
+    bool dir_failed = false;
+    for (long i = 0; i < f.nleaf && !dir_failed; ++i)
+      dir_failed = (h[i] || h[f.nleaf + i]) && f.route_h[i / f.nl1];
+    if (!dir_failed || attempt > 0) break;
+    f.opts.leaf_route = 1;
+    f.build_prof.reset(f.opts.profile != 0, f.stream);
+  }
+  check_info(h, 0, f.nleaf, "leaf interior block");
+  check_info(h, f.nleaf, f.nleaf, "leaf boundary Schur complement");
   for (int l = 0; l < f.L; ++l) check_info(h, sc.info_off[l], f.lv[l].nbox, "interface matrix W");
   // release the ItI buffer that no longer holds a kept operator
   if (!f.opts.keep_all_R) {

@@ -92,6 +92,12 @@ struct LeafDesc {
   double* R = nullptr;           // device [nleaf][nb*nb] complex
   double* Mg = nullptr;          // scratch of the interior inverse (leaf_scratch_bytes)
   int* info = nullptr;           // device [nleaf]
+  // Dirichlet-block route (leaf_dir.hip)
+  const int* route = nullptr;    // device [problem]: 1 = Dirichlet-block route, 0 = impedance
+                                 // route; each route's kernels skip the other's leaves
+  const double* rtab = nullptr;  // device real line tables, leaf_rtable_len(p) per problem
+  double* X = nullptr;           // scratch [nleaf][n_i x n_b] real: A^{-1} A_ib
+  double* Z = nullptr;           // scratch [nleaf][n_b x n_i] real: N_i A^{-1}
 };
 // scratch the leaf inverse needs for nleaf leaves (0 when it fits in registers)
 size_t leaf_scratch_bytes(int p, long nleaf);
@@ -102,6 +108,14 @@ int leaf_table_len(int p);
 void leaf_interior_inverse(const LeafDesc& d, hipStream_t st);  // S_i^{-1} -> Y_i block
 // Psi_i = -Y_i W, the boundary rows [Psi_b | Y_b] and R, from the Y_i block
 void leaf_psi_and_boundary(const LeafDesc& d, hipStream_t st);
+// Dirichlet-block route: doubles of the real line table of one problem; the largest c of
+// each problem (nprob problems of per_prob samples); A^{-1} into the Y_i block (real
+// values); X, Z into scratch and S = F_bb - N_i X into the Psi_b block; R from Psi_b
+int leaf_rtable_len(int p);
+void leaf_cmax(const double* c, int nprob, long per_prob, double* cmax, hipStream_t st);
+void leaf_dirichlet_inverse(const LeafDesc& d, hipStream_t st);
+void leaf_dirichlet_xz(const LeafDesc& d, hipStream_t st);
+void leaf_dirichlet_R(const LeafDesc& d, hipStream_t st);
 
 // ------------------------------------------------------------------ merge helpers
 struct MergeLevelDesc {

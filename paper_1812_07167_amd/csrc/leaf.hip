@@ -113,6 +113,7 @@ __global__ __launch_bounds__(LeafCfg<P>::NT) void leaf_sinv_kernel(LeafDesc d) {
   const long h = blockIdx.x;
   const int g = d.leaf_grid[h];
   const long prob = (d.h0 + h) / d.nl1;
+  if (d.route && d.route[prob]) return;  // this problem takes the Dirichlet-block route
   const double2* tab = reinterpret_cast<const double2*>(d.tab) + prob * leaf_table_len_dev(P);
   for (int e = tid; e < m * m; e += Cfg::NT) {
     sG[0][e] = tab[TabIdx{m}.gx() + e];
@@ -423,6 +424,7 @@ __global__ __launch_bounds__(512) void leaf_psi_bnd_kernel(LeafDesc d) {
   const int tid = threadIdx.x;
   const long h = blockIdx.x;
   const long prob = (d.h0 + h) / d.nl1;
+  if (d.route && d.route[prob]) return;  // this problem takes the Dirichlet-block route
   const double2* tab = reinterpret_cast<const double2*>(d.tab) + prob * leaf_table_len_dev(P);
   const TabIdx T{m};
   for (int e = tid; e < m; e += NT) {

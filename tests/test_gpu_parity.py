@@ -51,6 +51,68 @@ def test_leaf_operators(nx, ny, p):
     f.free()
 
 
+def _leaf_route_taken(f):
+    """'dirichlet' or 'impedance': the leaf kernels that ran in a profiled build."""
+    names = {r[0].split("[")[0] for r in f.stage_times(0)}
+    if "leaf_ainv" in names and "leaf_sinv" not in names:
+        return "dirichlet"
+    if "leaf_sinv" in names and "leaf_ainv" not in names:
+        return "impedance"
+    return "both"
+
+
+@pytest.mark.parametrize("nx,ny,p", [(2, 2, 4), (2, 1, 5), (1, 2, 7), (2, 1, 8), (2, 2, 9),
+                                     (2, 2, 10), (2, 2, 11), (2, 2, 12), (1, 2, 13),
+                                     (2, 1, 14), (1, 2, 15), (2, 2, 16)])
+def test_leaf_operators_dirichlet_route(nx, ny, p):
+    """Leaves well inside a wavelength (kappa^2 max c below half the leaf's smallest
+    Dirichlet eigenvalue): the automatic choice inverts the real interior block and
+    eliminates the boundary afterwards.  Psi, Y and R against the oracle's dense B^{-1},
+    and against the impedance-row elimination of the same leaves."""
+    from paper_1812_07167_amd import hps as H
+    _say("leaf operators, Dirichlet route", nx, ny, p)
+    cs = Case(nx, ny, p, 6.0, eta=6.0 + 1.5j, box=(0.0, 0.5, -0.25, 0.25), seed=p)
+    f = cs.gpu_build(keep_all_R=True, profile=True)
+    assert _leaf_route_taken(f) == "dirichlet"
+    fi = cs.gpu_build(keep_all_R=True, profile=True, leaf_route=1)
+    assert _leaf_route_taken(fi) == "impedance"
+    L = f.info.levels
+    for h in range(nx * ny):
+        ix0, ix1, iy0, iy1 = f.box(L, h)
+        g = iy0 * nx + ix0
+        o = O.leaf_operators(*cs.prob.leaf_box(ix0, iy0), p, cs.kappa, cs.eta,
+                             cs.c[g * (p - 2) ** 2:(g + 1) * (p - 2) ** 2])
+        for what, key in [(H.OP_PSI, "Psi"), (H.OP_Y, "Y"), (H.OP_R, "R")]:
+            a = f.get(what, L, h)
+            assert rel(a, o[key]) < TOL, (h, key)
+            assert rel(a, fi.get(what, L, h)) < TOL, (h, key)
+    u = cs.gpu_solve(f)
+    assert rel(u, cs.oracle_solve(cs.oracle_build())) < TOL
+    f.free()
+    fi.free()
+
+
+def test_leaf_routes_mixed_in_one_batch():
+    """Problems of one shape built together, some below the Dirichlet-route bound (kappa
+    3, 6) and some above it (kappa 40, 70): each problem takes its own route within the
+    same launches, and every one matches the oracle; complex128 and mixed precision."""
+    import torch
+    from paper_1812_07167_amd import hps as H
+    _say("leaf routes mixed in one batch")
+    kappas = [3.0, 40.0, 6.0, 70.0]
+    cases = [Case(4, 4, 10, k, seed=40 + i, nrhs=2) for i, k in enumerate(kappas)]
+    for precision in (0, 1):
+        doms = [H.domain(4, 4) for _ in cases]
+        cs_d = [torch.tensor(cs.c, dtype=torch.float64, device="cuda") for cs in cases]
+        fs = H.hps_build_batch(doms, [10] * 4, kappas, kappas, cs_d, precision=precision,
+                               profile=True)
+        assert _leaf_route_taken(fs[0]) == "both"
+        for cs, f in zip(cases, fs):
+            assert rel(cs.gpu_solve(f), cs.oracle_solve(cs.oracle_build())) < TOL
+        for f in fs:
+            f.free()
+
+
 # ---------------------------------------------------------------- merge operators (Sec. 2.2)
 
 
