@@ -111,6 +111,14 @@ typedef struct {
                              impedance rows and the complex interior Schur complement is
                              inverted.
                              1 = the impedance-row elimination for every problem.          */
+  int32_t interface_pivoting; /* how W = I - R33^b R33^a is inverted (W^{-1} of eq. (talpha)):
+                             0 = diagonal blocks of 64 columns as pivots, each inverted with
+                             partial pivoting inside it, block steps on the matrix cores
+                             (default; W is identity minus a product of two compressions of
+                             ItI operators, which for real c and eta are contractions in the
+                             boundary quadrature norm, so no exchanges between blocks are
+                             needed -- a singular diagonal block repeats the build with 1);
+                             1 = partial pivoting over whole columns (LAPACK's choice).     */
 } hps_opts;
 
 /* Outcome of the most recent solve on a factor (hps_last_solve_info). */

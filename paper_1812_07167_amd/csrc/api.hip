@@ -302,6 +302,8 @@ struct hps_group {
                                            // precision only)
   hps::View BI32;                          // mixed precision: complex64 copy of [Psi | Y]
   bool mixed = false;                      // opts.precision == HPS_PREC_MIXED
+  bool full_pivoting = false;              // interface inverses pivot over whole columns
+                                           // (set when the block-pivot form broke down)
   hps::DevBuf rbuf[2];                     // ping-pong ItI operators (level l uses l % 2)
   std::vector<hps::DevBuf> rkeep;          // every level's R when opts.keep_all_R
   std::vector<hps::View> R;                // per level ItI operators (L+1 entries)
@@ -1102,11 +1104,11 @@ void build_level(hps_group& f, int l, BuildScratch& sc) {
       const long cnt = 2L * nbox * n3 * n3;
       to_c128(reinterpret_cast<const float*>(P.Winv.p), sc.w64.d(), cnt, st);
       zinv((int)n3, (int)nbox, sc.w64.d(), n3, n3 * n3, sc.w64.d(), n3, n3 * n3, info,
-           sc.work.p, st, false);
+           sc.work.p, st, false, f.full_pivoting);
       to_c64(sc.w64.d(), reinterpret_cast<float*>(P.Winv.p), cnt, st);
     } else {
       zinv((int)n3, (int)nbox, P.Winv.d(), n3, n3 * n3, P.Winv.d(), n3, n3 * n3, info,
-           sc.work.p, st, P.c64);
+           sc.work.p, st, P.c64, f.full_pivoting);
     }
   }
   // Phi^a = W^{-1} T   (eq. (talpha))
@@ -1169,14 +1171,20 @@ void build_all(hps_group& f, const double* c) {
     HPS_HIP(hipStreamSynchronize(f.stream));
     h.assign(sc.info.bytes / sizeof(int), 0);
     HPS_HIP(hipMemcpy(h.data(), sc.info.p, sc.info.bytes, hipMemcpyDeviceToHost));
-    // A leaf of the Dirichlet-block route whose elimination broke down (a zero pivot
-    // block or growth past the check) is not an error of the problem: the build is
-    // repeated with every leaf eliminated through its impedance rows.
-    bool dir_failed = false;
+    // An elimination without row exchanges that broke down is not an error of the
+    // problem: a leaf of the Dirichlet-block route (a zero pivot block or growth past
+    // the check) repeats the build with every leaf eliminated through its impedance rows,
+    // an interface matrix whose diagonal block was singular repeats it with pivoting over
+    // whole columns.  A failure of the fully pivoted forms is reported.
+    bool dir_failed = false, w_failed = false;
     for (long i = 0; i < f.nleaf && !dir_failed; ++i)
       dir_failed = (h[i] || h[f.nleaf + i]) && f.route_h[i / f.nl1];
-    if (!dir_failed || attempt > 0) break;
-    f.opts.leaf_route = 1;
+    for (int l = 0; l < f.L && !w_failed; ++l)
+      for (long i = 0; i < f.lv[l].nbox && !w_failed; ++i)
+        w_failed = h[sc.info_off[l] + i] != 0 && f.lv[l].n3 > 64 && !f.full_pivoting;
+    if ((!dir_failed && !w_failed) || attempt > 0) break;
+    if (dir_failed) f.opts.leaf_route = 1;
+    if (w_failed) f.full_pivoting = true;
     f.build_prof.reset(f.opts.profile != 0, f.stream);
   }
   check_info(h, 0, f.nleaf, "leaf interior block");
@@ -1517,6 +1525,7 @@ std::shared_ptr<hps_group> build_group(const hps_domain& dom, int p, int nprob,
   if (f->opts.fp64_top_levels < 0) throw Error(HPS_E_INVALID, "fp64_top_levels must be >= 0");
   if (!(f->opts.refine_tol > 0.0)) throw Error(HPS_E_INVALID, "refine_tol must be > 0");
   f->mixed = f->opts.precision == HPS_PREC_MIXED;
+  f->full_pivoting = f->opts.interface_pivoting == 1;
   f->p = p; f->m = p - 2; f->n = p * p - 4; f->nb = 4 * (p - 2); f->ni = (p - 2) * (p - 2);
   f->nx = dom.nx; f->ny = dom.ny;
   f->nprob = nprob; f->nl1 = dom.nx * dom.ny; f->nleaf = f->nl1 * nprob;

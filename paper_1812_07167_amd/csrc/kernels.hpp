@@ -66,15 +66,18 @@ size_t skinny_work_bytes(const SkinnyDesc& d);
 void zgemm_skinny(const SkinnyDesc& d, hipStream_t st);
 
 // ------------------------------------------------------------------ complex inversion
-// Batched Gauss-Jordan inversion with partial pivoting of n x n complex matrices.
+// Batched Gauss-Jordan inversion of n x n complex matrices.
 // In: A_b (lda, sA).  Out: Inv_b (ldo, sO); Out may alias A (A is read completely before
 // Out is written).  info[b] is set to (k+1) if the k-th pivot is exactly zero (info must
 // be zeroed by the caller).  Workspace is allocated by the caller through
 // zinv_workspace_bytes.  c64: A, Out and the arithmetic are complex64 (strides still in
-// complex entries).
+// complex entries).  Up to 64, and with full_pivoting, partial pivoting over the whole
+// column; otherwise (in place only) the diagonal blocks of 64 columns are the pivots,
+// each inverted with partial pivoting inside it, and the block steps run on the GEMM.
 size_t zinv_workspace_bytes(int n, int batch, bool c64 = false);
 void zinv(int n, int batch, const double* A, long lda, long sA, double* Out, long ldo,
-          long sO, int* info, void* work, hipStream_t st, bool c64 = false);
+          long sO, int* info, void* work, hipStream_t st, bool c64 = false,
+          bool full_pivoting = false);
 
 // ------------------------------------------------------------------ leaf stage
 struct LeafDesc {

@@ -7,10 +7,18 @@
 // inv(A)[k][r_j] = M[r_k][j], which the final write-out applies.
 //
 // * n <= SMALL_MAX: one workgroup per matrix, matrix resident in registers.
-// * larger n: blocked right-looking form.  For each block K of PNB (16 or 8) columns a panel
-//   kernel (one workgroup per matrix, panel rows spread over its waves, each row's PNB
-//   panel entries in registers) runs the PNB elimination steps on the panel and emits
-//   the block transformation Q; an update kernel then forms
+// * larger n, by default: blocked Gauss-Jordan with the diagonal blocks of BNB columns as
+//   pivots (each block inverted in LDS with its own 16 x 16 diagonal blocks as pivots),
+//   the block transformations applied by the matrix-core GEMM.  The interface matrices
+//   W = I - R33^b R33^a of the merge are identity minus a product of two compressions of
+//   ItI operators (contractions in the boundary quadrature norm for real c and eta), so
+//   the elimination needs no row exchanges (the measured growth of their entries is at
+//   most 3); a zero pivot, or growth past a bound, is reported, and the build then
+//   repeats with the fully pivoted form.
+// * larger n, fully pivoted (the fallback): blocked right-looking form.  For each block K
+//   of PNB (16 or 8) columns a panel kernel (one workgroup per matrix, panel rows spread
+//   over its waves, each row's PNB panel entries in registers) runs the PNB elimination
+//   steps on the panel and emits the block transformation Q; an update kernel then forms
 //   M = (pivot rows of K cleared) + Q M[P_K, :] on every column outside K.
 #include "kernels.hpp"
 
@@ -465,19 +473,244 @@ void zinv_t(int n, int batch, const double* A, long lda, long sA, double* Out, l
   HPS_LAUNCH_CHECK();
 }
 
+// ------------------------------------------------------------------ block pivots
+// One block step of the block-pivot form, after P^{-1} (Pinv, nb x nb per matrix) and
+// Q = -M[:, K] P^{-1} (n x nb per matrix) are formed: Q's rows K take P^{-1}; the block's
+// rows go to X = M[K, :] (nb x n, the identity on the columns K) and are zeroed in M, and
+// M's columns K are zeroed, so that the update M += Q X completes the step.  A thread's
+// element belongs to exactly one of the three index sets.
+template <class T>
+__global__ __launch_bounds__(256) void zinv_bstep_kernel(int n, int nb, int k0, double* Mg,
+                                                         long ld, long sM, const double* Pinv,
+                                                         double* Qg, double* Xg,
+                                                         const int* info) {
+  typedef typename Cx<T>::t C2;
+  const long b = blockIdx.y;
+  if (info[b]) return;
+  C2* M = reinterpret_cast<C2*>(Mg) + b * sM;
+  const C2* Pi = reinterpret_cast<const C2*>(Pinv) + b * (long)nb * nb;
+  C2* Q = reinterpret_cast<C2*>(Qg) + b * (long)n * nb;
+  C2* X = reinterpret_cast<C2*>(Xg) + b * (long)nb * n;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nq = (long)nb * nb, nx = (long)nb * n, nz = (long)n * nb;
+  if (e < nq) {  // Q's rows K
+    const int r = (int)(e % nb), j = (int)(e / nb);
+    Q[(k0 + r) + (long)n * j] = Pi[r + (long)nb * j];
+  } else if (e < nq + nx) {  // X and the rows K of M
+    const long f = e - nq;
+    const int r = (int)(f % nb), c = (int)(f / nb);
+    const int jc = c - k0;
+    const long at = (k0 + r) + ld * c;
+    X[r + (long)nb * c] = (jc >= 0 && jc < nb) ? Cx<T>::mk(jc == r ? 1 : 0, 0) : M[at];
+    M[at] = Cx<T>::mk(0, 0);
+  } else if (e < nq + nx + nz) {  // the columns K of M
+    const long f = e - nq - nx;
+    const int r = (int)(f % n), j = (int)(f / n);
+    M[r + ld * (k0 + j)] = Cx<T>::mk(0, 0);
+  }
+}
+
+// Inverse of the n x n diagonal block P of a matrix (n <= 64) with its own 16 x 16
+// diagonal blocks as pivots: one workgroup of 256 threads per matrix, P in LDS.  Per
+// block K of 16 columns, the first wave inverts P[K, K] in registers (lane l holds row
+// l % 16, columns l / 16 + 4 q; row and column k are exchanged by cross-lane reads), then
+// Q = -P[:, K] P[K, K]^{-1} (rows K: P[K, K]^{-1}) and X = P[K, :] (identity on K), and
+// P <- (rows K and columns K zeroed) + Q X.  A zero or non-finite pivot, or an entry of
+// the inverse beyond 1e12 times the largest of P, sets info (the build then repeats with
+// full pivoting).
+template <class T>
+__device__ inline typename Cx<T>::t shfl_c(typename Cx<T>::t v, int src) {
+  return Cx<T>::mk(__shfl(v.x, src), __shfl(v.y, src));
+}
+template <class T>
+__device__ inline typename Cx<T>::t pick4c(const typename Cx<T>::t (&v)[4], int q) {
+  return q == 0 ? v[0] : q == 1 ? v[1] : q == 2 ? v[2] : v[3];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void zinv_np_kernel(int n, const double* Ain, long lda,
+                                                      long sA, double* Out, long ldo, long sO,
+                                                      int* info) {
+  typedef typename Cx<T>::t C2;
+  constexpr int LD = 65;         // column stride of the LDS copy (odd: no bank pattern)
+  __shared__ C2 Ms[64 * LD];     // Ms[c * LD + r] = P[r][c], padded with the identity
+  __shared__ C2 Qs[16 * 64];     // Qs[t * 64 + r] = Q[r][t]
+  __shared__ C2 Xs[16 * 64];     // Xs[t * 64 + c] = X[t][c]
+  __shared__ C2 Pk[16 * 16];     // Pk[j * 16 + i] = P[K, K]^{-1}[i][j]
+  __shared__ int s_bad;
+  __shared__ float s_max;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const long b = blockIdx.x;
+  const C2* A = reinterpret_cast<const C2*>(Ain) + b * sA;
+  float amax = 0.f;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    const C2 v = (r < n && c < n) ? A[r + lda * c] : Cx<T>::mk(r == c ? 1 : 0, 0);
+    Ms[c * LD + r] = v;
+    amax = fmaxf(amax, (float)cabs1(v));
+  }
+  if (tid == 0) {
+    s_bad = 0;
+    s_max = 0.f;
+  }
+  __syncthreads();
+  atomicMax(reinterpret_cast<unsigned*>(&s_max), __float_as_uint(amax));
+#pragma unroll 1
+  for (int k0 = 0; k0 < 64; k0 += 16) {
+    if (tid < 64) {
+      const int i = lane & 15, c0 = lane >> 4;
+      C2 v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = Ms[(k0 + c0 + 4 * q) * LD + k0 + i];
+      bool bad = false;
+#pragma unroll 1
+      for (int k = 0; k < 16; ++k) {
+        C2 rk[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rk[q] = shfl_c<T>(v[q], k + 16 * c0);
+        const C2 vk = pick4c<T>(v, k >> 2);
+        const C2 cik = shfl_c<T>(vk, i + 16 * (k & 3));
+        const C2 pk = shfl_c<T>(vk, k + 16 * (k & 3));
+        bad = bad || !(cabs1(pk) > 0) || !isfinite((double)pk.x) || !isfinite((double)pk.y);
+        const C2 ip = crcp(pk);
+        const C2 f = cmul(cik, ip);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int j = c0 + 4 * q;
+          if (i == k) v[q] = (j == k) ? ip : cmul(rk[q], ip);
+          else v[q] = (j == k) ? Cx<T>::mk(-f.x, -f.y) : csub(v[q], cmul(f, rk[q]));
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Pk[(c0 + 4 * q) * 16 + i] = v[q];
+      if (bad) s_bad = 1;
+    }
+    __syncthreads();
+    // Q (64 x 16) and X (16 x 64)
+    for (int e = tid; e < 64 * 16; e += 256) {
+      const int r = e & 63, j = e >> 6;
+      const int ir = r - k0;
+      C2 q = Cx<T>::mk(0, 0);
+      if (ir >= 0 && ir < 16) {
+        q = Pk[j * 16 + ir];
+      } else {
+#pragma unroll
+        for (int t = 0; t < 16; ++t) q = cfma(Ms[(k0 + t) * LD + r], Pk[j * 16 + t], q);
+        q = Cx<T>::mk(-q.x, -q.y);
+      }
+      Qs[j * 64 + r] = q;
+      const int c = r, t = j;  // X[t][c]
+      const int jc = c - k0;
+      Xs[t * 64 + c] = (jc >= 0 && jc < 16) ? Cx<T>::mk(jc == t ? 1 : 0, 0) : Ms[c * LD + k0 + t];
+    }
+    __syncthreads();
+    // P <- (rows K and columns K zeroed) + Q X: thread row r = lane, columns w + 4 q
+    {
+      const int r = lane, w = tid >> 6;
+      const bool rK = r >= k0 && r < k0 + 16;
+      C2 qr[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) qr[t] = Qs[t * 64 + r];
+#pragma unroll 4
+      for (int q = 0; q < 16; ++q) {
+        const int c = w + 4 * q;
+        const bool cK = c >= k0 && c < k0 + 16;
+        C2 acc = (rK || cK) ? Cx<T>::mk(0, 0) : Ms[c * LD + r];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) acc = cfma(qr[t], Xs[t * 64 + c], acc);
+        Ms[c * LD + r] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  C2* O = reinterpret_cast<C2*>(Out) + b * sO;
+  const float lim = 1e12f * fmaxf(s_max, 1e-30f);
+  bool grown = false;
+  for (int e = tid; e < n * n; e += 256) {
+    const int r = e % n, c = e / n;
+    const C2 v = Ms[c * LD + r];
+    grown |= !((float)cabs1(v) <= lim);
+    O[r + ldo * c] = v;
+  }
+  if (grown) s_bad = 1;
+  __syncthreads();
+  if (s_bad && tid == 0) info[b] = 1;
+}
+
+// Block-pivot inversion in place: for each block K of BNB columns, P^{-1} = inv(M[K, K])
+// (the kernel above), Q = -M[:, K] P^{-1} (GEMM), the step kernel, then M += Q X (GEMM).
+constexpr int BNB = 64;
+void zinv_blockpivot(int n, int batch, double* A, long lda, long sA, int* info, void* work,
+                     hipStream_t st, bool c64) {
+  const size_t e = c64 ? 8 : 16;
+  char* w = static_cast<char*>(work);
+  double* Pinv = reinterpret_cast<double*>(w);
+  w += ((size_t)batch * BNB * BNB * e + 255) & ~size_t(255);
+  double* Qg = reinterpret_cast<double*>(w);
+  w += ((size_t)batch * n * BNB * e + 255) & ~size_t(255);
+  double* Xg = reinterpret_cast<double*>(w);
+  for (int k0 = 0; k0 < n; k0 += BNB) {
+    const int nb = std::min(BNB, n - k0);
+    // the diagonal block's inverse (16 x 16 blocks as its pivots)
+    double* Ablk = A + (c64 ? 1 : 2) * (size_t)(k0 + lda * (long)k0);
+    if (c64)
+      hipLaunchKernelGGL(zinv_np_kernel<float>, dim3(batch), dim3(256), 0, st, nb, Ablk, lda,
+                         sA, Pinv, nb, (long)nb * nb, info);
+    else
+      hipLaunchKernelGGL(zinv_np_kernel<double>, dim3(batch), dim3(256), 0, st, nb, Ablk, lda,
+                         sA, Pinv, nb, (long)nb * nb, info);
+    HPS_LAUNCH_CHECK();
+    GemmDesc g;
+    g.M = n; g.N = nb; g.K = nb; g.batch = batch;
+    g.A = A + (c64 ? 1 : 2) * (size_t)lda * k0; g.lda = lda; g.sA = sA;
+    g.B = Pinv; g.ldb = nb; g.sB = (long)nb * nb;
+    g.C = Qg; g.ldc = n; g.sC = (long)n * nb;
+    g.alpha = -1.0; g.beta = 0.0; g.c64 = c64;
+    zgemm(g, st);
+    const long tot = (long)nb * nb + 2L * nb * n;
+    if (c64)
+      hipLaunchKernelGGL(zinv_bstep_kernel<float>, dim3(cdiv(tot, 256), batch), dim3(256), 0,
+                         st, n, nb, k0, A, lda, sA, Pinv, Qg, Xg, info);
+    else
+      hipLaunchKernelGGL(zinv_bstep_kernel<double>, dim3(cdiv(tot, 256), batch), dim3(256), 0,
+                         st, n, nb, k0, A, lda, sA, Pinv, Qg, Xg, info);
+    HPS_LAUNCH_CHECK();
+    g = GemmDesc();
+    g.M = n; g.N = n; g.K = nb; g.batch = batch;
+    g.A = Qg; g.lda = n; g.sA = (long)n * nb;
+    g.B = Xg; g.ldb = nb; g.sB = (long)nb * n;
+    g.C = A; g.ldc = lda; g.sC = sA;
+    g.alpha = 1.0; g.beta = 1.0; g.c64 = c64;
+    zgemm(g, st);
+  }
+}
+
 }  // namespace
 
 size_t zinv_workspace_bytes(int n, int batch, bool c64) {
   if (n <= SMALL_MAX) return 0;
-  size_t nn = (size_t)n * n * (c64 ? 8 : 16);
-  size_t ints = (size_t)n * 4 * 2;
-  return (size_t)batch * (2 * nn + ints) + 256;
+  const size_t e = c64 ? 8 : 16;
+  // fully pivoted form: two copies of the matrix and the pivot records
+  const size_t nn = (size_t)n * n * e;
+  const size_t ints = (size_t)n * 4 * 2;
+  const size_t piv = (size_t)batch * (2 * nn + ints) + 256;
+  // block-pivot form: P^{-1}, Q and X
+  auto r256 = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t blk = r256((size_t)batch * BNB * BNB * e) + r256((size_t)batch * n * BNB * e) +
+                     r256((size_t)batch * BNB * n * e);
+  return std::max(piv, blk);
 }
 
 void zinv(int n, int batch, const double* A, long lda, long sA, double* Out, long ldo,
-          long sO, int* info, void* work, hipStream_t st, bool c64) {
+          long sO, int* info, void* work, hipStream_t st, bool c64, bool full_pivoting) {
   if (n <= 0 || batch <= 0) return;
   if (batch > 65535) throw Error(1, "zinv: batch exceeds grid limit");
+  if (n > SMALL_MAX && !full_pivoting) {
+    if (A != Out || lda != ldo || sA != sO)
+      throw Error(1, "zinv: the block-pivot form works in place");
+    zinv_blockpivot(n, batch, Out, ldo, sO, info, work, st, c64);
+    return;
+  }
   if (c64) zinv_t<float>(n, batch, A, lda, sA, Out, ldo, sO, info, work, st);
   else zinv_t<double>(n, batch, A, lda, sA, Out, ldo, sO, info, work, st);
 }

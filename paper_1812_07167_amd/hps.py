@@ -55,7 +55,8 @@ class Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("keep_all_R", C.c_int32), ("store_root_R", C.c_int32),
                 ("profile", C.c_int32), ("stream", C.c_void_p), ("fp64_top_levels", C.c_int32),
                 ("refine_max_iter", C.c_int32), ("refine_tol", C.c_double),
-                ("autotune", C.c_int32), ("leaf_route", C.c_int32)]
+                ("autotune", C.c_int32), ("leaf_route", C.c_int32),
+                ("interface_pivoting", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -261,7 +262,7 @@ class Factor:
 
 
 def _opts(keep_all_R, store_root_R, stream, profile, precision, fp64_top_levels,
-          refine_max_iter, refine_tol, autotune=False, leaf_route=0):
+          refine_max_iter, refine_tol, autotune=False, leaf_route=0, interface_pivoting=0):
     import torch
     lib = load()
     opts = Opts()
@@ -278,6 +279,7 @@ def _opts(keep_all_R, store_root_R, stream, profile, precision, fp64_top_levels,
         opts.refine_tol = float(refine_tol)
     opts.autotune = int(autotune)
     opts.leaf_route = int(leaf_route)
+    opts.interface_pivoting = int(interface_pivoting)
     st = stream if stream is not None else torch.cuda.current_stream()
     opts.stream = C.c_void_p(st.cuda_stream)
     return opts, st
@@ -285,13 +287,14 @@ def _opts(keep_all_R, store_root_R, stream, profile, precision, fp64_top_levels,
 
 def hps_build_batch(doms, ps, kappas, etas, cs, keep_all_R=False, store_root_R=True,
                     stream=None, profile=False, precision=HPS_PREC_C128, fp64_top_levels=None,
-                    refine_max_iter=None, refine_tol=None, autotune=False, leaf_route=0):
+                    refine_max_iter=None, refine_tol=None, autotune=False, leaf_route=0,
+                    interface_pivoting=0):
     """Build several problems at once (problems of one shape share every launch).  doms:
     list of Domain; cs: list of float64 device tensors.  Returns a list of Factors."""
     lib = load()
     n = len(doms)
     opts, st = _opts(keep_all_R, store_root_R, stream, profile, precision, fp64_top_levels,
-                     refine_max_iter, refine_tol, autotune, leaf_route)
+                     refine_max_iter, refine_tol, autotune, leaf_route, interface_pivoting)
     D = (Domain * n)(*doms)
     P = (C.c_int32 * n)(*[int(p) for p in ps])
     K = (C.c_double * n)(*[float(k) for k in kappas])
@@ -327,7 +330,7 @@ def hps_solve_batch(fs, ts, ss=None, us=None):
 def hps_build(dom: Domain, p: int, kappa: float, eta: complex, c_interior, keep_all_R=False,
               store_root_R=True, stream=None, profile=False, precision=HPS_PREC_C128,
               fp64_top_levels=None, refine_max_iter=None, refine_tol=None,
-              autotune=False, leaf_route=0) -> Factor:
+              autotune=False, leaf_route=0, interface_pivoting=0) -> Factor:
     """c_interior: float64 device tensor [nx*ny*(p-2)^2].  Returns a Factor.  Options left
     at None keep the library's defaults."""
     import torch
@@ -346,6 +349,7 @@ def hps_build(dom: Domain, p: int, kappa: float, eta: complex, c_interior, keep_
         opts.refine_tol = float(refine_tol)
     opts.autotune = int(autotune)
     opts.leaf_route = int(leaf_route)
+    opts.interface_pivoting = int(interface_pivoting)
     st = stream if stream is not None else torch.cuda.current_stream()
     opts.stream = C.c_void_p(st.cuda_stream)
     out = C.c_void_p()

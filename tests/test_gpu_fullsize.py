@@ -139,8 +139,13 @@ def test_root_interface_above_1024_nodes(request):
     cs = Case(128, 128, 11, 60.0, seed=12, nrhs=2)
     f = cs.gpu_build()
     u_g = cs.gpu_solve(f)
-    say("  GPU build + solve done")
+    fp = cs.gpu_build(interface_pivoting=1)
+    u_p = cs.gpu_solve(fp)
+    fp.free()
+    say("  GPU build + solve done (diagonal-block and whole-column pivots)")
     boxes, u_o = _oracle(cs, say, "128x128")
+    say("  u: whole-column vs diagonal-block pivots rel L2 %.3e" % rel(u_p, u_g))
+    assert rel(u_p, u_o) < TOL
     r = rel(u_g, u_o)
     say("  u: GPU vs oracle rel L2 %.3e" % r)
     assert r < TOL

@@ -117,16 +117,20 @@ def test_leaf_routes_mixed_in_one_batch():
 
 
 # interface sizes n3: (4,4,8) 6..24; (8,8,5) 3..24; (8,8,11) 9, 18, 36, 72 (every width of
-# the register-resident inverse, and the blocked one with a ragged last panel)
+# the register-resident inverse, and the blocked ones with a ragged last block); (8,8,16)
+# up to 112 and (4,8,14) up to 96 (two diagonal blocks of the block-pivot form); each
+# with pivots on the diagonal blocks (0) and over whole columns (1)
+@pytest.mark.parametrize("pivoting", [0, 1])
 @pytest.mark.parametrize("nx,ny,p,kappa", [(4, 4, 8, 20.0), (4, 2, 6, 9.0), (2, 4, 10, 14.0),
-                                           (8, 8, 5, 30.0), (8, 8, 11, 22.0)])
-def test_merge_operators_every_level(nx, ny, p, kappa):
+                                           (8, 8, 5, 30.0), (8, 8, 11, 22.0), (8, 8, 16, 45.0),
+                                           (4, 8, 14, 60.0)])
+def test_merge_operators_every_level(nx, ny, p, kappa, pivoting):
     from paper_1812_07167_amd import hps as H
-    _say("merge operators", nx, ny, p)
+    _say("merge operators", nx, ny, p, "pivoting", pivoting)
     cs = Case(nx, ny, p, kappa, seed=3)
     boxes = cs.oracle_build()
     ob = oracle_box_index(boxes)
-    f = cs.gpu_build(keep_all_R=True)
+    f = cs.gpu_build(keep_all_R=True, interface_pivoting=pivoting)
     m = p - 2
     for l in range(f.info.levels + 1):
         for q in range(1 << l):
