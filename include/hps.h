@@ -90,7 +90,8 @@ typedef struct {
                              is level 0) invert W in complex128 (default 3)              */
   int32_t refine_max_iter; /* residual correction steps per solve; -1 = automatic: 10 for
                              HPS_PREC_MIXED, 0 for HPS_PREC_C128 (default -1)            */
-  double refine_tol;       /* correction stops once, for every right-hand side r,
+  double refine_tol;       /* correction stops once, for every right-hand side r (of
+                             every problem of a batched solve, each measured on its own),
                              ||delta_r|| <= refine_tol ||u_r||, or the corrections contract
                              (each below half the last) so that the next one, estimated as
                              ||delta_r||^2 / ||delta_r^prev||, is below that (default 1e-12) */
@@ -125,7 +126,8 @@ typedef struct {
 typedef struct {
   int32_t iterations;  /* residual correction steps taken (0 when correction is off)     */
   int32_t converged;   /* 1 when the last relative correction met refine_tol             */
-  double correction;   /* max over right-hand sides of ||delta|| / ||u|| in the last step,
+  double correction;   /* max over right-hand sides (and problems of a batched solve) of
+                          ||delta|| / ||u|| in the last step,
                           or of its contraction estimate of the next step where that is
                           what met the tolerance                                        */
 } hps_solve_info;
@@ -247,8 +249,13 @@ int hps_build_batch(int32_t nprob, const hps_domain* doms, const int32_t* p,
  * (s[i] may be NULL, and s itself may be NULL for all-zero body loads; t[i], u[i] as for
  * hps_solve).  Requests on problems of one group run as one solve over all of them (the
  * right-hand sides padded with zeros to the largest nrhs[i] of the group), so every
- * per-level launch covers all those problems.  A problem may appear once per call.
- * Synchronizes the stream when residual correction is on.  Errors: as hps_solve. */
+ * per-level launch covers all those problems.  Requests on problems of different groups
+ * that share the leaf grid, p, level precisions and stream, without residual
+ * correction, also share every per-level launch, up to 16 problems per solve (each
+ * problem's launches cover only its own nrhs[i] right-hand sides).  A problem may
+ * appear once per call.  Runs on the stream of f[i]'s factor (the first of each
+ * sharing set).  Synchronizes the stream when residual correction is on.  Errors: as
+ * hps_solve. */
 int hps_solve_batch(int32_t nprob, hps_factor* const* f, const int32_t* nrhs,
                     const double* const* s, const double* const* t, double* const* u);
 
@@ -367,7 +374,7 @@ int hps_estimate_bytes(const hps_domain* dom, int32_t p, const hps_opts* opts,
  * Serving (not in the paper).  A server keeps factored problems resident in device
  * memory and runs build and solve requests on a pool of work slots, each a host thread
  * with its own stream, so that work of several requests overlaps on the device.
- *   - Admission by memory: every work item (a build, or one solve of a problem) starts
+ *   - Admission by memory: every work item (a build, or one solve) starts
  *     only when the bytes it needs (hps_estimate_bytes' build_peak, or the solve's
  *     workspace and staging) fit under the budget beside what is already committed
  *     (resident factors, running items).  If it does not fit, factors of idle problems
@@ -376,8 +383,13 @@ int hps_estimate_bytes(const hps_domain* dom, int32_t p, const hps_opts* opts,
  *     data when its next solve request comes up.
  *   - Continuous batching: when a slot takes a problem's solve, it merges every queued
  *     request of that problem (up to max_batch_rhs right-hand sides) into one solve.
- *     Requests that arrive while others run are taken as soon as a slot and memory free
- *     up.
+ *     With share_problems set, the same solve also takes the queued requests of other
+ *     idle resident problems that can share its launches (same leaf grid, p and level
+ *     precisions, no residual correction; oldest first, up to 16 problems, each up to
+ *     max_batch_rhs), so every per-level launch covers all of them.  Requests that
+ *     arrive while others run are taken as soon as a slot and memory free up.
+ *   - Solve slots: the first solve_slots slots never take a build, so a solve does not
+ *     wait for a slot behind long builds.
  * A request's result does not depend on what it was batched with beyond round-off.
  * Inputs (c, s, t) must be complete on the device when submitted (the server's streams
  * do not wait on the caller's); u is complete when its completion is returned by
@@ -391,6 +403,9 @@ typedef struct {
                                  HPS_E_BUSY (default 64)                                   */
   int32_t evict_idle;         /* 1 = free idle factors, least recently used first, to admit
                                  work (default 1)                                          */
+  int32_t solve_slots;        /* slots that take only solves (default 1; at most slots - 1) */
+  int32_t share_problems;     /* 1 = one solve serves several shareable problems
+                                 (default 1)                                               */
 } hps_server_opts;
 
 enum { HPS_REQ_BUILD = 0, HPS_REQ_SOLVE = 1 };
@@ -420,6 +435,8 @@ typedef struct {
   double wall_s;                        /* first submission to last completion            */
   double rhs_per_s, solves_per_s;       /* over wall_s                                    */
   int64_t budget_bytes, committed_bytes, peak_committed_bytes;
+  int64_t shared_batches;               /* solve calls that served several problems       */
+  int64_t shared_problems;              /* problems those calls served, summed            */
 } hps_stats;
 
 /* Fill *opts with the defaults. */

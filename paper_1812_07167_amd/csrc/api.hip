@@ -1259,8 +1259,36 @@ struct Arena {
 // Solve sweeps of Algorithm 2 for problems [pb, pb + np) of the group, nrhs right-hand
 // sides each.  Layouts (complex128): s [nrhs][np nl1 ni], jmp [nrhs][np nl1 nb],
 // t [np][nrhs][nt], u [nrhs][np nl1 n].
+// Problems of several factors of one shape, solved together: their right-hand sides are
+// laid out as for one group of np problems (problem q's leaves [q nl1, (q+1) nl1)), each
+// operator launch takes the factors' operator bases from tables, and the leaf maps come
+// from the plan of an np-problem group.
+struct Across {
+  static constexpr int kMax = SkinnyDesc::kMaxTab;
+  int np = 0;
+  std::shared_ptr<const PlanShape> sh;  // leaf maps of an np-problem group
+  int nrq[kMax] = {};                   // right-hand sides of each problem
+  const double* leaf[kMax] = {};        // [Psi | Y] of the problem's first leaf
+  PrmTab prm;                           // kappa, Re eta, Im eta of each problem
+  struct Level {
+    const double *R33b[kMax], *Winv[kMax], *R33a[kMax], *R13a[kMax], *R23b[kMax],
+        *PhiA[kMax], *PhiB[kMax];
+  };
+  std::vector<Level> lv;
+  // route launch k through the tables: entry b of factor b / per, operator tab (and tab2)
+  void put(SkinnyDesc& k, int per, const double* const* tab, const double* const* tab2 = nullptr,
+           long add = 0) const {
+    k.aper = per;
+    for (int q = 0; q < np; ++q) {
+      k.Atab[q] = tab[q] + add;
+      if (tab2) k.Atab2[q] = tab2[q] + add;
+      k.nrq[q] = nrq[q];
+    }
+  }
+};
+
 void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const double* t,
-                const double* jmp, double* u, Arena& ws) {
+                const double* jmp, double* u, Arena& ws, const Across* ax = nullptr) {
   hipStream_t st = ws.st;
   Profiler& pr = f.solve_prof;
   pr.reset(!ws.dry && !ws.fixed && f.opts.profile != 0, st);
@@ -1268,7 +1296,10 @@ void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const d
   const long nl = (long)np * f.nl1, n = f.n, nb = f.nb, ni = f.ni;
   const long h0 = (long)pb * f.nl1;  // first leaf of the range
   const int le = f.mixed ? 1 : 2;    // doubles per complex entry of the leaf operators
-  const double* leafops = (f.mixed ? f.BI32.d() : f.BI.d()) + le * h0 * n * n;
+  const double* leafops = ax ? nullptr : (f.mixed ? f.BI32.d() : f.BI.d()) + le * h0 * n * n;
+  const long* xoff = ax ? ax->sh->dxoff.l() : f.pxoff + h0;
+  const long* uoff = ax ? ax->sh->duoff.l() : f.puoff + h0;
+  const long lbase = ax ? 0 : h0;  // leaf index the offset tables start from
   // the upward pass runs for a body load or for right-hand sides on shared-edge rows
   const bool up = (s != nullptr) || (jmp != nullptr);
   std::vector<double*> h(f.L + 1, nullptr), tt(f.L + 1, nullptr), tta(f.L, nullptr),
@@ -1281,14 +1312,17 @@ void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const d
       // leaf: u~ = Y s   (Algorithm 2 step (3))
       SkinnyDesc k;
       k.M = n; k.K = ni; k.nrhs = nrhs; k.batch = (int)nl;
-      k.A = leafops + le * n * nb; k.a_c64 = f.mixed;
+      k.a_c64 = f.mixed;
+      if (ax) ax->put(k, f.nl1, ax->leaf, nullptr, le * n * nb);
+      else k.A = leafops + le * n * nb;
       k.lda = n; k.sA = n * n;
-      k.X = s; k.ldx = nl * ni; k.xoff = f.pxoff + h0; k.xbase = h0 * ni;
+      k.X = s; k.ldx = nl * ni; k.xoff = xoff; k.xbase = lbase * ni;
       k.C = ut; k.ldc = n; k.sC = n * nrhs;
       ws.skinny(pr, nm, k);
       Stage sg(pr, "solve_gather", 0.0, nl * nb * nrhs * 32.0);
       if (!ws.dry)
-        leaf_h_from_u((int)nl, f.n, f.nb, nrhs, f.dprm.d() + 4 * pb, f.nl1, ut, h[f.L], st);
+        leaf_h_from_u((int)nl, f.n, f.nb, nrhs, f.dprm.d() + 4 * pb, f.nl1, ut, h[f.L], st,
+                      ax ? &ax->prm : nullptr);
     } else if (!ws.dry) {
       fill_zero(ut, 2 * nl * n * nrhs, st);
       fill_zero(h[f.L], 2 * nl * nb * nrhs, st);
@@ -1303,6 +1337,8 @@ void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const d
       const long n1 = P.n1, n2 = P.n2, n3 = P.n3, nbp = P.nbp;
       const int e = P.c64 ? 1 : 2;
       auto op = [&](const View& v, long per) { return v.d() + box0 * per * e; };
+      const Across::Level* tl = ax ? &ax->lv[l] : nullptr;
+      const int per = 1 << l;  // boxes of one problem on the level
       double* h3a = ws.get((size_t)nbox * n3 * nrhs * 16);
       double* v = ws.get((size_t)nbox * n3 * nrhs * 16);
       tta[l] = ws.get((size_t)nbox * n3 * nrhs * 16);
@@ -1319,6 +1355,7 @@ void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const d
       SkinnyDesc k;
       k.M = n3; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox; k.a_c64 = P.c64;
       k.A = op(P.R33b, n3 * n3); k.lda = n3; k.sA = n3 * n3;
+      if (tl) ax->put(k, per, tl->R33b);
       k.X = h3a; k.ldx = n3; k.sX = n3 * nrhs;
       k.C = v; k.ldc = n3; k.sC = n3 * nrhs; k.accumulate = true;
       ws.skinny(pr, nm, k);
@@ -1326,6 +1363,7 @@ void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const d
       k = SkinnyDesc();
       k.M = n3; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox; k.a_c64 = P.c64;
       k.A = op(P.Winv, n3 * n3); k.lda = n3; k.sA = n3 * n3;
+      if (tl) ax->put(k, per, tl->Winv);
       k.X = v; k.ldx = n3; k.sX = n3 * nrhs;
       k.C = tta[l]; k.ldc = n3; k.sC = n3 * nrhs;
       ws.skinny(pr, nm, k);
@@ -1333,6 +1371,7 @@ void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const d
       k = SkinnyDesc();
       k.M = n3; k.K = n3; k.nrhs = nrhs; k.batch = (int)nbox; k.a_c64 = P.c64;
       k.A = op(P.R33a, n3 * n3); k.lda = n3; k.sA = n3 * n3;
+      if (tl) ax->put(k, per, tl->R33a);
       k.X = tta[l]; k.ldx = n3; k.sX = n3 * nrhs;
       k.C = ttb[l]; k.ldc = n3; k.sC = n3 * nrhs; k.accumulate = true; k.alpha = -1.0;
       ws.skinny(pr, nm, k);
@@ -1346,11 +1385,14 @@ void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const d
         k.C = h[l]; k.ldc = nbp; k.sC = nbp * nrhs; k.crow = P.dperm; k.accumulate = true;
         if (n1 == n2) {
           k.A2 = op(P.R23b, n2 * n3); k.X2 = ttb[l]; k.C2 = h[l]; k.crow2 = P.dperm + n1;
+          if (tl) ax->put(k, per, tl->R13a, tl->R23b);
           ws.skinny(pr, nm, k);
         } else {
+          if (tl) ax->put(k, per, tl->R13a);
           ws.skinny(pr, nm, k);
           k.M = n2;
           k.A = op(P.R23b, n2 * n3); k.lda = n2; k.sA = n2 * n3;
+          if (tl) ax->put(k, per, tl->R23b);
           k.X = ttb[l];
           k.crow = P.dperm + n1;
           ws.skinny(pr, nm, k);
@@ -1380,6 +1422,7 @@ void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const d
     k.M = n3; k.K = nbp; k.nrhs = nrhs; k.batch = (int)nbox; k.a_c64 = P.c64;
     k.A = P.PhiA.d() + box0 * n3 * nbp * e;
     k.A2 = P.PhiB.d() + box0 * n3 * nbp * e;
+    if (ax) ax->put(k, 1 << l, ax->lv[l].PhiA, ax->lv[l].PhiB);
     k.lda = n3; k.sA = n3 * nbp;
     k.X = tp; k.ldx = nbp; k.sX = sp;
     k.C = tt[l + 1]; k.C2 = tt[l + 1] + 2 * nbc * nrhs; k.ldc = nbc; k.sC = 2 * nbc * nrhs;
@@ -1395,8 +1438,9 @@ void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const d
     SkinnyDesc k;
     k.M = n; k.K = nb; k.nrhs = nrhs; k.batch = (int)nl; k.a_c64 = f.mixed;
     k.A = leafops; k.lda = n; k.sA = n * n;
+    if (ax) ax->put(k, f.nl1, ax->leaf);
     k.X = (f.L == 0) ? t : tt[f.L]; k.ldx = nb; k.sX = nb * nrhs;
-    k.C = u; k.ldc = nl * n; k.coff = f.puoff + h0; k.cbase = h0 * n;
+    k.C = u; k.ldc = nl * n; k.coff = uoff; k.cbase = lbase * n;
     if (up) {
       k.C0 = ut; k.ld0 = n; k.s0 = n * nrhs;
     }
@@ -1658,9 +1702,10 @@ int refine_iters(const hps_group& f) {
 
 // Solve problems [pb, pb + np), then (when enabled) residual correction in FP64:
 // r = b - A u on the global collocation system, delta = Solve(r) with r's shared-edge
-// rows as interface jumps, u += delta, until every right-hand side's relative
-// correction |delta_r| / |u_r| (norms over the problems of the range), or its contraction
-// estimate of the next one, is <= tol, or the iteration limit.
+// rows as interface jumps, u += delta, until the relative correction |delta| / |u| of
+// every right-hand side of every problem (each problem's share of a right-hand side
+// measured on its own, so that problems of very different scale do not hide each other),
+// or its contraction estimate of the next one, is <= tol, or the iteration limit.
 void solve_impl(hps_group& f, int pb, int np, int nrhs, const double* s, const double* t,
                 const double* jmp, double* u, hipStream_t st, hps_solve_info* info,
                 size_t* ws_bytes = nullptr, char* fixed = nullptr, size_t fixed_cap = 0) {
@@ -1687,7 +1732,7 @@ void solve_impl(hps_group& f, int pb, int np, int nrhs, const double* s, const d
       rt = ws.get((size_t)np * nrhs * nt * 16);
       rj = ws.get((size_t)nrhs * nl * nb * 16);
       dl = ws.get((size_t)nrhs * nl * n * 16);
-      part = ws.get((size_t)nrhs * nblk * 2 * sizeof(double));
+      part = ws.get((size_t)nrhs * np * nblk * 2 * sizeof(double));
     }
     mark = ws.used;
     solve_pass(f, pb, np, nrhs, s, t, jmp, u, ws);  // pass 0 only sizes the workspace
@@ -1699,8 +1744,11 @@ void solve_impl(hps_group& f, int pb, int np, int nrhs, const double* s, const d
   }
   *info = hps_solve_info{};
   if (iters <= 0) return;
-  std::vector<double> hpart((size_t)nrhs * nblk * 2);
-  std::vector<double> prev((size_t)nrhs, 0.0);  // previous relative correction per RHS
+  // norms per right-hand side and problem: u is [nrhs][np][nl1 * n], so column
+  // c = r * np + q of length nl1 * n is problem q's share of right-hand side r
+  const long ncol = (long)nrhs * np, clen = (long)f.nl1 * n;
+  std::vector<double> hpart((size_t)ncol * nblk * 2);
+  std::vector<double> prev((size_t)ncol, 0.0);  // previous relative correction per column
   double corr = 0.0;
   int it = 0;
   bool conv = false;
@@ -1712,19 +1760,19 @@ void solve_impl(hps_group& f, int pb, int np, int nrhs, const double* s, const d
     residual(r, nrhs, st);
     ws.used = mark;
     solve_pass(f, pb, np, nrhs, rs, rt, rj, dl, ws);
-    norms_partial(nl * n, nrhs, dl, u, part, st);
+    norms_partial(clen, (int)ncol, dl, u, part, st);
     axpy((long)nrhs * nl * n, dl, u, st);
     HPS_HIP(hipMemcpyAsync(hpart.data(), part, hpart.size() * sizeof(double),
                            hipMemcpyDeviceToHost, st));
     HPS_HIP(hipStreamSynchronize(st));
-    // Per right-hand side: c = ||delta|| / ||u||.  Done when every c <= tol, or when
-    // the corrections contract (c below half the previous one) fast enough that the
-    // next one, estimated as c * (c / c_prev), is <= tol: then u already carries the
-    // accuracy another sweep would only confirm.  corr reports the larger of c and that
-    // estimate over the right-hand sides.
+    // Per right-hand side of each problem: c = ||delta|| / ||u||.  Done when every c <=
+    // tol, or when the corrections contract (c below half the previous one) fast enough
+    // that the next one, estimated as c * (c / c_prev), is <= tol: then u already
+    // carries the accuracy another sweep would only confirm.  corr reports the larger of
+    // c and that estimate over the columns.
     corr = 0.0;
     bool all_done = true;
-    for (int q = 0; q < nrhs; ++q) {
+    for (long q = 0; q < ncol; ++q) {
       double dd = 0, uu = 0;
       for (int b = 0; b < nblk; ++b) {
         dd += hpart[2 * ((size_t)q * nblk + b)];
@@ -1751,6 +1799,135 @@ void solve_impl(hps_group& f, int pb, int np, int nrhs, const double* s, const d
   if (!conv)
     throw Error(HPS_E_NOT_CONVERGED, "residual correction did not reach refine_tol (last "
                                      "relative correction " + std::to_string(corr) + ")");
+}
+
+size_t align_up(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Problems of two factors can share a solve's launches when their trees, operator shapes
+// and level precisions agree and no residual correction runs (the correction reads each
+// problem's collocation data, which the tabled launches do not carry).
+bool shareable(const hps_group& a, const hps_group& b) {
+  if (a.nx != b.nx || a.ny != b.ny || a.p != b.p || a.L != b.L || a.mixed != b.mixed)
+    return false;
+  if (refine_iters(a) > 0 || refine_iters(b) > 0) return false;
+  for (int l = 0; l < a.L; ++l)
+    if (a.lv[l].c64 != b.lv[l].c64) return false;
+  return true;
+}
+
+bool same_problem(const hps_factor* a, const hps_factor* b) {
+  return a->g.get() == b->g.get() && a->b0 == b->b0;
+}
+
+// One solve over the parts' problems (pairwise shareable, at most Across::kMax distinct):
+// parts on one problem take consecutive right-hand-side columns of it.  Right-hand sides
+// are staged side by side as for a group of the problems, the sweeps run once through
+// the tabled launches, and each part's solution is copied out.  With ws_bytes set, only
+// returns the device bytes the call allocates (workspace and staging).
+void solve_across(const std::vector<SolvePart>& parts, hipStream_t st, size_t* ws_bytes) {
+  if (parts.empty()) return;
+  std::vector<const hps_factor*> fs;
+  std::vector<int> qof(parts.size()), col0(parts.size()), nrq;
+  bool any_s = false;
+  for (size_t i = 0; i < parts.size(); ++i) {
+    const SolvePart& pt = parts[i];
+    if (!pt.f || !pt.t || !pt.u || pt.nrhs < 1) throw Error(HPS_E_INVALID, "bad solve part");
+    size_t q = 0;
+    while (q < fs.size() && !same_problem(fs[q], pt.f)) ++q;
+    if (q == fs.size()) {
+      if (q > 0 && !shareable(*fs[0]->g, *pt.f->g))
+        throw Error(HPS_E_INVALID, "problems of different shapes cannot share a solve");
+      fs.push_back(pt.f);
+      nrq.push_back(0);
+    }
+    qof[i] = (int)q;
+    col0[i] = nrq[q];
+    nrq[q] += pt.nrhs;
+    any_s = any_s || pt.s != nullptr;
+  }
+  const int np = (int)fs.size();
+  if (np > Across::kMax)
+    throw Error(HPS_E_INVALID, "more than " + std::to_string(Across::kMax) +
+                                   " problems in one shared solve");
+  hps_group& g0 = *fs[0]->g;
+  const int R = *std::max_element(nrq.begin(), nrq.end());
+  const long nl1 = g0.nl1, nl = (long)np * nl1, n = g0.n, ni = g0.ni;
+  const long nt = 2L * (g0.nx + g0.ny) * g0.m;
+  Across ax;
+  ax.np = np;
+  {
+    hps_group t;  // leaf maps of an np-problem group of this shape
+    t.p = g0.p; t.m = g0.m; t.n = g0.n; t.nb = g0.nb; t.ni = g0.ni;
+    t.nx = g0.nx; t.ny = g0.ny; t.nprob = np; t.nl1 = g0.nl1; t.nleaf = np * g0.nl1;
+    ax.sh = plan_for(t);
+  }
+  ax.lv.resize(g0.L);
+  for (int q = 0; q < np; ++q) {
+    const hps_group& G = *fs[q]->g;
+    const long b = fs[q]->b0;
+    ax.nrq[q] = nrq[q];
+    ax.leaf[q] = (G.mixed ? G.BI32.d() : G.BI.d()) + (G.mixed ? 1 : 2) * b * nl1 * n * n;
+    ax.prm.p[q] = G.dprm.d() + 4 * b;
+    for (int l = 0; l < G.L; ++l) {
+      const LevelPlan& P = G.lv[l];
+      const long box0 = b << l, e = P.c64 ? 1 : 2;
+      const long n1 = P.n1, n2 = P.n2, n3 = P.n3, nbp = P.nbp;
+      Across::Level& T = ax.lv[l];
+      T.R33b[q] = P.R33b.d() + box0 * n3 * n3 * e;
+      T.Winv[q] = P.Winv.d() + box0 * n3 * n3 * e;
+      T.R33a[q] = P.R33a.d() + box0 * n3 * n3 * e;
+      T.R13a[q] = P.R13a.d() + box0 * n1 * n3 * e;
+      T.R23b[q] = P.R23b.d() + box0 * n2 * n3 * e;
+      T.PhiA[q] = P.PhiA.d() + box0 * n3 * nbp * e;
+      T.PhiB[q] = P.PhiB.d() + box0 * n3 * nbp * e;
+    }
+  }
+  const size_t bs = any_s ? align_up((size_t)R * nl * ni * 16) : 0;
+  const size_t bt = align_up((size_t)np * R * nt * 16), bu = align_up((size_t)R * nl * n * 16);
+  Arena ws;
+  ws.st = st;
+  // sizing pass: placeholders stand in for the vectors and are never dereferenced
+  const double* ph = reinterpret_cast<const double*>(4096);
+  solve_pass(g0, 0, np, R, any_s ? ph : nullptr, ph, nullptr, const_cast<double*>(ph), ws, &ax);
+  if (ws_bytes) {
+    *ws_bytes = std::max(ws.used, ws.peak) + ws.split_need + 256 + bs + bt + bu + 256;
+    return;
+  }
+  void* stage = ws_alloc(bs + bt + bu + 256, st);
+  struct Free {
+    void* p; hipStream_t st;
+    ~Free() { ws_free(p, st); }
+  } fr{stage, st};
+  char* base = static_cast<char*>(stage);
+  double* S = any_s ? reinterpret_cast<double*>(base) : nullptr;
+  double* T = reinterpret_cast<double*>(base + bs);
+  double* U = reinterpret_cast<double*>(base + bs + bt);
+  // columns of a problem beyond its own right-hand sides are never read: the tabled
+  // launches skip them, so only the parts' columns are staged
+  for (size_t i = 0; i < parts.size(); ++i) {
+    const SolvePart& pt = parts[i];
+    const long q = qof[i], c = col0[i];
+    if (S) {
+      double* dst = S + 2 * (c * nl + q * nl1) * ni;
+      if (pt.s)
+        HPS_HIP(hipMemcpy2DAsync(dst, (size_t)nl * ni * 16, pt.s, (size_t)nl1 * ni * 16,
+                                 (size_t)nl1 * ni * 16, pt.nrhs, hipMemcpyDeviceToDevice, st));
+      else
+        for (int r = 0; r < pt.nrhs; ++r) fill_zero(dst + 2 * r * nl * ni, 2 * nl1 * ni, st);
+    }
+    HPS_HIP(hipMemcpyAsync(T + 2 * (q * R + c) * nt, pt.t, (size_t)pt.nrhs * nt * 16,
+                           hipMemcpyDeviceToDevice, st));
+  }
+  ws.allocate();
+  solve_pass(g0, 0, np, R, S, T, nullptr, U, ws, &ax);
+  for (size_t i = 0; i < parts.size(); ++i) {
+    const SolvePart& pt = parts[i];
+    const long q = qof[i], c = col0[i];
+    HPS_HIP(hipMemcpy2DAsync(pt.u, (size_t)nl1 * n * 16, U + 2 * (c * nl + q * nl1) * n,
+                             (size_t)nl * n * 16, (size_t)nl1 * n * 16, pt.nrhs,
+                             hipMemcpyDeviceToDevice, st));
+  }
+  for (int q = 0; q < np; ++q) fs[q]->g->last_info = hps_solve_info{};
 }
 
 }  // namespace
@@ -1801,25 +1978,44 @@ int hps_solve_batch(int32_t nprob, hps_factor* const* f, const int32_t* nrhs,
       if (!f[i] || !t[i] || !u[i]) throw Error(HPS_E_INVALID, "NULL factor, t or u");
       if (nrhs[i] < 1) throw Error(HPS_E_INVALID, "nrhs must be >= 1");
     }
-    // requests of one group go through one batched solve over the problem range they
-    // span (problems of the range without a request get zero data)
+    for (int i = 0; i < nprob; ++i)
+      for (int j = 0; j < i; ++j)
+        if (same_problem(f[i], f[j]))
+          throw Error(HPS_E_INVALID, "a problem appears twice in one batch");
+    // Requests of one group go through one batched solve over the problem range they
+    // span (problems of the range without a request get zero data).  Requests on
+    // shareable problems of several groups on one stream share tabled launches, up to
+    // Across::kMax problems per solve.
     std::vector<char> done(nprob, 0);
     for (int i = 0; i < nprob; ++i) {
       if (done[i]) continue;
       hps_group& G = *f[i]->g;
-      std::vector<int> mem;
-      for (int j = i; j < nprob; ++j)
-        if (!done[j] && f[j]->g.get() == &G) {
-          mem.push_back(j);
-          done[j] = 1;
+      std::vector<int> mem, other;
+      for (int j = i; j < nprob; ++j) {
+        if (done[j]) continue;
+        if (f[j]->g.get() == &G) mem.push_back(j);
+        else if (f[j]->g->stream == G.stream && shareable(G, *f[j]->g)) other.push_back(j);
+      }
+      if (!other.empty()) {
+        std::vector<int> all(mem);
+        all.insert(all.end(), other.begin(), other.end());
+        std::sort(all.begin(), all.end());
+        for (size_t a = 0; a < all.size(); a += Across::kMax) {
+          std::vector<SolvePart> parts;
+          for (size_t b = a; b < std::min(all.size(), a + Across::kMax); ++b) {
+            const int j = all[b];
+            done[j] = 1;
+            parts.push_back({f[j], nrhs[j], s ? s[j] : nullptr, t[j], u[j]});
+          }
+          solve_across(parts, G.stream, nullptr);
         }
+        continue;
+      }
+      for (int j : mem) done[j] = 1;
       int pb = G.nprob, pe = 0, R = 1;
       bool any_s = false;
-      std::vector<char> seen(G.nprob, 0);
       for (int j : mem) {
         const int b = f[j]->b0;
-        if (seen[b]) throw Error(HPS_E_INVALID, "a problem appears twice in one batch");
-        seen[b] = 1;
         pb = std::min(pb, b);
         pe = std::max(pe, b + 1);
         R = std::max(R, (int)nrhs[j]);
@@ -2316,6 +2512,16 @@ size_t solve_workspace_bytes(hps_factor* f, int nrhs, bool with_s) {
 void solve_on(hps_factor* f, int nrhs, const double* s, const double* t, double* u,
               hipStream_t st, hps_solve_info* info) {
   solve_impl(*f->g, f->b0, 1, nrhs, s, t, nullptr, u, st, info);
+}
+
+bool solve_shareable(const hps_factor* a, const hps_factor* b) {
+  return shareable(*a->g, *b->g);
+}
+
+int solve_share_max() { return Across::kMax; }
+
+void solve_parts(const std::vector<SolvePart>& parts, hipStream_t st, size_t* bytes) {
+  solve_across(parts, st, bytes);
 }
 
 }  // namespace hps

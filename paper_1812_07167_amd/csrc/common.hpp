@@ -148,5 +148,7 @@ inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 // Blocks of 256 threads for an elementwise kernel over n items with a grid-stride loop:
 // a dispatch counts its work-items in 32 bits, so the grid is capped (2^28 threads).
 inline unsigned grid1d(long n) { return (unsigned)std::min<long>(cdiv(n, 256), 1L << 20); }
+// a grid's y or z extent (at most 65535); kernels launched with it loop over the rest
+inline unsigned grid_y(long n) { return (unsigned)std::max<long>(1, std::min<long>(n, 65535)); }
 
 }  // namespace hps

@@ -366,15 +366,26 @@ std::string zgemm_variant(const GemmDesc& d) {
 }
 
 void zgemm_check(const GemmDesc& d) {
-  if (d.batch > 65535) throw Error(1, "zgemm: batch exceeds grid limit");
   if (d.K <= 0) throw Error(1, "zgemm: K must be positive");
 }
 
+// Batches beyond the grid's y limit run as consecutive slices (operands advanced by
+// their batch strides; doubles per element: 1 for real or complex64, 2 for complex128).
 void zgemm(const GemmDesc& d, hipStream_t st) {
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
   zgemm_check(d);
-  launch_variant(pick_tile(d), d, st);
-  HPS_LAUNCH_CHECK();
+  const Tile tile = pick_tile(d);
+  const long ea = (d.a_real || d.c64) ? 1 : 2, eb = (d.b_real || d.c64) ? 1 : 2;
+  const long ec = d.c64 ? 1 : 2;
+  for (long b0 = 0; b0 < d.batch; b0 += 65535) {
+    GemmDesc s = d;
+    s.batch = (int)std::min<long>(65535, d.batch - b0);
+    s.A = d.A + b0 * d.sA * ea;
+    s.B = d.B + b0 * d.sB * eb;
+    s.C = d.C + b0 * d.sC * ec;
+    launch_variant(tile, s, st);
+    HPS_LAUNCH_CHECK();
+  }
 }
 
 // Time every tile variant on d's operands (output to a dense scratch matrix, beta = 0,
@@ -389,7 +400,8 @@ void zgemm_tune(const GemmDesc& d, hipStream_t st) {
     if (g_tune.count(key)) return;
   }
   const size_t esz = d.c64 ? 8 : 16;
-  void* scratch = dev_alloc((size_t)d.batch * d.M * d.N * esz);
+  const int tb = std::min(d.batch, 65535);  // timed on the first grid-sized slice
+  void* scratch = dev_alloc((size_t)tb * d.M * d.N * esz);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int best = heuristic_tile(d);
   float best_ms = 0.0f;
@@ -397,6 +409,7 @@ void zgemm_tune(const GemmDesc& d, hipStream_t st) {
     HPS_HIP(hipEventCreate(&e0));
     HPS_HIP(hipEventCreate(&e1));
     GemmDesc t = d;
+    t.batch = tb;
     t.C = static_cast<double*>(scratch);
     t.ldc = d.M;
     t.sC = (long)d.M * d.N;

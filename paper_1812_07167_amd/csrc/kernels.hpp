@@ -61,6 +61,16 @@ struct SkinnyDesc {
   const int* crow2 = nullptr;
   const double* C02 = nullptr;
   const double* X2 = nullptr;
+  // Operators of several factors of one shape in one launch: when aper > 0, entry b
+  // belongs to factor q = b / aper and its operator is Atab[q] + (b % aper) * sA (Atab2
+  // for the second operator); A and A2 are then unused.  nrq[q] > 0 limits factor q to
+  // its first nrq[q] right-hand sides: its entries skip the columns beyond (their
+  // outputs are left unwritten).
+  static constexpr int kMaxTab = 16;
+  int aper = 0;
+  const double* Atab[kMaxTab] = {};
+  const double* Atab2[kMaxTab] = {};
+  int nrq[kMaxTab] = {};
 };
 size_t skinny_work_bytes(const SkinnyDesc& d);
 void zgemm_skinny(const SkinnyDesc& d, hipStream_t st);
@@ -155,9 +165,11 @@ void merge_add_diag(const MergeLevelDesc& d, hipStream_t st);
 
 // ------------------------------------------------------------------ solve helpers
 // h_b = -2 i eta * u_b[0:nb]  for every leaf (u_b is n x nrhs, h_b is nb x nrhs); eta of
-// leaf b is that of problem b / nl1 in prm ([problem][4]: kappa, Re eta, Im eta, 0)
+// leaf b is that of problem b / nl1 in prm ([problem][4]: kappa, Re eta, Im eta, 0), or,
+// when tab is given, in the row tab->p[b / nl1] (problems of several factors)
+struct PrmTab { const double* p[SkinnyDesc::kMaxTab] = {}; };
 void leaf_h_from_u(int nleaf, int n, int nb, int nrhs, const double* prm, int nl1,
-                   const double* u, double* h, hipStream_t st);
+                   const double* u, double* h, hipStream_t st, const PrmTab* tab = nullptr);
 // Upward gather of one level: h3a, -h3a (into ttb), -h3b (into v), and the h1/h2 parts
 // of the parent's h.  hc: children's h [2*nbox][nbc x nrhs]; hp: [nbox][nbp x nrhs].
 // With right-hand sides on the shared-edge rows (jmp: [nrhs][ldj], ja/jb: per merge and

@@ -56,9 +56,9 @@ __global__ void extract_kernel(MergeLevelDesc d) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long nn = (long)d.nbc * d.nbc;
   if (e >= nn) return;
-  const long q = blockIdx.y;
   const int side = blockIdx.z;
   const int i = e % d.nbc, j = e / d.nbc;
+  for (long q = blockIdx.y; q < d.nbox; q += gridDim.y) {
   const Cc* R = reinterpret_cast<const Cc*>(d.Rc) + (2 * q + side) * nn;
   const Cc w = R[e];
   const Cp v = Cx<Tp>::mk((Tp)w.x, (Tp)w.y);
@@ -86,6 +86,7 @@ __global__ void extract_kernel(MergeLevelDesc d) {
       reinterpret_cast<Cp*>(d.R23b)[q * n2 * n3 + ki + (long)n2 * kj] = v;
     }
   }
+  }  // boxes
 }
 
 // Parent R += blockdiag(R11^a, R22^b) in canonical order: entry (i, j) of I1 x I1 comes
@@ -94,13 +95,13 @@ template <class Tc, class Tp>
 __global__ void add_diag_kernel(MergeLevelDesc d) {
   typedef typename Cx<Tc>::t Cc;
   typedef typename Cx<Tp>::t Cp;
-  const long q = blockIdx.y;
   const int side = blockIdx.z;
   const int nk = side ? d.n2 : d.n1;
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)nk * nk) return;
   const int i = e % nk, j = e / nk;
   const long nn = (long)d.nbc * d.nbc;
+  for (long q = blockIdx.y; q < d.nbox; q += gridDim.y) {
   const Cc* R = reinterpret_cast<const Cc*>(d.Rc) + (2 * q + side) * nn;
   const int* pos = side ? d.i2b : d.i1a;
   const int* pm = d.perm + (side ? d.n1 : 0);
@@ -110,17 +111,19 @@ __global__ void add_diag_kernel(MergeLevelDesc d) {
   v.x += (Tp)w.x;
   v.y += (Tp)w.y;
   *P = v;
+  }  // boxes
 }
 
 __global__ void leaf_h_kernel(int nleaf, int n, int nb, int nrhs, const double* prm, int nl1,
-                              const double2* u, double2* h) {
+                              const double2* u, double2* h, PrmTab tab, bool use_tab) {
   const long per = (long)nb * nrhs;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < per * nleaf;
        e += (long)gridDim.x * blockDim.x) {
     const long b = e / per;
     const int loc = e % per;
     const int k = loc % nb, r = loc / nb;
-    const double* pp = prm + 4 * (b / nl1);  // the leaf's problem: kappa, Re eta, Im eta
+    // the leaf's problem: kappa, Re eta, Im eta
+    const double* pp = use_tab ? tab.p[b / nl1] : prm + 4 * (b / nl1);
     const double2 x = u[b * (long)n * nrhs + k + (long)n * r];
     h[e] = cmul(cmk(2.0 * pp[2], -2.0 * pp[1]), x);
   }
@@ -129,12 +132,12 @@ __global__ void leaf_h_kernel(int nleaf, int n, int nb, int nrhs, const double* 
 __global__ void up_gather_kernel(MergeLevelDesc d, int nrhs, const double2* hc, double2* h3a,
                                  double2* v, double2* ttb, double2* hp, const double2* jmp,
                                  long ldj, const int* ja, const int* jb, long jbase) {
-  const long q = blockIdx.y;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const int n1 = d.n1, n2 = d.n2, n3 = d.n3, nbc = d.nbc, nbp = d.nbp;
   const int rows = n3 + n1 + n2;
   if (e >= rows * nrhs) return;
   const int k = e % rows, r = e / rows;
+  for (long q = blockIdx.y; q < d.nbox; q += gridDim.y) {
   const double2* ha = hc + (2 * q) * (long)nbc * nrhs;
   const double2* hb = hc + (2 * q + 1) * (long)nbc * nrhs;
   if (k < n3) {
@@ -156,16 +159,17 @@ __global__ void up_gather_kernel(MergeLevelDesc d, int nrhs, const double2* hc, 
     const int kk = k - n3 - n1;
     hp[q * (long)nbp * nrhs + d.perm[n1 + kk] + (long)nbp * r] = hb[d.i2b[kk] + (long)nbc * r];
   }
+  }  // boxes
 }
 
 __global__ void down_scatter_kernel(MergeLevelDesc d, int nrhs, const double2* tp, long ldp,
                                     double2* tc) {
-  const long q = blockIdx.y;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const int n1 = d.n1, n2 = d.n2, nbc = d.nbc, nbp = d.nbp;
   const int rows = n1 + n2;
   if (e >= rows * nrhs) return;
   const int k = e % rows, r = e / rows;
+  for (long q = blockIdx.y; q < d.nbox; q += gridDim.y) {
   const double2* t = tp + q * (long)nbp * nrhs;
   if (k < n1) {
     tc[(2 * q) * (long)nbc * nrhs + d.i1a[k] + (long)nbc * r] = t[d.perm[k] + ldp * r];
@@ -173,6 +177,7 @@ __global__ void down_scatter_kernel(MergeLevelDesc d, int nrhs, const double2* t
     const int kk = k - n1;
     tc[(2 * q + 1) * (long)nbc * nrhs + d.i2b[kk] + (long)nbc * r] = t[d.perm[n1 + kk] + ldp * r];
   }
+  }  // boxes
 }
 
 }  // namespace
@@ -215,7 +220,7 @@ void fill_identity(double* p, int n, long stride, int batch, hipStream_t st, boo
 
 void merge_extract(const MergeLevelDesc& d, hipStream_t st) {
   long nn = (long)d.nbc * d.nbc;
-  const dim3 grid(cdiv(nn, 256), d.nbox, 2);
+  const dim3 grid(cdiv(nn, 256), grid_y(d.nbox), 2);
   if (d.child_c64 && d.c64)
     hipLaunchKernelGGL((extract_kernel<float, float>), grid, dim3(256), 0, st, d);
   else if (d.c64)
@@ -229,7 +234,7 @@ void merge_extract(const MergeLevelDesc& d, hipStream_t st) {
 
 void merge_add_diag(const MergeLevelDesc& d, hipStream_t st) {
   const long nk = std::max(d.n1, d.n2);
-  const dim3 grid(cdiv(nk * nk, 256), d.nbox, 2);
+  const dim3 grid(cdiv(nk * nk, 256), grid_y(d.nbox), 2);
   if (d.child_c64 && d.c64)
     hipLaunchKernelGGL((add_diag_kernel<float, float>), grid, dim3(256), 0, st, d);
   else if (d.c64)
@@ -242,10 +247,12 @@ void merge_add_diag(const MergeLevelDesc& d, hipStream_t st) {
 }
 
 void leaf_h_from_u(int nleaf, int n, int nb, int nrhs, const double* prm, int nl1,
-                   const double* u, double* h, hipStream_t st) {
+                   const double* u, double* h, hipStream_t st, const PrmTab* tab) {
   long tot = (long)nleaf * nb * nrhs;
+  const PrmTab t = tab ? *tab : PrmTab();
   hipLaunchKernelGGL(leaf_h_kernel, dim3(grid1d(tot)), dim3(256), 0, st, nleaf, n, nb, nrhs,
-                     prm, nl1, reinterpret_cast<const double2*>(u), reinterpret_cast<double2*>(h));
+                     prm, nl1, reinterpret_cast<const double2*>(u), reinterpret_cast<double2*>(h),
+                     t, tab != nullptr);
   HPS_LAUNCH_CHECK();
 }
 
@@ -253,7 +260,7 @@ void up_gather(const MergeLevelDesc& d, int nrhs, const double* hc, double* h3a,
                double* ttb, double* hp, const double* jmp, long ldj, const int* ja,
                const int* jb, long jbase, hipStream_t st) {
   long rows = (long)(d.n3 + d.n1 + d.n2) * nrhs;
-  hipLaunchKernelGGL(up_gather_kernel, dim3(cdiv(rows, 256), d.nbox), dim3(256), 0, st, d, nrhs,
+  hipLaunchKernelGGL(up_gather_kernel, dim3(cdiv(rows, 256), grid_y(d.nbox)), dim3(256), 0, st, d, nrhs,
                      reinterpret_cast<const double2*>(hc), reinterpret_cast<double2*>(h3a),
                      reinterpret_cast<double2*>(v), reinterpret_cast<double2*>(ttb),
                      reinterpret_cast<double2*>(hp), reinterpret_cast<const double2*>(jmp), ldj,
@@ -264,7 +271,7 @@ void up_gather(const MergeLevelDesc& d, int nrhs, const double* hc, double* h3a,
 void down_scatter(const MergeLevelDesc& d, int nrhs, const double* tp, long ldp, double* tc,
                   hipStream_t st) {
   long rows = (long)(d.n1 + d.n2) * nrhs;
-  hipLaunchKernelGGL(down_scatter_kernel, dim3(cdiv(rows, 256), d.nbox), dim3(256), 0, st, d,
+  hipLaunchKernelGGL(down_scatter_kernel, dim3(cdiv(rows, 256), grid_y(d.nbox)), dim3(256), 0, st, d,
                      nrhs, reinterpret_cast<const double2*>(tp), ldp,
                      reinterpret_cast<double2*>(tc));
   HPS_LAUNCH_CHECK();

@@ -148,18 +148,20 @@ __global__ void axpy_kernel(long n, const double2* x, double2* y) {
     y[e] = cadd(y[e], x[e]);
 }
 
-// partial sums of |x|^2 and |y|^2 per block of one right-hand side (fixed order)
-__global__ __launch_bounds__(256) void norms_kernel(long len, const double2* x, const double2* y,
-                                                    double* part) {
+// partial sums of |x|^2 and |y|^2 per block of one column (fixed order); columns beyond
+// the grid's y extent are taken in turn
+__global__ __launch_bounds__(256) void norms_kernel(long len, int ncol, const double2* x,
+                                                    const double2* y, double* part) {
   __shared__ double sx[256], sy[256];
-  const int r = blockIdx.y;
-  const long base = (long)r * len;
+  for (long r = blockIdx.y; r < ncol; r += gridDim.y) {
+  const long base = r * len;
   double ax = 0, ay = 0;
   for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < len; e += (long)gridDim.x * 256) {
     const double2 a = x[base + e], b = y[base + e];
     ax += a.x * a.x + a.y * a.y;
     ay += b.x * b.x + b.y * b.y;
   }
+  __syncthreads();  // the previous column's sums have been read
   sx[threadIdx.x] = ax;
   sy[threadIdx.x] = ay;
   __syncthreads();
@@ -171,9 +173,10 @@ __global__ __launch_bounds__(256) void norms_kernel(long len, const double2* x, 
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    part[2 * ((long)r * gridDim.x + blockIdx.x)] = sx[0];
-    part[2 * ((long)r * gridDim.x + blockIdx.x) + 1] = sy[0];
+    part[2 * (r * gridDim.x + blockIdx.x)] = sx[0];
+    part[2 * (r * gridDim.x + blockIdx.x) + 1] = sy[0];
   }
+  }  // columns
 }
 
 }  // namespace
@@ -206,9 +209,9 @@ int norms_blocks() { return 64; }
 void norms_partial(long len, int nrhs, const double* x, const double* y, double* part,
                    hipStream_t st) {
   if (len <= 0 || nrhs <= 0) return;
-  hipLaunchKernelGGL(norms_kernel, dim3(norms_blocks(), nrhs), dim3(256), 0, st, len,
-                     reinterpret_cast<const double2*>(x), reinterpret_cast<const double2*>(y),
-                     part);
+  hipLaunchKernelGGL(norms_kernel, dim3(norms_blocks(), grid_y(nrhs)), dim3(256), 0, st, len,
+                     nrhs, reinterpret_cast<const double2*>(x),
+                     reinterpret_cast<const double2*>(y), part);
   HPS_LAUNCH_CHECK();
 }
 

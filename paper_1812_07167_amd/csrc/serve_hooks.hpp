@@ -1,11 +1,13 @@
 // Library-internal entry points shared by the C ABI and the request loop: the solve of
-// one factor on an explicit stream, the size of its workspace, and the workspace pool.
+// one factor, or of several factors' problems together, on an explicit stream, the size
+// of its workspace, and the workspace pool.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
 #include <string>
+#include <vector>
 
 #include "../../include/hps.h"
 
@@ -19,6 +21,26 @@ size_t solve_workspace_bytes(hps_factor* f, int nrhs, bool with_s);
 // hps::Error on failure.
 void solve_on(hps_factor* f, int nrhs, const double* s, const double* t, double* u,
               hipStream_t st, hps_solve_info* info);
+
+// One request's share of a solve over several problems: nrhs right-hand sides of factor
+// f's problem (s may be NULL), solution into u; pointers as for hps_solve.
+struct SolvePart {
+  hps_factor* f = nullptr;
+  int nrhs = 0;
+  const double* s = nullptr;
+  const double* t = nullptr;
+  double* u = nullptr;
+};
+// Whether the problems of a and b can share one solve's launches (same leaf grid, p and
+// level precisions, no residual correction).
+bool solve_shareable(const hps_factor* a, const hps_factor* b);
+// Most distinct problems one shared solve takes.
+int solve_share_max();
+// Solve the parts (pairwise shareable problems, at most solve_share_max() distinct; parts
+// of one problem take consecutive right-hand-side columns) with one launch per level
+// step on stream st.  With bytes set, only returns the device bytes the call allocates.
+// Throws hps::Error.
+void solve_parts(const std::vector<SolvePart>& parts, hipStream_t st, size_t* bytes = nullptr);
 
 // Device memory for one call's workspace or staging, from the library's cache of
 // buffers on the current device: ws_alloc orders stream st after the buffer's previous

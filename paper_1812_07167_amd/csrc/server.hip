@@ -2,15 +2,17 @@
 // one problem at a time): builds and solves of many problems run on a pool of work slots
 // (a host thread and a stream each) so that their kernels overlap on the device; every
 // work item is admitted against a device-memory budget; queued right-hand sides of one
-// problem are merged into a single solve (continuous batching).
+// problem are merged into a single solve (continuous batching), and so are those of
+// other idle problems that can share the solve's launches.
 //
 // Scheduling: a slot that is free takes the oldest admissible item, oldest meaning the
 // earliest submission among the requests it would serve.  An item is a problem's
-// (re)build or one solve of a problem over its queued requests.  At most one item per
-// problem runs at a time.  An item is admissible when the bytes it needs fit beside the
-// committed bytes (server copies of c, resident factors, running items); otherwise idle
-// factors are freed least recently used first, when that makes it fit.  When nothing
-// runs and the oldest item still cannot fit, it fails with HPS_E_NOMEM.
+// (re)build or one solve over queued requests of one or more problems.  The first
+// solve_slots slots take no builds.  At most one item per problem runs at a time.  An
+// item is admissible when the bytes it needs fit beside the committed bytes (server
+// copies of c, resident factors, running items); otherwise idle factors are freed least
+// recently used first, when that makes it fit.  When nothing runs and the oldest item
+// still cannot fit, it fails with HPS_E_NOMEM.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -68,15 +70,21 @@ struct Problem {
   bool rebuilt = false;      // rebuilt after an eviction, not yet solved with since
 };
 
-struct Work {
-  enum Kind { None, Build, Solve } kind = None;
+// one problem's requests in a solve
+struct Share {
   Problem* pr = nullptr;
   std::vector<SolveReq> reqs;
+  bool after_rebuild = false;  // the first solve after a rebuild of its factor
+};
+
+struct Work {
+  enum Kind { None, Build, Solve } kind = None;
+  Problem* pr = nullptr;     // the build's problem, or the first problem of a solve
+  std::vector<Share> shares; // a solve's problems, pr's first
   size_t mem = 0;            // bytes committed while it runs
   bool rebuild = false;
-  int R = 0;                 // right-hand sides of a solve
+  int R = 0;                 // right-hand sides of a solve, over all its problems
   bool any_s = false;
-  bool after_rebuild = false;  // a solve that follows a rebuild of its factor
 };
 
 struct Freed {
@@ -111,7 +119,8 @@ struct hps_server {
   hps::Clock::time_point t0;
   int running = 0, max_running = 0;
   int64_t builds = 0, rebuilds = 0, evictions = 0, solves = 0, rhs = 0, batches = 0;
-  int64_t rejected = 0, failed = 0;
+  int64_t rejected = 0, failed = 0, shared_batches = 0, shared_problems = 0;
+  int solve_only = 0;  // slots [0, solve_only) take no builds
   std::vector<double> lat_ms;
   double first_submit = -1.0, last_end = 0.0;
   double now() const {
@@ -192,6 +201,25 @@ size_t solve_need(Problem& p, size_t k, int* R, bool* any_s) {
   return ws + staging_bytes(p, r, s, k) + 1024;
 }
 
+// the parts of a shared solve: every request of every share
+std::vector<SolvePart> parts_of(const std::vector<Share>& sh) {
+  std::vector<SolvePart> parts;
+  for (const Share& x : sh)
+    for (const SolveReq& r : x.reqs) parts.push_back({x.pr->f, r.nrhs, r.s, r.t, r.u});
+  return parts;
+}
+
+// bytes a shared solve needs
+size_t shared_need(const std::vector<Share>& sh) {
+  size_t b = 0;
+  try {
+    solve_parts(parts_of(sh), nullptr, &b);
+  } catch (const std::exception&) {
+    return ~size_t(0) / 4;
+  }
+  return b + 1024;
+}
+
 // requests of p's queue that one merged solve takes (at least one)
 size_t batch_len(const Problem& p, int max_rhs) {
   size_t k = 0;
@@ -205,7 +233,7 @@ size_t batch_len(const Problem& p, int max_rhs) {
 
 // Choose the next work item (caller holds the lock).  Returns true when it changed
 // anything (took work, queued frees, produced completions).
-bool pick(hps_server& S, Work& w, std::vector<Freed>& fr) {
+bool pick(hps_server& S, Work& w, std::vector<Freed>& fr, bool builds) {
   bool progress = false;
   const double tnow = S.now();
   // failed problems answer their queued solves; released idle problems go away
@@ -238,9 +266,11 @@ bool pick(hps_server& S, Work& w, std::vector<Freed>& fr) {
   for (auto& kv : S.problems) {
     Problem* p = kv.second.get();
     if (p->busy) continue;
-    if (p->state == PState::Queued) cands.push_back({p->build_submit, p, Work::Build});
-    else if (p->state == PState::Evicted && !p->pending.empty())
-      cands.push_back({p->pending.front().t_submit, p, Work::Build});
+    if (p->state == PState::Queued) {
+      if (builds) cands.push_back({p->build_submit, p, Work::Build});
+    } else if (p->state == PState::Evicted && !p->pending.empty()) {
+      if (builds) cands.push_back({p->pending.front().t_submit, p, Work::Build});
+    }
     else if (p->state == PState::Resident && !p->pending.empty())
       cands.push_back({p->pending.front().t_submit, p, Work::Solve});
   }
@@ -272,10 +302,53 @@ bool pick(hps_server& S, Work& w, std::vector<Freed>& fr) {
       w.mem = need;
       w.R = R;
       w.any_s = any_s;
-      w.after_rebuild = p.rebuilt;
-      p.rebuilt = false;
-      w.reqs.assign(p.pending.begin(), p.pending.begin() + (long)k);
+      Share mine;
+      mine.pr = &p;
+      mine.reqs.assign(p.pending.begin(), p.pending.begin() + (long)k);
+      w.shares.push_back(std::move(mine));
+      if (S.opts.share_problems) {
+        // idle resident problems whose queued requests can ride along, oldest first
+        std::vector<Problem*> more;
+        for (auto& kv : S.problems) {
+          Problem* q = kv.second.get();
+          if (q != &p && !q->busy && q->state == PState::Resident && !q->pending.empty() &&
+              solve_shareable(p.f, q->f))
+            more.push_back(q);
+        }
+        std::stable_sort(more.begin(), more.end(), [](const Problem* a, const Problem* b) {
+          return a->pending.front().t_submit < b->pending.front().t_submit;
+        });
+        if ((int)more.size() > solve_share_max() - 1) more.resize(solve_share_max() - 1);
+        if (!more.empty()) {
+          std::vector<Share> sh = w.shares;
+          for (Problem* q : more) {
+            Share x;
+            x.pr = q;
+            const size_t kq = batch_len(*q, S.opts.max_batch_rhs);
+            x.reqs.assign(q->pending.begin(), q->pending.begin() + (long)kq);
+            sh.push_back(std::move(x));
+          }
+          const size_t need2 = shared_need(sh);
+          if (evict_for(S, need2, &p, fr)) {
+            w.shares = std::move(sh);
+            w.mem = need2;
+            for (size_t i = 1; i < w.shares.size(); ++i) {
+              Problem& q = *w.shares[i].pr;
+              q.pending.erase(q.pending.begin(), q.pending.begin() + (long)w.shares[i].reqs.size());
+              for (const SolveReq& r : w.shares[i].reqs) {
+                w.R += r.nrhs;
+                w.any_s = w.any_s || r.s != nullptr;
+              }
+            }
+          }
+        }
+      }
       p.pending.erase(p.pending.begin(), p.pending.begin() + (long)k);
+      for (Share& x : w.shares) {
+        x.after_rebuild = x.pr->rebuilt;
+        x.pr->rebuilt = false;
+        x.pr->busy = true;
+      }
     }
     p.busy = true;
     S.committed += w.mem;
@@ -312,13 +385,18 @@ struct StreamFree {
 };
 
 // One merged solve: requests' s and t side by side in staging, one solve, u scattered.
+// A solve over several problems stages through the shared-solve path.
 int run_solve(Problem& p, const Work& w, hipStream_t st, hps_solve_info* info,
               std::string* msg) {
   try {
     const long nl = p.nl1, n = p.n, ni = p.ni, nt = p.nt;
     const int R = w.R;
-    if (w.reqs.size() == 1) {
-      const SolveReq& r = w.reqs[0];
+    const std::vector<SolveReq>& reqs = w.shares[0].reqs;
+    if (w.shares.size() > 1) {
+      *info = hps_solve_info{};
+      solve_parts(parts_of(w.shares), st);
+    } else if (reqs.size() == 1) {
+      const SolveReq& r = reqs[0];
       solve_on(p.f, r.nrhs, r.s, r.t, r.u, st, info);
     } else {
       const size_t bs = w.any_s ? align256((size_t)R * nl * ni * 16) : 0;
@@ -332,7 +410,7 @@ int run_solve(Problem& p, const Work& w, hipStream_t st, hps_solve_info* info,
       double* T = reinterpret_cast<double*>(base + bs);
       double* U = reinterpret_cast<double*>(base + bs + bt);
       long o = 0;
-      for (const SolveReq& r : w.reqs) {
+      for (const SolveReq& r : reqs) {
         if (S) {
           if (r.s)
             HPS_HIP(hipMemcpyAsync(S + 2 * o * nl * ni, r.s, (size_t)r.nrhs * nl * ni * 16,
@@ -346,7 +424,7 @@ int run_solve(Problem& p, const Work& w, hipStream_t st, hps_solve_info* info,
       }
       solve_on(p.f, R, S, T, U, st, info);
       o = 0;
-      for (const SolveReq& r : w.reqs) {
+      for (const SolveReq& r : reqs) {
         HPS_HIP(hipMemcpyAsync(r.u, U + 2 * o * nl * n, (size_t)r.nrhs * nl * n * 16,
                                hipMemcpyDeviceToDevice, st));
         o += r.nrhs;
@@ -372,7 +450,7 @@ void slot_main(hps_server* S, int slot) {
   while (!S->stop) {
     Work w;
     std::vector<Freed> fr;
-    if (!pick(*S, w, fr)) {
+    if (!pick(*S, w, fr, slot >= S->solve_only)) {
       S->cv_work.wait(lk);
       continue;
     }
@@ -411,6 +489,10 @@ void slot_main(hps_server* S, int slot) {
       --S->running;
       p.busy = false;
       p.last_use = ++S->lru_clock;
+      for (size_t i = 1; i < w.shares.size(); ++i) {
+        w.shares[i].pr->busy = false;
+        w.shares[i].pr->last_use = S->lru_clock;
+      }
       if (w.kind == Work::Build) {
         if (status == HPS_OK) {
           p.f = built;
@@ -430,15 +512,20 @@ void slot_main(hps_server* S, int slot) {
                    t_start, t_end);
       } else {
         ++S->batches;
-        for (const SolveReq& r : w.reqs) {
-          complete(*S, p, HPS_REQ_SOLVE, r.id, status, r.nrhs, w.R, info.iterations,
-                   w.after_rebuild, r.t_submit, t_start, t_end);
-          if (status == HPS_OK) {
-            ++S->solves;
-            S->rhs += r.nrhs;
-            S->lat_ms.push_back(1e3 * (t_end - r.t_submit));
-          }
+        if (w.shares.size() > 1) {
+          ++S->shared_batches;
+          S->shared_problems += (int64_t)w.shares.size();
         }
+        for (const Share& x : w.shares)
+          for (const SolveReq& r : x.reqs) {
+            complete(*S, *x.pr, HPS_REQ_SOLVE, r.id, status, r.nrhs, w.R, info.iterations,
+                     x.after_rebuild, r.t_submit, t_start, t_end);
+            if (status == HPS_OK) {
+              ++S->solves;
+              S->rhs += r.nrhs;
+              S->lat_ms.push_back(1e3 * (t_end - r.t_submit));
+            }
+          }
       }
     }
     S->cv_work.notify_all();
@@ -485,6 +572,8 @@ void hps_server_default_opts(hps_server_opts* o) {
   o->max_batch_rhs = 64;
   o->max_pending_builds = 64;
   o->evict_idle = 1;
+  o->solve_slots = 1;
+  o->share_problems = 1;
 }
 
 int hps_server_create(size_t hbm_budget, const hps_server_opts* opts, hps_server** out) {
@@ -497,8 +586,10 @@ int hps_server_create(size_t hbm_budget, const hps_server_opts* opts, hps_server
     if (o.slots < 1 || o.slots > 16) throw Error(HPS_E_INVALID, "slots must be in [1, 16]");
     if (o.max_batch_rhs < 1) throw Error(HPS_E_INVALID, "max_batch_rhs must be >= 1");
     if (o.max_pending_builds < 1) throw Error(HPS_E_INVALID, "max_pending_builds must be >= 1");
+    if (o.solve_slots < 0) throw Error(HPS_E_INVALID, "solve_slots must be >= 0");
     std::unique_ptr<hps_server> S(new hps_server);
     S->opts = o;
+    S->solve_only = std::min(o.solve_slots, o.slots - 1);
     HPS_HIP(hipGetDevice(&S->device));
     if (hbm_budget == 0) {
       size_t fr = 0, tot = 0;
@@ -671,6 +762,8 @@ int hps_server_stats(hps_server* S, hps_stats* st) {
     z.budget_bytes = (int64_t)S->budget;
     z.committed_bytes = (int64_t)S->committed;
     z.peak_committed_bytes = (int64_t)S->peak_committed;
+    z.shared_batches = S->shared_batches;
+    z.shared_problems = S->shared_problems;
     *st = z;
     return HPS_OK;
   });

@@ -47,12 +47,16 @@ template <> struct SkMfma<float> {
 constexpr int KC = 64;   // K chunk staged in LDS
 constexpr int NRB = 16;  // right-hand sides per pass (the MFMA's N)
 
+// a second operator is applied in the same launch
+__host__ __device__ inline bool has2(const SkinnyDesc& d) {
+  return d.aper > 0 ? d.Atab2[0] != nullptr : d.A2 != nullptr;
+}
 // batch entries of a launch: the second operator's follow the first's
-__host__ __device__ inline int nbatch(const SkinnyDesc& d) { return d.A2 ? 2 * d.batch : d.batch; }
+__host__ __device__ inline int nbatch(const SkinnyDesc& d) { return has2(d) ? 2 * d.batch : d.batch; }
 
 template <class T, int TW, int WK>
 __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int nr, int kper,
-                                                     double2* partial) {
+                                                     double2* partial, long y0) {
   typedef typename Cx<T>::t C2;
   typedef SkMfma<T> MF;
   typedef typename MF::acc acc_t;
@@ -64,13 +68,23 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave % WR, kw = wave / WR;
   const int li = lane & 15, lk = lane >> 4;
-  const long bb = blockIdx.y;  // batch entry of the launch
-  const bool two = d.A2 && bb >= d.batch;
+  const long bb = y0 + blockIdx.y;  // batch entry of the launch
+  const bool two = has2(d) && bb >= d.batch;
   const long b = two ? bb - d.batch : bb;  // entry of its operator
   const int ks = blockIdx.z;
   const int kbeg = ks * kper, kend = min(d.K, kbeg + kper);
   const int row0 = blockIdx.x * ROWS + wr * 16 * TW;
-  const C2* A = reinterpret_cast<const C2*>(two ? d.A2 : d.A) + b * d.sA;
+  const C2* A;
+  if (d.aper > 0) {
+    const int q = (int)(b / d.aper);
+    if (d.nrq[q] > 0) {
+      if (d.nrq[q] <= r0) return;  // whole workgroup: this factor has no such columns
+      nr = min(nr, d.nrq[q] - r0);
+    }
+    A = reinterpret_cast<const C2*>(two ? d.Atab2[q] : d.Atab[q]) + (b % d.aper) * d.sA;
+  } else {
+    A = reinterpret_cast<const C2*>(two ? d.A2 : d.A) + b * d.sA;
+  }
   const double2* X = reinterpret_cast<const double2*>(two && d.X2 ? d.X2 : d.X) +
                      (d.xoff ? d.xoff[b] - d.xbase : b * d.sX);
 
@@ -185,8 +199,12 @@ __global__ void skinny_reduce_kernel(SkinnyDesc d, int r0, int nr, int nsplit,
     const int i = e % d.M;
     const int r = (e / d.M) % nr;
     const long bb = e / ((long)d.M * nr);
-    const bool two = d.A2 && bb >= d.batch;
+    const bool two = has2(d) && bb >= d.batch;
     const long b = two ? bb - d.batch : bb;
+    if (d.aper > 0) {
+      const int nq = d.nrq[b / d.aper];
+      if (nq > 0 && r0 + r >= nq) continue;  // a column the factor does not have
+    }
     double2 acc = cmk(0, 0);
     for (int s = 0; s < nsplit; ++s)
       acc = cadd(acc, partial[(((long)s * nbt + bb) * NRB + r) * d.M + i]);
@@ -237,22 +255,31 @@ int split_plan(const SkinnyDesc& d, int* kper_out) {
   return nsplit;
 }
 
+// launches of batches beyond the grid's y limit take consecutive slices of it
+constexpr long kGridY = 65535;
+
 template <class T, int TW, int WK>
 void run_chunk(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
   const int tiles = cdiv(d.M, 16 * TW * (4 / WK));
   int kper = 0;
   const int nsplit = split_plan(d, &kper);
+  const long nbt = nbatch(d);
   if (nsplit == 1) {
-    hipLaunchKernelGGL((skinny_kernel<T, TW, WK>), dim3(tiles, nbatch(d), 1), dim3(256), 0, st,
-                       d, r0, nr, d.K, (double2*)nullptr);
-    HPS_LAUNCH_CHECK();
+    for (long y0 = 0; y0 < nbt; y0 += kGridY) {
+      hipLaunchKernelGGL((skinny_kernel<T, TW, WK>), dim3(tiles, std::min(kGridY, nbt - y0), 1),
+                         dim3(256), 0, st, d, r0, nr, d.K, (double2*)nullptr, y0);
+      HPS_LAUNCH_CHECK();
+    }
     return;
   }
   if (!d.work) throw Error(1, "zgemm_skinny: split-K needs a workspace");
   double2* part = static_cast<double2*>(d.work);
-  hipLaunchKernelGGL((skinny_kernel<T, TW, WK>), dim3(tiles, nbatch(d), nsplit), dim3(256), 0,
-                     st, d, r0, nr, kper, part);
-  HPS_LAUNCH_CHECK();
+  for (long y0 = 0; y0 < nbt; y0 += kGridY) {
+    hipLaunchKernelGGL((skinny_kernel<T, TW, WK>),
+                       dim3(tiles, std::min(kGridY, nbt - y0), nsplit), dim3(256), 0, st, d, r0,
+                       nr, kper, part, y0);
+    HPS_LAUNCH_CHECK();
+  }
   long tot = (long)nbatch(d) * d.M * nr;
   hipLaunchKernelGGL(skinny_reduce_kernel, dim3(grid1d(tot)), dim3(256), 0, st, d, r0, nr,
                      nsplit, (const double2*)part);
@@ -286,9 +313,15 @@ size_t skinny_work_bytes(const SkinnyDesc& d) {
 
 void zgemm_skinny(const SkinnyDesc& d, hipStream_t st) {
   if (d.M <= 0 || d.batch <= 0 || d.nrhs <= 0) return;
-  if (nbatch(d) > 65535) throw Error(1, "zgemm_skinny: batch exceeds grid limit");
-  if (d.A2 && !d.C2) throw Error(1, "zgemm_skinny: second operator without output");
-  if (d.X2 && !d.A2) throw Error(1, "zgemm_skinny: second right-hand side block without operator");
+  if (has2(d) && !d.C2) throw Error(1, "zgemm_skinny: second operator without output");
+  if (d.X2 && !has2(d)) throw Error(1, "zgemm_skinny: second right-hand side block without operator");
+  if (d.aper > 0) {
+    if ((long)d.batch > (long)d.aper * SkinnyDesc::kMaxTab || d.batch % d.aper)
+      throw Error(1, "zgemm_skinny: batch is not a whole number of tabled factors");
+    for (int q = 0; q < d.batch / d.aper; ++q)
+      if (!d.Atab[q] || (d.Atab2[0] && !d.Atab2[q]))
+        throw Error(1, "zgemm_skinny: missing operator of a tabled factor");
+  }
   if (d.K <= 0) throw Error(1, "zgemm_skinny: K must be positive");
   for (int r0 = 0; r0 < d.nrhs; r0 += NRB) run_pass(d, r0, std::min(NRB, d.nrhs - r0), st);
 }

@@ -704,7 +704,14 @@ size_t zinv_workspace_bytes(int n, int batch, bool c64) {
 void zinv(int n, int batch, const double* A, long lda, long sA, double* Out, long ldo,
           long sO, int* info, void* work, hipStream_t st, bool c64, bool full_pivoting) {
   if (n <= 0 || batch <= 0) return;
-  if (batch > 65535) throw Error(1, "zinv: batch exceeds grid limit");
+  if (batch > 65535) {
+    // consecutive slices within the grid's limits; each reuses the workspace
+    const long e = c64 ? 1 : 2;  // doubles per complex entry
+    for (long b0 = 0; b0 < batch; b0 += 65535)
+      zinv(n, (int)std::min<long>(65535, batch - b0), A + b0 * sA * e, lda, sA,
+           Out + b0 * sO * e, ldo, sO, info + b0, work, st, c64, full_pivoting);
+    return;
+  }
   if (n > SMALL_MAX && !full_pivoting) {
     if (A != Out || lda != ldo || sA != sO)
       throw Error(1, "zinv: the block-pivot form works in place");

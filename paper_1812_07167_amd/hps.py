@@ -76,7 +76,8 @@ class FactorInfo(C.Structure):
 
 class ServerOpts(C.Structure):
     _fields_ = [("slots", C.c_int32), ("max_batch_rhs", C.c_int32),
-                ("max_pending_builds", C.c_int32), ("evict_idle", C.c_int32)]
+                ("max_pending_builds", C.c_int32), ("evict_idle", C.c_int32),
+                ("solve_slots", C.c_int32), ("share_problems", C.c_int32)]
 
 
 class Completion(C.Structure):
@@ -94,7 +95,8 @@ class Stats(C.Structure):
                 ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("max_ms", C.c_double),
                 ("wall_s", C.c_double), ("rhs_per_s", C.c_double), ("solves_per_s", C.c_double),
                 ("budget_bytes", C.c_int64), ("committed_bytes", C.c_int64),
-                ("peak_committed_bytes", C.c_int64)]
+                ("peak_committed_bytes", C.c_int64), ("shared_batches", C.c_int64),
+                ("shared_problems", C.c_int64)]
 
 
 _lib = None
@@ -507,7 +509,7 @@ class Server:
     solve() are kept referenced here until their completion has been polled."""
 
     def __init__(self, budget_bytes=0, slots=None, max_batch_rhs=None, max_pending_builds=None,
-                 evict_idle=None):
+                 evict_idle=None, solve_slots=None, share_problems=None):
         lib = load()
         o = ServerOpts()
         lib.hps_server_default_opts(C.byref(o))
@@ -519,6 +521,10 @@ class Server:
             o.max_pending_builds = int(max_pending_builds)
         if evict_idle is not None:
             o.evict_idle = int(evict_idle)
+        if solve_slots is not None:
+            o.solve_slots = int(solve_slots)
+        if share_problems is not None:
+            o.share_problems = int(share_problems)
         h = C.c_void_p()
         _check(lib.hps_server_create(int(budget_bytes), C.byref(o), C.byref(h)))
         self.h = h

@@ -171,3 +171,94 @@ def test_config3_strata_match_oracle(side, precision):
         assert rel(u.cpu().numpy(), uo) < TOL, (q["seed"], q["p"])
     for f in fs:
         f.free()
+
+
+# ------------------------------------------- problems of different groups share launches
+
+
+def test_solve_batch_shares_launches_across_groups():
+    """Separately built factors of one shape (and two problems of one batch-built group of
+    that shape) solved in one call: uneven nrhs (1..33, so some problems skip 16-column
+    passes that others run), s = NULL for some, one problem of another shape in the same
+    call.  Each result against the same problem solved alone (1e-12) and, for three of
+    them, against the oracle (1e-10)."""
+    import torch
+    from paper_1812_07167_amd import hps as H
+    nr = [1, 17, 3, 33, 2, 5, 16]
+    cases = [Case(8, 4, 10, 20.0 + 6 * i, eta=(15.0 + 4 * i) + 1j * i, seed=60 + i, nrhs=nr[i])
+             for i in range(7)]
+    odd = Case(4, 4, 8, 25.0, seed=70, nrhs=2)
+    singles = [c.gpu_build() for c in cases[:5]]
+    grouped = _batch_build(cases[5:])
+    fo = odd.gpu_build()
+    fs = singles + grouped + [fo]
+    allc = cases + [odd]
+    ss = [None if i in (2, 5) else _dev(c.s) for i, c in enumerate(allc)]
+    us = H.hps_solve_batch(fs, [_dev(c.t) for c in allc], ss)
+    torch.cuda.synchronize()
+    for i, (c, f, u) in enumerate(zip(allc, fs, us)):
+        s_i = None if ss[i] is None else c.s
+        ua = c.gpu_solve(f, s=s_i)
+        assert rel(u.cpu().numpy(), ua) < SAME, i
+        if i in (0, 3, 5):
+            uo = c.oracle_solve(c.oracle_build(), s=s_i)
+            assert rel(u.cpu().numpy(), uo) < TOL, i
+    for f in fs:
+        f.free()
+
+
+def test_solve_batch_more_problems_than_one_shared_solve_takes():
+    """18 separately built problems of one shape: two shared solves (16 + 2)."""
+    import torch
+    from paper_1812_07167_amd import hps as H
+    cases = [Case(4, 4, 8, 10.0 + 2 * i, seed=80 + i, nrhs=1 + i % 3) for i in range(18)]
+    fs = [c.gpu_build() for c in cases]
+    us = H.hps_solve_batch(fs, [_dev(c.t) for c in cases], [_dev(c.s) for c in cases])
+    torch.cuda.synchronize()
+    for i in (0, 7, 15, 16, 17):
+        assert rel(us[i].cpu().numpy(), cases[i].gpu_solve(fs[i])) < SAME, i
+    for f in fs:
+        f.free()
+
+
+def test_batch_beyond_the_grid_y_limit():
+    """130 problems of 32 x 32 leaves, p = 4, in one group: 66560 merges on the level
+    above the leaves and 133120 leaves, more than one launch's grid y extent (65535), so
+    the merge, inversion, GEMM, gather and solve launches take slices.  Sampled problems
+    against the same problems built alone (1e-12) and one against the oracle."""
+    import torch
+    from paper_1812_07167_amd import hps as H
+    cases = [Case(32, 32, 4, 3.0 + 0.05 * i, seed=200 + i, nrhs=1) for i in range(130)]
+    print("grid-y batch: 130 problems 32x32 p=4", flush=True)
+    fs = _batch_build(cases)
+    us = H.hps_solve_batch(fs, [_dev(c.t) for c in cases], [_dev(c.s) for c in cases])
+    torch.cuda.synchronize()
+    for i in (0, 64, 129):
+        f1 = cases[i].gpu_build()
+        assert rel(us[i].cpu().numpy(), cases[i].gpu_solve(f1)) < SAME, i
+        f1.free()
+    uo = cases[129].oracle_solve(cases[129].oracle_build())
+    assert rel(us[129].cpu().numpy(), uo) < TOL
+    for f in fs:
+        f.free()
+
+
+def test_mixed_refinement_judges_each_problem_on_its_own_scale():
+    """Two problems of one batch-built mixed-precision group, the second (a harder kappa)
+    with data scaled by 1e-6: its corrections are measured against its own solution, not
+    the first's, so both end at complex128 accuracy (1e-10 against complex128 builds)."""
+    import torch
+    from paper_1812_07167_amd import hps as H
+    a = Case(8, 8, 12, 20.0, seed=90, nrhs=2)
+    b = Case(8, 8, 12, 120.0, seed=91, nrhs=2)
+    b.s = b.s * 1e-6
+    b.t = b.t * 1e-6
+    fs = _batch_build([a, b], precision=H.HPS_PREC_MIXED)
+    us = H.hps_solve_batch(fs, [_dev(a.t), _dev(b.t)], [_dev(a.s), _dev(b.s)])
+    torch.cuda.synchronize()
+    for c, u in zip((a, b), us):
+        f1 = c.gpu_build()
+        assert rel(u.cpu().numpy(), c.gpu_solve(f1)) < TOL
+        f1.free()
+    for f in fs:
+        f.free()

@@ -185,3 +185,67 @@ def test_rejection_release_and_unknown_problems():
         assert e.value.code == H.HPS_E_INVALID
     finally:
         srv.close()
+
+
+def test_solves_of_several_problems_share_one_solve():
+    """Requests queued on four resident problems of one shape (while a larger build holds
+    the only slot) are served by shared solves (one launch per level step over the
+    problems); each result equals the request solved alone (1e-12), and sampled ones
+    match the oracle (1e-10)."""
+    import torch
+    from paper_1812_07167_amd import hps as H
+    cases = [Case(8, 8, 10, 25.0 + 7 * k, seed=120 + k, nrhs=3) for k in range(4)]
+    big = Case(32, 32, 12, 50.0, seed=9, nrhs=1)
+    reqs = _requests(cases, 40, seed=11)
+    dev = [(_dev(t), None if s is None else _dev(s)) for _, t, s in reqs]
+    torch.cuda.synchronize()
+    srv = H.Server(slots=1, max_batch_rhs=8)
+    try:
+        built = [_submit_build(srv, c) for c in cases]
+        pids = [pid for pid, _ in built]
+        srv.wait([req for _, req in built])
+        _submit_build(srv, big)
+        ids, us = [], []
+        for (j, _, _), (td, sd) in zip(reqs, dev):
+            r, u = srv.solve(pids[j], td, sd, sync=False)
+            ids.append(r)
+            us.append(u)
+        done = srv.wait(ids)
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert all(done[r]["status"] == 0 for r in ids)
+    assert st["shared_batches"] >= 1, st
+    assert st["shared_problems"] >= 2 * st["shared_batches"]
+    fs = [c.gpu_build() for c in cases]
+    for q, ((j, t, s), u) in enumerate(zip(reqs, us)):
+        assert rel(u.cpu().numpy(), _alone(cases[j], fs[j], t, s)) < SAME, q
+    from oracle import hps_oracle as O
+    obs = {}
+    for q in range(0, len(reqs), 7):
+        j, t, s = reqs[q]
+        if j not in obs:
+            obs[j] = cases[j].oracle_build()
+        assert rel(us[q].cpu().numpy(), O.solve(cases[j].prob, obs[j], s, t)) < TOL, q
+    for f in fs:
+        f.free()
+
+
+def test_solve_slot_is_never_taken_by_a_build():
+    """With two slots, one for solves only: a solve submitted just after a long build
+    finishes before that build does."""
+    from paper_1812_07167_amd import hps as H
+    small = Case(4, 4, 8, 20.0, seed=130, nrhs=1)
+    big = Case(64, 64, 16, 100.0, c="bump", seed=131, nrhs=1)
+    srv = H.Server(slots=2, solve_slots=1)
+    try:
+        pid, breq = _submit_build(srv, small)
+        srv.wait([breq])
+        _, big_req = _submit_build(srv, big)
+        r, u = srv.solve(pid, _dev(small.t), _dev(small.s), sync=False)
+        done = srv.wait([r, big_req], timeout_s=300)
+    finally:
+        srv.close()
+    assert done[r]["status"] == 0 and done[big_req]["status"] == 0
+    assert done[r]["t_end"] < done[big_req]["t_end"], (done[r], done[big_req])
+    assert rel(u.cpu().numpy(), small.oracle_solve(small.oracle_build())) < TOL
