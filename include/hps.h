@@ -379,8 +379,9 @@ int hps_estimate_bytes(const hps_domain* dom, int32_t p, const hps_opts* opts,
  *     workspace and staging) fit under the budget beside what is already committed
  *     (resident factors, running items).  If it does not fit, factors of idle problems
  *     (no queued or running request) are freed, least recently used first (when
- *     evict_idle is set); an evicted problem is rebuilt from the server's copy of its
- *     data when its next solve request comes up.
+ *     evict_idle is set; a solve evicts only while no other solve runs, otherwise it
+ *     waits for their memory to come back); an evicted problem is rebuilt from the
+ *     server's copy of its data when its next solve request comes up.
  *   - Continuous batching: when a slot takes a problem's solve, it merges every queued
  *     request of that problem (up to max_batch_rhs right-hand sides) into one solve.
  *     With share_problems set, the same solve also takes the queued requests of other

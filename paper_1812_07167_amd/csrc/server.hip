@@ -11,7 +11,8 @@
 // solve_slots slots take no builds.  At most one item per problem runs at a time.  An
 // item is admissible when the bytes it needs fit beside the committed bytes (server
 // copies of c, resident factors, running items); otherwise idle factors are freed least
-// recently used first, when that makes it fit.  When nothing runs and the oldest item
+// recently used first, when that makes it fit (for a solve, only while no other solve
+// runs: a running solve's memory comes back soon).  When nothing runs and the oldest item
 // still cannot fit, it fails with HPS_E_NOMEM.
 #include <hip/hip_runtime.h>
 
@@ -118,6 +119,7 @@ struct hps_server {
   uint64_t next_id = 1, lru_clock = 0;
   hps::Clock::time_point t0;
   int running = 0, max_running = 0;
+  int running_solves = 0;
   int64_t builds = 0, rebuilds = 0, evictions = 0, solves = 0, rhs = 0, batches = 0;
   int64_t rejected = 0, failed = 0, shared_batches = 0, shared_problems = 0;
   int solve_only = 0;  // slots [0, solve_only) take no builds
@@ -286,16 +288,19 @@ bool pick(hps_server& S, Work& w, std::vector<Freed>& fr, bool builds) {
       w.rebuild = p.state == PState::Evicted;
       p.state = PState::Building;
     } else {
+      // A solve's memory returns when it ends, a factor's only with a rebuild: while
+      // another solve runs, a solve that does not fit waits for it instead of evicting.
+      const bool may_evict = S.running_solves == 0;
+      auto admit = [&](size_t b) { return may_evict ? evict_for(S, b, &p, fr) : fits(S, b); };
       size_t k = batch_len(p, S.opts.max_batch_rhs);
       int R = 0;
       bool any_s = false;
       size_t need = solve_need(p, k, &R, &any_s);
-      if (!evict_for(S, need, &p, fr) && k > 1) {
+      if (!admit(need)) {
+        if (k == 1) continue;
         k = 1;
         need = solve_need(p, k, &R, &any_s);
-        if (!evict_for(S, need, &p, fr)) continue;
-      } else if (!fits(S, need)) {
-        continue;
+        if (!admit(need)) continue;
       }
       w.kind = Work::Solve;
       w.pr = &p;
@@ -328,8 +333,9 @@ bool pick(hps_server& S, Work& w, std::vector<Freed>& fr, bool builds) {
             x.reqs.assign(q->pending.begin(), q->pending.begin() + (long)kq);
             sh.push_back(std::move(x));
           }
+          // riding along is opportunistic: it never evicts a factor
           const size_t need2 = shared_need(sh);
-          if (evict_for(S, need2, &p, fr)) {
+          if (fits(S, need2)) {
             w.shares = std::move(sh);
             w.mem = need2;
             for (size_t i = 1; i < w.shares.size(); ++i) {
@@ -354,6 +360,7 @@ bool pick(hps_server& S, Work& w, std::vector<Freed>& fr, bool builds) {
     S.committed += w.mem;
     S.peak_committed = std::max(S.peak_committed, S.committed);
     ++S.running;
+    if (w.kind == Work::Solve) ++S.running_solves;
     S.max_running = std::max(S.max_running, S.running);
     return true;
   }
@@ -487,6 +494,7 @@ void slot_main(hps_server* S, int slot) {
       Problem& p = *w.pr;
       S->committed -= w.mem;
       --S->running;
+      if (w.kind == Work::Solve) --S->running_solves;
       p.busy = false;
       p.last_use = ++S->lru_clock;
       for (size_t i = 1; i < w.shares.size(); ++i) {

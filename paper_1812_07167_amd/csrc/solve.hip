@@ -1,16 +1,17 @@
 // Solve-stage operator application (Algorithm 2): out = alpha * A X + addend for a
 // batch of stored operators A (M x K, complex) and a block of nrhs right-hand sides.
 //
-// This is HBM-bound: every operator entry is read once per call and used for all (up to
-// 16) right-hand sides of a pass.  The product runs on the FP64 matrix cores: a wave
-// owns TW tiles of 16 rows, the 16 right-hand sides are the 16 columns of the MFMA's B
-// operand.  The right-hand side block is staged through LDS in chunks of KC rows (each
-// lane reads one complex value per 4-deep k step, so there are no broadcast reads);
-// operator entries go from global memory straight into the A operand registers.  A
+// This is HBM-bound: every operator entry is read once per pass and used for all (up to
+// 64) right-hand sides of the pass.  The product runs on the FP64 matrix cores: a wave
+// owns TW tiles of 16 rows, and each group of 16 right-hand sides is the 16 columns of
+// one MFMA's B operand; NB such groups (NB = 1, 2 or 4) share every operator load.  The
+// right-hand side block is staged through LDS in chunks of KC rows (each lane reads one
+// complex value per 4-deep k step, so there are no broadcast reads); operator entries
+// go from global memory straight into the A operand registers.  A
 // complex product takes three real MFMAs (the 3M method: ArXr, AiXi and
 // (Ar + Ai)(Xr + Xi), folded into the real and imaginary parts after the K loop).  A
-// workgroup covers at most 128 rows (TW <= 2); registers then allow at least four waves
-// per SIMD.  For
+// workgroup covers at most 128 rows (TW <= 2, and TW = 1 when NB > 1); registers then
+// allow at least four waves per SIMD.  For
 // short operators the waves of a workgroup split K and add their partial tiles through
 // LDS in a fixed order.
 // Operators with few rows and a long K (the top merges) are also split along K across
@@ -44,8 +45,12 @@ template <> struct SkMfma<float> {
   static __device__ inline int row(int lk, int v) { return 4 * lk + v; }
 };
 
-constexpr int KC = 64;   // K chunk staged in LDS
-constexpr int NRB = 16;  // right-hand sides per pass (the MFMA's N)
+constexpr int KC = 64;   // K granularity of the split-K plan
+constexpr int NRB = 16;  // right-hand sides of one MFMA column block (the MFMA's N)
+constexpr int MAXNB = 4; // column blocks per pass at most: 64 right-hand sides
+
+// column blocks of a pass over nr right-hand sides
+inline int nb_of(int nr) { return nr > 2 * NRB ? 4 : nr > NRB ? 2 : 1; }
 
 // a second operator is applied in the same launch
 __host__ __device__ inline bool has2(const SkinnyDesc& d) {
@@ -54,7 +59,7 @@ __host__ __device__ inline bool has2(const SkinnyDesc& d) {
 // batch entries of a launch: the second operator's follow the first's
 __host__ __device__ inline int nbatch(const SkinnyDesc& d) { return has2(d) ? 2 * d.batch : d.batch; }
 
-template <class T, int TW, int WK>
+template <class T, int TW, int WK, int NB>
 __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int nr, int kper,
                                                      double2* partial, long y0) {
   typedef typename Cx<T>::t C2;
@@ -62,8 +67,14 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
   typedef typename MF::acc acc_t;
   constexpr int WR = 4 / WK;              // row groups of waves
   constexpr int ROWS = 16 * TW * WR;      // rows per workgroup
-  __shared__ C2 Xs[KC][NRB];
-  __shared__ acc_t red[WK > 1 ? (WK - 1) * WR * TW * 2 * 64 : 1];
+  constexpr int NC = NRB * NB;            // right-hand sides of the pass
+  constexpr int KCX = NB == 4 ? 32 : 64;  // K chunk staged in LDS
+  constexpr int XS_BYTES = KCX * NC * (int)sizeof(C2);
+  constexpr int RED_BYTES = WK > 1 ? (WK - 1) * WR * TW * 2 * NB * 64 * (int)sizeof(acc_t) : 0;
+  // the staged right-hand sides, and after the K loop the cross-wave partial tiles
+  __shared__ __align__(16) char smem[XS_BYTES > RED_BYTES ? XS_BYTES : RED_BYTES];
+  C2 (*Xs)[NC] = reinterpret_cast<C2 (*)[NC]>(smem);
+  acc_t* red = reinterpret_cast<acc_t*>(smem);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave % WR, kw = wave / WR;
@@ -94,79 +105,101 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
   for (int t = 0; t < TW; ++t) arow[t] = min(row0 + 16 * t + li, d.M - 1);
 
   // 3M: accR, accX, accI hold ArXr, AiXi, (Ar + Ai)(Xr + Xi) until after the K loop
-  acc_t accR[TW], accI[TW], accX[TW];
+  acc_t accR[TW][NB], accI[TW][NB], accX[TW][NB];
 #pragma unroll
-  for (int t = 0; t < TW; ++t) {
-    accR[t] = acc_t{0, 0, 0, 0};
-    accI[t] = acc_t{0, 0, 0, 0};
-    accX[t] = acc_t{0, 0, 0, 0};
-  }
-  for (int k0 = kbeg; k0 < kend; k0 += KC) {
-    const int kc = min(KC, kend - k0);
+  for (int t = 0; t < TW; ++t)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      accR[t][j] = acc_t{0, 0, 0, 0};
+      accI[t][j] = acc_t{0, 0, 0, 0};
+      accX[t][j] = acc_t{0, 0, 0, 0};
+    }
+  for (int k0 = kbeg; k0 < kend; k0 += KCX) {
+    const int kc = min(KCX, kend - k0);
     __syncthreads();
-    for (int e = tid; e < KC * NRB; e += 256) {
-      const int k = e % KC, r = e / KC;
+    for (int e = tid; e < KCX * NC; e += 256) {
+      const int k = e % KCX, r = e / KCX;
       const double2 xv = (k < kc && r < nr) ? X[(k0 + k) + d.ldx * (long)(r0 + r)] : cmk(0, 0);
       Xs[k][r] = Cx<T>::mk((T)xv.x, (T)xv.y);
     }
     __syncthreads();
     const int nsteps = (kc + 3) >> 2;
-#pragma unroll 4
+#pragma unroll 2
     for (int s = kw; s < nsteps; s += WK) {
       const int kl = 4 * s + lk;
       // k past the chunk meets a zero right-hand side; clamp its address into A
       const long kg = min(k0 + kl, d.K - 1);
-      const C2 bx = Xs[kl][li];
-      const T bs = bx.x + bx.y;
+      C2 bx[NB];
+      T bs[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        bx[j] = Xs[kl][NRB * j + li];
+        bs[j] = bx[j].x + bx[j].y;
+      }
 #pragma unroll
       for (int t = 0; t < TW; ++t) {
         const C2 a = A[arow[t] + d.lda * kg];
-        accR[t] = MF::op(a.x, bx.x, accR[t]);
-        accX[t] = MF::op(a.y, bx.y, accX[t]);
-        accI[t] = MF::op(a.x + a.y, bs, accI[t]);
+        const T as = a.x + a.y;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          accR[t][j] = MF::op(a.x, bx[j].x, accR[t][j]);
+          accX[t][j] = MF::op(a.y, bx[j].y, accX[t][j]);
+          accI[t][j] = MF::op(as, bs[j], accI[t][j]);
+        }
       }
     }
   }
 #pragma unroll
   for (int t = 0; t < TW; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const T t1 = accR[t][v], t2 = accX[t][v];
-      accR[t][v] = t1 - t2;
-      accI[t][v] = accI[t][v] - t1 - t2;
-    }
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const T t1 = accR[t][j][v], t2 = accX[t][j][v];
+        accR[t][j][v] = t1 - t2;
+        accI[t][j][v] = accI[t][j][v] - t1 - t2;
+      }
   if (WK > 1) {
-    // waves kw > 0 hand their tiles to the kw = 0 wave of their row group
+    // waves kw > 0 hand their tiles to the kw = 0 wave of their row group (through the
+    // LDS the staged right-hand sides used: every wave is past its last read of them)
+    __syncthreads();
     if (kw > 0) {
 #pragma unroll
-      for (int t = 0; t < TW; ++t) {
-        const int base = (((kw - 1) * WR + wr) * TW + t) * 2;
-        red[(base + 0) * 64 + lane] = accR[t];
-        red[(base + 1) * 64 + lane] = accI[t];
-      }
+      for (int t = 0; t < TW; ++t)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const int base = ((((kw - 1) * WR + wr) * TW + t) * NB + j) * 2;
+          red[(base + 0) * 64 + lane] = accR[t][j];
+          red[(base + 1) * 64 + lane] = accI[t][j];
+        }
     }
     __syncthreads();
     if (kw > 0) return;
     for (int q = 1; q < WK; ++q)
 #pragma unroll
-      for (int t = 0; t < TW; ++t) {
-        const int base = (((q - 1) * WR + wr) * TW + t) * 2;
-        accR[t] += red[(base + 0) * 64 + lane];
-        accI[t] += red[(base + 1) * 64 + lane];
-      }
+      for (int t = 0; t < TW; ++t)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const int base = ((((q - 1) * WR + wr) * TW + t) * NB + j) * 2;
+          accR[t][j] += red[(base + 0) * 64 + lane];
+          accI[t][j] += red[(base + 1) * 64 + lane];
+        }
   }
-  const int rhs = li;
-  if (rhs >= nr) return;
   if (partial) {
-    // [ks][bb][rhs][i]
-    double2* P = partial + (((long)ks * nbatch(d) + bb) * NRB + rhs) * d.M;
+    // [ks][bb][rhs of the pass][i]
 #pragma unroll
-    for (int t = 0; t < TW; ++t)
+    for (int j = 0; j < NB; ++j) {
+      const int rhs = NRB * j + li;
+      if (rhs >= nr) continue;
+      double2* P = partial + (((long)ks * nbatch(d) + bb) * NC + rhs) * d.M;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = row0 + 16 * t + MF::row(lk, v);
-        if (i < d.M) P[i] = cmk(accR[t][v], accI[t][v]);
-      }
+      for (int t = 0; t < TW; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = row0 + 16 * t + MF::row(lk, v);
+          if (i < d.M) P[i] = cmk(accR[t][j][v], accI[t][j][v]);
+        }
+    }
     return;
   }
   double2* C = reinterpret_cast<double2*>(two ? d.C2 : d.C) +
@@ -176,21 +209,26 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
       c0p ? reinterpret_cast<const double2*>(c0p) + (d.c0off ? d.c0off[b] : b * d.s0) : nullptr;
   const int* crow = two ? d.crow2 : d.crow;
 #pragma unroll
-  for (int t = 0; t < TW; ++t)
+  for (int j = 0; j < NB; ++j) {
+    const int rhs = NRB * j + li;
+    if (rhs >= nr) continue;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = row0 + 16 * t + MF::row(lk, v);
-      if (i >= d.M) continue;
-      const long ci = crow ? crow[i] : i;
-      double2 val = cmk(d.alpha * accR[t][v], d.alpha * accI[t][v]);
-      double2* p = C + ci + d.ldc * (long)(r0 + rhs);
-      if (C0) val = cadd(val, C0[i + d.ld0 * (long)(r0 + rhs)]);
-      else if (d.accumulate) val = cadd(val, *p);
-      *p = val;
-    }
+    for (int t = 0; t < TW; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = row0 + 16 * t + MF::row(lk, v);
+        if (i >= d.M) continue;
+        const long ci = crow ? crow[i] : i;
+        double2 val = cmk(d.alpha * accR[t][j][v], d.alpha * accI[t][j][v]);
+        double2* p = C + ci + d.ldc * (long)(r0 + rhs);
+        if (C0) val = cadd(val, C0[i + d.ld0 * (long)(r0 + rhs)]);
+        else if (d.accumulate) val = cadd(val, *p);
+        *p = val;
+      }
+  }
 }
 
-__global__ void skinny_reduce_kernel(SkinnyDesc d, int r0, int nr, int nsplit,
+__global__ void skinny_reduce_kernel(SkinnyDesc d, int r0, int nr, int nc, int nsplit,
                                      const double2* partial) {
   const int nbt = nbatch(d);
   const long tot = (long)nbt * d.M * nr;
@@ -207,7 +245,7 @@ __global__ void skinny_reduce_kernel(SkinnyDesc d, int r0, int nr, int nsplit,
     }
     double2 acc = cmk(0, 0);
     for (int s = 0; s < nsplit; ++s)
-      acc = cadd(acc, partial[(((long)s * nbt + bb) * NRB + r) * d.M + i]);
+      acc = cadd(acc, partial[(((long)s * nbt + bb) * nc + r) * d.M + i]);
     double2* C = reinterpret_cast<double2*>(two ? d.C2 : d.C) +
                  (d.coff ? d.coff[b] - d.cbase : b * d.sC);
     const int* crow = two ? d.crow2 : d.crow;
@@ -228,17 +266,18 @@ __global__ void skinny_reduce_kernel(SkinnyDesc d, int r0, int nr, int nsplit,
 
 // rows covered by one workgroup: by the operator's height, and for few tall operators
 // (the top merge levels) at most 64, so that the row blocks (times the K splits below)
-// spread the matrix-core work over the device instead of a few compute units
-int block_rows(const SkinnyDesc& d) {
+// spread the matrix-core work over the device instead of a few compute units; at most
+// 64 when a pass has several column blocks (TW = 1)
+int block_rows(const SkinnyDesc& d, int nb) {
   int rows = d.M <= 16 ? 16 : d.M <= 32 ? 32 : d.M <= 64 ? 64 : 128;
-  while (rows > 64 && (long)cdiv(d.M, rows) * nbatch(d) < 512) rows /= 2;
+  while (rows > 64 && (nb > 1 || (long)cdiv(d.M, rows) * nbatch(d) < 512)) rows /= 2;
   return rows;
 }
 
 // K is split across workgroups when the row blocks x batch cannot fill the device.
-// Returns the number of splits and the K range per split.
-int split_plan(const SkinnyDesc& d, int* kper_out) {
-  const int tiles = cdiv(d.M, block_rows(d));
+// Returns the number of splits and the K range per split (a multiple of KC).
+int split_plan(const SkinnyDesc& d, int nb, int* kper_out) {
+  const int tiles = cdiv(d.M, block_rows(d, nb));
   int nsplit = 1;
   const long blocks = (long)tiles * nbatch(d);
   if (blocks < 1024 && d.K >= 2 * KC) {
@@ -258,16 +297,17 @@ int split_plan(const SkinnyDesc& d, int* kper_out) {
 // launches of batches beyond the grid's y limit take consecutive slices of it
 constexpr long kGridY = 65535;
 
-template <class T, int TW, int WK>
+template <class T, int TW, int WK, int NB>
 void run_chunk(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
   const int tiles = cdiv(d.M, 16 * TW * (4 / WK));
   int kper = 0;
-  const int nsplit = split_plan(d, &kper);
+  const int nsplit = split_plan(d, NB, &kper);
   const long nbt = nbatch(d);
   if (nsplit == 1) {
     for (long y0 = 0; y0 < nbt; y0 += kGridY) {
-      hipLaunchKernelGGL((skinny_kernel<T, TW, WK>), dim3(tiles, std::min(kGridY, nbt - y0), 1),
-                         dim3(256), 0, st, d, r0, nr, d.K, (double2*)nullptr, y0);
+      hipLaunchKernelGGL((skinny_kernel<T, TW, WK, NB>),
+                         dim3(tiles, std::min(kGridY, nbt - y0), 1), dim3(256), 0, st, d, r0,
+                         nr, d.K, (double2*)nullptr, y0);
       HPS_LAUNCH_CHECK();
     }
     return;
@@ -275,24 +315,33 @@ void run_chunk(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
   if (!d.work) throw Error(1, "zgemm_skinny: split-K needs a workspace");
   double2* part = static_cast<double2*>(d.work);
   for (long y0 = 0; y0 < nbt; y0 += kGridY) {
-    hipLaunchKernelGGL((skinny_kernel<T, TW, WK>),
+    hipLaunchKernelGGL((skinny_kernel<T, TW, WK, NB>),
                        dim3(tiles, std::min(kGridY, nbt - y0), nsplit), dim3(256), 0, st, d, r0,
                        nr, kper, part, y0);
     HPS_LAUNCH_CHECK();
   }
   long tot = (long)nbatch(d) * d.M * nr;
   hipLaunchKernelGGL(skinny_reduce_kernel, dim3(grid1d(tot)), dim3(256), 0, st, d, r0, nr,
-                     nsplit, (const double2*)part);
+                     NRB * NB, nsplit, (const double2*)part);
   HPS_LAUNCH_CHECK();
+}
+
+template <class T, int NB>
+void run_pass_nb(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
+  switch (block_rows(d, NB)) {
+    case 16: run_chunk<T, 1, 4, NB>(d, r0, nr, st); break;
+    case 32: run_chunk<T, 1, 2, NB>(d, r0, nr, st); break;
+    case 64: run_chunk<T, 1, 1, NB>(d, r0, nr, st); break;
+    default: run_chunk<T, NB == 1 ? 2 : 1, 1, NB>(d, r0, nr, st); break;
+  }
 }
 
 template <class T>
 void run_pass_t(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
-  switch (block_rows(d)) {
-    case 16: run_chunk<T, 1, 4>(d, r0, nr, st); break;
-    case 32: run_chunk<T, 1, 2>(d, r0, nr, st); break;
-    case 64: run_chunk<T, 1, 1>(d, r0, nr, st); break;
-    default: run_chunk<T, 2, 1>(d, r0, nr, st); break;
+  switch (nb_of(nr)) {
+    case 1: run_pass_nb<T, 1>(d, r0, nr, st); break;
+    case 2: run_pass_nb<T, 2>(d, r0, nr, st); break;
+    default: run_pass_nb<T, 4>(d, r0, nr, st); break;
   }
 }
 
@@ -301,14 +350,23 @@ void run_pass(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
   else run_pass_t<double>(d, r0, nr, st);
 }
 
+// bytes of the split-K partial sums of a pass over nr right-hand sides
+size_t pass_work_bytes(const SkinnyDesc& d, int nr) {
+  const int nb = nb_of(nr);
+  int kper = 0;
+  const int nsplit = split_plan(d, nb, &kper);
+  if (nsplit == 1) return 0;
+  return (size_t)nsplit * nbatch(d) * NRB * nb * d.M * sizeof(double2);
+}
+
 }  // namespace
 
 size_t skinny_work_bytes(const SkinnyDesc& d) {
-  if (d.M <= 0 || d.batch <= 0 || d.K <= 0) return 0;
-  int kper = 0;
-  const int nsplit = split_plan(d, &kper);
-  if (nsplit == 1) return 0;
-  return (size_t)nsplit * nbatch(d) * NRB * d.M * sizeof(double2);
+  if (d.M <= 0 || d.batch <= 0 || d.K <= 0 || d.nrhs <= 0) return 0;
+  constexpr int NCMAX = NRB * MAXNB;
+  size_t b = pass_work_bytes(d, std::min(d.nrhs, NCMAX));
+  if (d.nrhs > NCMAX && d.nrhs % NCMAX) b = std::max(b, pass_work_bytes(d, d.nrhs % NCMAX));
+  return b;
 }
 
 void zgemm_skinny(const SkinnyDesc& d, hipStream_t st) {
@@ -323,7 +381,9 @@ void zgemm_skinny(const SkinnyDesc& d, hipStream_t st) {
         throw Error(1, "zgemm_skinny: missing operator of a tabled factor");
   }
   if (d.K <= 0) throw Error(1, "zgemm_skinny: K must be positive");
-  for (int r0 = 0; r0 < d.nrhs; r0 += NRB) run_pass(d, r0, std::min(NRB, d.nrhs - r0), st);
+  // passes of up to 64 right-hand sides; the last takes the rest
+  constexpr int NCMAX = NRB * MAXNB;
+  for (int r0 = 0; r0 < d.nrhs; r0 += NCMAX) run_pass(d, r0, std::min(NCMAX, d.nrhs - r0), st);
 }
 
 }  // namespace hps

@@ -311,13 +311,15 @@ def test_config2_sampled_leaves(config2):
         assert rel(f.get(H.OP_Y, L, int(h)), o["Y"]) < TOL
 
 
+@pytest.mark.parametrize("nrhs", [1, 16, 20, 37, 64, 70, 131])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_many_right_hand_sides_in_ragged_passes(precision):
-    """37 right-hand sides: the solve products take them in passes of 16, 16 and 5 (the
-    paired launches of both sweeps included), with and without a body load, against the
-    oracle."""
-    _say("37 RHS, precision", precision)
-    cs = Case(8, 8, 10, 30.0, seed=21, nrhs=37)
+def test_many_right_hand_sides_in_ragged_passes(precision, nrhs):
+    """The solve products take up to 64 right-hand sides per pass, in one, two or four
+    16-column blocks (1, 16: one block; 20: two; 37, 64: four; 70 = 64 + 6 and
+    131 = 64 + 64 + 3: several passes with a ragged tail), the paired launches of both
+    sweeps included, with and without a body load, against the oracle."""
+    _say(nrhs, "RHS, precision", precision)
+    cs = Case(8, 8, 10, 30.0, seed=21, nrhs=nrhs)
     f = cs.gpu_build(precision=precision)
     boxes = cs.oracle_build()
     assert rel(cs.gpu_solve(f), cs.oracle_solve(boxes)) < TOL
