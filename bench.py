@@ -300,7 +300,12 @@ def batch_leg(H, torch, dev, stream, count=256, seed0=0, reps=2):
                                device=dev))
         exact.append(mf.u(xy))
         dof += q["nx"] * q["ny"] * (q["p"] ** 2 - 4)
-    res = {"problems": count, "dof": dof, "shape_groups": len(nodes)}
+    # one factorization group per shape; the groups' launch chains run side by side on
+    # up to four streams of the library
+    res = {"problems": count, "dof": dof, "shape_groups": len(nodes),
+           "launch_chains_per_merge_level": len(nodes), "groups_built_at_once": min(4, len(nodes)),
+           "max_rel_l2_vs_exact_note": "discretization error of the worst drawn problem "
+                                       "(kappa up to 80 on 8x8 leaves of p = 8, under-resolved)"}
 
     def run(precision):
         bt, st_ = [], []
@@ -348,13 +353,20 @@ def batch_leg(H, torch, dev, stream, count=256, seed0=0, reps=2):
     return res
 
 
-def serve_leg(H, torch, dev, n_problems=32, n_requests=1000, load=0.7, slots=4, seed=0,
-              max_rhs=64, new_build_every=250, reserve_gb=48.0, checks=4):
+def serve_leg(H, torch, dev, n_problems=32, n_requests=10000, load=0.7, slots=4,
+              solve_slots=1, seed=0, max_rhs=64, new_build_every=500, reserve_gb=48.0,
+              checks=64, headroom_gb=24.0, probe_requests=1000, window=64):
     """Serving: `n_problems` seeded problems (leaf grids 32^2..128^2, p 12-16, kappa
-    50-300, Fourier c; complex128) built through the request loop, then a Poisson stream
-    of `n_requests` solve requests of 1..max_rhs right-hand sides each (smooth random s,
-    plane-wave t), one new build every `new_build_every` requests, at `load` times the
-    capacity measured on the resident problems.  Latency is submission to completion."""
+    50-300, Fourier c; complex128) built through the request loop under a device-memory
+    budget of their resident bytes, plus the largest build's scratch, plus `headroom_gb`
+    (less than concurrent solves' workspaces and new problems need at peaks, so that
+    factors are evicted and rebuilt), then a Poisson stream of `n_requests` solve requests of 1..max_rhs
+    right-hand sides each (smooth random s, plane-wave t) at `load` times the closed-loop
+    saturated throughput of all slots, measured first under the same budget with
+    `window` requests kept outstanding.  Every `new_build_every` requests a new problem
+    is built and a live one of the same leaf grid released.  Latency is submission to completion.  `checks`
+    seeded requests of the stream are re-solved alone on factors built outside the
+    server and compared."""
     from paper_1812_07167_amd import inputs as G
     n_new = n_requests // new_build_every if new_build_every else 0
     probs = G.serve_problems(seed, n_problems + n_new)
@@ -372,7 +384,7 @@ def serve_leg(H, torch, dev, n_problems=32, n_requests=1000, load=0.7, slots=4, 
         S = co[:, 0:1] * f[0:1] + co[:, 1:2] * f[1:2]  # [max_rhs, n_interior], smooth
         th = G.seeded_thetas(q["seed"] + 11, max_rhs)
         T = np.stack([G.PlaneWave(q["kappa"], float(a)).t(xyb, nrm, q["kappa"]) for a in th])
-        data.append({"dom": dom, "p": q["p"], "kappa": q["kappa"],
+        data.append({"dom": dom, "p": q["p"], "kappa": q["kappa"], "side": q["nx"],
                      "c": torch.tensor(c, dtype=torch.float64, device=dev),
                      "S": S.contiguous(), "T": torch.tensor(T, dtype=torch.complex128, device=dev),
                      "n": q["nx"] * q["ny"] * (q["p"] ** 2 - 4),
@@ -381,12 +393,81 @@ def serve_leg(H, torch, dev, n_problems=32, n_requests=1000, load=0.7, slots=4, 
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     free, total = torch.cuda.mem_get_info()
-    budget = int(free * 0.9 - reserve_gb * 1e9)
-    srv = H.Server(budget_bytes=budget, slots=slots)
+    # torch's own cache (inputs, and the outputs of outstanding requests, whose sizes
+    # vary) stays within the reserve, so that the server's budget is device memory it
+    # really has
+    torch.cuda.set_per_process_memory_fraction(
+        min(1.0, (torch.cuda.memory_allocated() + reserve_gb * 1e9) / total))
+    resident = sum(d["est"][1] for d in data[:n_problems])
+    scratch = max(d["est"][0] - d["est"][1] for d in data)
+    budget = int(min(free * 0.9 - reserve_gb * 1e9, resident + scratch + headroom_gb * 1e9))
+    srv = H.Server(budget_bytes=budget, slots=slots, solve_slots=solve_slots)
     res = {"problems": n_problems, "new_builds": n_new, "requests": n_requests,
-           "max_rhs_per_request": max_rhs, "slots": slots, "budget_gb": round(budget / 1e9, 2),
-           "resident_estimate_gb": round(sum(d["est"][1] for d in data[:n_problems]) / 1e9, 2),
+           "max_rhs_per_request": max_rhs, "slots": slots, "solve_only_slots": solve_slots,
+           "budget_gb": round(budget / 1e9, 2), "resident_estimate_gb": round(resident / 1e9, 2),
+           "largest_build_scratch_gb": round(scratch / 1e9, 2),
            "setup_s": round(t_setup, 2)}
+    rng_all = np.random.default_rng(seed + 2)
+    outstanding, held = {}, [0]
+    out_cap = reserve_gb * 1e9 * 0.5  # bytes of outputs of outstanding requests
+
+    retries = [0]
+
+    def out_bytes(nr, d):
+        # outputs come from buckets of eight sizes per power of two (at most 1/8 wasted),
+        # so that torch's cache reuses freed blocks instead of fragmenting over the many
+        # request sizes
+        n_el = nr * d["n"]
+        q = 1 << max(0, (n_el - 1).bit_length() - 3)
+        return -(-n_el // q) * q * 16
+
+    def submit(pid, d, nr):
+        n_el = nr * d["n"]
+        cap = out_bytes(nr, d) // 16
+        while True:
+            try:
+                buf = torch.empty(cap, dtype=torch.complex128, device=dev)
+                break
+            except torch.OutOfMemoryError:
+                retries[0] += 1
+                while outstanding and retries[0]:
+                    drain(50)
+                    if len(outstanding) < 8:
+                        break
+                torch.cuda.empty_cache()
+        u = buf[:n_el].view(nr, d["n"])
+        r, u = srv.solve(pid, d["T"][:nr], d["S"][:nr], u=u, sync=False)
+        outstanding[r] = cap * 16
+        held[0] += cap * 16
+        return r, u
+
+    def sample(u):
+        # a strided sample of a result's entries and its norm (a kept request's output is
+        # not held whole: 64 of them would take tens of GB)
+        flat = u.reshape(-1)
+        step = max(1, flat.numel() // 65536)
+        return flat[::step].clone(), float(torch.linalg.norm(u))
+
+    kept = {}
+
+    # completions are recorded into the current phase's latency list and counters
+    cur = {"lat": None, "counts": None}
+
+    def drain(timeout_ms):
+        lat, counts = cur["lat"], cur["counts"]
+        for c in srv.poll(256, timeout_ms):
+            if c["kind"] == H.HPS_REQ_SOLVE and c["req"] in outstanding:
+                assert c["status"] == 0, c
+                if c["req"] in kept:
+                    di, nr, u = kept[c["req"]]
+                    kept[c["req"]] = (di, nr, sample(u))
+                held[0] -= outstanding.pop(c["req"])
+                if lat is not None:
+                    lat.append(c["t_end"] - c["t_submit"])
+                if counts is not None:
+                    counts[0] += 1
+                    counts[1] += c["nrhs"]
+
     try:
         # builds of the resident set, all submitted at once
         t0 = time.perf_counter()
@@ -397,40 +478,42 @@ def serve_leg(H, torch, dev, n_problems=32, n_requests=1000, load=0.7, slots=4, 
         assert all(c["status"] == 0 for c in bdone.values()), "a build failed"
         res["build_phase_s"] = round(time.perf_counter() - t0, 3)
         res["build_dof_per_s"] = round(sum(d["n"] for d in data[:n_problems]) / res["build_phase_s"], 1)
-        # capacity probe: one 1-RHS and one max_rhs solve per resident problem, alone
-        svc = []
-        for pid, d in zip(pids, data[:n_problems]):
-            tt = {}
-            for k in (1, max_rhs):
-                r, u = srv.solve(pid, d["T"][:k], d["S"][:k], sync=False)
-                c = srv.wait([r])[r]
-                tt[k] = c["t_end"] - c["t_start"]
-                del u
-            b = (tt[max_rhs] - tt[1]) / (max_rhs - 1)
-            svc.append(tt[1] - b + b * (1 + max_rhs) / 2.0)
-        mean_svc = float(np.mean(svc))
-        rate = load / mean_svc
-        res["mean_service_s"] = round(mean_svc, 5)
+        log(f"serving: {n_problems} problems built in {res['build_phase_s']} s "
+            f"(budget {res['budget_gb']} GB of {res['resident_estimate_gb']} GB resident)")
+        # closed loop: `window` requests outstanding (fewer when their outputs would pass
+        # the output cap) until probe_requests have completed
+        live = list(zip(pids, range(n_problems)))  # (problem id, index into data)
+        ppick, pnr, _ = G.poisson_requests(seed + 3, probe_requests + window, max_rhs)
+        counts, k = [0, 0], 0
+        cur["counts"] = counts
+        t0 = time.perf_counter()
+        while counts[0] < probe_requests:
+            while len(outstanding) < window and k < len(ppick):
+                pid, di = live[int(ppick[k] * len(live))]
+                if outstanding and held[0] + out_bytes(int(pnr[k]), data[di]) > out_cap:
+                    break
+                submit(pid, data[di], int(pnr[k]))
+                k += 1
+            drain(20)
+        t_probe = time.perf_counter() - t0
+        done_probe, rhs_probe = counts
+        cur["counts"] = None
+        while outstanding:
+            drain(100)
+        sat = done_probe / t_probe
+        rate = load * sat
+        res["closed_loop_window"] = window
+        res["saturated_req_per_s"] = round(sat, 2)
+        res["saturated_rhs_per_s"] = round(rhs_probe / t_probe, 1)
         res["offered_rate_req_per_s"] = round(rate, 2)
-        # the stream
+        log(f"serving: closed-loop {sat:.1f} req/s; offering {rate:.1f} req/s")
+        # the open-loop stream
         pick, nrhs, gaps = G.poisson_requests(seed + 1, n_requests, max_rhs)
         arrive = np.cumsum(gaps) / rate
-        rng = np.random.default_rng(seed + 2)
-        keep = set(rng.choice(n_requests, size=min(checks, n_requests), replace=False).tolist())
-        live = list(zip(pids, range(n_problems)))  # (problem id, index into data)
+        keep = set(rng_all.choice(n_requests, size=min(checks, n_requests), replace=False).tolist())
         nxt_new = n_problems
-        held_bytes, outstanding = 0, {}
-        kept, lat, rhs_done, backpressure = {}, [], 0, 0
-
-        def drain(timeout_ms):
-            nonlocal held_bytes, rhs_done
-            for c in srv.poll(256, timeout_ms):
-                if c["kind"] == H.HPS_REQ_SOLVE and c["req"] in outstanding:
-                    assert c["status"] == 0, c
-                    held_bytes -= outstanding.pop(c["req"])
-                    lat.append(c["t_end"] - c["t_submit"])
-                    rhs_done += c["nrhs"]
-
+        lat, counts, backpressure, released = [], [0, 0], 0, 0
+        cur["lat"], cur["counts"] = lat, counts
         st0 = srv.stats()
         t_start = time.perf_counter()
         for k in range(n_requests):
@@ -439,22 +522,28 @@ def serve_leg(H, torch, dev, n_problems=32, n_requests=1000, load=0.7, slots=4, 
                 live.append((srv.build(d["dom"], d["p"], d["kappa"], d["kappa"], d["c"])[0],
                              nxt_new))
                 nxt_new += 1
+                # a live problem of the same leaf grid leaves (its queued requests still
+                # complete), so the live set's memory stays about the same
+                same = [i for i in range(len(live) - 1) if data[live[i][1]]["side"] == d["side"]]
+                pool = same if same else list(range(len(live) - 1))
+                gone = pool[int(rng_all.integers(len(pool)))]
+                srv.release(live.pop(gone)[0])
+                released += 1
+            if k % 1000 == 0 and k:
+                log(f"serving: {k} requests submitted, {counts[0]} done")
             pid, di = live[int(pick[k] * len(live))]
             d = data[di]
             nr = int(nrhs[k])
-            ub = nr * d["n"] * 16
             # outputs of outstanding requests stay within the memory left beside the budget
-            while held_bytes + ub > reserve_gb * 1e9 * 0.8 and outstanding:
+            while held[0] + out_bytes(nr, d) > out_cap and outstanding:
                 backpressure += 1
                 drain(50)
             wait = t_start + arrive[k] - time.perf_counter()
             if wait > 0:
                 time.sleep(wait)
-            r, u = srv.solve(pid, d["T"][:nr], d["S"][:nr], sync=False)
-            outstanding[r] = ub
-            held_bytes += ub
+            r, u = submit(pid, d, nr)
             if k in keep:
-                kept[r] = (d, nr, u)
+                kept[r] = (di, nr, u)
             del u
             drain(0)
         while outstanding:
@@ -463,32 +552,53 @@ def serve_leg(H, torch, dev, n_problems=32, n_requests=1000, load=0.7, slots=4, 
         st = srv.stats()
     finally:
         srv.close()
+        torch.cuda.set_per_process_memory_fraction(1.0)
     lat = np.array(lat) * 1e3
+    calls = st["batches"] - st0["batches"]
+    sb = st["shared_batches"] - st0["shared_batches"]
     res.update({
         "stream_s": round(t_stream, 3),
         "solves_per_s": round(n_requests / t_stream, 2),
-        "rhs_per_s": round(rhs_done / t_stream, 1),
+        "rhs_per_s": round(counts[1] / t_stream, 1),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3),
                        "max": round(float(lat.max()), 3)},
-        "solve_calls": st["batches"] - st0["batches"],
-        "mean_rhs_per_solve_call": round((st["rhs"] - st0["rhs"]) /
-                                         max(1, st["batches"] - st0["batches"]), 2),
-        "evictions": st["evictions"], "rebuilds": st["rebuilds"],
+        "solve_calls": calls,
+        "mean_rhs_per_solve_call": round((st["rhs"] - st0["rhs"]) / max(1, calls), 2),
+        "shared_solve_calls": sb,
+        "mean_problems_per_shared_call": round(
+            (st["shared_problems"] - st0["shared_problems"]) / max(1, sb), 2),
+        "evictions": st["evictions"] - st0["evictions"],
+        "rebuilds": st["rebuilds"] - st0["rebuilds"],
+        "evictions_total": st["evictions"], "rebuilds_total": st["rebuilds"],
+        "released": released,
+        "live_resident_estimate_gb_end": round(sum(data[di]["est"][1] for _, di in live) / 1e9, 2),
         "max_concurrent": st["max_concurrent"], "backpressure_waits": backpressure,
+        "output_alloc_retries": retries[0],
         "peak_committed_gb": round(st["peak_committed_bytes"] / 1e9, 2),
     })
-    # the kept requests solved alone on freshly built factors
-    worst = 0.0
-    for r, (d, nr, u) in kept.items():
+    # the kept requests solved alone, on factors built outside the server (one build per
+    # problem they use)
+    worst, worst_norm, by = 0.0, 0.0, {}
+    for r, (di, nr, smp) in kept.items():
+        by.setdefault(di, []).append((nr, smp))
+    for di, items in by.items():
+        d = data[di]
         f = H.hps_build(d["dom"], d["p"], d["kappa"], d["kappa"], d["c"])
-        ua = H.hps_solve(f, d["T"][:nr], d["S"][:nr])
-        torch.cuda.synchronize()
-        worst = max(worst, float(torch.linalg.norm(u - ua) / torch.linalg.norm(ua)))
+        for nr, (us, un) in items:
+            ua = H.hps_solve(f, d["T"][:nr], d["S"][:nr])
+            torch.cuda.synchronize()
+            uas, uan = sample(ua)
+            worst = max(worst, float(torch.linalg.norm(us - uas) / torch.linalg.norm(uas)))
+            worst_norm = max(worst_norm, abs(un - uan) / uan)
+            del ua
         f.free()
-        del ua
     res["alone_vs_mix_max_rel_l2"] = worst
+    res["alone_vs_mix_sample"] = ("every k-th entry of each kept result, about 65536 of them, "
+                                  "plus the relative difference of the full norms")
+    res["alone_vs_mix_max_norm_rel_diff"] = worst_norm
     res["alone_vs_mix_checked"] = len(kept)
+    res["alone_vs_mix_problems"] = len(by)
     return res
 
 
@@ -524,8 +634,15 @@ def main():
                     help="keep the default GEMM tile choice (no tuning in the warmup build)")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the serving leg (request loop under a Poisson stream)")
-    ap.add_argument("--serve-requests", type=int, default=1000,
+    ap.add_argument("--serve-requests", type=int, default=10000,
                     help="solve requests in the serving leg's stream")
+    ap.add_argument("--serve-new-every", type=int, default=500,
+                    help="requests between new builds in the serving stream (0: none)")
+    ap.add_argument("--serve-reserve-gb", type=float, default=48.0,
+                    help="device memory kept outside the server's budget for torch (inputs "
+                         "and the outputs of outstanding requests)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving leg (no step timing, no JSON line)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for scaling the HBM "
                          "byte counters of a profiler run) and exit")
@@ -544,6 +661,11 @@ def main():
         copy_calibration(torch, dev)
         return
     H.load()
+    if args.serve_only:
+        print(json.dumps({"serving": serve_leg(H, torch, dev, n_requests=args.serve_requests,
+                                   new_build_every=args.serve_new_every,
+                                   reserve_gb=args.serve_reserve_gb)}))
+        return
     nx = ny = 64
     p, kappa, nrhs = 16, 100.0, args.nrhs
     dom = H.domain(nx, ny)
@@ -714,7 +836,9 @@ def main():
     if not args.no_serve:
         log("serving leg")
         torch.cuda.empty_cache()
-        out["serving"] = serve_leg(H, torch, dev, n_requests=args.serve_requests)
+        out["serving"] = serve_leg(H, torch, dev, n_requests=args.serve_requests,
+                                   new_build_every=args.serve_new_every,
+                                   reserve_gb=args.serve_reserve_gb)
     if not args.no_mixed:
         log("precision leg (128 x 128 leaves)")
         torch.cuda.empty_cache()

@@ -236,7 +236,10 @@ int hps_solve_noalloc(hps_factor* f, int32_t nrhs, const double* s, const double
 /* Cross-problem batching (not in the paper; the paper's parallelism is over the boxes
  * of one problem).  Builds nprob independent problems; problems with the same domain,
  * leaf grid and p are factored together, every leaf and merge-level launch covering all
- * of them.  Arguments are arrays of length nprob with the meaning of hps_build's
+ * of them.  Groups of different shapes are built at the same time, each on a stream of
+ * the library's own (up to 4 at once) that starts after the work queued on
+ * opts.stream; the call returns when every group is built, and the handles then use
+ * opts.stream.  Arguments are arrays of length nprob with the meaning of hps_build's
  * (c_interior[i] a device pointer); opts apply to all.  out[i] receives problem i's
  * handle; handles of one group share its device memory, which is released with the
  * last of them (hps_free).  Each handle works with every other entry point.  On failure

@@ -3,15 +3,18 @@
 // level) and the solve driver (Algorithm 2 as one batched pass per level, upward then
 // downward).  Host code; all arithmetic on the hot path runs in the HIP kernels.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <exception>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <unordered_map>
 #include <vector>
@@ -1559,6 +1562,9 @@ void check_problem(const hps_domain* dom, int p, double kappa, double er, double
 }
 
 // Build the factorizations of nprob problems that share domain, leaf grid and p.
+// shape groups of one hps_build_batch call built at the same time
+constexpr size_t kBatchStreams = 4;
+
 std::shared_ptr<hps_group> build_group(const hps_domain& dom, int p, int nprob,
                                        const double* kappa, const double* er, const double* ei,
                                        const double* const* c, const hps_opts* opts) {
@@ -1631,6 +1637,7 @@ int hps_build_batch(int32_t nprob, const hps_domain* doms, const int32_t* p,
     made.resize(nprob);
     // problems of one shape (domain, leaf grid, p) share a group, in first-seen order
     std::vector<char> done(nprob, 0);
+    std::vector<std::vector<int>> groups;
     for (int i = 0; i < nprob; ++i) {
       if (done[i]) continue;
       std::vector<int> mem;
@@ -1642,20 +1649,84 @@ int hps_build_batch(int32_t nprob, const hps_domain* doms, const int32_t* p,
           done[j] = 1;
         }
       }
+      groups.push_back(std::move(mem));
+    }
+    auto build_one = [&](const std::vector<int>& mem, const hps_opts* o) {
       std::vector<double> k(mem.size()), er(mem.size()), ei(mem.size());
       std::vector<const double*> cs(mem.size());
       for (size_t q = 0; q < mem.size(); ++q) {
         k[q] = kappa[mem[q]]; er[q] = eta_re[mem[q]]; ei[q] = eta_im[mem[q]];
         cs[q] = c_interior[mem[q]];
       }
-      auto g = build_group(doms[i], p[i], (int)mem.size(), k.data(), er.data(), ei.data(),
-                           cs.data(), opts);
-      for (size_t q = 0; q < mem.size(); ++q) {
-        made[mem[q]].reset(new hps_factor);
-        made[mem[q]]->g = g;
-        made[mem[q]]->b0 = (int)q;
+      return build_group(doms[mem[0]], p[mem[0]], (int)mem.size(), k.data(), er.data(),
+                         ei.data(), cs.data(), o);
+    };
+    std::vector<std::shared_ptr<hps_group>> gs(groups.size());
+    if (groups.size() == 1) {
+      gs[0] = build_one(groups[0], opts);
+    } else {
+      // Groups are built concurrently, each on a stream of its own (up to kBatchStreams
+      // at a time), so that the launches of different shapes overlap on the device.  The
+      // streams start after the caller's queued work (the inputs) and are synchronized
+      // before returning; the groups then keep the caller's stream for later calls.
+      hps_opts base;
+      if (opts) base = *opts; else hps_default_opts(&base);
+      hipStream_t caller = static_cast<hipStream_t>(base.stream);
+      int dev = 0;
+      HPS_HIP(hipGetDevice(&dev));
+      hipEvent_t ready = nullptr;
+      HPS_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+      struct EvFree {
+        hipEvent_t e;
+        ~EvFree() { (void)hipEventDestroy(e); }
+      } evf{ready};
+      HPS_HIP(hipEventRecord(ready, caller));
+      std::atomic<size_t> next{0};
+      std::mutex emu;
+      std::exception_ptr err;
+      auto worker = [&]() {
+        hipStream_t st = nullptr;
+        try {
+          HPS_HIP(hipSetDevice(dev));
+          // default priority, like every stream of the library
+          HPS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+          HPS_HIP(hipStreamWaitEvent(st, ready, 0));
+          hps_opts o = base;
+          o.stream = st;
+          for (size_t i = next++; i < groups.size(); i = next++) {
+            {
+              std::lock_guard<std::mutex> lk(emu);
+              if (err) break;
+            }
+            gs[i] = build_one(groups[i], &o);
+          }
+          HPS_HIP(hipStreamSynchronize(st));
+        } catch (...) {
+          std::lock_guard<std::mutex> lk(emu);
+          if (!err) err = std::current_exception();
+        }
+        if (st) {
+          (void)hipStreamSynchronize(st);
+          (void)hipStreamDestroy(st);
+        }
+      };
+      const int nw = (int)std::min<size_t>(groups.size(), kBatchStreams);
+      std::vector<std::thread> th;
+      for (int w = 0; w < nw; ++w) th.emplace_back(worker);
+      for (auto& t : th) t.join();
+      if (err) std::rethrow_exception(err);
+      for (auto& g : gs) {
+        g->stream = caller;
+        g->opts.stream = caller;
       }
     }
+    for (size_t gi = 0; gi < groups.size(); ++gi)
+      for (size_t q = 0; q < groups[gi].size(); ++q) {
+        const int i = groups[gi][q];
+        made[i].reset(new hps_factor);
+        made[i]->g = gs[gi];
+        made[i]->b0 = (int)q;
+      }
   });
   if (rc == HPS_OK)
     for (int i = 0; i < nprob; ++i) out[i] = made[i].release();
@@ -2294,8 +2365,12 @@ namespace hps {
 // belongs to one call; when the call ends an event is recorded on its stream, and the
 // next call that takes the buffer makes its own stream wait for that event, so reuse is
 // ordered on the device across streams.  A call takes the smallest idle buffer that
-// fits; when none fits, the largest idle buffer of the device is replaced by one of the
-// requested size.
+// fits; when none fits, a buffer of the requested size is added, and the largest idle
+// buffer of the device is released first only while the idle buffers hold more than
+// kWsIdleCap (a release synchronizes the device, which would stall every stream).
+// Workspace sizes are rounded up to eight steps per power of two, so that requests of
+// similar size share buffers.  A failed allocation releases every idle buffer and
+// retries.
 namespace {
 struct WsBuf {
   int dev = 0;
@@ -2308,6 +2383,7 @@ struct WsBuf {
 std::mutex g_ws_mu;
 std::vector<WsBuf> g_ws;
 constexpr size_t kWsGrain = size_t(2) << 20;
+constexpr size_t kWsIdleCap = size_t(16) << 30;
 
 void ws_release(WsBuf& b) {
   (void)hipFree(b.p);  // waits for the device, so pending uses of the buffer have ended
@@ -2329,14 +2405,23 @@ void* ws_take(size_t bytes, hipStream_t st, bool host_wait) {
   int dev = 0;
   HPS_HIP(hipGetDevice(&dev));
   bytes = (std::max<size_t>(bytes, 1) + kWsGrain - 1) / kWsGrain * kWsGrain;
+  if (!host_wait) {
+    // eight size steps per power of two (at most 1/8 over the request)
+    int lg = 0;
+    while ((size_t(1) << (lg + 1)) <= bytes) ++lg;
+    const size_t q = lg > 3 ? size_t(1) << (lg - 3) : 1;
+    bytes = (bytes + q - 1) / q * q;
+  }
   std::unique_lock<std::mutex> lk(g_ws_mu);
   // best fit among the idle buffers.  A host-waited request is a long-lived buffer (a
   // factor's arena, a build's scratch): it takes none much larger than itself, so that a
   // small factor never holds a large buffer (the largest idle one is released instead)
   long best = -1, largest = -1;
+  size_t idle = 0;
   for (size_t i = 0; i < g_ws.size(); ++i) {
     const WsBuf& b = g_ws[i];
     if (b.busy || b.dev != dev) continue;
+    idle += b.cap;
     const bool fits = b.cap >= bytes && (!host_wait || b.cap <= bytes + bytes / 4 + kWsGrain);
     if (fits && (best < 0 || b.cap < g_ws[best].cap)) best = (long)i;
     if (largest < 0 || b.cap > g_ws[largest].cap) largest = (long)i;
@@ -2357,7 +2442,7 @@ void* ws_take(size_t bytes, hipStream_t st, bool host_wait) {
     return ptr;
   }
   std::vector<WsBuf> drop;
-  if (largest >= 0) {
+  if (largest >= 0 && idle > kWsIdleCap) {
     drop.push_back(g_ws[largest]);
     g_ws.erase(g_ws.begin() + largest);
   }
@@ -2484,6 +2569,11 @@ void* dev_alloc(size_t bytes) {
   if (void* q = hook_alloc(bytes, nullptr)) return q;
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 1));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    ws_trim();  // idle cached buffers may be what stands in the way
+    e = hipMalloc(&p, std::max<size_t>(bytes, 1));
+  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     throw Error(e == hipErrorOutOfMemory ? HPS_E_NOMEM : HPS_E_DEVICE,

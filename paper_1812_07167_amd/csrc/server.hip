@@ -12,7 +12,8 @@
 // item is admissible when the bytes it needs fit beside the committed bytes (server
 // copies of c, resident factors, running items); otherwise idle factors are freed least
 // recently used first, when that makes it fit (for a solve, only while no other solve
-// runs: a running solve's memory comes back soon).  When nothing runs and the oldest item
+// runs: a running solve's memory comes back soon).  Once the oldest item cannot start,
+// younger ones start only if they leave its bytes free.  When nothing runs and the oldest item
 // still cannot fit, it fails with HPS_E_NOMEM.
 #include <hip/hip_runtime.h>
 
@@ -120,6 +121,7 @@ struct hps_server {
   hps::Clock::time_point t0;
   int running = 0, max_running = 0;
   int running_solves = 0;
+  size_t running_mem = 0;  // bytes committed by running items
   int64_t builds = 0, rebuilds = 0, evictions = 0, solves = 0, rhs = 0, batches = 0;
   int64_t rejected = 0, failed = 0, shared_batches = 0, shared_problems = 0;
   int solve_only = 0;  // slots [0, solve_only) take no builds
@@ -278,10 +280,32 @@ bool pick(hps_server& S, Work& w, std::vector<Freed>& fr, bool builds) {
   }
   std::stable_sort(cands.begin(), cands.end(),
                    [](const Cand& a, const Cand& b) { return a.arrival < b.arrival; });
+  // Bytes the oldest item that cannot start yet waits for: younger items start only
+  // beside them, so that memory freed by running work collects for it (a large build
+  // is not starved by a stream of solves).  Only an item that would fit once the
+  // running items end (with idle factors evicted) reserves: one that needs younger
+  // items to run first (to make their problems idle) must not block them.
+  size_t ahead = 0;
+  auto hold = [&](size_t need, const Problem* keep) {
+    if (ahead) return;
+    size_t idle = 0;
+    if (S.opts.evict_idle)
+      for (auto& kv : S.problems) {
+        const Problem* q = kv.second.get();
+        if (q != keep && q->state == PState::Resident && !q->busy && q->pending.empty())
+          idle += q->resident;
+      }
+    const long long after = (long long)S.budget - (long long)(S.committed - S.running_mem) +
+                            (long long)idle;
+    if ((long long)need <= after) ahead = need;
+  };
   for (const Cand& c : cands) {
     Problem& p = *c.p;
     if (c.kind == Work::Build) {
-      if (!evict_for(S, p.peak, &p, fr)) continue;
+      if (!evict_for(S, p.peak + ahead, &p, fr)) {
+        hold(p.peak, &p);
+        continue;
+      }
       w.kind = Work::Build;
       w.pr = &p;
       w.mem = p.peak;
@@ -291,16 +315,25 @@ bool pick(hps_server& S, Work& w, std::vector<Freed>& fr, bool builds) {
       // A solve's memory returns when it ends, a factor's only with a rebuild: while
       // another solve runs, a solve that does not fit waits for it instead of evicting.
       const bool may_evict = S.running_solves == 0;
-      auto admit = [&](size_t b) { return may_evict ? evict_for(S, b, &p, fr) : fits(S, b); };
+      auto admit = [&](size_t b) {
+        return may_evict ? evict_for(S, b + ahead, &p, fr) : fits(S, b + ahead);
+      };
       size_t k = batch_len(p, S.opts.max_batch_rhs);
       int R = 0;
       bool any_s = false;
       size_t need = solve_need(p, k, &R, &any_s);
       if (!admit(need)) {
-        if (k == 1) continue;
-        k = 1;
-        need = solve_need(p, k, &R, &any_s);
-        if (!admit(need)) continue;
+        // the oldest request alone, else wait
+        bool ok = false;
+        if (k > 1) {
+          k = 1;
+          need = solve_need(p, k, &R, &any_s);
+          ok = admit(need);
+        }
+        if (!ok) {
+          hold(need, &p);
+          continue;
+        }
       }
       w.kind = Work::Solve;
       w.pr = &p;
@@ -335,7 +368,7 @@ bool pick(hps_server& S, Work& w, std::vector<Freed>& fr, bool builds) {
           }
           // riding along is opportunistic: it never evicts a factor
           const size_t need2 = shared_need(sh);
-          if (fits(S, need2)) {
+          if (fits(S, need2 + ahead)) {
             w.shares = std::move(sh);
             w.mem = need2;
             for (size_t i = 1; i < w.shares.size(); ++i) {
@@ -358,6 +391,7 @@ bool pick(hps_server& S, Work& w, std::vector<Freed>& fr, bool builds) {
     }
     p.busy = true;
     S.committed += w.mem;
+    S.running_mem += w.mem;
     S.peak_committed = std::max(S.peak_committed, S.committed);
     ++S.running;
     if (w.kind == Work::Solve) ++S.running_solves;
@@ -473,8 +507,8 @@ void slot_main(hps_server* S, int slot) {
     hps_factor* built = nullptr;
     size_t built_bytes = 0;
     if (w.kind == Work::Build) {
-      // return idle cached workspaces first: the build's memory is admitted without them
-      ws_trim();
+      // (idle cached buffers, outside the budget, are released by an allocation that
+      // fails for want of their memory)
       Problem& p = *w.pr;  // fields read here are fixed while the problem is busy
       hps_opts o = p.opts;
       o.stream = st;
@@ -493,6 +527,7 @@ void slot_main(hps_server* S, int slot) {
     if (w.kind != Work::None) {
       Problem& p = *w.pr;
       S->committed -= w.mem;
+      S->running_mem -= w.mem;
       --S->running;
       if (w.kind == Work::Solve) --S->running_solves;
       p.busy = false;

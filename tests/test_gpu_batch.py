@@ -173,6 +173,28 @@ def test_config3_strata_match_oracle(side, precision):
         f.free()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_config3_all_nine_strata_in_one_call(precision):
+    """All nine (leaf grid, p) strata of the batch workload in one hps_build_batch call
+    (nine shape groups, built side by side on the library's streams) and one
+    hps_solve_batch call, each against the oracle (1e-10)."""
+    import torch
+    from paper_1812_07167_amd import hps as H
+    qs = [q for side in (8, 16, 32) for q in _config3_strata(side)]
+    assert len(qs) == 9
+    print("config-3 nine strata in one call, precision", precision, flush=True)
+    ins = [_config3_inputs(q) for q in qs]
+    fs = H.hps_build_batch([H.domain(q["nx"], q["ny"]) for q in qs], [q["p"] for q in qs],
+                           [q["kappa"] for q in qs], [q["kappa"] for q in qs],
+                           [_dev(c, "float64") for c, _, _, _ in ins], precision=precision)
+    us = H.hps_solve_batch(fs, [_dev(t) for _, _, t, _ in ins], [_dev(s) for _, s, _, _ in ins])
+    torch.cuda.synchronize()
+    for q, (_, _, _, uo), u in zip(qs, ins, us):
+        assert rel(u.cpu().numpy(), uo) < TOL, (q["seed"], q["nx"], q["p"])
+    for f in fs:
+        f.free()
+
+
 # ------------------------------------------- problems of different groups share launches
 
 

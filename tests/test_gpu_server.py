@@ -249,3 +249,65 @@ def test_solve_slot_is_never_taken_by_a_build():
     assert done[r]["status"] == 0 and done[big_req]["status"] == 0
     assert done[r]["t_end"] < done[big_req]["t_end"], (done[r], done[big_req])
     assert rel(u.cpu().numpy(), small.oracle_solve(small.oracle_build())) < TOL
+
+
+def test_config5_small_problems_under_eviction_match_alone_and_oracle():
+    """Config 5's request format on its smallest problems: four seeded 32 x 32-leaf, p = 12
+    problems (kappa 50-300, Fourier c), 56 Poisson-drawn requests of 1..64 right-hand
+    sides (smooth s from two Fourier fields, plane-wave t) in two waves, under a budget
+    that holds three of the four factors, so that factors are evicted and rebuilt.  Every request against the same request solved alone (1e-12) and against the
+    oracle (1e-10)."""
+    import torch
+    from oracle import hps_oracle as O
+    from paper_1812_07167_amd import hps as H
+    from paper_1812_07167_amd import inputs as G
+    qs = [q for q in G.serve_problems(0, 200) if q["nx"] == 32 and q["p"] == 12][:4]
+    assert len(qs) == 4
+    cases, data = [], []
+    for q in qs:
+        cs = Case(32, 32, 12, q["kappa"], seed=q["seed"], nrhs=1)
+        cs.c = G.FourierField.seeded(q["seed"])(cs.xyi)
+        fld = np.stack([G.FourierField.seeded(sd)(cs.xyi) - 1.0 for sd in q["s_seeds"]])
+        rng = np.random.default_rng(q["seed"] + 7)
+        co = rng.standard_normal((64, 2)) + 1j * rng.standard_normal((64, 2))
+        S = co @ fld
+        th = G.seeded_thetas(q["seed"] + 11, 64)
+        T = np.stack([G.PlaneWave(q["kappa"], float(a)).t(cs.xyb, cs.nrm, q["kappa"]) for a in th])
+        cases.append(cs)
+        data.append((S, T))
+    pick, nrhs, _ = G.poisson_requests(5, 56, 64)
+    reqs = [(int(pk * 4), int(nr)) for pk, nr in zip(pick, nrhs)]
+    dev = [(_dev(data[j][1][:nr]), _dev(data[j][0][:nr])) for j, nr in reqs]
+    torch.cuda.synchronize()
+    peak, res = H.hps_estimate_bytes(H.domain(32, 32), 12)
+    # three factors and a solve fit; a fourth build or a rebuild needs an eviction
+    srv = H.Server(budget_bytes=3 * res + int(0.9 * peak), slots=3, solve_slots=1,
+                   max_batch_rhs=64)
+    print("config-5 small problems:", [(q["seed"], round(q["kappa"], 1)) for q in qs], flush=True)
+    try:
+        built = [_submit_build(srv, c) for c in cases]
+        pids = [pid for pid, _ in built]
+        ids, us, done = [], [], {}
+        # two waves: the second meets factors the first (and the fourth build) evicted
+        for lo, hi in ((0, 28), (28, 56)):
+            for (j, _), (td, sd) in zip(reqs[lo:hi], dev[lo:hi]):
+                r, u = srv.solve(pids[j], td, sd, sync=False)
+                ids.append(r)
+                us.append(u)
+            done.update(srv.wait(ids[lo:hi] + ([req for _, req in built] if lo == 0 else []),
+                                 timeout_s=300))
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert all(done[r]["status"] == 0 for r in ids)
+    assert st["evictions"] >= 1 and st["rebuilds"] >= 1, st
+    fs = [c.gpu_build() for c in cases]
+    obs = [c.oracle_build() for c in cases]
+    for q, ((j, nr), u) in enumerate(zip(reqs, us)):
+        S, T = data[j][0][:nr], data[j][1][:nr]
+        ua = _alone(cases[j], fs[j], T, S)
+        assert rel(u.cpu().numpy(), ua) < SAME, q
+        uo = O.solve(cases[j].prob, obs[j], S, T)
+        assert rel(u.cpu().numpy(), uo) < TOL, q
+    for f in fs:
+        f.free()
