@@ -392,6 +392,10 @@ def serve_leg(H, torch, dev, n_problems=32, n_requests=10000, load=0.7, slots=4,
         del f, co
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
+    # memory cached by earlier legs (torch's and the library's) goes back to the device
+    # before the budget is sized from what is free
+    torch.cuda.empty_cache()
+    H.hps_release_cached()
     free, total = torch.cuda.mem_get_info()
     # torch's own cache (inputs, and the outputs of outstanding requests, whose sizes
     # vary) stays within the reserve, so that the server's budget is device memory it

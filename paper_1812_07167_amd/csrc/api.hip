@@ -933,10 +933,12 @@ void choose_routes(hps_group& f, const double* c) {
   if (!f.dcmax.p) f.dcmax.alloc((size_t)f.nprob * sizeof(double));
   if (f.opts.leaf_route != 1) {
     leaf_cmax(c, f.nprob, (long)f.nl1 * f.ni, f.dcmax.d(), f.stream);
-    std::vector<double> cm(f.nprob);
-    HPS_HIP(hipMemcpyAsync(cm.data(), f.dcmax.p, cm.size() * sizeof(double),
+    std::vector<unsigned long long> key(f.nprob);
+    HPS_HIP(hipMemcpyAsync(key.data(), f.dcmax.p, key.size() * sizeof(unsigned long long),
                            hipMemcpyDeviceToHost, f.stream));
     HPS_HIP(hipStreamSynchronize(f.stream));
+    std::vector<double> cm(f.nprob);
+    for (int b = 0; b < f.nprob; ++b) cm[b] = leaf_cmax_value(key[b]);
     const double hx = (f.x1 - f.x0) / f.nx, hy = (f.y1 - f.y0) / f.ny;
     const double lam1 = M_PI * M_PI * (1.0 / (hx * hx) + 1.0 / (hy * hy));
     for (int b = 0; b < f.nprob; ++b) {

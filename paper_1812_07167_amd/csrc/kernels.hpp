@@ -125,7 +125,11 @@ void leaf_psi_and_boundary(const LeafDesc& d, hipStream_t st);
 // each problem (nprob problems of per_prob samples); A^{-1} into the Y_i block (real
 // values); X, Z into scratch and S = F_bb - N_i X into the Psi_b block; R from Psi_b
 int leaf_rtable_len(int p);
+// leaf_cmax leaves each problem's largest c in cmax as an order-preserving 64-bit key
+// (NaN counted as +infinity); leaf_cmax_value turns a key copied to the host back into
+// the double
 void leaf_cmax(const double* c, int nprob, long per_prob, double* cmax, hipStream_t st);
+double leaf_cmax_value(unsigned long long key);
 void leaf_dirichlet_inverse(const LeafDesc& d, hipStream_t st);
 void leaf_dirichlet_xz(const LeafDesc& d, hipStream_t st);
 void leaf_dirichlet_R(const LeafDesc& d, hipStream_t st);

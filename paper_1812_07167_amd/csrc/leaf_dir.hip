@@ -20,6 +20,8 @@
 // [Psi | Y]), leaf_xz (X, Z and S from A^{-1}, S into the Psi_b block), leaf_dir_R
 // (R from Psi_b once S is inverted).  S^{-1} and the three products run on the shared
 // inversion and GEMM kernels (api.hip).
+#include <cstring>
+
 #include "kernels.hpp"
 
 namespace hps {
@@ -52,29 +54,41 @@ struct RIdx {
 };
 
 // ------------------------------------------------------------------ largest c per problem
-// cmax[b] = max of c over the interior nodes of problem b's leaves (NaN if any is NaN).
+// Order-preserving map of doubles to unsigned integers (NaN is taken as +infinity), so
+// that an integer atomic max finds the largest c.
+__device__ inline unsigned long long cmax_key(double x) {
+  if (x != x) x = INFINITY;
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+__global__ void leaf_cmax_init_kernel(int nprob, unsigned long long* key) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nprob) key[b] = cmax_key(-INFINITY);
+}
+
+// key[b] = max over problem b's samples (of a slice of them per workgroup: x covers the
+// samples, y the problems), as cmax_key.
 __global__ __launch_bounds__(256) void leaf_cmax_kernel(const double* c, long per_prob,
-                                                        double* cmax) {
-  __shared__ double red[256];
-  const long b = blockIdx.x;
+                                                        int nprob, unsigned long long* key) {
+  __shared__ unsigned long long red[256];
+  for (long b = blockIdx.y; b < nprob; b += gridDim.y) {
   const double* cb = c + b * per_prob;
-  double v = -INFINITY;
-  bool nan = false;
-  for (long e = threadIdx.x; e < per_prob; e += 256) {
-    const double x = cb[e];
-    nan = nan || (x != x);
-    v = x > v ? x : v;
+  unsigned long long v = cmax_key(-INFINITY);
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < per_prob; e += (long)gridDim.x * 256) {
+    const unsigned long long k = cmax_key(cb[e]);
+    v = k > v ? k : v;
   }
-  red[threadIdx.x] = nan ? NAN : v;
+  red[threadIdx.x] = v;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      const double a = red[threadIdx.x], o = red[threadIdx.x + s];
-      red[threadIdx.x] = (a != a || o != o) ? NAN : (o > a ? o : a);
-    }
+    if ((int)threadIdx.x < s && red[threadIdx.x + s] > red[threadIdx.x])
+      red[threadIdx.x] = red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) cmax[b] = red[0];
+  if (threadIdx.x == 0) atomicMax(key + b, red[0]);
+  __syncthreads();  // red is reused for the next problem
+  }  // problems
 }
 
 // ------------------------------------------------------------------ A^{-1} (real)
@@ -531,8 +545,20 @@ int leaf_rtable_len(int p) { return RIdx{p - 2}.len(); }
 
 void leaf_cmax(const double* c, int nprob, long per_prob, double* cmax, hipStream_t st) {
   if (nprob <= 0) return;
-  hipLaunchKernelGGL(leaf_cmax_kernel, dim3(nprob), dim3(256), 0, st, c, per_prob, cmax);
+  unsigned long long* key = reinterpret_cast<unsigned long long*>(cmax);
+  hipLaunchKernelGGL(leaf_cmax_init_kernel, dim3(cdiv(nprob, 256)), dim3(256), 0, st, nprob, key);
   HPS_LAUNCH_CHECK();
+  const unsigned gx = (unsigned)std::min<long>(64, std::max<long>(1, cdiv(per_prob, 4096)));
+  hipLaunchKernelGGL(leaf_cmax_kernel, dim3(gx, grid_y(nprob)), dim3(256), 0, st, c, per_prob,
+                     nprob, key);
+  HPS_LAUNCH_CHECK();
+}
+
+double leaf_cmax_value(unsigned long long k) {
+  const unsigned long long u = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+  double x;
+  std::memcpy(&x, &u, sizeof x);
+  return x;
 }
 
 void leaf_dirichlet_inverse(const LeafDesc& d, hipStream_t st) {
