@@ -394,6 +394,9 @@ int hps_estimate_bytes(const hps_domain* dom, int32_t p, const hps_opts* opts,
  *     arrive while others run are taken as soon as a slot and memory free up.
  *   - Solve slots: the first solve_slots slots never take a build, so a solve does not
  *     wait for a slot behind long builds.
+ *   - A solve or build whose allocation fails for want of device memory while other work
+ *     runs is put back in the queue and retried once some of that work has ended
+ *     (stats.retried); with nothing else running it fails with HPS_E_NOMEM.
  * A request's result does not depend on what it was batched with beyond round-off.
  * Inputs (c, s, t) must be complete on the device when submitted (the server's streams
  * do not wait on the caller's); u is complete when its completion is returned by
@@ -441,6 +444,9 @@ typedef struct {
   int64_t budget_bytes, committed_bytes, peak_committed_bytes;
   int64_t shared_batches;               /* solve calls that served several problems       */
   int64_t shared_problems;              /* problems those calls served, summed            */
+  int64_t retried;                      /* solves and builds put back in the queue after
+                                           running out of device memory beside other
+                                           running work                                  */
 } hps_stats;
 
 /* Fill *opts with the defaults. */

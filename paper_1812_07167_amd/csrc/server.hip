@@ -96,6 +96,10 @@ struct Freed {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// Device bytes a solve's allocations take for `b` bytes of workspace and staging: the
+// workspace cache rounds each buffer up by at most an eighth, plus its 2 MiB grain.
+size_t with_rounding(size_t b) { return b + b / 8 + (size_t(8) << 20); }
+
 // staging of a merged solve: S (if any request has s), T, U, each 256-byte aligned
 size_t staging_bytes(const Problem& p, int R, bool any_s, size_t nreq) {
   if (nreq <= 1) return 0;
@@ -122,8 +126,10 @@ struct hps_server {
   int running = 0, max_running = 0;
   int running_solves = 0;
   size_t running_mem = 0;  // bytes committed by running items
+  bool nomem_wait = false; // after an item ran out of device memory beside running
+                           // work: nothing new starts until one of those ends
   int64_t builds = 0, rebuilds = 0, evictions = 0, solves = 0, rhs = 0, batches = 0;
-  int64_t rejected = 0, failed = 0, shared_batches = 0, shared_problems = 0;
+  int64_t rejected = 0, failed = 0, shared_batches = 0, shared_problems = 0, retried = 0;
   int solve_only = 0;  // slots [0, solve_only) take no builds
   std::vector<double> lat_ms;
   double first_submit = -1.0, last_end = 0.0;
@@ -202,7 +208,7 @@ size_t solve_need(Problem& p, size_t k, int* R, bool* any_s) {
   } catch (const std::exception&) {
     return ~size_t(0) / 4;  // cannot be sized: never admitted, fails once nothing runs
   }
-  return ws + staging_bytes(p, r, s, k) + 1024;
+  return with_rounding(ws + staging_bytes(p, r, s, k));
 }
 
 // the parts of a shared solve: every request of every share
@@ -221,7 +227,7 @@ size_t shared_need(const std::vector<Share>& sh) {
   } catch (const std::exception&) {
     return ~size_t(0) / 4;
   }
-  return b + 1024;
+  return with_rounding(b);
 }
 
 // requests of p's queue that one merged solve takes (at least one)
@@ -238,6 +244,7 @@ size_t batch_len(const Problem& p, int max_rhs) {
 // Choose the next work item (caller holds the lock).  Returns true when it changed
 // anything (took work, queued frees, produced completions).
 bool pick(hps_server& S, Work& w, std::vector<Freed>& fr, bool builds) {
+  if (S.nomem_wait && S.running > 0) return false;
   bool progress = false;
   const double tnow = S.now();
   // failed problems answer their queued solves; released idle problems go away
@@ -530,13 +537,19 @@ void slot_main(hps_server* S, int slot) {
       S->running_mem -= w.mem;
       --S->running;
       if (w.kind == Work::Solve) --S->running_solves;
+      S->nomem_wait = false;  // this item's memory is back
       p.busy = false;
       p.last_use = ++S->lru_clock;
       for (size_t i = 1; i < w.shares.size(); ++i) {
         w.shares[i].pr->busy = false;
         w.shares[i].pr->last_use = S->lru_clock;
       }
-      if (w.kind == Work::Build) {
+      if (w.kind == Work::Build && status == HPS_E_NOMEM && S->running > 0) {
+        // device memory ran short beside other running work: build again later
+        ++S->retried;
+        S->nomem_wait = true;
+        p.state = w.rebuild ? PState::Evicted : PState::Queued;
+      } else if (w.kind == Work::Build) {
         if (status == HPS_OK) {
           p.f = built;
           p.resident = built_bytes;
@@ -553,6 +566,17 @@ void slot_main(hps_server* S, int slot) {
         if (!w.rebuild)
           complete(*S, p, HPS_REQ_BUILD, p.build_req, status, 0, 0, 0, false, p.build_submit,
                    t_start, t_end);
+      } else if (status == HPS_E_NOMEM && S->running > 0) {
+        // device memory ran short beside other running work (memory outside the
+        // budget: another process, fragmentation): the requests go back to the front
+        // of their queues and are retried once memory frees up
+        ++S->retried;
+        S->nomem_wait = true;
+        for (auto it = w.shares.rbegin(); it != w.shares.rend(); ++it) {
+          Problem& q = *it->pr;
+          q.pending.insert(q.pending.begin(), it->reqs.begin(), it->reqs.end());
+          q.rebuilt = q.rebuilt || it->after_rebuild;
+        }
       } else {
         ++S->batches;
         if (w.shares.size() > 1) {
@@ -807,6 +831,7 @@ int hps_server_stats(hps_server* S, hps_stats* st) {
     z.peak_committed_bytes = (int64_t)S->peak_committed;
     z.shared_batches = S->shared_batches;
     z.shared_problems = S->shared_problems;
+    z.retried = S->retried;
     *st = z;
     return HPS_OK;
   });

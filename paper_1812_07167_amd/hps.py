@@ -96,7 +96,7 @@ class Stats(C.Structure):
                 ("wall_s", C.c_double), ("rhs_per_s", C.c_double), ("solves_per_s", C.c_double),
                 ("budget_bytes", C.c_int64), ("committed_bytes", C.c_int64),
                 ("peak_committed_bytes", C.c_int64), ("shared_batches", C.c_int64),
-                ("shared_problems", C.c_int64)]
+                ("shared_problems", C.c_int64), ("retried", C.c_int64)]
 
 
 _lib = None
