@@ -511,7 +511,8 @@ __global__ __launch_bounds__(256) void zinv_bstep_kernel(int n, int nb, int k0, 
 }
 
 // Inverse of the n x n diagonal block P of a matrix (n <= 64) with its own 16 x 16
-// diagonal blocks as pivots: one workgroup of 256 threads per matrix, P in LDS.  Per
+// diagonal blocks as pivots: one workgroup of 1024 threads (16 waves) per matrix, P in
+// LDS; the block transformations and updates spread over all of them.  Per
 // block K of 16 columns, the first wave inverts P[K, K] in registers (lane l holds row
 // l % 16, columns l / 16 + 4 q; row and column k are exchanged by cross-lane reads), then
 // Q = -P[:, K] P[K, K]^{-1} (rows K: P[K, K]^{-1}) and X = P[K, :] (identity on K), and
@@ -523,12 +524,7 @@ __device__ inline typename Cx<T>::t shfl_c(typename Cx<T>::t v, int src) {
   return Cx<T>::mk(__shfl(v.x, src), __shfl(v.y, src));
 }
 template <class T>
-__device__ inline typename Cx<T>::t pick4c(const typename Cx<T>::t (&v)[4], int q) {
-  return q == 0 ? v[0] : q == 1 ? v[1] : q == 2 ? v[2] : v[3];
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void zinv_np_kernel(int n, const double* Ain, long lda,
+__global__ __launch_bounds__(1024) void zinv_np_kernel(int n, const double* Ain, long lda,
                                                       long sA, double* Out, long ldo, long sO,
                                                       int* info) {
   typedef typename Cx<T>::t C2;
@@ -543,7 +539,7 @@ __global__ __launch_bounds__(256) void zinv_np_kernel(int n, const double* Ain, 
   const long b = blockIdx.x;
   const C2* A = reinterpret_cast<const C2*>(Ain) + b * sA;
   float amax = 0.f;
-  for (int e = tid; e < 64 * 64; e += 256) {
+  for (int e = tid; e < 64 * 64; e += 1024) {
     const int r = e & 63, c = e >> 6;
     const C2 v = (r < n && c < n) ? A[r + lda * c] : Cx<T>::mk(r == c ? 1 : 0, 0);
     Ms[c * LD + r] = v;
@@ -568,7 +564,11 @@ __global__ __launch_bounds__(256) void zinv_np_kernel(int n, const double* Ain, 
         C2 rk[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) rk[q] = shfl_c<T>(v[q], k + 16 * c0);
-        const C2 vk = pick4c<T>(v, k >> 2);
+        // column k's entry of this lane's row: slot k / 4 of lane i + 16 (k % 4)
+        C2 vk = v[0];
+#pragma unroll
+        for (int q = 1; q < 4; ++q)
+          if ((k >> 2) == q) vk = v[q];
         const C2 cik = shfl_c<T>(vk, i + 16 * (k & 3));
         const C2 pk = shfl_c<T>(vk, k + 16 * (k & 3));
         bad = bad || !(cabs1(pk) > 0) || !isfinite((double)pk.x) || !isfinite((double)pk.y);
@@ -586,8 +586,8 @@ __global__ __launch_bounds__(256) void zinv_np_kernel(int n, const double* Ain, 
       if (bad) s_bad = 1;
     }
     __syncthreads();
-    // Q (64 x 16) and X (16 x 64)
-    for (int e = tid; e < 64 * 16; e += 256) {
+    // Q (64 x 16) and X (16 x 64): one entry of each per thread
+    for (int e = tid; e < 64 * 16; e += 1024) {
       const int r = e & 63, j = e >> 6;
       const int ir = r - k0;
       C2 q = Cx<T>::mk(0, 0);
@@ -604,16 +604,16 @@ __global__ __launch_bounds__(256) void zinv_np_kernel(int n, const double* Ain, 
       Xs[t * 64 + c] = (jc >= 0 && jc < 16) ? Cx<T>::mk(jc == t ? 1 : 0, 0) : Ms[c * LD + k0 + t];
     }
     __syncthreads();
-    // P <- (rows K and columns K zeroed) + Q X: thread row r = lane, columns w + 4 q
+    // P <- (rows K and columns K zeroed) + Q X: thread row r = lane, columns w + 16 q
     {
       const int r = lane, w = tid >> 6;
       const bool rK = r >= k0 && r < k0 + 16;
       C2 qr[16];
 #pragma unroll
       for (int t = 0; t < 16; ++t) qr[t] = Qs[t * 64 + r];
-#pragma unroll 4
-      for (int q = 0; q < 16; ++q) {
-        const int c = w + 4 * q;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = w + 16 * q;
         const bool cK = c >= k0 && c < k0 + 16;
         C2 acc = (rK || cK) ? Cx<T>::mk(0, 0) : Ms[c * LD + r];
 #pragma unroll
@@ -626,7 +626,7 @@ __global__ __launch_bounds__(256) void zinv_np_kernel(int n, const double* Ain, 
   C2* O = reinterpret_cast<C2*>(Out) + b * sO;
   const float lim = 1e12f * fmaxf(s_max, 1e-30f);
   bool grown = false;
-  for (int e = tid; e < n * n; e += 256) {
+  for (int e = tid; e < n * n; e += 1024) {
     const int r = e % n, c = e / n;
     const C2 v = Ms[c * LD + r];
     grown |= !((float)cabs1(v) <= lim);
@@ -654,10 +654,10 @@ void zinv_blockpivot(int n, int batch, double* A, long lda, long sA, int* info, 
     // the diagonal block's inverse (16 x 16 blocks as its pivots)
     double* Ablk = A + (c64 ? 1 : 2) * (size_t)(k0 + lda * (long)k0);
     if (c64)
-      hipLaunchKernelGGL(zinv_np_kernel<float>, dim3(batch), dim3(256), 0, st, nb, Ablk, lda,
+      hipLaunchKernelGGL(zinv_np_kernel<float>, dim3(batch), dim3(1024), 0, st, nb, Ablk, lda,
                          sA, Pinv, nb, (long)nb * nb, info);
     else
-      hipLaunchKernelGGL(zinv_np_kernel<double>, dim3(batch), dim3(256), 0, st, nb, Ablk, lda,
+      hipLaunchKernelGGL(zinv_np_kernel<double>, dim3(batch), dim3(1024), 0, st, nb, Ablk, lda,
                          sA, Pinv, nb, (long)nb * nb, info);
     HPS_LAUNCH_CHECK();
     GemmDesc g;
