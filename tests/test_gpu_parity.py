@@ -340,6 +340,19 @@ def test_large_interfaces_polynomial_reproduction():
     assert rel(u, cs.exact) < 1e-10
 
 
+def test_largest_leaf_grid_polynomial_reproduction():
+    """256 x 256 leaves (2^16, the most a domain takes) at p = 4: the leaf sweeps of the
+    solve cover 65536 leaves, more than one launch's grid y extent, and run in slices;
+    a polynomial of degree 3 must come back to round-off."""
+    _say("256x256 leaves, p=4, polynomial")
+    cs = Case(256, 256, 4, 3.0, rhs="polynomial", nrhs=2, seed=3)
+    f = cs.gpu_build()
+    u = cs.gpu_solve(f)
+    _say("256x256 poly rel", rel(u, cs.exact))
+    assert rel(u, cs.exact) < 1e-9
+    f.free()
+
+
 def test_config2_manufactured_solution(config2):
     cs, f = config2
     mf = Case(64, 64, 16, 100.0, c="bump", rhs="manufactured", nrhs=3, seed=11)
