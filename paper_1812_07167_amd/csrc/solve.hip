@@ -2,18 +2,19 @@
 // batch of stored operators A (M x K, complex) and a block of nrhs right-hand sides.
 //
 // This is HBM-bound: every operator entry is read once per pass and used for all (up to
-// 64) right-hand sides of the pass.  The product runs on the FP64 matrix cores: a wave
-// owns TW tiles of 16 rows, and each group of 16 right-hand sides is the 16 columns of
-// one MFMA's B operand; NB such groups (NB = 1, 2 or 4) share every operator load.  The
-// right-hand side block is staged through LDS in chunks of KC rows (each lane reads one
-// complex value per 4-deep k step, so there are no broadcast reads); operator entries
-// go from global memory straight into the A operand registers.  A
-// complex product takes three real MFMAs (the 3M method: ArXr, AiXi and
+// 64) right-hand sides of the pass.  The product runs on the matrix cores: a wave owns
+// 16 rows, and each group of 16 right-hand sides is the 16 columns of one MFMA's B
+// operand; NB such groups (NB = 1, 2 or 4) share every operator load.  The right-hand
+// side block is staged through LDS in chunks of 64 (32 for NB = 4) k rows; each lane
+// reads one complex value per 4-deep k step, so there are no broadcast reads.  Operator
+// entries go from memory straight into the A operand registers, through a buffer
+// resource (one 32-bit offset per lane; columns past K read as zero): a wave requests all
+// of its fragments of a chunk before the chunk's right-hand sides are staged, which keeps
+// enough loads in flight to cover the memory latency (one dependent load per step does
+// not).  A complex product takes three real MFMAs (the 3M method: ArXr, AiXi and
 // (Ar + Ai)(Xr + Xi), folded into the real and imaginary parts after the K loop).  A
-// workgroup covers at most 128 rows (TW <= 2, and TW = 1 when NB > 1); registers then
-// allow at least four waves per SIMD.  For
-// short operators the waves of a workgroup split K and add their partial tiles through
-// LDS in a fixed order.
+// workgroup covers at most 64 rows; for short operators its waves split K and add their
+// partial tiles through LDS in a fixed order.
 // Operators with few rows and a long K (the top merges) are also split along K across
 // workgroups; those partial sums are reduced in a fixed order by a second kernel, so
 // results never depend on scheduling.  Two operators of one shape share a launch: applied
@@ -59,24 +60,50 @@ __host__ __device__ inline bool has2(const SkinnyDesc& d) {
 // batch entries of a launch: the second operator's follow the first's
 __host__ __device__ inline int nbatch(const SkinnyDesc& d) { return has2(d) ? 2 * d.batch : d.batch; }
 
-template <class T, int TW, int WK, int NB>
-__global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int nr, int kper,
+// One operator entry through a buffer resource: an offset past the resource's extent
+// reads as zero (the range check takes the per-lane offset; the scalar offset is 0).
+template <class T> struct SkLoad;
+template <> struct SkLoad<double> {
+  static __device__ inline double2 ld(__amdgpu_buffer_rsrc_t r, int off) {
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    const v2 v = __builtin_bit_cast(v2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    return make_double2(v.x, v.y);
+  }
+};
+template <> struct SkLoad<float> {
+  static __device__ inline float2 ld(__amdgpu_buffer_rsrc_t r, int off) {
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    const v2 v = __builtin_bit_cast(v2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    return make_float2(v.x, v.y);
+  }
+};
+
+// buffer resource word 3 of a raw (stride 0) buffer of 32-bit elements on this target
+constexpr int kBufWord3 = 0x00020000;
+
+template <class T, int WK, int NB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB == 1 ? 3 : 2))) void skinny_kernel(SkinnyDesc d, int r0, int nr, int kper,
                                                      double2* partial, long y0) {
   typedef typename Cx<T>::t C2;
   typedef SkMfma<T> MF;
   typedef typename MF::acc acc_t;
   constexpr int WR = 4 / WK;              // row groups of waves
-  constexpr int ROWS = 16 * TW * WR;      // rows per workgroup
+  constexpr int ROWS = 16 * WR;           // rows per workgroup
   constexpr int NC = NRB * NB;            // right-hand sides of the pass
   constexpr int KCX = NB == 4 ? 32 : 64;  // K chunk staged in LDS
-  constexpr int XS_BYTES = KCX * NC * (int)sizeof(C2);
-  constexpr int RED_BYTES = WK > 1 ? (WK - 1) * WR * TW * 2 * NB * 64 * (int)sizeof(acc_t) : 0;
+  constexpr int XLD = NC + 1;             // LDS row pitch (padded: staging writes spread banks)
+  constexpr int NS = KCX / 4 / WK;        // 4-deep k steps of one wave per chunk
+  constexpr int NX = KCX * NC / 256;      // staged right-hand side entries per thread
+  constexpr int XS_BYTES = KCX * XLD * (int)sizeof(C2);
+  constexpr int RED_BYTES = WK > 1 ? (WK - 1) * WR * 2 * NB * 64 * (int)sizeof(acc_t) : 0;
+  static_assert(NX * 256 == KCX * NC, "staging covers the chunk in whole rounds");
   // the staged right-hand sides, and after the K loop the cross-wave partial tiles
   __shared__ __align__(16) char smem[XS_BYTES > RED_BYTES ? XS_BYTES : RED_BYTES];
-  C2 (*Xs)[NC] = reinterpret_cast<C2 (*)[NC]>(smem);
+  C2 (*Xs)[XLD] = reinterpret_cast<C2 (*)[XLD]>(smem);
   acc_t* red = reinterpret_cast<acc_t*>(smem);
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave % WR, kw = wave / WR;
   const int li = lane & 15, lk = lane >> 4;
   const long bb = y0 + blockIdx.y;  // batch entry of the launch
@@ -84,7 +111,7 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
   const long b = two ? bb - d.batch : bb;  // entry of its operator
   const int ks = blockIdx.z;
   const int kbeg = ks * kper, kend = min(d.K, kbeg + kper);
-  const int row0 = blockIdx.x * ROWS + wr * 16 * TW;
+  const int row0 = blockIdx.x * ROWS + wr * 16;
   const C2* A;
   if (d.aper > 0) {
     const int q = (int)(b / d.aper);
@@ -98,92 +125,97 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
   }
   const double2* X = reinterpret_cast<const double2*>(two && d.X2 ? d.X2 : d.X) +
                      (d.xoff ? d.xoff[b] - d.xbase : b * d.sX);
-
-  // rows this lane loads (clamped into the operator; rows past M are never written)
-  long arow[TW];
-#pragma unroll
-  for (int t = 0; t < TW; ++t) arow[t] = min(row0 + 16 * t + li, d.M - 1);
+  // The entry's operator as a buffer of lda x K entries: a column past K reads as zero.
+  // A lane's byte offset is its row (rows past M repeat the last, never written) at its
+  // k of a step; consecutive 4-deep steps are kstep bytes apart.  The host keeps every
+  // offset below 2^31.
+  const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<C2*>(A), (short)0, (int)((long)d.lda * d.K * (long)sizeof(C2)), kBufWord3);
+  const int aoff = (min(row0 + li, d.M - 1) + d.lda * lk) * (int)sizeof(C2);
+  const int kstep = 4 * d.lda * (int)sizeof(C2);
 
   // 3M: accR, accX, accI hold ArXr, AiXi, (Ar + Ai)(Xr + Xi) until after the K loop
-  acc_t accR[TW][NB], accI[TW][NB], accX[TW][NB];
+  acc_t accR[NB], accI[NB], accX[NB];
 #pragma unroll
-  for (int t = 0; t < TW; ++t)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      accR[t][j] = acc_t{0, 0, 0, 0};
-      accI[t][j] = acc_t{0, 0, 0, 0};
-      accX[t][j] = acc_t{0, 0, 0, 0};
-    }
+  for (int j = 0; j < NB; ++j) {
+    accR[j] = acc_t{0, 0, 0, 0};
+    accI[j] = acc_t{0, 0, 0, 0};
+    accX[j] = acc_t{0, 0, 0, 0};
+  }
   for (int k0 = kbeg; k0 < kend; k0 += KCX) {
     const int kc = min(KCX, kend - k0);
-    __syncthreads();
-    for (int e = tid; e < KCX * NC; e += 256) {
+    const int nsteps = (kc + 3) >> 2;
+    // The chunk's right-hand sides, then every operator fragment this wave takes from
+    // the chunk, are requested before anything waits, so a lane has NX + NS loads in
+    // flight.  The loads are unconditional so that the waits can count them: a
+    // right-hand side entry past the chunk is read at a clamped address and zeroed,
+    // operator steps past the chunk are loaded but never used.
+    double2 xr[NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      const int e = tid + 256 * i;
       const int k = e % KCX, r = e / KCX;
-      const double2 xv = (k < kc && r < nr) ? X[(k0 + k) + d.ldx * (long)(r0 + r)] : cmk(0, 0);
-      Xs[k][r] = Cx<T>::mk((T)xv.x, (T)xv.y);
+      const bool ok = k < kc && r < nr;
+      xr[i] = X[ok ? (k0 + k) + d.ldx * (long)(r0 + r) : 0];
+    }
+    C2 af[NS];
+    const int c0 = (k0 >> 2) + kw;  // first step of this wave in the chunk
+#pragma unroll
+    for (int i = 0; i < NS; ++i) af[i] = SkLoad<T>::ld(ra, aoff + (c0 + WK * i) * kstep);
+    __syncthreads();  // the previous chunk's right-hand sides have been read
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      const int e = tid + 256 * i;
+      const int k = e % KCX, r = e / KCX;
+      const bool ok = k < kc && r < nr;
+      Xs[k][r] = ok ? Cx<T>::mk((T)xr[i].x, (T)xr[i].y) : Cx<T>::mk(0, 0);
     }
     __syncthreads();
-    const int nsteps = (kc + 3) >> 2;
-#pragma unroll 2
-    for (int s = kw; s < nsteps; s += WK) {
-      const int kl = 4 * s + lk;
-      // k past the chunk meets a zero right-hand side; clamp its address into A
-      const long kg = min(k0 + kl, d.K - 1);
-      C2 bx[NB];
-      T bs[NB];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const int st = kw + WK * i;
+      if (st >= nsteps) break;
+      const int kl = 4 * st + lk;
+      const C2 a = af[i];
+      const T as = a.x + a.y;
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
-        bx[j] = Xs[kl][NRB * j + li];
-        bs[j] = bx[j].x + bx[j].y;
-      }
-#pragma unroll
-      for (int t = 0; t < TW; ++t) {
-        const C2 a = A[arow[t] + d.lda * kg];
-        const T as = a.x + a.y;
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          accR[t][j] = MF::op(a.x, bx[j].x, accR[t][j]);
-          accX[t][j] = MF::op(a.y, bx[j].y, accX[t][j]);
-          accI[t][j] = MF::op(as, bs[j], accI[t][j]);
-        }
+        const C2 bx = Xs[kl][NRB * j + li];
+        accR[j] = MF::op(a.x, bx.x, accR[j]);
+        accX[j] = MF::op(a.y, bx.y, accX[j]);
+        accI[j] = MF::op(as, bx.x + bx.y, accI[j]);
       }
     }
   }
 #pragma unroll
-  for (int t = 0; t < TW; ++t)
+  for (int j = 0; j < NB; ++j)
 #pragma unroll
-    for (int j = 0; j < NB; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const T t1 = accR[t][j][v], t2 = accX[t][j][v];
-        accR[t][j][v] = t1 - t2;
-        accI[t][j][v] = accI[t][j][v] - t1 - t2;
-      }
+    for (int v = 0; v < 4; ++v) {
+      const T t1 = accR[j][v], t2 = accX[j][v];
+      accR[j][v] = t1 - t2;
+      accI[j][v] = accI[j][v] - t1 - t2;
+    }
   if (WK > 1) {
     // waves kw > 0 hand their tiles to the kw = 0 wave of their row group (through the
     // LDS the staged right-hand sides used: every wave is past its last read of them)
     __syncthreads();
     if (kw > 0) {
 #pragma unroll
-      for (int t = 0; t < TW; ++t)
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          const int base = ((((kw - 1) * WR + wr) * TW + t) * NB + j) * 2;
-          red[(base + 0) * 64 + lane] = accR[t][j];
-          red[(base + 1) * 64 + lane] = accI[t][j];
-        }
+      for (int j = 0; j < NB; ++j) {
+        const int base = ((((kw - 1) * WR + wr)) * NB + j) * 2;
+        red[(base + 0) * 64 + lane] = accR[j];
+        red[(base + 1) * 64 + lane] = accI[j];
+      }
     }
     __syncthreads();
     if (kw > 0) return;
     for (int q = 1; q < WK; ++q)
 #pragma unroll
-      for (int t = 0; t < TW; ++t)
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          const int base = ((((q - 1) * WR + wr) * TW + t) * NB + j) * 2;
-          accR[t][j] += red[(base + 0) * 64 + lane];
-          accI[t][j] += red[(base + 1) * 64 + lane];
-        }
+      for (int j = 0; j < NB; ++j) {
+        const int base = ((((q - 1) * WR + wr)) * NB + j) * 2;
+        accR[j] += red[(base + 0) * 64 + lane];
+        accI[j] += red[(base + 1) * 64 + lane];
+      }
   }
   if (partial) {
     // [ks][bb][rhs of the pass][i]
@@ -193,12 +225,10 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
       if (rhs >= nr) continue;
       double2* P = partial + (((long)ks * nbatch(d) + bb) * NC + rhs) * d.M;
 #pragma unroll
-      for (int t = 0; t < TW; ++t)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = row0 + 16 * t + MF::row(lk, v);
-          if (i < d.M) P[i] = cmk(accR[t][j][v], accI[t][j][v]);
-        }
+      for (int v = 0; v < 4; ++v) {
+        const int i = row0 + MF::row(lk, v);
+        if (i < d.M) P[i] = cmk(accR[j][v], accI[j][v]);
+      }
     }
     return;
   }
@@ -213,18 +243,16 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyDesc d, int r0, int n
     const int rhs = NRB * j + li;
     if (rhs >= nr) continue;
 #pragma unroll
-    for (int t = 0; t < TW; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = row0 + 16 * t + MF::row(lk, v);
-        if (i >= d.M) continue;
-        const long ci = crow ? crow[i] : i;
-        double2 val = cmk(d.alpha * accR[t][j][v], d.alpha * accI[t][j][v]);
-        double2* p = C + ci + d.ldc * (long)(r0 + rhs);
-        if (C0) val = cadd(val, C0[i + d.ld0 * (long)(r0 + rhs)]);
-        else if (d.accumulate) val = cadd(val, *p);
-        *p = val;
-      }
+    for (int v = 0; v < 4; ++v) {
+      const int i = row0 + MF::row(lk, v);
+      if (i >= d.M) continue;
+      const long ci = crow ? crow[i] : i;
+      double2 val = cmk(d.alpha * accR[j][v], d.alpha * accI[j][v]);
+      double2* p = C + ci + d.ldc * (long)(r0 + rhs);
+      if (C0) val = cadd(val, C0[i + d.ld0 * (long)(r0 + rhs)]);
+      else if (d.accumulate) val = cadd(val, *p);
+      *p = val;
+    }
   }
 }
 
@@ -264,20 +292,14 @@ __global__ void skinny_reduce_kernel(SkinnyDesc d, int r0, int nr, int nc, int n
   }
 }
 
-// rows covered by one workgroup: by the operator's height, and for few tall operators
-// (the top merge levels) at most 64, so that the row blocks (times the K splits below)
-// spread the matrix-core work over the device instead of a few compute units; at most
-// 64 when a pass has several column blocks (TW = 1)
-int block_rows(const SkinnyDesc& d, int nb) {
-  int rows = d.M <= 16 ? 16 : d.M <= 32 ? 32 : d.M <= 64 ? 64 : 128;
-  while (rows > 64 && (nb > 1 || (long)cdiv(d.M, rows) * nbatch(d) < 512)) rows /= 2;
-  return rows;
-}
+// rows covered by one workgroup: by the operator's height, at most 64 (four waves of
+// 16 rows; shorter operators split K across the waves instead)
+int block_rows(const SkinnyDesc& d) { return d.M <= 16 ? 16 : d.M <= 32 ? 32 : 64; }
 
 // K is split across workgroups when the row blocks x batch cannot fill the device.
 // Returns the number of splits and the K range per split (a multiple of KC).
-int split_plan(const SkinnyDesc& d, int nb, int* kper_out) {
-  const int tiles = cdiv(d.M, block_rows(d, nb));
+int split_plan(const SkinnyDesc& d, int* kper_out) {
+  const int tiles = cdiv(d.M, block_rows(d));
   int nsplit = 1;
   const long blocks = (long)tiles * nbatch(d);
   if (blocks < 1024 && d.K >= 2 * KC) {
@@ -297,17 +319,16 @@ int split_plan(const SkinnyDesc& d, int nb, int* kper_out) {
 // launches of batches beyond the grid's y limit take consecutive slices of it
 constexpr long kGridY = 65535;
 
-template <class T, int TW, int WK, int NB>
+template <class T, int WK, int NB>
 void run_chunk(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
-  const int tiles = cdiv(d.M, 16 * TW * (4 / WK));
+  const int tiles = cdiv(d.M, 16 * (4 / WK));
   int kper = 0;
-  const int nsplit = split_plan(d, NB, &kper);
+  const int nsplit = split_plan(d, &kper);
   const long nbt = nbatch(d);
   if (nsplit == 1) {
     for (long y0 = 0; y0 < nbt; y0 += kGridY) {
-      hipLaunchKernelGGL((skinny_kernel<T, TW, WK, NB>),
-                         dim3(tiles, std::min(kGridY, nbt - y0), 1), dim3(256), 0, st, d, r0,
-                         nr, d.K, (double2*)nullptr, y0);
+      hipLaunchKernelGGL((skinny_kernel<T, WK, NB>), dim3(tiles, std::min(kGridY, nbt - y0), 1),
+                         dim3(256), 0, st, d, r0, nr, d.K, (double2*)nullptr, y0);
       HPS_LAUNCH_CHECK();
     }
     return;
@@ -315,7 +336,7 @@ void run_chunk(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
   if (!d.work) throw Error(1, "zgemm_skinny: split-K needs a workspace");
   double2* part = static_cast<double2*>(d.work);
   for (long y0 = 0; y0 < nbt; y0 += kGridY) {
-    hipLaunchKernelGGL((skinny_kernel<T, TW, WK, NB>),
+    hipLaunchKernelGGL((skinny_kernel<T, WK, NB>),
                        dim3(tiles, std::min(kGridY, nbt - y0), nsplit), dim3(256), 0, st, d, r0,
                        nr, kper, part, y0);
     HPS_LAUNCH_CHECK();
@@ -328,11 +349,10 @@ void run_chunk(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
 
 template <class T, int NB>
 void run_pass_nb(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
-  switch (block_rows(d, NB)) {
-    case 16: run_chunk<T, 1, 4, NB>(d, r0, nr, st); break;
-    case 32: run_chunk<T, 1, 2, NB>(d, r0, nr, st); break;
-    case 64: run_chunk<T, 1, 1, NB>(d, r0, nr, st); break;
-    default: run_chunk<T, NB == 1 ? 2 : 1, 1, NB>(d, r0, nr, st); break;
+  switch (block_rows(d)) {
+    case 16: run_chunk<T, 4, NB>(d, r0, nr, st); break;
+    case 32: run_chunk<T, 2, NB>(d, r0, nr, st); break;
+    default: run_chunk<T, 1, NB>(d, r0, nr, st); break;
   }
 }
 
@@ -354,7 +374,7 @@ void run_pass(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
 size_t pass_work_bytes(const SkinnyDesc& d, int nr) {
   const int nb = nb_of(nr);
   int kper = 0;
-  const int nsplit = split_plan(d, nb, &kper);
+  const int nsplit = split_plan(d, &kper);
   if (nsplit == 1) return 0;
   return (size_t)nsplit * nbatch(d) * NRB * nb * d.M * sizeof(double2);
 }
@@ -381,6 +401,10 @@ void zgemm_skinny(const SkinnyDesc& d, hipStream_t st) {
         throw Error(1, "zgemm_skinny: missing operator of a tabled factor");
   }
   if (d.K <= 0) throw Error(1, "zgemm_skinny: K must be positive");
+  // operator byte offsets (rows, steps past K by up to one chunk) stay below 2^31
+  const long esz = d.a_c64 ? 8 : 16;
+  if (d.lda < d.M || ((long)d.lda * (d.K + 2 * KC) + d.M) * esz >= (1L << 31))
+    throw Error(1, "zgemm_skinny: operator of more than 2 GiB or lda below M");
   // passes of up to 64 right-hand sides; the last takes the rest
   constexpr int NCMAX = NRB * MAXNB;
   for (int r0 = 0; r0 < d.nrhs; r0 += NCMAX) run_pass(d, r0, std::min(NCMAX, d.nrhs - r0), st);
