@@ -10,9 +10,12 @@
 // matrices on the leaf's full tensor grid; the four corners are never read (interior
 // rows and normal rows only touch nodes off the corners).
 //
-// One workgroup per (leaf, right-hand side): the leaf's values go into LDS on the full
-// p x p grid; interior rows and the leaf's own F on its boundary come from there, the
-// neighbour's G from the neighbour's values in global memory (p values per node).
+// Two passes.  One workgroup per (leaf, right-hand side) puts the leaf's values into LDS
+// on the full p x p grid and writes the interior rows, and the outward normal derivative
+// of its own interpolant at every edge node (into the boundary rows, as scratch).  Then
+// one thread per shared edge node (the leaf whose east or north side it lies on owns the
+// pair) or root-boundary node combines those derivatives with the edge values into the
+// impedance rows of both leaves; each boundary row is read and written by one thread.
 #include "kernels.hpp"
 
 namespace hps {
@@ -37,6 +40,7 @@ template <class V>
 __device__ inline double2 normal_deriv(int side, int idx, int p, const double* Dx1,
                                        const double* Dy1, V val) {
   double2 acc = cmk(0, 0);
+#pragma unroll 4
   for (int k = 0; k < p; ++k) {
     double2 x;
     double w;
@@ -61,10 +65,9 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualDesc d) {
   const int tid = threadIdx.x;
   const int lg = blockIdx.x, r = blockIdx.y;   // leaf of the launch, right-hand side
   const int nl1 = d.nx * d.ny;
-  const int prob = lg / nl1, l = lg % nl1;      // problem, leaf within it (grid order)
+  const int prob = lg / nl1;                    // problem of the leaf
   const int nleaf = nl1 * d.nprob;              // leaves of the launch
-  const int ix = l % d.nx, iy = l / d.nx;
-  const double kappa = d.prm[4 * prob], eta_re = d.prm[4 * prob + 1], eta_im = d.prm[4 * prob + 2];
+  const double kappa = d.prm[4 * prob];
   for (int e = tid; e < 4 * P * P; e += 256) sD[e / (P * P)][e % (P * P)] = d.D[e];
   const double2* u = reinterpret_cast<const double2*>(d.u) + (long)r * nleaf * N;
   const double2* ul = u + (long)lg * N;
@@ -83,6 +86,8 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualDesc d) {
   for (int e = tid; e < NI; e += 256) {
     const int i = e % M + 1, j = e / M + 1;
     double2 lap = cmk(0, 0);
+    // (partly unrolled: a full unroll holds every operand at once and halves occupancy)
+#pragma unroll 4
     for (int k = 0; k < P; ++k) {
       const double2 a = Ug[k + P * j], b = Ug[i + P * k];
       lap.x += Dxx[i + P * k] * a.x + Dyy[j + P * k] * b.x;
@@ -95,51 +100,78 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualDesc d) {
     if (d.s) b = reinterpret_cast<const double2*>(d.s)[(long)r * nleaf * NI + (long)lg * NI + e];
     reinterpret_cast<double2*>(d.rs)[r * d.rs_rhs + lg * d.rs_leaf + e] = csub(b, Au);
   }
-  // boundary rows
-  const int nt = 2 * (d.nx + d.ny) * M;
+  // boundary rows: the leaf's own outward normal derivative N u_l, combined below
+  double2* rb = reinterpret_cast<double2*>(d.rb) + r * d.rb_rhs + lg * d.rb_leaf;
   for (int e = tid; e < NB; e += 256) {
-    const int side = e / M, q = e % M, idx = q + 1;
     auto own = [&](int i, int j) { return Ug[i + P * j]; };
-    const double2 nd = normal_deriv(side, idx, P, Dx1, Dy1, own);
-    const double2 ue = ul[e];
-    // F u = N u + i eta u
-    const double2 Fu = cmk(nd.x - eta_im * ue.x - eta_re * ue.y,
-                           nd.y + eta_re * ue.x - eta_im * ue.y);
-    // neighbour across this side, and the root-boundary position when there is none
-    int jx = ix, jy = iy, nside = 0, root = -1;
+    rb[e] = normal_deriv(e / M, e % M + 1, P, Dx1, Dy1, own);
+  }
+}
+
+// Impedance rows from the normal derivatives the leaf pass left in rb: entry e of leaf l
+// on side `side`.  A root-boundary node gives t - F u_l (F = N + i eta); a node shared
+// with leaf l' (its entry e') gives jump - (F_l u_l + G_l' u_l') (G = N - i eta) for l
+// and the mirror image for l'.  Threads of west and south entries with a neighbour do
+// nothing: the neighbour's east or north thread writes both rows.
+__global__ __launch_bounds__(256) void residual_edge_kernel(ResidualDesc d, int M) {
+  const int NB = 4 * M;
+  const int nl1 = d.nx * d.ny;
+  const long nleaf = (long)nl1 * d.nprob;
+  const long tot = (long)d.nrhs * nleaf * NB;
+  const int nt = 2 * (d.nx + d.ny) * M;
+  for (long g = (long)blockIdx.x * 256 + threadIdx.x; g < tot; g += (long)gridDim.x * 256) {
+    const int e = (int)(g % NB);
+    const long lg = (g / NB) % nleaf;
+    const int r = (int)(g / (NB * nleaf));
+    const int prob = (int)(lg / nl1), l = (int)(lg % nl1);
+    const int ix = l % d.nx, iy = l / d.nx;
+    const int side = e / M, q = e % M;
+    int root = -1;
     switch (side) {
-      case 0: jy = iy - 1; nside = 2; if (iy == 0) root = ix * M + q; break;
-      case 1: jx = ix + 1; nside = 3; if (ix == d.nx - 1) root = d.nx * M + iy * M + q; break;
-      case 2: jy = iy + 1; nside = 0; if (iy == d.ny - 1) root = (d.nx + d.ny) * M + ix * M + q; break;
-      default: jx = ix - 1; nside = 1; if (ix == 0) root = (2 * d.nx + d.ny) * M + iy * M + q; break;
+      case 0: if (iy == 0) root = ix * M + q; break;
+      case 1: if (ix == d.nx - 1) root = d.nx * M + iy * M + q; break;
+      case 2: if (iy == d.ny - 1) root = (d.nx + d.ny) * M + ix * M + q; break;
+      default: if (ix == 0) root = (2 * d.nx + d.ny) * M + iy * M + q; break;
     }
-    double2* rb = reinterpret_cast<double2*>(d.rb) + r * d.rb_rhs + lg * d.rb_leaf;
-    const long trow = ((long)prob * d.nrhs + r) * nt;  // t, rt: [problem][rhs][nt]
+    if (root < 0 && (side == 0 || side == 3)) continue;  // written by the neighbour
+    const double eta_re = d.prm[4 * prob + 1], eta_im = d.prm[4 * prob + 2];
+    // F v = N v + i eta v and G v = N v - i eta v at one node
+    auto Fv = [&](double2 nd, double2 v) {
+      return cmk(nd.x - eta_im * v.x - eta_re * v.y, nd.y + eta_re * v.x - eta_im * v.y);
+    };
+    auto Gv = [&](double2 nd, double2 v) {
+      return cmk(nd.x + eta_im * v.x + eta_re * v.y, nd.y - eta_re * v.x + eta_im * v.y);
+    };
+    const double2* u = reinterpret_cast<const double2*>(d.u) + (long)r * nleaf * (NB + M * M);
+    double2* rb = reinterpret_cast<double2*>(d.rb) + r * d.rb_rhs;
+    const double2 ndl = rb[lg * d.rb_leaf + e];
+    const double2 ul = u[lg * (NB + M * M) + e];
     if (root >= 0) {
+      const long trow = ((long)prob * d.nrhs + r) * nt;  // t, rt: [problem][rhs][nt]
       double2 tv = cmk(0, 0);
       if (d.t) tv = reinterpret_cast<const double2*>(d.t)[trow + root];
-      const double2 res = csub(tv, Fu);
+      const double2 res = csub(tv, Fv(ndl, ul));
       if (d.rt) {
         reinterpret_cast<double2*>(d.rt)[trow + root] = res;
-        rb[e] = cmk(0, 0);
+        rb[lg * d.rb_leaf + e] = cmk(0, 0);
       } else {
-        rb[e] = res;
+        rb[lg * d.rb_leaf + e] = res;
       }
-    } else {
-      const double2* un = u + ((long)prob * nl1 + jy * d.nx + jx) * N;
-      auto nbr = [&](int i, int j) {
-        const int pos = node_pos(i, j, P);
-        return pos < 0 ? cmk(0, 0) : un[pos];
-      };
-      const double2 ndn = normal_deriv(nside, idx, P, Dx1, Dy1, nbr);
-      const double2 un_e = un[nside * M + q];
-      // G u' = N' u' - i eta u'
-      const double2 Gu = cmk(ndn.x + eta_im * un_e.x + eta_re * un_e.y,
-                             ndn.y - eta_re * un_e.x + eta_im * un_e.y);
-      double2 jv = cmk(0, 0);
-      if (d.jmp) jv = reinterpret_cast<const double2*>(d.jmp)[(long)r * nleaf * NB + (long)lg * NB + e];
-      rb[e] = csub(jv, cadd(Fu, Gu));
+      continue;
     }
+    // east side: the neighbour's west entry q; north side: the neighbour's south entry q
+    const long ln = (long)prob * nl1 + (side == 1 ? l + 1 : l + d.nx);
+    const int en = (side == 1 ? 3 : 0) * M + q;
+    const double2 ndn = rb[ln * d.rb_leaf + en];
+    const double2 un = u[ln * (NB + M * M) + en];
+    double2 jl = cmk(0, 0), jn = cmk(0, 0);
+    if (d.jmp) {
+      const double2* jp = reinterpret_cast<const double2*>(d.jmp) + (long)r * nleaf * NB;
+      jl = jp[lg * NB + e];
+      jn = jp[ln * NB + en];
+    }
+    rb[lg * d.rb_leaf + e] = csub(jl, cadd(Fv(ndl, ul), Gv(ndn, un)));
+    rb[ln * d.rb_leaf + en] = csub(jn, cadd(Fv(ndn, un), Gv(ndl, ul)));
   }
 }
 
@@ -184,6 +216,7 @@ __global__ __launch_bounds__(256) void norms_kernel(long len, int ncol, const do
 void residual(const ResidualDesc& d, int nrhs, hipStream_t st) {
   if (nrhs <= 0) return;
   if (nrhs > 65535) throw Error(1, "residual: too many right-hand sides");
+  if (nrhs != d.nrhs) throw Error(1, "residual: right-hand side count differs from the layout");
   const dim3 grid(d.nx * d.ny * d.nprob, nrhs);
   switch (d.p) {
 #define HPS_RES_CASE(PP) \
@@ -194,6 +227,9 @@ void residual(const ResidualDesc& d, int nrhs, hipStream_t st) {
 #undef HPS_RES_CASE
     default: throw Error(1, "residual: unsupported p");
   }
+  HPS_LAUNCH_CHECK();
+  const long tot = (long)nrhs * d.nx * d.ny * d.nprob * 4 * (d.p - 2);
+  hipLaunchKernelGGL(residual_edge_kernel, dim3(grid1d(tot)), dim3(256), 0, st, d, d.p - 2);
   HPS_LAUNCH_CHECK();
 }
 
