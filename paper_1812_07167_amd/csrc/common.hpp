@@ -77,6 +77,14 @@ __host__ __device__ inline float2 crcp_fast(float2 a) {
   const float d = 1.0f / fmaf(a.x, a.x, a.y * a.y);
   return make_float2(a.x * d, -a.y * d);
 }
+__host__ __device__ inline float2 crcp_pivot(float2 a) {
+  const float n2 = fmaf(a.x, a.x, a.y * a.y);
+  if (n2 > 1e-35f && n2 < 1e35f) {
+    const float d = 1.0f / n2;
+    return make_float2(a.x * d, -a.y * d);
+  }
+  return crcp(a);
+}
 __host__ __device__ inline float cabs1(float2 a) { return fabsf(a.x) + fabsf(a.y); }
 
 // complex type of a real element type

@@ -513,16 +513,11 @@ __global__ __launch_bounds__(256) void zinv_bstep_kernel(int n, int nb, int k0, 
 // Inverse of the n x n diagonal block P of a matrix (n <= 64) with its own 16 x 16
 // diagonal blocks as pivots: one workgroup of 1024 threads (16 waves) per matrix, P in
 // LDS; the block transformations and updates spread over all of them.  Per
-// block K of 16 columns, the first wave inverts P[K, K] in registers (lane l holds row
-// l % 16, columns l / 16 + 4 q; row and column k are exchanged by cross-lane reads), then
+// block K of 16 columns, the first wave inverts P[K, K] by Gauss-Jordan in LDS, then
 // Q = -P[:, K] P[K, K]^{-1} (rows K: P[K, K]^{-1}) and X = P[K, :] (identity on K), and
 // P <- (rows K and columns K zeroed) + Q X.  A zero or non-finite pivot, or an entry of
 // the inverse beyond 1e12 times the largest of P, sets info (the build then repeats with
 // full pivoting).
-template <class T>
-__device__ inline typename Cx<T>::t shfl_c(typename Cx<T>::t v, int src) {
-  return Cx<T>::mk(__shfl(v.x, src), __shfl(v.y, src));
-}
 template <class T>
 __global__ __launch_bounds__(1024) void zinv_np_kernel(int n, const double* Ain, long lda,
                                                       long sA, double* Out, long ldo, long sO,
@@ -554,35 +549,38 @@ __global__ __launch_bounds__(1024) void zinv_np_kernel(int n, const double* Ain,
 #pragma unroll 1
   for (int k0 = 0; k0 < 64; k0 += 16) {
     if (tid < 64) {
+      // Gauss-Jordan on P[K, K] in Pk (LDS): lane l owns row i = l % 16, columns
+      // c0 + 4 q (c0 = l / 16).  A step reads the pivot row, the lane's column-k entry and
+      // the pivot with broadcast LDS reads, all issued together, and writes the lane's
+      // four entries back; one wave, so its LDS accesses stay in program order.
       const int i = lane & 15, c0 = lane >> 4;
-      C2 v[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] = Ms[(k0 + c0 + 4 * q) * LD + k0 + i];
+      for (int q = 0; q < 4; ++q) Pk[(c0 + 4 * q) * 16 + i] = Ms[(k0 + c0 + 4 * q) * LD + k0 + i];
       bool bad = false;
 #pragma unroll 1
       for (int k = 0; k < 16; ++k) {
-        C2 rk[4];
+        C2 v[4], rk[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) rk[q] = shfl_c<T>(v[q], k + 16 * c0);
-        // column k's entry of this lane's row: slot k / 4 of lane i + 16 (k % 4)
-        C2 vk = v[0];
-#pragma unroll
-        for (int q = 1; q < 4; ++q)
-          if ((k >> 2) == q) vk = v[q];
-        const C2 cik = shfl_c<T>(vk, i + 16 * (k & 3));
-        const C2 pk = shfl_c<T>(vk, k + 16 * (k & 3));
+        for (int q = 0; q < 4; ++q) {
+          v[q] = Pk[(c0 + 4 * q) * 16 + i];
+          rk[q] = Pk[(c0 + 4 * q) * 16 + k];
+        }
+        const C2 cik = Pk[k * 16 + i];
+        const C2 pk = Pk[k * 16 + k];
         bad = bad || !(cabs1(pk) > 0) || !isfinite((double)pk.x) || !isfinite((double)pk.y);
-        const C2 ip = crcp(pk);
+        const C2 ip = crcp_pivot(pk);
         const C2 f = cmul(cik, ip);
+        __builtin_amdgcn_wave_barrier();  // every lane's reads of the step precede the writes
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int j = c0 + 4 * q;
-          if (i == k) v[q] = (j == k) ? ip : cmul(rk[q], ip);
-          else v[q] = (j == k) ? Cx<T>::mk(-f.x, -f.y) : csub(v[q], cmul(f, rk[q]));
+          C2 w;
+          if (i == k) w = (j == k) ? ip : cmul(rk[q], ip);
+          else w = (j == k) ? Cx<T>::mk(-f.x, -f.y) : csub(v[q], cmul(f, rk[q]));
+          Pk[j * 16 + i] = w;
         }
+        __builtin_amdgcn_wave_barrier();  // and the next step's reads follow them
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) Pk[(c0 + 4 * q) * 16 + i] = v[q];
       if (bad) s_bad = 1;
     }
     __syncthreads();
