@@ -83,7 +83,7 @@ constexpr int kBufWord3 = 0x00020000;
 
 template <class T, int WK, int NB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB == 1 ? 3 : 2))) void skinny_kernel(SkinnyDesc d, int r0, int nr, int kper,
-                                                     double2* partial, long y0) {
+                                                     double2* partial, long y0, bool xcd) {
   typedef typename Cx<T>::t C2;
   typedef SkMfma<T> MF;
   typedef typename MF::acc acc_t;
@@ -106,12 +106,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB == 1 ? 3
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave % WR, kw = wave / WR;
   const int li = lane & 15, lk = lane >> 4;
-  const long bb = y0 + blockIdx.y;  // batch entry of the launch
+  // Workgroups are dealt to the 8 XCDs in turn by their linear index.  With xcd set
+  // (launches without a K split), the index is remapped so that all row blocks of one
+  // batch entry run on the same XCD and its right-hand sides are fetched into one L2;
+  // the grid then has the batch rounded up to a multiple of 8 and extra entries exit.
+  int tile = blockIdx.x;
+  long bb = y0 + blockIdx.y;  // batch entry of the launch
+  if (xcd) {
+    const long L = blockIdx.x + (long)gridDim.x * blockIdx.y;
+    const long slot = L >> 3;
+    tile = (int)(slot % gridDim.x);
+    bb = y0 + (slot / gridDim.x) * 8 + (L & 7);
+    if (bb >= nbatch(d)) return;
+  }
   const bool two = has2(d) && bb >= d.batch;
   const long b = two ? bb - d.batch : bb;  // entry of its operator
   const int ks = blockIdx.z;
   const int kbeg = ks * kper, kend = min(d.K, kbeg + kper);
-  const int row0 = blockIdx.x * ROWS + wr * 16;
+  const int row0 = tile * ROWS + wr * 16;
   const C2* A;
   if (d.aper > 0) {
     const int q = (int)(b / d.aper);
@@ -326,9 +338,12 @@ void run_chunk(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
   const int nsplit = split_plan(d, &kper);
   const long nbt = nbatch(d);
   if (nsplit == 1) {
-    for (long y0 = 0; y0 < nbt; y0 += kGridY) {
-      hipLaunchKernelGGL((skinny_kernel<T, WK, NB>), dim3(tiles, std::min(kGridY, nbt - y0), 1),
-                         dim3(256), 0, st, d, r0, nr, d.K, (double2*)nullptr, y0);
+    // slices of a multiple of 8 entries; the last is rounded up to one (see the kernel)
+    constexpr long kSlice = kGridY / 8 * 8;
+    for (long y0 = 0; y0 < nbt; y0 += kSlice) {
+      const long ny = std::min(kSlice, (nbt - y0 + 7) / 8 * 8);
+      hipLaunchKernelGGL((skinny_kernel<T, WK, NB>), dim3(tiles, ny, 1), dim3(256), 0, st, d, r0,
+                         nr, d.K, (double2*)nullptr, y0, true);
       HPS_LAUNCH_CHECK();
     }
     return;
@@ -338,7 +353,7 @@ void run_chunk(const SkinnyDesc& d, int r0, int nr, hipStream_t st) {
   for (long y0 = 0; y0 < nbt; y0 += kGridY) {
     hipLaunchKernelGGL((skinny_kernel<T, WK, NB>),
                        dim3(tiles, std::min(kGridY, nbt - y0), nsplit), dim3(256), 0, st, d, r0,
-                       nr, kper, part, y0);
+                       nr, kper, part, y0, false);
     HPS_LAUNCH_CHECK();
   }
   long tot = (long)nbatch(d) * d.M * nr;
