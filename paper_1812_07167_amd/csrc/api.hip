@@ -1344,6 +1344,42 @@ void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const d
       auto op = [&](const View& v, long per) { return v.d() + box0 * per * e; };
       const Across::Level* tl = ax ? &ax->lv[l] : nullptr;
       const int per = 1 << l;  // boxes of one problem on the level
+      if (l > 0 && n3 <= up_fused_max_n3()) {
+        // a short interface: gather, the three interface products and h^tau of each box
+        // in one launch, the box's vectors in LDS
+        tta[l] = ws.get((size_t)nbox * n3 * nrhs * 16);
+        ttb[l] = ws.get((size_t)nbox * n3 * nrhs * 16);
+        h[l] = ws.get((size_t)nbox * nbp * nrhs * 16);
+        UpLevelDesc u;
+        u.nbox = (int)nbox; u.nbc = P.nbc; u.n1 = (int)n1; u.n2 = (int)n2; u.n3 = (int)n3;
+        u.nbp = (int)nbp; u.nrhs = nrhs;
+        u.perm = P.dperm; u.i1a = P.di1a; u.i3a = P.di3a; u.i2b = P.di2b; u.i3b = P.di3b;
+        u.hc = h[l + 1]; u.hp = h[l]; u.tta = tta[l]; u.ttb = ttb[l];
+        if (jmp) {
+          u.jmp = jmp; u.ldj = nl * nb; u.ja = P.dja + box0 * n3; u.jb = P.djb + box0 * n3;
+          u.jbase = h0 * nb;
+        }
+        u.c64 = P.c64;
+        if (tl) {
+          u.per = per;
+          for (int q = 0; q < ax->np; ++q) {
+            u.R33b[q] = tl->R33b[q]; u.Winv[q] = tl->Winv[q]; u.R33a[q] = tl->R33a[q];
+            u.R13a[q] = tl->R13a[q]; u.R23b[q] = tl->R23b[q]; u.nrq[q] = ax->nrq[q];
+          }
+        } else {
+          u.per = (int)nbox;
+          u.R33b[0] = op(P.R33b, n3 * n3); u.Winv[0] = op(P.Winv, n3 * n3);
+          u.R33a[0] = op(P.R33a, n3 * n3); u.R13a[0] = op(P.R13a, n1 * n3);
+          u.R23b[0] = op(P.R23b, n2 * n3);
+        }
+        const double fl = 8.0 * nbox * nrhs * (3.0 * n3 * n3 + (double)(n1 + n2) * n3);
+        // operators once; children's h in, t~3a, t~3b and h out
+        const double by = nbox * ((3.0 * n3 * n3 + (double)(n1 + n2) * n3) * 8.0 * e +
+                                  (2.0 * P.nbc + 2.0 * n3 + nbp) * nrhs * 16.0);
+        Stage sg(pr, nm, fl, by);
+        if (!ws.dry) up_fused(u, st);
+        continue;
+      }
       double* h3a = ws.get((size_t)nbox * n3 * nrhs * 16);
       double* v = ws.get((size_t)nbox * n3 * nrhs * 16);
       tta[l] = ws.get((size_t)nbox * n3 * nrhs * 16);

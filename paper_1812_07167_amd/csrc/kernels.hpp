@@ -73,6 +73,32 @@ struct SkinnyDesc {
   int nrq[kMaxTab] = {};
 };
 size_t skinny_work_bytes(const SkinnyDesc& d);
+
+// One upward-sweep merge level in one launch, for levels whose interface is short
+// (n3 <= up_fused_max_n3()): one workgroup per box gathers the children's outgoing data,
+// forms t~3a = W^{-1} (R33b h3a - h3b), t~3b = -h3a - R33a t~3a and the parent's
+// h = [h1a + R13a t~3a ; h2b + R23b t~3b] with the box's vectors in LDS, and writes
+// t~3a, t~3b (kept for the downward sweep) and h.  Layouts as the separate launches
+// use: hc [2 nbox][nrhs][nbc], hp [nbox][nrhs][nbp], tta/ttb [nbox][nrhs][n3]; jumps
+// (optional) as for up_gather.  Box q's operators: factor f = q / per, box q % per of
+// its level arrays R33b[f], Winv[f], R33a[f], R13a[f], R23b[f]; nrq[f] > 0 limits
+// factor f to its first nrq[f] right-hand sides (the other columns are left unwritten).
+struct UpLevelDesc {
+  int nbox = 0, nbc = 0, n1 = 0, n2 = 0, n3 = 0, nbp = 0, nrhs = 0;
+  const int *perm = nullptr, *i1a = nullptr, *i3a = nullptr, *i2b = nullptr, *i3b = nullptr;
+  const double* hc = nullptr;
+  double* hp = nullptr;
+  double *tta = nullptr, *ttb = nullptr;
+  const double* jmp = nullptr; long ldj = 0; const int *ja = nullptr, *jb = nullptr; long jbase = 0;
+  bool c64 = false;  // the level's operators are complex64
+  int per = 0;       // boxes per factor
+  const double *R33b[SkinnyDesc::kMaxTab] = {}, *Winv[SkinnyDesc::kMaxTab] = {},
+               *R33a[SkinnyDesc::kMaxTab] = {}, *R13a[SkinnyDesc::kMaxTab] = {},
+               *R23b[SkinnyDesc::kMaxTab] = {};
+  int nrq[SkinnyDesc::kMaxTab] = {};
+};
+int up_fused_max_n3();
+void up_fused(const UpLevelDesc& d, hipStream_t st);
 void zgemm_skinny(const SkinnyDesc& d, hipStream_t st);
 
 // ------------------------------------------------------------------ complex inversion

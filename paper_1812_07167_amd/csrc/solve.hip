@@ -394,6 +394,201 @@ size_t pass_work_bytes(const SkinnyDesc& d, int nr) {
   return (size_t)nsplit * nbatch(d) * NRB * nb * d.M * sizeof(double2);
 }
 
+// ------------------------------------------------------------------ fused up level
+constexpr int kUpMaxN3 = 56;  // interface length of the levels the fused kernel takes
+
+// Products Y = A X of one box, A (M x K, column-major lda = M) from memory, X (K x 16,
+// LDS, X[k * 16 + r], complex128) a staged block of vectors.  A 16-row tile of A is one
+// wave's; its NS 4-deep steps are loaded first (frag_load, through a buffer resource:
+// steps past K read as zero) and applied later (frag_apply, 3M MFMA products as in the
+// skinny kernel), so a box's next operator can be in flight while the current one is
+// applied.  out(v, i, r, y) receives every entry with i < M, r < 16 (v: the lane's
+// accumulator slot, i = frag_row(tile, lane, v)).
+template <class T, int NS>
+struct Frag {
+  typename Cx<T>::t a[NS];
+};
+template <class T, int NS>
+__device__ inline void frag_load(Frag<T, NS>& f, const double* Ad, int M, int K, int tile,
+                                 int lane) {
+  typedef typename Cx<T>::t C2;
+  const int li = lane & 15, lk = lane >> 4;
+  const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<double*>(Ad), (short)0, (int)((long)M * K * (long)sizeof(C2)), kBufWord3);
+  const int aoff = (min(tile * 16 + li, M - 1) + M * lk) * (int)sizeof(C2);
+  const int kstep = 4 * M * (int)sizeof(C2);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) f.a[s] = SkLoad<T>::ld(ra, aoff + s * kstep);
+}
+template <class T, int NS, class Out>
+__device__ inline void frag_apply(const Frag<T, NS>& f, int M, int K, int tile,
+                                  const double2* X, int lane, Out out) {
+  typedef typename Cx<T>::t C2;
+  typedef SkMfma<T> MF;
+  typedef typename MF::acc acc_t;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nsteps = (K + 3) >> 2;
+  acc_t accR = acc_t{0, 0, 0, 0}, accX = acc_t{0, 0, 0, 0}, accI = acc_t{0, 0, 0, 0};
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    if (s < nsteps) {  // (a guard, not a break: the loop stays unrolled, f in registers)
+      const int k = 4 * s + lk;
+      const double2 xv = k < K ? X[k * 16 + li] : cmk(0, 0);
+      const C2 bx = Cx<T>::mk((T)xv.x, (T)xv.y);
+      const C2 a = f.a[s];
+      accR = MF::op(a.x, bx.x, accR);
+      accX = MF::op(a.y, bx.y, accX);
+      accI = MF::op(a.x + a.y, bx.x + bx.y, accI);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = tile * 16 + MF::row(lk, v);
+    if (i < M)
+      out(v, i, li, cmk((double)accR[v] - (double)accX[v],
+                        (double)accI[v] - (double)accR[v] - (double)accX[v]));
+  }
+}
+// the rows i = tile * 16 + row(lane, v) that frag_apply hands this lane
+template <class T>
+__device__ inline int frag_row(int tile, int lane, int v) {
+  return tile * 16 + SkMfma<T>::row(lane >> 4, v);
+}
+
+// NS = the level's 4-deep steps (n3 <= 4 NS); the n3 x n3 operators have at most 4 row
+// tiles, one per wave, and their fragments are loaded one product ahead.
+template <class T, int NS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NS <= 4 ? 3 : NS <= 8 ? 2 : 1))) void up_fused_kernel(UpLevelDesc d) {
+  constexpr int NR = NRB;  // right-hand sides per pass
+  extern __shared__ double2 sv[];
+  const int n3 = d.n3, nbc = d.nbc, nbp = d.nbp, n1 = d.n1, n2 = d.n2;
+  double2* H3a = sv;            // [n3][16]
+  double2* V = sv + n3 * NR;    // v = R33b h3a - h3b
+  double2* T3a = V + n3 * NR;   // t~3a
+  double2* T3b = T3a + n3 * NR; // t~3b
+  // the level's index maps (the same for every box): i3a, i3b, then i1a, i2b, then perm
+  int* im = reinterpret_cast<int*>(T3b + n3 * NR);
+  int* si3a = im;
+  int* si3b = im + n3;
+  int* si1a = im + 2 * n3;
+  int* si2b = si1a + n1;
+  int* sperm = si2b + n2;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const long q = blockIdx.x;
+  const int f = (int)(q / d.per), qb = (int)(q % d.per);
+  int nrhs = d.nrhs;
+  if (d.nrq[f] > 0) nrhs = min(nrhs, d.nrq[f]);
+  const long e = d.c64 ? 1 : 2;  // doubles per operator entry
+  const double* R33b = d.R33b[f] + qb * (long)n3 * n3 * e;
+  const double* Winv = d.Winv[f] + qb * (long)n3 * n3 * e;
+  const double* R33a = d.R33a[f] + qb * (long)n3 * n3 * e;
+  const double* R13a = d.R13a[f] + qb * (long)n1 * n3 * e;
+  const double* R23b = d.R23b[f] + qb * (long)n2 * n3 * e;
+  const double2* ha = reinterpret_cast<const double2*>(d.hc) + (2 * q) * (long)nbc * d.nrhs;
+  const double2* hb = reinterpret_cast<const double2*>(d.hc) + (2 * q + 1) * (long)nbc * d.nrhs;
+  double2* hp = reinterpret_cast<double2*>(d.hp) + q * (long)nbp * d.nrhs;
+  double2* tta = reinterpret_cast<double2*>(d.tta) + q * (long)n3 * d.nrhs;
+  double2* ttb = reinterpret_cast<double2*>(d.ttb) + q * (long)n3 * d.nrhs;
+  const double2* jmp = reinterpret_cast<const double2*>(d.jmp);
+  const bool mine = wave * 16 < n3;  // this wave's row tile of the n3 x n3 operators
+  Frag<T, NS> fa, fb;
+  if (mine) frag_load(fa, R33b, n3, n3, wave, lane);
+  for (int x = tid; x < 2 * n3 + n1 + n2 + nbp; x += 256) {
+    int v;
+    if (x < n3) v = d.i3a[x];
+    else if (x < 2 * n3) v = d.i3b[x - n3];
+    else if (x < 2 * n3 + n1) v = d.i1a[x - 2 * n3];
+    else if (x < 2 * n3 + n1 + n2) v = d.i2b[x - 2 * n3 - n1];
+    else v = d.perm[x - 2 * n3 - n1 - n2];
+    im[x] = v;
+  }
+  for (int r0 = 0; r0 < nrhs; r0 += NR) {
+    const int nr = min(NR, nrhs - r0);
+    if (r0 > 0 && mine) frag_load(fa, R33b, n3, n3, wave, lane);
+    __syncthreads();  // index maps staged; the previous pass's vectors have been read
+    // gather: h3a, and v = -h3b (jumps subtracted), zero past the pass's columns
+    for (int x = tid; x < n3 * NR; x += 256) {
+      const int k = x / NR, r = x % NR;
+      double2 a = cmk(0, 0), b = cmk(0, 0);
+      if (r < nr) {
+        const long c = (long)nbc * (r0 + r);
+        a = ha[si3a[k] + c];
+        b = hb[si3b[k] + c];
+        if (jmp) {
+          const long qk = q * (long)n3 + k;
+          a = csub(a, jmp[(long)(r0 + r) * d.ldj + d.jb[qk] - d.jbase]);  // h3a - j2
+          b = csub(b, jmp[(long)(r0 + r) * d.ldj + d.ja[qk] - d.jbase]);  // h3b - j1
+        }
+      }
+      H3a[x] = a;
+      V[x] = cmk(-b.x, -b.y);
+    }
+    __syncthreads();
+    if (mine) {
+      frag_load(fb, Winv, n3, n3, wave, lane);
+      frag_apply(fa, n3, n3, wave, H3a, lane, [&](int, int i, int r, double2 y) {
+        V[i * NR + r] = cadd(V[i * NR + r], y);
+      });
+    }
+    __syncthreads();
+    if (mine) {
+      frag_load(fa, R33a, n3, n3, wave, lane);
+      frag_apply(fb, n3, n3, wave, V, lane, [&](int, int i, int r, double2 y) {
+        T3a[i * NR + r] = y;
+        if (r < nr) tta[i + (long)n3 * (r0 + r)] = y;
+      });
+    }
+    __syncthreads();
+    // this wave's first R13a tile, and the I1 entries of child a it adds to, in flight
+    // while t~3b is formed
+    const int li = lane & 15;
+    const bool rok = li < nr;
+    double2 add[4];
+    if (wave * 16 < n1) {
+      frag_load(fb, R13a, n1, n3, wave, lane);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = min(frag_row<T>(wave, lane, v), n1 - 1);
+        add[v] = rok ? ha[si1a[i] + (long)nbc * (r0 + li)] : cmk(0, 0);
+      }
+    }
+    if (mine)
+      frag_apply(fa, n3, n3, wave, T3a, lane, [&](int, int i, int r, double2 y) {
+        const double2 h = H3a[i * NR + r];
+        const double2 w = cmk(-h.x - y.x, -h.y - y.y);
+        T3b[i * NR + r] = w;
+        if (r < nr) ttb[i + (long)n3 * (r0 + r)] = w;
+      });
+    __syncthreads();
+    // h^tau: R13a t~3a into the parent's I1 rows, R23b t~3b into its I2 rows
+    for (int t = wave; t * 16 < n1; t += 4) {
+      if (t != wave) {
+        frag_load(fb, R13a, n1, n3, t, lane);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = min(frag_row<T>(t, lane, v), n1 - 1);
+          add[v] = rok ? ha[si1a[i] + (long)nbc * (r0 + li)] : cmk(0, 0);
+        }
+      }
+      frag_apply(fb, n1, n3, t, T3a, lane, [&](int v, int i, int r, double2 y) {
+        if (r < nr) hp[sperm[i] + (long)nbp * (r0 + r)] = cadd(add[v], y);
+      });
+    }
+    for (int t = wave; t * 16 < n2; t += 4) {
+      frag_load(fa, R23b, n2, n3, t, lane);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = min(frag_row<T>(t, lane, v), n2 - 1);
+        add[v] = rok ? hb[si2b[i] + (long)nbc * (r0 + li)] : cmk(0, 0);
+      }
+      frag_apply(fa, n2, n3, t, T3b, lane, [&](int v, int i, int r, double2 y) {
+        if (r < nr) hp[sperm[n1 + i] + (long)nbp * (r0 + r)] = cadd(add[v], y);
+      });
+    }
+  }
+}
+
 }  // namespace
 
 size_t skinny_work_bytes(const SkinnyDesc& d) {
@@ -423,6 +618,32 @@ void zgemm_skinny(const SkinnyDesc& d, hipStream_t st) {
   // passes of up to 64 right-hand sides; the last takes the rest
   constexpr int NCMAX = NRB * MAXNB;
   for (int r0 = 0; r0 < d.nrhs; r0 += NCMAX) run_pass(d, r0, std::min(NCMAX, d.nrhs - r0), st);
+}
+
+int up_fused_max_n3() { return kUpMaxN3; }
+
+void up_fused(const UpLevelDesc& d, hipStream_t st) {
+  if (d.nbox <= 0 || d.nrhs <= 0) return;
+  if (d.n3 > kUpMaxN3 || d.n3 <= 0) throw Error(1, "up_fused: interface longer than the fused kernel takes");
+  if (d.per <= 0 || (d.nbox + d.per - 1) / d.per > SkinnyDesc::kMaxTab)
+    throw Error(1, "up_fused: boxes per factor");
+  const size_t lds = (size_t)4 * d.n3 * NRB * sizeof(double2) +
+                     (size_t)(2 * d.n3 + d.n1 + d.n2 + d.nbp) * sizeof(int);
+  if (d.n1 + d.n2 != d.nbp) throw Error(1, "up_fused: parent boundary is not I1 + I2");
+  const int ns = (d.n3 + 3) / 4;
+#define HPS_UPF(T, NS) \
+  hipLaunchKernelGGL((up_fused_kernel<T, NS>), dim3(d.nbox), dim3(256), lds, st, d)
+  if (d.c64) {
+    if (ns <= 4) HPS_UPF(float, 4);
+    else if (ns <= 8) HPS_UPF(float, 8);
+    else HPS_UPF(float, 14);
+  } else {
+    if (ns <= 4) HPS_UPF(double, 4);
+    else if (ns <= 8) HPS_UPF(double, 8);
+    else HPS_UPF(double, 14);
+  }
+#undef HPS_UPF
+  HPS_LAUNCH_CHECK();
 }
 
 }  // namespace hps
