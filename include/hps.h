@@ -94,9 +94,7 @@ typedef struct {
                              every problem of a batched solve, each measured on its own),
                              ||delta_r|| <= refine_tol ||u_r||, or the corrections contract
                              (each below half the last) so that the next one, estimated as
-                             ||delta_r||^2 / ||delta_r^prev||, is below that; the solve
-                             itself counts as a correction of relative size 1 (default
-                             1e-12)                                                      */
+                             ||delta_r||^2 / ||delta_r^prev||, is below that (default 1e-12) */
   int32_t autotune;        /* 1 = time every tile variant of each merge GEMM shape not yet
                              in the process's tuning table and record the fastest (the
                              build synchronizes its stream per new shape); builds launch

@@ -1857,10 +1857,7 @@ void solve_impl(hps_group& f, int pb, int np, int nrhs, const double* s, const d
   // c = r * np + q of length nl1 * n is problem q's share of right-hand side r
   const long ncol = (long)nrhs * np, clen = (long)f.nl1 * n;
   std::vector<double> hpart((size_t)ncol * nblk * 2);
-  // previous relative correction per column: the reduced-precision solve itself is the
-  // first step of the iteration (a correction from zero, of relative size 1), so the
-  // contraction estimate already applies to the first residual correction
-  std::vector<double> prev((size_t)ncol, 1.0);
+  std::vector<double> prev((size_t)ncol, 0.0);  // previous relative correction per column
   double corr = 0.0;
   int it = 0;
   bool conv = false;
