@@ -1453,6 +1453,36 @@ void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const d
     const double* tp = (l == 0) ? t : tt[l];
     const long sp = nbp * nrhs;
     tt[l + 1] = ws.get((size_t)2 * nbox * nbc * nrhs * 16);
+    if (l > 0 && down_fused_fits(P.n1, P.n2, (int)n3, (int)nbp)) {
+      // a short interface: the children's outer rows and both Phi products of each box in
+      // one launch, the parent's t in LDS
+      DownLevelDesc dd;
+      dd.nbox = (int)nbox; dd.nbc = (int)nbc; dd.n1 = P.n1; dd.n2 = P.n2; dd.n3 = (int)n3;
+      dd.nbp = (int)nbp; dd.nrhs = nrhs;
+      dd.perm = P.dperm; dd.i1a = P.di1a; dd.i3a = P.di3a; dd.i2b = P.di2b; dd.i3b = P.di3b;
+      dd.tp = tp; dd.tc = tt[l + 1];
+      if (up) {
+        dd.tta = tta[l];
+        dd.ttb = ttb[l];
+      }
+      dd.c64 = P.c64;
+      if (ax) {
+        dd.per = 1 << l;
+        for (int q = 0; q < ax->np; ++q) {
+          dd.PhiA[q] = ax->lv[l].PhiA[q]; dd.PhiB[q] = ax->lv[l].PhiB[q]; dd.nrq[q] = ax->nrq[q];
+        }
+      } else {
+        dd.per = (int)nbox;
+        dd.PhiA[0] = P.PhiA.d() + box0 * n3 * nbp * e;
+        dd.PhiB[0] = P.PhiB.d() + box0 * n3 * nbp * e;
+      }
+      const double fl = 16.0 * nbox * nrhs * (double)n3 * nbp;
+      const double by = nbox * (2.0 * n3 * nbp * 8.0 * e +
+                                (nbp + 2.0 * nbc + (up ? 2.0 * n3 : 0.0)) * nrhs * 16.0);
+      Stage sg(pr, nm, fl, by);
+      if (!ws.dry) down_fused(dd, st);
+      continue;
+    }
     {
       Stage sg(pr, "solve_gather", 0.0, nbox * 2.0 * (P.n1 + P.n2) * nrhs * 16);
       if (!ws.dry) down_scatter(d, nrhs, tp, nbp, tt[l + 1], st);

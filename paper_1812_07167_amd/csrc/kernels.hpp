@@ -99,6 +99,25 @@ struct UpLevelDesc {
 };
 int up_fused_max_n3();
 void up_fused(const UpLevelDesc& d, hipStream_t st);
+
+// One downward-sweep merge level in one launch, for the same short-interface levels:
+// one workgroup per box stages the parent's incoming data t (tp [nbox][nrhs][nbp]),
+// copies its I1 / I2 entries into the children's outer rows and writes the children's
+// interface rows t3a = Phi^a t (+ t~3a), t3b = Phi^b t (+ t~3b) (tc [2 nbox][nrhs][nbc];
+// tta/ttb optional [nbox][nrhs][n3]).  Operators and nrq as for UpLevelDesc.
+struct DownLevelDesc {
+  int nbox = 0, nbc = 0, n1 = 0, n2 = 0, n3 = 0, nbp = 0, nrhs = 0;
+  const int *perm = nullptr, *i1a = nullptr, *i3a = nullptr, *i2b = nullptr, *i3b = nullptr;
+  const double* tp = nullptr;
+  double* tc = nullptr;
+  const double *tta = nullptr, *ttb = nullptr;
+  bool c64 = false;
+  int per = 0;
+  const double *PhiA[SkinnyDesc::kMaxTab] = {}, *PhiB[SkinnyDesc::kMaxTab] = {};
+  int nrq[SkinnyDesc::kMaxTab] = {};
+};
+bool down_fused_fits(int n1, int n2, int n3, int nbp);  // the level's box fits the kernel
+void down_fused(const DownLevelDesc& d, hipStream_t st);
 void zgemm_skinny(const SkinnyDesc& d, hipStream_t st);
 
 // ------------------------------------------------------------------ complex inversion

@@ -589,6 +589,148 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NS <= 4 ? 3
   }
 }
 
+// ------------------------------------------------------------------ fused down level
+// Work items of a box: (operator, 16-row tile, K part); an operator of one tile splits K
+// in two so that the four waves have work.  A wave accumulates an item over its K range
+// in chunks of DNS 4-deep steps, the next chunk's fragments loaded while the current one
+// is applied, and leaves its tile in LDS; the outputs add the K parts in order.
+constexpr int DNS = 8;
+template <class T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void down_fused_kernel(DownLevelDesc d) {
+  typedef typename Cx<T>::t C2;
+  typedef SkMfma<T> MF;
+  typedef typename MF::acc acc_t;
+  constexpr int NR = NRB;
+  extern __shared__ double2 sv[];
+  const int n3 = d.n3, nbc = d.nbc, nbp = d.nbp, n1 = d.n1, n2 = d.n2;
+  const int ntile = (n3 + 15) / 16;
+  const int nk = ntile == 1 ? 2 : 1;
+  const int nitem = 2 * ntile * nk;
+  const int Kq = ((nbp + nk - 1) / nk + 3) & ~3;  // K range of a part (whole steps)
+  double2* X = sv;                      // [nbp][16] the parent's t
+  double2* Pt = X + nbp * NR;           // [nitem][16 rows][16 rhs] partial tiles
+  int* im = reinterpret_cast<int*>(Pt + nitem * 256);
+  int* si1a = im;
+  int* si2b = si1a + n1;
+  int* si3a = si2b + n2;
+  int* si3b = si3a + n3;
+  int* sperm = si3b + n3;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const long q = blockIdx.x;
+  const int f = (int)(q / d.per), qb = (int)(q % d.per);
+  int nrhs = d.nrhs;
+  if (d.nrq[f] > 0) nrhs = min(nrhs, d.nrq[f]);
+  const long e = d.c64 ? 1 : 2;
+  const double* Pa = d.PhiA[f] + qb * (long)n3 * nbp * e;
+  const double* Pb = d.PhiB[f] + qb * (long)n3 * nbp * e;
+  const double2* tp = reinterpret_cast<const double2*>(d.tp) + q * (long)nbp * d.nrhs;
+  double2* tca = reinterpret_cast<double2*>(d.tc) + (2 * q) * (long)nbc * d.nrhs;
+  double2* tcb = reinterpret_cast<double2*>(d.tc) + (2 * q + 1) * (long)nbc * d.nrhs;
+  const double2* t0a = d.tta ? reinterpret_cast<const double2*>(d.tta) + q * (long)n3 * d.nrhs : nullptr;
+  const double2* t0b = d.ttb ? reinterpret_cast<const double2*>(d.ttb) + q * (long)n3 * d.nrhs : nullptr;
+  for (int x = tid; x < n1 + n2 + 2 * n3 + nbp; x += 256) {
+    int v;
+    if (x < n1) v = d.i1a[x];
+    else if (x < n1 + n2) v = d.i2b[x - n1];
+    else if (x < n1 + n2 + n3) v = d.i3a[x - n1 - n2];
+    else if (x < n1 + n2 + 2 * n3) v = d.i3b[x - n1 - n2 - n3];
+    else v = d.perm[x - n1 - n2 - 2 * n3];
+    im[x] = v;
+  }
+  // an item's operator, row tile and K range
+  struct Item {
+    __amdgpu_buffer_rsrc_t ra;
+    int tile, kbeg, kend, aoff;
+  };
+  auto item = [&](int it) {
+    const int op = it / (ntile * nk), rem = it % (ntile * nk);
+    Item m;
+    m.tile = rem / nk;
+    const int kq = rem % nk;
+    m.kbeg = kq * Kq;
+    m.kend = min(nbp, m.kbeg + Kq);
+    m.ra = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(op ? Pb : Pa), (short)0,
+                                             (int)((long)n3 * nbp * (long)sizeof(C2)), kBufWord3);
+    m.aoff = (min(m.tile * 16 + li, n3 - 1) + n3 * lk) * (int)sizeof(C2);
+    return m;
+  };
+  const int kstep = 4 * n3 * (int)sizeof(C2);
+  C2 fa[DNS], fb[DNS];
+  auto load = [&](const Item& m, C2* fr, int s0) {
+#pragma unroll
+    for (int i = 0; i < DNS; ++i) fr[i] = SkLoad<T>::ld(m.ra, m.aoff + (s0 + i) * kstep);
+  };
+  for (int r0 = 0; r0 < nrhs; r0 += NR) {
+    const int nr = min(NR, nrhs - r0);
+    // the operators do not depend on t: this wave's first chunk is requested before it
+    if (wave < nitem) {
+      const Item m = item(wave);
+      load(m, fa, m.kbeg >> 2);
+    }
+    __syncthreads();  // index maps staged; the previous pass's LDS has been read
+    for (int x = tid; x < nbp * NR; x += 256) {
+      const int k = x / NR, r = x % NR;
+      X[x] = r < nr ? tp[k + (long)nbp * (r0 + r)] : cmk(0, 0);
+    }
+    __syncthreads();
+    // the children's outer rows: copies of the parent's I1 and I2 entries
+    for (int x = tid; x < (n1 + n2) * nr; x += 256) {
+      const int k = x % (n1 + n2), r = x / (n1 + n2);
+      const double2 v = X[sperm[k] * NR + r];
+      if (k < n1) tca[si1a[k] + (long)nbc * (r0 + r)] = v;
+      else tcb[si2b[k - n1] + (long)nbc * (r0 + r)] = v;
+    }
+    for (int it = wave; it < nitem; it += 4) {
+      const Item m = item(it);
+      const int s_end = (m.kend + 3) >> 2;
+      acc_t accR = acc_t{0, 0, 0, 0}, accX = acc_t{0, 0, 0, 0}, accI = acc_t{0, 0, 0, 0};
+      auto apply = [&](const C2* fr, int s0) {
+#pragma unroll
+        for (int i = 0; i < DNS; ++i) {
+          if (s0 + i < s_end) {
+            const int k = 4 * (s0 + i) + lk;
+            const double2 xv = k < m.kend ? X[k * NR + li] : cmk(0, 0);
+            const C2 bx = Cx<T>::mk((T)xv.x, (T)xv.y);
+            const C2 a = fr[i];
+            accR = MF::op(a.x, bx.x, accR);
+            accX = MF::op(a.y, bx.y, accX);
+            accI = MF::op(a.x + a.y, bx.x + bx.y, accI);
+          }
+        }
+      };
+      int s = m.kbeg >> 2;
+      if (it != wave) load(m, fa, s);  // (the first item's first chunk is in flight)
+      for (; s < s_end; s += 2 * DNS) {
+        if (s + DNS < s_end) load(m, fb, s + DNS);
+        apply(fa, s);
+        if (s + DNS >= s_end) break;
+        if (s + 2 * DNS < s_end) load(m, fa, s + 2 * DNS);
+        apply(fb, s + DNS);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        Pt[it * 256 + MF::row(lk, v) * NR + li] =
+            cmk((double)accR[v] - (double)accX[v],
+                (double)accI[v] - (double)accR[v] - (double)accX[v]);
+    }
+    __syncthreads();
+    // the children's interface rows: the K parts in order, plus t~3
+    for (int x = tid; x < 2 * n3 * nr; x += 256) {
+      const int op = x / (n3 * nr), rem = x % (n3 * nr);
+      const int i = rem % n3, r = rem / n3;
+      const int tile = i / 16, row = i % 16;
+      double2 y = cmk(0, 0);
+      for (int kq = 0; kq < nk; ++kq) y = cadd(y, Pt[((op * ntile + tile) * nk + kq) * 256 + row * NR + r]);
+      const double2* t0 = op ? t0b : t0a;
+      if (t0) y = cadd(y, t0[i + (long)n3 * (r0 + r)]);
+      if (op == 0) tca[si3a[i] + (long)nbc * (r0 + r)] = y;
+      else tcb[si3b[i] + (long)nbc * (r0 + r)] = y;
+    }
+  }
+}
+
 }  // namespace
 
 size_t skinny_work_bytes(const SkinnyDesc& d) {
@@ -622,6 +764,33 @@ void zgemm_skinny(const SkinnyDesc& d, hipStream_t st) {
 
 int up_fused_max_n3() { return kUpMaxN3; }
 
+// LDS of a box of the fused downward kernel: the parent's t, the partial tiles, the maps
+size_t down_fused_lds(int n1, int n2, int n3, int nbp) {
+  const int ntile = (n3 + 15) / 16, nitem = 2 * ntile * (ntile == 1 ? 2 : 1);
+  return (size_t)nbp * NRB * sizeof(double2) + (size_t)nitem * 256 * sizeof(double2) +
+         (size_t)(n1 + n2 + 2 * n3 + nbp) * sizeof(int);
+}
+// dynamic LDS a launch takes without a per-kernel attribute
+constexpr size_t kDynLds = 64 * 1024;
+
+bool down_fused_fits(int n1, int n2, int n3, int nbp) {
+  return n3 > 0 && n3 <= kUpMaxN3 && n1 + n2 == nbp && down_fused_lds(n1, n2, n3, nbp) <= kDynLds;
+}
+
+void down_fused(const DownLevelDesc& d, hipStream_t st) {
+  if (d.nbox <= 0 || d.nrhs <= 0) return;
+  if (!down_fused_fits(d.n1, d.n2, d.n3, d.nbp))
+    throw Error(1, "down_fused: a level the fused kernel does not take");
+  if (d.per <= 0 || (d.nbox + d.per - 1) / d.per > SkinnyDesc::kMaxTab)
+    throw Error(1, "down_fused: boxes per factor");
+  const size_t lds = down_fused_lds(d.n1, d.n2, d.n3, d.nbp);
+  if (d.c64)
+    hipLaunchKernelGGL(down_fused_kernel<float>, dim3(d.nbox), dim3(256), lds, st, d);
+  else
+    hipLaunchKernelGGL(down_fused_kernel<double>, dim3(d.nbox), dim3(256), lds, st, d);
+  HPS_LAUNCH_CHECK();
+}
+
 void up_fused(const UpLevelDesc& d, hipStream_t st) {
   if (d.nbox <= 0 || d.nrhs <= 0) return;
   if (d.n3 > kUpMaxN3 || d.n3 <= 0) throw Error(1, "up_fused: interface longer than the fused kernel takes");
@@ -630,6 +799,7 @@ void up_fused(const UpLevelDesc& d, hipStream_t st) {
   const size_t lds = (size_t)4 * d.n3 * NRB * sizeof(double2) +
                      (size_t)(2 * d.n3 + d.n1 + d.n2 + d.nbp) * sizeof(int);
   if (d.n1 + d.n2 != d.nbp) throw Error(1, "up_fused: parent boundary is not I1 + I2");
+  if (lds > 64 * 1024) throw Error(1, "up_fused: the level's vectors exceed 64 KB of LDS");
   const int ns = (d.n3 + 3) / 4;
 #define HPS_UPF(T, NS) \
   hipLaunchKernelGGL((up_fused_kernel<T, NS>), dim3(d.nbox), dim3(256), lds, st, d)
