@@ -770,7 +770,8 @@ size_t down_fused_lds(int n1, int n2, int n3, int nbp) {
   return (size_t)nbp * NRB * sizeof(double2) + (size_t)nitem * 256 * sizeof(double2) +
          (size_t)(n1 + n2 + 2 * n3 + nbp) * sizeof(int);
 }
-// dynamic LDS a launch takes without a per-kernel attribute
+// LDS limit of a fused downward box: above 64 KB (the two n3 = 56 levels at p = 16, one
+// workgroup per CU) the fused form was slower than the separate launches
 constexpr size_t kDynLds = 64 * 1024;
 
 bool down_fused_fits(int n1, int n2, int n3, int nbp) {
