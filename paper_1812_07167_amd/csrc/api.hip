@@ -247,7 +247,8 @@ void timed_gemm(Profiler& pr, const char* name, const GemmDesc& g, hipStream_t s
   const double fl = (g.a_real || g.b_real) ? 4.0 * mnk : 8.0 * mnk;
   const double by = (double)g.batch * ((double)g.M * g.K * (g.a_real ? 8 : 16) +
                                        (double)g.K * g.N * (g.b_real ? 8 : 16) +
-                                       (double)g.M * g.N * 16 * (g.beta != 0.0 ? 2 : 1));
+                                       (double)g.M * g.N * 16 * (g.beta != 0.0 ? 2 : 1) +
+                                       (g.C0r ? (double)g.M * g.N * 8 : 0.0));
   // one record name per kernel variant, so that a record's launches are launches of one
   // kernel (what a profiler's per-kernel average refers to)
   const std::string nm = std::string(name) + "[" + zgemm_variant(g) + "]";
@@ -809,10 +810,10 @@ size_t arena_layout(hps_group& f, char* base) {
 
 // Leaf-stage scratch of one chunk of leaves (byte offsets): the impedance route's
 // inverse copies (mg), in mixed precision the chunk's complex128 [Psi | Y] (bi), then the
-// Dirichlet route's X (n_i x n_b) and Z (n_b x n_i) per leaf.  Both routes may run on
+// Dirichlet route's X (n_i x n_b), Z (n_b x n_i) and real A^{-1} (n_i x n_i) per leaf.  Both routes may run on
 // one chunk (problems of one group can take different routes), so both are laid out.
 struct LeafScratch {
-  size_t mg = 0, bi = 0, x = 0, z = 0, total = 0;
+  size_t mg = 0, bi = 0, x = 0, z = 0, ai = 0, total = 0;
 };
 LeafScratch leaf_scratch(const hps_group& f) {
   auto r256 = [](size_t b) { return (b + 255) & ~size_t(255); };
@@ -822,7 +823,8 @@ LeafScratch leaf_scratch(const hps_group& f) {
   L.bi = r256(leaf_scratch_bytes(f.p, (long)lch));
   L.x = L.bi + (f.mixed ? r256(lch * n * n * 16) : 0);
   L.z = L.x + r256(lch * ni * nb * 8);
-  L.total = L.z + r256(lch * nb * ni * 8);
+  L.ai = L.z + r256(lch * nb * ni * 8);
+  L.total = L.ai + r256(lch * ni * ni * 8);
   return L;
 }
 
@@ -979,6 +981,7 @@ void build_leaves(hps_group& f, const double* c, BuildScratch& sc) {
     dc.Mg = mg_bytes ? reinterpret_cast<double*>(scr) : nullptr;
     dc.X = reinterpret_cast<double*>(scr + LS.x);
     dc.Z = reinterpret_cast<double*>(scr + LS.z);
+    dc.Ai = reinterpret_cast<double*>(scr + LS.ai);
     long nR = 0;  // leaves of the chunk on the Dirichlet route
     for (long hh = h0; hh < h0 + cnt; ++hh) nR += f.route_h[hh / f.nl1];
     const long nC = cnt - nR;
@@ -986,14 +989,14 @@ void build_leaves(hps_group& f, const double* c, BuildScratch& sc) {
     if (nR > 0) {
       {
         // A^{-1}: real Gauss-Jordan, 2 n_i^3 flops
-        Stage s(pr, "leaf_ainv", r_ * 2.0 * ni * ni * ni, r_ * (ni * 8.0 + ni * ni * 16.0));
+        Stage s(pr, "leaf_ainv", r_ * 2.0 * ni * ni * ni, r_ * (ni * 8.0 + ni * ni * 8.0));
         leaf_dirichlet_inverse(dc, st);
       }
       {
         // X = A^{-1} A_ib and Z = N_i A^{-1} (2 n_i^2 n_b each as dense products),
         // S = F_bb - N_i X (2 n_b^2 n_i)
         Stage s(pr, "leaf_xz", r_ * (4.0 * ni * ni * nb + 2.0 * nb * nb * ni),
-                r_ * (ni * ni * 16.0 + 2.0 * ni * nb * 8.0 + nb * nb * 16.0));
+                r_ * (ni * ni * 8.0 + 2.0 * ni * nb * 8.0 + nb * nb * 16.0));
         leaf_dirichlet_xz(dc, st);
       }
       {
@@ -1024,7 +1027,8 @@ void build_leaves(hps_group& f, const double* c, BuildScratch& sc) {
       g.A = dc.X; g.lda = ni; g.sA = ni * nb; g.a_real = true;
       g.B = dc.BI + 2 * n * nb; g.ldb = n; g.sB = n * n;
       g.C = dc.BI + 2 * (n * nb + nb); g.ldc = n; g.sC = n * n;
-      g.alpha = -1.0; g.beta = 1.0;
+      g.alpha = -1.0; g.beta = 0.0;
+      g.C0r = dc.Ai; g.ld0 = ni; g.s0 = ni * ni;  // + A^{-1} (real)
       timed_gemm(pr, "leaf_gemm", g, st, f.opts.autotune != 0);
       if (f.mixed) {
         Stage s(pr, "leaf_round", 0.0, cnt * (double)n * n * 24.0);

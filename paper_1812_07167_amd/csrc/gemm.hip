@@ -267,6 +267,7 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_kernel(GemmDesc d) {
           const long cj = d.ccol ? d.ccol[j] : j;
           cplx_t* p = C + ri + d.ldc * cj;
           cplx_t val = MF::mk(alpha * accR[x][y][v], alpha * accI[x][y][v]);
+          if (d.C0r) val.x += (T)d.C0r[b * d.s0 + i + d.ld0 * (long)j];
           if (d.beta != 0.0) {
             const cplx_t old = *p;
             val.x += beta * old.x;
@@ -328,7 +329,7 @@ struct TuneKey {
 
 TuneKey key_of(const GemmDesc& d) {
   const int flags = (d.a_real ? 1 : 0) | (d.b_real ? 2 : 0) | (d.c64 ? 4 : 0) |
-                    (d.beta != 0.0 ? 8 : 0) | ((d.crow || d.ccol) ? 16 : 0);
+                    (d.beta != 0.0 ? 8 : 0) | ((d.crow || d.ccol) ? 16 : 0) | (d.C0r ? 32 : 0);
   return TuneKey{d.M, d.N, d.K, d.batch, flags};
 }
 
@@ -367,6 +368,7 @@ std::string zgemm_variant(const GemmDesc& d) {
 
 void zgemm_check(const GemmDesc& d) {
   if (d.K <= 0) throw Error(1, "zgemm: K must be positive");
+  if (d.C0r && d.c64) throw Error(1, "zgemm: the real addend is for complex128 outputs");
 }
 
 // Batches beyond the grid's y limit run as consecutive slices (operands advanced by
@@ -383,6 +385,7 @@ void zgemm(const GemmDesc& d, hipStream_t st) {
     s.A = d.A + b0 * d.sA * ea;
     s.B = d.B + b0 * d.sB * eb;
     s.C = d.C + b0 * d.sC * ec;
+    if (d.C0r) s.C0r = d.C0r + b0 * d.s0;
     launch_variant(tile, s, st);
     HPS_LAUNCH_CHECK();
   }

@@ -21,6 +21,9 @@ struct GemmDesc {
   const int* crow = nullptr;
   const int* ccol = nullptr;
   bool c64 = false;  // A, B and C are complex64 (interleaved float); FP32 accumulation
+  // optional real addend of the (i, j) entry (before the row and column maps): C0r[b * s0
+  // + i + ld0 * j] is added to the real part (complex128 only)
+  const double* C0r = nullptr; long ld0 = 0, s0 = 0;
 };
 void zgemm(const GemmDesc& d, hipStream_t st);
 // Autotuner: time every tile variant for d's shape and record the fastest (synchronizes
@@ -156,6 +159,7 @@ struct LeafDesc {
   const double* rtab = nullptr;  // device real line tables, leaf_rtable_len(p) per problem
   double* X = nullptr;           // scratch [nleaf][n_i x n_b] real: A^{-1} A_ib
   double* Z = nullptr;           // scratch [nleaf][n_b x n_i] real: N_i A^{-1}
+  double* Ai = nullptr;          // scratch [nleaf][n_i x n_i] real: A^{-1} (column-major)
 };
 // scratch the leaf inverse needs for nleaf leaves (0 when it fits in registers)
 size_t leaf_scratch_bytes(int p, long nleaf);

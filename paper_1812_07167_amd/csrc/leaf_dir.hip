@@ -16,8 +16,8 @@
 // only then (leaf_route), and the impedance route of leaf.hip otherwise.
 //
 // Kernels: leaf_cmax (largest c of each problem, for that test), leaf_ainv (A^{-1} by
-// blocked Gauss-Jordan with partial pivoting in registers, into the Y_i block of
-// [Psi | Y]), leaf_xz (X, Z and S from A^{-1}, S into the Psi_b block), leaf_dir_R
+// blocked Gauss-Jordan with partial pivoting in registers, into a compact real scratch
+// copy), leaf_xz (X, Z and S from A^{-1}, S into the Psi_b block), leaf_dir_R
 // (R from Psi_b once S is inverted).  S^{-1} and the three products run on the shared
 // inversion and GEMM kernels (api.hip).
 #include <cstring>
@@ -109,8 +109,8 @@ __global__ __launch_bounds__(256) void leaf_cmax_kernel(const double* c, long pe
 //      other row i takes -M[i, K] P^{-1}; owners publish the block's rows X = M[K, :]
 //      (the identity on the columns K);
 //   4. every entry becomes (rows K and columns K zeroed) + Q X.
-// After the last block M holds A^{-1} in place, which is written as the real part of the
-// Y_i block.
+// After the last block M holds A^{-1} in place, which is written to the real scratch copy
+// (n_i x n_i per leaf; the Y_i product adds it as a real addend).
 template <int P> struct DirCfg {
   static constexpr int m = P - 2;
   static constexpr int NI = m * m;
@@ -320,16 +320,16 @@ __global__ __launch_bounds__(DirCfg<P>::NT) void leaf_ainv_kernel(LeafDesc d) {
     return;
   }
   // A^{-1} in place: consecutive threads hold consecutive rows of a column, so the
-  // stores into the column-major Y_i block are coalesced.  An entry beyond 1e8 times the
+  // stores into the column-major scratch copy are coalesced.  An entry beyond 1e8 times the
   // largest of A, or a non-finite one, marks the leaf (growth check).
   const double lim = 1e8 * __longlong_as_double((long long)s_amax);
   bool grown = false;
   if (live) {
     // the output addresses are formed here (the empty asm hides the base from loop-invariant
     // code motion, which would otherwise keep 80 addresses live through the elimination)
-    double* base = d.BI;
+    double* base = d.Ai;
     asm volatile("" : "+s"(base));
-    double2* BI = reinterpret_cast<double2*>(base) + h * (long)N * N;
+    double* Ai = base + h * (long)NI * NI;
 #pragma unroll
     for (int a = 0; a < ER; ++a)
 #pragma unroll
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(DirCfg<P>::NT) void leaf_ainv_kernel(LeafDesc d) {
         const int ra = tr + GR * a, c = tc + GC * b;
         if (ra < NI && c < NI) {
           grown |= !(fabs(M[a][b]) <= lim);
-          BI[(NB + ra) + (long)N * (NB + c)] = make_double2(M[a][b], 0.0);
+          Ai[ra + (long)NI * c] = M[a][b];
         }
       }
   }
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(DirCfg<P>::NT) void leaf_ainv_kernel(LeafDesc d) {
 }
 
 // ------------------------------------------------------------------ X, Z and S
-// One workgroup per leaf.  A^{-1} (real parts of the Y_i block) is read by grid rows:
+// One workgroup per leaf.  A^{-1} (the real scratch copy) is read by grid rows:
 // chunk k stages the m columns of the interior nodes (i, k) in LDS.  Then
 //   X[r, W_k] = sum_i A^{-1}[r, (i,k)] aW[i] and X[r, E_k] likewise are complete, and
 //   X[r, S_i] += A^{-1}[r, (i,k)] aS[k], X[r, N_i] += ... aN[k] accumulate (registers);
@@ -392,6 +392,7 @@ __global__ __launch_bounds__(512) void leaf_xz_kernel(LeafDesc d) {
   const double* fx = st + 8 * m + 4;
   double* X = d.X + h * (long)NI * NB;
   double* Z = d.Z + h * (long)NB * NI;
+  const double* Ai = d.Ai + h * (long)NI * NI;
   const int r = tid % (NT / 2), hh = tid / (NT / 2);  // hh 0: S and W columns; 1: N and E
   double acc[m];
 #pragma unroll
@@ -402,7 +403,7 @@ __global__ __launch_bounds__(512) void leaf_xz_kernel(LeafDesc d) {
 #pragma unroll
     for (int q = 0; q < IT; ++q) {
       const int e = tid + NT * q;
-      av[q] = e < NI * m ? BI[(NB + e % NI) + (long)N * (NB + k * m + e / NI)].x : 0.0;
+      av[q] = e < NI * m ? Ai[e % NI + (long)NI * (k * m + e / NI)] : 0.0;
     }
   };
   load_chunk(0);
