@@ -86,7 +86,9 @@ __global__ __launch_bounds__(256) void zinv_small_kernel(int n, const double* Ai
         bad = k + 1;
         break;
       }
-      const C2 ip = crcp(colv[sb][r]);
+      // (one division: the pivot is its column's largest entry, so |p|^2 stays in range
+      // unless the matrix's own scale is extreme, and then the guarded form falls back)
+      const C2 ip = crcp_pivot(colv[sb][r]);
       // the pivot row's values in this wave's columns, read before this step's updates
       C2 pr[NJ];
 #pragma unroll
