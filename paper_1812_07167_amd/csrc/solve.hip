@@ -146,6 +146,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB == 1 ? 3
   const int aoff = (min(row0 + li, d.M - 1) + d.lda * lk) * (int)sizeof(C2);
   const int kstep = 4 * d.lda * (int)sizeof(C2);
 
+  // The output and its addend (C0, or the current C when accumulating).  Without a K
+  // split the addends are requested now, so that they arrive during the K loop instead
+  // of costing the epilogue a memory round trip.
+  double2* C = reinterpret_cast<double2*>(two ? d.C2 : d.C) +
+               (d.coff ? d.coff[b] - d.cbase : b * d.sC);
+  const double* c0p = two ? d.C02 : d.C0;
+  const double2* C0 =
+      c0p ? reinterpret_cast<const double2*>(c0p) + (d.c0off ? d.c0off[b] : b * d.s0) : nullptr;
+  const int* crow = two ? d.crow2 : d.crow;
+  double2 addend[NB][4];
+  if (!partial && (C0 || d.accumulate)) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rhs = NRB * j + li;
+        const int i = row0 + MF::row(lk, v);
+        addend[j][v] = cmk(0, 0);
+        if (rhs < nr && i < d.M)
+          addend[j][v] = C0 ? C0[i + d.ld0 * (long)(r0 + rhs)]
+                            : C[(crow ? crow[i] : i) + d.ldc * (long)(r0 + rhs)];
+      }
+  }
+
   // 3M: accR, accX, accI hold ArXr, AiXi, (Ar + Ai)(Xr + Xi) until after the K loop
   acc_t accR[NB], accI[NB], accX[NB];
 #pragma unroll
@@ -244,12 +268,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB == 1 ? 3
     }
     return;
   }
-  double2* C = reinterpret_cast<double2*>(two ? d.C2 : d.C) +
-               (d.coff ? d.coff[b] - d.cbase : b * d.sC);
-  const double* c0p = two ? d.C02 : d.C0;
-  const double2* C0 =
-      c0p ? reinterpret_cast<const double2*>(c0p) + (d.c0off ? d.c0off[b] : b * d.s0) : nullptr;
-  const int* crow = two ? d.crow2 : d.crow;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     const int rhs = NRB * j + li;
@@ -260,10 +278,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB == 1 ? 3
       if (i >= d.M) continue;
       const long ci = crow ? crow[i] : i;
       double2 val = cmk(d.alpha * accR[j][v], d.alpha * accI[j][v]);
-      double2* p = C + ci + d.ldc * (long)(r0 + rhs);
-      if (C0) val = cadd(val, C0[i + d.ld0 * (long)(r0 + rhs)]);
-      else if (d.accumulate) val = cadd(val, *p);
-      *p = val;
+      if (C0 || d.accumulate) val = cadd(val, addend[j][v]);
+      C[ci + d.ldc * (long)(r0 + rhs)] = val;
     }
   }
 }
