@@ -855,6 +855,16 @@ def main():
         cx, cy = (int(v) for v in args.cpu_leaves.lower().split("x"))
         log("cpu baseline (oracle) on %dx%d leaves" % (cx, cy))
         out["cpu_baseline"] = cpu_baseline(cx, cy, p, kappa, nrhs, 0)
+        # the same oracle with its BLAS held to one thread, on a quarter of that sample
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1, user_api="blas"):
+                one = cpu_baseline(max(1, cx // 2), max(1, cy // 2), p, kappa, nrhs, 0)
+            out["cpu_baseline"]["single_thread"] = {k: one[k] for k in
+                                                    ("value", "unit", "cores", "seconds",
+                                                     "rel_l2_vs_exact", "sample")}
+        except Exception as e:  # the main figure stands without it
+            out["cpu_baseline"]["single_thread"] = {"error": repr(e)}
     print(json.dumps(out), flush=True)
 
 
