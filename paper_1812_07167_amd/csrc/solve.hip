@@ -321,8 +321,13 @@ __global__ void skinny_reduce_kernel(SkinnyDesc d, int r0, int nr, int nc, int n
 }
 
 // rows covered by one workgroup: by the operator's height, at most 64 (four waves of
-// 16 rows; shorter operators split K across the waves instead)
-int block_rows(const SkinnyDesc& d) { return d.M <= 16 ? 16 : d.M <= 32 ? 32 : 64; }
+// 16 rows; shorter operators split K across the waves instead).  Launches of few tall
+// operators (the top merge levels: under 256 blocks of 64 rows) take 16-row blocks with
+// K split over the four waves, which shortens each workgroup's chain of K steps.
+int block_rows(const SkinnyDesc& d) {
+  if ((long)cdiv(d.M, 64) * nbatch(d) < 256) return 16;
+  return d.M <= 16 ? 16 : d.M <= 32 ? 32 : 64;
+}
 
 // K is split across workgroups when the row blocks x batch cannot fill the device.
 // Returns the number of splits and the K range per split (a multiple of KC).
