@@ -1348,7 +1348,7 @@ void solve_pass(hps_group& f, int pb, int np, int nrhs, const double* s, const d
       auto op = [&](const View& v, long per) { return v.d() + box0 * per * e; };
       const Across::Level* tl = ax ? &ax->lv[l] : nullptr;
       const int per = 1 << l;  // boxes of one problem on the level
-      if (l > 0 && n3 <= up_fused_max_n3()) {
+      if (l > 0 && up_fused_fits((int)n1, (int)n2, (int)n3, (int)nbp)) {
         // a short interface: gather, the three interface products and h^tau of each box
         // in one launch, the box's vectors in LDS
         tta[l] = ws.get((size_t)nbox * n3 * nrhs * 16);

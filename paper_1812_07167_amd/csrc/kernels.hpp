@@ -78,7 +78,7 @@ struct SkinnyDesc {
 size_t skinny_work_bytes(const SkinnyDesc& d);
 
 // One upward-sweep merge level in one launch, for levels whose interface is short
-// (n3 <= up_fused_max_n3()): one workgroup per box gathers the children's outgoing data,
+// (up_fused_fits): one workgroup per box gathers the children's outgoing data,
 // forms t~3a = W^{-1} (R33b h3a - h3b), t~3b = -h3a - R33a t~3a and the parent's
 // h = [h1a + R13a t~3a ; h2b + R23b t~3b] with the box's vectors in LDS, and writes
 // t~3a, t~3b (kept for the downward sweep) and h.  Layouts as the separate launches
@@ -100,7 +100,7 @@ struct UpLevelDesc {
                *R23b[SkinnyDesc::kMaxTab] = {};
   int nrq[SkinnyDesc::kMaxTab] = {};
 };
-int up_fused_max_n3();
+bool up_fused_fits(int n1, int n2, int n3, int nbp);  // the level's box fits the kernel
 void up_fused(const UpLevelDesc& d, hipStream_t st);
 
 // One downward-sweep merge level in one launch, for the same short-interface levels:

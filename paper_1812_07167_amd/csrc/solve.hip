@@ -783,7 +783,14 @@ void zgemm_skinny(const SkinnyDesc& d, hipStream_t st) {
   for (int r0 = 0; r0 < d.nrhs; r0 += NCMAX) run_pass(d, r0, std::min(NCMAX, d.nrhs - r0), st);
 }
 
-int up_fused_max_n3() { return kUpMaxN3; }
+// LDS of a box of the fused upward kernel: four vectors of the pass, then the index maps
+static size_t up_fused_lds(int n1, int n2, int n3, int nbp) {
+  return (size_t)4 * n3 * NRB * sizeof(double2) + (size_t)(2 * n3 + n1 + n2 + nbp) * sizeof(int);
+}
+
+bool up_fused_fits(int n1, int n2, int n3, int nbp) {
+  return n3 > 0 && n3 <= kUpMaxN3 && n1 + n2 == nbp && up_fused_lds(n1, n2, n3, nbp) <= 64 * 1024;
+}
 
 // LDS of a box of the fused downward kernel: the parent's t, the partial tiles, the maps
 size_t down_fused_lds(int n1, int n2, int n3, int nbp) {
@@ -815,13 +822,11 @@ void down_fused(const DownLevelDesc& d, hipStream_t st) {
 
 void up_fused(const UpLevelDesc& d, hipStream_t st) {
   if (d.nbox <= 0 || d.nrhs <= 0) return;
-  if (d.n3 > kUpMaxN3 || d.n3 <= 0) throw Error(1, "up_fused: interface longer than the fused kernel takes");
+  if (!up_fused_fits(d.n1, d.n2, d.n3, d.nbp))
+    throw Error(1, "up_fused: a level the fused kernel does not take");
   if (d.per <= 0 || (d.nbox + d.per - 1) / d.per > SkinnyDesc::kMaxTab)
     throw Error(1, "up_fused: boxes per factor");
-  const size_t lds = (size_t)4 * d.n3 * NRB * sizeof(double2) +
-                     (size_t)(2 * d.n3 + d.n1 + d.n2 + d.nbp) * sizeof(int);
-  if (d.n1 + d.n2 != d.nbp) throw Error(1, "up_fused: parent boundary is not I1 + I2");
-  if (lds > 64 * 1024) throw Error(1, "up_fused: the level's vectors exceed 64 KB of LDS");
+  const size_t lds = up_fused_lds(d.n1, d.n2, d.n3, d.nbp);
   const int ns = (d.n3 + 3) / 4;
 #define HPS_UPF(T, NS) \
   hipLaunchKernelGGL((up_fused_kernel<T, NS>), dim3(d.nbox), dim3(256), lds, st, d)
