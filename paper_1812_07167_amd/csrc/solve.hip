@@ -329,14 +329,17 @@ int block_rows(const SkinnyDesc& d) {
   return d.M <= 16 ? 16 : d.M <= 32 ? 32 : 64;
 }
 
-// K is split across workgroups when the row blocks x batch cannot fill the device.
-// Returns the number of splits and the K range per split (a multiple of KC).
+// K is split across workgroups when the row blocks x batch cannot fill the device: up to
+// about kSplitTarget workgroups (with the top levels' 16-row blocks, 512 measured faster
+// than 1024 or 2048: fewer, longer K ranges).  Returns the number of splits and the K
+// range per split (a multiple of KC).
+constexpr long kSplitTarget = 512;
 int split_plan(const SkinnyDesc& d, int* kper_out) {
   const int tiles = cdiv(d.M, block_rows(d));
   int nsplit = 1;
   const long blocks = (long)tiles * nbatch(d);
-  if (blocks < 1024 && d.K >= 2 * KC) {
-    nsplit = (int)std::min<long>((1024 + blocks - 1) / blocks, (d.K + KC - 1) / KC);
+  if (blocks < kSplitTarget && d.K >= 2 * KC) {
+    nsplit = (int)std::min<long>((kSplitTarget + blocks - 1) / blocks, (d.K + KC - 1) / KC);
     nsplit = std::max(1, std::min(nsplit, 64));
   }
   int kper = d.K;
